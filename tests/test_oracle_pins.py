@@ -1,0 +1,565 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: numpy /
+scipy library routines, brute force on tiny inputs, exact rational
+arithmetic, closed forms of special cases, and the exact invariants the
+paper proves (Lemma 2, Theorem 2, Theorem 4, Proposition 1, Lemma 3).
+"""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from tests.helpers import augmented, qpsk, random_problem, rzf_numpy
+
+
+# --------------------------------------------------------------------------
+# Philox4x64-10: pinned to numpy.random.Philox (same generator, 10 rounds).
+# numpy increments its 256-bit counter before producing a block, so its
+# first block for counter c is Philox(c + 1).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("key,ctr", [
+    ((0, 0), (0, 0, 0, 0)),
+    ((7, 0), (5, 6, 7, 0)),
+    ((2**64 - 1, 12345), (2**64 - 1, 3, 9, 1)),
+    ((0xDEADBEEF, 0), (1000, 17, 3, 0)),
+])
+def test_philox_matches_numpy(key, ctr):
+    c = np.array(ctr, dtype=np.uint64)
+    # numpy's counter carries across words; build c - 1 with borrow
+    words = [int(v) for v in ctr]
+    val = sum(w << (64 * i) for i, w in enumerate(words))
+    prev = (val - 1) % (1 << 256)
+    prev_words = np.array([(prev >> (64 * i)) & (2**64 - 1) for i in range(4)], dtype=np.uint64)
+    g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=prev_words)
+    want = g.random_raw(4)
+    got = oracle.philox4x64_10(c, np.array(key, dtype=np.uint64))
+    assert [int(a) for a in got] == [int(b) for b in want]
+
+
+def test_uniform24_is_top_bits_of_philox():
+    for step, rhs, drop in [(0, 0, 0), (5, 3, 2), (123456, 4095, 511)]:
+        out = oracle.philox4x64_10(np.array([step, rhs, drop, 0], dtype=np.uint64),
+                                   np.array([99, 0], dtype=np.uint64))
+        u = oracle.uniform24(99, step, rhs, drop)
+        assert u == (int(out[0]) >> 40) / 2.0**24
+        assert 0.0 <= u < 1.0
+
+
+# --------------------------------------------------------------------------
+# Closed-form RZF (precoding equation; Theorem 1; Remark 1)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("nt,k,seed", [(64, 8, 0), (128, 16, 1), (40, 48, 2), (256, 1, 3), (96, 12, 4)])
+def test_rzf_cholesky_matches_numpy_and_scipy(nt, k, seed):
+    rng = np.random.default_rng(seed)
+    H, vs, vl, xi = random_problem(rng, nt, k)
+    S = qpsk(rng, (5, k))
+    X, V = oracle.rzf(H, vs, vl, S, xi)
+    Xn, Vn = rzf_numpy(H, S, xi)
+    np.testing.assert_allclose(X, Xn, rtol=0, atol=1e-12 * np.abs(Xn).max())
+    np.testing.assert_allclose(V, Vn, rtol=0, atol=1e-12 * np.abs(Vn).max())
+    M = H @ H.conj().T + xi * np.eye(k)
+    c = scipy.linalg.cho_factor(M, lower=True)
+    Vs = scipy.linalg.cho_solve(c, S.T).T
+    np.testing.assert_allclose(V, Vs, rtol=0, atol=1e-12 * np.abs(Vs).max())
+
+
+def test_min_norm_bruteforce_tiny():
+    """Theorem 1 + Remark 1: the min-norm solution of [H, sqrt(xi) I] z = s
+    (pinv, brute force) has x in its first Nt entries and sqrt(xi) v in the
+    last K."""
+    rng = np.random.default_rng(10)
+    for nt, k in [(16, 4), (24, 8), (8, 8), (6, 10)]:
+        H, vs, vl, xi = random_problem(rng, nt, k, lo=2, hi=nt)
+        s = qpsk(rng, (k,))
+        z = np.linalg.pinv(augmented(H, xi)) @ s
+        X, V = oracle.rzf(H, vs, vl, s, xi)
+        np.testing.assert_allclose(X[0], z[:nt], atol=1e-12)
+        np.testing.assert_allclose(V[0], z[nt:] / np.sqrt(xi), atol=1e-12)
+
+
+def test_least_squares_form_appendix_a():
+    """Appendix A: v = argmin ||G v - g||, G = [H^H; sqrt(xi) I] (paper
+    orientation), g = [0; s / sqrt(xi)]."""
+    rng = np.random.default_rng(11)
+    H, vs, vl, xi = random_problem(rng, 48, 6)
+    s = qpsk(rng, (6,))
+    G = np.vstack([H.conj().T, np.sqrt(xi) * np.eye(6)])
+    g = np.concatenate([np.zeros(48), s / np.sqrt(xi)])
+    v = np.linalg.lstsq(G, g, rcond=None)[0]
+    _, V = oracle.rzf(H, vs, vl, s, xi)
+    np.testing.assert_allclose(V[0], v, atol=1e-12)
+
+
+def _gauss_solve_exact(M, b):
+    """Gauss-Jordan over Gaussian rationals (pairs of Fractions)."""
+    n = len(b)
+    A = [[M[i][j] for j in range(n)] + [b[i]] for i in range(n)]
+
+    def mul(a, c):
+        return (a[0] * c[0] - a[1] * c[1], a[0] * c[1] + a[1] * c[0])
+
+    def inv(a):
+        d = a[0] * a[0] + a[1] * a[1]
+        return (a[0] / d, -a[1] / d)
+
+    for c in range(n):
+        piv = next(r for r in range(c, n) if A[r][c] != (0, 0))
+        A[c], A[piv] = A[piv], A[c]
+        iv = inv(A[c][c])
+        A[c] = [mul(iv, e) for e in A[c]]
+        for r in range(n):
+            if r != c and A[r][c] != (0, 0):
+                f = A[r][c]
+                A[r] = [(A[r][j][0] - mul(f, A[c][j])[0], A[r][j][1] - mul(f, A[c][j])[1])
+                        for j in range(n + 1)]
+    return [A[i][n] for i in range(n)]
+
+
+def test_rzf_exact_rational_small_integer_channel():
+    """Integer channel entries, xi = 1: v = (H H^H + I)^-1 s and x = H^H v
+    computed exactly in rational arithmetic."""
+    Hi = [[(1, 2), (0, -1), (3, 0), (0, 0), (0, 0)],
+          [(0, 0), (2, 1), (-1, 1), (1, 0), (0, 0)],
+          [(0, 0), (0, 0), (0, 0), (1, -2), (2, 2)]]
+    vs = np.array([0, 1, 3], dtype=np.int32)
+    vl = np.array([3, 3, 2], dtype=np.int32)
+    s = [(1, 1), (-1, 1), (1, -1)]
+    K, N = 3, 5
+    Fr = [[(Fraction(a), Fraction(b)) for (a, b) in row] for row in Hi]
+    M = []
+    for i in range(K):
+        row = []
+        for j in range(K):
+            re = sum(Fr[i][n][0] * Fr[j][n][0] + Fr[i][n][1] * Fr[j][n][1] for n in range(N))
+            im = sum(Fr[i][n][1] * Fr[j][n][0] - Fr[i][n][0] * Fr[j][n][1] for n in range(N))
+            row.append((re + (1 if i == j else 0), im))
+        M.append(row)
+    v = _gauss_solve_exact(M, [(Fraction(a), Fraction(b)) for a, b in s])
+    x = []
+    for n in range(N):
+        re = sum(Fr[k][n][0] * v[k][0] + Fr[k][n][1] * v[k][1] for k in range(K))
+        im = sum(Fr[k][n][0] * v[k][1] - Fr[k][n][1] * v[k][0] for k in range(K))
+        x.append(complex(float(re), float(im)))
+    H = np.array([[complex(a, b) for a, b in row] for row in Hi])
+    X, V = oracle.rzf(H, vs, vl, np.array([complex(a, b) for a, b in s]), 1.0)
+    np.testing.assert_allclose(X[0], np.array(x), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(V[0], np.array([complex(float(a), float(b)) for a, b in v]), atol=1e-14)
+
+
+def test_rzf_special_cases():
+    rng = np.random.default_rng(12)
+    # K = 1: x = conj(h) s / (||h||^2 + xi), one projection is exact
+    H, vs, vl, xi = random_problem(rng, 64, 1)
+    s = np.array([0.3 - 0.7j])
+    X, _ = oracle.rzf(H, vs, vl, s, xi)
+    np.testing.assert_allclose(X[0], H[0].conj() * s[0] / (np.vdot(H[0], H[0]).real + xi), atol=1e-15)
+    o = oracle.solve(H, vs, vl, s, xi, variant="grk", tol=1e-14)
+    assert o["iters"] == 1
+    np.testing.assert_allclose(o["x"], X[0], atol=1e-15)
+    # disjoint VRs: H H^H diagonal, x = sum_k conj(h_k) s_k / (||h_k||^2 + xi)
+    H, vs, vl, xi = random_problem(rng, 128, 8, disjoint=True)
+    s = qpsk(rng, (8,))
+    X, V = oracle.rzf(H, vs, vl, s, xi)
+    want = sum(H[k].conj() * s[k] / (np.vdot(H[k], H[k]).real + xi) for k in range(8))
+    np.testing.assert_allclose(X[0], want, atol=1e-14)
+    # large xi: x ~ H^H s / xi (MRC limit)
+    H, vs, vl, _ = random_problem(rng, 64, 8)
+    s = qpsk(rng, (8,))
+    X, _ = oracle.rzf(H, vs, vl, s, 1e9)
+    np.testing.assert_allclose(X[0] * 1e9, H.conj().T @ s, rtol=1e-6, atol=1e-9)
+    # small xi approaches ZF when H has full row rank
+    X, _ = oracle.rzf(H, vs, vl, s, 1e-10)
+    zf = H.conj().T @ np.linalg.solve(H @ H.conj().T, s)
+    np.testing.assert_allclose(X[0], zf, rtol=0, atol=1e-6 * np.abs(zf).max())
+    # zero-length VR: that row is [0, sqrt(xi) e_k], so v_k = s_k / xi
+    H, vs, vl, xi = random_problem(rng, 64, 6)
+    vl[2] = 0
+    H[2] = 0
+    s = qpsk(rng, (6,))
+    _, V = oracle.rzf(H, vs, vl, s, xi)
+    assert abs(V[0, 2] - s[2] / xi) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# VR structure: X_k and the orthogonal set F
+# --------------------------------------------------------------------------
+def test_overlap_sets_match_structural_gram():
+    """X_k = users whose channel rows are structurally non-orthogonal to
+    row k (Lemma 1), read off the support of H."""
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        H, vs, vl, xi = random_problem(rng, 50, 9, lo=0, hi=20)
+        sup = np.abs(H) > 0
+        got = oracle.overlap_sets(H, vs, vl)
+        for k in range(9):
+            want = {j for j in range(9) if j == k or np.any(sup[k] & sup[j])}
+            assert set(got[k].tolist()) == want
+
+
+def _brute_mis_size(vs, vl):
+    k = len(vs)
+    best = 0
+    for m in range(1, 1 << k):
+        idx = [i for i in range(k) if m >> i & 1]
+        ok = all(max(vs[a], vs[b]) >= min(vs[a] + vl[a], vs[b] + vl[b])
+                 for a, b in itertools.combinations(idx, 2))
+        if ok:
+            best = max(best, len(idx))
+    return best
+
+
+def test_mis_is_maximum_independent_set_bruteforce():
+    """Problem max_set: F is independent and as large as brute force finds."""
+    rng = np.random.default_rng(14)
+    for trial in range(60):
+        k = int(rng.integers(1, 11))
+        H, vs, vl, xi = random_problem(rng, 40, k, lo=0, hi=25)
+        f = oracle.mis(H, vs, vl)
+        idx = np.flatnonzero(f)
+        for a, b in itertools.combinations(idx, 2):
+            assert max(vs[a], vs[b]) >= min(vs[a] + vl[a], vs[b] + vl[b])
+        assert len(idx) == _brute_mis_size(vs, vl)
+
+
+# --------------------------------------------------------------------------
+# Iterations converge to the pinned RZF for every variant, rule and seed
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", ["grk", "ahk", "vr_ogrk", "vr_oahk"])
+@pytest.mark.parametrize("rule", ["baiwu", "residual", "max"])
+def test_iterations_converge_to_rzf(variant, rule):
+    rng = np.random.default_rng(15)
+    H, vs, vl, xi = random_problem(rng, 96, 12)
+    for seed in range(3):
+        s = qpsk(rng, (12,))
+        X, _ = oracle.rzf(H, vs, vl, s, xi)
+        o = oracle.solve(H, vs, vl, s, xi, variant=variant, select=rule, tol=1e-12, seed=seed)
+        assert o["flags"] == oracle.F_CONVERGED
+        assert np.linalg.norm(o["x"] - X[0]) <= 1e-10 * np.linalg.norm(X[0])
+
+
+def test_disjoint_vrs_one_iteration_and_k_steps():
+    """Theorem 4 / Prop. 1 with F = all users: VR-OAHK converges in one
+    iteration; the max rule fixes each row once (Theorem 2), so it needs
+    exactly one step per nonzero symbol."""
+    rng = np.random.default_rng(16)
+    H, vs, vl, xi = random_problem(rng, 160, 10, disjoint=True)
+    s = qpsk(rng, (10,))
+    s[3] = 0
+    X, _ = oracle.rzf(H, vs, vl, s, xi)
+    assert oracle.mis(H, vs, vl).all()
+    o = oracle.solve(H, vs, vl, s, xi, variant="vr_oahk", tol=1e-13)
+    assert o["iters"] == 1 and o["flags"] == oracle.F_CONVERGED
+    np.testing.assert_allclose(o["x"], X[0], atol=1e-14)
+    o = oracle.solve(H, vs, vl, s, xi, variant="grk", select="max", tol=1e-13)
+    assert o["iters"] == 9
+    np.testing.assert_allclose(o["x"], X[0], atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Exact invariants of the paper
+# --------------------------------------------------------------------------
+def _zstar(H, vs, vl, s, xi):
+    X, V = oracle.rzf(H, vs, vl, s, xi)
+    return np.concatenate([X[0], np.sqrt(xi) * V[0]])
+
+
+def _zz(z, nt, xi):
+    """trace rows hold [x; q]; z-space is [x; sqrt(xi) q]."""
+    return np.concatenate([z[:nt], np.sqrt(xi) * z[nt:]])
+
+
+@pytest.mark.parametrize("variant,rule", [("grk", "baiwu"), ("vr_ogrk", "residual"),
+                                          ("ahk", "baiwu"), ("vr_oahk", "baiwu"), ("grk", "max")])
+def test_pythagorean_identity_every_step(variant, rule):
+    """Lemma 2 / (gougu) and Lemma 3 / (gougu2): in z-space,
+    ||e_{t+1}||^2 = ||e_t||^2 - ||z_{t+1} - z_t||^2 at every (half-)step."""
+    rng = np.random.default_rng(17)
+    H, vs, vl, xi = random_problem(rng, 80, 10)
+    s = qpsk(rng, (10,))
+    zs = _zstar(H, vs, vl, s, xi)
+    o = oracle.solve(H, vs, vl, s, xi, variant=variant, select=rule, tol=1e-12, trace=True, seed=3)
+    Z = np.array([_zz(z, 80, xi) for z in o["z"]])
+    e2 = np.sum(np.abs(Z - zs) ** 2, axis=1)
+    d2 = np.sum(np.abs(np.diff(Z, axis=0)) ** 2, axis=1)
+    assert len(Z) > 3
+    np.testing.assert_allclose(e2[1:], e2[:-1] - d2, rtol=0, atol=1e-12 * e2[0])
+    assert np.all(np.diff(e2) <= 1e-14 * e2[0])
+
+
+def test_theorem2_orthogonal_rows_keep_residual_bitwise():
+    """Theorem 2: after projecting row i, rows orthogonal to it keep their
+    residual exactly (checked bit for bit in FP64 with numpy)."""
+    rng = np.random.default_rng(18)
+    H, vs, vl, xi = random_problem(rng, 120, 12, lo=10, hi=40)
+    s = qpsk(rng, (12,))
+    o = oracle.solve(H, vs, vl, s, xi, variant="grk", tol=1e-12, trace=True, seed=1)
+    xsets = oracle.overlap_sets(H, vs, vl)
+    nt = 120
+    checked = 0
+    for t in range(1, len(o["z"])):
+        i = o["idx"][t]
+        z0, z1 = o["z"][t - 1], o["z"][t]
+        r0 = s - H @ z0[:nt] - xi * z0[nt:]
+        r1 = s - H @ z1[:nt] - xi * z1[nt:]
+        for j in range(12):
+            if j not in xsets[i]:
+                assert r0[j] == r1[j]
+                checked += 1
+    assert checked > 50
+
+
+def test_theorem4_orthogonal_half_step_solves_f_rows():
+    """Theorem 4: after the aggregated step over the mutually orthogonal
+    set F, A_F z = s_F holds (to rounding)."""
+    rng = np.random.default_rng(19)
+    H, vs, vl, xi = random_problem(rng, 200, 14, lo=20, hi=60)
+    s = qpsk(rng, (14,))
+    f = oracle.mis(H, vs, vl)
+    assert f.sum() >= 2
+    o = oracle.solve(H, vs, vl, s, xi, variant="vr_oahk", tol=1e-12, trace=True)
+    nt = 200
+    n_half = 0
+    for t in range(len(o["z"])):
+        if o["idx"][t] == -1:
+            z = o["z"][t]
+            r = s - H @ z[:nt] - xi * z[nt:]
+            assert np.abs(r[f]).max() <= 1e-13
+            n_half += 1
+    assert n_half >= 2
+
+
+def test_proposition1_sequential_equals_grouped():
+    """Prop. 1 / Appendix D: single-row projections over disjoint rows, one
+    after another, equal the grouped step with gamma = 1."""
+    rng = np.random.default_rng(20)
+    H, vs, vl, xi = random_problem(rng, 150, 12, lo=10, hi=50)
+    s = qpsk(rng, (12,))
+    f = oracle.mis(H, vs, vl)
+    x = (rng.standard_normal(150) + 1j * rng.standard_normal(150)) * 0.1
+    q = (rng.standard_normal(12) + 1j * rng.standard_normal(12)) * 0.1
+    xg, qg = oracle.step_orthogonal(H, vs, vl, xi, f, s, x, q)
+    xs, qs = x.copy(), q.copy()
+    for i in np.flatnonzero(f)[::-1]:
+        xs, qs = oracle.step_row(H, vs, vl, xi, i, s, xs, qs)
+    np.testing.assert_allclose(xg, xs, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(qg, qs, rtol=0, atol=1e-15)
+    # and the general aggregated step restricted to F gives the same move
+    xa, qa = oracle.step_aggregate(H, vs, vl, xi, f, s, x, q)
+    np.testing.assert_allclose(xa, xg, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(qa, qg, rtol=0, atol=1e-14)
+
+
+def test_aggregate_with_unit_coefficient_is_single_row_step():
+    """(update4) with phi = e_i reduces to the Kaczmarz update (update)."""
+    rng = np.random.default_rng(21)
+    H, vs, vl, xi = random_problem(rng, 64, 8)
+    s = qpsk(rng, (8,))
+    x = rng.standard_normal(64) * 0.1 + 0j
+    q = rng.standard_normal(8) * 0.1 + 0j
+    for i in range(8):
+        m = np.zeros(8, dtype=bool)
+        m[i] = True
+        xa, qa = oracle.step_aggregate(H, vs, vl, xi, m, s, x, q)
+        xr, qr = oracle.step_row(H, vs, vl, xi, i, s, x, q)
+        np.testing.assert_allclose(xa, xr, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(qa, qr, rtol=0, atol=1e-15)
+
+
+def test_aggregated_step_decrease_and_rate():
+    """(update4): the z-space error drops by exactly (phi^H r)^2/||A^H phi||^2
+    and the per-step factor is < 1 whenever r != 0 (Theorem 5's alpha)."""
+    rng = np.random.default_rng(22)
+    H, vs, vl, xi = random_problem(rng, 90, 10)
+    s = qpsk(rng, (10,))
+    zs = _zstar(H, vs, vl, s, xi)
+    A = augmented(H, xi)
+    nrm = np.sum(np.abs(A) ** 2, axis=1)
+    x = np.zeros(90, complex)
+    q = np.zeros(10, complex)
+    allm = np.ones(10, dtype=bool)
+    for _ in range(6):
+        z = np.concatenate([x, np.sqrt(xi) * q])
+        r = s - A @ z
+        phi = r / nrm
+        pred = np.vdot(phi, r).real ** 2 / np.sum(np.abs(A.conj().T @ phi) ** 2)
+        x, q = oracle.step_aggregate(H, vs, vl, xi, allm, s, x, q)
+        z1 = np.concatenate([x, np.sqrt(xi) * q])
+        e0 = np.sum(np.abs(z - zs) ** 2)
+        e1 = np.sum(np.abs(z1 - zs) ** 2)
+        assert abs((e0 - e1) - pred) <= 1e-12 * e0
+        assert e1 < e0
+
+
+def test_selection_rules_against_definitions():
+    """Threshold-and-sample selection: with u swept over [0, 1), the
+    BAIWU rule picks exactly the rows with |r_i|^2 >= eps ||r||^2 ||a_i||^2
+    (eps as in the cited greedy randomized Kaczmarz), each with probability
+    |r_i|^2 / sum_U |r_j|^2; RESIDUAL uses every row with |r_i|^2/||r||^2;
+    MAX picks the largest |r_i|^2/||a_i||^2."""
+    rng = np.random.default_rng(23)
+    for _ in range(10):
+        K = 12
+        r = (rng.standard_normal(K) + 1j * rng.standard_normal(K)) * rng.random(K) ** 3
+        nrm = rng.random(K) + 0.5
+        w = np.abs(r) ** 2
+        eps = 0.5 * (np.max(w / nrm) / w.sum() + 1.0 / nrm.sum())
+        U = set(np.flatnonzero(w >= eps * w.sum() * nrm).tolist())
+        us = (np.arange(4096) + 0.5) / 4096
+        picks = np.array([oracle.select(r, nrm, "baiwu", u) for u in us])
+        assert set(picks.tolist()) == U
+        wu = np.array([w[i] if i in U else 0.0 for i in range(K)])
+        freq = np.bincount(picks, minlength=K) / len(us)
+        np.testing.assert_allclose(freq, wu / wu.sum(), atol=2.0 / 4096)
+        picks = np.array([oracle.select(r, nrm, "residual", u) for u in us])
+        freq = np.bincount(picks, minlength=K) / len(us)
+        np.testing.assert_allclose(freq, w / w.sum(), atol=2.0 / 4096)
+        assert oracle.select(r, nrm, "max", 0.3) == int(np.argmax(w / nrm))
+
+
+def test_theorem3_rate_bound():
+    """Theorem 3 (as corrected): per step, ||e_{t+1}||^2 <= (1 -
+    sigma_min(A)^2/||A||_F^2) ||e_t||^2. For the threshold and max rules it
+    holds at every step; for the residual-proportional rule it holds in
+    expectation (averaged over seeds from a common state)."""
+    rng = np.random.default_rng(24)
+    H, vs, vl, xi = random_problem(rng, 70, 10)
+    A = augmented(H, xi)
+    sig = np.linalg.svd(A, compute_uv=False)
+    eta = 1.0 - sig[-1] ** 2 / np.sum(np.abs(A) ** 2)
+    s = qpsk(rng, (10,))
+    zs = _zstar(H, vs, vl, s, xi)
+    for rule in ["baiwu", "max"]:
+        for seed in range(5):
+            o = oracle.solve(H, vs, vl, s, xi, variant="grk", select=rule, tol=1e-12, trace=True,
+                             seed=seed)
+            e2 = np.array([np.sum(np.abs(_zz(z, 70, xi) - zs) ** 2) for z in o["z"]])
+            assert np.all(e2[1:] <= eta * e2[:-1] * (1 + 1e-9) + 1e-28)
+    # expectation for the residual rule: one step from a common state
+    o = oracle.solve(H, vs, vl, s, xi, variant="grk", select="residual", tol=0.0, max_iters=5,
+                     trace=True)
+    z5 = o["z"][-1]
+    e0 = np.sum(np.abs(_zz(z5, 70, xi) - zs) ** 2)
+    r = s - H @ z5[:70] - xi * z5[70:]
+    nrm = oracle.row_norms(H, vs, vl, xi)
+    drops = []
+    for seed in range(400):
+        i = oracle.select(r, nrm, "residual", oracle.uniform24(seed, 0, 0, 0))
+        x1, q1 = oracle.step_row(H, vs, vl, xi, i, s, z5[:70], z5[70:])
+        drops.append(np.sum(np.abs(_zz(np.concatenate([x1, q1]), 70, xi) - zs) ** 2))
+    assert np.mean(drops) <= eta * e0
+
+
+def test_iteration_count_ordering():
+    """Qualitative claim of the simulation section: the aggregated method
+    needs far fewer iterations than the single-row greedy method."""
+    rng = np.random.default_rng(25)
+    H, vs, vl, xi = random_problem(rng, 256, 24, lo=40, hi=120)
+    s = qpsk(rng, (24,))
+    a = oracle.solve(H, vs, vl, s, xi, variant="vr_ogrk", tol=1e-6)["iters"]
+    b = oracle.solve(H, vs, vl, s, xi, variant="vr_oahk", tol=1e-6)["iters"]
+    assert b * 3 < a
+
+
+# --------------------------------------------------------------------------
+# Flags and degenerate inputs
+# --------------------------------------------------------------------------
+def test_flags_and_degenerate_inputs():
+    rng = np.random.default_rng(26)
+    H, vs, vl, xi = random_problem(rng, 64, 8)
+    o = oracle.solve(H, vs, vl, np.zeros(8), xi, variant="grk")
+    assert o["iters"] == 0 and o["flags"] == oracle.F_CONVERGED and not o["x"].any()
+    s = qpsk(rng, (8,))
+    o = oracle.solve(H, vs, vl, s, xi, variant="ahk", tol=1e-12, max_iters=1)
+    assert o["iters"] == 1 and o["flags"] == oracle.F_MAXITER
+    Hn = H.copy()
+    Hn[2, vs[2]] = np.nan
+    o = oracle.solve(Hn, vs, vl, s, xi, variant="vr_oahk")
+    assert o["flags"] & oracle.F_NONFINITE
+    with pytest.raises(ValueError):
+        oracle.solve(H, vs, vl, s, 0.0)
+    bad = vs.copy()
+    bad[0] = 64 - vl[0] + 1
+    with pytest.raises(ValueError):
+        oracle.solve(H, bad, vl, s, xi)
+
+
+# --------------------------------------------------------------------------
+# Gradient of the closed form: finite differences and torch autograd
+# --------------------------------------------------------------------------
+def _loss_and_explicit(H, S, X, lam):
+    """L = mean_b ||H x_b - s_b||^2 + lam ||x_b||^2 with its torch-convention
+    gradient on X (G) and its explicit parts on H and S."""
+    B = S.shape[0]
+    R = X @ H.T - S                          # rows: H x_b - s_b
+    L = (np.sum(np.abs(R) ** 2) + lam * np.sum(np.abs(X) ** 2)) / B
+    G = 2.0 * (R @ H.conj() + lam * X) / B   # 2 dL/d conj(x)
+    gH_exp = 2.0 * R.T @ X.conj() / B        # 2 dL/d conj(H) holding x fixed
+    gS_exp = -2.0 * R / B
+    return L, G, gH_exp, gS_exp
+
+
+def test_rzf_gradient_matches_finite_differences():
+    rng = np.random.default_rng(27)
+    nt, k, lam = 64, 8, 0.1
+    H, vs, vl, xi = random_problem(rng, nt, k)
+    S = qpsk(rng, (4, k))
+
+    def total(Hc, Sc, xic):
+        X, _ = oracle.rzf(Hc, vs, vl, Sc, xic)
+        return _loss_and_explicit(Hc, Sc, X, lam)[0]
+
+    X, _ = oracle.rzf(H, vs, vl, S, xi)
+    L, G, gHe, gSe = _loss_and_explicit(H, S, X, lam)
+    gH, gS, gxi = oracle.rzf_grad(H, vs, vl, S, xi, G)
+    gH = gH + gHe * (np.abs(H) > 0)
+    gS = gS + gSe
+    h = 1e-6
+    for (kk, n) in [(0, vs[0]), (3, vs[3] + vl[3] // 2), (7, vs[7] + vl[7] - 1)]:
+        for part, unit in [("re", 1.0), ("im", 1j)]:
+            Hp, Hm = H.copy(), H.copy()
+            Hp[kk, n] += h * unit
+            Hm[kk, n] -= h * unit
+            fd = (total(Hp, S, xi) - total(Hm, S, xi)) / (2 * h)
+            want = gH[kk, n].real if part == "re" else gH[kk, n].imag
+            assert abs(fd - want) <= 1e-7 * max(1.0, abs(want))
+    for (b, kk) in [(0, 0), (3, 5)]:
+        for unit in [1.0, 1j]:
+            Sp, Sm = S.copy(), S.copy()
+            Sp[b, kk] += h * unit
+            Sm[b, kk] -= h * unit
+            fd = (total(H, Sp, xi) - total(H, Sm, xi)) / (2 * h)
+            want = gS[b, kk].real if unit == 1.0 else gS[b, kk].imag
+            assert abs(fd - want) <= 1e-7 * max(1.0, abs(want))
+    fd = (total(H, S, xi + h) - total(H, S, xi - h)) / (2 * h)
+    assert abs(fd - gxi) <= 1e-7 * max(1.0, abs(gxi))
+
+
+def test_rzf_gradient_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(28)
+    nt, k, lam = 48, 6, 0.1
+    H, vs, vl, xi = random_problem(rng, nt, k)
+    S = qpsk(rng, (3, k))
+    mask = torch.tensor(np.abs(H) > 0)
+    Ht = torch.tensor(H, requires_grad=True)
+    St = torch.tensor(S, requires_grad=True)
+    xit = torch.tensor(xi, dtype=torch.float64, requires_grad=True)
+    Hm = Ht * mask
+    M = Hm @ Hm.conj().T + xit * torch.eye(k, dtype=torch.complex128)
+    V = torch.linalg.solve(M, St.T)
+    X = (Hm.conj().T @ V).T
+    R = X @ Hm.T - St
+    L = (R.abs().pow(2).sum() + lam * X.abs().pow(2).sum()) / 3
+    L.backward()
+    Xn, _ = oracle.rzf(H, vs, vl, S, xi)
+    _, G, gHe, gSe = _loss_and_explicit(H, S, Xn, lam)
+    gH, gS, gxi = oracle.rzf_grad(H, vs, vl, S, xi, G)
+    np.testing.assert_allclose(gH + gHe * (np.abs(H) > 0), Ht.grad.numpy(), atol=1e-12)
+    np.testing.assert_allclose(gS + gSe, St.grad.numpy(), atol=1e-12)
+    assert abs(gxi - float(xit.grad)) <= 1e-12 * max(1.0, abs(gxi))
