@@ -1,0 +1,181 @@
+/*
+ * vrk.h - C ABI of libvrk.so: VR-banded Kaczmarz RZF precoding on MI355X.
+ *
+ * What it computes (paper: "Low-Complexity Iterative Precoding Design for
+ * Near-field Multiuser Systems With Spatial Non-Stationarity"):
+ *   the RZF-precoded vector x = H^H (H H^H + xi I)^-1 s of each symbol
+ *   vector s (precoding equation, Sec. II-C), as the first Nt entries of the
+ *   minimum-norm solution of the consistent augmented system
+ *   [H, sqrt(xi) I_K] z = s (Theorem 1, Sec. III-B), and v = (H H^H + xi I)^-1 s
+ *   as its scaled last K entries (Remark 1). The system is solved by one of
+ *   four Kaczmarz sweeps started from z = 0 (Alg. 1 initialisation):
+ *     VRK_GRK      greedy randomized Kaczmarz (Sec. IV-A)
+ *     VRK_AHK      aggregation-hyperplane Kaczmarz, eqs. (update4) and
+ *                  (coefficient) (Sec. V-A)
+ *     VRK_VR_OGRK  GRK refreshing only the overlapping rows X_i (Alg. 2,
+ *                  Theorem 2)
+ *     VRK_VR_OAHK  orthogonal-set half-step (Theorem 4, Prop. 1) then an
+ *                  aggregated half-step on the rest (Alg. 3)
+ *
+ * Layout. H is row-major K x Nt interleaved complex (row k = the channel
+ * user k sees: y_k = sum_n H[k,n] x[n]; the paper's channel matrix is its
+ * conjugate transpose). User k's visibility region (VR) is the half-open
+ * antenna interval [vr_start[k], vr_start[k] + vr_len[k]); only those
+ * entries of H are read, the rest are taken to be zero (VR mask of the
+ * channel equation). S, X, V hold one vector per row: S is B x K, X is
+ * B x Nt, V is B x K. Complex64 = two float32, complex128 = two float64.
+ *
+ * Ownership. All device buffers belong to the caller and must outlive the
+ * plan. The library never allocates device memory: the caller supplies one
+ * workspace of the size vrk_plan_create reports. vrk_solve and
+ * vrk_solve_adjoint only enqueue kernels on the given stream (no host
+ * synchronisation, no allocation, no host<->device copy), so they can be
+ * captured into a HIP graph.
+ *
+ * Errors. Every call returns a vrk_status; argument errors are found on
+ * the host before anything is enqueued (VRK_EINVAL), and vrk_last_error()
+ * gives a thread-local message. Outcomes of the iteration are per-RHS
+ * flags written on the device: bit 0 converged, bit 1 non-finite input or
+ * iterate, bit 2 stopped at max_iters (x is then the last iterate).
+ */
+#ifndef VRK_H
+#define VRK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VRK_OK = 0,
+    VRK_EINVAL = 1,       /* bad argument (sizes, strides, VR bounds, xi, tol, null pointer) */
+    VRK_EUNSUPPORTED = 2, /* valid but not supported by the chosen engine (e.g. LDS budget) */
+    VRK_EWORKSPACE = 3,   /* workspace null, misaligned or smaller than reported */
+    VRK_EHIP = 4,         /* a HIP runtime call failed (message in vrk_last_error) */
+    VRK_ESTATE = 5        /* call order violated (solve before bind, adjoint without buffers) */
+} vrk_status;
+
+typedef enum { VRK_GRK = 0, VRK_AHK = 1, VRK_VR_OGRK = 2, VRK_VR_OAHK = 3 } vrk_variant;
+
+/* Row selection of the greedy sweeps (Sec. IV-A).
+ *  BAIWU    threshold-and-sample rule of the greedy randomized Kaczmarz the
+ *           paper cites: rows with |r_i|^2 >= eps ||r||^2 ||a_i||^2,
+ *           eps = (max_i |r_i|^2/||a_i||^2 / ||r||^2 + 1/||A||_F^2) / 2, are
+ *           sampled with probability proportional to |r_i|^2.
+ *  RESIDUAL the printed rule p_i = |r_i|^2 / ||r||^2.
+ *  MAX      argmax_i |r_i|^2 / ||a_i||^2 (lowest index on ties).
+ * Sampling draws u = (Philox4x64-10(key (seed, 0), counter (step, rhs, prob, 0))[0]
+ * >> 40) * 2^-24 and picks the smallest row index whose inclusive prefix of
+ * weights exceeds u times their total. */
+typedef enum { VRK_SEL_BAIWU = 0, VRK_SEL_RESIDUAL = 1, VRK_SEL_MAX = 2 } vrk_select;
+
+typedef enum { VRK_C64 = 0, VRK_C128 = 1 } vrk_dtype;
+
+/* Execution engine. VECTOR: one workgroup per right-hand side, vector ALU,
+ * complex64 or complex128. MFMA: 16 right-hand sides per workgroup sharing
+ * H, residual and aggregation as FP32 matrix-core products (complex64
+ * only). AUTO picks MFMA for complex64 problems with >= 16 right-hand
+ * sides, VECTOR otherwise. */
+typedef enum { VRK_ENGINE_AUTO = 0, VRK_ENGINE_VECTOR = 1, VRK_ENGINE_MFMA = 2 } vrk_engine;
+
+/* Schedule of the aggregated update H^H phi in the VECTOR engine:
+ * GATHER  each thread owns antennas and sums over the users covering them;
+ * COLOUR  users in one colour class (pairwise disjoint VRs, Lemma 1) are
+ *         scattered concurrently, classes one after another. */
+typedef enum { VRK_SCHED_AUTO = 0, VRK_SCHED_GATHER = 1, VRK_SCHED_COLOUR = 2 } vrk_schedule;
+
+/* One channel drop with its batch of symbol vectors. */
+typedef struct {
+    int32_t nt, k;                     /* antennas >= 1, users >= 1 (k >= nt allowed) */
+    double xi;                         /* regulariser, finite and > 0 */
+    const void *H;   int64_t ldh;      /* device, K x Nt, row stride ldh >= nt (elements) */
+    const int32_t *vr_start;           /* HOST [k], 0 <= start */
+    const int32_t *vr_len;             /* HOST [k], 0 <= len, start + len <= nt */
+    int32_t nrhs;                      /* B >= 0 */
+    const void *S;   int64_t lds;      /* device, B x K, lds >= k */
+    void *X;         int64_t ldx;      /* device out, B x Nt, ldx >= nt */
+    void *V;         int64_t ldv;      /* device out, B x K (nullable) */
+    /* Adjoint buffers; all null unless vrk_solve_adjoint is used. */
+    const void *GX;  int64_t ldgx;     /* device in, B x Nt: 2 dL/d conj(x) */
+    void *GH;        int64_t ldgh;     /* device out, K x Nt: dL/dH on VR entries (others untouched) */
+    void *GS;        int64_t ldgs;     /* device out, B x K: dL/ds */
+    double *gxi;                       /* device out, one double: dL/dxi */
+} vrk_problem;
+
+typedef struct {
+    int32_t variant;     /* vrk_variant */
+    int32_t select;      /* vrk_select (greedy variants only) */
+    int32_t dtype;       /* vrk_dtype of H, S, X, V, GX, GH, GS */
+    int32_t engine;      /* vrk_engine */
+    double tol;          /* stop when ||s - H x - xi q|| / ||s|| <= tol; >= 0 */
+    int64_t max_iters;   /* > 0: row updates (greedy) or iterations (aggregated) */
+    uint64_t seed;       /* Philox key word 0 */
+    int32_t schedule;    /* vrk_schedule */
+    int32_t tile_waves;  /* MFMA engine waves per workgroup: 0 (auto), 4, 8 or 16 */
+    int32_t persistent;  /* MFMA engine: 1 = persistent grid with a work queue */
+    int32_t reserved;
+} vrk_options;
+
+typedef struct vrk_plan vrk_plan;
+
+/* Fills o with: VR_OAHK, BAIWU, C64, AUTO engine, tol 1e-5,
+ * max_iters 100000, seed 0, schedules and tiles auto. */
+void vrk_default_options(vrk_options *o);
+
+/* Host only (no device access): validates nprob problems, builds the VR
+ * plan of each (overlap sets X_k, the orthogonal set F as a maximum
+ * independent set of the interval overlap graph, colour classes, tile
+ * maps) and reports the workspace size in bytes. *out receives a plan the
+ * caller frees with vrk_plan_destroy. The vr_start / vr_len arrays are
+ * copied; device pointers are recorded, not read. */
+vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_options *opt,
+                           size_t *ws_bytes, vrk_plan **out);
+
+/* Attaches the caller's device workspace (>= ws_bytes, 256-byte aligned),
+ * copies the plan tables into it and enqueues the row-norm and tile-pack
+ * kernels on `stream` (a hipStream_t; null = default stream). Reads H.
+ * Must be called again if H changes. */
+vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Enqueues the solve of every right-hand side of every problem. Writes X,
+ * V and, when non-null, per-RHS statistics laid out problem after problem
+ * (sum of nrhs entries): d_iters (updates done), d_relres (final relative
+ * residual), d_flags (bit 0 converged, 1 non-finite, 2 max_iters). */
+vrk_status vrk_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres,
+                     int32_t *d_flags);
+
+/* Implicit-differentiation backward pass of x = H^H (H H^H + xi I)^-1 s,
+ * given GX = 2 dL/d conj(x) of a real loss and the X, V of a previous
+ * vrk_solve on the same plan: forms b = H g, runs the same Kaczmarz solve
+ * on the same system with right-hand side b (mu = its q, xh = H^H mu = its
+ * x), then writes GS = mu, *gxi = -Re sum_b mu_b^H v_b and, on VR entries,
+ * GH = sum_b v_b (g_b - xh_b)^H - mu_b x_b^H. Statistics as vrk_solve. */
+vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres,
+                             int32_t *d_flags);
+
+/* Plan inspection (host only), for tests and tooling. Writes up to `cap`
+ * int32 values of the requested table of problem `prob` into out and
+ * returns the table length, or -1 on a bad argument. */
+typedef enum {
+    VRK_Q_PERM = 0,      /* users sorted by (VR start, end, index) */
+    VRK_Q_FSET = 1,      /* orthogonal set F, ascending user index */
+    VRK_Q_COLOUR = 2,    /* colour class of each user */
+    VRK_Q_XOFF = 3,      /* CSR offsets of X_k, length k + 1 */
+    VRK_Q_XIDX = 4,      /* CSR indices of X_k (ascending, includes k) */
+    VRK_Q_ENGINE = 5,    /* [engine, schedule, tile_waves, lds_bytes] chosen */
+    VRK_Q_TILES = 6      /* [residual chunks, aggregation chunks, band MACs] per problem */
+} vrk_query;
+int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *out, int64_t cap);
+
+void vrk_plan_destroy(vrk_plan *pl);
+
+const char *vrk_status_string(vrk_status s);
+const char *vrk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VRK_H */

@@ -1,0 +1,151 @@
+// Device helpers shared by the HIP kernels: complex arithmetic, wave64
+// reductions, Philox4x64-10 and the greedy row selection.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vrk_desc.h"
+
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename R>
+__device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b)
+{
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename R>
+__device__ __forceinline__ R cnorm2(cx<R> a)
+{
+    return a.re * a.re + a.im * a.im;
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_max(R v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// Inclusive prefix sum across the 64 lanes (Hillis-Steele).
+template <typename R>
+__device__ __forceinline__ R wave_scan(R v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        R o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x64
+// S-box with the published multipliers and Weyl key increments. Returns
+// the first output word.
+__device__ __forceinline__ uint64_t philox4x64_10_w0(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                     uint64_t c3, uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    return c0;
+}
+
+// u = top 24 bits of Philox(key (seed, 0), counter (step, rhs, prob, 0)) / 2^24,
+// exactly representable in float and double.
+__device__ __forceinline__ double uniform24(uint64_t seed, int64_t step, int64_t rhs, int64_t prob)
+{
+    uint64_t w = philox4x64_10_w0((uint64_t)step, (uint64_t)rhs, (uint64_t)prob, 0, seed, 0);
+    return (double)(w >> 40) * (1.0 / 16777216.0);
+}
+
+// Greedy row selection by one wave (Sec. IV-A). get(i) returns
+// {|r_i|^2, ||a_i||^2} for user i (original index order). The threshold
+// rule keeps rows with rho_i = |r_i|^2/||a_i||^2 >= theta,
+// theta = min(rho_max, (rho_max + ||r||^2/||A||_F^2)/2) (the cited greedy
+// randomized Kaczmarz criterion); RESIDUAL keeps every row; MAX returns the
+// first argmax of rho. Sampling: smallest index whose inclusive prefix of
+// kept weights exceeds u * total, else the last kept index. `pre` is LDS
+// scratch of K entries owned by the calling wave.
+template <typename R, typename Get>
+__device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
+{
+    const int lane = threadIdx.x & 63;
+    R rr = 0, best = -1;
+    int bi = 0x7fffffff;
+    for (int base = 0; base < K; base += 64) {
+        int i = base + lane;
+        if (i < K) {
+            cx<R> wn = get(i);
+            R rho = wn.re / wn.im;
+            rr += wn.re;
+            if (rho > best) { best = rho; bi = i; }
+        }
+    }
+    rr = wave_sum(rr);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        R ob = __shfl_xor(best, m, 64);
+        int oi = __shfl_xor(bi, m, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (bi >= K) bi = 0;   // unreachable for finite residuals; keeps the index in range
+    if (rule == 2) return bi;
+    R theta = 0;
+    if (rule == 0) {
+        theta = (R)0.5 * (best + rr / fro2);
+        if (theta > best) theta = best;
+    }
+    R carry = 0;
+    int last = bi;
+    for (int base = 0; base < K; base += 64) {
+        int i = base + lane;
+        R wt = 0;
+        if (i < K) {
+            cx<R> wn = get(i);
+            bool in = (rule == 1) || (wn.re / wn.im >= theta);
+            wt = (in && wn.re > 0) ? wn.re : (R)0;
+        }
+        R v = wave_scan(wt, lane);
+        if (i < K) pre[i] = carry + v;
+        uint64_t pos = __ballot(wt > 0);
+        if (pos) last = base + 63 - __clzll(pos);
+        carry += __shfl(v, 63, 64);
+    }
+    R target = u * carry;
+    __builtin_amdgcn_wave_barrier();
+    for (int base = 0; base < K; base += 64) {
+        int i = base + lane;
+        uint64_t hit = __ballot(i < K && pre[i] > target);
+        if (hit) return base + __ffsll((unsigned long long)hit) - 1;
+    }
+    return last;
+}

@@ -1,0 +1,45 @@
+// Host-side launchers of the HIP kernels (defined in the .hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/vrk.h"
+#include "vrk_desc.h"
+
+struct VrkSolveArgs {
+    const VrkDesc *desc;      // device array [nprob]
+    int32_t nprob;
+    int32_t max_rhs;          // largest nrhs over the problems (grid x of the vector engine)
+    int32_t dtype;            // 0 complex64, 1 complex128
+    int32_t variant, select, schedule;
+    int32_t adjoint;          // 0: S -> X, V; 1: Sadj -> Xadj, GS
+    double tol;
+    int64_t max_iters;
+    uint64_t seed;
+    int32_t *iters;
+    float *relres;
+    int32_t *flags;
+};
+
+// Row norms ||a_i||^2 = ||H[i, VR_i]||^2 + xi and ||A||_F^2, per problem.
+hipError_t vrk_launch_norms(const VrkDesc *desc, int32_t nprob, int32_t dtype, hipStream_t s);
+// MFMA residual / aggregation tiles from the VR bands of H.
+hipError_t vrk_launch_pack(const VrkDesc *desc, int32_t nprob, int64_t max_tiles, hipStream_t s);
+
+// Vector engine: one workgroup per right-hand side.
+size_t vrk_vec_lds_bytes(int32_t dtype, int32_t nt, int32_t k);
+hipError_t vrk_launch_vec_solve(const VrkSolveArgs &a, size_t lds_bytes, hipStream_t s);
+
+// MFMA engine: 16 right-hand sides per workgroup (complex64).
+int vrk_mfma_supported(int32_t nt, int32_t waves);
+size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t waves);
+hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, int32_t nwork,
+                                 int32_t waves, int32_t na, size_t lds_bytes, hipStream_t s);
+
+// Adjoint pieces: b = H g (right-hand side of the adjoint solve) and the
+// gradient assembly.
+hipError_t vrk_launch_adjoint_rhs(const VrkDesc *desc, int32_t nprob, int32_t max_rhs,
+                                  int32_t dtype, hipStream_t s);
+hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t max_k,
+                                    int32_t dtype, hipStream_t s);

@@ -1,0 +1,625 @@
+// Host side of libvrk: argument validation, the VR plan of each problem,
+// workspace carving, table upload and kernel dispatch.
+//
+// The VR plan follows the VR-structure passages of the paper:
+//  * overlap sets X_k (Sec. IV-B): users whose VR intersects user k's,
+//    including k; Lemma 1 makes every other row orthogonal to row k;
+//  * the orthogonal set F (Sec. V-B, problem max_set): a maximum independent
+//    set of the VR overlap graph. Contiguous VRs make it an interval graph,
+//    where the earliest-end greedy is exact; V is the complement;
+//  * colour classes: a minimum partition of the users into sets of pairwise
+//    disjoint VRs (optimal interval-graph colouring), used as the group
+//    schedule of concurrent row updates (Prop. 1 generalised to every class).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/vrk.h"
+#include "kernels.h"
+#include "vrk_desc.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+vrk_status fail(vrk_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+vrk_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(VRK_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 1));
+        return o;
+    }
+};
+
+struct ProbPlan {
+    vrk_problem p{};
+    std::vector<int32_t> vs, ve, perm, pos, xoff, xidx, flist, vlist, colour, col_off, col_users;
+    std::vector<int32_t> gb_off, gb_users;
+    std::vector<uint8_t> inf;
+    int32_t ncol = 0;
+    // MFMA tables
+    int32_t nub = 0, nab = 0, ntile = 0;
+    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, fown;
+    std::vector<int64_t> ha_off;
+    int64_t n_ha = 0, n_hg = 0, band = 0;
+    // workspace offsets
+    size_t o_vs, o_ve, o_xoff, o_xidx, o_flist, o_vlist, o_inf, o_coloff, o_colusr, o_gboff,
+        o_gbusr, o_perm, o_pos, o_nrm, o_fro2, o_rablo, o_rabhi, o_haoff, o_agoff, o_aguc,
+        o_fown, o_ha, o_hg, o_sadj, o_xadj, o_vfwd;
+    int64_t rhs_base = 0;
+};
+
+}  // namespace
+
+struct vrk_plan {
+    vrk_options opt{};
+    std::vector<ProbPlan> pp;
+    int32_t engine = VRK_ENGINE_VECTOR, schedule = VRK_SCHED_GATHER, waves = 8, na = 0;
+    size_t lds = 0;
+    size_t table_end = 0, ws_bytes = 0, o_desc = 0, o_work = 0;
+    int64_t total_rhs = 0, max_tiles = 0;
+    int32_t max_rhs = 0, max_k = 0;
+    bool adjoint_ready = false;
+    std::vector<VrkWork> work;
+    std::vector<uint8_t> image;
+    uint8_t *d_ws = nullptr;
+    bool bound = false;
+};
+
+namespace {
+
+int32_t elem_bytes(int32_t dtype) { return dtype == VRK_C128 ? 16 : 8; }
+
+vrk_status validate_problem(const vrk_problem &p, int idx, const vrk_options &o)
+{
+    if (p.nt < 1 || p.k < 1) return fail(VRK_EINVAL, "problem %d: nt=%d k=%d must be >= 1", idx, p.nt, p.k);
+    if (!(p.xi > 0.0) || !std::isfinite(p.xi))
+        return fail(VRK_EINVAL, "problem %d: xi=%g must be finite and > 0", idx, p.xi);
+    if (!p.H || p.ldh < p.nt) return fail(VRK_EINVAL, "problem %d: H null or ldh < nt", idx);
+    if (!p.vr_start || !p.vr_len) return fail(VRK_EINVAL, "problem %d: vr_start/vr_len null", idx);
+    if (p.nrhs < 0) return fail(VRK_EINVAL, "problem %d: nrhs < 0", idx);
+    if (p.nrhs > 0) {
+        if (!p.S || p.lds < p.k) return fail(VRK_EINVAL, "problem %d: S null or lds < k", idx);
+        if (!p.X || p.ldx < p.nt) return fail(VRK_EINVAL, "problem %d: X null or ldx < nt", idx);
+        if (p.V && p.ldv < p.k) return fail(VRK_EINVAL, "problem %d: ldv < k", idx);
+    }
+    for (int i = 0; i < p.k; ++i) {
+        int64_t s = p.vr_start[i], l = p.vr_len[i];
+        if (s < 0 || l < 0 || s + l > p.nt)
+            return fail(VRK_EINVAL, "problem %d: VR of user %d = [%lld, %lld) outside [0, %d)", idx, i,
+                        (long long)s, (long long)(s + l), p.nt);
+    }
+    bool any_adj = p.GX || p.GH || p.GS || p.gxi;
+    if (any_adj) {
+        if (!(p.GX && p.GH && p.GS && p.gxi))
+            return fail(VRK_EINVAL, "problem %d: adjoint buffers GX, GH, GS, gxi must be all set or all null", idx);
+        if (p.ldgx < p.nt || p.ldgh < p.nt || p.ldgs < p.k)
+            return fail(VRK_EINVAL, "problem %d: adjoint strides too small", idx);
+    }
+    (void)o;
+    return VRK_OK;
+}
+
+// Earliest-end greedy maximum independent set on the interval graph.
+void build_mis(ProbPlan &q)
+{
+    const int K = q.p.k;
+    q.inf.assign(K, 0);
+    std::vector<int32_t> ord;
+    for (int i = 0; i < K; ++i) {
+        if (q.ve[i] == q.vs[i]) q.inf[i] = 1;   // empty VR: orthogonal to every row
+        else ord.push_back(i);
+    }
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+        if (q.ve[a] != q.ve[b]) return q.ve[a] < q.ve[b];
+        if (q.vs[a] != q.vs[b]) return q.vs[a] < q.vs[b];
+        return a < b;
+    });
+    int64_t last = INT64_MIN;
+    for (int i : ord)
+        if (q.vs[i] >= last) { q.inf[i] = 1; last = q.ve[i]; }
+    q.flist.clear();
+    q.vlist.clear();
+    for (int i = 0; i < K; ++i) (q.inf[i] ? q.flist : q.vlist).push_back(i);
+}
+
+// Optimal interval colouring: sweep by start, reuse the smallest colour
+// whose interval has ended.
+void build_colours(ProbPlan &q)
+{
+    const int K = q.p.k;
+    q.colour.assign(K, 0);
+    std::vector<int32_t> ord;
+    for (int i = 0; i < K; ++i)
+        if (q.ve[i] > q.vs[i]) ord.push_back(i);
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+        if (q.vs[a] != q.vs[b]) return q.vs[a] < q.vs[b];
+        if (q.ve[a] != q.ve[b]) return q.ve[a] < q.ve[b];
+        return a < b;
+    });
+    using End = std::pair<int32_t, int32_t>;   // (end, colour)
+    std::priority_queue<End, std::vector<End>, std::greater<End>> active;
+    std::set<int32_t> freec;
+    int32_t ncol = 0;
+    for (int i : ord) {
+        while (!active.empty() && active.top().first <= q.vs[i]) {
+            freec.insert(active.top().second);
+            active.pop();
+        }
+        int32_t c;
+        if (!freec.empty()) { c = *freec.begin(); freec.erase(freec.begin()); }
+        else c = ncol++;
+        q.colour[i] = c;
+        active.push({q.ve[i], c});
+    }
+    if (ncol == 0) ncol = 1;   // only empty VRs: one class
+    q.ncol = ncol;
+    q.col_off.assign(ncol + 1, 0);
+    for (int i = 0; i < K; ++i) q.col_off[q.colour[i] + 1]++;
+    for (int c = 0; c < ncol; ++c) q.col_off[c + 1] += q.col_off[c];
+    q.col_users.assign(K, 0);
+    std::vector<int32_t> fillp(q.col_off.begin(), q.col_off.end() - 1);
+    for (int i = 0; i < K; ++i) q.col_users[fillp[q.colour[i]]++] = i;
+}
+
+void build_tables(ProbPlan &q)
+{
+    const vrk_problem &p = q.p;
+    const int K = p.k, N = p.nt;
+    q.vs.assign(p.vr_start, p.vr_start + K);
+    q.ve.resize(K);
+    q.band = 0;
+    for (int i = 0; i < K; ++i) { q.ve[i] = q.vs[i] + p.vr_len[i]; q.band += p.vr_len[i]; }
+    // users sorted by (start, end, index)
+    q.perm.resize(K);
+    std::iota(q.perm.begin(), q.perm.end(), 0);
+    std::sort(q.perm.begin(), q.perm.end(), [&](int a, int b) {
+        if (q.vs[a] != q.vs[b]) return q.vs[a] < q.vs[b];
+        if (q.ve[a] != q.ve[b]) return q.ve[a] < q.ve[b];
+        return a < b;
+    });
+    q.pos.resize(K);
+    for (int i = 0; i < K; ++i) q.pos[q.perm[i]] = i;
+    // overlap sets X_k (includes k), via the sorted order
+    q.xoff.assign(K + 1, 0);
+    q.xidx.clear();
+    for (int kk = 0; kk < K; ++kk) {
+        q.xoff[kk] = (int32_t)q.xidx.size();
+        for (int j = 0; j < K; ++j) {
+            bool ov = std::max(q.vs[kk], q.vs[j]) < std::min(q.ve[kk], q.ve[j]);
+            if (j == kk || ov) q.xidx.push_back(j);
+        }
+    }
+    q.xoff[K] = (int32_t)q.xidx.size();
+    build_mis(q);
+    build_colours(q);
+    // gather lists: users meeting each 64-antenna block
+    const int ngb = (N + VRK_GATHER_BLOCK - 1) / VRK_GATHER_BLOCK;
+    q.gb_off.assign(ngb + 1, 0);
+    q.gb_users.clear();
+    for (int g = 0; g < ngb; ++g) {
+        q.gb_off[g] = (int32_t)q.gb_users.size();
+        int32_t lo = g * VRK_GATHER_BLOCK, hi = std::min(N, lo + VRK_GATHER_BLOCK);
+        for (int i = 0; i < K; ++i)
+            if (std::max(lo, q.vs[i]) < std::min(hi, q.ve[i])) q.gb_users.push_back(i);
+    }
+    q.gb_off[ngb] = (int32_t)q.gb_users.size();
+    // MFMA tiles (sorted user order)
+    q.nub = (K + VRK_UB - 1) / VRK_UB;
+    q.nab = (N + VRK_AB - 1) / VRK_AB;
+    q.ntile = (p.nrhs + VRK_TILE_RHS - 1) / VRK_TILE_RHS;
+    q.rab_lo.assign(q.nub, 0);
+    q.rab_hi.assign(q.nub, 0);
+    q.ha_off.assign(q.nub + 1, 0);
+    for (int ub = 0; ub < q.nub; ++ub) {
+        int32_t lo = INT32_MAX, hi = INT32_MIN;
+        for (int i = ub * VRK_UB; i < std::min(K, (ub + 1) * VRK_UB); ++i) {
+            int u = q.perm[i];
+            if (q.ve[u] == q.vs[u]) continue;
+            lo = std::min(lo, q.vs[u] / VRK_AB);
+            hi = std::max(hi, (q.ve[u] + VRK_AB - 1) / VRK_AB);
+        }
+        if (lo > hi) lo = hi = 0;
+        q.rab_lo[ub] = lo;
+        q.rab_hi[ub] = hi;
+        q.ha_off[ub + 1] = q.ha_off[ub] + 4 * (int64_t)(hi - lo);
+    }
+    q.n_ha = q.ha_off[q.nub];
+    const int nuc = q.nub * (VRK_UB / 4);
+    q.ag_off.assign(q.nab + 1, 0);
+    q.ag_uc.clear();
+    for (int ab = 0; ab < q.nab; ++ab) {
+        q.ag_off[ab] = (int32_t)q.ag_uc.size();
+        int32_t lo = ab * VRK_AB, hi = lo + VRK_AB;
+        for (int uc = 0; uc < nuc; ++uc) {
+            bool any = false;
+            for (int t = 0; t < 4; ++t) {
+                int i = uc * 4 + t;
+                if (i >= K) break;
+                int u = q.perm[i];
+                if (std::max(lo, q.vs[u]) < std::min(hi, q.ve[u])) any = true;
+            }
+            if (any) q.ag_uc.push_back(uc);
+        }
+    }
+    q.ag_off[q.nab] = (int32_t)q.ag_uc.size();
+    q.n_hg = (int64_t)q.ag_uc.size();
+    q.fown.assign((size_t)q.nab * VRK_AB, -1);
+    for (int u : q.flist)
+        for (int32_t n = q.vs[u]; n < q.ve[u]; ++n) q.fown[n] = q.pos[u];
+}
+
+template <class T>
+void put(std::vector<uint8_t> &img, size_t off, const std::vector<T> &v)
+{
+    if (!v.empty()) std::memcpy(img.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+}  // namespace
+
+extern "C" {
+
+void vrk_default_options(vrk_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->variant = VRK_VR_OAHK;
+    o->select = VRK_SEL_BAIWU;
+    o->dtype = VRK_C64;
+    o->engine = VRK_ENGINE_AUTO;
+    o->tol = 1e-5;
+    o->max_iters = 100000;
+    o->seed = 0;
+    o->schedule = VRK_SCHED_AUTO;
+    o->tile_waves = 0;
+    o->persistent = 0;
+}
+
+vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_options *opt,
+                           size_t *ws_bytes, vrk_plan **out)
+{
+    g_err.clear();
+    if (!out || !ws_bytes) return fail(VRK_EINVAL, "out and ws_bytes must be non-null");
+    *out = nullptr;
+    if (!probs || nprob < 1) return fail(VRK_EINVAL, "need at least one problem");
+    if (!opt) return fail(VRK_EINVAL, "options null");
+    const vrk_options &o = *opt;
+    if (o.variant < 0 || o.variant > 3) return fail(VRK_EINVAL, "variant %d", o.variant);
+    if (o.select < 0 || o.select > 2) return fail(VRK_EINVAL, "select %d", o.select);
+    if (o.dtype != VRK_C64 && o.dtype != VRK_C128) return fail(VRK_EINVAL, "dtype %d", o.dtype);
+    if (o.engine < 0 || o.engine > 2) return fail(VRK_EINVAL, "engine %d", o.engine);
+    if (o.schedule < 0 || o.schedule > 2) return fail(VRK_EINVAL, "schedule %d", o.schedule);
+    if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(VRK_EINVAL, "tol %g", o.tol);
+    if (o.max_iters < 1) return fail(VRK_EINVAL, "max_iters must be >= 1");
+    if (o.tile_waves != 0 && o.tile_waves != 4 && o.tile_waves != 8 && o.tile_waves != 16)
+        return fail(VRK_EINVAL, "tile_waves %d", o.tile_waves);
+    for (int i = 0; i < nprob; ++i) {
+        vrk_status s = validate_problem(probs[i], i, o);
+        if (s != VRK_OK) return s;
+    }
+    vrk_plan *pl = new vrk_plan();
+    pl->opt = o;
+    pl->pp.resize(nprob);
+    bool all_adj = true;
+    int32_t max_nt = 0, max_k = 0, min_rhs = INT32_MAX, max_kpad = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ProbPlan &q = pl->pp[i];
+        q.p = probs[i];
+        build_tables(q);
+        q.rhs_base = pl->total_rhs;
+        pl->total_rhs += q.p.nrhs;
+        pl->max_rhs = std::max(pl->max_rhs, q.p.nrhs);
+        pl->max_k = std::max(pl->max_k, q.p.k);
+        all_adj = all_adj && q.p.GX;
+        max_nt = std::max(max_nt, q.p.nt);
+        max_k = std::max(max_k, q.p.k);
+        max_kpad = std::max(max_kpad, q.nub * VRK_UB);
+        min_rhs = std::min(min_rhs, q.p.nrhs);
+        q.p.vr_start = nullptr;   // the caller's host arrays are not kept
+        q.p.vr_len = nullptr;
+    }
+    pl->adjoint_ready = all_adj;
+    // engine choice
+    int32_t waves = o.tile_waves ? o.tile_waves : 8;
+    bool mfma_ok = o.dtype == VRK_C64 && vrk_mfma_supported(max_nt, waves);
+    int32_t eng = o.engine;
+    if (eng == VRK_ENGINE_AUTO) eng = (mfma_ok && min_rhs >= VRK_TILE_RHS) ? VRK_ENGINE_MFMA : VRK_ENGINE_VECTOR;
+    if (eng == VRK_ENGINE_MFMA && !mfma_ok) {
+        delete pl;
+        return fail(VRK_EUNSUPPORTED, "MFMA engine needs complex64 and nt <= %d with %d waves",
+                    16 * VRK_AB * waves, waves);
+    }
+    pl->engine = eng;
+    pl->waves = waves;
+    pl->schedule = o.schedule == VRK_SCHED_AUTO ? VRK_SCHED_GATHER : o.schedule;
+    if (eng == VRK_ENGINE_VECTOR) {
+        pl->lds = vrk_vec_lds_bytes(o.dtype, max_nt, max_k);
+        if (pl->lds > 160 * 1024) {
+            delete pl;
+            return fail(VRK_EUNSUPPORTED, "vector engine needs %zu bytes of LDS (> 160 KiB) for nt=%d k=%d",
+                        pl->lds, max_nt, max_k);
+        }
+    } else {
+        int32_t max_nab = (max_nt + VRK_AB - 1) / VRK_AB;
+        int32_t na = (max_nab + waves - 1) / waves;
+        int32_t nap = 1;
+        while (nap < na) nap *= 2;
+        pl->na = nap;
+        pl->lds = vrk_mfma_lds_bytes(max_kpad, waves);
+        if (pl->lds > 160 * 1024) {
+            delete pl;
+            return fail(VRK_EUNSUPPORTED, "MFMA engine needs %zu bytes of LDS for k=%d", pl->lds, max_k);
+        }
+        // work items: (problem, tile), most expensive first
+        for (int i = 0; i < nprob; ++i)
+            for (int t = 0; t < pl->pp[i].ntile; ++t) pl->work.push_back({i, t});
+        std::stable_sort(pl->work.begin(), pl->work.end(), [&](const VrkWork &a, const VrkWork &b) {
+            const ProbPlan &x = pl->pp[a.prob], &y = pl->pp[b.prob];
+            return x.n_ha + x.n_hg > y.n_ha + y.n_hg;
+        });
+    }
+    // workspace carving
+    const int32_t eb = elem_bytes(o.dtype), rb = o.dtype == VRK_C128 ? 8 : 4;
+    Carver cv;
+    pl->o_desc = cv.take(sizeof(VrkDesc) * nprob);
+    pl->o_work = cv.take(sizeof(VrkWork) * std::max<size_t>(1, pl->work.size()));
+    for (auto &q : pl->pp) {
+        const int K = q.p.k;
+        q.o_vs = cv.take(4 * K);
+        q.o_ve = cv.take(4 * K);
+        q.o_xoff = cv.take(4 * (K + 1));
+        q.o_xidx = cv.take(4 * q.xidx.size());
+        q.o_flist = cv.take(4 * q.flist.size());
+        q.o_vlist = cv.take(4 * q.vlist.size());
+        q.o_inf = cv.take(K);
+        q.o_coloff = cv.take(4 * q.col_off.size());
+        q.o_colusr = cv.take(4 * q.col_users.size());
+        q.o_gboff = cv.take(4 * q.gb_off.size());
+        q.o_gbusr = cv.take(4 * q.gb_users.size());
+        q.o_perm = cv.take(4 * K);
+        q.o_pos = cv.take(4 * K);
+        q.o_rablo = cv.take(4 * q.rab_lo.size());
+        q.o_rabhi = cv.take(4 * q.rab_hi.size());
+        q.o_haoff = cv.take(8 * q.ha_off.size());
+        q.o_agoff = cv.take(4 * q.ag_off.size());
+        q.o_aguc = cv.take(4 * q.ag_uc.size());
+        q.o_fown = cv.take(4 * q.fown.size());
+    }
+    pl->table_end = cv.off;
+    for (auto &q : pl->pp) {
+        q.o_nrm = cv.take((size_t)rb * std::max(q.p.k, q.nub * VRK_UB));
+        q.o_fro2 = cv.take(rb);
+        if (eng == VRK_ENGINE_MFMA) {
+            q.o_ha = cv.take(q.n_ha * 64 * 8);
+            q.o_hg = cv.take(q.n_hg * 64 * 8);
+            pl->max_tiles = std::max(pl->max_tiles, std::max(q.n_ha, q.n_hg));
+        }
+        if (q.p.GX) {
+            q.o_sadj = cv.take((size_t)eb * q.p.nrhs * q.p.k);
+            q.o_xadj = cv.take((size_t)eb * q.p.nrhs * q.p.nt);
+            q.o_vfwd = q.p.V ? 0 : cv.take((size_t)eb * q.p.nrhs * q.p.k);
+        }
+    }
+    pl->ws_bytes = cv.off;
+    *ws_bytes = pl->ws_bytes;
+    *out = pl;
+    return VRK_OK;
+}
+
+vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    if (!pl) return fail(VRK_EINVAL, "plan null");
+    if (!d_ws || ws_bytes < pl->ws_bytes || (reinterpret_cast<uintptr_t>(d_ws) & 255))
+        return fail(VRK_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned (got %zu at %p)",
+                    pl->ws_bytes, ws_bytes, d_ws);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *base = reinterpret_cast<uint8_t *>(d_ws);
+    pl->image.assign(pl->table_end, 0);
+    std::vector<VrkDesc> descs(pl->pp.size());
+    const vrk_options &o = pl->opt;
+    const int32_t eb = elem_bytes(o.dtype);
+    for (size_t i = 0; i < pl->pp.size(); ++i) {
+        ProbPlan &q = pl->pp[i];
+        auto &img = pl->image;
+        put(img, q.o_vs, q.vs);
+        put(img, q.o_ve, q.ve);
+        put(img, q.o_xoff, q.xoff);
+        put(img, q.o_xidx, q.xidx);
+        put(img, q.o_flist, q.flist);
+        put(img, q.o_vlist, q.vlist);
+        put(img, q.o_inf, q.inf);
+        put(img, q.o_coloff, q.col_off);
+        put(img, q.o_colusr, q.col_users);
+        put(img, q.o_gboff, q.gb_off);
+        put(img, q.o_gbusr, q.gb_users);
+        put(img, q.o_perm, q.perm);
+        put(img, q.o_pos, q.pos);
+        put(img, q.o_rablo, q.rab_lo);
+        put(img, q.o_rabhi, q.rab_hi);
+        put(img, q.o_haoff, q.ha_off);
+        put(img, q.o_agoff, q.ag_off);
+        put(img, q.o_aguc, q.ag_uc);
+        put(img, q.o_fown, q.fown);
+        VrkDesc &d = descs[i];
+        std::memset(&d, 0, sizeof d);
+        const vrk_problem &p = q.p;
+        d.nt = p.nt; d.k = p.k; d.nrhs = p.nrhs;
+        d.nf = (int32_t)q.flist.size(); d.nv = (int32_t)q.vlist.size();
+        d.ncol = q.ncol; d.ngb = (int32_t)q.gb_off.size() - 1; d.nub = q.nub;
+        d.nab = q.nab; d.ntile = q.ntile;
+        d.xi = p.xi;
+        d.ldh = p.ldh; d.lds = p.lds; d.ldx = p.ldx; d.ldv = p.V ? p.ldv : p.k;
+        d.ldgx = p.ldgx; d.ldgh = p.ldgh; d.ldgs = p.ldgs;
+        d.rhs_base = q.rhs_base;
+        d.H = p.H; d.S = p.S; d.X = p.X;
+        d.V = p.V ? p.V : (p.GX ? base + q.o_vfwd : nullptr);
+        d.GX = p.GX; d.GH = p.GH; d.GS = p.GS; d.gxi = p.gxi;
+        d.Sadj = p.GX ? base + q.o_sadj : nullptr;
+        d.Xadj = p.GX ? base + q.o_xadj : nullptr;
+        d.Vfwd = nullptr;
+        d.vs = (const int32_t *)(base + q.o_vs);
+        d.ve = (const int32_t *)(base + q.o_ve);
+        d.xoff = (const int32_t *)(base + q.o_xoff);
+        d.xidx = (const int32_t *)(base + q.o_xidx);
+        d.flist = (const int32_t *)(base + q.o_flist);
+        d.vlist = (const int32_t *)(base + q.o_vlist);
+        d.inf = (const uint8_t *)(base + q.o_inf);
+        d.col_off = (const int32_t *)(base + q.o_coloff);
+        d.col_users = (const int32_t *)(base + q.o_colusr);
+        d.gb_off = (const int32_t *)(base + q.o_gboff);
+        d.gb_users = (const int32_t *)(base + q.o_gbusr);
+        d.perm = (const int32_t *)(base + q.o_perm);
+        d.pos = (const int32_t *)(base + q.o_pos);
+        d.nrm = base + q.o_nrm;
+        d.fro2 = base + q.o_fro2;
+        d.rab_lo = (const int32_t *)(base + q.o_rablo);
+        d.rab_hi = (const int32_t *)(base + q.o_rabhi);
+        d.ha_off = (const int64_t *)(base + q.o_haoff);
+        d.ag_off = (const int32_t *)(base + q.o_agoff);
+        d.ag_uc = (const int32_t *)(base + q.o_aguc);
+        d.fown = (const int32_t *)(base + q.o_fown);
+        d.HA = pl->engine == VRK_ENGINE_MFMA ? base + q.o_ha : nullptr;
+        d.HG = pl->engine == VRK_ENGINE_MFMA ? base + q.o_hg : nullptr;
+        (void)eb;
+    }
+    std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());
+    if (!pl->work.empty())
+        std::memcpy(pl->image.data() + pl->o_work, pl->work.data(), sizeof(VrkWork) * pl->work.size());
+    hipError_t e = hipMemcpyAsync(base, pl->image.data(), pl->table_end, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan tables)");
+    const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(base + pl->o_desc);
+    e = vrk_launch_norms(dd, (int32_t)pl->pp.size(), o.dtype, s);
+    if (e != hipSuccess) return hip_fail(e, "row-norm kernel");
+    if (pl->engine == VRK_ENGINE_MFMA) {
+        e = vrk_launch_pack(dd, (int32_t)pl->pp.size(), pl->max_tiles, s);
+        if (e != hipSuccess) return hip_fail(e, "tile-pack kernel");
+    }
+    pl->d_ws = base;
+    pl->bound = true;
+    return VRK_OK;
+}
+
+static vrk_status run_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres,
+                            int32_t *d_flags, int adjoint)
+{
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    VrkSolveArgs a{};
+    a.desc = reinterpret_cast<const VrkDesc *>(pl->d_ws + pl->o_desc);
+    a.nprob = (int32_t)pl->pp.size();
+    a.max_rhs = pl->max_rhs;
+    a.dtype = pl->opt.dtype;
+    a.variant = pl->opt.variant;
+    a.select = pl->opt.select;
+    a.schedule = pl->schedule;
+    a.adjoint = adjoint;
+    a.tol = pl->opt.tol;
+    a.max_iters = pl->opt.max_iters;
+    a.seed = pl->opt.seed;
+    a.iters = d_iters;
+    a.relres = d_relres;
+    a.flags = d_flags;
+    if (pl->total_rhs == 0) return VRK_OK;
+    hipError_t e;
+    if (pl->engine == VRK_ENGINE_MFMA)
+        e = vrk_launch_mfma_solve(a, reinterpret_cast<const VrkWork *>(pl->d_ws + pl->o_work),
+                                  (int32_t)pl->work.size(), pl->waves, pl->na, pl->lds, s);
+    else
+        e = vrk_launch_vec_solve(a, pl->lds, s);
+    if (e != hipSuccess) return hip_fail(e, "solve kernel");
+    return VRK_OK;
+}
+
+vrk_status vrk_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres, int32_t *d_flags)
+{
+    g_err.clear();
+    if (!pl) return fail(VRK_EINVAL, "plan null");
+    if (!pl->bound) return fail(VRK_ESTATE, "vrk_plan_bind must precede vrk_solve");
+    return run_solve(pl, stream, d_iters, d_relres, d_flags, 0);
+}
+
+vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres,
+                             int32_t *d_flags)
+{
+    g_err.clear();
+    if (!pl) return fail(VRK_EINVAL, "plan null");
+    if (!pl->bound) return fail(VRK_ESTATE, "vrk_plan_bind must precede vrk_solve_adjoint");
+    if (!pl->adjoint_ready) return fail(VRK_ESTATE, "problems were planned without adjoint buffers");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(pl->d_ws + pl->o_desc);
+    if (pl->total_rhs == 0) return VRK_OK;
+    hipError_t e = vrk_launch_adjoint_rhs(dd, (int32_t)pl->pp.size(), pl->max_rhs, pl->opt.dtype, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint right-hand side kernel");
+    vrk_status st = run_solve(pl, stream, d_iters, d_relres, d_flags, 1);
+    if (st != VRK_OK) return st;
+    e = vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint gradient kernel");
+    return VRK_OK;
+}
+
+int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *out, int64_t cap)
+{
+    if (!pl || prob < 0 || prob >= (int32_t)pl->pp.size() || cap < 0 || (cap > 0 && !out)) return -1;
+    const ProbPlan &q = pl->pp[prob];
+    std::vector<int32_t> v;
+    switch (what) {
+    case VRK_Q_PERM: v = q.perm; break;
+    case VRK_Q_FSET: v = q.flist; break;
+    case VRK_Q_COLOUR: v = q.colour; break;
+    case VRK_Q_XOFF: v = q.xoff; break;
+    case VRK_Q_XIDX: v = q.xidx; break;
+    case VRK_Q_ENGINE: v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds}; break;
+    case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band}; break;
+    default: return -1;
+    }
+    int64_t n = (int64_t)v.size();
+    for (int64_t i = 0; i < std::min(n, cap); ++i) out[i] = v[i];
+    return n;
+}
+
+void vrk_plan_destroy(vrk_plan *pl) { delete pl; }
+
+const char *vrk_status_string(vrk_status s)
+{
+    switch (s) {
+    case VRK_OK: return "ok";
+    case VRK_EINVAL: return "invalid argument";
+    case VRK_EUNSUPPORTED: return "unsupported";
+    case VRK_EWORKSPACE: return "workspace too small or misaligned";
+    case VRK_EHIP: return "HIP runtime error";
+    case VRK_ESTATE: return "call order";
+    }
+    return "unknown status";
+}
+
+const char *vrk_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,509 @@
+// Vector engine: one workgroup (4 waves) per right-hand side, for
+// complex64 and complex128. The whole Kaczmarz solve of one symbol vector
+// runs inside one launch with x, q, r, phi in LDS; H is read from its VR
+// bands in global memory (L2-resident across the workgroups of a drop).
+//
+// Also here: row norms, MFMA tile packing, and the adjoint right-hand side
+// and gradient kernels.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+template <typename R>
+__device__ R block_sum(R v, R *red)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    R t = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += red[i];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Row norms: nrm_i = ||H[i, VR_i]||^2 + xi (the stored norms of Alg. 1) and
+// ||A||_F^2 = sum_i nrm_i. One workgroup per problem.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_norms(const VrkDesc *descs)
+{
+    __shared__ R red[kWaves];
+    const VrkDesc &d = descs[blockIdx.x];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const cx<R> *H = reinterpret_cast<const cx<R> *>(d.H);
+    R *nrm = reinterpret_cast<R *>(d.nrm);
+    R part = 0;
+    for (int i = w; i < d.k; i += kWaves) {
+        R acc = 0;
+        for (int n = d.vs[i] + lane; n < d.ve[i]; n += 64) acc += cnorm2(H[(int64_t)i * d.ldh + n]);
+        acc = wave_sum(acc) + (R)d.xi;
+        if (lane == 0) nrm[i] = acc;
+        part += acc;
+    }
+    // padded users of the MFMA engine get a unit norm (their residual is 0)
+    for (int i = d.k + threadIdx.x; i < d.nub * VRK_UB; i += kThreads) nrm[i] = 1;
+    if (lane == 0) red[w] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        R t = 0;
+        for (int i = 0; i < kWaves; ++i) t += red[i];
+        *reinterpret_cast<R *>(d.fro2) = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA tile packing (complex64). Residual tile (ub, c): lane l = i + 16 kk
+// holds H[perm[16 ub + i], 16 ab + 4 kk + m] with ab = rab_lo[ub] + c / 4,
+// m = c % 4, zero outside that user's VR. Aggregation tile e of antenna
+// block ab: lane l = i + 16 kk holds conj(H[perm[4 uc + kk], 16 ab + i]).
+// One wave per tile.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
+{
+    const VrkDesc &d = descs[blockIdx.y];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * kWaves + w;
+    const int64_t n_ha = d.ha_off[d.nub];
+    const int64_t n_hg = d.ag_off[d.nab];
+    const cx<float> *H = reinterpret_cast<const cx<float> *>(d.H);
+    const int i = lane & 15, kk = lane >> 4;
+    if (t < n_ha) {
+        int ub = 0;
+        while (d.ha_off[ub + 1] <= t) ++ub;
+        int64_t c = t - d.ha_off[ub];
+        int ab = d.rab_lo[ub] + (int)(c >> 2), m = (int)(c & 3);
+        int n = ab * VRK_AB + 4 * kk + m;
+        int ku = ub * VRK_UB + i;
+        cx<float> v = {0.f, 0.f};
+        if (ku < d.k) {
+            int u = d.perm[ku];
+            if (n >= d.vs[u] && n < d.ve[u]) v = H[(int64_t)u * d.ldh + n];
+        }
+        reinterpret_cast<cx<float> *>(d.HA)[t * 64 + lane] = v;
+    }
+    if (t < n_hg) {
+        int lo = 0, hi = d.nab;   // ab with ag_off[ab] <= t < ag_off[ab+1]
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (d.ag_off[mid] <= t) lo = mid; else hi = mid;
+        }
+        int ab = lo;
+        int uc = d.ag_uc[t];
+        int n = ab * VRK_AB + i;
+        int ku = uc * 4 + kk;
+        cx<float> v = {0.f, 0.f};
+        if (ku < d.k) {
+            int u = d.perm[ku];
+            if (n >= d.vs[u] && n < d.ve[u]) {
+                cx<float> h = H[(int64_t)u * d.ldh + n];
+                v = {h.re, -h.im};
+            }
+        }
+        reinterpret_cast<cx<float> *>(d.HG)[t * 64 + lane] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The vector-engine solve.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct VecCtx {
+    const VrkDesc *d;
+    const cx<R> *H;
+    cx<R> *x, *p, *r, *q, *phi, *s;
+    R *nrm, *pre, *red;
+    R xi;
+};
+
+// r_i = s_i - H[i, VR_i] x[VR_i] - xi q_i for the rows of `list` (all rows
+// when list is null): one wave per row, lanes along the band.
+template <typename R>
+__device__ void residual_rows(const VecCtx<R> &c, const int32_t *list, int n)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const VrkDesc &d = *c.d;
+    for (int t = w; t < n; t += kWaves) {
+        int i = list ? list[t] : t;
+        const cx<R> *h = c.H + (int64_t)i * d.ldh;
+        R ar = 0, ai = 0;
+        for (int nn = d.vs[i] + lane; nn < d.ve[i]; nn += 64) {
+            cx<R> hv = h[nn], xv = c.x[nn];
+            ar += hv.re * xv.re - hv.im * xv.im;
+            ai += hv.re * xv.im + hv.im * xv.re;
+        }
+        ar = wave_sum(ar);
+        ai = wave_sum(ai);
+        if (lane == 0)
+            c.r[i] = {c.s[i].re - ar - c.xi * c.q[i].re, c.s[i].im - ai - c.xi * c.q[i].im};
+    }
+}
+
+// Aggregated projection (update4) over the rows with in_set(i):
+// phi_i = r_i / ||a_i||^2, p = H^H phi, gamma = sum |r_i|^2/||a_i||^2 /
+// (||p||^2 + xi ||phi||^2), x += gamma p, q += gamma phi.
+template <typename R, typename InSet>
+__device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
+{
+    const VrkDesc &d = *c.d;
+    const int tid = threadIdx.x;
+    R num = 0, phin = 0;
+    for (int i = tid; i < d.k; i += kThreads) {
+        cx<R> f = {0, 0};
+        if (in_set(i)) {
+            R inv = (R)1 / c.nrm[i];
+            f = {c.r[i].re * inv, c.r[i].im * inv};
+            num += cnorm2(c.r[i]) * inv;
+            phin += cnorm2(f);
+        }
+        c.phi[i] = f;
+    }
+    num = block_sum(num, c.red);
+    phin = block_sum(phin, c.red + kWaves);
+    if (!(num > 0)) return;   // zero residual on the set: no move (uniform)
+    R pn = 0;
+    if (schedule == VRK_SCHED_COLOUR) {
+        for (int n = tid; n < d.nt; n += kThreads) c.p[n] = {0, 0};
+        __syncthreads();
+        for (int col = 0; col < d.ncol; ++col) {
+            // users of one class have pairwise disjoint VRs: no write conflicts
+            for (int e = d.col_off[col]; e < d.col_off[col + 1]; ++e) {
+                int u = d.col_users[e];
+                cx<R> f = c.phi[u];
+                if (f.re == 0 && f.im == 0) continue;
+                const cx<R> *h = c.H + (int64_t)u * d.ldh;
+                for (int n = d.vs[u] + tid; n < d.ve[u]; n += kThreads) {
+                    cx<R> t = cmulc(f, h[n]);
+                    c.p[n].re += t.re;
+                    c.p[n].im += t.im;
+                }
+            }
+            __syncthreads();
+        }
+        for (int n = tid; n < d.nt; n += kThreads) pn += cnorm2(c.p[n]);
+    } else {
+        // each thread owns antennas and gathers the users covering them
+        for (int n = tid; n < d.nt; n += kThreads) {
+            int g = n / VRK_GATHER_BLOCK;
+            R ar = 0, ai = 0;
+            for (int e = d.gb_off[g]; e < d.gb_off[g + 1]; ++e) {
+                int u = d.gb_users[e];
+                cx<R> f = c.phi[u];
+                if (f.re == 0 && f.im == 0) continue;
+                if (n >= d.vs[u] && n < d.ve[u]) {
+                    cx<R> t = cmulc(f, c.H[(int64_t)u * d.ldh + n]);
+                    ar += t.re;
+                    ai += t.im;
+                }
+            }
+            c.p[n] = {ar, ai};
+            pn += ar * ar + ai * ai;
+        }
+    }
+    pn = block_sum(pn, c.red + 2 * kWaves);
+    R gamma = num / (pn + c.xi * phin);
+    for (int n = tid; n < d.nt; n += kThreads) {
+        c.x[n].re += gamma * c.p[n].re;
+        c.x[n].im += gamma * c.p[n].im;
+    }
+    for (int i = tid; i < d.k; i += kThreads)
+        if (in_set(i)) {
+            c.q[i].re += gamma * c.phi[i].re;
+            c.q[i].im += gamma * c.phi[i].im;
+        }
+    __syncthreads();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int prob = blockIdx.y;
+    const VrkDesc &d = a.desc[prob];
+    const int b = blockIdx.x;
+    if (b >= d.nrhs) return;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int N = d.nt, K = d.k;
+
+    VecCtx<R> c;
+    c.d = &d;
+    c.H = reinterpret_cast<const cx<R> *>(d.H);
+    c.xi = (R)d.xi;
+    cx<R> *base = reinterpret_cast<cx<R> *>(smem);
+    c.x = base;
+    c.p = c.x + N;
+    c.r = c.p + N;
+    c.q = c.r + K;
+    c.phi = c.q + K;
+    c.s = c.phi + K;
+    c.nrm = reinterpret_cast<R *>(c.s + K);
+    c.pre = c.nrm + K;
+    c.red = c.pre + K;
+    __shared__ int sh_i;
+    __shared__ R sh_g[2];
+
+    const cx<R> *S;
+    cx<R> *X, *V;
+    int64_t lds_, ldx_, ldv_;
+    if (a.adjoint) {
+        S = reinterpret_cast<const cx<R> *>(d.Sadj); lds_ = K;
+        X = reinterpret_cast<cx<R> *>(d.Xadj); ldx_ = N;
+        V = reinterpret_cast<cx<R> *>(d.GS); ldv_ = d.ldgs;
+    } else {
+        S = reinterpret_cast<const cx<R> *>(d.S); lds_ = d.lds;
+        X = reinterpret_cast<cx<R> *>(d.X); ldx_ = d.ldx;
+        V = reinterpret_cast<cx<R> *>(d.V); ldv_ = d.ldv;
+    }
+    const R *nrm_g = reinterpret_cast<const R *>(d.nrm);
+    for (int n = tid; n < N; n += kThreads) c.x[n] = {0, 0};
+    R s2 = 0;
+    for (int i = tid; i < K; i += kThreads) {
+        cx<R> sv = S[(int64_t)b * lds_ + i];
+        c.s[i] = sv;
+        c.r[i] = sv;   // r0 = s since z0 = 0
+        c.q[i] = {0, 0};
+        c.nrm[i] = nrm_g[i];
+        s2 += cnorm2(sv);
+    }
+    s2 = block_sum(s2, c.red);
+    const R fro2 = *reinterpret_cast<const R *>(d.fro2);
+    const R snorm = sqrt(s2);
+    int32_t flags = 0;
+    int64_t t = 0;
+    R rel = 0;
+    const int variant = a.variant;
+    if (!isfinite(snorm) || !isfinite(fro2)) {
+        flags = VRK_FLAG_NONFINITE;
+    } else if (s2 == 0) {
+        flags = VRK_FLAG_CONVERGED;
+    } else {
+        for (;;) {
+            if (variant != 2) {   // every variant but VR-OGRK recomputes all rows
+                residual_rows(c, nullptr, K);
+                __syncthreads();
+            }
+            R r2 = 0;
+            for (int i = tid; i < K; i += kThreads) r2 += cnorm2(c.r[i]);
+            r2 = block_sum(r2, c.red + 3 * kWaves);
+            rel = sqrt(r2) / snorm;
+            if (!isfinite(rel)) { flags = VRK_FLAG_NONFINITE; break; }
+            if (rel <= (R)a.tol) { flags = VRK_FLAG_CONVERGED; break; }
+            if (t >= a.max_iters) { flags = VRK_FLAG_MAXITER; break; }
+            if (variant == 0 || variant == 2) {
+                if (w == 0) {
+                    R u = (R)uniform24(a.seed, t, b, prob);
+                    int i = select_row_wave<R>(K, a.select, fro2, u, [&](int j) -> cx<R> {
+                        return {cnorm2(c.r[j]), c.nrm[j]};
+                    }, c.pre);
+                    if (lane == 0) {
+                        sh_i = i;
+                        R inv = (R)1 / c.nrm[i];
+                        sh_g[0] = c.r[i].re * inv;
+                        sh_g[1] = c.r[i].im * inv;
+                    }
+                }
+                __syncthreads();
+                const int i = sh_i;
+                const cx<R> g = {sh_g[0], sh_g[1]};
+                // single-row projection (update): x += gamma conj(H[i, VR_i]), q_i += gamma
+                const cx<R> *h = c.H + (int64_t)i * d.ldh;
+                for (int n = d.vs[i] + tid; n < d.ve[i]; n += kThreads) {
+                    cx<R> tv = cmulc(g, h[n]);
+                    c.x[n].re += tv.re;
+                    c.x[n].im += tv.im;
+                }
+                if (tid == 0) {
+                    c.q[i].re += g.re;
+                    c.q[i].im += g.im;
+                }
+                __syncthreads();
+                if (variant == 2) {   // refresh only the rows of X_i (Theorem 2)
+                    residual_rows(c, d.xidx + d.xoff[i], d.xoff[i + 1] - d.xoff[i]);
+                    __syncthreads();
+                }
+            } else if (variant == 1) {
+                aggregate(c, [](int) { return true; }, a.schedule);
+            } else {
+                // orthogonal half-step on F with gamma = 1 (Prop. 1): the
+                // bands are disjoint, so all of F updates concurrently
+                for (int e = 0; e < d.nf; ++e) {
+                    int i = d.flist[e];
+                    R inv = (R)1 / c.nrm[i];
+                    cx<R> f = {c.r[i].re * inv, c.r[i].im * inv};
+                    const cx<R> *h = c.H + (int64_t)i * d.ldh;
+                    for (int n = d.vs[i] + tid; n < d.ve[i]; n += kThreads) {
+                        cx<R> tv = cmulc(f, h[n]);
+                        c.x[n].re += tv.re;
+                        c.x[n].im += tv.im;
+                    }
+                    if (tid == 0) {
+                        c.q[i].re += f.re;
+                        c.q[i].im += f.im;
+                    }
+                }
+                __syncthreads();
+                if (d.nv > 0) {
+                    residual_rows(c, d.vlist, d.nv);
+                    __syncthreads();
+                    const uint8_t *inf = d.inf;
+                    aggregate(c, [inf](int i) { return inf[i] == 0; }, a.schedule);
+                }
+            }
+            ++t;
+        }
+    }
+    __syncthreads();
+    for (int n = tid; n < N; n += kThreads) X[(int64_t)b * ldx_ + n] = c.x[n];
+    if (V)
+        for (int i = tid; i < K; i += kThreads) V[(int64_t)b * ldv_ + i] = c.q[i];
+    if (tid == 0) {
+        int64_t g = d.rhs_base + b;
+        if (a.iters) a.iters[g] = (int32_t)t;
+        if (a.relres) a.relres[g] = (float)rel;
+        if (a.flags) a.flags[g] = flags;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint right-hand side: Sadj[b, k] = sum_{n in VR_k} H[k, n] GX[b, n].
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_adjoint_rhs(const VrkDesc *descs)
+{
+    const VrkDesc &d = descs[blockIdx.y];
+    const int b = blockIdx.x;
+    if (b >= d.nrhs) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const cx<R> *H = reinterpret_cast<const cx<R> *>(d.H);
+    const cx<R> *g = reinterpret_cast<const cx<R> *>(d.GX) + (int64_t)b * d.ldgx;
+    cx<R> *out = reinterpret_cast<cx<R> *>(d.Sadj) + (int64_t)b * d.k;
+    for (int i = w; i < d.k; i += kWaves) {
+        R ar = 0, ai = 0;
+        for (int n = d.vs[i] + lane; n < d.ve[i]; n += 64) {
+            cx<R> t = cmul(H[(int64_t)i * d.ldh + n], g[n]);
+            ar += t.re;
+            ai += t.im;
+        }
+        ar = wave_sum(ar);
+        ai = wave_sum(ai);
+        if (lane == 0) out[i] = {ar, ai};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint gradients, one workgroup per (problem, user k):
+//   GH[k, n] = sum_b V[b,k] conj(GX[b,n] - Xadj[b,n]) - GS[b,k] conj(X[b,n])
+// on the VR band of k, and (by user 0) gxi = -Re sum_{b,k} conj(GS[b,k]) V[b,k].
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_adjoint_grads(const VrkDesc *descs)
+{
+    __shared__ R red[kWaves];
+    const VrkDesc &d = descs[blockIdx.y];
+    const int k = blockIdx.x;
+    if (k >= d.k) return;
+    const cx<R> *V = reinterpret_cast<const cx<R> *>(d.V);
+    const cx<R> *GS = reinterpret_cast<const cx<R> *>(d.GS);
+    const cx<R> *GX = reinterpret_cast<const cx<R> *>(d.GX);
+    const cx<R> *XA = reinterpret_cast<const cx<R> *>(d.Xadj);
+    const cx<R> *X = reinterpret_cast<const cx<R> *>(d.X);
+    cx<R> *GH = reinterpret_cast<cx<R> *>(d.GH) + (int64_t)k * d.ldgh;
+    for (int n = d.vs[k] + threadIdx.x; n < d.ve[k]; n += kThreads) {
+        R ar = 0, ai = 0;
+        for (int b = 0; b < d.nrhs; ++b) {
+            cx<R> v = V[(int64_t)b * d.ldv + k], mu = GS[(int64_t)b * d.ldgs + k];
+            cx<R> gx = GX[(int64_t)b * d.ldgx + n], xa = XA[(int64_t)b * d.nt + n];
+            cx<R> xv = X[(int64_t)b * d.ldx + n];
+            cx<R> t1 = cmulc(v, cx<R>{gx.re - xa.re, gx.im - xa.im});
+            cx<R> t2 = cmulc(mu, xv);
+            ar += t1.re - t2.re;
+            ai += t1.im - t2.im;
+        }
+        GH[n] = {ar, ai};
+    }
+    if (k == 0) {
+        R acc = 0;
+        int64_t tot = (int64_t)d.nrhs * d.k;
+        for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+            int b = (int)(e / d.k), kk = (int)(e % d.k);
+            cx<R> mu = GS[(int64_t)b * d.ldgs + kk], v = V[(int64_t)b * d.ldv + kk];
+            acc += mu.re * v.re + mu.im * v.im;
+        }
+        acc = wave_sum(acc);
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (lane == 0) red[w] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            R t = 0;
+            for (int i = 0; i < kWaves; ++i) t += red[i];
+            *d.gxi = -(double)t;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t vrk_launch_norms(const VrkDesc *desc, int32_t nprob, int32_t dtype, hipStream_t s)
+{
+    if (dtype == 1) hipLaunchKernelGGL(k_norms<double>, dim3(nprob), dim3(kThreads), 0, s, desc);
+    else hipLaunchKernelGGL(k_norms<float>, dim3(nprob), dim3(kThreads), 0, s, desc);
+    return hipGetLastError();
+}
+
+hipError_t vrk_launch_pack(const VrkDesc *desc, int32_t nprob, int64_t max_tiles, hipStream_t s)
+{
+    if (max_tiles <= 0) return hipSuccess;
+    unsigned gx = (unsigned)((max_tiles + kWaves - 1) / kWaves);
+    hipLaunchKernelGGL(k_pack, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
+    return hipGetLastError();
+}
+
+size_t vrk_vec_lds_bytes(int32_t dtype, int32_t nt, int32_t k)
+{
+    size_t rb = dtype == 1 ? 8 : 4;
+    return (size_t)(2 * nt + 4 * k) * 2 * rb + (size_t)(2 * k) * rb + 4 * kWaves * rb + 64;
+}
+
+hipError_t vrk_launch_vec_solve(const VrkSolveArgs &a, size_t lds_bytes, hipStream_t s)
+{
+    dim3 grid((unsigned)a.max_rhs, (unsigned)a.nprob);
+    hipError_t e;
+    if (a.dtype == 1) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_vec_solve<double>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_vec_solve<double>, grid, dim3(kThreads), lds_bytes, s, a);
+    } else {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_vec_solve<float>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_vec_solve<float>, grid, dim3(kThreads), lds_bytes, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t vrk_launch_adjoint_rhs(const VrkDesc *desc, int32_t nprob, int32_t max_rhs, int32_t dtype,
+                                  hipStream_t s)
+{
+    dim3 grid((unsigned)max_rhs, (unsigned)nprob);
+    if (dtype == 1) hipLaunchKernelGGL(k_adjoint_rhs<double>, grid, dim3(kThreads), 0, s, desc);
+    else hipLaunchKernelGGL(k_adjoint_rhs<float>, grid, dim3(kThreads), 0, s, desc);
+    return hipGetLastError();
+}
+
+hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t max_k, int32_t dtype,
+                                    hipStream_t s)
+{
+    dim3 grid((unsigned)max_k, (unsigned)nprob);
+    if (dtype == 1) hipLaunchKernelGGL(k_adjoint_grads<double>, grid, dim3(kThreads), 0, s, desc);
+    else hipLaunchKernelGGL(k_adjoint_grads<float>, grid, dim3(kThreads), 0, s, desc);
+    return hipGetLastError();
+}

@@ -1,0 +1,59 @@
+// Device-side problem descriptor shared by the host plan (plan.cpp) and the
+// kernels. Plain data only; every pointer is a device address inside the
+// caller's buffers or the bound workspace.
+#pragma once
+#include <stdint.h>
+
+// Antennas per block of the gather lists of the vector engine.
+#define VRK_GATHER_BLOCK 64
+// MFMA engine geometry: 16 users x 16 right-hand sides per output tile,
+// 16-antenna blocks, 4-deep reduction chunks of v_mfma_f32_16x16x4f32.
+#define VRK_TILE_RHS 16
+#define VRK_UB 16
+#define VRK_AB 16
+// users per group of the cross-wave residual reduction in the MFMA engine
+#define VRK_RGROUP 32
+
+enum { VRK_FLAG_CONVERGED = 1, VRK_FLAG_NONFINITE = 2, VRK_FLAG_MAXITER = 4 };
+
+struct VrkDesc {
+    int32_t nt, k, nrhs, nf;      // antennas, users, right-hand sides, |F|
+    int32_t nv, ncol, ngb, nub;   // |V|, colour classes, gather blocks, 16-user blocks
+    int32_t nab, ntile, pad0, pad1;  // 16-antenna blocks, RHS tiles of 16
+    double xi;
+    int64_t ldh, lds, ldx, ldv, ldgx, ldgh, ldgs;
+    int64_t rhs_base;             // offset of this problem's RHS in the stats arrays
+    const void *H;
+    const void *S;
+    void *X;
+    void *V;
+    const void *GX;
+    void *GH;
+    void *GS;
+    double *gxi;
+    void *Sadj;                   // workspace, B x K: right-hand side H g of the adjoint
+    void *Xadj;                   // workspace, B x Nt: x of the adjoint solve (H^H mu)
+    void *Vfwd;                   // V of the forward solve when the caller passed none
+    // VR tables, original user index unless noted
+    const int32_t *vs, *ve;       // VR [start, end)
+    const int32_t *xoff, *xidx;   // overlap sets X_k (CSR, includes k)
+    const int32_t *flist, *vlist; // F and V = complement, ascending
+    const uint8_t *inf;           // F mask
+    const int32_t *col_off, *col_users;  // colour classes (CSR)
+    const int32_t *gb_off, *gb_users;    // users meeting each 64-antenna block (CSR)
+    const int32_t *perm, *pos;    // perm[sorted] = user, pos[user] = sorted
+    void *nrm;                    // real[k]: ||a_i||^2 = ||H_i||^2 + xi (written at bind)
+    void *fro2;                   // real[1]: ||A||_F^2
+    // MFMA engine tables (sorted user order)
+    const int32_t *rab_lo, *rab_hi;  // per 16-user block: 16-antenna block range of its bands
+    const int64_t *ha_off;        // per 16-user block: first residual tile
+    const int32_t *ag_off, *ag_uc;   // per 16-antenna block: 4-user chunks meeting it (CSR)
+    const int32_t *fown;          // per antenna: sorted index of the F user covering it, or -1
+    void *HA;                     // residual tiles, 64 complex64 each
+    void *HG;                     // aggregation tiles (conjugated), 64 complex64 each
+};
+
+// One unit of work of the MFMA engine: a problem and a tile of 16 RHS.
+struct VrkWork {
+    int32_t prob, tile;
+};

@@ -1,0 +1,122 @@
+"""Host-side tests of libvrk.so (no GPU needed): the C ABI loads and exports
+every function include/vrk.h declares, argument validation, and the VR
+plan (overlap sets, orthogonal set F, colour classes) against the oracle
+and brute force."""
+from __future__ import annotations
+
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_10689_amd import vrk
+from tests.helpers import random_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "vrk.h")).read()
+    names = set(re.findall(r"^(?:const\s+)?[a-z_0-9]+\s*\*?\s*(vrk_[a-z_0-9]+)\(", hdr, re.M))
+    assert {"vrk_plan_create", "vrk_plan_bind", "vrk_solve", "vrk_solve_adjoint"} <= names
+    L = vrk.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def test_plan_matches_oracle_structure():
+    rng = np.random.default_rng(0)
+    for trial in range(30):
+        nt, k = int(rng.integers(16, 200)), int(rng.integers(1, 40))
+        H, vs, vl, xi = random_problem(rng, nt, k, lo=0, hi=max(1, nt // 2))
+        hp = vrk.host_plan(nt, k, vs, vl, xi, engine="vector")
+        f = np.zeros(k, dtype=bool)
+        f[hp.query(vrk.Q_FSET)] = True
+        assert np.array_equal(f, oracle.mis(H, vs, vl, xi))
+        xoff, xidx = hp.query(vrk.Q_XOFF), hp.query(vrk.Q_XIDX)
+        want = oracle.overlap_sets(H, vs, vl, xi)
+        for i in range(k):
+            assert np.array_equal(xidx[xoff[i]:xoff[i + 1]], want[i])
+        perm = hp.query(vrk.Q_PERM)
+        assert sorted(perm.tolist()) == list(range(k))
+        keys = [(vs[u], vs[u] + vl[u], u) for u in perm]
+        assert keys == sorted(keys)
+
+
+def _max_clique(vs, vl):
+    ev = []
+    for s, l in zip(vs, vl):
+        if l > 0:
+            ev += [(s, 1), (s + l, -1)]
+    ev.sort(key=lambda e: (e[0], e[1]))   # ends before starts at the same antenna
+    cur = best = 0
+    for _, d in ev:
+        cur += d
+        best = max(best, cur)
+    return best
+
+
+def test_colour_classes_are_disjoint_and_optimal():
+    rng = np.random.default_rng(1)
+    for trial in range(40):
+        nt, k = 120, int(rng.integers(1, 30))
+        H, vs, vl, xi = random_problem(rng, nt, k, lo=0, hi=60)
+        col = vrk.host_plan(nt, k, vs, vl, xi, engine="vector").query(vrk.Q_COLOUR)
+        for a, b in itertools.combinations(range(k), 2):
+            if col[a] == col[b]:
+                assert max(vs[a], vs[b]) >= min(vs[a] + vl[a], vs[b] + vl[b])
+        assert col.max() + 1 == max(1, _max_clique(vs, vl))
+
+
+@pytest.mark.parametrize("bad", ["xi0", "xinan", "vrout", "vrneg", "ldh", "tol", "iters", "variant"])
+def test_validation_errors(bad):
+    vs = np.array([0, 10], dtype=np.int32)
+    vl = np.array([8, 6], dtype=np.int32)
+    kw = dict(engine="vector")
+    nt, k, xi = 32, 2, 1.0
+    if bad == "xi0":
+        xi = 0.0
+    elif bad == "xinan":
+        xi = float("nan")
+    elif bad == "vrout":
+        vl[1] = 23
+    elif bad == "vrneg":
+        vs[0] = -1
+    elif bad == "tol":
+        kw["tol"] = -1.0
+    elif bad == "iters":
+        kw["max_iters"] = 0
+    elif bad == "variant":
+        kw["variant"] = 7
+    if bad == "ldh":
+        p = vrk.Problem()
+        p.nt, p.k, p.xi, p.H, p.ldh = nt, k, xi, 256, nt - 1
+        p.vr_start, p.vr_len = vs.ctypes.data, vl.ctypes.data
+        import ctypes as C
+        ws, h = C.c_size_t(), C.c_void_p()
+        o = vrk.options(**kw)
+        st = vrk.lib().vrk_plan_create(C.byref(p), 1, C.byref(o), C.byref(ws), C.byref(h))
+        assert st == 1
+        return
+    with pytest.raises(vrk.VrkError) as e:
+        vrk.host_plan(nt, k, vs, vl, xi, **kw)
+    assert e.value.status == 1
+
+
+def test_solve_before_bind_is_a_state_error():
+    import ctypes as C
+    vs = np.array([0], dtype=np.int32)
+    vl = np.array([4], dtype=np.int32)
+    p = vrk.Problem()
+    p.nt, p.k, p.xi, p.H, p.ldh = 8, 1, 1.0, 256, 8
+    p.vr_start, p.vr_len = vs.ctypes.data, vl.ctypes.data
+    o = vrk.options(engine="vector")
+    ws, h = C.c_size_t(), C.c_void_p()
+    assert vrk.lib().vrk_plan_create(C.byref(p), 1, C.byref(o), C.byref(ws), C.byref(h)) == 0
+    assert vrk.lib().vrk_solve(h, None, None, None, None) == 5
+    assert vrk.lib().vrk_solve_adjoint(h, None, None, None, None) == 5
+    assert vrk.lib().vrk_plan_bind(h, None, 0, None) == 3
+    vrk.lib().vrk_plan_destroy(h)
