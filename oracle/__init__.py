@@ -58,6 +58,7 @@ def _load():
             "orc_step_orthogonal": (None, [P, vp, vp, vp, vp]),
             "orc_step_aggregate": (C.c_int, [P, vp, vp, vp, vp]),
             "orc_select": (C.c_int, [C.c_int, C.c_int, vp, vp, f64, f64]),
+            "orc_num_threads": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -90,6 +91,11 @@ class Problem:
 def _check(st):
     if st != 0:
         raise ValueError("oracle rejected the arguments (status %d)" % st)
+
+
+def num_threads() -> int:
+    """OpenMP threads the batched oracle calls use."""
+    return int(_load().orc_num_threads())
 
 
 def philox4x64_10(ctr, key) -> np.ndarray:

@@ -589,3 +589,16 @@ int orc_select(int K, int rule, const cplx *r, const double *nrm, double fro2, d
 {
     return select_row(K, rule, r, nrm, fro2, u);
 }
+
+/* Threads an OpenMP parallel region of this library uses (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

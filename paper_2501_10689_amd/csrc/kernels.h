@@ -33,7 +33,7 @@ hipError_t vrk_launch_vec_solve(const VrkSolveArgs &a, size_t lds_bytes, hipStre
 
 // MFMA engine: 16 right-hand sides per workgroup (complex64).
 int vrk_mfma_supported(int32_t nt, int32_t waves);
-size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t waves);
+size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves);
 hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, int32_t nwork,
                                  int32_t waves, int32_t na, size_t lds_bytes, hipStream_t s);
 

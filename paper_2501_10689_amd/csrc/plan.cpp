@@ -373,7 +373,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         int32_t nap = 1;
         while (nap < na) nap *= 2;
         pl->na = nap;
-        pl->lds = vrk_mfma_lds_bytes(max_kpad, waves);
+        pl->lds = vrk_mfma_lds_bytes(max_kpad, max_nab, waves);
         if (pl->lds > 160 * 1024) {
             delete pl;
             return fail(VRK_EUNSUPPORTED, "MFMA engine needs %zu bytes of LDS for k=%d", pl->lds, max_k);

@@ -1,0 +1,132 @@
+"""GPU parity of the MFMA engine (16 RHS per workgroup, FP32 matrix cores)
+against the FP64 oracle, through the C ABI."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rel_err_rows, run_plan
+from tests.helpers import qpsk, random_problem
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = ["grk", "ahk", "vr_ogrk", "vr_oahk"]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_many_rhs_ragged_tiles(variant):
+    """Nt 1024, K 64 with 37 vectors: two full tiles of 16 and a ragged tail."""
+    d = synth.make_workload("many_rhs", nrhs=37)[0]
+    res, plan = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, engine="mfma")
+    assert plan.query(0, 5)[0] == 2   # MFMA engine chosen
+    g = res[0]
+    X, V = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+    err = rel_err_rows(g["X"], X)
+    print(variant, "max err %.2e" % err.max(), "iters", g["iters"].min(), g["iters"].max())
+    assert np.all(g["flags"] == oracle.F_CONVERGED)
+    assert err.max() <= 1e-4
+    assert rel_err_rows(g["V"], V).max() <= 1e-4
+    assert np.all(g["relres"] <= 1e-5)
+
+
+@pytest.mark.parametrize("nt,k,nrhs", [(1000, 20, 21), (200, 16, 16), (512, 37, 33), (2048, 128, 17),
+                                       (64, 100, 16), (1536, 5, 48)])
+@pytest.mark.parametrize("variant", ["grk", "vr_oahk", "ahk"])
+def test_shapes_padding(nt, k, nrhs, variant):
+    """Nt not a multiple of 16, K not a multiple of 16, K > Nt, tiny K."""
+    rng = np.random.default_rng(nt + k)
+    H, vs, vl, xi = random_problem(rng, nt, k, lo=max(1, nt // 8), hi=max(1, nt // 2))
+    S = qpsk(rng, (nrhs, k))
+    res, _ = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="mfma", tol=1e-5)
+    X, _ = oracle.rzf(H, vs, vl, S, xi)
+    g = res[0]
+    assert np.all(g["flags"] == oracle.F_CONVERGED), g["flags"]
+    assert rel_err_rows(g["X"], X).max() <= 1e-4
+
+
+def test_edge_cases_mfma():
+    rng = np.random.default_rng(9)
+    drops = []
+    H, vs, vl, xi = random_problem(rng, 96, 12)
+    vl[2] = 0
+    H[2] = 0
+    S = qpsk(rng, (18, 12))
+    S[1] = 0
+    drops.append((H, vs, vl, S, xi))
+    H3, vs3, vl3, xi3 = random_problem(rng, 256, 8, disjoint=True)
+    drops.append((H3, vs3, vl3, qpsk(rng, (16, 8)), xi3))
+    for variant in VARIANTS:
+        res, _ = run_plan(drops, variant=variant, engine="mfma", tol=1e-6)
+        for jd, (H, vs, vl, S, xi) in enumerate(drops):
+            X, _ = oracle.rzf(H, vs, vl, S, xi)
+            g = res[jd]
+            assert np.all(g["flags"] == oracle.F_CONVERGED), (variant, jd)
+            nz = np.linalg.norm(X, axis=1) > 0
+            assert rel_err_rows(g["X"], X)[nz].max() <= 1e-4, (variant, jd)
+        assert res[0]["iters"][1] == 0 and not res[0]["X"][1].any()
+        if variant == "vr_oahk":
+            assert np.all(res[1]["iters"] == 1)
+
+
+def test_flags_mfma():
+    rng = np.random.default_rng(10)
+    H, vs, vl, xi = random_problem(rng, 128, 16)
+    S = qpsk(rng, (16, 16))
+    res, _ = run_plan([(H, vs, vl, S, xi)], variant="ahk", engine="mfma", tol=1e-9, max_iters=2)
+    assert np.all(res[0]["flags"] == oracle.F_MAXITER) and np.all(res[0]["iters"] == 2)
+    Hn = H.copy()
+    Hn[3, vs[3]] = np.nan
+    res, _ = run_plan([(Hn, vs, vl, S, xi)], variant="vr_oahk", engine="mfma")
+    assert np.all(res[0]["flags"] & oracle.F_NONFINITE)
+
+
+def test_mfma_matches_vector_engine_iterations():
+    """Both engines run the same method: aggregated variants need the same
+    number of iterations (to within one, from FP32 rounding order)."""
+    d = synth.make_workload("many_rhs", nrhs=32, nt=512, k=32)[0]
+    for variant in ["ahk", "vr_oahk"]:
+        a, _ = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, engine="mfma")
+        b, _ = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, engine="vector")
+        assert np.abs(a[0]["iters"] - b[0]["iters"]).max() <= 1
+        assert rel_err_rows(a[0]["X"], b[0]["X"]).max() <= 5e-5
+
+
+def test_uneven_batch_mfma():
+    drops = [(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+             for d in synth.make_workload("uneven", drops=6, nrhs=24)]
+    for variant in ["vr_oahk", "grk"]:
+        res, _ = run_plan(drops, variant=variant, engine="mfma", tol=1e-5)
+        for jd, (H, vs, vl, S, xi) in enumerate(drops):
+            X, _ = oracle.rzf(H, vs, vl, S, xi)
+            assert np.all(res[jd]["flags"] == oracle.F_CONVERGED), (variant, jd)
+            assert rel_err_rows(res[jd]["X"], X).max() <= 1e-4, (variant, jd)
+
+
+def test_full_size_many_rhs_every_vector():
+    """The benchmarked launch: Nt 1024, K 64, 4096 vectors, VR-OAHK, SNR
+    10 dB. Every one of the 4096 x is checked against the Cholesky RZF."""
+    d = synth.make_workload("many_rhs")[0]
+    res, _ = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant="vr_oahk", engine="auto")
+    X, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+    err = rel_err_rows(res[0]["X"], X)
+    print("full size: max err %.2e mean iters %.2f" % (err.max(), res[0]["iters"].mean()))
+    assert np.all(res[0]["flags"] == oracle.F_CONVERGED)
+    assert err.max() <= 1e-4
+
+
+def test_adjoint_mfma_matches_closed_form():
+    rng = np.random.default_rng(11)
+    H, vs, vl, xi = random_problem(rng, 256, 16)
+    S = qpsk(rng, (32, 16))
+    X, _ = oracle.rzf(H, vs, vl, S, xi)
+    G = 2.0 * ((X @ H.T - S) @ H.conj() + 0.1 * X) / 32
+    gH, gS, gxi = oracle.rzf_grad(H, vs, vl, S, xi, G)
+    res, _ = run_plan([(H, vs, vl, S, xi)], variant="vr_oahk", engine="mfma", tol=1e-6, adjoint_g=[G])
+    g = res[0]
+    m = np.abs(H) > 0
+    assert np.all(g["adj_flags"] == oracle.F_CONVERGED)
+    assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m])
+    assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS)
+    assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
