@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=4096)
     ap.add_argument("--snr", type=float, default=10.0)
     ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--tile-waves", type=int, default=0, choices=[0, 8, 16])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -89,7 +90,8 @@ def main():
     GH = torch.zeros_like(H)
     GS = torch.zeros_like(S)
     gxi = torch.zeros(1, dtype=torch.float64, device=dev)
-    opts = vrk.options(variant=args.variant, dtype="c64", engine=args.engine, tol=args.tol)
+    opts = vrk.options(variant=args.variant, dtype="c64", engine=args.engine, tol=args.tol,
+                       tile_waves=args.tile_waves)
     plan = vrk.Plan([vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X, V, GX, GH, GS, gxi)], opts)
     eng = plan.query(0, vrk.Q_ENGINE)
     engine = {1: "vector", 2: "mfma"}[int(eng[0])]
@@ -157,7 +159,8 @@ def main():
         "config": {"workload": "single channel, many symbols: Nt=1024, K=64, VR U[256,512], "
                                "LoS+CN(0,0.1), %d QPSK vectors, SNR %g dB, tol %g; fwd+adjoint"
                                % (B, args.snr, args.tol),
-                   "variant": args.variant, "engine": engine, "nrhs": B, "nt": N, "k": K},
+                   "variant": args.variant, "engine": engine, "tile_waves": int(eng[2]),
+                   "nrhs": B, "nt": N, "k": K},
         "roofline": roof,
         "accuracy": {"max_rel_err": float(err.max()), "mean_rel_err": float(err.mean()),
                      "all_converged": bool(np.all(fl == 1)), "mean_iters": float(it.mean()),
@@ -171,7 +174,8 @@ def main():
             Xv = torch.zeros_like(X)
             Vv = torch.zeros_like(V)
             pv = vrk.Plan([vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, Xv, Vv)],
-                          vrk.options(variant=var, dtype="c64", engine=args.engine, tol=args.tol))
+                          vrk.options(variant=var, dtype="c64", engine=args.engine, tol=args.tol,
+                                      tile_waves=args.tile_waves))
             sv = pv.stats_buffers()
             pv.solve(stream=stream, stats=sv)
             torch.cuda.synchronize()

@@ -29,12 +29,13 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// acc += A * B for complex operands held one per lane (4 real products).
+// acc += A * B for complex operands held one per lane (4 real products,
+// alternating accumulators so consecutive MFMAs are independent).
 __device__ __forceinline__ void cmfma(f4 &re, f4 &im, float2 a, float2 b)
 {
     re = mfma(a.x, b.x, re);
-    re = mfma(-a.y, b.y, re);
     im = mfma(a.x, b.y, im);
+    re = mfma(-a.y, b.y, re);
     im = mfma(a.y, b.x, im);
 }
 
@@ -230,28 +231,52 @@ __device__ __forceinline__ void tile_phi(const TileCtx &c, int sel)
     __syncthreads();
 }
 
-// Aggregated projection (update4): P = H^H phi per antenna block; pass 1
-// gives ||P||^2 per column and gamma = num / (||P||^2 + xi ||phi||^2);
-// pass 2 recomputes P and applies x += gamma P in registers; q += gamma phi.
+// P = H^H phi on antenna block ab: chunks e of that block's list, two at a
+// time so the loads of one pair overlap the MFMAs of the other.
+__device__ __forceinline__ void agg_block(const TileCtx &c, int ab, f4 &pr, f4 &pi)
+{
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    const VrkDesc &d = *c.d;
+    pr = f4{0.f, 0.f, 0.f, 0.f};
+    pi = f4{0.f, 0.f, 0.f, 0.f};
+    const int e0 = c.L.agoff[ab], e1 = c.L.agoff[ab + 1];
+    int e = e0;
+#pragma unroll 1
+    for (; e + 1 < e1; e += 2) {
+        const int uc0 = d.ag_uc[e], uc1 = d.ag_uc[e + 1];
+        float2 h0 = c.HG[(int64_t)e * 64 + lane], h1 = c.HG[(int64_t)(e + 1) * 64 + lane];
+        float2 f0 = c.L.R[(4 * uc0 + g) * 16 + j], f1 = c.L.R[(4 * uc1 + g) * 16 + j];
+        cmfma(pr, pi, h0, f0);
+        cmfma(pr, pi, h1, f1);
+    }
+    if (e < e1) {
+        const int uc = d.ag_uc[e];
+        cmfma(pr, pi, c.HG[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
+    }
+}
+
+// Aggregated projection (update4): P = H^H phi per antenna block gives
+// ||P||^2 per column and gamma = num / (||P||^2 + xi ||phi||^2), then
+// x += gamma P in registers and q += gamma phi. With at most 8 blocks per
+// wave set P stays in registers between the two when x and P together take
+// at most a quarter of the per-wave register budget (2048 / W); otherwise
+// P is recomputed.
 template <int W, int NA>
 __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA], f4 (&xq)[NA])
 {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
+    constexpr bool kKeepP = 16 * NA * W <= 512;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15;
     const int er = tid >> 4, rows_per_pass = W * 4;
-    const VrkDesc &d = *c.d;
     float pn = 0.f;
+    f4 pr[kKeepP ? NA : 1], pi[kKeepP ? NA : 1];
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
         const int ab = w + W * t;
+        const int ts = kKeepP ? t : 0;
         if (ab < c.nab) {
-            f4 pr = {0.f, 0.f, 0.f, 0.f}, pi = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-            for (int e = c.L.agoff[ab]; e < c.L.agoff[ab + 1]; ++e) {
-                const int uc = d.ag_uc[e];
-                cmfma(pr, pi, c.HG[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
-            }
+            agg_block(c, ab, pr[ts], pi[ts]);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) pn += pr[r] * pr[r] + pi[r] * pi[r];
+            for (int r = 0; r < 4; ++r) pn += pr[ts][r] * pr[ts][r] + pi[ts][r] * pi[ts][r];
         }
     }
     pn = col_sum<W>(pn, c.L.red);
@@ -266,14 +291,15 @@ __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA], f
     for (int t = 0; t < NA; ++t) {
         const int ab = w + W * t;
         if (ab < c.nab) {
-            f4 pr = {0.f, 0.f, 0.f, 0.f}, pi = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-            for (int e = c.L.agoff[ab]; e < c.L.agoff[ab + 1]; ++e) {
-                const int uc = d.ag_uc[e];
-                cmfma(pr, pi, c.HG[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
+            if constexpr (kKeepP) {
+                xr[t] += gm * pr[t];
+                xq[t] += gm * pi[t];
+            } else {
+                f4 qr, qi;
+                agg_block(c, ab, qr, qi);
+                xr[t] += gm * qr;
+                xq[t] += gm * qi;
             }
-            xr[t] += gm * pr;
-            xq[t] += gm * pi;
         }
     }
     for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
@@ -547,11 +573,13 @@ hipError_t launch_variant(const VrkSolveArgs &a, const VrkWork *work, int32_t nw
 }  // namespace
 
 // x of one tile lives in registers: at most 16 antenna blocks per wave with
-// 8 waves (two waves per SIMD), i.e. Nt <= 2048.
+// 8 waves (two waves per SIMD) and 8 with 16 waves (four per SIMD); both
+// give Nt <= 2048.
 int vrk_mfma_supported(int32_t nt, int32_t waves)
 {
     int nab = (nt + VRK_AB - 1) / VRK_AB;
     if (waves == 8) return nab <= 16 * 8;
+    if (waves == 16) return nab <= 8 * 16;
     return 0;
 }
 
@@ -571,6 +599,13 @@ hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, int
         case 4: return launch_variant<8, 4>(a, work, nwork, lds, s);
         case 8: return launch_variant<8, 8>(a, work, nwork, lds, s);
         case 16: return launch_variant<8, 16>(a, work, nwork, lds, s);
+        }
+    } else if (waves == 16) {
+        switch (na) {
+        case 1: return launch_variant<16, 1>(a, work, nwork, lds, s);
+        case 2: return launch_variant<16, 2>(a, work, nwork, lds, s);
+        case 4: return launch_variant<16, 4>(a, work, nwork, lds, s);
+        case 8: return launch_variant<16, 8>(a, work, nwork, lds, s);
         }
     }
     return hipErrorInvalidValue;

@@ -89,6 +89,9 @@ struct vrk_plan {
     int32_t max_rhs = 0, max_k = 0;
     bool adjoint_ready = false;
     std::vector<VrkWork> work;
+    std::vector<int4> gtiles;   // band tiles of the adjoint gradient (MFMA engine)
+    size_t o_gtiles = 0;
+    int32_t max_nub = 0;
     std::vector<uint8_t> image;
     uint8_t *d_ws = nullptr;
     bool bound = false;
@@ -348,7 +351,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     }
     pl->adjoint_ready = all_adj;
     // engine choice
-    int32_t waves = o.tile_waves ? o.tile_waves : 8;
+    int32_t waves = o.tile_waves ? o.tile_waves : 16;   // four waves per SIMD by default
     bool mfma_ok = o.dtype == VRK_C64 && vrk_mfma_supported(max_nt, waves);
     int32_t eng = o.engine;
     if (eng == VRK_ENGINE_AUTO) eng = (mfma_ok && min_rhs >= VRK_TILE_RHS) ? VRK_ENGINE_MFMA : VRK_ENGINE_VECTOR;
@@ -385,12 +388,25 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             const ProbPlan &x = pl->pp[a.prob], &y = pl->pp[b.prob];
             return x.n_ha + x.n_hg > y.n_ha + y.n_hg;
         });
+        for (int i = 0; i < nprob; ++i) pl->max_nub = std::max(pl->max_nub, pl->pp[i].nub);
+        if (all_adj)
+            for (int i = 0; i < nprob; ++i) {
+                const ProbPlan &q = pl->pp[i];
+                int first = 1;
+                for (int ub = 0; ub < q.nub; ++ub)
+                    for (int ab = q.rab_lo[ub]; ab < q.rab_hi[ub]; ++ab) {
+                        pl->gtiles.push_back(make_int4(i, ub, ab, first));
+                        first = 0;
+                    }
+                if (first) pl->gtiles.push_back(make_int4(i, -1, 0, 1));
+            }
     }
     // workspace carving
     const int32_t eb = elem_bytes(o.dtype), rb = o.dtype == VRK_C128 ? 8 : 4;
     Carver cv;
     pl->o_desc = cv.take(sizeof(VrkDesc) * nprob);
     pl->o_work = cv.take(sizeof(VrkWork) * std::max<size_t>(1, pl->work.size()));
+    pl->o_gtiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->gtiles.size()));
     for (auto &q : pl->pp) {
         const int K = q.p.k;
         q.o_vs = cv.take(4 * K);
@@ -514,6 +530,8 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());
     if (!pl->work.empty())
         std::memcpy(pl->image.data() + pl->o_work, pl->work.data(), sizeof(VrkWork) * pl->work.size());
+    if (!pl->gtiles.empty())
+        std::memcpy(pl->image.data() + pl->o_gtiles, pl->gtiles.data(), sizeof(int4) * pl->gtiles.size());
     hipError_t e = hipMemcpyAsync(base, pl->image.data(), pl->table_end, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan tables)");
     const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(base + pl->o_desc);
@@ -576,11 +594,16 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(pl->d_ws + pl->o_desc);
     if (pl->total_rhs == 0) return VRK_OK;
-    hipError_t e = vrk_launch_adjoint_rhs(dd, (int32_t)pl->pp.size(), pl->max_rhs, pl->opt.dtype, s);
+    const bool mf = pl->engine == VRK_ENGINE_MFMA;
+    const VrkWork *dw = reinterpret_cast<const VrkWork *>(pl->d_ws + pl->o_work);
+    hipError_t e = mf ? vrk_launch_adjoint_rhs_mfma(dd, dw, (int32_t)pl->work.size(), pl->max_nub, s)
+                      : vrk_launch_adjoint_rhs(dd, (int32_t)pl->pp.size(), pl->max_rhs, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint right-hand side kernel");
     vrk_status st = run_solve(pl, stream, d_iters, d_relres, d_flags, 1);
     if (st != VRK_OK) return st;
-    e = vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
+    e = mf ? vrk_launch_adjoint_grads_mfma(dd, reinterpret_cast<const int4 *>(pl->d_ws + pl->o_gtiles),
+                                           (int32_t)pl->gtiles.size(), s)
+           : vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient kernel");
     return VRK_OK;
 }

@@ -15,11 +15,14 @@ pytestmark = pytest.mark.gpu
 VARIANTS = ["grk", "ahk", "vr_ogrk", "vr_oahk"]
 
 
+@pytest.mark.parametrize("waves", [8, 16])
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_many_rhs_ragged_tiles(variant):
-    """Nt 1024, K 64 with 37 vectors: two full tiles of 16 and a ragged tail."""
+def test_many_rhs_ragged_tiles(variant, waves):
+    """Nt 1024, K 64 with 37 vectors: two full tiles of 16 and a ragged tail,
+    with 8 and 16 waves per workgroup."""
     d = synth.make_workload("many_rhs", nrhs=37)[0]
-    res, plan = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, engine="mfma")
+    res, plan = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, engine="mfma",
+                         tile_waves=waves)
     assert plan.query(0, 5)[0] == 2   # MFMA engine chosen
     g = res[0]
     X, V = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
@@ -34,12 +37,14 @@ def test_many_rhs_ragged_tiles(variant):
 @pytest.mark.parametrize("nt,k,nrhs", [(1000, 20, 21), (200, 16, 16), (512, 37, 33), (2048, 128, 17),
                                        (64, 100, 16), (1536, 5, 48)])
 @pytest.mark.parametrize("variant", ["grk", "vr_oahk", "ahk"])
-def test_shapes_padding(nt, k, nrhs, variant):
+@pytest.mark.parametrize("waves", [8, 16])
+def test_shapes_padding(nt, k, nrhs, variant, waves):
     """Nt not a multiple of 16, K not a multiple of 16, K > Nt, tiny K."""
     rng = np.random.default_rng(nt + k)
     H, vs, vl, xi = random_problem(rng, nt, k, lo=max(1, nt // 8), hi=max(1, nt // 2))
     S = qpsk(rng, (nrhs, k))
-    res, _ = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="mfma", tol=1e-5)
+    res, _ = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="mfma", tol=1e-5,
+                      tile_waves=waves)
     X, _ = oracle.rzf(H, vs, vl, S, xi)
     g = res[0]
     assert np.all(g["flags"] == oracle.F_CONVERGED), g["flags"]
@@ -116,12 +121,15 @@ def test_full_size_many_rhs_every_vector():
     assert err.max() <= 1e-4
 
 
-def test_adjoint_mfma_matches_closed_form():
-    rng = np.random.default_rng(11)
-    H, vs, vl, xi = random_problem(rng, 256, 16)
-    S = qpsk(rng, (32, 16))
+@pytest.mark.parametrize("nt,k,nrhs", [(256, 16, 32), (1000, 40, 37), (64, 20, 16)])
+def test_adjoint_mfma_matches_closed_form(nt, k, nrhs):
+    """MFMA adjoint (b = H g, adjoint solve, band-tile gradient GEMM) vs the
+    oracle's closed-form gradient, ragged RHS count and padded users."""
+    rng = np.random.default_rng(11 + nt)
+    H, vs, vl, xi = random_problem(rng, nt, k)
+    S = qpsk(rng, (nrhs, k))
     X, _ = oracle.rzf(H, vs, vl, S, xi)
-    G = 2.0 * ((X @ H.T - S) @ H.conj() + 0.1 * X) / 32
+    G = 2.0 * ((X @ H.T - S) @ H.conj() + 0.1 * X) / nrhs
     gH, gS, gxi = oracle.rzf_grad(H, vs, vl, S, xi, G)
     res, _ = run_plan([(H, vs, vl, S, xi)], variant="vr_oahk", engine="mfma", tol=1e-6, adjoint_g=[G])
     g = res[0]
@@ -130,3 +138,22 @@ def test_adjoint_mfma_matches_closed_form():
     assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m])
     assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS)
     assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
+
+
+def test_adjoint_mfma_uneven_batch():
+    """One launch of each adjoint kernel over several drops of uneven shape."""
+    ds = synth.make_workload("uneven", drops=4, nrhs=20)
+    drops, Gs, refs = [], [], []
+    for d in ds:
+        X, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+        G = 2.0 * ((X @ d.H.T - d.S) @ d.H.conj() + 0.1 * X) / d.nrhs
+        drops.append((d.H, d.vr_start, d.vr_len, d.S, d.xi))
+        Gs.append(G)
+        refs.append(oracle.rzf_grad(d.H, d.vr_start, d.vr_len, d.S, d.xi, G))
+    res, _ = run_plan(drops, variant="vr_oahk", engine="mfma", tol=1e-6, adjoint_g=Gs)
+    for jd, (gH, gS, gxi) in enumerate(refs):
+        g = res[jd]
+        m = np.abs(drops[jd][0]) > 0
+        assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m]), jd
+        assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS), jd
+        assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi), jd
