@@ -113,8 +113,10 @@ typedef struct {
     int64_t max_iters;   /* > 0: row updates (greedy) or iterations (aggregated) */
     uint64_t seed;       /* Philox key word 0 */
     int32_t schedule;    /* vrk_schedule */
-    int32_t tile_waves;  /* MFMA engine waves per workgroup: 0 (auto), 4, 8 or 16 */
-    int32_t persistent;  /* MFMA engine: 1 = persistent grid with a work queue */
+    int32_t tile_waves;  /* MFMA engine waves per workgroup: 0 (auto = 16), 8 or 16 */
+    int32_t persistent;  /* MFMA engine: 1 = one workgroup per resident slot, draining
+                            per-XCD work queues (drops assigned by cost); 0 = one
+                            workgroup per 16-RHS tile */
     int32_t reserved;
 } vrk_options;
 
@@ -155,6 +157,25 @@ vrk_status vrk_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relr
 vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres,
                              int32_t *d_flags);
 
+/* Autotuner. Picks the execution configuration of a batch by timing it
+ * on the device: for complex64 the MFMA engine with 8 or 16 waves per
+ * workgroup, each with one workgroup per 16-RHS tile or the persistent
+ * per-XCD work queues, and the vector engine with the gather and
+ * colour-class schedules; for complex128 the vector engine's two
+ * schedules. Each candidate is planned, bound to d_ws, run once and timed
+ * over `reps` solves with HIP events on `stream` (the call synchronises
+ * the stream; it is not graph-capturable). The caller's X and V are
+ * overwritten. On return opt's engine, tile_waves, persistent and
+ * schedule hold the fastest candidate and *best_ms its time per solve.
+ * With d_ws null nothing runs: *ws_needed gets the workspace size the
+ * largest candidate needs. cache_path (nullable) names a text file of
+ * previous results keyed by the batch's shape signature (variant, dtype,
+ * and per problem Nt, K, B and band size); a hit returns the cached choice
+ * without timing, a miss appends the new result. */
+vrk_status vrk_autotune(const vrk_problem *probs, int32_t nprob, vrk_options *opt, void *d_ws,
+                        size_t ws_bytes, void *stream, const char *cache_path, int32_t reps,
+                        size_t *ws_needed, float *best_ms);
+
 /* Plan inspection (host only), for tests and tooling. Writes up to `cap`
  * int32 values of the requested table of problem `prob` into out and
  * returns the table length, or -1 on a bad argument. */
@@ -164,7 +185,7 @@ typedef enum {
     VRK_Q_COLOUR = 2,    /* colour class of each user */
     VRK_Q_XOFF = 3,      /* CSR offsets of X_k, length k + 1 */
     VRK_Q_XIDX = 4,      /* CSR indices of X_k (ascending, includes k) */
-    VRK_Q_ENGINE = 5,    /* [engine, schedule, tile_waves, lds_bytes] chosen */
+    VRK_Q_ENGINE = 5,    /* [engine, schedule, tile_waves, lds_bytes, persistent, grid] chosen */
     VRK_Q_TILES = 6      /* [residual chunks, aggregation chunks, band MACs] per problem */
 } vrk_query;
 int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *out, int64_t cap);

@@ -6,6 +6,7 @@ from .vrk import (  # noqa: F401
     Plan,
     ProblemSpec,
     VrkError,
+    autotune,
     host_plan,
     lib,
     options,

@@ -29,13 +29,19 @@ hipError_t vrk_launch_pack(const VrkDesc *desc, int32_t nprob, int64_t max_tiles
 
 // Vector engine: one workgroup per right-hand side.
 size_t vrk_vec_lds_bytes(int32_t dtype, int32_t nt, int32_t k);
+hipError_t vrk_prepare_vec_solve(int32_t dtype, size_t lds_bytes);   // LDS attribute, once at bind
 hipError_t vrk_launch_vec_solve(const VrkSolveArgs &a, size_t lds_bytes, hipStream_t s);
 
 // MFMA engine: 16 right-hand sides per workgroup (complex64).
 int vrk_mfma_supported(int32_t nt, int32_t waves);
 size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves);
-hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, int32_t nwork,
-                                 int32_t waves, int32_t na, size_t lds_bytes, hipStream_t s);
+// mode 0 launches (grid = work items, or the persistent grid when q.count is
+// set); mode 1 only sets the kernel's LDS attribute and writes its resident
+// workgroups per CU to *blocks_per_cu (called once at bind, never during
+// graph capture).
+hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid,
+                                 int32_t waves, int32_t na, size_t lds_bytes, hipStream_t s, int mode,
+                                 int *blocks_per_cu);
 
 // Adjoint pieces: b = H g (right-hand side of the adjoint solve) and the
 // gradient assembly.

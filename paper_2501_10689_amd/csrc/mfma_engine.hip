@@ -311,10 +311,8 @@ __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA], f
 }
 
 template <int W, int NA, int VARIANT>
-__global__ void __launch_bounds__(W * 64) k_mfma_solve(VrkSolveArgs a, const VrkWork *work)
+__device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork wk, char *smem)
 {
-    extern __shared__ __align__(16) char smem[];
-    const VrkWork wk = work[blockIdx.x];
     const VrkDesc &d = a.desc[wk.prob];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
     TileCtx c;
@@ -547,25 +545,77 @@ __global__ void __launch_bounds__(W * 64) k_mfma_solve(VrkSolveArgs a, const Vrk
     }
 }
 
+
+// Next work item of this workgroup: its own XCD's queue first, then the
+// others in turn; -1 when every queue is drained. Queue q holds the work
+// items [qbase[q], qbase[q] + qsize[q]) and its counter qcount[q].
+__device__ __forceinline__ int next_item(const VrkQueue &q, int *sh)
+{
+    if (threadIdx.x == 0) {
+        const int x = blockIdx.x % VRK_NQUEUE;
+        int item = -1;
+        for (int s = 0; s < VRK_NQUEUE && item < 0; ++s) {
+            const int qi = (x + s) % VRK_NQUEUE;
+            const int pos = atomicAdd(q.count + qi, 1);
+            if (pos < q.size[qi]) item = q.base[qi] + pos;
+        }
+        *sh = item;
+    }
+    __syncthreads();
+    const int item = *sh;
+    __syncthreads();
+    return item;
+}
+
 template <int W, int NA, int VARIANT>
-hipError_t launch_one(const VrkSolveArgs &a, const VrkWork *work, int32_t nwork, size_t lds, hipStream_t s)
+__global__ void __launch_bounds__(W * 64) k_mfma_solve(VrkSolveArgs a, const VrkWork *work, VrkQueue q)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int sh_item;
+    if (!q.count) {   // one workgroup per work item
+        solve_item<W, NA, VARIANT>(a, work[blockIdx.x], smem);
+        return;
+    }
+    // persistent: drain the work queues
+    for (;;) {
+        const int item = next_item(q, &sh_item);
+        if (item < 0) break;
+        solve_item<W, NA, VARIANT>(a, work[item], smem);
+        __syncthreads();
+    }
+}
+
+__global__ void k_queue_reset(int *count)
+{
+    if (threadIdx.x < VRK_NQUEUE) count[threadIdx.x] = 0;
+}
+
+// Launch (mode 0), set the LDS attribute and report occupancy (mode 1).
+template <int W, int NA, int VARIANT>
+hipError_t launch_one(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid, size_t lds,
+                      hipStream_t s, int mode, int *blocks_per_cu)
 {
     auto kern = k_mfma_solve<W, NA, VARIANT>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nwork), dim3(W * 64), lds, s, a, work);
+    if (mode == 1) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, W * 64, lds);
+    }
+    if (q.count) hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q.count);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(W * 64), lds, s, a, work, q);
     return hipGetLastError();
 }
 
 template <int W, int NA>
-hipError_t launch_variant(const VrkSolveArgs &a, const VrkWork *work, int32_t nwork, size_t lds, hipStream_t s)
+hipError_t launch_variant(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid, size_t lds,
+                          hipStream_t s, int mode, int *bpc)
 {
     switch (a.variant) {
-    case 0: return launch_one<W, NA, 0>(a, work, nwork, lds, s);
-    case 1: return launch_one<W, NA, 1>(a, work, nwork, lds, s);
-    case 2: return launch_one<W, NA, 2>(a, work, nwork, lds, s);
-    case 3: return launch_one<W, NA, 3>(a, work, nwork, lds, s);
+    case 0: return launch_one<W, NA, 0>(a, work, q, grid, lds, s, mode, bpc);
+    case 1: return launch_one<W, NA, 1>(a, work, q, grid, lds, s, mode, bpc);
+    case 2: return launch_one<W, NA, 2>(a, work, q, grid, lds, s, mode, bpc);
+    case 3: return launch_one<W, NA, 3>(a, work, q, grid, lds, s, mode, bpc);
     }
     return hipErrorInvalidValue;
 }
@@ -588,25 +638,23 @@ size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves)
     return mfma_lds_layout(kpad, nab, waves, nullptr, nullptr);
 }
 
-hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, int32_t nwork, int32_t waves,
-                                 int32_t na, size_t lds, hipStream_t s)
+hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid,
+                                 int32_t waves, int32_t na, size_t lds, hipStream_t s, int mode, int *bpc)
 {
-    if (nwork <= 0) return hipSuccess;
-    if (waves == 8) {
-        switch (na) {
-        case 1: return launch_variant<8, 1>(a, work, nwork, lds, s);
-        case 2: return launch_variant<8, 2>(a, work, nwork, lds, s);
-        case 4: return launch_variant<8, 4>(a, work, nwork, lds, s);
-        case 8: return launch_variant<8, 8>(a, work, nwork, lds, s);
-        case 16: return launch_variant<8, 16>(a, work, nwork, lds, s);
-        }
-    } else if (waves == 16) {
-        switch (na) {
-        case 1: return launch_variant<16, 1>(a, work, nwork, lds, s);
-        case 2: return launch_variant<16, 2>(a, work, nwork, lds, s);
-        case 4: return launch_variant<16, 4>(a, work, nwork, lds, s);
-        case 8: return launch_variant<16, 8>(a, work, nwork, lds, s);
-        }
+    if (grid <= 0) return hipSuccess;
+#define VRK_NA_CASES(W)                                                          \
+    switch (na) {                                                                \
+    case 1: return launch_variant<W, 1>(a, work, q, grid, lds, s, mode, bpc);    \
+    case 2: return launch_variant<W, 2>(a, work, q, grid, lds, s, mode, bpc);    \
+    case 4: return launch_variant<W, 4>(a, work, q, grid, lds, s, mode, bpc);    \
+    case 8: return launch_variant<W, 8>(a, work, q, grid, lds, s, mode, bpc);    \
     }
+    if (waves == 8) {
+        if (na == 16) return launch_variant<8, 16>(a, work, q, grid, lds, s, mode, bpc);
+        VRK_NA_CASES(8)
+    } else if (waves == 16) {
+        VRK_NA_CASES(16)
+    }
+#undef VRK_NA_CASES
     return hipErrorInvalidValue;
 }

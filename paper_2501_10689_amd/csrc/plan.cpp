@@ -91,6 +91,9 @@ struct vrk_plan {
     std::vector<VrkWork> work;
     std::vector<int4> gtiles;   // band tiles of the adjoint gradient (MFMA engine)
     size_t o_gtiles = 0;
+    int32_t qbase[VRK_NQUEUE] = {0}, qsize[VRK_NQUEUE] = {0};
+    size_t o_queue = 0;         // int32 counters[8], base[8], size[8]
+    int32_t persistent = 0, grid = 0;
     int32_t max_nub = 0;
     std::vector<uint8_t> image;
     uint8_t *d_ws = nullptr;
@@ -322,7 +325,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     if (o.schedule < 0 || o.schedule > 2) return fail(VRK_EINVAL, "schedule %d", o.schedule);
     if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(VRK_EINVAL, "tol %g", o.tol);
     if (o.max_iters < 1) return fail(VRK_EINVAL, "max_iters must be >= 1");
-    if (o.tile_waves != 0 && o.tile_waves != 4 && o.tile_waves != 8 && o.tile_waves != 16)
+    if (o.tile_waves != 0 && o.tile_waves != 8 && o.tile_waves != 16)
         return fail(VRK_EINVAL, "tile_waves %d", o.tile_waves);
     for (int i = 0; i < nprob; ++i) {
         vrk_status s = validate_problem(probs[i], i, o);
@@ -381,13 +384,28 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             delete pl;
             return fail(VRK_EUNSUPPORTED, "MFMA engine needs %zu bytes of LDS for k=%d", pl->lds, max_k);
         }
-        // work items: (problem, tile), most expensive first
-        for (int i = 0; i < nprob; ++i)
-            for (int t = 0; t < pl->pp[i].ntile; ++t) pl->work.push_back({i, t});
-        std::stable_sort(pl->work.begin(), pl->work.end(), [&](const VrkWork &a, const VrkWork &b) {
-            const ProbPlan &x = pl->pp[a.prob], &y = pl->pp[b.prob];
-            return x.n_ha + x.n_hg > y.n_ha + y.n_hg;
-        });
+        // Work items (problem, tile). Problems go to the XCD queues by cost,
+        // largest first onto the least loaded queue, so each XCD's L2 holds
+        // few channels at a time; within a queue the most expensive tiles
+        // come first.
+        std::vector<int> order(nprob);
+        std::iota(order.begin(), order.end(), 0);
+        auto cost = [&](int i) { return (double)(pl->pp[i].n_ha + pl->pp[i].n_hg) * pl->pp[i].ntile; };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        std::vector<std::vector<int>> qprobs(VRK_NQUEUE);
+        double load[VRK_NQUEUE] = {0};
+        for (int i : order) {
+            int qi = (int)(std::min_element(load, load + VRK_NQUEUE) - load);
+            qprobs[qi].push_back(i);
+            load[qi] += cost(i);
+        }
+        for (int qi = 0; qi < VRK_NQUEUE; ++qi) {
+            pl->qbase[qi] = (int32_t)pl->work.size();
+            for (int i : qprobs[qi])
+                for (int t = 0; t < pl->pp[i].ntile; ++t) pl->work.push_back({i, t});
+            pl->qsize[qi] = (int32_t)pl->work.size() - pl->qbase[qi];
+        }
+        pl->persistent = o.persistent ? 1 : 0;
         for (int i = 0; i < nprob; ++i) pl->max_nub = std::max(pl->max_nub, pl->pp[i].nub);
         if (all_adj)
             for (int i = 0; i < nprob; ++i) {
@@ -407,6 +425,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     pl->o_desc = cv.take(sizeof(VrkDesc) * nprob);
     pl->o_work = cv.take(sizeof(VrkWork) * std::max<size_t>(1, pl->work.size()));
     pl->o_gtiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->gtiles.size()));
+    pl->o_queue = cv.take(sizeof(int32_t) * 3 * VRK_NQUEUE);
     for (auto &q : pl->pp) {
         const int K = q.p.k;
         q.o_vs = cv.take(4 * K);
@@ -532,6 +551,14 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         std::memcpy(pl->image.data() + pl->o_work, pl->work.data(), sizeof(VrkWork) * pl->work.size());
     if (!pl->gtiles.empty())
         std::memcpy(pl->image.data() + pl->o_gtiles, pl->gtiles.data(), sizeof(int4) * pl->gtiles.size());
+    {
+        int32_t *qv = reinterpret_cast<int32_t *>(pl->image.data() + pl->o_queue);
+        for (int qi = 0; qi < VRK_NQUEUE; ++qi) {
+            qv[qi] = 0;
+            qv[VRK_NQUEUE + qi] = pl->qbase[qi];
+            qv[2 * VRK_NQUEUE + qi] = pl->qsize[qi];
+        }
+    }
     hipError_t e = hipMemcpyAsync(base, pl->image.data(), pl->table_end, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan tables)");
     const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(base + pl->o_desc);
@@ -540,6 +567,21 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
     if (pl->engine == VRK_ENGINE_MFMA) {
         e = vrk_launch_pack(dd, (int32_t)pl->pp.size(), pl->max_tiles, s);
         if (e != hipSuccess) return hip_fail(e, "tile-pack kernel");
+        VrkSolveArgs a{};
+        a.variant = o.variant;
+        int bpc = 0;
+        e = vrk_launch_mfma_solve(a, nullptr, VrkQueue{}, 1, pl->waves, pl->na, pl->lds, s, 1, &bpc);
+        if (e != hipSuccess) return hip_fail(e, "MFMA kernel attributes");
+        int dev = 0, cus = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "device query");
+        int64_t g = (int64_t)std::max(1, cus) * std::max(1, bpc);
+        pl->grid = pl->persistent ? (int32_t)std::min<int64_t>(g, (int64_t)pl->work.size())
+                                  : (int32_t)pl->work.size();
+    } else {
+        e = vrk_prepare_vec_solve(o.dtype, pl->lds);
+        if (e != hipSuccess) return hip_fail(e, "vector kernel attributes");
     }
     pl->d_ws = base;
     pl->bound = true;
@@ -567,10 +609,13 @@ static vrk_status run_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float 
     a.flags = d_flags;
     if (pl->total_rhs == 0) return VRK_OK;
     hipError_t e;
-    if (pl->engine == VRK_ENGINE_MFMA)
-        e = vrk_launch_mfma_solve(a, reinterpret_cast<const VrkWork *>(pl->d_ws + pl->o_work),
-                                  (int32_t)pl->work.size(), pl->waves, pl->na, pl->lds, s);
-    else
+    if (pl->engine == VRK_ENGINE_MFMA) {
+        int32_t *qv = reinterpret_cast<int32_t *>(pl->d_ws + pl->o_queue);
+        VrkQueue q{};
+        if (pl->persistent) q = VrkQueue{qv, qv + VRK_NQUEUE, qv + 2 * VRK_NQUEUE};
+        e = vrk_launch_mfma_solve(a, reinterpret_cast<const VrkWork *>(pl->d_ws + pl->o_work), q, pl->grid,
+                                  pl->waves, pl->na, pl->lds, s, 0, nullptr);
+    } else
         e = vrk_launch_vec_solve(a, pl->lds, s);
     if (e != hipSuccess) return hip_fail(e, "solve kernel");
     return VRK_OK;
@@ -619,7 +664,7 @@ int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *
     case VRK_Q_COLOUR: v = q.colour; break;
     case VRK_Q_XOFF: v = q.xoff; break;
     case VRK_Q_XIDX: v = q.xidx; break;
-    case VRK_Q_ENGINE: v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds}; break;
+    case VRK_Q_ENGINE: v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid}; break;
     case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band}; break;
     default: return -1;
     }
@@ -646,3 +691,158 @@ const char *vrk_status_string(vrk_status s)
 const char *vrk_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+namespace {
+
+uint64_t fnv1a(uint64_t hsh, const void *data, size_t n)
+{
+    const uint8_t *p = static_cast<const uint8_t *>(data);
+    for (size_t i = 0; i < n; ++i) {
+        hsh ^= p[i];
+        hsh *= 1099511628211ULL;
+    }
+    return hsh;
+}
+
+uint64_t shape_key(const vrk_problem *probs, int32_t nprob, const vrk_options &o)
+{
+    uint64_t hsh = 1469598103934665603ULL;
+    int32_t head[4] = {o.variant, o.select, o.dtype, nprob};
+    hsh = fnv1a(hsh, head, sizeof head);
+    for (int i = 0; i < nprob; ++i) {
+        int64_t band = 0;
+        for (int k = 0; k < probs[i].k; ++k) band += probs[i].vr_len[k];
+        int64_t v[4] = {probs[i].nt, probs[i].k, probs[i].nrhs, band};
+        hsh = fnv1a(hsh, v, sizeof v);
+    }
+    return hsh;
+}
+
+struct Cand {
+    int32_t engine, waves, persistent, schedule;
+};
+
+bool cache_lookup(const char *path, uint64_t key, Cand *c, float *ms)
+{
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool hit = false;
+    while (fgets(line, sizeof line, f)) {
+        unsigned long long k;
+        Cand t;
+        float m;
+        if (sscanf(line, "%llx %d %d %d %d %f", &k, &t.engine, &t.waves, &t.persistent, &t.schedule, &m) == 6 &&
+            (uint64_t)k == key) {
+            *c = t;
+            *ms = m;
+            hit = true;
+        }
+    }
+    fclose(f);
+    return hit;
+}
+
+void cache_store(const char *path, uint64_t key, const Cand &c, float ms)
+{
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%016llx %d %d %d %d %.6f\n", (unsigned long long)key, c.engine, c.waves, c.persistent, c.schedule,
+            ms);
+    fclose(f);
+}
+
+void apply(vrk_options &o, const Cand &c)
+{
+    o.engine = c.engine;
+    o.tile_waves = c.waves;
+    o.persistent = c.persistent;
+    o.schedule = c.schedule;
+}
+
+}  // namespace
+
+extern "C" vrk_status vrk_autotune(const vrk_problem *probs, int32_t nprob, vrk_options *opt, void *d_ws,
+                                   size_t ws_bytes, void *stream, const char *cache_path, int32_t reps,
+                                   size_t *ws_needed, float *best_ms)
+{
+    g_err.clear();
+    if (!opt || !probs || nprob < 1) return fail(VRK_EINVAL, "autotune: null options or no problems");
+    std::vector<Cand> cands;
+    if (opt->dtype == VRK_C64) {
+        for (int w : {8, 16})
+            for (int per : {0, 1}) cands.push_back({VRK_ENGINE_MFMA, w, per, VRK_SCHED_GATHER});
+    }
+    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_GATHER});
+    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_COLOUR});
+    // workspace each candidate needs (host-only planning)
+    std::vector<size_t> need(cands.size(), 0);
+    std::vector<bool> ok(cands.size(), false);
+    size_t maxneed = 0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+        vrk_options o = *opt;
+        apply(o, cands[c]);
+        vrk_plan *pl = nullptr;
+        size_t ws = 0;
+        if (vrk_plan_create(probs, nprob, &o, &ws, &pl) == VRK_OK) {
+            ok[c] = true;
+            need[c] = ws;
+            maxneed = std::max(maxneed, ws);
+            vrk_plan_destroy(pl);
+        }
+    }
+    g_err.clear();
+    if (ws_needed) *ws_needed = maxneed;
+    if (!d_ws) return VRK_OK;
+    const uint64_t key = shape_key(probs, nprob, *opt);
+    Cand hitc;
+    float hitms;
+    if (cache_lookup(cache_path, key, &hitc, &hitms)) {
+        apply(*opt, hitc);
+        if (best_ms) *best_ms = hitms;
+        return VRK_OK;
+    }
+    if (reps < 1) reps = 1;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(VRK_EHIP, "autotune: hipEventCreate failed");
+    float best = -1.f;
+    Cand bestc{};
+    vrk_status st = VRK_OK;
+    for (size_t c = 0; c < cands.size() && st == VRK_OK; ++c) {
+        if (!ok[c] || need[c] > ws_bytes) continue;
+        vrk_options o = *opt;
+        apply(o, cands[c]);
+        vrk_plan *pl = nullptr;
+        size_t ws = 0;
+        if (vrk_plan_create(probs, nprob, &o, &ws, &pl) != VRK_OK) continue;
+        st = vrk_plan_bind(pl, d_ws, ws_bytes, stream);
+        if (st == VRK_OK) st = vrk_solve(pl, stream, nullptr, nullptr, nullptr);   // warm-up
+        if (st == VRK_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(VRK_EHIP, "autotune: event record");
+        for (int r = 0; r < reps && st == VRK_OK; ++r) st = vrk_solve(pl, stream, nullptr, nullptr, nullptr);
+        float ms = 0.f;
+        if (st == VRK_OK) {
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                st = fail(VRK_EHIP, "autotune: event timing");
+        }
+        vrk_plan_destroy(pl);
+        if (st != VRK_OK) break;
+        ms /= reps;
+        if (best < 0.f || ms < best) {
+            best = ms;
+            bestc = cands[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != VRK_OK) return st;
+    if (best < 0.f) return fail(VRK_EWORKSPACE, "autotune: no candidate fits the %zu-byte workspace", ws_bytes);
+    apply(*opt, bestc);
+    if (best_ms) *best_ms = best;
+    cache_store(cache_path, key, bestc, best);
+    return VRK_OK;
+}

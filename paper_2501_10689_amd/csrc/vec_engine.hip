@@ -472,21 +472,18 @@ size_t vrk_vec_lds_bytes(int32_t dtype, int32_t nt, int32_t k)
     return (size_t)(2 * nt + 4 * k) * 2 * rb + (size_t)(2 * k) * rb + 4 * kWaves * rb + 64;
 }
 
+hipError_t vrk_prepare_vec_solve(int32_t dtype, size_t lds_bytes)
+{
+    const void *f = dtype == 1 ? reinterpret_cast<const void *>(k_vec_solve<double>)
+                               : reinterpret_cast<const void *>(k_vec_solve<float>);
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
 hipError_t vrk_launch_vec_solve(const VrkSolveArgs &a, size_t lds_bytes, hipStream_t s)
 {
     dim3 grid((unsigned)a.max_rhs, (unsigned)a.nprob);
-    hipError_t e;
-    if (a.dtype == 1) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_vec_solve<double>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_vec_solve<double>, grid, dim3(kThreads), lds_bytes, s, a);
-    } else {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_vec_solve<float>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_vec_solve<float>, grid, dim3(kThreads), lds_bytes, s, a);
-    }
+    if (a.dtype == 1) hipLaunchKernelGGL(k_vec_solve<double>, grid, dim3(kThreads), lds_bytes, s, a);
+    else hipLaunchKernelGGL(k_vec_solve<float>, grid, dim3(kThreads), lds_bytes, s, a);
     return hipGetLastError();
 }
 

@@ -57,3 +57,14 @@ struct VrkDesc {
 struct VrkWork {
     int32_t prob, tile;
 };
+
+// Work queues of the persistent MFMA launch, one per XCD: queue q owns the
+// work items [base[q], base[q] + size[q]); count[q] is its claim counter,
+// zeroed by a kernel before every launch. count == null: one workgroup per
+// work item instead.
+#define VRK_NQUEUE 8
+struct VrkQueue {
+    int32_t *count;
+    const int32_t *base;
+    const int32_t *size;
+};

@@ -75,6 +75,9 @@ def lib():
         L.vrk_solve.argtypes = [vp, vp, vp, vp, vp]
         L.vrk_solve_adjoint.restype = C.c_int
         L.vrk_solve_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.vrk_autotune.restype = C.c_int
+        L.vrk_autotune.argtypes = [P, C.c_int32, C.POINTER(Options), vp, C.c_size_t, vp, C.c_char_p,
+                                   C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_float)]
         L.vrk_plan_query.restype = C.c_int64
         L.vrk_plan_query.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int64]
         L.vrk_plan_destroy.restype = None
@@ -220,6 +223,51 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _problem_array(probs):
+    keep = []
+    arr = (Problem * len(probs))()
+    for i, sp in enumerate(probs):
+        vs = np.ascontiguousarray(sp.vr_start, dtype=np.int32)
+        vl = np.ascontiguousarray(sp.vr_len, dtype=np.int32)
+        keep += [vs, vl]
+        p = arr[i]
+        p.k, p.nt = int(sp.H.shape[0]), int(sp.H.shape[1])
+        p.xi = float(sp.xi)
+        p.H, p.ldh = _ptr(sp.H), _stride(sp.H)
+        p.vr_start, p.vr_len = _ptr(vs), _ptr(vl)
+        p.nrhs = int(sp.S.shape[0]) if sp.S is not None else 0
+        p.S, p.lds = _ptr(sp.S), _stride(sp.S)
+        p.X, p.ldx = _ptr(sp.X), _stride(sp.X)
+        p.V, p.ldv = _ptr(sp.V), _stride(sp.V)
+        p.GX, p.ldgx = _ptr(sp.GX), _stride(sp.GX)
+        p.GH, p.ldgh = _ptr(sp.GH), _stride(sp.GH)
+        p.GS, p.ldgs = _ptr(sp.GS), _stride(sp.GS)
+        p.gxi = _ptr(sp.gxi)
+    return arr, keep
+
+
+def autotune(probs, opts: Options, cache_path=None, reps=3, stream=None):
+    """Run vrk_autotune on the batch (device timing; overwrites X and V).
+    Returns (tuned Options, ms per solve)."""
+    import torch
+    arr, keep = _problem_array(probs)
+    o = Options()
+    C.pointer(o)[0] = opts
+    need = C.c_size_t(0)
+    _check(lib().vrk_autotune(arr, len(probs), C.byref(o), None, 0, None, None, reps, C.byref(need), None))
+    dev = probs[0].H.device
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=dev)
+    ptr = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+    st = (torch.cuda.current_stream(dev).cuda_stream if stream is None else
+          (stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)))
+    ms = C.c_float(0.0)
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().vrk_autotune(arr, len(probs), C.byref(o), ptr, int(need.value), st, cp, reps,
+                              C.byref(need), C.byref(ms)))
+    del keep
+    return o, float(ms.value)
 
 
 def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, **kw):

@@ -1,0 +1,144 @@
+"""Batching on the GPU: persistent per-XCD work queues, HIP-graph capture
+and replay, the full uneven-drop workload in one launch, and the
+autotuner."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rel_err_rows, run_plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _drops(n, nrhs, seed=None):
+    return [(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+            for d in synth.make_workload("uneven", drops=n, nrhs=nrhs, seed=seed)]
+
+
+@pytest.mark.parametrize("variant", ["vr_oahk", "grk"])
+def test_persistent_equals_per_tile_launch_bitwise(variant):
+    drops = _drops(12, 40)
+    a, pa = run_plan(drops, variant=variant, engine="mfma", persistent=0)
+    b, pb = run_plan(drops, variant=variant, engine="mfma", persistent=1)
+    info = pb.query(0, 5)
+    assert info[4] == 1 and info[5] <= sum(-(-d[3].shape[0] // 16) for d in drops)
+    for x, y in zip(a, b):
+        assert np.array_equal(x["X"], y["X"])
+        assert np.array_equal(x["iters"], y["iters"])
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_graph_capture_replays_match_eager(persistent):
+    """The fwd solve + adjoint of an uneven batch captured once into a HIP
+    graph and replayed with new symbols each time; every replay is checked
+    against an eager run on the same inputs."""
+    import torch
+    from paper_2501_10689_amd import vrk
+    ds = synth.make_workload("uneven", drops=5, nrhs=32, seed=7)
+    specs, Ss, Gs = [], [], []
+    for d in ds:
+        H = torch.tensor(d.H, dtype=torch.complex64, device="cuda")
+        S = torch.tensor(d.S, dtype=torch.complex64, device="cuda")
+        X = torch.zeros((d.nrhs, d.nt), dtype=torch.complex64, device="cuda")
+        V = torch.zeros((d.nrhs, d.k), dtype=torch.complex64, device="cuda")
+        GX = torch.zeros_like(X)
+        sp = vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X, V, GX, torch.zeros_like(H),
+                             torch.zeros_like(S), torch.zeros(1, dtype=torch.float64, device="cuda"))
+        specs.append(sp)
+    plan = vrk.Plan(specs, vrk.options(variant="vr_oahk", engine="mfma", persistent=persistent))
+    rng = np.random.default_rng(0)
+
+    def new_inputs():
+        ins = []
+        for sp, d in zip(specs, ds):
+            s = synth.qpsk(rng, (d.nrhs, d.k))
+            gx = (rng.standard_normal((d.nrhs, d.nt)) + 1j * rng.standard_normal((d.nrhs, d.nt))) * 0.01
+            ins.append((s, gx))
+        return ins
+
+    def load(ins):
+        for sp, (s, gx) in zip(specs, ins):
+            sp.S.copy_(torch.tensor(s, dtype=torch.complex64))
+            sp.GX.copy_(torch.tensor(gx, dtype=torch.complex64))
+
+    def outputs():
+        return [(sp.X.cpu().numpy(), sp.GH.cpu().numpy(), sp.GS.cpu().numpy(), float(sp.gxi.cpu()[0]))
+                for sp in specs]
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.solve(stream=side)
+        plan.solve_adjoint(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.solve()
+        plan.solve_adjoint()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        ins = new_inputs()
+        load(ins)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = outputs()
+        load(ins)
+        plan.solve()
+        plan.solve_adjoint()
+        torch.cuda.synchronize()
+        want = outputs()
+        for (xa, ha, sa, ga), (xb, hb, sb, gb) in zip(got, want):
+            assert np.array_equal(xa, xb) and np.array_equal(ha, hb) and np.array_equal(sa, sb)
+            assert ga == gb
+        for sp, d, (s, _) in zip(specs, ds, ins):
+            Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, s, d.xi)
+            assert rel_err_rows(sp.X.cpu().numpy().astype(np.complex128), Xr).max() <= 1e-4
+
+
+def test_full_uneven_workload_one_persistent_launch():
+    """512 drops (Nt in {512, 1024, 2048}, K in [16, 128], VR U[Nt/8, Nt/2],
+    256 QPSK vectors each, SNR U[0, 20] dB): one persistent launch; every
+    one of the 131072 vectors against the FP64 Cholesky RZF."""
+    ds = synth.make_workload("uneven")
+    drops = [(d.H, d.vr_start, d.vr_len, d.S, d.xi) for d in ds]
+    res, plan = run_plan(drops, variant="vr_oahk", engine="mfma", persistent=1)
+    worst = 0.0
+    for jd, (H, vs, vl, S, xi) in enumerate(drops):
+        X, _ = oracle.rzf(H, vs, vl, S, xi)
+        assert np.all(res[jd]["flags"] == oracle.F_CONVERGED), jd
+        worst = max(worst, rel_err_rows(res[jd]["X"], X).max())
+    print("uneven workload: worst rel err %.2e" % worst)
+    assert worst <= 1e-4
+
+
+def test_autotune_picks_a_valid_config_and_caches(tmp_path):
+    import torch
+    from paper_2501_10689_amd import vrk
+    ds = synth.make_workload("uneven", drops=4, nrhs=48, seed=11)
+    specs = []
+    for d in ds:
+        specs.append(vrk.ProblemSpec(torch.tensor(d.H, dtype=torch.complex64, device="cuda"), d.vr_start,
+                                     d.vr_len, d.xi, torch.tensor(d.S, dtype=torch.complex64, device="cuda"),
+                                     torch.zeros((d.nrhs, d.nt), dtype=torch.complex64, device="cuda"),
+                                     torch.zeros((d.nrhs, d.k), dtype=torch.complex64, device="cuda")))
+    cache = str(tmp_path / "tune.txt")
+    o, ms = vrk.autotune(specs, vrk.options(variant="vr_oahk"), cache_path=cache, reps=2)
+    assert ms > 0 and o.engine in (1, 2)
+    assert os.path.exists(cache) and len(open(cache).read().splitlines()) == 1
+    o2, ms2 = vrk.autotune(specs, vrk.options(variant="vr_oahk"), cache_path=cache, reps=2)
+    assert (o2.engine, o2.tile_waves, o2.persistent, o2.schedule) == (o.engine, o.tile_waves, o.persistent,
+                                                                       o.schedule)
+    assert abs(ms2 - ms) < 1e-3
+    plan = vrk.Plan(specs, o)
+    plan.solve()
+    torch.cuda.synchronize()
+    for sp, d in zip(specs, ds):
+        Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+        assert rel_err_rows(sp.X.cpu().numpy().astype(np.complex128), Xr).max() <= 1e-4
