@@ -34,6 +34,8 @@ hipError_t vrk_launch_vec_solve(const VrkSolveArgs &a, size_t lds_bytes, hipStre
 
 // MFMA engine: 16 right-hand sides per workgroup (complex64).
 int vrk_mfma_supported(int32_t nt, int32_t waves);
+// Register blocks per wave for x (1, 2, 4, 8, 16), or 0: x in the workspace.
+int vrk_mfma_register_na(int32_t nt, int32_t waves);
 size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves);
 // mode 0 launches (grid = work items, or the persistent grid when q.count is
 // set); mode 1 only sets the kernel's LDS attribute and writes its resident

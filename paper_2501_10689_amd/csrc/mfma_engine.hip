@@ -123,6 +123,7 @@ struct TileCtx {
     const VrkDesc *d;
     MfmaLds L;
     const float2 *S, *H, *HA, *HG;
+    float2 *Xw;   // global-iterate mode: this tile's x, [ab][r][lane] (MFMA result order)
     int64_t lds;
     int K, N, nub, kpad, nab, b0, nrhs, prob;
     float xi;
@@ -132,8 +133,8 @@ struct TileCtx {
 // with a deterministic cross-wave reduction through LDS. With `ogrk` only
 // the rows of X_pick are written (the others keep their value, Theorem 2).
 template <int W, int NA>
-__device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[NA], const f4 (&xq)[NA],
-                                              bool ogrk)
+__device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[NA ? NA : 1],
+                                              const f4 (&xq)[NA ? NA : 1], bool ogrk)
 {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
     const VrkDesc &d = *c.d;
@@ -148,16 +149,32 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
             if (ub < c.nub) {
                 const int lo = c.L.rlo[ub], hi = c.L.rhi[ub];
                 const int64_t hb = c.L.hoff[ub];
-#pragma unroll
-                for (int t = 0; t < NA; ++t) {
-                    const int ab = w + W * t;
-                    if (ab >= lo && ab < hi) {
+                if constexpr (NA == 0) {
+                    // global iterate: the wave's blocks w, w + W, ... inside [lo, hi)
+                    int ab = lo + ((w - lo) % W + W) % W;
+#pragma unroll 1
+                    for (; ab < hi; ab += W) {
                         const float2 *hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
+                        const float2 *xp = c.Xw + (int64_t)ab * 256 + lane;
                         float2 h0 = hp[0], h1 = hp[64], h2 = hp[128], h3 = hp[192];
-                        cmfma(are, aim, h0, float2{xr[t][0], xq[t][0]});
-                        cmfma(are, aim, h1, float2{xr[t][1], xq[t][1]});
-                        cmfma(are, aim, h2, float2{xr[t][2], xq[t][2]});
-                        cmfma(are, aim, h3, float2{xr[t][3], xq[t][3]});
+                        float2 x0 = xp[0], x1 = xp[64], x2 = xp[128], x3 = xp[192];
+                        cmfma(are, aim, h0, x0);
+                        cmfma(are, aim, h1, x1);
+                        cmfma(are, aim, h2, x2);
+                        cmfma(are, aim, h3, x3);
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < NA; ++t) {
+                        const int ab = w + W * t;
+                        if (ab >= lo && ab < hi) {
+                            const float2 *hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
+                            float2 h0 = hp[0], h1 = hp[64], h2 = hp[128], h3 = hp[192];
+                            cmfma(are, aim, h0, float2{xr[t][0], xq[t][0]});
+                            cmfma(are, aim, h1, float2{xr[t][1], xq[t][1]});
+                            cmfma(are, aim, h2, float2{xr[t][2], xq[t][2]});
+                            cmfma(are, aim, h3, float2{xr[t][3], xq[t][3]});
+                        }
                     }
                 }
             }
@@ -262,21 +279,30 @@ __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, f4 &pr, f4 &
 // at most a quarter of the per-wave register budget (2048 / W); otherwise
 // P is recomputed.
 template <int W, int NA>
-__device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA], f4 (&xq)[NA])
+__device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? NA : 1], f4 (&xq)[NA ? NA : 1])
 {
-    constexpr bool kKeepP = 16 * NA * W <= 512;
+    constexpr bool kKeepP = NA > 0 && 16 * NA * W <= 512;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15;
     const int er = tid >> 4, rows_per_pass = W * 4;
     float pn = 0.f;
     f4 pr[kKeepP ? NA : 1], pi[kKeepP ? NA : 1];
+    if constexpr (NA == 0) {
+#pragma unroll 1
+        for (int ab = w; ab < c.nab; ab += W) {
+            agg_block(c, ab, pr[0], pi[0]);
 #pragma unroll
-    for (int t = 0; t < NA; ++t) {
-        const int ab = w + W * t;
-        const int ts = kKeepP ? t : 0;
-        if (ab < c.nab) {
-            agg_block(c, ab, pr[ts], pi[ts]);
+            for (int r = 0; r < 4; ++r) pn += pr[0][r] * pr[0][r] + pi[0][r] * pi[0][r];
+        }
+    } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) pn += pr[ts][r] * pr[ts][r] + pi[ts][r] * pi[ts][r];
+        for (int t = 0; t < NA; ++t) {
+            const int ab = w + W * t;
+            const int ts = kKeepP ? t : 0;
+            if (ab < c.nab) {
+                agg_block(c, ab, pr[ts], pi[ts]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) pn += pr[ts][r] * pr[ts][r] + pi[ts][r] * pi[ts][r];
+            }
         }
     }
     pn = col_sum<W>(pn, c.L.red);
@@ -287,6 +313,19 @@ __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA], f
     }
     __syncthreads();
     const float gm = c.L.gre[j];
+    if constexpr (NA == 0) {
+#pragma unroll 1
+        for (int ab = w; ab < c.nab; ab += W) {
+            f4 qr, qi;
+            agg_block(c, ab, qr, qi);
+            float2 *xp = c.Xw + (int64_t)ab * 256 + lane;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float2 x = xp[64 * r];
+                xp[64 * r] = float2{x.x + gm * qr[r], x.y + gm * qi[r]};
+            }
+        }
+    }
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
         const int ab = w + W * t;
@@ -342,18 +381,24 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
     c.H = reinterpret_cast<const float2 *>(d.H);
     c.HA = reinterpret_cast<const float2 *>(d.HA);
     c.HG = reinterpret_cast<const float2 *>(d.HG);
+    c.Xw = NA == 0 ? reinterpret_cast<float2 *>(d.Xw) + (int64_t)wk.tile * c.nab * 256 : nullptr;
     const float *nrm_g = reinterpret_cast<const float *>(d.nrm);
     const int K = c.K, N = c.N, kpad = c.kpad, b0 = c.b0;
     const int rows_per_pass = W * 4;   // (row, column) entries: tid -> (tid / 16, tid % 16)
     const int er = tid >> 4;
 
     // ---- init: x = 0, q = 0, r = s (z0 = 0), norms in VR-start order
-    f4 xr[NA], xq[NA];
+    constexpr int NR = NA ? NA : 1;
+    f4 xr[NR], xq[NR];
 #pragma unroll
-    for (int t = 0; t < NA; ++t) {
+    for (int t = 0; t < NR; ++t) {
         xr[t] = f4{0.f, 0.f, 0.f, 0.f};
         xq[t] = f4{0.f, 0.f, 0.f, 0.f};
     }
+    if constexpr (NA == 0)
+        for (int ab = w; ab < c.nab; ab += W)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c.Xw[(int64_t)ab * 256 + 64 * r + lane] = float2{0.f, 0.f};
     float s2 = 0.f;
     for (int ku = er; ku < kpad; ku += rows_per_pass) {
         float2 sv = {0.f, 0.f};
@@ -453,7 +498,25 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
             {
                 const int i = L.pick[j];
                 const float gr = L.gre[j], gi = L.gim[j];
-                if (i >= 0 && (gr != 0.f || gi != 0.f)) {
+                if (NA == 0 && i >= 0 && (gr != 0.f || gi != 0.f)) {
+                    const int s0 = d.vs[i], e0 = d.ve[i];
+                    const float2 *hrow = c.H + (int64_t)i * d.ldh;
+                    for (int ab = w; ab < c.nab; ab += W) {
+                        const int nb = 16 * ab + 4 * g;
+                        if (nb + 3 < s0 || nb >= e0) continue;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int n = nb + r;
+                            if (n >= s0 && n < e0) {
+                                float2 h = hrow[n];
+                                float2 *xp = c.Xw + (int64_t)ab * 256 + 64 * r + lane;
+                                float2 x = *xp;
+                                *xp = float2{x.x + gr * h.x + gi * h.y, x.y + gi * h.x - gr * h.y};
+                            }
+                        }
+                    }
+                }
+                if (NA > 0 && i >= 0 && (gr != 0.f || gi != 0.f)) {
                     const int s0 = d.vs[i], e0 = d.ve[i];
                     const float2 *hrow = c.H + (int64_t)i * d.ldh;
 #pragma unroll
@@ -484,6 +547,24 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
             // orthogonal half-step on F with gamma = 1 (Prop. 1); each antenna
             // belongs to at most one user of F
             tile_phi<W>(c, 1);
+            if constexpr (NA == 0) {
+                for (int ab = w; ab < c.nab; ab += W) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int n = 16 * ab + 4 * g + r;
+                        if (n < N) {
+                            const int o = d.fown[n];
+                            if (o >= 0) {
+                                float2 f = L.R[o * 16 + j];
+                                float2 h = c.H[(int64_t)d.perm[o] * d.ldh + n];
+                                float2 *xp = c.Xw + (int64_t)ab * 256 + 64 * r + lane;
+                                float2 x = *xp;
+                                *xp = float2{x.x + f.x * h.x + f.y * h.y, x.y + f.y * h.x - f.x * h.y};
+                            }
+                        }
+                    }
+                }
+            }
 #pragma unroll
             for (int t = 0; t < NA; ++t) {
                 const int nb = 16 * (w + W * t) + 4 * g;
@@ -520,6 +601,13 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
     {
         const int b = b0 + j;
         if (b < c.nrhs) {
+            if constexpr (NA == 0)
+                for (int ab = w; ab < c.nab; ab += W)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int n = 16 * ab + 4 * g + r;
+                        if (n < N) X[(int64_t)b * ldx_ + n] = c.Xw[(int64_t)ab * 256 + 64 * r + lane];
+                    }
 #pragma unroll
             for (int t = 0; t < NA; ++t) {
                 const int nb = 16 * (w + W * t) + 4 * g;
@@ -567,21 +655,16 @@ __device__ __forceinline__ int next_item(const VrkQueue &q, int *sh)
     return item;
 }
 
-template <int W, int NA, int VARIANT>
+template <int W, int NA, int VARIANT, bool PERSIST>
 __global__ void __launch_bounds__(W * 64) k_mfma_solve(VrkSolveArgs a, const VrkWork *work, VrkQueue q)
 {
     extern __shared__ __align__(16) char smem[];
-    __shared__ int sh_item;
-    if (!q.count) {   // one workgroup per work item
-        solve_item<W, NA, VARIANT>(a, work[blockIdx.x], smem);
-        return;
-    }
-    // persistent: drain the work queues
-    for (;;) {
-        const int item = next_item(q, &sh_item);
-        if (item < 0) break;
-        solve_item<W, NA, VARIANT>(a, work[item], smem);
-        __syncthreads();
+    if constexpr (!PERSIST) {
+        solve_item<W, NA, VARIANT>(a, work[blockIdx.x], smem);   // one workgroup per work item
+    } else {
+        __shared__ int sh_item;
+        for (int item = next_item(q, &sh_item); item >= 0; item = next_item(q, &sh_item))
+            solve_item<W, NA, VARIANT>(a, work[item], smem);
     }
 }
 
@@ -591,20 +674,28 @@ __global__ void k_queue_reset(int *count)
 }
 
 // Launch (mode 0), set the LDS attribute and report occupancy (mode 1).
-template <int W, int NA, int VARIANT>
-hipError_t launch_one(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid, size_t lds,
-                      hipStream_t s, int mode, int *blocks_per_cu)
+template <int W, int NA, int VARIANT, bool PERSIST>
+hipError_t launch_kernel(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid,
+                         size_t lds, hipStream_t s, int mode, int *blocks_per_cu)
 {
-    auto kern = k_mfma_solve<W, NA, VARIANT>;
+    auto kern = k_mfma_solve<W, NA, VARIANT, PERSIST>;
     if (mode == 1) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, W * 64, lds);
     }
-    if (q.count) hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q.count);
+    if (PERSIST) hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q.count);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(W * 64), lds, s, a, work, q);
     return hipGetLastError();
+}
+
+template <int W, int NA, int VARIANT>
+hipError_t launch_one(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid, size_t lds,
+                      hipStream_t s, int mode, int *blocks_per_cu)
+{
+    if (q.count) return launch_kernel<W, NA, VARIANT, true>(a, work, q, grid, lds, s, mode, blocks_per_cu);
+    return launch_kernel<W, NA, VARIANT, false>(a, work, q, grid, lds, s, mode, blocks_per_cu);
 }
 
 template <int W, int NA>
@@ -622,15 +713,22 @@ hipError_t launch_variant(const VrkSolveArgs &a, const VrkWork *work, const VrkQ
 
 }  // namespace
 
-// x of one tile lives in registers: at most 16 antenna blocks per wave with
-// 8 waves (two waves per SIMD) and 8 with 16 waves (four per SIMD); both
-// give Nt <= 2048.
+// x of one tile lives in registers when it fits: at most 16 antenna blocks
+// per wave with 8 waves (two waves per SIMD) and 8 with 16 waves (four per
+// SIMD), i.e. Nt <= 2048. Larger Nt keeps x in a workspace buffer (NA = 0).
 int vrk_mfma_supported(int32_t nt, int32_t waves)
 {
-    int nab = (nt + VRK_AB - 1) / VRK_AB;
-    if (waves == 8) return nab <= 16 * 8;
-    if (waves == 16) return nab <= 8 * 16;
-    return 0;
+    (void)nt;
+    return waves == 8 || waves == 16;
+}
+
+int vrk_mfma_register_na(int32_t nt, int32_t waves)
+{
+    const int nab = (nt + VRK_AB - 1) / VRK_AB;
+    const int cap = waves == 8 ? 16 : 8;
+    int na = (nab + waves - 1) / waves, nap = 1;
+    while (nap < na) nap *= 2;
+    return nap <= cap ? nap : 0;
 }
 
 size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves)
@@ -651,8 +749,10 @@ hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, con
     }
     if (waves == 8) {
         if (na == 16) return launch_variant<8, 16>(a, work, q, grid, lds, s, mode, bpc);
+        if (na == 0) return launch_variant<8, 0>(a, work, q, grid, lds, s, mode, bpc);
         VRK_NA_CASES(8)
     } else if (waves == 16) {
+        if (na == 0) return launch_variant<16, 0>(a, work, q, grid, lds, s, mode, bpc);
         VRK_NA_CASES(16)
     }
 #undef VRK_NA_CASES

@@ -75,6 +75,7 @@ struct ProbPlan {
         o_gbusr, o_perm, o_pos, o_nrm, o_fro2, o_rablo, o_rabhi, o_haoff, o_agoff, o_aguc,
         o_fown, o_ha, o_hg, o_sadj, o_xadj, o_vfwd;
     int64_t rhs_base = 0;
+    size_t o_xw = 0;   // MFMA iterate buffer when x does not fit registers
 };
 
 }  // namespace
@@ -325,6 +326,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     if (o.schedule < 0 || o.schedule > 2) return fail(VRK_EINVAL, "schedule %d", o.schedule);
     if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(VRK_EINVAL, "tol %g", o.tol);
     if (o.max_iters < 1) return fail(VRK_EINVAL, "max_iters must be >= 1");
+    if (o.x_in_workspace != 0 && o.x_in_workspace != 1) return fail(VRK_EINVAL, "x_in_workspace %d", o.x_in_workspace);
     if (o.tile_waves != 0 && o.tile_waves != 8 && o.tile_waves != 16)
         return fail(VRK_EINVAL, "tile_waves %d", o.tile_waves);
     for (int i = 0; i < nprob; ++i) {
@@ -375,10 +377,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         }
     } else {
         int32_t max_nab = (max_nt + VRK_AB - 1) / VRK_AB;
-        int32_t na = (max_nab + waves - 1) / waves;
-        int32_t nap = 1;
-        while (nap < na) nap *= 2;
-        pl->na = nap;
+        pl->na = o.x_in_workspace ? 0 : vrk_mfma_register_na(max_nt, waves);   // 0: iterate in the workspace
         pl->lds = vrk_mfma_lds_bytes(max_kpad, max_nab, waves);
         if (pl->lds > 160 * 1024) {
             delete pl;
@@ -455,6 +454,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         if (eng == VRK_ENGINE_MFMA) {
             q.o_ha = cv.take(q.n_ha * 64 * 8);
             q.o_hg = cv.take(q.n_hg * 64 * 8);
+            if (pl->na == 0) q.o_xw = cv.take((size_t)q.ntile * q.nab * 256 * 8);
             pl->max_tiles = std::max(pl->max_tiles, std::max(q.n_ha, q.n_hg));
         }
         if (q.p.GX) {
@@ -544,6 +544,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.fown = (const int32_t *)(base + q.o_fown);
         d.HA = pl->engine == VRK_ENGINE_MFMA ? base + q.o_ha : nullptr;
         d.HG = pl->engine == VRK_ENGINE_MFMA ? base + q.o_hg : nullptr;
+        d.Xw = (pl->engine == VRK_ENGINE_MFMA && pl->na == 0) ? base + q.o_xw : nullptr;
         (void)eb;
     }
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());
@@ -570,7 +571,10 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         VrkSolveArgs a{};
         a.variant = o.variant;
         int bpc = 0;
-        e = vrk_launch_mfma_solve(a, nullptr, VrkQueue{}, 1, pl->waves, pl->na, pl->lds, s, 1, &bpc);
+        int32_t *qv = reinterpret_cast<int32_t *>(base + pl->o_queue);
+        VrkQueue qa{};
+        if (pl->persistent) qa = VrkQueue{qv, qv + VRK_NQUEUE, qv + 2 * VRK_NQUEUE};
+        e = vrk_launch_mfma_solve(a, nullptr, qa, 1, pl->waves, pl->na, pl->lds, s, 1, &bpc);
         if (e != hipSuccess) return hip_fail(e, "MFMA kernel attributes");
         int dev = 0, cus = 0;
         e = hipGetDevice(&dev);
@@ -664,7 +668,8 @@ int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *
     case VRK_Q_COLOUR: v = q.colour; break;
     case VRK_Q_XOFF: v = q.xoff; break;
     case VRK_Q_XIDX: v = q.xidx; break;
-    case VRK_Q_ENGINE: v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid}; break;
+    case VRK_Q_ENGINE: v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->na};
+        break;
     case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band}; break;
     default: return -1;
     }
@@ -719,7 +724,7 @@ uint64_t shape_key(const vrk_problem *probs, int32_t nprob, const vrk_options &o
 }
 
 struct Cand {
-    int32_t engine, waves, persistent, schedule;
+    int32_t engine, waves, persistent, schedule, xws;
 };
 
 bool cache_lookup(const char *path, uint64_t key, Cand *c, float *ms)
@@ -733,7 +738,8 @@ bool cache_lookup(const char *path, uint64_t key, Cand *c, float *ms)
         unsigned long long k;
         Cand t;
         float m;
-        if (sscanf(line, "%llx %d %d %d %d %f", &k, &t.engine, &t.waves, &t.persistent, &t.schedule, &m) == 6 &&
+        if (sscanf(line, "%llx %d %d %d %d %d %f", &k, &t.engine, &t.waves, &t.persistent, &t.schedule, &t.xws,
+                   &m) == 7 &&
             (uint64_t)k == key) {
             *c = t;
             *ms = m;
@@ -749,8 +755,8 @@ void cache_store(const char *path, uint64_t key, const Cand &c, float ms)
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%016llx %d %d %d %d %.6f\n", (unsigned long long)key, c.engine, c.waves, c.persistent, c.schedule,
-            ms);
+    fprintf(f, "%016llx %d %d %d %d %d %.6f\n", (unsigned long long)key, c.engine, c.waves, c.persistent,
+            c.schedule, c.xws, ms);
     fclose(f);
 }
 
@@ -760,6 +766,7 @@ void apply(vrk_options &o, const Cand &c)
     o.tile_waves = c.waves;
     o.persistent = c.persistent;
     o.schedule = c.schedule;
+    o.x_in_workspace = c.xws;
 }
 
 }  // namespace
@@ -773,10 +780,11 @@ extern "C" vrk_status vrk_autotune(const vrk_problem *probs, int32_t nprob, vrk_
     std::vector<Cand> cands;
     if (opt->dtype == VRK_C64) {
         for (int w : {8, 16})
-            for (int per : {0, 1}) cands.push_back({VRK_ENGINE_MFMA, w, per, VRK_SCHED_GATHER});
+            for (int per : {0, 1}) cands.push_back({VRK_ENGINE_MFMA, w, per, VRK_SCHED_GATHER, 0});
+        cands.push_back({VRK_ENGINE_MFMA, 16, 0, VRK_SCHED_GATHER, 1});
     }
-    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_GATHER});
-    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_COLOUR});
+    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_GATHER, 0});
+    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_COLOUR, 0});
     // workspace each candidate needs (host-only planning)
     std::vector<size_t> need(cands.size(), 0);
     std::vector<bool> ok(cands.size(), false);

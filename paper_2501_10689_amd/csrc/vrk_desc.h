@@ -51,6 +51,8 @@ struct VrkDesc {
     const int32_t *fown;          // per antenna: sorted index of the F user covering it, or -1
     void *HA;                     // residual tiles, 64 complex64 each
     void *HG;                     // aggregation tiles (conjugated), 64 complex64 each
+    void *Xw;                     // iterate of each 16-RHS tile when it does not fit registers:
+                                  // [tile][ab][r][lane] complex64 (MFMA result order)
 };
 
 // One unit of work of the MFMA engine: a problem and a tile of 16 RHS.

@@ -37,14 +37,15 @@ def test_many_rhs_ragged_tiles(variant, waves):
 @pytest.mark.parametrize("nt,k,nrhs", [(1000, 20, 21), (200, 16, 16), (512, 37, 33), (2048, 128, 17),
                                        (64, 100, 16), (1536, 5, 48)])
 @pytest.mark.parametrize("variant", ["grk", "vr_oahk", "ahk"])
-@pytest.mark.parametrize("waves", [8, 16])
-def test_shapes_padding(nt, k, nrhs, variant, waves):
-    """Nt not a multiple of 16, K not a multiple of 16, K > Nt, tiny K."""
+@pytest.mark.parametrize("waves,xws", [(8, 0), (16, 0), (16, 1)])
+def test_shapes_padding(nt, k, nrhs, variant, waves, xws):
+    """Nt not a multiple of 16, K not a multiple of 16, K > Nt, tiny K; the
+    iterate in registers (8 or 16 waves) or in the workspace."""
     rng = np.random.default_rng(nt + k)
     H, vs, vl, xi = random_problem(rng, nt, k, lo=max(1, nt // 8), hi=max(1, nt // 2))
     S = qpsk(rng, (nrhs, k))
     res, _ = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="mfma", tol=1e-5,
-                      tile_waves=waves)
+                      tile_waves=waves, x_in_workspace=xws)
     X, _ = oracle.rzf(H, vs, vl, S, xi)
     g = res[0]
     assert np.all(g["flags"] == oracle.F_CONVERGED), g["flags"]
@@ -157,3 +158,32 @@ def test_adjoint_mfma_uneven_batch():
         assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m]), jd
         assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS), jd
         assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi), jd
+
+
+@pytest.mark.parametrize("variant", ["vr_oahk", "ahk", "grk", "vr_ogrk"])
+def test_large_shape_workspace_iterate(variant):
+    """Nt 4096, K 256 (VR U[256, 1024], 16-QAM): the iterate of a tile does
+    not fit registers and lives in the workspace; 2 drops x 40 vectors."""
+    ds = synth.make_workload("large", drops=2, nrhs=40)
+    drops = [(d.H, d.vr_start, d.vr_len, d.S, d.xi) for d in ds]
+    res, plan = run_plan(drops, variant=variant, engine="mfma", tol=1e-5)
+    assert plan.query(0, 5)[6] == 0
+    for jd, (H, vs, vl, S, xi) in enumerate(drops):
+        X, _ = oracle.rzf(H, vs, vl, S, xi)
+        assert np.all(res[jd]["flags"] == oracle.F_CONVERGED), (variant, jd)
+        assert rel_err_rows(res[jd]["X"], X).max() <= 1e-4, (variant, jd)
+
+
+def test_large_shape_adjoint():
+    ds = synth.make_workload("large", drops=1, nrhs=32)
+    d = ds[0]
+    X, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+    G = 2.0 * ((X @ d.H.T - d.S) @ d.H.conj() + 0.1 * X) / d.nrhs
+    gH, gS, gxi = oracle.rzf_grad(d.H, d.vr_start, d.vr_len, d.S, d.xi, G)
+    res, _ = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant="vr_oahk", engine="mfma", tol=1e-6,
+                      adjoint_g=[G])
+    g = res[0]
+    m = np.abs(d.H) > 0
+    assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m])
+    assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS)
+    assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
