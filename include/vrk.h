@@ -190,7 +190,7 @@ typedef enum {
     VRK_Q_XIDX = 4,      /* CSR indices of X_k (ascending, includes k) */
     VRK_Q_ENGINE = 5,    /* [engine, schedule, tile_waves, lds_bytes, persistent, grid,
                             register blocks per wave (0: iterate in the workspace)] */
-    VRK_Q_TILES = 6      /* [residual chunks, aggregation chunks, band MACs] per problem */
+    VRK_Q_TILES = 6      /* [residual tiles, aggregation tiles, band entries, Gram tiles] per problem */
 } vrk_query;
 int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *out, int64_t cap);
 

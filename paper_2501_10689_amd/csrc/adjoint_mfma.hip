@@ -20,6 +20,19 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Sums of complex products with three real products each (Gauss):
+// u += Ar Br, v += Ai Bi, w += (Ar + Ai)(Br + Bi); Re = u - v, Im = w - u - v.
+struct C3 {
+    f4 u, v, w;
+};
+
+__device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
+{
+    acc.u = mfma(a.x, b.x, acc.u);
+    acc.v = mfma(a.y, b.y, acc.v);
+    acc.w = mfma(a.x + a.y, b.x + b.y, acc.w);
+}
+
 // b = H g for one tile of 16 RHS and one 16-user block (one wave):
 // D[user][rhs] = sum over the block's band chunks of HA-tile x GX.
 __global__ void __launch_bounds__(64) k_adj_rhs_mfma(const VrkDesc *descs, const VrkWork *work)
@@ -36,20 +49,18 @@ __global__ void __launch_bounds__(64) k_adj_rhs_mfma(const VrkDesc *descs, const
     const int64_t hb = d.ha_off[ub];
     const bool bok = b < d.nrhs;
     const float2 *grow = GX + (int64_t)(bok ? b : 0) * d.ldgx;
-    f4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    C3 acc = {z, z, z};
     for (int ab = lo; ab < hi; ++ab) {
         const float2 *hp = HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int n = 16 * ab + 4 * g + m;   // reduction slot g of chunk (ab, m)
             float2 x = (bok && n < d.nt) ? grow[n] : float2{0.f, 0.f};
-            float2 h = hp[64 * m];
-            re = mfma(h.x, x.x, re);
-            re = mfma(-h.y, x.y, re);
-            im = mfma(h.x, x.y, im);
-            im = mfma(h.y, x.x, im);
+            c3mfma(acc, hp[64 * m], x);
         }
     }
+    const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
     if (bok) {
         float2 *out = reinterpret_cast<float2 *>(d.Sadj) + (int64_t)b * d.k;
 #pragma unroll
@@ -80,7 +91,8 @@ __device__ __forceinline__ void grads_tile(const VrkDesc &d, int ub, int ab, flo
     const int B = d.nrhs;
     const int per = (B + kGW - 1) / kGW;
     const int bs = w * per, be = min(B, bs + per);
-    f4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    C3 acc = {z, z, z};
     for (int b0 = bs; b0 < be; b0 += 4) {
         const int b = b0 + kk;
         float2 v = {0.f, 0.f}, mu = {0.f, 0.f}, y = {0.f, 0.f}, xv = {0.f, 0.f};
@@ -95,17 +107,10 @@ __device__ __forceinline__ void grads_tile(const VrkDesc &d, int ub, int ab, flo
                 xv = X[(int64_t)b * d.ldx + n];
             }
         }
-        // v * conj(y)
-        re = mfma(v.x, y.x, re);
-        re = mfma(v.y, y.y, re);
-        im = mfma(v.y, y.x, im);
-        im = mfma(-v.x, y.y, im);
-        // - mu * conj(x)
-        re = mfma(-mu.x, xv.x, re);
-        re = mfma(-mu.y, xv.y, re);
-        im = mfma(-mu.y, xv.x, im);
-        im = mfma(mu.x, xv.y, im);
+        c3mfma(acc, v, float2{y.x, -y.y});            // v conj(y)
+        c3mfma(acc, float2{-mu.x, -mu.y}, float2{xv.x, -xv.y});   // - mu conj(x)
     }
+    const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
     // D layout: lane (j, g) register r holds user 4 g + r, antenna j
     const int jj = lane & 15, gg = lane >> 4;
 #pragma unroll

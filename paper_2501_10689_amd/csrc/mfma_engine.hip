@@ -29,21 +29,37 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// acc += A * B for complex operands held one per lane (4 real products,
-// alternating accumulators so consecutive MFMAs are independent).
-__device__ __forceinline__ void cmfma(f4 &re, f4 &im, float2 a, float2 b)
+// Complex product A * B accumulated with three real products (Gauss):
+// u += Ar Br, v += Ai Bi, w += (Ar + Ai)(Br + Bi); then Re = u - v and
+// Im = w - u - v. Operands are held one complex value per lane.
+struct C3 {
+    f4 u, v, w;
+};
+
+__device__ __forceinline__ C3 c3_zero()
 {
-    re = mfma(a.x, b.x, re);
-    im = mfma(a.x, b.y, im);
-    re = mfma(-a.y, b.y, re);
-    im = mfma(a.y, b.x, im);
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    return C3{z, z, z};
+}
+
+__device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
+{
+    acc.u = mfma(a.x, b.x, acc.u);
+    acc.v = mfma(a.y, b.y, acc.v);
+    acc.w = mfma(a.x + a.y, b.x + b.y, acc.w);
+}
+
+__device__ __forceinline__ void c3_get(const C3 &acc, f4 &re, f4 &im)
+{
+    re = acc.u - acc.v;
+    im = acc.w - acc.u - acc.v;
 }
 
 struct MfmaLds {
     float2 *R, *Q, *Rp;
     float *nrm, *pre, *red, *snorm, *rel, *gre, *gim, *num, *phin, *pnw;
     int *posl, *active, *iters, *flags, *pick, *any;
-    int *agoff, *rlo, *rhi, *hoff;   // copies of the tile tables of this problem
+    int *agoff, *rlo, *rhi, *hoff, *gmoff;   // copies of the tile tables of this problem
 };
 
 __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char *base, MfmaLds *L)
@@ -64,13 +80,14 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
     char *pnw = take((size_t)W * 16 * 4);
     char *posl = take((size_t)kpad * 4);
     char *ints = take(16 * 4 * 4 + 16);
-    char *tabs = take((size_t)(nab + 1 + 3 * (kpad / 16)) * 4);
+    char *tabs = take((size_t)(nab + 1 + 4 * (kpad / 16) + 1) * 4);
     if (L) {
         int *tb = (int *)tabs;
         L->agoff = tb;
         L->rlo = tb + nab + 1;
         L->rhi = L->rlo + kpad / 16;
         L->hoff = L->rhi + kpad / 16;
+        L->gmoff = L->hoff + kpad / 16;
         L->R = (float2 *)R;
         L->Q = (float2 *)Q;
         L->Rp = (float2 *)Rp;
@@ -122,7 +139,7 @@ __device__ __forceinline__ float col_sum(float v, float *red)
 struct TileCtx {
     const VrkDesc *d;
     MfmaLds L;
-    const float2 *S, *H, *HA, *HG;
+    const float2 *S, *H, *HA, *HG, *GM;
     float2 *Xw;   // global-iterate mode: this tile's x, [ab][r][lane] (MFMA result order)
     int64_t lds;
     int K, N, nub, kpad, nab, b0, nrhs, prob;
@@ -145,7 +162,7 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
 #pragma unroll 1
         for (int u2 = 0; u2 < 2; ++u2) {
             const int ub = gi * 2 + u2;
-            f4 are = {0.f, 0.f, 0.f, 0.f}, aim = {0.f, 0.f, 0.f, 0.f};
+            C3 acc = c3_zero();
             if (ub < c.nub) {
                 const int lo = c.L.rlo[ub], hi = c.L.rhi[ub];
                 const int64_t hb = c.L.hoff[ub];
@@ -158,10 +175,10 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                         const float2 *xp = c.Xw + (int64_t)ab * 256 + lane;
                         float2 h0 = hp[0], h1 = hp[64], h2 = hp[128], h3 = hp[192];
                         float2 x0 = xp[0], x1 = xp[64], x2 = xp[128], x3 = xp[192];
-                        cmfma(are, aim, h0, x0);
-                        cmfma(are, aim, h1, x1);
-                        cmfma(are, aim, h2, x2);
-                        cmfma(are, aim, h3, x3);
+                        c3mfma(acc, h0, x0);
+                        c3mfma(acc, h1, x1);
+                        c3mfma(acc, h2, x2);
+                        c3mfma(acc, h3, x3);
                     }
                 } else {
 #pragma unroll
@@ -170,14 +187,16 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                         if (ab >= lo && ab < hi) {
                             const float2 *hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
                             float2 h0 = hp[0], h1 = hp[64], h2 = hp[128], h3 = hp[192];
-                            cmfma(are, aim, h0, float2{xr[t][0], xq[t][0]});
-                            cmfma(are, aim, h1, float2{xr[t][1], xq[t][1]});
-                            cmfma(are, aim, h2, float2{xr[t][2], xq[t][2]});
-                            cmfma(are, aim, h3, float2{xr[t][3], xq[t][3]});
+                            c3mfma(acc, h0, float2{xr[t][0], xq[t][0]});
+                            c3mfma(acc, h1, float2{xr[t][1], xq[t][1]});
+                            c3mfma(acc, h2, float2{xr[t][2], xq[t][2]});
+                            c3mfma(acc, h3, float2{xr[t][3], xq[t][3]});
                         }
                     }
                 }
             }
+            f4 are, aim;
+            c3_get(acc, are, aim);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 c.L.Rp[(w * VRK_RGROUP + u2 * 16 + 4 * g + r) * 16 + j] = float2{are[r], aim[r]};
@@ -254,8 +273,7 @@ __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, f4 &pr, f4 &
 {
     const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
     const VrkDesc &d = *c.d;
-    pr = f4{0.f, 0.f, 0.f, 0.f};
-    pi = f4{0.f, 0.f, 0.f, 0.f};
+    C3 acc = c3_zero();
     const int e0 = c.L.agoff[ab], e1 = c.L.agoff[ab + 1];
     int e = e0;
 #pragma unroll 1
@@ -263,51 +281,48 @@ __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, f4 &pr, f4 &
         const int uc0 = d.ag_uc[e], uc1 = d.ag_uc[e + 1];
         float2 h0 = c.HG[(int64_t)e * 64 + lane], h1 = c.HG[(int64_t)(e + 1) * 64 + lane];
         float2 f0 = c.L.R[(4 * uc0 + g) * 16 + j], f1 = c.L.R[(4 * uc1 + g) * 16 + j];
-        cmfma(pr, pi, h0, f0);
-        cmfma(pr, pi, h1, f1);
+        c3mfma(acc, h0, f0);
+        c3mfma(acc, h1, f1);
     }
     if (e < e1) {
         const int uc = d.ag_uc[e];
-        cmfma(pr, pi, c.HG[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
+        c3mfma(acc, c.HG[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
     }
+    c3_get(acc, pr, pi);
 }
 
-// Aggregated projection (update4): P = H^H phi per antenna block gives
-// ||P||^2 per column and gamma = num / (||P||^2 + xi ||phi||^2), then
-// x += gamma P in registers and q += gamma phi. With at most 8 blocks per
-// wave set P stays in registers between the two when x and P together take
-// at most a quarter of the per-wave register budget (2048 / W); otherwise
-// P is recomputed.
+// Aggregated projection (update4): x += gamma H^H phi, q += gamma phi with
+// gamma = phi^H r / ||A^H phi||^2. The denominator is evaluated through the
+// Gram identity ||A^H phi||^2 = ||H^H phi||^2 + xi ||phi||^2
+// = phi^H (H H^H + xi I) phi on the Gram tiles, so gamma is known before
+// P = H^H phi is formed and P goes straight into x (one pass).
 template <int W, int NA>
 __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? NA : 1], f4 (&xq)[NA ? NA : 1])
 {
-    constexpr bool kKeepP = NA > 0 && 16 * NA * W <= 512;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
     const int er = tid >> 4, rows_per_pass = W * 4;
-    float pn = 0.f;
-    f4 pr[kKeepP ? NA : 1], pi[kKeepP ? NA : 1];
-    if constexpr (NA == 0) {
+    const VrkDesc &d = *c.d;
+    // phi^H M phi: row blocks mb of M phi on the waves, dotted with phi
+    float den = 0.f;
 #pragma unroll 1
-        for (int ab = w; ab < c.nab; ab += W) {
-            agg_block(c, ab, pr[0], pi[0]);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) pn += pr[0][r] * pr[0][r] + pi[0][r] * pi[0][r];
+    for (int mb = w; mb < c.nub; mb += W) {
+        C3 acc = c3_zero();
+        const int e0 = c.L.gmoff[mb], e1 = c.L.gmoff[mb + 1];
+#pragma unroll 1
+        for (int e = e0; e < e1; ++e) {
+            const int uc = d.gm_c[e];
+            c3mfma(acc, c.GM[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
         }
-    } else {
+        f4 mr, mi;
+        c3_get(acc, mr, mi);
 #pragma unroll
-        for (int t = 0; t < NA; ++t) {
-            const int ab = w + W * t;
-            const int ts = kKeepP ? t : 0;
-            if (ab < c.nab) {
-                agg_block(c, ab, pr[ts], pi[ts]);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) pn += pr[ts][r] * pr[ts][r] + pi[ts][r] * pi[ts][r];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const float2 f = c.L.R[(16 * mb + 4 * g + r) * 16 + j];
+            den += f.x * mr[r] + f.y * mi[r];
         }
     }
-    pn = col_sum<W>(pn, c.L.red);
+    den = col_sum<W>(den, c.L.red);
     if (tid < 16) {
-        const float den = pn + c.xi * c.L.phin[tid];
         const float num = c.L.num[tid];
         c.L.gre[tid] = (c.L.active[tid] && num > 0.f && den > 0.f) ? num / den : 0.f;
     }
@@ -325,15 +340,11 @@ __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? N
                 xp[64 * r] = float2{x.x + gm * qr[r], x.y + gm * qi[r]};
             }
         }
-    }
+    } else {
 #pragma unroll
-    for (int t = 0; t < NA; ++t) {
-        const int ab = w + W * t;
-        if (ab < c.nab) {
-            if constexpr (kKeepP) {
-                xr[t] += gm * pr[t];
-                xq[t] += gm * pi[t];
-            } else {
+        for (int t = 0; t < NA; ++t) {
+            const int ab = w + W * t;
+            if (ab < c.nab) {
                 f4 qr, qi;
                 agg_block(c, ab, qr, qi);
                 xr[t] += gm * qr;
@@ -381,6 +392,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
     c.H = reinterpret_cast<const float2 *>(d.H);
     c.HA = reinterpret_cast<const float2 *>(d.HA);
     c.HG = reinterpret_cast<const float2 *>(d.HG);
+    c.GM = reinterpret_cast<const float2 *>(d.GM);
     c.Xw = NA == 0 ? reinterpret_cast<float2 *>(d.Xw) + (int64_t)wk.tile * c.nab * 256 : nullptr;
     const float *nrm_g = reinterpret_cast<const float *>(d.nrm);
     const int K = c.K, N = c.N, kpad = c.kpad, b0 = c.b0;
@@ -413,6 +425,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
         if (ku < K) L.posl[d.perm[ku]] = ku;
     }
     for (int i = tid; i <= c.nab; i += W * 64) L.agoff[i] = d.ag_off[i];
+    for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = d.gm_off[i];
     for (int i = tid; i < c.nub; i += W * 64) {
         L.rlo[i] = d.rab_lo[i];
         L.rhi[i] = d.rab_hi[i];

@@ -67,15 +67,16 @@ struct ProbPlan {
     int32_t ncol = 0;
     // MFMA tables
     int32_t nub = 0, nab = 0, ntile = 0;
-    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, fown;
+    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, fown, gm_off, gm_c;
     std::vector<int64_t> ha_off;
-    int64_t n_ha = 0, n_hg = 0, band = 0;
+    int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
     // workspace offsets
     size_t o_vs, o_ve, o_xoff, o_xidx, o_flist, o_vlist, o_inf, o_coloff, o_colusr, o_gboff,
         o_gbusr, o_perm, o_pos, o_nrm, o_fro2, o_rablo, o_rabhi, o_haoff, o_agoff, o_aguc,
         o_fown, o_ha, o_hg, o_sadj, o_xadj, o_vfwd;
     int64_t rhs_base = 0;
     size_t o_xw = 0;   // MFMA iterate buffer when x does not fit registers
+    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0;
 };
 
 }  // namespace
@@ -282,6 +283,26 @@ void build_tables(ProbPlan &q)
     q.fown.assign((size_t)q.nab * VRK_AB, -1);
     for (int u : q.flist)
         for (int32_t n = q.vs[u]; n < q.ve[u]; ++n) q.fown[n] = q.pos[u];
+    // Gram blocks (16-user block, 4-user chunk) with any pair of overlapping
+    // VRs or a shared user (the diagonal), in VR-start order
+    q.gm_off.assign(q.nub + 1, 0);
+    q.gm_c.clear();
+    for (int mb = 0; mb < q.nub; ++mb) {
+        q.gm_off[mb] = (int32_t)q.gm_c.size();
+        for (int uc = 0; uc < nuc; ++uc) {
+            bool any = false;
+            for (int i = mb * VRK_UB; i < std::min(K, (mb + 1) * VRK_UB) && !any; ++i)
+                for (int t = 0; t < 4 && !any; ++t) {
+                    const int kv = uc * 4 + t;
+                    if (kv >= K) break;
+                    const int a = q.perm[i], b = q.perm[kv];
+                    any = (a == b) || std::max(q.vs[a], q.vs[b]) < std::min(q.ve[a], q.ve[b]);
+                }
+            if (any) q.gm_c.push_back(uc);
+        }
+    }
+    q.gm_off[q.nub] = (int32_t)q.gm_c.size();
+    q.n_gm = (int64_t)q.gm_c.size();
 }
 
 template <class T>
@@ -446,6 +467,8 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_agoff = cv.take(4 * q.ag_off.size());
         q.o_aguc = cv.take(4 * q.ag_uc.size());
         q.o_fown = cv.take(4 * q.fown.size());
+        q.o_gmoff = cv.take(4 * q.gm_off.size());
+        q.o_gmc = cv.take(4 * q.gm_c.size());
     }
     pl->table_end = cv.off;
     for (auto &q : pl->pp) {
@@ -455,6 +478,8 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             q.o_ha = cv.take(q.n_ha * 64 * 8);
             q.o_hg = cv.take(q.n_hg * 64 * 8);
             if (pl->na == 0) q.o_xw = cv.take((size_t)q.ntile * q.nab * 256 * 8);
+            q.o_gm = cv.take(q.n_gm * 64 * 8);
+            pl->max_tiles = std::max(pl->max_tiles, q.n_gm);
             pl->max_tiles = std::max(pl->max_tiles, std::max(q.n_ha, q.n_hg));
         }
         if (q.p.GX) {
@@ -504,6 +529,8 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         put(img, q.o_agoff, q.ag_off);
         put(img, q.o_aguc, q.ag_uc);
         put(img, q.o_fown, q.fown);
+        put(img, q.o_gmoff, q.gm_off);
+        put(img, q.o_gmc, q.gm_c);
         VrkDesc &d = descs[i];
         std::memset(&d, 0, sizeof d);
         const vrk_problem &p = q.p;
@@ -545,6 +572,9 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.HA = pl->engine == VRK_ENGINE_MFMA ? base + q.o_ha : nullptr;
         d.HG = pl->engine == VRK_ENGINE_MFMA ? base + q.o_hg : nullptr;
         d.Xw = (pl->engine == VRK_ENGINE_MFMA && pl->na == 0) ? base + q.o_xw : nullptr;
+        d.gm_off = (const int32_t *)(base + q.o_gmoff);
+        d.gm_c = (const int32_t *)(base + q.o_gmc);
+        d.GM = pl->engine == VRK_ENGINE_MFMA ? base + q.o_gm : nullptr;
         (void)eb;
     }
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());
@@ -670,7 +700,7 @@ int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *
     case VRK_Q_XIDX: v = q.xidx; break;
     case VRK_Q_ENGINE: v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->na};
         break;
-    case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band}; break;
+    case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band, (int32_t)q.n_gm}; break;
     default: return -1;
     }
     int64_t n = (int64_t)v.size();

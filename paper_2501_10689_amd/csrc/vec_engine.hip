@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(kThreads) k_norms(const VrkDesc *descs)
 // holds H[perm[16 ub + i], 16 ab + 4 kk + m] with ab = rab_lo[ub] + c / 4,
 // m = c % 4, zero outside that user's VR. Aggregation tile e of antenna
 // block ab: lane l = i + 16 kk holds conj(H[perm[4 uc + kk], 16 ab + i]).
-// One wave per tile.
+// Gram tiles hold H H^H + xi I in VR-start order. One wave per tile.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
 {
@@ -109,6 +109,28 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
             }
         }
         reinterpret_cast<cx<float> *>(d.HG)[t * 64 + lane] = v;
+    }
+    const int64_t n_gm = d.gm_off[d.nub];
+    if (t < n_gm) {
+        // Gram tile e of user block mb: lane l = i + 16 kk holds
+        // M[perm[16 mb + i], perm[4 c + kk]] = sum over the overlap of
+        // H[u, n] conj(H[v, n]) (+ xi on the diagonal)
+        int mb = 0;
+        while (d.gm_off[mb + 1] <= t) ++mb;
+        const int uc = d.gm_c[t];
+        const int ku = mb * VRK_UB + i, kv = uc * 4 + kk;
+        float ar = 0.f, ai = 0.f;
+        if (ku < d.k && kv < d.k) {
+            const int u = d.perm[ku], v2 = d.perm[kv];
+            const int lo = max(d.vs[u], d.vs[v2]), hi = min(d.ve[u], d.ve[v2]);
+            for (int n = lo; n < hi; ++n) {
+                cx<float> a = H[(int64_t)u * d.ldh + n], b = H[(int64_t)v2 * d.ldh + n];
+                ar += a.re * b.re + a.im * b.im;
+                ai += a.im * b.re - a.re * b.im;
+            }
+            if (u == v2) ar += (float)d.xi;
+        }
+        reinterpret_cast<cx<float> *>(d.GM)[t * 64 + lane] = cx<float>{ar, ai};
     }
 }
 

@@ -53,6 +53,8 @@ struct VrkDesc {
     void *HG;                     // aggregation tiles (conjugated), 64 complex64 each
     void *Xw;                     // iterate of each 16-RHS tile when it does not fit registers:
                                   // [tile][ab][r][lane] complex64 (MFMA result order)
+    const int32_t *gm_off, *gm_c; // per 16-user block: 4-user chunks with a nonzero Gram block (CSR)
+    void *GM;                     // Gram tiles of H H^H + xi I (VR-start order), 64 complex64 each
 };
 
 // One unit of work of the MFMA engine: a problem and a tile of 16 RHS.
