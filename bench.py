@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after timing, copy a device buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path has no cross-GPU exchange "
@@ -291,6 +293,13 @@ def main():
                                "sample": "%d vectors from the first %d of %d drops (%.1f s): FP64 %s "
                                          "iterations to tol %g (OpenMP over vectors) + closed-form gradient"
                                          % (n_cpu, done, len(drops), t_cpu, args.variant, tol)}
+    if args.copy_mb:
+        src = torch.ones(args.copy_mb * 262144, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = args.copy_mb * 1048576
     print(json.dumps(out), flush=True)
 
 

@@ -76,7 +76,8 @@ __global__ void __launch_bounds__(64) k_adj_rhs_mfma(const VrkDesc *descs, const
 // dimension split over the 8 waves and reduced through LDS.
 constexpr int kGW = 8;
 
-__device__ __forceinline__ void grads_tile(const VrkDesc &d, int ub, int ab, float2 (*part)[256])
+__device__ __forceinline__ void grads_tile(const VrkDesc &d, int ub, int ab, int bs0, int be0,
+                                           float2 (*part)[256], float2 *out)
 {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 15, kk = lane >> 4;
     const float2 *V = reinterpret_cast<const float2 *>(d.V);
@@ -88,9 +89,9 @@ __device__ __forceinline__ void grads_tile(const VrkDesc &d, int ub, int ab, flo
     const int user = ku < d.k ? d.perm[ku] : -1;
     const int n = ab * VRK_AB + i;           // B operand column (antenna) of this lane
     const bool nok = n < d.nt;
-    const int B = d.nrhs;
-    const int per = (B + kGW - 1) / kGW;
-    const int bs = w * per, be = min(B, bs + per);
+    // this workgroup's RHS range [bs0, be0), split over the waves
+    const int per = (be0 - bs0 + kGW - 1) / kGW;
+    const int bs = bs0 + w * per, be = min(be0, bs + per);
     const f4 z = {0.f, 0.f, 0.f, 0.f};
     C3 acc = {z, z, z};
     for (int b0 = bs; b0 < be; b0 += 4) {
@@ -117,36 +118,71 @@ __device__ __forceinline__ void grads_tile(const VrkDesc &d, int ub, int ab, flo
     for (int r = 0; r < 4; ++r) part[w][(4 * gg + r) * 16 + jj] = float2{re[r], im[r]};
     __syncthreads();
     if (tid < 256) {
-        const int ii = tid >> 4, nj = tid & 15;
         float sr = 0.f, si = 0.f;
 #pragma unroll
         for (int ww = 0; ww < kGW; ++ww) {
             sr += part[ww][tid].x;
             si += part[ww][tid].y;
         }
-        const int kq = ub * VRK_UB + ii, nn = ab * VRK_AB + nj;
-        if (kq < d.k) {
-            const int u = d.perm[kq];
-            if (nn >= d.vs[u] && nn < d.ve[u])
-                reinterpret_cast<float2 *>(d.GH)[(int64_t)u * d.ldgh + nn] = float2{sr, si};
+        if (out) {
+            out[tid] = float2{sr, si};   // partial over this workgroup's RHS range
+        } else {
+            const int ii = tid >> 4, nj = tid & 15;
+            const int kq = ub * VRK_UB + ii, nn = ab * VRK_AB + nj;
+            if (kq < d.k) {
+                const int u = d.perm[kq];
+                if (nn >= d.vs[u] && nn < d.ve[u])
+                    reinterpret_cast<float2 *>(d.GH)[(int64_t)u * d.ldgh + nn] = float2{sr, si};
+            }
         }
     }
 }
 
-__global__ void __launch_bounds__(kGW * 64) k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles)
+// Sum the RHS-split partials of each band tile in fixed order and write the
+// VR band entries of GH.
+__global__ void __launch_bounds__(256) k_adj_grads_reduce(const VrkDesc *descs, const int4 *tiles, int nsplit,
+                                                          const float2 *gpart)
+{
+    const int4 tl = tiles[blockIdx.x];
+    if (tl.y < 0) return;
+    const VrkDesc &d = descs[tl.x];
+    const int tid = threadIdx.x, ii = tid >> 4, nj = tid & 15;
+    float sr = 0.f, si = 0.f;
+    for (int sp = 0; sp < nsplit; ++sp) {
+        float2 p = gpart[((int64_t)blockIdx.x * nsplit + sp) * 256 + tid];
+        sr += p.x;
+        si += p.y;
+    }
+    const int kq = tl.y * VRK_UB + ii, nn = tl.z * VRK_AB + nj;
+    if (kq < d.k) {
+        const int u = d.perm[kq];
+        if (nn >= d.vs[u] && nn < d.ve[u])
+            reinterpret_cast<float2 *>(d.GH)[(int64_t)u * d.ldgh + nn] = float2{sr, si};
+    }
+}
+
+// Workgroup (tile, split): RHS range split of the band tile; with nsplit 1
+// it writes GH directly, else its partial to gpart.
+__global__ void __launch_bounds__(kGW * 64) k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, int nsplit,
+                                                             float2 *gpart)
 {
     __shared__ float2 part[kGW][256];
     __shared__ float red[kGW];
-    const int4 tl = tiles[blockIdx.x];   // (problem, user block, antenna block, first-of-problem)
+    const int tix = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+    const int4 tl = tiles[tix];   // (problem, user block, antenna block, first-of-problem)
     const VrkDesc &d = descs[tl.x];
     const int ub = tl.y, ab = tl.z;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const float2 *V = reinterpret_cast<const float2 *>(d.V);
     const float2 *GS = reinterpret_cast<const float2 *>(d.GS);
     const int B = d.nrhs;
-    if (ub >= 0) grads_tile(d, ub, ab, part);
+    const int per = (B + nsplit - 1) / nsplit;
+    const int bs0 = min(B, split * per), be0 = min(B, bs0 + per);
+    if (ub >= 0)
+        grads_tile(d, ub, ab, bs0, be0, part,
+                   nsplit > 1 ? gpart + ((int64_t)tix * nsplit + split) * 256 : nullptr);
     // dL/dxi = -Re sum_{b,k} conj(mu) v, by one entry per problem
-    if (tl.w) {
+    if (tl.w && split == 0) {
         float acc = 0.f;
         const int64_t tot = (int64_t)B * d.k;
         for (int64_t e = tid; e < tot; e += kGW * 64) {
@@ -176,9 +212,14 @@ hipError_t vrk_launch_adjoint_rhs_mfma(const VrkDesc *desc, const VrkWork *work,
     return hipGetLastError();
 }
 
-hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, hipStream_t s)
+hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
+                                         float2 *gpart, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_grads_mfma, dim3(ntiles), dim3(kGW * 64), 0, s, desc, tiles);
+    hipLaunchKernelGGL(k_adj_grads_mfma, dim3((unsigned)ntiles * nsplit), dim3(kGW * 64), 0, s, desc, tiles, nsplit,
+                       gpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsplit <= 1) return e;
+    hipLaunchKernelGGL(k_adj_grads_reduce, dim3(ntiles), dim3(256), 0, s, desc, tiles, nsplit, gpart);
     return hipGetLastError();
 }

@@ -56,5 +56,7 @@ hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t 
 // first-of-problem flag for the xi gradient; user block -1 = xi only).
 hipError_t vrk_launch_adjoint_rhs_mfma(const VrkDesc *desc, const VrkWork *work, int32_t nwork,
                                        int32_t max_nub, hipStream_t s);
-hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles,
-                                         hipStream_t s);
+// nsplit > 1 splits each tile's RHS range over nsplit workgroups writing
+// partials to gpart (ntiles * nsplit * 256 complex64), summed by a second kernel.
+hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
+                                         float2 *gpart, hipStream_t s);

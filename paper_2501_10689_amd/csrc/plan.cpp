@@ -95,6 +95,8 @@ struct vrk_plan {
     size_t o_gtiles = 0;
     int32_t qbase[VRK_NQUEUE] = {0}, qsize[VRK_NQUEUE] = {0};
     size_t o_queue = 0;         // int32 counters[8], base[8], size[8]
+    int32_t gsplit = 1;         // RHS splits of the adjoint gradient tiles
+    size_t o_gpart = 0;
     int32_t persistent = 0, grid = 0;
     int32_t max_nub = 0;
     std::vector<uint8_t> image;
@@ -438,6 +440,13 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
                     }
                 if (first) pl->gtiles.push_back(make_int4(i, -1, 0, 1));
             }
+        if (!pl->gtiles.empty()) {
+            // enough workgroups to fill the device (about 2048), each split
+            // keeping at least 64 right-hand sides
+            int64_t want = 2048 / (int64_t)pl->gtiles.size();
+            int64_t cap = std::max<int64_t>(1, min_rhs / 64);
+            pl->gsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 16}));
+        }
     }
     // workspace carving
     const int32_t eb = elem_bytes(o.dtype), rb = o.dtype == VRK_C128 ? 8 : 4;
@@ -446,6 +455,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     pl->o_work = cv.take(sizeof(VrkWork) * std::max<size_t>(1, pl->work.size()));
     pl->o_gtiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->gtiles.size()));
     pl->o_queue = cv.take(sizeof(int32_t) * 3 * VRK_NQUEUE);
+    pl->o_gpart = cv.take(pl->gsplit > 1 ? pl->gtiles.size() * (size_t)pl->gsplit * 256 * 8 : 0);
     for (auto &q : pl->pp) {
         const int K = q.p.k;
         q.o_vs = cv.take(4 * K);
@@ -681,7 +691,8 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
     vrk_status st = run_solve(pl, stream, d_iters, d_relres, d_flags, 1);
     if (st != VRK_OK) return st;
     e = mf ? vrk_launch_adjoint_grads_mfma(dd, reinterpret_cast<const int4 *>(pl->d_ws + pl->o_gtiles),
-                                           (int32_t)pl->gtiles.size(), s)
+                                           (int32_t)pl->gtiles.size(), pl->gsplit,
+                                           reinterpret_cast<float2 *>(pl->d_ws + pl->o_gpart), s)
            : vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient kernel");
     return VRK_OK;
