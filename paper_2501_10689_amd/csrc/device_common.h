@@ -6,6 +6,25 @@
 
 #include "vrk_desc.h"
 
+// AMDGPU address spaces: global memory, and the read-only constant space
+// whose wave-uniform loads are scalar loads into SGPRs. Pointers read from a
+// descriptor are generic; casting them to global lets the compiler issue
+// global (not flat) loads, which do not hold up waits on LDS traffic.
+// The host pass of hipcc type-checks the same templates for x86, which has
+// no such address spaces: there the qualifiers are empty.
+#ifdef __HIP_DEVICE_COMPILE__
+#define VRK_GLOBAL __attribute__((address_space(1)))
+#define VRK_CONST __attribute__((address_space(4)))
+#else
+#define VRK_GLOBAL
+#define VRK_CONST
+#endif
+template <typename T>
+__device__ __forceinline__ VRK_GLOBAL T *gmem(T *p)
+{
+    return (VRK_GLOBAL T *)p;
+}
+
 template <typename R>
 struct cx {
     R re, im;

@@ -57,8 +57,8 @@ __device__ __forceinline__ void c3_get(const C3 &acc, f4 &re, f4 &im)
 
 struct MfmaLds {
     float2 *R, *Q, *Rp;
-    float *nrm, *pre, *red, *snorm, *rel, *gre, *gim, *num, *phin, *pnw;
-    int *posl, *active, *iters, *flags, *pick, *any;
+    float *nrm, *pre, *red, *snorm, *rel, *gre, *gim;
+    int *posl, *active, *iters, *flags, *pick;
     int *agoff, *rlo, *rhi, *hoff, *gmoff;   // copies of the tile tables of this problem
 };
 
@@ -75,13 +75,14 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
     char *Rp = take((size_t)W * VRK_RGROUP * 16 * 8);
     char *nrm = take((size_t)kpad * 4);
     char *pre = take((size_t)W * kpad * 4);
-    char *red = take((size_t)(W * 16 + 16) * 4);
-    char *sc = take(16 * 4 * 8);
-    char *pnw = take((size_t)W * 16 * 4);
+    char *red = take((size_t)2 * W * 16 * 4);
+    char *sc = take(16 * 4 * 4);
     char *posl = take((size_t)kpad * 4);
-    char *ints = take(16 * 4 * 4 + 16);
+    char *ints = take(16 * 4 * 4);
     char *tabs = take((size_t)(nab + 1 + 4 * (kpad / 16) + 1) * 4);
-    if (L) {
+    // test the LDS base, not L: L points into a caller's register-resident
+    // struct, and comparing its address would pin that struct to memory
+    if (base) {
         int *tb = (int *)tabs;
         L->agoff = tb;
         L->rlo = tb + nab + 1;
@@ -99,22 +100,19 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         L->rel = s + 16;
         L->gre = s + 32;
         L->gim = s + 48;
-        L->num = s + 64;
-        L->phin = s + 80;
-        L->pnw = (float *)pnw;
         L->posl = (int *)posl;
         int *ip = (int *)ints;
         L->active = ip;
         L->iters = ip + 16;
         L->flags = ip + 32;
         L->pick = ip + 48;
-        L->any = ip + 64;
     }
     return off;
 }
 
-// Sum over the threads of each RHS column j = tid % 16; every thread gets
-// its column's total. Deterministic order.
+// Sums over the threads of each RHS column j = tid % 16; every thread gets
+// its column's totals. Two barriers: one before the per-wave partials are
+// written (earlier readers of the buffer are done), one after. Fixed order.
 template <int W>
 __device__ __forceinline__ float col_sum(float v, float *red)
 {
@@ -124,23 +122,47 @@ __device__ __forceinline__ float col_sum(float v, float *red)
     __syncthreads();
     if (lane < 16) red[w * 16 + lane] = v;
     __syncthreads();
-    if (tid < 16) {
-        float s = 0;
+    float s = 0.f;
 #pragma unroll
-        for (int i = 0; i < W; ++i) s += red[i * 16 + tid];
-        red[W * 16 + tid] = s;
+    for (int i = 0; i < W; ++i) s += red[i * 16 + (tid & 15)];
+    return s;
+}
+
+template <int W>
+__device__ __forceinline__ float2 col_sum2(float a, float b, float *red)
+{
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    a += __shfl_xor(a, 16, 64);
+    a += __shfl_xor(a, 32, 64);
+    b += __shfl_xor(b, 16, 64);
+    b += __shfl_xor(b, 32, 64);
+    __syncthreads();
+    if (lane < 16) {
+        red[w * 16 + lane] = a;
+        red[(W + w) * 16 + lane] = b;
     }
     __syncthreads();
-    return red[W * 16 + (tid & 15)];
+    float sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        sa += red[i * 16 + (tid & 15)];
+        sb += red[(W + i) * 16 + (tid & 15)];
+    }
+    return float2{sa, sb};
 }
 
 // Per-tile constants shared by the phases below (passed by value so that
 // everything stays in registers after inlining).
+using CDesc = const VRK_CONST VrkDesc;
+template <typename T>
+using gp = VRK_GLOBAL T *;
+
 struct TileCtx {
-    const VrkDesc *d;
     MfmaLds L;
-    const float2 *S, *H, *HA, *HG, *GM;
-    float2 *Xw;   // global-iterate mode: this tile's x, [ab][r][lane] (MFMA result order)
+    gp<const float2> S, H, HA, HG, GM, FH;
+    gp<float2> Xw;   // global-iterate mode: this tile's x, [ab][r][lane] (MFMA result order)
+    gp<const int32_t> perm, vs, ve, ag_uc, gm_c, fown;
+    gp<const uint8_t> inf;
     int64_t lds;
     int K, N, nub, kpad, nab, b0, nrhs, prob;
     float xi;
@@ -154,7 +176,6 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                                               const f4 (&xq)[NA ? NA : 1], bool ogrk)
 {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
-    const VrkDesc &d = *c.d;
     const int nug = (c.nub + 1) / 2;
     const int er = tid >> 4, rows_per_pass = W * 4;
 #pragma unroll 1
@@ -171,8 +192,8 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                     int ab = lo + ((w - lo) % W + W) % W;
 #pragma unroll 1
                     for (; ab < hi; ab += W) {
-                        const float2 *hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
-                        const float2 *xp = c.Xw + (int64_t)ab * 256 + lane;
+                        const gp<const float2> hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
+                        const gp<const float2> xp = c.Xw + (int64_t)ab * 256 + lane;
                         float2 h0 = hp[0], h1 = hp[64], h2 = hp[128], h3 = hp[192];
                         float2 x0 = xp[0], x1 = xp[64], x2 = xp[128], x3 = xp[192];
                         c3mfma(acc, h0, x0);
@@ -185,7 +206,7 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                     for (int t = 0; t < NA; ++t) {
                         const int ab = w + W * t;
                         if (ab >= lo && ab < hi) {
-                            const float2 *hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
+                            const gp<const float2> hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
                             float2 h0 = hp[0], h1 = hp[64], h2 = hp[128], h3 = hp[192];
                             c3mfma(acc, h0, float2{xr[t][0], xq[t][0]});
                             c3mfma(acc, h1, float2{xr[t][1], xq[t][1]});
@@ -216,8 +237,8 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                 if (ogrk) {
                     const int pk = c.L.pick[j];
                     if (ku < c.K && pk >= 0) {
-                        const int u = d.perm[ku];
-                        keep = (u == pk) || (max(d.vs[u], d.vs[pk]) < min(d.ve[u], d.ve[pk]));
+                        const int u = c.perm[ku];
+                        keep = (u == pk) || (max(c.vs[u], c.vs[pk]) < min(c.ve[u], c.ve[pk]));
                     } else {
                         keep = false;
                     }
@@ -225,7 +246,7 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                 if (keep) {
                     float2 sv = {0.f, 0.f};
                     const int b = c.b0 + j;
-                    if (ku < c.K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + d.perm[ku]];
+                    if (ku < c.K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + c.perm[ku]];
                     float2 q = c.L.Q[ku * 16 + j];
                     c.L.R[ku * 16 + j] = float2{sv.x - sr - c.xi * q.x, sv.y - si - c.xi * q.y};
                 }
@@ -236,20 +257,20 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
 }
 
 // phi <- r / ||a||^2 on the rows with sel (0 elsewhere) of the active
-// columns, in place over R; per-column num = sum |r|^2/||a||^2 and ||phi||^2.
+// columns, in place over R. Returns, for the calling thread's column,
+// num = sum |r_i|^2/||a_i||^2 over the rows and ||phi||^2.
 // sel: 0 all rows, 1 rows of F, 2 rows of V.
 template <int W>
-__device__ __forceinline__ void tile_phi(const TileCtx &c, int sel)
+__device__ __forceinline__ float2 tile_phi(const TileCtx &c, int sel)
 {
     const int tid = threadIdx.x, j = tid & 15, er = tid >> 4, rows_per_pass = W * 4;
-    const VrkDesc &d = *c.d;
     float nm = 0.f, pf = 0.f;
     const bool act = c.L.active[j] != 0;
     for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
         float2 r = c.L.R[ku * 16 + j];
         float2 f = {0.f, 0.f};
         bool in = ku < c.K;
-        if (in && sel) in = (d.inf[d.perm[ku]] != 0) == (sel == 1);
+        if (in && sel) in = (c.inf[c.perm[ku]] != 0) == (sel == 1);
         if (act && in) {
             const float inv = 1.f / c.L.nrm[ku];
             f = float2{r.x * inv, r.y * inv};
@@ -258,13 +279,7 @@ __device__ __forceinline__ void tile_phi(const TileCtx &c, int sel)
         }
         c.L.R[ku * 16 + j] = f;
     }
-    nm = col_sum<W>(nm, c.L.red);
-    pf = col_sum<W>(pf, c.L.red);
-    if (tid < 16) {
-        c.L.num[tid] = nm;
-        c.L.phin[tid] = pf;
-    }
-    __syncthreads();
+    return col_sum2<W>(nm, pf, c.L.red);
 }
 
 // P = H^H phi on antenna block ab: chunks e of that block's list, two at a
@@ -272,20 +287,19 @@ __device__ __forceinline__ void tile_phi(const TileCtx &c, int sel)
 __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, f4 &pr, f4 &pi)
 {
     const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
-    const VrkDesc &d = *c.d;
     C3 acc = c3_zero();
     const int e0 = c.L.agoff[ab], e1 = c.L.agoff[ab + 1];
     int e = e0;
 #pragma unroll 1
     for (; e + 1 < e1; e += 2) {
-        const int uc0 = d.ag_uc[e], uc1 = d.ag_uc[e + 1];
+        const int uc0 = c.ag_uc[e], uc1 = c.ag_uc[e + 1];
         float2 h0 = c.HG[(int64_t)e * 64 + lane], h1 = c.HG[(int64_t)(e + 1) * 64 + lane];
         float2 f0 = c.L.R[(4 * uc0 + g) * 16 + j], f1 = c.L.R[(4 * uc1 + g) * 16 + j];
         c3mfma(acc, h0, f0);
         c3mfma(acc, h1, f1);
     }
     if (e < e1) {
-        const int uc = d.ag_uc[e];
+        const int uc = c.ag_uc[e];
         c3mfma(acc, c.HG[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
     }
     c3_get(acc, pr, pi);
@@ -297,11 +311,11 @@ __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, f4 &pr, f4 &
 // = phi^H (H H^H + xi I) phi on the Gram tiles, so gamma is known before
 // P = H^H phi is formed and P goes straight into x (one pass).
 template <int W, int NA>
-__device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? NA : 1], f4 (&xq)[NA ? NA : 1])
+__device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? NA : 1], f4 (&xq)[NA ? NA : 1],
+                                               float num)
 {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
     const int er = tid >> 4, rows_per_pass = W * 4;
-    const VrkDesc &d = *c.d;
     // phi^H M phi: row blocks mb of M phi on the waves, dotted with phi
     float den = 0.f;
 #pragma unroll 1
@@ -310,7 +324,7 @@ __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? N
         const int e0 = c.L.gmoff[mb], e1 = c.L.gmoff[mb + 1];
 #pragma unroll 1
         for (int e = e0; e < e1; ++e) {
-            const int uc = d.gm_c[e];
+            const int uc = c.gm_c[e];
             c3mfma(acc, c.GM[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
         }
         f4 mr, mi;
@@ -322,18 +336,13 @@ __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? N
         }
     }
     den = col_sum<W>(den, c.L.red);
-    if (tid < 16) {
-        const float num = c.L.num[tid];
-        c.L.gre[tid] = (c.L.active[tid] && num > 0.f && den > 0.f) ? num / den : 0.f;
-    }
-    __syncthreads();
-    const float gm = c.L.gre[j];
+    const float gm = (c.L.active[j] && num > 0.f && den > 0.f) ? num / den : 0.f;
     if constexpr (NA == 0) {
 #pragma unroll 1
         for (int ab = w; ab < c.nab; ab += W) {
             f4 qr, qi;
             agg_block(c, ab, qr, qi);
-            float2 *xp = c.Xw + (int64_t)ab * 256 + lane;
+            const gp<float2> xp = c.Xw + (int64_t)ab * 256 + lane;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float2 x = xp[64 * r];
@@ -352,49 +361,59 @@ __device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? N
             }
         }
     }
+    // each thread updates its own (row, column) entries; the next phase reads
+    // Q and rewrites R only after a barrier of its own
     for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
         float2 f = c.L.R[ku * 16 + j];
         float2 q = c.L.Q[ku * 16 + j];
         c.L.Q[ku * 16 + j] = float2{q.x + gm * f.x, q.y + gm * f.y};
     }
-    __syncthreads();
+    if constexpr (NA == 0) __syncthreads();   // the residual reads every wave's x blocks
 }
 
 template <int W, int NA, int VARIANT>
-__device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork wk, char *smem)
+__device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob, const int tile, char *smem)
 {
-    const VrkDesc &d = a.desc[wk.prob];
+    // prob and tile are wave-uniform, so the descriptor is read with scalar loads
+    CDesc &d = ((CDesc *)a.desc)[prob];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
     TileCtx c;
-    c.d = &d;
-    c.prob = wk.prob;
+    c.prob = prob;
     c.K = d.k;
     c.N = d.nt;
     c.nub = d.nub;
     c.kpad = d.nub * VRK_UB;
     c.nab = d.nab;
     c.xi = (float)d.xi;
-    c.b0 = wk.tile * VRK_TILE_RHS;
+    c.b0 = tile * VRK_TILE_RHS;
     c.nrhs = d.nrhs;
     mfma_lds_layout(c.kpad, c.nab, W, smem, &c.L);
     const MfmaLds &L = c.L;
-    float2 *X, *V;
+    gp<float2> X, V;
     int64_t ldx_, ldv_;
     if (a.adjoint) {
-        c.S = reinterpret_cast<const float2 *>(d.Sadj); c.lds = c.K;
-        X = reinterpret_cast<float2 *>(d.Xadj); ldx_ = c.N;
-        V = reinterpret_cast<float2 *>(d.GS); ldv_ = d.ldgs;
+        c.S = gmem(static_cast<const float2 *>(d.Sadj)); c.lds = c.K;
+        X = gmem(static_cast<float2 *>(d.Xadj)); ldx_ = c.N;
+        V = gmem(static_cast<float2 *>(d.GS)); ldv_ = d.ldgs;
     } else {
-        c.S = reinterpret_cast<const float2 *>(d.S); c.lds = d.lds;
-        X = reinterpret_cast<float2 *>(d.X); ldx_ = d.ldx;
-        V = reinterpret_cast<float2 *>(d.V); ldv_ = d.ldv;
+        c.S = gmem(static_cast<const float2 *>(d.S)); c.lds = d.lds;
+        X = gmem(static_cast<float2 *>(d.X)); ldx_ = d.ldx;
+        V = gmem(static_cast<float2 *>(d.V)); ldv_ = d.ldv;
     }
-    c.H = reinterpret_cast<const float2 *>(d.H);
-    c.HA = reinterpret_cast<const float2 *>(d.HA);
-    c.HG = reinterpret_cast<const float2 *>(d.HG);
-    c.GM = reinterpret_cast<const float2 *>(d.GM);
-    c.Xw = NA == 0 ? reinterpret_cast<float2 *>(d.Xw) + (int64_t)wk.tile * c.nab * 256 : nullptr;
-    const float *nrm_g = reinterpret_cast<const float *>(d.nrm);
+    c.H = gmem(static_cast<const float2 *>(d.H));
+    c.HA = gmem(static_cast<const float2 *>(d.HA));
+    c.HG = gmem(static_cast<const float2 *>(d.HG));
+    c.GM = gmem(static_cast<const float2 *>(d.GM));
+    c.FH = gmem(static_cast<const float2 *>(d.FH));
+    c.Xw = NA == 0 ? gmem(static_cast<float2 *>(d.Xw)) + (int64_t)tile * c.nab * 256 : nullptr;
+    c.perm = gmem(d.perm);
+    c.vs = gmem(d.vs);
+    c.ve = gmem(d.ve);
+    c.ag_uc = gmem(d.ag_uc);
+    c.gm_c = gmem(d.gm_c);
+    c.fown = gmem(d.fown);
+    c.inf = gmem(d.inf);
+    const gp<const float> nrm_g = gmem(static_cast<const float *>(d.nrm));
     const int K = c.K, N = c.N, kpad = c.kpad, b0 = c.b0;
     const int rows_per_pass = W * 4;   // (row, column) entries: tid -> (tid / 16, tid % 16)
     const int er = tid >> 4;
@@ -415,24 +434,24 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
     for (int ku = er; ku < kpad; ku += rows_per_pass) {
         float2 sv = {0.f, 0.f};
         const int b = b0 + j;
-        if (ku < K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + d.perm[ku]];
+        if (ku < K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + c.perm[ku]];
         L.R[ku * 16 + j] = sv;
         L.Q[ku * 16 + j] = float2{0.f, 0.f};
         s2 += sv.x * sv.x + sv.y * sv.y;
     }
     for (int ku = tid; ku < kpad; ku += W * 64) {
-        L.nrm[ku] = ku < K ? nrm_g[d.perm[ku]] : 1.f;
-        if (ku < K) L.posl[d.perm[ku]] = ku;
+        L.nrm[ku] = ku < K ? nrm_g[c.perm[ku]] : 1.f;
+        if (ku < K) L.posl[c.perm[ku]] = ku;
     }
-    for (int i = tid; i <= c.nab; i += W * 64) L.agoff[i] = d.ag_off[i];
-    for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = d.gm_off[i];
+    for (int i = tid; i <= c.nab; i += W * 64) L.agoff[i] = gmem(d.ag_off)[i];
+    for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
     for (int i = tid; i < c.nub; i += W * 64) {
-        L.rlo[i] = d.rab_lo[i];
-        L.rhi[i] = d.rab_hi[i];
-        L.hoff[i] = (int)d.ha_off[i];
+        L.rlo[i] = gmem(d.rab_lo)[i];
+        L.rhi[i] = gmem(d.rab_hi)[i];
+        L.hoff[i] = (int)gmem(d.ha_off)[i];
     }
     s2 = col_sum<W>(s2, L.red);
-    const float fro2 = *reinterpret_cast<const float *>(d.fro2);
+    const float fro2 = *gmem(static_cast<const float *>(d.fro2));
     if (tid < 16) {
         const int b = b0 + tid;
         float sn = sqrtf(s2);
@@ -462,24 +481,32 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
             r2 += r.x * r.x + r.y * r.y;
         }
         r2 = col_sum<W>(r2, L.red);
-        if (tid < 16) {
-            if (L.active[tid]) {
-                const float rel = sqrtf(r2) / L.snorm[tid];
+        // every lane evaluates its column's stop rule; lanes 0..15 of each wave
+        // cover all 16 columns, so a ballot tells whether any stays active
+        bool still = false;
+        {
+            const bool was = L.active[j] != 0;
+            const float rel = sqrtf(r2) / L.snorm[j];
+            int fl = 0;
+            if (was) {
+                if (!isfinite(rel)) fl = VRK_FLAG_NONFINITE;
+                else if (rel <= (float)a.tol) fl = VRK_FLAG_CONVERGED;
+                else if (t_it >= a.max_iters) fl = VRK_FLAG_MAXITER;
+                still = fl == 0;
+            }
+            __syncthreads();   // every lane has read its column's old state
+            if (tid < 16 && was) {
                 L.rel[tid] = rel;
                 L.iters[tid] = (int)t_it;
-                if (!isfinite(rel)) { L.flags[tid] = VRK_FLAG_NONFINITE; L.active[tid] = 0; }
-                else if (rel <= (float)a.tol) { L.flags[tid] = VRK_FLAG_CONVERGED; L.active[tid] = 0; }
-                else if (t_it >= a.max_iters) { L.flags[tid] = VRK_FLAG_MAXITER; L.active[tid] = 0; }
+                if (fl) {
+                    L.flags[tid] = fl;
+                    L.active[tid] = 0;
+                }
             }
         }
+        const bool any = __ballot(still) != 0;
         __syncthreads();
-        if (tid == 0) {
-            int any = 0;
-            for (int cc = 0; cc < 16; ++cc) any |= L.active[cc];
-            *L.any = any;
-        }
-        __syncthreads();
-        if (!*L.any) break;
+        if (!any) break;
 
         if constexpr (variant == 0 || variant == 2) {
             // greedy selection, one wave per column
@@ -512,8 +539,8 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
                 const int i = L.pick[j];
                 const float gr = L.gre[j], gi = L.gim[j];
                 if (NA == 0 && i >= 0 && (gr != 0.f || gi != 0.f)) {
-                    const int s0 = d.vs[i], e0 = d.ve[i];
-                    const float2 *hrow = c.H + (int64_t)i * d.ldh;
+                    const int s0 = c.vs[i], e0 = c.ve[i];
+                    const gp<const float2> hrow = c.H + (int64_t)i * d.ldh;
                     for (int ab = w; ab < c.nab; ab += W) {
                         const int nb = 16 * ab + 4 * g;
                         if (nb + 3 < s0 || nb >= e0) continue;
@@ -522,7 +549,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
                             const int n = nb + r;
                             if (n >= s0 && n < e0) {
                                 float2 h = hrow[n];
-                                float2 *xp = c.Xw + (int64_t)ab * 256 + 64 * r + lane;
+                                const gp<float2> xp = c.Xw + (int64_t)ab * 256 + 64 * r + lane;
                                 float2 x = *xp;
                                 *xp = float2{x.x + gr * h.x + gi * h.y, x.y + gi * h.x - gr * h.y};
                             }
@@ -530,8 +557,8 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
                     }
                 }
                 if (NA > 0 && i >= 0 && (gr != 0.f || gi != 0.f)) {
-                    const int s0 = d.vs[i], e0 = d.ve[i];
-                    const float2 *hrow = c.H + (int64_t)i * d.ldh;
+                    const int s0 = c.vs[i], e0 = c.ve[i];
+                    const gp<const float2> hrow = c.H + (int64_t)i * d.ldh;
 #pragma unroll
                     for (int t = 0; t < NA; ++t) {
                         const int nb = 16 * (w + W * t) + 4 * g;
@@ -554,44 +581,53 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
             }
             __syncthreads();
         } else if constexpr (variant == 1) {
-            tile_phi<W>(c, 0);
-            tile_aggregate<W, NA>(c, xr, xq);
+            const float2 nf = tile_phi<W>(c, 0);
+            tile_aggregate<W, NA>(c, xr, xq, nf.x);
         } else {
             // orthogonal half-step on F with gamma = 1 (Prop. 1); each antenna
             // belongs to at most one user of F
-            tile_phi<W>(c, 1);
+            (void)tile_phi<W>(c, 1);
+            // x_n += phi_o conj(H[o, n]) for the F owner o of antenna n; a lane
+            // reads the owners and H entries of its 4 antennas as vectors
+            auto fstep = [&](int nb, float (&xre)[4], float (&xim)[4]) {
+                const int4 o4 = *(gp<const int4>)(c.fown + nb);
+                const float4 h01 = *(gp<const float4>)(c.FH + nb);
+                const float4 h23 = *(gp<const float4>)(c.FH + nb + 2);
+                const int o[4] = {o4.x, o4.y, o4.z, o4.w};
+                const float hr[4] = {h01.x, h01.z, h23.x, h23.z}, hi[4] = {h01.y, h01.w, h23.y, h23.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float2 f = o[r] >= 0 ? L.R[o[r] * 16 + j] : float2{0.f, 0.f};
+                    xre[r] += f.x * hr[r] + f.y * hi[r];
+                    xim[r] += f.y * hr[r] - f.x * hi[r];
+                }
+            };
             if constexpr (NA == 0) {
                 for (int ab = w; ab < c.nab; ab += W) {
+                    const gp<float2> xp = c.Xw + (int64_t)ab * 256 + lane;
+                    float xre[4], xim[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int n = 16 * ab + 4 * g + r;
-                        if (n < N) {
-                            const int o = d.fown[n];
-                            if (o >= 0) {
-                                float2 f = L.R[o * 16 + j];
-                                float2 h = c.H[(int64_t)d.perm[o] * d.ldh + n];
-                                float2 *xp = c.Xw + (int64_t)ab * 256 + 64 * r + lane;
-                                float2 x = *xp;
-                                *xp = float2{x.x + f.x * h.x + f.y * h.y, x.y + f.y * h.x - f.x * h.y};
-                            }
-                        }
+                        const float2 x = xp[64 * r];
+                        xre[r] = x.x;
+                        xim[r] = x.y;
                     }
+                    fstep(16 * ab + 4 * g, xre, xim);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) xp[64 * r] = float2{xre[r], xim[r]};
                 }
             }
 #pragma unroll
             for (int t = 0; t < NA; ++t) {
-                const int nb = 16 * (w + W * t) + 4 * g;
+                const int ab = w + W * t;
+                if (ab < c.nab) {
+                    float xre[4] = {xr[t][0], xr[t][1], xr[t][2], xr[t][3]};
+                    float xim[4] = {xq[t][0], xq[t][1], xq[t][2], xq[t][3]};
+                    fstep(16 * ab + 4 * g, xre, xim);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int n = nb + r;
-                    if (n < N) {
-                        const int o = d.fown[n];
-                        if (o >= 0) {
-                            float2 f = L.R[o * 16 + j];
-                            float2 h = c.H[(int64_t)d.perm[o] * d.ldh + n];
-                            xr[t][r] += f.x * h.x + f.y * h.y;
-                            xq[t][r] += f.y * h.x - f.x * h.y;
-                        }
+                    for (int r = 0; r < 4; ++r) {
+                        xr[t][r] = xre[r];
+                        xq[t][r] = xim[r];
                     }
                 }
             }
@@ -600,48 +636,58 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const VrkWork 
                 float2 q = L.Q[ku * 16 + j];
                 L.Q[ku * 16 + j] = float2{q.x + f.x, q.y + f.y};
             }
-            __syncthreads();
+            if constexpr (NA == 0) __syncthreads();   // the residual reads every wave's x blocks
             if (d.nv > 0) {
                 tile_residual<W, NA>(c, xr, xq, false);
-                tile_phi<W>(c, 2);
-                tile_aggregate<W, NA>(c, xr, xq);
+                const float2 nf = tile_phi<W>(c, 2);
+                tile_aggregate<W, NA>(c, xr, xq, nf.x);
             }
         }
         ++t_it;
     }
 
-    // ---- outputs
+    // ---- outputs. Each lane holds 4 consecutive antennas of one RHS: two
+    // 16-byte stores when the row is 32-byte aligned, else four 8-byte ones.
     {
         const int b = b0 + j;
         if (b < c.nrhs) {
+            const gp<float2> xrow = X + (int64_t)b * ldx_;
+            const bool vec = ((reinterpret_cast<uintptr_t>(xrow) & 31) == 0);
+            auto put4 = [&](int nb, float2 v0, float2 v1, float2 v2, float2 v3) {
+                if (vec && nb + 3 < N) {
+                    const gp<float4> p4 = (gp<float4>)(xrow + nb);
+                    p4[0] = float4{v0.x, v0.y, v1.x, v1.y};
+                    p4[1] = float4{v2.x, v2.y, v3.x, v3.y};
+                } else {
+                    if (nb < N) xrow[nb] = v0;
+                    if (nb + 1 < N) xrow[nb + 1] = v1;
+                    if (nb + 2 < N) xrow[nb + 2] = v2;
+                    if (nb + 3 < N) xrow[nb + 3] = v3;
+                }
+            };
             if constexpr (NA == 0)
-                for (int ab = w; ab < c.nab; ab += W)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int n = 16 * ab + 4 * g + r;
-                        if (n < N) X[(int64_t)b * ldx_ + n] = c.Xw[(int64_t)ab * 256 + 64 * r + lane];
-                    }
+                for (int ab = w; ab < c.nab; ab += W) {
+                    const gp<const float2> xp = c.Xw + (int64_t)ab * 256 + lane;
+                    put4(16 * ab + 4 * g, xp[0], xp[64], xp[128], xp[192]);
+                }
 #pragma unroll
             for (int t = 0; t < NA; ++t) {
                 const int nb = 16 * (w + W * t) + 4 * g;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int n = nb + r;
-                    if (n < N) X[(int64_t)b * ldx_ + n] = float2{xr[t][r], xq[t][r]};
-                }
+                put4(nb, float2{xr[t][0], xq[t][0]}, float2{xr[t][1], xq[t][1]}, float2{xr[t][2], xq[t][2]},
+                     float2{xr[t][3], xq[t][3]});
             }
             if (V)
                 for (int ku = er; ku < K; ku += rows_per_pass)
-                    V[(int64_t)b * ldv_ + d.perm[ku]] = L.Q[ku * 16 + j];
+                    V[(int64_t)b * ldv_ + c.perm[ku]] = L.Q[ku * 16 + j];
         }
     }
     if (tid < 16) {
         const int b = b0 + tid;
         if (b < c.nrhs) {
             const int64_t gidx = d.rhs_base + b;
-            if (a.iters) a.iters[gidx] = L.iters[tid];
-            if (a.relres) a.relres[gidx] = L.rel[tid];
-            if (a.flags) a.flags[gidx] = L.flags[tid];
+            if (a.iters) gmem(a.iters)[gidx] = L.iters[tid];
+            if (a.relres) gmem(a.relres)[gidx] = L.rel[tid];
+            if (a.flags) gmem(a.flags)[gidx] = L.flags[tid];
         }
     }
 }
@@ -663,7 +709,7 @@ __device__ __forceinline__ int next_item(const VrkQueue &q, int *sh)
         *sh = item;
     }
     __syncthreads();
-    const int item = *sh;
+    const int item = __builtin_amdgcn_readfirstlane(*sh);
     __syncthreads();
     return item;
 }
@@ -673,11 +719,16 @@ __global__ void __launch_bounds__(W * 64) k_mfma_solve(VrkSolveArgs a, const Vrk
 {
     extern __shared__ __align__(16) char smem[];
     if constexpr (!PERSIST) {
-        solve_item<W, NA, VARIANT>(a, work[blockIdx.x], smem);   // one workgroup per work item
+        const VrkWork wk = gmem(work)[blockIdx.x];   // one workgroup per work item
+        solve_item<W, NA, VARIANT>(a, __builtin_amdgcn_readfirstlane(wk.prob),
+                                   __builtin_amdgcn_readfirstlane(wk.tile), smem);
     } else {
         __shared__ int sh_item;
-        for (int item = next_item(q, &sh_item); item >= 0; item = next_item(q, &sh_item))
-            solve_item<W, NA, VARIANT>(a, work[item], smem);
+        for (int item = next_item(q, &sh_item); item >= 0; item = next_item(q, &sh_item)) {
+            const VrkWork wk = gmem(work)[item];
+            solve_item<W, NA, VARIANT>(a, __builtin_amdgcn_readfirstlane(wk.prob),
+                                       __builtin_amdgcn_readfirstlane(wk.tile), smem);
+        }
     }
 }
 

@@ -76,7 +76,7 @@ struct ProbPlan {
         o_fown, o_ha, o_hg, o_sadj, o_xadj, o_vfwd;
     int64_t rhs_base = 0;
     size_t o_xw = 0;   // MFMA iterate buffer when x does not fit registers
-    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0;
+    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_fh = 0;
 };
 
 }  // namespace
@@ -489,7 +489,9 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             q.o_hg = cv.take(q.n_hg * 64 * 8);
             if (pl->na == 0) q.o_xw = cv.take((size_t)q.ntile * q.nab * 256 * 8);
             q.o_gm = cv.take(q.n_gm * 64 * 8);
+            q.o_fh = cv.take((size_t)q.nab * VRK_AB * 8);
             pl->max_tiles = std::max(pl->max_tiles, q.n_gm);
+            pl->max_tiles = std::max(pl->max_tiles, (int64_t)(q.nab + 3) / 4);   // 64 antennas per pack wave
             pl->max_tiles = std::max(pl->max_tiles, std::max(q.n_ha, q.n_hg));
         }
         if (q.p.GX) {
@@ -585,6 +587,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.gm_off = (const int32_t *)(base + q.o_gmoff);
         d.gm_c = (const int32_t *)(base + q.o_gmc);
         d.GM = pl->engine == VRK_ENGINE_MFMA ? base + q.o_gm : nullptr;
+        d.FH = pl->engine == VRK_ENGINE_MFMA ? base + q.o_fh : nullptr;
         (void)eb;
     }
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());

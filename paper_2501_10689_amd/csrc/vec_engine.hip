@@ -110,6 +110,15 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
         }
         reinterpret_cast<cx<float> *>(d.HG)[t * 64 + lane] = v;
     }
+    // F-step table: the entry of H that antenna n meets in the orthogonal
+    // half-step (its F owner's row), 64 antennas per wave
+    if (d.FH && t * 64 + lane < (int64_t)d.nab * VRK_AB) {
+        const int n = (int)(t * 64) + lane;
+        cx<float> v = {0.f, 0.f};
+        const int o = d.fown[n];
+        if (o >= 0) v = H[(int64_t)d.perm[o] * d.ldh + n];
+        reinterpret_cast<cx<float> *>(d.FH)[n] = v;
+    }
     const int64_t n_gm = d.gm_off[d.nub];
     if (t < n_gm) {
         // Gram tile e of user block mb: lane l = i + 16 kk holds

@@ -55,6 +55,7 @@ struct VrkDesc {
                                   // [tile][ab][r][lane] complex64 (MFMA result order)
     const int32_t *gm_off, *gm_c; // per 16-user block: 4-user chunks with a nonzero Gram block (CSR)
     void *GM;                     // Gram tiles of H H^H + xi I (VR-start order), 64 complex64 each
+    void *FH;                     // per antenna (nab * 16): H[perm[fown[n]], n], 0 where fown[n] < 0
 };
 
 // One unit of work of the MFMA engine: a problem and a tile of 16 RHS.
