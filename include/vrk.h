@@ -189,7 +189,8 @@ typedef enum {
     VRK_Q_XOFF = 3,      /* CSR offsets of X_k, length k + 1 */
     VRK_Q_XIDX = 4,      /* CSR indices of X_k (ascending, includes k) */
     VRK_Q_ENGINE = 5,    /* [engine, schedule, tile_waves, lds_bytes, persistent, grid,
-                            register blocks per wave (0: iterate in the workspace)] */
+                            register blocks per wave (0: iterate in the workspace),
+                            RHS splits of the MFMA adjoint gradient tiles] */
     VRK_Q_TILES = 6      /* [residual tiles, aggregation tiles, band entries, Gram tiles] per problem */
 } vrk_query;
 int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *out, int64_t cap);

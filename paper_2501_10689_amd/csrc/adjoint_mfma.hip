@@ -33,171 +33,261 @@ __device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
     acc.w = mfma(a.x + a.y, b.x + b.y, acc.w);
 }
 
-// b = H g for one tile of 16 RHS and one 16-user block (one wave):
-// D[user][rhs] = sum over the block's band chunks of HA-tile x GX.
-__global__ void __launch_bounds__(64) k_adj_rhs_mfma(const VrkDesc *descs, const VrkWork *work)
+using CDesc = const VRK_CONST VrkDesc;
+template <typename T>
+using gp = VRK_GLOBAL T *;
+
+// b = H g for one tile of 16 RHS and one 16-user block:
+// D[user][rhs] = sum over the block's band chunks of HA-tile x GX. The four
+// waves take every fourth antenna block, two per step so that the loads of
+// one overlap the other's MFMAs, and add their tiles in LDS in fixed order.
+constexpr int kRW = 4;
+
+__global__ void __launch_bounds__(kRW * 64) k_adj_rhs_mfma(const VrkDesc *descs, const VrkWork *work)
 {
-    const VrkWork wk = work[blockIdx.x];
-    const VrkDesc &d = descs[wk.prob];
+    __shared__ float2 part[kRW][256];
+    const VrkWork wk = gmem(work)[blockIdx.x];
+    const int prob = __builtin_amdgcn_readfirstlane(wk.prob), tile = __builtin_amdgcn_readfirstlane(wk.tile);
+    CDesc &d = ((CDesc *)descs)[prob];
     const int ub = blockIdx.y;
     if (ub >= d.nub) return;
-    const int lane = threadIdx.x, j = lane & 15, g = lane >> 4;
-    const int b = wk.tile * VRK_TILE_RHS + j;
-    const float2 *HA = reinterpret_cast<const float2 *>(d.HA);
-    const float2 *GX = reinterpret_cast<const float2 *>(d.GX);
-    const int lo = d.rab_lo[ub], hi = d.rab_hi[ub];
-    const int64_t hb = d.ha_off[ub];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
+    const int b = tile * VRK_TILE_RHS + j;
+    const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
+    const gp<const float2> GX = gmem(static_cast<const float2 *>(d.GX));
+    const int lo = gmem(d.rab_lo)[ub], hi = gmem(d.rab_hi)[ub];
+    const int64_t hb = gmem(d.ha_off)[ub];
     const bool bok = b < d.nrhs;
-    const float2 *grow = GX + (int64_t)(bok ? b : 0) * d.ldgx;
+    const int nt = d.nt;
+    const gp<const float2> grow = GX + (int64_t)(bok ? b : 0) * d.ldgx;
     const f4 z = {0.f, 0.f, 0.f, 0.f};
     C3 acc = {z, z, z};
-    for (int ab = lo; ab < hi; ++ab) {
-        const float2 *hp = HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
+    auto load = [&](int ab, float2 (&h)[4], float2 (&x)[4]) {
+        const gp<const float2> hp = HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int n = 16 * ab + 4 * g + m;   // reduction slot g of chunk (ab, m)
-            float2 x = (bok && n < d.nt) ? grow[n] : float2{0.f, 0.f};
-            c3mfma(acc, hp[64 * m], x);
+            h[m] = hp[64 * m];
+            x[m] = float2{0.f, 0.f};
+            if (bok && n < nt) x[m] = grow[n];
         }
+    };
+    int ab = lo + w;
+    for (; ab + kRW < hi; ab += 2 * kRW) {
+        float2 h0[4], x0[4], h1[4], x1[4];
+        load(ab, h0, x0);
+        load(ab + kRW, h1, x1);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) c3mfma(acc, h0[m], x0[m]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) c3mfma(acc, h1[m], x1[m]);
+    }
+    if (ab < hi) {
+        float2 h0[4], x0[4];
+        load(ab, h0, x0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) c3mfma(acc, h0[m], x0[m]);
     }
     const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
-    if (bok) {
-        float2 *out = reinterpret_cast<float2 *>(d.Sadj) + (int64_t)b * d.k;
+    // D layout: lane (j, g) register r holds user 4 g + r, RHS j
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ku = ub * VRK_UB + 4 * g + r;
-            if (ku < d.k) out[d.perm[ku]] = float2{re[r], im[r]};
+    for (int r = 0; r < 4; ++r) part[w][(4 * g + r) * 16 + j] = float2{re[r], im[r]};
+    __syncthreads();
+    const int ii = tid >> 4, jj = tid & 15;   // user ii of the block, RHS jj
+    const int bb = tile * VRK_TILE_RHS + jj, ku = ub * VRK_UB + ii;
+    if (bb < d.nrhs && ku < d.k) {
+        float sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int q = 0; q < kRW; ++q) {
+            sr += part[q][tid].x;
+            si += part[q][tid].y;
         }
+        gmem(static_cast<float2 *>(d.Sadj))[(int64_t)bb * d.k + gmem(d.perm)[ku]] = float2{sr, si};
     }
 }
 
-// GH on the band tile (ub, ab): D[user i][antenna j] = sum_b A[i][b] B[b][j]
-// with A = V^T, B = conj(GX - Xadj) plus A = -GS^T, B = conj(X), the RHS
-// dimension split over the 8 waves and reduced through LDS.
-constexpr int kGW = 8;
+// GH on the band tiles (ub, ab) of the user blocks ub = 4 ubg .. 4 ubg + 3
+// that meet antenna block ab: D[user i][antenna j] = sum_b A[i][b] B[b][j]
+// with A = V^T, B = conj(GX - Xadj) plus A = -M^T, B = conj(X). A wave loads
+// the antenna operands of 4 RHS once for all blocks of the group; v and mu
+// come from the VR-start-order copies (16 users = 128 contiguous bytes).
+// The RHS range is split over the waves and reduced through LDS.
+constexpr int kGW = 4;
+constexpr int kUG = VRK_GRAD_UG;
 
-__device__ __forceinline__ void grads_tile(const VrkDesc &d, int ub, int ab, int bs0, int be0,
-                                           float2 (*part)[256], float2 *out)
+__device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, int be0,
+                                            float2 (*part)[kUG][256], gp<float2> out)
 {
+    // (the gxi partial of a group-first tile is taken by the caller)
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 15, kk = lane >> 4;
-    const float2 *V = reinterpret_cast<const float2 *>(d.V);
-    const float2 *GS = reinterpret_cast<const float2 *>(d.GS);
-    const float2 *GX = reinterpret_cast<const float2 *>(d.GX);
-    const float2 *XA = reinterpret_cast<const float2 *>(d.Xadj);
-    const float2 *X = reinterpret_cast<const float2 *>(d.X);
-    const int ku = ub * VRK_UB + i;          // A operand row (user) of this lane
-    const int user = ku < d.k ? d.perm[ku] : -1;
+    const gp<const float2> VS = gmem(static_cast<const float2 *>(d.Vsrt));
+    const gp<const float2> MS = gmem(static_cast<const float2 *>(d.Msrt));
+    const gp<const float2> GX = gmem(static_cast<const float2 *>(d.GX));
+    const gp<const float2> XA = gmem(static_cast<const float2 *>(d.Xadj));
+    const gp<const float2> X = gmem(static_cast<const float2 *>(d.X));
+    const int64_t ldgx = d.ldgx, ldx = d.ldx, ldxa = d.nt;
+    const int nub = d.nub, kpad = nub * VRK_UB;
+    const int ub0 = ubg * kUG;
+    // blocks of the group that meet ab (wave-uniform)
+    bool live[kUG];
+#pragma unroll
+    for (int u = 0; u < kUG; ++u) {
+        const int ub = ub0 + u;
+        live[u] = ub < nub && gmem(d.rab_lo)[ub] <= ab && ab < gmem(d.rab_hi)[ub];
+    }
     const int n = ab * VRK_AB + i;           // B operand column (antenna) of this lane
     const bool nok = n < d.nt;
-    // this workgroup's RHS range [bs0, be0), split over the waves
     const int per = (be0 - bs0 + kGW - 1) / kGW;
     const int bs = bs0 + w * per, be = min(be0, bs + per);
     const f4 z = {0.f, 0.f, 0.f, 0.f};
-    C3 acc = {z, z, z};
-    for (int b0 = bs; b0 < be; b0 += 4) {
-        const int b = b0 + kk;
-        float2 v = {0.f, 0.f}, mu = {0.f, 0.f}, y = {0.f, 0.f}, xv = {0.f, 0.f};
-        if (b < be) {
-            if (user >= 0) {
-                v = V[(int64_t)b * d.ldv + user];
-                mu = GS[(int64_t)b * d.ldgs + user];
+    C3 acc[kUG];
+#pragma unroll
+    for (int u = 0; u < kUG; ++u) acc[u] = C3{z, z, z};
+    constexpr int kQ = 2;   // MFMA reduction steps (4 RHS each) per iteration
+    for (int b0 = bs; b0 < be; b0 += 4 * kQ) {
+        float2 y[kQ], xv[kQ], v[kQ][kUG], mu[kQ][kUG];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int b = b0 + 4 * q + kk;
+            const bool bok = b < be;
+            y[q] = xv[q] = float2{0.f, 0.f};
+            if (bok && nok) {
+                const float2 gx = GX[(int64_t)b * ldgx + n], xa = XA[(int64_t)b * ldxa + n];
+                y[q] = float2{gx.x - xa.x, gx.y - xa.y};
+                xv[q] = X[(int64_t)b * ldx + n];
             }
-            if (nok) {
-                float2 gx = GX[(int64_t)b * d.ldgx + n], xa = XA[(int64_t)b * d.nt + n];
-                y = float2{gx.x - xa.x, gx.y - xa.y};
-                xv = X[(int64_t)b * d.ldx + n];
+#pragma unroll
+            for (int u = 0; u < kUG; ++u) {
+                v[q][u] = mu[q][u] = float2{0.f, 0.f};
+                if (live[u] && bok) {
+                    const int64_t o = (int64_t)b * kpad + (ub0 + u) * VRK_UB + i;
+                    v[q][u] = VS[o];
+                    mu[q][u] = MS[o];
+                }
             }
         }
-        c3mfma(acc, v, float2{y.x, -y.y});            // v conj(y)
-        c3mfma(acc, float2{-mu.x, -mu.y}, float2{xv.x, -xv.y});   // - mu conj(x)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const float2 cy = float2{y[q].x, -y[q].y}, cx_ = float2{xv[q].x, -xv[q].y};
+#pragma unroll
+            for (int u = 0; u < kUG; ++u)
+                if (live[u]) {
+                    c3mfma(acc[u], v[q][u], cy);                                  // v conj(y)
+                    c3mfma(acc[u], float2{-mu[q][u].x, -mu[q][u].y}, cx_);        // - mu conj(x)
+                }
+        }
     }
-    const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
     // D layout: lane (j, g) register r holds user 4 g + r, antenna j
     const int jj = lane & 15, gg = lane >> 4;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) part[w][(4 * gg + r) * 16 + jj] = float2{re[r], im[r]};
+    for (int u = 0; u < kUG; ++u) {
+        const f4 re = acc[u].u - acc[u].v, im = acc[u].w - acc[u].u - acc[u].v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[w][u][(4 * gg + r) * 16 + jj] = float2{re[r], im[r]};
+    }
     __syncthreads();
-    if (tid < 256) {
+    // thread tid owns entry tid of every block: user tid / 16, antenna tid % 16
+    const int ii = tid >> 4, nj = tid & 15, nn = ab * VRK_AB + nj;
+#pragma unroll
+    for (int u = 0; u < kUG; ++u) {
         float sr = 0.f, si = 0.f;
 #pragma unroll
         for (int ww = 0; ww < kGW; ++ww) {
-            sr += part[ww][tid].x;
-            si += part[ww][tid].y;
+            sr += part[ww][u][tid].x;
+            si += part[ww][u][tid].y;
         }
         if (out) {
-            out[tid] = float2{sr, si};   // partial over this workgroup's RHS range
-        } else {
-            const int ii = tid >> 4, nj = tid & 15;
-            const int kq = ub * VRK_UB + ii, nn = ab * VRK_AB + nj;
+            out[u * 256 + tid] = float2{sr, si};   // partial over this workgroup's RHS range
+        } else if (live[u]) {
+            const int kq = (ub0 + u) * VRK_UB + ii;
             if (kq < d.k) {
-                const int u = d.perm[kq];
-                if (nn >= d.vs[u] && nn < d.ve[u])
-                    reinterpret_cast<float2 *>(d.GH)[(int64_t)u * d.ldgh + nn] = float2{sr, si};
+                const int us = gmem(d.perm)[kq];
+                if (nn >= gmem(d.vs)[us] && nn < gmem(d.ve)[us])
+                    gmem(static_cast<float2 *>(d.GH))[(int64_t)us * d.ldgh + nn] = float2{sr, si};
             }
         }
     }
 }
 
-// Sum the RHS-split partials of each band tile in fixed order and write the
-// VR band entries of GH.
+// Workgroup (tile, u): sum the RHS-split partials of user block 4 ubg + u of
+// the tile in fixed order and write its VR band entries of GH (nsplit > 1).
+// Workgroup (first tile of a problem, 0) also adds the gxi partials of its
+// problem's tiles.
 __global__ void __launch_bounds__(256) k_adj_grads_reduce(const VrkDesc *descs, const int4 *tiles, int nsplit,
-                                                          const float2 *gpart)
+                                                          const float2 *gpart, const float *gxpart)
 {
-    const int4 tl = tiles[blockIdx.x];
-    if (tl.y < 0) return;
-    const VrkDesc &d = descs[tl.x];
-    const int tid = threadIdx.x, ii = tid >> 4, nj = tid & 15;
+    const int4 tl = gmem(tiles)[blockIdx.x];
+    CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
+    const int tid = threadIdx.x, u = blockIdx.y;
+    const int flags = __builtin_amdgcn_readfirstlane(tl.w);
+    if ((flags & 1) && u == 0 && tid < 64) {
+        // this problem's tiles: blockIdx.x and the next (flags >> 2) - 1
+        const int64_t n = (int64_t)(flags >> 2) * nsplit, e0 = (int64_t)blockIdx.x * nsplit;
+        float t = 0.f;
+        for (int64_t e = tid; e < n; e += 64) t += gmem(gxpart)[e0 + e];
+        t = wave_sum(t);
+        if (tid == 0) *gmem(d.gxi) = -(double)t;
+    }
+    if (nsplit <= 1 || tl.y < 0) return;
+    const int ub = __builtin_amdgcn_readfirstlane(tl.y) * kUG + u, ab = __builtin_amdgcn_readfirstlane(tl.z);
+    if (ub >= d.nub || ab < gmem(d.rab_lo)[ub] || ab >= gmem(d.rab_hi)[ub]) return;
+    const int ii = tid >> 4, nj = tid & 15, nn = ab * VRK_AB + nj;
+    const gp<const float2> src = gmem(gpart) + (int64_t)blockIdx.x * nsplit * kUG * 256 + u * 256 + tid;
     float sr = 0.f, si = 0.f;
+#pragma unroll 8
     for (int sp = 0; sp < nsplit; ++sp) {
-        float2 p = gpart[((int64_t)blockIdx.x * nsplit + sp) * 256 + tid];
+        const float2 p = src[(int64_t)sp * kUG * 256];
         sr += p.x;
         si += p.y;
     }
-    const int kq = tl.y * VRK_UB + ii, nn = tl.z * VRK_AB + nj;
+    const int kq = ub * VRK_UB + ii;
     if (kq < d.k) {
-        const int u = d.perm[kq];
-        if (nn >= d.vs[u] && nn < d.ve[u])
-            reinterpret_cast<float2 *>(d.GH)[(int64_t)u * d.ldgh + nn] = float2{sr, si};
+        const int us = gmem(d.perm)[kq];
+        if (nn >= gmem(d.vs)[us] && nn < gmem(d.ve)[us])
+            gmem(static_cast<float2 *>(d.GH))[(int64_t)us * d.ldgh + nn] = float2{sr, si};
     }
 }
 
-// Workgroup (tile, split): RHS range split of the band tile; with nsplit 1
-// it writes GH directly, else its partial to gpart.
+// Workgroup (tile, split): one RHS range of a tile; with nsplit 1 it writes
+// GH directly, else its partials to gpart. A group-first tile (tile.w bit 1)
+// also writes the partial of dL/dxi = -Re sum_{b,k} conj(mu) v over the
+// users of its group and its RHS range to gxpart (0 for other tiles).
 __global__ void __launch_bounds__(kGW * 64) k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, int nsplit,
-                                                             float2 *gpart)
+                                                             float2 *gpart, float *gxpart)
 {
-    __shared__ float2 part[kGW][256];
+    __shared__ float2 part[kGW][kUG][256];
     __shared__ float red[kGW];
     const int tix = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
-    const int4 tl = tiles[tix];   // (problem, user block, antenna block, first-of-problem)
-    const VrkDesc &d = descs[tl.x];
-    const int ub = tl.y, ab = tl.z;
+    const int4 tl = gmem(tiles)[tix];   // (problem, user-block group, antenna block, flags)
+    CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
+    const int ubg = __builtin_amdgcn_readfirstlane(tl.y), ab = __builtin_amdgcn_readfirstlane(tl.z);
+    const int flags = __builtin_amdgcn_readfirstlane(tl.w);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const float2 *V = reinterpret_cast<const float2 *>(d.V);
-    const float2 *GS = reinterpret_cast<const float2 *>(d.GS);
     const int B = d.nrhs;
     const int per = (B + nsplit - 1) / nsplit;
     const int bs0 = min(B, split * per), be0 = min(B, bs0 + per);
-    if (ub >= 0)
-        grads_tile(d, ub, ab, bs0, be0, part,
-                   nsplit > 1 ? gpart + ((int64_t)tix * nsplit + split) * 256 : nullptr);
-    // dL/dxi = -Re sum_{b,k} conj(mu) v, by one entry per problem
-    if (tl.w && split == 0) {
-        float acc = 0.f;
-        const int64_t tot = (int64_t)B * d.k;
-        for (int64_t e = tid; e < tot; e += kGW * 64) {
-            const int b = (int)(e / d.k), k = (int)(e % d.k);
-            float2 mu = GS[(int64_t)b * d.ldgs + k], v = V[(int64_t)b * d.ldv + k];
+    if (ubg >= 0)
+        grads_group(d, ubg, ab, bs0, be0, part,
+                    nsplit > 1 ? gmem(gpart) + ((int64_t)tix * nsplit + split) * kUG * 256 : nullptr);
+    float acc = 0.f;
+    if (ubg >= 0 && (flags & 2)) {
+        const int kpad = d.nub * VRK_UB, c0 = ubg * kUG * VRK_UB, c1 = min(kpad, c0 + kUG * VRK_UB);
+        const int cw = c1 - c0;
+        const gp<const float2> VS = gmem(static_cast<const float2 *>(d.Vsrt));
+        const gp<const float2> MS = gmem(static_cast<const float2 *>(d.Msrt));
+        for (int e = tid; e < (be0 - bs0) * cw; e += kGW * 64) {
+            const int b = bs0 + e / cw, c = c0 + e % cw;
+            const float2 mu = MS[(int64_t)b * kpad + c], v = VS[(int64_t)b * kpad + c];
             acc += mu.x * v.x + mu.y * v.y;
         }
-        acc = wave_sum(acc);
-        if (lane == 0) red[w] = acc;
-        __syncthreads();
-        if (tid == 0) {
-            float t = 0.f;
-            for (int q = 0; q < kGW; ++q) t += red[q];
-            *d.gxi = -(double)t;
-        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.f;
+        for (int q = 0; q < kGW; ++q) t += red[q];
+        gmem(gxpart)[blockIdx.x] = t;
     }
 }
 
@@ -208,18 +298,18 @@ hipError_t vrk_launch_adjoint_rhs_mfma(const VrkDesc *desc, const VrkWork *work,
                                        int32_t max_nub, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_rhs_mfma, dim3(nwork, max_nub), dim3(64), 0, s, desc, work);
+    hipLaunchKernelGGL(k_adj_rhs_mfma, dim3(nwork, max_nub), dim3(kRW * 64), 0, s, desc, work);
     return hipGetLastError();
 }
 
 hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
-                                         float2 *gpart, hipStream_t s)
+                                         float2 *gpart, float *gxpart, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_adj_grads_mfma, dim3((unsigned)ntiles * nsplit), dim3(kGW * 64), 0, s, desc, tiles, nsplit,
-                       gpart);
+                       gpart, gxpart);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nsplit <= 1) return e;
-    hipLaunchKernelGGL(k_adj_grads_reduce, dim3(ntiles), dim3(256), 0, s, desc, tiles, nsplit, gpart);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_grads_reduce, dim3(ntiles, kUG), dim3(256), 0, s, desc, tiles, nsplit, gpart, gxpart);
     return hipGetLastError();
 }

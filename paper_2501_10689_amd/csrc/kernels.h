@@ -56,7 +56,11 @@ hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t 
 // first-of-problem flag for the xi gradient; user block -1 = xi only).
 hipError_t vrk_launch_adjoint_rhs_mfma(const VrkDesc *desc, const VrkWork *work, int32_t nwork,
                                        int32_t max_nub, hipStream_t s);
-// nsplit > 1 splits each tile's RHS range over nsplit workgroups writing
-// partials to gpart (ntiles * nsplit * 256 complex64), summed by a second kernel.
+// Tiles are (problem, user-block group, antenna block, flags: bit 0 first
+// tile of its problem, bit 1 first tile of its group, bits 2.. on a problem's
+// first tile: its problem's tile count). nsplit > 1 splits each
+// tile's RHS range over nsplit workgroups writing partials to gpart
+// (ntiles * nsplit * VRK_GRAD_UG * 256 complex64); gxpart (ntiles * nsplit
+// floats) takes the partials of dL/dxi. A second kernel sums both in fixed order.
 hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
-                                         float2 *gpart, hipStream_t s);
+                                         float2 *gpart, float *gxpart, hipStream_t s);

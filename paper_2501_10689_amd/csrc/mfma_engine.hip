@@ -1,20 +1,29 @@
-// MFMA engine: 16 right-hand sides per workgroup share H; the banded
-// complex products of every Kaczmarz variant run on the FP32 matrix cores
-// (v_mfma_f32_16x16x4f32, complex product as four real products).
+// MFMA engine: 16 right-hand sides per workgroup share H; the complex
+// products of every Kaczmarz variant run on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32, complex product as three real products).
+//
+// Dual-space iteration. Every Kaczmarz step on A z = s, A = [H, sqrt(xi) I],
+// adds gamma a_i to z and gamma to q_i, so from z = 0 the iterate always is
+// x = H^H q and the residual is r = s - A A^H q = s - M q with the Gram matrix
+// M = H H^H + xi I (band-sparse: M[i][k] = 0 unless the VRs of i and k
+// overlap, which is the orthogonality of Lemma 1 and Theorem 2). The engine
+// therefore keeps r and q (K x 16 per tile) in LDS and updates r with Gram
+// products, r -= M (gamma phi): the same iterates as the paper's updates of
+// x and the re-evaluated residuals, at the cost of the Gram band instead of
+// the channel band per step. When every column has met the stop rule, x =
+// H^H q is formed and the true residual s - H x - xi q is evaluated from it;
+// a column whose true residual misses the tolerance resumes from it.
 //
 // Layout. Lane l of a wave is (j, g) = (l % 16, l / 16): RHS column j and
-// row group g. The iterate x of the tile never leaves registers: wave w
-// owns the 16-antenna blocks ab = w + W a, and lane (j, g) holds
-// x[16 ab + 4 g + r][j] in register r of float4 pair xr[a], xq[a] - the
-// layout of an MFMA result tile. Feeding the residual product
+// row group g. Wave w owns the 16-antenna blocks ab = w + W a of x, lane
+// (j, g) holding x[16 ab + 4 g + r][j] in register r of float4 pair xr[a],
+// xq[a] - the layout of an MFMA result tile, which the residual product
 //   R[u][j] = sum_n H[u][n] x[n][j]
-// the reduction index of chunk (ab, m) is ordered as antenna 16 ab + 4 kk + m
-// for slot kk, so register m of xr[a] is already the B operand; the packed
-// residual tile (ub, ab, m) holds H of 16 users at those antennas. The
-// aggregation product P[n][j] = sum_u conj(H[u][n]) phi[u][j] produces
-// tiles in the same layout as x, so x += gamma P is register-local.
-// Users are processed in VR-start order (perm), which keeps the nonzero
-// tiles of the banded H few.
+// takes as its B operand when the reduction index of chunk (ab, m) is
+// ordered as antenna 16 ab + 4 kk + m for slot kk. The aggregation product
+// x[n][j] = sum_u conj(H[u][n]) q[u][j] produces tiles in that layout. Users
+// are processed in VR-start order (perm), which keeps the nonzero tiles of
+// the banded H and M few.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -56,11 +65,17 @@ __device__ __forceinline__ void c3_get(const C3 &acc, f4 &re, f4 &im)
 }
 
 struct MfmaLds {
-    float2 *R, *Q, *Rp;
+    float2 *R, *Q, *Rp, *P, *MP;   // P and MP share the space of Rp (never live together)
     float *nrm, *pre, *red, *snorm, *rel, *gre, *gim;
     int *posl, *active, *iters, *flags, *pick;
     int *agoff, *rlo, *rhi, *hoff, *gmoff;   // copies of the tile tables of this problem
+    int *gmc;    // copy of the Gram chunk columns (at most nub * kpad / 4)
+    int *rsel;   // per sorted row: 1 user of F, 2 user of V, 0 padding
 };
+
+// Column state beyond the public flags: stopped on the maintained residual,
+// waiting for the true residual to confirm.
+constexpr int kPending = 8;
 
 __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char *base, MfmaLds *L)
 {
@@ -70,9 +85,10 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         off += (bytes + 15) & ~size_t(15);
         return base ? base + o : nullptr;
     };
+    const size_t rp = (size_t)W * VRK_RGROUP * 16, pm = (size_t)2 * kpad * 16;
     char *R = take((size_t)kpad * 16 * 8);
     char *Q = take((size_t)kpad * 16 * 8);
-    char *Rp = take((size_t)W * VRK_RGROUP * 16 * 8);
+    char *Rp = take((rp > pm ? rp : pm) * 8);
     char *nrm = take((size_t)kpad * 4);
     char *pre = take((size_t)W * kpad * 4);
     char *red = take((size_t)2 * W * 16 * 4);
@@ -80,6 +96,8 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
     char *posl = take((size_t)kpad * 4);
     char *ints = take(16 * 4 * 4);
     char *tabs = take((size_t)(nab + 1 + 4 * (kpad / 16) + 1) * 4);
+    char *gmc = take((size_t)(kpad / 16) * (kpad / 4) * 4);
+    char *rsel = take((size_t)kpad * 4);
     // test the LDS base, not L: L points into a caller's register-resident
     // struct, and comparing its address would pin that struct to memory
     if (base) {
@@ -89,9 +107,13 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         L->rhi = L->rlo + kpad / 16;
         L->hoff = L->rhi + kpad / 16;
         L->gmoff = L->hoff + kpad / 16;
+        L->gmc = (int *)gmc;
+        L->rsel = (int *)rsel;
         L->R = (float2 *)R;
         L->Q = (float2 *)Q;
         L->Rp = (float2 *)Rp;
+        L->P = (float2 *)Rp;
+        L->MP = (float2 *)Rp + (size_t)kpad * 16;
         L->nrm = (float *)nrm;
         L->pre = (float *)pre;
         L->red = (float *)red;
@@ -169,11 +191,10 @@ struct TileCtx {
 };
 
 // R <- s - H x - xi q (rows in VR-start order), two 16-user blocks at a time
-// with a deterministic cross-wave reduction through LDS. With `ogrk` only
-// the rows of X_pick are written (the others keep their value, Theorem 2).
+// with a deterministic cross-wave reduction through LDS (buffer Rp).
 template <int W, int NA>
 __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[NA ? NA : 1],
-                                              const f4 (&xq)[NA ? NA : 1], bool ogrk)
+                                              const f4 (&xq)[NA ? NA : 1])
 {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
     const int nug = (c.nub + 1) / 2;
@@ -188,7 +209,7 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                 const int lo = c.L.rlo[ub], hi = c.L.rhi[ub];
                 const int64_t hb = c.L.hoff[ub];
                 if constexpr (NA == 0) {
-                    // global iterate: the wave's blocks w, w + W, ... inside [lo, hi)
+                    // iterate in the workspace: the wave's blocks w, w + W, ... inside [lo, hi)
                     int ab = lo + ((w - lo) % W + W) % W;
 #pragma unroll 1
                     for (; ab < hi; ab += W) {
@@ -233,58 +254,20 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
                     sr += p.x;
                     si += p.y;
                 }
-                bool keep = true;
-                if (ogrk) {
-                    const int pk = c.L.pick[j];
-                    if (ku < c.K && pk >= 0) {
-                        const int u = c.perm[ku];
-                        keep = (u == pk) || (max(c.vs[u], c.vs[pk]) < min(c.ve[u], c.ve[pk]));
-                    } else {
-                        keep = false;
-                    }
-                }
-                if (keep) {
-                    float2 sv = {0.f, 0.f};
-                    const int b = c.b0 + j;
-                    if (ku < c.K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + c.perm[ku]];
-                    float2 q = c.L.Q[ku * 16 + j];
-                    c.L.R[ku * 16 + j] = float2{sv.x - sr - c.xi * q.x, sv.y - si - c.xi * q.y};
-                }
+                float2 sv = {0.f, 0.f};
+                const int b = c.b0 + j;
+                if (ku < c.K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + c.perm[ku]];
+                float2 q = c.L.Q[ku * 16 + j];
+                c.L.R[ku * 16 + j] = float2{sv.x - sr - c.xi * q.x, sv.y - si - c.xi * q.y};
             }
         }
         __syncthreads();
     }
 }
 
-// phi <- r / ||a||^2 on the rows with sel (0 elsewhere) of the active
-// columns, in place over R. Returns, for the calling thread's column,
-// num = sum |r_i|^2/||a_i||^2 over the rows and ||phi||^2.
-// sel: 0 all rows, 1 rows of F, 2 rows of V.
-template <int W>
-__device__ __forceinline__ float2 tile_phi(const TileCtx &c, int sel)
-{
-    const int tid = threadIdx.x, j = tid & 15, er = tid >> 4, rows_per_pass = W * 4;
-    float nm = 0.f, pf = 0.f;
-    const bool act = c.L.active[j] != 0;
-    for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
-        float2 r = c.L.R[ku * 16 + j];
-        float2 f = {0.f, 0.f};
-        bool in = ku < c.K;
-        if (in && sel) in = (c.inf[c.perm[ku]] != 0) == (sel == 1);
-        if (act && in) {
-            const float inv = 1.f / c.L.nrm[ku];
-            f = float2{r.x * inv, r.y * inv};
-            nm += (r.x * r.x + r.y * r.y) * inv;
-            pf += f.x * f.x + f.y * f.y;
-        }
-        c.L.R[ku * 16 + j] = f;
-    }
-    return col_sum2<W>(nm, pf, c.L.red);
-}
-
-// P = H^H phi on antenna block ab: chunks e of that block's list, two at a
-// time so the loads of one pair overlap the MFMAs of the other.
-__device__ __forceinline__ void agg_block(const TileCtx &c, int ab, f4 &pr, f4 &pi)
+// H^H F on antenna block ab (F in LDS, [row][16]): chunks e of that block's
+// list, two at a time so the loads of one pair overlap the MFMAs of the other.
+__device__ __forceinline__ void agg_block(const TileCtx &c, int ab, const float2 *F, f4 &pr, f4 &pi)
 {
     const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
     C3 acc = c3_zero();
@@ -294,81 +277,163 @@ __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, f4 &pr, f4 &
     for (; e + 1 < e1; e += 2) {
         const int uc0 = c.ag_uc[e], uc1 = c.ag_uc[e + 1];
         float2 h0 = c.HG[(int64_t)e * 64 + lane], h1 = c.HG[(int64_t)(e + 1) * 64 + lane];
-        float2 f0 = c.L.R[(4 * uc0 + g) * 16 + j], f1 = c.L.R[(4 * uc1 + g) * 16 + j];
+        float2 f0 = F[(4 * uc0 + g) * 16 + j], f1 = F[(4 * uc1 + g) * 16 + j];
         c3mfma(acc, h0, f0);
         c3mfma(acc, h1, f1);
     }
     if (e < e1) {
         const int uc = c.ag_uc[e];
-        c3mfma(acc, c.HG[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
+        c3mfma(acc, c.HG[(int64_t)e * 64 + lane], F[(4 * uc + g) * 16 + j]);
     }
     c3_get(acc, pr, pi);
 }
 
-// Aggregated projection (update4): x += gamma H^H phi, q += gamma phi with
-// gamma = phi^H r / ||A^H phi||^2. The denominator is evaluated through the
-// Gram identity ||A^H phi||^2 = ||H^H phi||^2 + xi ||phi||^2
-// = phi^H (H H^H + xi I) phi on the Gram tiles, so gamma is known before
-// P = H^H phi is formed and P goes straight into x (one pass).
+// x <- H^H q (every column), into the registers of the wave's antenna
+// blocks or, without register blocks, into the tile's workspace rows.
 template <int W, int NA>
-__device__ __forceinline__ void tile_aggregate(const TileCtx &c, f4 (&xr)[NA ? NA : 1], f4 (&xq)[NA ? NA : 1],
-                                               float num)
+__device__ __forceinline__ void form_x(const TileCtx &c, f4 (&xr)[NA ? NA : 1], f4 (&xq)[NA ? NA : 1])
 {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
-    const int er = tid >> 4, rows_per_pass = W * 4;
-    // phi^H M phi: row blocks mb of M phi on the waves, dotted with phi
-    float den = 0.f;
-#pragma unroll 1
-    for (int mb = w; mb < c.nub; mb += W) {
-        C3 acc = c3_zero();
-        const int e0 = c.L.gmoff[mb], e1 = c.L.gmoff[mb + 1];
-#pragma unroll 1
-        for (int e = e0; e < e1; ++e) {
-            const int uc = c.gm_c[e];
-            c3mfma(acc, c.GM[(int64_t)e * 64 + lane], c.L.R[(4 * uc + g) * 16 + j]);
-        }
-        f4 mr, mi;
-        c3_get(acc, mr, mi);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float2 f = c.L.R[(16 * mb + 4 * g + r) * 16 + j];
-            den += f.x * mr[r] + f.y * mi[r];
-        }
-    }
-    den = col_sum<W>(den, c.L.red);
-    const float gm = (c.L.active[j] && num > 0.f && den > 0.f) ? num / den : 0.f;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if constexpr (NA == 0) {
 #pragma unroll 1
         for (int ab = w; ab < c.nab; ab += W) {
             f4 qr, qi;
-            agg_block(c, ab, qr, qi);
+            agg_block(c, ab, c.L.Q, qr, qi);
             const gp<float2> xp = c.Xw + (int64_t)ab * 256 + lane;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float2 x = xp[64 * r];
-                xp[64 * r] = float2{x.x + gm * qr[r], x.y + gm * qi[r]};
-            }
+            for (int r = 0; r < 4; ++r) xp[64 * r] = float2{qr[r], qi[r]};
         }
+        __syncthreads();   // the residual reads every wave's blocks
     } else {
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
             const int ab = w + W * t;
-            if (ab < c.nab) {
-                f4 qr, qi;
-                agg_block(c, ab, qr, qi);
-                xr[t] += gm * qr;
-                xq[t] += gm * qi;
-            }
+            const f4 z = {0.f, 0.f, 0.f, 0.f};
+            xr[t] = z;
+            xq[t] = z;
+            if (ab < c.nab) agg_block(c, ab, c.L.Q, xr[t], xq[t]);
         }
     }
-    // each thread updates its own (row, column) entries; the next phase reads
-    // Q and rewrites R only after a barrier of its own
-    for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
-        float2 f = c.L.R[ku * 16 + j];
-        float2 q = c.L.Q[ku * 16 + j];
-        c.L.Q[ku * 16 + j] = float2{q.x + gm * f.x, q.y + gm * f.y};
+}
+
+// Gram tiles held in registers: the first GR tiles of the wave's first row
+// block (mb = w), loaded once per iteration phase.
+template <int GR>
+struct GramRegs {
+    float2 m[GR];
+};
+
+template <int W, int GR>
+__device__ __forceinline__ void gram_load(const TileCtx &c, GramRegs<GR> &gr)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int e0 = w < c.nub ? c.L.gmoff[w] : 0, n = w < c.nub ? c.L.gmoff[w + 1] - e0 : 0;
+#pragma unroll
+    for (int q = 0; q < GR; ++q) {
+        gr.m[q] = float2{0.f, 0.f};
+        if (q < n) gr.m[q] = c.GM[(int64_t)(e0 + q) * 64 + lane];
     }
-    if constexpr (NA == 0) __syncthreads();   // the residual reads every wave's x blocks
+}
+
+// Gram product of the wave's 16-row blocks mb = w, w + W, ...: the MFMA
+// result (rows 16 mb + 4 g + r, column j) of M F goes to fn(mb, re, im).
+template <int W, int GR, typename Fn>
+__device__ __forceinline__ void gram_rows(const TileCtx &c, const float2 *F, const GramRegs<GR> &gr, Fn fn)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+#pragma unroll 1
+    for (int mb = w; mb < c.nub; mb += W) {
+        C3 acc = c3_zero();
+        const int e0 = c.L.gmoff[mb], e1 = c.L.gmoff[mb + 1];
+        int e = e0;
+        if (mb == w) {
+#pragma unroll
+            for (int q = 0; q < GR; ++q)
+                if (e0 + q < e1) c3mfma(acc, gr.m[q], F[(4 * c.L.gmc[e0 + q] + g) * 16 + j]);
+            e = e0 + GR;
+        }
+#pragma unroll 1
+        for (; e + 1 < e1; e += 2) {
+            const int uc0 = c.L.gmc[e], uc1 = c.L.gmc[e + 1];
+            float2 m0 = c.GM[(int64_t)e * 64 + lane], m1 = c.GM[(int64_t)(e + 1) * 64 + lane];
+            float2 f0 = F[(4 * uc0 + g) * 16 + j], f1 = F[(4 * uc1 + g) * 16 + j];
+            c3mfma(acc, m0, f0);
+            c3mfma(acc, m1, f1);
+        }
+        if (e < e1) c3mfma(acc, c.GM[(int64_t)e * 64 + lane], F[(4 * c.L.gmc[e] + g) * 16 + j]);
+        f4 mr, mi;
+        c3_get(acc, mr, mi);
+        fn(mb, mr, mi);
+    }
+}
+
+// P <- r / ||a||^2 on the rows with sel (0 elsewhere) of the active columns.
+// sel: 0 all rows, 1 rows of F, 2 rows of V.
+template <int W>
+__device__ __forceinline__ void phi_rows(const TileCtx &c, int sel)
+{
+    const int tid = threadIdx.x, j = tid & 15, er = tid >> 4, rows_per_pass = W * 4;
+    const bool act = c.L.active[j] != 0;
+    for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
+        float2 f = {0.f, 0.f};
+        const int rs = c.L.rsel[ku];
+        const bool in = act && rs != 0 && (sel == 0 || rs == sel);
+        if (in) {
+            const float2 r = c.L.R[ku * 16 + j];
+            const float inv = 1.f / c.L.nrm[ku];
+            f = float2{r.x * inv, r.y * inv};
+        }
+        c.L.P[ku * 16 + j] = f;
+    }
+}
+
+// Aggregated projection (update4) in the dual: with phi = P (rows of sel),
+// gamma = phi^H r / ||A^H phi||^2 where ||A^H phi||^2 = phi^H M phi (Gram
+// identity), then q += gamma phi and r -= gamma M phi. P must be complete
+// (a barrier after phi_rows).
+template <int W, int GR>
+__device__ __forceinline__ void aggregate_step(const TileCtx &c, const GramRegs<GR> &gr)
+{
+    const int tid = threadIdx.x, lane = tid & 63, j = lane & 15, g = lane >> 4;
+    const int er = tid >> 4, rows_per_pass = W * 4;
+    float num = 0.f, den = 0.f;
+    gram_rows<W, GR>(c, c.L.P, gr, [&](int mb, const f4 &mr, const f4 &mi) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ku = 16 * mb + 4 * g + r;
+            const float2 f = c.L.P[ku * 16 + j], rr = c.L.R[ku * 16 + j];
+            c.L.MP[ku * 16 + j] = float2{mr[r], mi[r]};
+            den += f.x * mr[r] + f.y * mi[r];
+            num += f.x * rr.x + f.y * rr.y;   // |r|^2 / ||a||^2 on the rows of phi
+        }
+    });
+    const float2 nd = col_sum2<W>(num, den, c.L.red);
+    const float gm = (c.L.active[j] && nd.x > 0.f && nd.y > 0.f) ? nd.x / nd.y : 0.f;
+    for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
+        const float2 f = c.L.P[ku * 16 + j], m = c.L.MP[ku * 16 + j];
+        const float2 q = c.L.Q[ku * 16 + j], rr = c.L.R[ku * 16 + j];
+        c.L.Q[ku * 16 + j] = float2{q.x + gm * f.x, q.y + gm * f.y};
+        c.L.R[ku * 16 + j] = float2{rr.x - gm * m.x, rr.y - gm * m.y};
+    }
+}
+
+// Step with unit weight on the rows of P (the orthogonal half-step, or the
+// one-hot step of the greedy variants with gamma folded into P): q += P,
+// r -= M P. The wave owning a row block updates it; ends with a barrier.
+template <int W, int GR>
+__device__ __forceinline__ void unit_step(const TileCtx &c, const GramRegs<GR> &gr)
+{
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    gram_rows<W, GR>(c, c.L.P, gr, [&](int mb, const f4 &mr, const f4 &mi) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ku = 16 * mb + 4 * g + r;
+            const float2 f = c.L.P[ku * 16 + j], q = c.L.Q[ku * 16 + j], rr = c.L.R[ku * 16 + j];
+            c.L.Q[ku * 16 + j] = float2{q.x + f.x, q.y + f.y};
+            c.L.R[ku * 16 + j] = float2{rr.x - mr[r], rr.y - mi[r]};
+        }
+    });
+    __syncthreads();
 }
 
 template <int W, int NA, int VARIANT>
@@ -418,18 +483,9 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     const int rows_per_pass = W * 4;   // (row, column) entries: tid -> (tid / 16, tid % 16)
     const int er = tid >> 4;
 
-    // ---- init: x = 0, q = 0, r = s (z0 = 0), norms in VR-start order
+    // ---- init: q = 0, r = s (z0 = 0), norms in VR-start order
     constexpr int NR = NA ? NA : 1;
     f4 xr[NR], xq[NR];
-#pragma unroll
-    for (int t = 0; t < NR; ++t) {
-        xr[t] = f4{0.f, 0.f, 0.f, 0.f};
-        xq[t] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-    if constexpr (NA == 0)
-        for (int ab = w; ab < c.nab; ab += W)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) c.Xw[(int64_t)ab * 256 + 64 * r + lane] = float2{0.f, 0.f};
     float s2 = 0.f;
     for (int ku = er; ku < kpad; ku += rows_per_pass) {
         float2 sv = {0.f, 0.f};
@@ -445,6 +501,8 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     }
     for (int i = tid; i <= c.nab; i += W * 64) L.agoff[i] = gmem(d.ag_off)[i];
     for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
+    for (int i = tid; i < gmem(d.gm_off)[c.nub]; i += W * 64) L.gmc[i] = c.gm_c[i];
+    for (int ku = tid; ku < kpad; ku += W * 64) L.rsel[ku] = ku < K ? (c.inf[c.perm[ku]] ? 1 : 2) : 0;
     for (int i = tid; i < c.nub; i += W * 64) {
         L.rlo[i] = gmem(d.rab_lo)[i];
         L.rhi[i] = gmem(d.rab_hi)[i];
@@ -471,179 +529,132 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     __syncthreads();
 
     constexpr int variant = VARIANT;
+    // Gram tiles kept in registers per wave (two VGPRs each)
+    constexpr int GR = W == 8 ? 32 : 16;
     int64_t t_it = 0;
     for (;;) {
-        if (t_it > 0) tile_residual<W, NA>(c, xr, xq, variant == 2);
-        // stop rule per column
-        float r2 = 0.f;
+        // iteration phase: runs until every column has stopped
+        GramRegs<GR> gr;
+        gram_load<W, GR>(c, gr);
+        for (;;) {
+            // stop rule per column on the maintained residual; lanes 0..15 of
+            // each wave cover all 16 columns, so a ballot tells whether any goes on
+            float r2 = 0.f;
+            for (int ku = er; ku < kpad; ku += rows_per_pass) {
+                float2 r = L.R[ku * 16 + j];
+                r2 += r.x * r.x + r.y * r.y;
+            }
+            r2 = col_sum<W>(r2, L.red);
+            bool still = false;
+            {
+                const bool was = L.active[j] != 0;
+                const float rel = sqrtf(r2) / L.snorm[j];
+                int fl = 0;
+                if (was) {
+                    if (!isfinite(rel)) fl = VRK_FLAG_NONFINITE;
+                    else if (rel <= (float)a.tol) fl = kPending;
+                    else if (t_it >= a.max_iters) fl = VRK_FLAG_MAXITER;
+                    still = fl == 0;
+                }
+                __syncthreads();   // every lane has read its column's old state
+                if (tid < 16 && was) {
+                    L.rel[tid] = rel;
+                    L.iters[tid] = (int)t_it;
+                    if (fl) {
+                        L.flags[tid] = fl;
+                        L.active[tid] = 0;
+                    }
+                }
+            }
+            if (__ballot(still) == 0) break;
+            __syncthreads();
+
+            if constexpr (variant == 0 || variant == 2) {
+                // greedy selection, one wave per column (M's sparsity confines the
+                // residual change to the rows of X_pick, Theorem 2)
+                for (int cc = w; cc < 16; cc += W) {
+                    if (!L.active[cc]) {
+                        if (lane == 0) { L.gre[cc] = 0.f; L.gim[cc] = 0.f; L.pick[cc] = -1; }
+                        continue;
+                    }
+                    const float u = (float)uniform24(a.seed, t_it, b0 + cc, c.prob);
+                    const float2 *Rl = L.R;
+                    const float *nl = L.nrm;
+                    const int *pl = L.posl;
+                    const int i = select_row_wave<float>(K, a.select, fro2, u, [Rl, nl, pl, cc](int q) -> cx<float> {
+                        const int ku = pl[q];
+                        float2 r = Rl[ku * 16 + cc];
+                        return {r.x * r.x + r.y * r.y, nl[ku]};
+                    }, L.pre + w * kpad);
+                    if (lane == 0) {
+                        const int ku = L.posl[i];
+                        const float inv = 1.f / L.nrm[ku];
+                        float2 r = L.R[ku * 16 + cc];
+                        L.pick[cc] = i;
+                        L.gre[cc] = r.x * inv;
+                        L.gim[cc] = r.y * inv;
+                    }
+                }
+                __syncthreads();
+                {
+                    const int pk = L.pick[j];
+                    const int kp = pk >= 0 ? L.posl[pk] : -1;
+                    const float2 gmj = float2{L.gre[j], L.gim[j]};
+                    for (int ku = er; ku < kpad; ku += rows_per_pass)
+                        L.P[ku * 16 + j] = ku == kp ? gmj : float2{0.f, 0.f};
+                }
+                __syncthreads();
+                unit_step<W, GR>(c, gr);
+            } else if constexpr (variant == 1) {
+                phi_rows<W>(c, 0);
+                __syncthreads();
+                aggregate_step<W, GR>(c, gr);
+            } else {
+                // orthogonal half-step on F with gamma = 1 (Prop. 1), then the
+                // aggregated step on V
+                phi_rows<W>(c, 1);
+                __syncthreads();
+                unit_step<W, GR>(c, gr);
+                if (d.nv > 0) {
+                    phi_rows<W>(c, 2);
+                    __syncthreads();
+                    aggregate_step<W, GR>(c, gr);
+                }
+            }
+            ++t_it;
+        }
+        // every column stopped: x = H^H q and the true residual decide
+        __syncthreads();
+        form_x<W, NA>(c, xr, xq);
+        tile_residual<W, NA>(c, xr, xq);
+        float t2 = 0.f;
         for (int ku = er; ku < kpad; ku += rows_per_pass) {
             float2 r = L.R[ku * 16 + j];
-            r2 += r.x * r.x + r.y * r.y;
+            t2 += r.x * r.x + r.y * r.y;
         }
-        r2 = col_sum<W>(r2, L.red);
-        // every lane evaluates its column's stop rule; lanes 0..15 of each wave
-        // cover all 16 columns, so a ballot tells whether any stays active
-        bool still = false;
-        {
-            const bool was = L.active[j] != 0;
-            const float rel = sqrtf(r2) / L.snorm[j];
-            int fl = 0;
-            if (was) {
-                if (!isfinite(rel)) fl = VRK_FLAG_NONFINITE;
-                else if (rel <= (float)a.tol) fl = VRK_FLAG_CONVERGED;
-                else if (t_it >= a.max_iters) fl = VRK_FLAG_MAXITER;
-                still = fl == 0;
-            }
-            __syncthreads();   // every lane has read its column's old state
-            if (tid < 16 && was) {
-                L.rel[tid] = rel;
-                L.iters[tid] = (int)t_it;
-                if (fl) {
-                    L.flags[tid] = fl;
-                    L.active[tid] = 0;
-                }
-            }
+        t2 = col_sum<W>(t2, L.red);
+        // columns stopped by the rule or the iteration cap take the true
+        // residual's verdict; a column it rejects resumes while the cap allows
+        const float rel = sqrtf(t2) / L.snorm[j];
+        const int fl = L.flags[j];
+        const bool open = fl == kPending || fl == VRK_FLAG_MAXITER;
+        int nf = fl;
+        if (open) {
+            if (!isfinite(rel)) nf = VRK_FLAG_NONFINITE;
+            else if (rel <= (float)a.tol) nf = VRK_FLAG_CONVERGED;
+            else if (t_it < a.max_iters) nf = 0;
+            else nf = VRK_FLAG_MAXITER;
         }
-        const bool any = __ballot(still) != 0;
+        const bool resume = open && nf == 0;
+        __syncthreads();   // every lane has read its column's state
+        if (tid < 16 && open) {
+            L.rel[tid] = rel;
+            L.flags[tid] = nf;
+            if (resume) L.active[tid] = 1;
+        }
+        const bool again = __ballot(resume) != 0;
         __syncthreads();
-        if (!any) break;
-
-        if constexpr (variant == 0 || variant == 2) {
-            // greedy selection, one wave per column
-            for (int cc = w; cc < 16; cc += W) {
-                if (!L.active[cc]) {
-                    if (lane == 0) { L.gre[cc] = 0.f; L.gim[cc] = 0.f; }
-                    continue;
-                }
-                const float u = (float)uniform24(a.seed, t_it, b0 + cc, c.prob);
-                const float2 *Rl = L.R;
-                const float *nl = L.nrm;
-                const int *pl = L.posl;
-                const int i = select_row_wave<float>(K, a.select, fro2, u, [Rl, nl, pl, cc](int q) -> cx<float> {
-                    const int ku = pl[q];
-                    float2 r = Rl[ku * 16 + cc];
-                    return {r.x * r.x + r.y * r.y, nl[ku]};
-                }, L.pre + w * kpad);
-                if (lane == 0) {
-                    const int ku = L.posl[i];
-                    const float inv = 1.f / L.nrm[ku];
-                    float2 r = L.R[ku * 16 + cc];
-                    L.pick[cc] = i;
-                    L.gre[cc] = r.x * inv;
-                    L.gim[cc] = r.y * inv;
-                }
-            }
-            __syncthreads();
-            // single-row projection per column: x += gamma conj(H[i, VR_i])
-            {
-                const int i = L.pick[j];
-                const float gr = L.gre[j], gi = L.gim[j];
-                if (NA == 0 && i >= 0 && (gr != 0.f || gi != 0.f)) {
-                    const int s0 = c.vs[i], e0 = c.ve[i];
-                    const gp<const float2> hrow = c.H + (int64_t)i * d.ldh;
-                    for (int ab = w; ab < c.nab; ab += W) {
-                        const int nb = 16 * ab + 4 * g;
-                        if (nb + 3 < s0 || nb >= e0) continue;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int n = nb + r;
-                            if (n >= s0 && n < e0) {
-                                float2 h = hrow[n];
-                                const gp<float2> xp = c.Xw + (int64_t)ab * 256 + 64 * r + lane;
-                                float2 x = *xp;
-                                *xp = float2{x.x + gr * h.x + gi * h.y, x.y + gi * h.x - gr * h.y};
-                            }
-                        }
-                    }
-                }
-                if (NA > 0 && i >= 0 && (gr != 0.f || gi != 0.f)) {
-                    const int s0 = c.vs[i], e0 = c.ve[i];
-                    const gp<const float2> hrow = c.H + (int64_t)i * d.ldh;
-#pragma unroll
-                    for (int t = 0; t < NA; ++t) {
-                        const int nb = 16 * (w + W * t) + 4 * g;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int n = nb + r;
-                            if (n >= s0 && n < e0) {
-                                float2 h = hrow[n];
-                                xr[t][r] += gr * h.x + gi * h.y;
-                                xq[t][r] += gi * h.x - gr * h.y;
-                            }
-                        }
-                    }
-                }
-            }
-            if (tid < 16 && L.active[tid]) {
-                const int ku = L.posl[L.pick[tid]];
-                float2 q = L.Q[ku * 16 + tid];
-                L.Q[ku * 16 + tid] = float2{q.x + L.gre[tid], q.y + L.gim[tid]};
-            }
-            __syncthreads();
-        } else if constexpr (variant == 1) {
-            const float2 nf = tile_phi<W>(c, 0);
-            tile_aggregate<W, NA>(c, xr, xq, nf.x);
-        } else {
-            // orthogonal half-step on F with gamma = 1 (Prop. 1); each antenna
-            // belongs to at most one user of F
-            (void)tile_phi<W>(c, 1);
-            // x_n += phi_o conj(H[o, n]) for the F owner o of antenna n; a lane
-            // reads the owners and H entries of its 4 antennas as vectors
-            auto fstep = [&](int nb, float (&xre)[4], float (&xim)[4]) {
-                const int4 o4 = *(gp<const int4>)(c.fown + nb);
-                const float4 h01 = *(gp<const float4>)(c.FH + nb);
-                const float4 h23 = *(gp<const float4>)(c.FH + nb + 2);
-                const int o[4] = {o4.x, o4.y, o4.z, o4.w};
-                const float hr[4] = {h01.x, h01.z, h23.x, h23.z}, hi[4] = {h01.y, h01.w, h23.y, h23.w};
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float2 f = o[r] >= 0 ? L.R[o[r] * 16 + j] : float2{0.f, 0.f};
-                    xre[r] += f.x * hr[r] + f.y * hi[r];
-                    xim[r] += f.y * hr[r] - f.x * hi[r];
-                }
-            };
-            if constexpr (NA == 0) {
-                for (int ab = w; ab < c.nab; ab += W) {
-                    const gp<float2> xp = c.Xw + (int64_t)ab * 256 + lane;
-                    float xre[4], xim[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float2 x = xp[64 * r];
-                        xre[r] = x.x;
-                        xim[r] = x.y;
-                    }
-                    fstep(16 * ab + 4 * g, xre, xim);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) xp[64 * r] = float2{xre[r], xim[r]};
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < NA; ++t) {
-                const int ab = w + W * t;
-                if (ab < c.nab) {
-                    float xre[4] = {xr[t][0], xr[t][1], xr[t][2], xr[t][3]};
-                    float xim[4] = {xq[t][0], xq[t][1], xq[t][2], xq[t][3]};
-                    fstep(16 * ab + 4 * g, xre, xim);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        xr[t][r] = xre[r];
-                        xq[t][r] = xim[r];
-                    }
-                }
-            }
-            for (int ku = er; ku < kpad; ku += rows_per_pass) {
-                float2 f = L.R[ku * 16 + j];
-                float2 q = L.Q[ku * 16 + j];
-                L.Q[ku * 16 + j] = float2{q.x + f.x, q.y + f.y};
-            }
-            if constexpr (NA == 0) __syncthreads();   // the residual reads every wave's x blocks
-            if (d.nv > 0) {
-                tile_residual<W, NA>(c, xr, xq, false);
-                const float2 nf = tile_phi<W>(c, 2);
-                tile_aggregate<W, NA>(c, xr, xq, nf.x);
-            }
-        }
-        ++t_it;
+        if (!again) break;   // else the resumed columns go on from the true residual
     }
 
     // ---- outputs. Each lane holds 4 consecutive antennas of one RHS: two
@@ -679,6 +690,11 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             if (V)
                 for (int ku = er; ku < K; ku += rows_per_pass)
                     V[(int64_t)b * ldv_ + c.perm[ku]] = L.Q[ku * 16 + j];
+            // the same in VR-start order for the gradient products
+            const gp<float2> VS = gmem(static_cast<float2 *>(a.adjoint ? d.Msrt : d.Vsrt));
+            if (VS)
+                for (int ku = er; ku < kpad; ku += rows_per_pass)
+                    VS[(int64_t)b * kpad + ku] = L.Q[ku * 16 + j];
         }
     }
     if (tid < 16) {

@@ -73,7 +73,7 @@ struct ProbPlan {
     // workspace offsets
     size_t o_vs, o_ve, o_xoff, o_xidx, o_flist, o_vlist, o_inf, o_coloff, o_colusr, o_gboff,
         o_gbusr, o_perm, o_pos, o_nrm, o_fro2, o_rablo, o_rabhi, o_haoff, o_agoff, o_aguc,
-        o_fown, o_ha, o_hg, o_sadj, o_xadj, o_vfwd;
+        o_fown, o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
     size_t o_xw = 0;   // MFMA iterate buffer when x does not fit registers
     size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_fh = 0;
@@ -96,7 +96,7 @@ struct vrk_plan {
     int32_t qbase[VRK_NQUEUE] = {0}, qsize[VRK_NQUEUE] = {0};
     size_t o_queue = 0;         // int32 counters[8], base[8], size[8]
     int32_t gsplit = 1;         // RHS splits of the adjoint gradient tiles
-    size_t o_gpart = 0;
+    size_t o_gpart = 0, o_gxpart = 0;
     int32_t persistent = 0, grid = 0;
     int32_t max_nub = 0;
     std::vector<uint8_t> image;
@@ -432,20 +432,31 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         if (all_adj)
             for (int i = 0; i < nprob; ++i) {
                 const ProbPlan &q = pl->pp[i];
+                // (problem, user-block group, antenna block, first of problem)
+                // for every antenna block that some block of the group meets
                 int first = 1;
-                for (int ub = 0; ub < q.nub; ++ub)
-                    for (int ab = q.rab_lo[ub]; ab < q.rab_hi[ub]; ++ab) {
-                        pl->gtiles.push_back(make_int4(i, ub, ab, first));
+                const size_t t0 = pl->gtiles.size();
+                for (int ubg = 0; ubg * VRK_GRAD_UG < q.nub; ++ubg) {
+                    const int u0 = ubg * VRK_GRAD_UG, u1 = std::min(q.nub, u0 + VRK_GRAD_UG);
+                    int gfirst = 2;
+                    for (int ab = 0; ab < q.nab; ++ab) {
+                        bool meets = false;
+                        for (int ub = u0; ub < u1; ++ub) meets = meets || (q.rab_lo[ub] <= ab && ab < q.rab_hi[ub]);
+                        if (!meets) continue;
+                        pl->gtiles.push_back(make_int4(i, ubg, ab, first | gfirst));
                         first = 0;
+                        gfirst = 0;
                     }
+                }
                 if (first) pl->gtiles.push_back(make_int4(i, -1, 0, 1));
+                pl->gtiles[t0].w |= (int32_t)(pl->gtiles.size() - t0) << 2;
             }
         if (!pl->gtiles.empty()) {
-            // enough workgroups to fill the device (about 2048), each split
-            // keeping at least 64 right-hand sides
-            int64_t want = 2048 / (int64_t)pl->gtiles.size();
+            // enough 4-wave workgroups to fill the device (about 4096), each
+            // split keeping at least 64 right-hand sides (16 per wave)
+            int64_t want = 4096 / (int64_t)pl->gtiles.size();
             int64_t cap = std::max<int64_t>(1, min_rhs / 64);
-            pl->gsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 16}));
+            pl->gsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 32}));
         }
     }
     // workspace carving
@@ -455,7 +466,8 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     pl->o_work = cv.take(sizeof(VrkWork) * std::max<size_t>(1, pl->work.size()));
     pl->o_gtiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->gtiles.size()));
     pl->o_queue = cv.take(sizeof(int32_t) * 3 * VRK_NQUEUE);
-    pl->o_gpart = cv.take(pl->gsplit > 1 ? pl->gtiles.size() * (size_t)pl->gsplit * 256 * 8 : 0);
+    pl->o_gpart = cv.take(pl->gsplit > 1 ? pl->gtiles.size() * (size_t)pl->gsplit * VRK_GRAD_UG * 256 * 8 : 0);
+    pl->o_gxpart = cv.take(pl->gtiles.size() * (size_t)pl->gsplit * 4);
     for (auto &q : pl->pp) {
         const int K = q.p.k;
         q.o_vs = cv.take(4 * K);
@@ -498,6 +510,10 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             q.o_sadj = cv.take((size_t)eb * q.p.nrhs * q.p.k);
             q.o_xadj = cv.take((size_t)eb * q.p.nrhs * q.p.nt);
             q.o_vfwd = q.p.V ? 0 : cv.take((size_t)eb * q.p.nrhs * q.p.k);
+            if (eng == VRK_ENGINE_MFMA) {
+                q.o_vsrt = cv.take((size_t)8 * q.p.nrhs * q.nub * VRK_UB);
+                q.o_msrt = cv.take((size_t)8 * q.p.nrhs * q.nub * VRK_UB);
+            }
         }
     }
     pl->ws_bytes = cv.off;
@@ -560,6 +576,9 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.Sadj = p.GX ? base + q.o_sadj : nullptr;
         d.Xadj = p.GX ? base + q.o_xadj : nullptr;
         d.Vfwd = nullptr;
+        const bool srt = p.GX && pl->engine == VRK_ENGINE_MFMA;
+        d.Vsrt = srt ? base + q.o_vsrt : nullptr;
+        d.Msrt = srt ? base + q.o_msrt : nullptr;
         d.vs = (const int32_t *)(base + q.o_vs);
         d.ve = (const int32_t *)(base + q.o_ve);
         d.xoff = (const int32_t *)(base + q.o_xoff);
@@ -695,7 +714,8 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
     if (st != VRK_OK) return st;
     e = mf ? vrk_launch_adjoint_grads_mfma(dd, reinterpret_cast<const int4 *>(pl->d_ws + pl->o_gtiles),
                                            (int32_t)pl->gtiles.size(), pl->gsplit,
-                                           reinterpret_cast<float2 *>(pl->d_ws + pl->o_gpart), s)
+                                           reinterpret_cast<float2 *>(pl->d_ws + pl->o_gpart),
+                                           reinterpret_cast<float *>(pl->d_ws + pl->o_gxpart), s)
            : vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient kernel");
     return VRK_OK;
@@ -712,7 +732,8 @@ int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *
     case VRK_Q_COLOUR: v = q.colour; break;
     case VRK_Q_XOFF: v = q.xoff; break;
     case VRK_Q_XIDX: v = q.xidx; break;
-    case VRK_Q_ENGINE: v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->na};
+    case VRK_Q_ENGINE:
+        v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->na, pl->gsplit};
         break;
     case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band, (int32_t)q.n_gm}; break;
     default: return -1;

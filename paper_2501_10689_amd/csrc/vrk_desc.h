@@ -56,7 +56,15 @@ struct VrkDesc {
     const int32_t *gm_off, *gm_c; // per 16-user block: 4-user chunks with a nonzero Gram block (CSR)
     void *GM;                     // Gram tiles of H H^H + xi I (VR-start order), 64 complex64 each
     void *FH;                     // per antenna (nab * 16): H[perm[fown[n]], n], 0 where fown[n] < 0
+    // MFMA engine with adjoint buffers: v of the forward solve and mu of the
+    // adjoint solve again, [rhs][nub * 16] complex64 in VR-start user order
+    // (zero on the padding users), for the gradient products
+    void *Vsrt, *Msrt;
 };
+
+// User blocks per tile of the MFMA adjoint gradient: the blocks 4 ubg ..
+// 4 ubg + 3 that meet one antenna block share its antenna operands.
+#define VRK_GRAD_UG 4
 
 // One unit of work of the MFMA engine: a problem and a tile of 16 RHS.
 struct VrkWork {

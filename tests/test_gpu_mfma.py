@@ -141,6 +141,27 @@ def test_adjoint_mfma_matches_closed_form(nt, k, nrhs):
     assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
 
 
+def test_adjoint_mfma_rhs_split():
+    """Enough right-hand sides that each gradient tile's RHS range is split
+    over workgroups (partials reduced in a second kernel); K 72 leaves a
+    user-block group with a single, padded block."""
+    rng = np.random.default_rng(23)
+    H, vs, vl, xi = random_problem(rng, 512, 72)
+    S = qpsk(rng, (700, 72))
+    X, _ = oracle.rzf(H, vs, vl, S, xi)
+    G = 2.0 * ((X @ H.T - S) @ H.conj() + 0.1 * X) / 700
+    gH, gS, gxi = oracle.rzf_grad(H, vs, vl, S, xi, G)
+    res, plan = run_plan([(H, vs, vl, S, xi)], variant="vr_oahk", engine="mfma", tol=1e-6, adjoint_g=[G])
+    assert plan.query(0, 5)[7] > 1
+    g = res[0]
+    m = np.abs(H) > 0
+    assert np.all(g["adj_flags"] == oracle.F_CONVERGED)
+    assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m])
+    assert not g["GH"][~m].any()
+    assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS)
+    assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
+
+
 def test_adjoint_mfma_uneven_batch():
     """One launch of each adjoint kernel over several drops of uneven shape."""
     ds = synth.make_workload("uneven", drops=4, nrhs=20)
