@@ -33,7 +33,8 @@ hipError_t vrk_prepare_vec_solve(int32_t dtype, size_t lds_bytes);   // LDS attr
 hipError_t vrk_launch_vec_solve(const VrkSolveArgs &a, size_t lds_bytes, hipStream_t s);
 
 // MFMA engine: 16 right-hand sides per workgroup (complex64).
-int vrk_mfma_supported(int32_t nt, int32_t waves);
+// 8 or 16 waves per tile, at most 32 users per wave (kpad: K rounded up to 16).
+int vrk_mfma_supported(int32_t kpad, int32_t waves);
 // Register blocks per wave for x (1, 2, 4, 8, 16), or 0: x in the workspace.
 int vrk_mfma_register_na(int32_t nt, int32_t waves);
 size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves);

@@ -65,9 +65,10 @@ __device__ __forceinline__ void c3_get(const C3 &acc, f4 &re, f4 &im)
 }
 
 struct MfmaLds {
-    float2 *R, *Q, *Rp, *P, *MP;   // P and MP share the space of Rp (never live together)
-    float *nrm, *pre, *red, *snorm, *rel, *gre, *gim;
-    int *posl, *active, *iters, *flags, *pick;
+    float2 *R, *Q, *Rp, *P, *MP;   // P and MP share the space of Rp (never live together);
+                                   // MP holds one partial Gram product per chunk part
+    float *nrm, *pre, *red;
+    int *posl;
     int *agoff, *rlo, *rhi, *hoff, *gmoff;   // copies of the tile tables of this problem
     int *gmc;    // copy of the Gram chunk columns (at most nub * kpad / 4)
     int *rsel;   // per sorted row: 1 user of F, 2 user of V, 0 padding
@@ -76,6 +77,16 @@ struct MfmaLds {
 // Column state beyond the public flags: stopped on the maintained residual,
 // waiting for the true residual to confirm.
 constexpr int kPending = 8;
+// (row, column) entries per thread in the element-wise passes: at most this
+// many passes of 4 W rows, so kpad <= kMaxPass * 4 W
+constexpr int kMaxPass = 8;
+
+// Waves per 16-row block of the Gram product: the chunk groups of a block
+// are split over nparts waves when there are more waves than blocks.
+__host__ __device__ inline int gram_parts(int nub, int W)
+{
+    return nub <= W ? W / nub : 1;
+}
 
 __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char *base, MfmaLds *L)
 {
@@ -85,16 +96,14 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         off += (bytes + 15) & ~size_t(15);
         return base ? base + o : nullptr;
     };
-    const size_t rp = (size_t)W * VRK_RGROUP * 16, pm = (size_t)2 * kpad * 16;
+    const size_t rp = (size_t)W * VRK_RGROUP * 16, pm = (size_t)(1 + gram_parts(kpad / 16, W)) * kpad * 16;
     char *R = take((size_t)kpad * 16 * 8);
     char *Q = take((size_t)kpad * 16 * 8);
     char *Rp = take((rp > pm ? rp : pm) * 8);
     char *nrm = take((size_t)kpad * 4);
     char *pre = take((size_t)W * kpad * 4);
-    char *red = take((size_t)2 * W * 16 * 4);
-    char *sc = take(16 * 4 * 4);
+    char *red = take((size_t)4 * W * 16 * 4);
     char *posl = take((size_t)kpad * 4);
-    char *ints = take(16 * 4 * 4);
     char *tabs = take((size_t)(nab + 1 + 4 * (kpad / 16) + 1) * 4);
     char *gmc = take((size_t)(kpad / 16) * (kpad / 4) * 4);
     char *rsel = take((size_t)kpad * 4);
@@ -117,61 +126,63 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         L->nrm = (float *)nrm;
         L->pre = (float *)pre;
         L->red = (float *)red;
-        float *s = (float *)sc;
-        L->snorm = s;
-        L->rel = s + 16;
-        L->gre = s + 32;
-        L->gim = s + 48;
         L->posl = (int *)posl;
-        int *ip = (int *)ints;
-        L->active = ip;
-        L->iters = ip + 16;
-        L->flags = ip + 32;
-        L->pick = ip + 48;
     }
     return off;
 }
 
 // Sums over the threads of each RHS column j = tid % 16; every thread gets
-// its column's totals. Two barriers: one before the per-wave partials are
-// written (earlier readers of the buffer are done), one after. Fixed order.
+// its column's totals, added in a fixed order. One barrier: consecutive sums
+// alternate between the two halves of the buffer (ColSums), so a sum never
+// overwrites partials that a thread may still be reading from the previous
+// one, and the sum before that was read before the previous barrier.
 template <int W>
-__device__ __forceinline__ float col_sum(float v, float *red)
-{
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    __syncthreads();
-    if (lane < 16) red[w * 16 + lane] = v;
-    __syncthreads();
-    float s = 0.f;
-#pragma unroll
-    for (int i = 0; i < W; ++i) s += red[i * 16 + (tid & 15)];
-    return s;
-}
+struct ColSums {
+    float *red;   // 2 halves x 2 values x W waves x 16 columns
+    int half;
 
-template <int W>
-__device__ __forceinline__ float2 col_sum2(float a, float b, float *red)
-{
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    a += __shfl_xor(a, 16, 64);
-    a += __shfl_xor(a, 32, 64);
-    b += __shfl_xor(b, 16, 64);
-    b += __shfl_xor(b, 32, 64);
-    __syncthreads();
-    if (lane < 16) {
-        red[w * 16 + lane] = a;
-        red[(W + w) * 16 + lane] = b;
+    __device__ __forceinline__ float *next()
+    {
+        half ^= 1;
+        return red + half * 2 * W * 16;
     }
-    __syncthreads();
-    float sa = 0.f, sb = 0.f;
+
+    __device__ __forceinline__ float sum(float v)
+    {
+        const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+        float *b = next();
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (lane < 16) b[w * 16 + lane] = v;
+        __syncthreads();
+        float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-        sa += red[i * 16 + (tid & 15)];
-        sb += red[(W + i) * 16 + (tid & 15)];
+        for (int i = 0; i < W; ++i) s += b[i * 16 + (tid & 15)];
+        return s;
     }
-    return float2{sa, sb};
-}
+
+    __device__ __forceinline__ float2 sum2(float a, float c)
+    {
+        const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+        float *b = next();
+        a += __shfl_xor(a, 16, 64);
+        a += __shfl_xor(a, 32, 64);
+        c += __shfl_xor(c, 16, 64);
+        c += __shfl_xor(c, 32, 64);
+        if (lane < 16) {
+            b[w * 16 + lane] = a;
+            b[(W + w) * 16 + lane] = c;
+        }
+        __syncthreads();
+        float sa = 0.f, sc = 0.f;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            sa += b[i * 16 + (tid & 15)];
+            sc += b[(W + i) * 16 + (tid & 15)];
+        }
+        return float2{sa, sc};
+    }
+};
 
 // Per-tile constants shared by the phases below (passed by value so that
 // everything stays in registers after inlining).
@@ -181,10 +192,9 @@ using gp = VRK_GLOBAL T *;
 
 struct TileCtx {
     MfmaLds L;
-    gp<const float2> S, H, HA, HG, GM, FH;
+    gp<const float2> S, HA, HG, GM;
     gp<float2> Xw;   // global-iterate mode: this tile's x, [ab][r][lane] (MFMA result order)
-    gp<const int32_t> perm, vs, ve, ag_uc, gm_c, fown;
-    gp<const uint8_t> inf;
+    gp<const int32_t> perm, ag_uc, gm_c;
     int64_t lds;
     int K, N, nub, kpad, nab, b0, nrhs, prob;
     float xi;
@@ -316,124 +326,115 @@ __device__ __forceinline__ void form_x(const TileCtx &c, f4 (&xr)[NA ? NA : 1], 
     }
 }
 
-// Gram tiles held in registers: the first GR tiles of the wave's first row
-// block (mb = w), loaded once per iteration phase.
+// Gram work of a wave: with nub <= W, wave w < nparts * nub takes chunk
+// groups [g0, g1) of row block mb = w % nub as part w / nub; with more blocks
+// than waves it takes the whole blocks w, w + W, ... The first GR chunks of
+// its first block sit in registers for an iteration phase (tiles and their
+// chunk columns), loaded by gram_load.
 template <int GR>
 struct GramRegs {
     float2 m[GR];
+    int uc[GR];
+    int mb, part, g0, g1;
 };
 
 template <int W, int GR>
 __device__ __forceinline__ void gram_load(const TileCtx &c, GramRegs<GR> &gr)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int e0 = w < c.nub ? c.L.gmoff[w] : 0, n = w < c.nub ? c.L.gmoff[w + 1] - e0 : 0;
+    const int np = gram_parts(c.nub, W);
+    gr.mb = -1;
+    gr.part = 0;
+    gr.g0 = gr.g1 = 0;
+    if (c.nub <= W) {
+        if (w < np * c.nub) {
+            gr.mb = w % c.nub;
+            gr.part = w / c.nub;
+            const int ng = (c.L.gmoff[gr.mb + 1] - c.L.gmoff[gr.mb]) / 4;
+            gr.g0 = gr.part * ng / np;
+            gr.g1 = (gr.part + 1) * ng / np;
+        }
+    } else if (w < c.nub) {
+        gr.mb = w;
+        gr.g1 = (c.L.gmoff[w + 1] - c.L.gmoff[w]) / 4;
+    }
+    const int e0 = gr.mb >= 0 ? c.L.gmoff[gr.mb] + 4 * gr.g0 : 0;
+    const int n = 4 * (gr.g1 - gr.g0);
 #pragma unroll
     for (int q = 0; q < GR; ++q) {
         gr.m[q] = float2{0.f, 0.f};
-        if (q < n) gr.m[q] = c.GM[(int64_t)(e0 + q) * 64 + lane];
+        gr.uc[q] = 0;
+        if (q < n) {
+            gr.m[q] = c.GM[(int64_t)(e0 + q) * 64 + lane];
+            gr.uc[q] = __builtin_amdgcn_readfirstlane(c.L.gmc[e0 + q]);
+        }
     }
 }
 
-// Gram product of the wave's 16-row blocks mb = w, w + W, ...: the MFMA
-// result (rows 16 mb + 4 g + r, column j) of M F goes to fn(mb, re, im).
-template <int W, int GR, typename Fn>
-__device__ __forceinline__ void gram_rows(const TileCtx &c, const float2 *F, const GramRegs<GR> &gr, Fn fn)
+// Four chunks e .. e + 3 of a row block from memory: loads first, then MFMAs.
+__device__ __forceinline__ void gram_group(const TileCtx &c, const float2 *F, int e, C3 &acc)
+{
+    const int lane = threadIdx.x & 63;
+    float2 m[4], f[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        m[i] = c.GM[(int64_t)(e + i) * 64 + lane];
+        f[i] = F[c.L.gmc[e + i] * 64 + lane];   // row 4 uc + g, column j
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c3mfma(acc, m[i], f[i]);
+}
+
+// Partial Gram products of the wave's work: the MFMA result (rows
+// 16 mb + 4 g + r, column j) of its chunks of M F goes to the part's slice
+// MP[part] of LDS. Parts are summed by the element-wise pass after a barrier.
+template <int W, int GR>
+__device__ __forceinline__ void gram_part(const TileCtx &c, const float2 *F, const GramRegs<GR> &gr)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
-#pragma unroll 1
-    for (int mb = w; mb < c.nub; mb += W) {
+    auto block = [&](int mb, int g0, int g1, bool regs) {
         C3 acc = c3_zero();
-        const int e0 = c.L.gmoff[mb], e1 = c.L.gmoff[mb + 1];
-        int e = e0;
-        if (mb == w) {
+        const int e0 = c.L.gmoff[mb];
+        int gg = g0;
+        if (regs) {
 #pragma unroll
-            for (int q = 0; q < GR; ++q)
-                if (e0 + q < e1) c3mfma(acc, gr.m[q], F[(4 * c.L.gmc[e0 + q] + g) * 16 + j]);
-            e = e0 + GR;
+            for (int q4 = 0; q4 < GR / 4; ++q4)
+                if (g0 + q4 < g1) {
+                    float2 f[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) f[i] = F[gr.uc[4 * q4 + i] * 64 + lane];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) c3mfma(acc, gr.m[4 * q4 + i], f[i]);
+                }
+            gg = g0 + GR / 4;
         }
 #pragma unroll 1
-        for (; e + 1 < e1; e += 2) {
-            const int uc0 = c.L.gmc[e], uc1 = c.L.gmc[e + 1];
-            float2 m0 = c.GM[(int64_t)e * 64 + lane], m1 = c.GM[(int64_t)(e + 1) * 64 + lane];
-            float2 f0 = F[(4 * uc0 + g) * 16 + j], f1 = F[(4 * uc1 + g) * 16 + j];
-            c3mfma(acc, m0, f0);
-            c3mfma(acc, m1, f1);
-        }
-        if (e < e1) c3mfma(acc, c.GM[(int64_t)e * 64 + lane], F[(4 * c.L.gmc[e] + g) * 16 + j]);
+        for (; gg < g1; ++gg) gram_group(c, F, e0 + 4 * gg, acc);
         f4 mr, mi;
         c3_get(acc, mr, mi);
-        fn(mb, mr, mi);
-    }
-}
-
-// P <- r / ||a||^2 on the rows with sel (0 elsewhere) of the active columns.
-// sel: 0 all rows, 1 rows of F, 2 rows of V.
-template <int W>
-__device__ __forceinline__ void phi_rows(const TileCtx &c, int sel)
-{
-    const int tid = threadIdx.x, j = tid & 15, er = tid >> 4, rows_per_pass = W * 4;
-    const bool act = c.L.active[j] != 0;
-    for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
-        float2 f = {0.f, 0.f};
-        const int rs = c.L.rsel[ku];
-        const bool in = act && rs != 0 && (sel == 0 || rs == sel);
-        if (in) {
-            const float2 r = c.L.R[ku * 16 + j];
-            const float inv = 1.f / c.L.nrm[ku];
-            f = float2{r.x * inv, r.y * inv};
-        }
-        c.L.P[ku * 16 + j] = f;
-    }
-}
-
-// Aggregated projection (update4) in the dual: with phi = P (rows of sel),
-// gamma = phi^H r / ||A^H phi||^2 where ||A^H phi||^2 = phi^H M phi (Gram
-// identity), then q += gamma phi and r -= gamma M phi. P must be complete
-// (a barrier after phi_rows).
-template <int W, int GR>
-__device__ __forceinline__ void aggregate_step(const TileCtx &c, const GramRegs<GR> &gr)
-{
-    const int tid = threadIdx.x, lane = tid & 63, j = lane & 15, g = lane >> 4;
-    const int er = tid >> 4, rows_per_pass = W * 4;
-    float num = 0.f, den = 0.f;
-    gram_rows<W, GR>(c, c.L.P, gr, [&](int mb, const f4 &mr, const f4 &mi) {
+        float2 *out = c.L.MP + (size_t)(regs ? gr.part : 0) * c.kpad * 16;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ku = 16 * mb + 4 * g + r;
-            const float2 f = c.L.P[ku * 16 + j], rr = c.L.R[ku * 16 + j];
-            c.L.MP[ku * 16 + j] = float2{mr[r], mi[r]};
-            den += f.x * mr[r] + f.y * mi[r];
-            num += f.x * rr.x + f.y * rr.y;   // |r|^2 / ||a||^2 on the rows of phi
-        }
-    });
-    const float2 nd = col_sum2<W>(num, den, c.L.red);
-    const float gm = (c.L.active[j] && nd.x > 0.f && nd.y > 0.f) ? nd.x / nd.y : 0.f;
-    for (int ku = er; ku < c.kpad; ku += rows_per_pass) {
-        const float2 f = c.L.P[ku * 16 + j], m = c.L.MP[ku * 16 + j];
-        const float2 q = c.L.Q[ku * 16 + j], rr = c.L.R[ku * 16 + j];
-        c.L.Q[ku * 16 + j] = float2{q.x + gm * f.x, q.y + gm * f.y};
-        c.L.R[ku * 16 + j] = float2{rr.x - gm * m.x, rr.y - gm * m.y};
+        for (int r = 0; r < 4; ++r) out[(16 * mb + 4 * g + r) * 16 + j] = float2{mr[r], mi[r]};
+    };
+    if (c.nub <= W) {
+        if (gr.mb >= 0) block(gr.mb, gr.g0, gr.g1, true);
+    } else {
+#pragma unroll 1
+        for (int mb = w; mb < c.nub; mb += W)
+            block(mb, 0, (c.L.gmoff[mb + 1] - c.L.gmoff[mb]) / 4, mb == w);
     }
 }
 
-// Step with unit weight on the rows of P (the orthogonal half-step, or the
-// one-hot step of the greedy variants with gamma folded into P): q += P,
-// r -= M P. The wave owning a row block updates it; ends with a barrier.
-template <int W, int GR>
-__device__ __forceinline__ void unit_step(const TileCtx &c, const GramRegs<GR> &gr)
+// Sum of the partial Gram products at entry (ku, j).
+__device__ __forceinline__ float2 gram_sum(const TileCtx &c, int np, int ku, int j)
 {
-    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
-    gram_rows<W, GR>(c, c.L.P, gr, [&](int mb, const f4 &mr, const f4 &mi) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ku = 16 * mb + 4 * g + r;
-            const float2 f = c.L.P[ku * 16 + j], q = c.L.Q[ku * 16 + j], rr = c.L.R[ku * 16 + j];
-            c.L.Q[ku * 16 + j] = float2{q.x + f.x, q.y + f.y};
-            c.L.R[ku * 16 + j] = float2{rr.x - mr[r], rr.y - mi[r]};
-        }
-    });
-    __syncthreads();
+    float2 s = {0.f, 0.f};
+    for (int p = 0; p < np; ++p) {
+        const float2 v = c.L.MP[((size_t)p * c.kpad + ku) * 16 + j];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    return s;
 }
 
 template <int W, int NA, int VARIANT>
@@ -465,118 +466,99 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         X = gmem(static_cast<float2 *>(d.X)); ldx_ = d.ldx;
         V = gmem(static_cast<float2 *>(d.V)); ldv_ = d.ldv;
     }
-    c.H = gmem(static_cast<const float2 *>(d.H));
     c.HA = gmem(static_cast<const float2 *>(d.HA));
     c.HG = gmem(static_cast<const float2 *>(d.HG));
     c.GM = gmem(static_cast<const float2 *>(d.GM));
-    c.FH = gmem(static_cast<const float2 *>(d.FH));
     c.Xw = NA == 0 ? gmem(static_cast<float2 *>(d.Xw)) + (int64_t)tile * c.nab * 256 : nullptr;
     c.perm = gmem(d.perm);
-    c.vs = gmem(d.vs);
-    c.ve = gmem(d.ve);
     c.ag_uc = gmem(d.ag_uc);
     c.gm_c = gmem(d.gm_c);
-    c.fown = gmem(d.fown);
-    c.inf = gmem(d.inf);
     const gp<const float> nrm_g = gmem(static_cast<const float *>(d.nrm));
     const int K = c.K, N = c.N, kpad = c.kpad, b0 = c.b0;
     const int rows_per_pass = W * 4;   // (row, column) entries: tid -> (tid / 16, tid % 16)
     const int er = tid >> 4;
 
-    // ---- init: q = 0, r = s (z0 = 0), norms in VR-start order
+    // ---- init: tables in LDS, then q = 0, r = s (z0 = 0), norms in VR-start order
     constexpr int NR = NA ? NA : 1;
     f4 xr[NR], xq[NR];
-    float s2 = 0.f;
+    for (int ku = tid; ku < kpad; ku += W * 64) {
+        L.nrm[ku] = ku < K ? nrm_g[c.perm[ku]] : 1.f;
+        L.rsel[ku] = ku < K ? (gmem(d.inf)[c.perm[ku]] ? 1 : 2) : 0;
+        if (ku < K) L.posl[c.perm[ku]] = ku;
+    }
+    for (int i = tid; i <= c.nab; i += W * 64) L.agoff[i] = gmem(d.ag_off)[i];
+    for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
+    for (int i = tid; i < gmem(d.gm_off)[c.nub]; i += W * 64) L.gmc[i] = max(c.gm_c[i], 0);   // padding: zero tile
+    for (int i = tid; i < c.nub; i += W * 64) {
+        L.rlo[i] = gmem(d.rab_lo)[i];
+        L.rhi[i] = gmem(d.rab_hi)[i];
+        L.hoff[i] = (int)gmem(d.ha_off)[i];
+    }
+    __syncthreads();
+    constexpr int variant = VARIANT;
+    // phi for the first step of an iteration from the residual of one entry:
+    // rows of F (VR-OAHK), every row (AHK), none (greedy variants: one-hot)
+    auto phi_first = [&](int ku, float2 rr) -> float2 {
+        const int rs = L.rsel[ku];
+        const bool in = variant == 1 ? rs != 0 : (variant == 3 ? rs == 1 : false);
+        const float inv = in ? 1.f / L.nrm[ku] : 0.f;
+        return float2{rr.x * inv, rr.y * inv};
+    };
+    ColSums<W> cs{L.red, 0};
+    float r2 = 0.f, num = 0.f;
     for (int ku = er; ku < kpad; ku += rows_per_pass) {
         float2 sv = {0.f, 0.f};
         const int b = b0 + j;
         if (ku < K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + c.perm[ku]];
         L.R[ku * 16 + j] = sv;
         L.Q[ku * 16 + j] = float2{0.f, 0.f};
-        s2 += sv.x * sv.x + sv.y * sv.y;
+        const float2 f = phi_first(ku, sv);
+        L.P[ku * 16 + j] = f;
+        r2 += sv.x * sv.x + sv.y * sv.y;
+        num += f.x * sv.x + f.y * sv.y;
     }
-    for (int ku = tid; ku < kpad; ku += W * 64) {
-        L.nrm[ku] = ku < K ? nrm_g[c.perm[ku]] : 1.f;
-        if (ku < K) L.posl[c.perm[ku]] = ku;
+    {
+        const float2 t = cs.sum2(r2, num);
+        r2 = t.x;
+        num = t.y;
     }
-    for (int i = tid; i <= c.nab; i += W * 64) L.agoff[i] = gmem(d.ag_off)[i];
-    for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
-    for (int i = tid; i < gmem(d.gm_off)[c.nub]; i += W * 64) L.gmc[i] = c.gm_c[i];
-    for (int ku = tid; ku < kpad; ku += W * 64) L.rsel[ku] = ku < K ? (c.inf[c.perm[ku]] ? 1 : 2) : 0;
-    for (int i = tid; i < c.nub; i += W * 64) {
-        L.rlo[i] = gmem(d.rab_lo)[i];
-        L.rhi[i] = gmem(d.rab_hi)[i];
-        L.hoff[i] = (int)gmem(d.ha_off)[i];
-    }
-    s2 = col_sum<W>(s2, L.red);
     const float fro2 = *gmem(static_cast<const float *>(d.fro2));
-    if (tid < 16) {
-        const int b = b0 + tid;
-        float sn = sqrtf(s2);
-        L.snorm[tid] = sn;
-        int act = 0, fl = 0;
-        if (b < c.nrhs) {
-            if (!isfinite(sn) || !isfinite(fro2)) fl = VRK_FLAG_NONFINITE;
-            else if (s2 == 0.f) fl = VRK_FLAG_CONVERGED;
-            else act = 1;
-        }
-        L.active[tid] = act;
-        L.flags[tid] = fl;
-        L.iters[tid] = 0;
-        L.rel[tid] = 0.f;
-        L.pick[tid] = -1;
+    // state of this thread's column j, identical in every thread of the column
+    const float sn = sqrtf(r2);
+    bool act = false;
+    int fl = 0, its = 0;
+    float rel = 0.f;
+    if (b0 + j < c.nrhs) {
+        if (!isfinite(sn) || !isfinite(fro2)) fl = VRK_FLAG_NONFINITE;
+        else if (r2 == 0.f) fl = VRK_FLAG_CONVERGED;
+        else act = true;
     }
-    __syncthreads();
 
-    constexpr int variant = VARIANT;
-    // Gram tiles kept in registers per wave (two VGPRs each)
-    constexpr int GR = W == 8 ? 32 : 16;
+    // Gram tiles kept in registers per wave (two VGPRs and a chunk column each)
+    constexpr int GR = W == 8 ? 16 : 8;
+    const int np = c.nub <= W ? gram_parts(c.nub, W) : 1;
     int64_t t_it = 0;
     for (;;) {
         // iteration phase: runs until every column has stopped
         GramRegs<GR> gr;
         gram_load<W, GR>(c, gr);
         for (;;) {
-            // stop rule per column on the maintained residual; lanes 0..15 of
-            // each wave cover all 16 columns, so a ballot tells whether any goes on
-            float r2 = 0.f;
-            for (int ku = er; ku < kpad; ku += rows_per_pass) {
-                float2 r = L.R[ku * 16 + j];
-                r2 += r.x * r.x + r.y * r.y;
+            // stop rule on the maintained residual
+            if (act) {
+                rel = sqrtf(r2) / sn;
+                its = (int)t_it;
+                if (!isfinite(rel)) { fl = VRK_FLAG_NONFINITE; act = false; }
+                else if (rel <= (float)a.tol) { fl = kPending; act = false; }
+                else if (t_it >= a.max_iters) { fl = VRK_FLAG_MAXITER; act = false; }
             }
-            r2 = col_sum<W>(r2, L.red);
-            bool still = false;
-            {
-                const bool was = L.active[j] != 0;
-                const float rel = sqrtf(r2) / L.snorm[j];
-                int fl = 0;
-                if (was) {
-                    if (!isfinite(rel)) fl = VRK_FLAG_NONFINITE;
-                    else if (rel <= (float)a.tol) fl = kPending;
-                    else if (t_it >= a.max_iters) fl = VRK_FLAG_MAXITER;
-                    still = fl == 0;
-                }
-                __syncthreads();   // every lane has read its column's old state
-                if (tid < 16 && was) {
-                    L.rel[tid] = rel;
-                    L.iters[tid] = (int)t_it;
-                    if (fl) {
-                        L.flags[tid] = fl;
-                        L.active[tid] = 0;
-                    }
-                }
-            }
-            if (__ballot(still) == 0) break;
-            __syncthreads();
+            if (__ballot(act) == 0) break;   // lanes 0..15 of a wave hold all 16 columns
 
             if constexpr (variant == 0 || variant == 2) {
-                // greedy selection, one wave per column (M's sparsity confines the
-                // residual change to the rows of X_pick, Theorem 2)
+                // greedy selection, one wave per column; phi is one-hot with
+                // gamma (P is zero elsewhere). M's sparsity confines the
+                // residual change to the rows of X_pick (Theorem 2).
                 for (int cc = w; cc < 16; cc += W) {
-                    if (!L.active[cc]) {
-                        if (lane == 0) { L.gre[cc] = 0.f; L.gim[cc] = 0.f; L.pick[cc] = -1; }
-                        continue;
-                    }
+                    if (!__shfl(act, cc, 64)) continue;
                     const float u = (float)uniform24(a.seed, t_it, b0 + cc, c.prob);
                     const float2 *Rl = L.R;
                     const float *nl = L.nrm;
@@ -589,72 +571,137 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                     if (lane == 0) {
                         const int ku = L.posl[i];
                         const float inv = 1.f / L.nrm[ku];
-                        float2 r = L.R[ku * 16 + cc];
-                        L.pick[cc] = i;
-                        L.gre[cc] = r.x * inv;
-                        L.gim[cc] = r.y * inv;
+                        const float2 r = L.R[ku * 16 + cc];
+                        L.P[ku * 16 + cc] = float2{r.x * inv, r.y * inv};
                     }
                 }
                 __syncthreads();
-                {
-                    const int pk = L.pick[j];
-                    const int kp = pk >= 0 ? L.posl[pk] : -1;
-                    const float2 gmj = float2{L.gre[j], L.gim[j]};
-                    for (int ku = er; ku < kpad; ku += rows_per_pass)
-                        L.P[ku * 16 + j] = ku == kp ? gmj : float2{0.f, 0.f};
+                gram_part<W, GR>(c, L.P, gr);
+                __syncthreads();
+                r2 = 0.f;
+                for (int ku = er; ku < kpad; ku += rows_per_pass) {
+                    const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
+                    float2 rr = L.R[ku * 16 + j];
+                    if (act) {
+                        const float2 q = L.Q[ku * 16 + j];
+                        L.Q[ku * 16 + j] = float2{q.x + f.x, q.y + f.y};
+                        rr = float2{rr.x - m.x, rr.y - m.y};
+                        L.R[ku * 16 + j] = rr;
+                    }
+                    L.P[ku * 16 + j] = float2{0.f, 0.f};
+                    r2 += rr.x * rr.x + rr.y * rr.y;
                 }
-                __syncthreads();
-                unit_step<W, GR>(c, gr);
+                r2 = cs.sum(r2);
             } else if constexpr (variant == 1) {
-                phi_rows<W>(c, 0);
+                // aggregated step over all rows: phi = P, num known
+                gram_part<W, GR>(c, L.P, gr);
                 __syncthreads();
-                aggregate_step<W, GR>(c, gr);
+                float den = 0.f;
+                for (int ku = er; ku < kpad; ku += rows_per_pass) {
+                    const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
+                    den += f.x * m.x + f.y * m.y;
+                }
+                den = cs.sum(den);
+                const float gm = (act && num > 0.f && den > 0.f) ? num / den : 0.f;
+                r2 = 0.f;
+                float nn = 0.f;
+                for (int ku = er; ku < kpad; ku += rows_per_pass) {
+                    const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
+                    const float2 q = L.Q[ku * 16 + j];
+                    const float2 rr = float2{L.R[ku * 16 + j].x - gm * m.x, L.R[ku * 16 + j].y - gm * m.y};
+                    L.Q[ku * 16 + j] = float2{q.x + gm * f.x, q.y + gm * f.y};
+                    L.R[ku * 16 + j] = rr;
+                    const float2 p = phi_first(ku, rr);
+                    L.P[ku * 16 + j] = p;
+                    r2 += rr.x * rr.x + rr.y * rr.y;
+                    nn += p.x * rr.x + p.y * rr.y;
+                }
+                const float2 t = cs.sum2(r2, nn);
+                r2 = t.x;
+                num = t.y;
             } else {
-                // orthogonal half-step on F with gamma = 1 (Prop. 1), then the
-                // aggregated step on V
-                phi_rows<W>(c, 1);
+                // orthogonal half-step on F with gamma = 1 (Prop. 1): q_F += phi_F,
+                // r -= M phi_F; then phi_V of the new residual
+                const bool hasv = d.nv > 0;
+                gram_part<W, GR>(c, L.P, gr);
                 __syncthreads();
-                unit_step<W, GR>(c, gr);
-                if (d.nv > 0) {
-                    phi_rows<W>(c, 2);
+                float nv_num = 0.f;
+                r2 = 0.f;
+                for (int ku = er; ku < kpad; ku += rows_per_pass) {
+                    const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
+                    float2 rr = L.R[ku * 16 + j];
+                    if (act) {
+                        const float2 q = L.Q[ku * 16 + j];
+                        L.Q[ku * 16 + j] = float2{q.x + f.x, q.y + f.y};
+                        rr = float2{rr.x - m.x, rr.y - m.y};
+                        L.R[ku * 16 + j] = rr;
+                    }
+                    // next phi: rows of V for the aggregated step, or, without
+                    // V, rows of F for the next iteration
+                    const int rs = L.rsel[ku];
+                    const float inv = rs == (hasv ? 2 : 1) ? 1.f / L.nrm[ku] : 0.f;
+                    const float2 p = float2{rr.x * inv, rr.y * inv};
+                    L.P[ku * 16 + j] = p;
+                    nv_num += p.x * rr.x + p.y * rr.y;
+                    r2 += rr.x * rr.x + rr.y * rr.y;
+                }
+                if (!hasv) {
+                    r2 = cs.sum(r2);
+                } else {
+                    // aggregated step on V: gamma = phi^H r / phi^H M phi
                     __syncthreads();
-                    aggregate_step<W, GR>(c, gr);
+                    gram_part<W, GR>(c, L.P, gr);
+                    __syncthreads();
+                    float den = 0.f;
+                    for (int ku = er; ku < kpad; ku += rows_per_pass) {
+                        const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
+                        den += f.x * m.x + f.y * m.y;
+                    }
+                    const float2 nd = cs.sum2(nv_num, den);
+                    const float gm = (act && nd.x > 0.f && nd.y > 0.f) ? nd.x / nd.y : 0.f;
+                    r2 = 0.f;
+                    for (int ku = er; ku < kpad; ku += rows_per_pass) {
+                        const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
+                        const float2 q = L.Q[ku * 16 + j];
+                        const float2 rr = float2{L.R[ku * 16 + j].x - gm * m.x, L.R[ku * 16 + j].y - gm * m.y};
+                        L.Q[ku * 16 + j] = float2{q.x + gm * f.x, q.y + gm * f.y};
+                        L.R[ku * 16 + j] = rr;
+                        L.P[ku * 16 + j] = phi_first(ku, rr);
+                        r2 += rr.x * rr.x + rr.y * rr.y;
+                    }
+                    r2 = cs.sum(r2);
                 }
             }
             ++t_it;
         }
         // every column stopped: x = H^H q and the true residual decide
-        __syncthreads();
         form_x<W, NA>(c, xr, xq);
         tile_residual<W, NA>(c, xr, xq);
-        float t2 = 0.f;
+        float t2 = 0.f, tn = 0.f;
         for (int ku = er; ku < kpad; ku += rows_per_pass) {
-            float2 r = L.R[ku * 16 + j];
-            t2 += r.x * r.x + r.y * r.y;
+            const float2 rr = L.R[ku * 16 + j];
+            const float2 p = phi_first(ku, rr);
+            L.P[ku * 16 + j] = p;
+            t2 += rr.x * rr.x + rr.y * rr.y;
+            tn += p.x * rr.x + p.y * rr.y;
         }
-        t2 = col_sum<W>(t2, L.red);
+        {
+            const float2 t = cs.sum2(t2, tn);
+            t2 = t.x;
+            tn = t.y;
+        }
         // columns stopped by the rule or the iteration cap take the true
         // residual's verdict; a column it rejects resumes while the cap allows
-        const float rel = sqrtf(t2) / L.snorm[j];
-        const int fl = L.flags[j];
-        const bool open = fl == kPending || fl == VRK_FLAG_MAXITER;
-        int nf = fl;
-        if (open) {
-            if (!isfinite(rel)) nf = VRK_FLAG_NONFINITE;
-            else if (rel <= (float)a.tol) nf = VRK_FLAG_CONVERGED;
-            else if (t_it < a.max_iters) nf = 0;
-            else nf = VRK_FLAG_MAXITER;
+        if (fl == kPending || fl == VRK_FLAG_MAXITER) {
+            rel = sqrtf(t2) / sn;
+            if (!isfinite(rel)) fl = VRK_FLAG_NONFINITE;
+            else if (rel <= (float)a.tol) fl = VRK_FLAG_CONVERGED;
+            else if (t_it < a.max_iters) { fl = 0; act = true; }
+            else fl = VRK_FLAG_MAXITER;
         }
-        const bool resume = open && nf == 0;
-        __syncthreads();   // every lane has read its column's state
-        if (tid < 16 && open) {
-            L.rel[tid] = rel;
-            L.flags[tid] = nf;
-            if (resume) L.active[tid] = 1;
-        }
-        const bool again = __ballot(resume) != 0;
-        __syncthreads();
-        if (!again) break;   // else the resumed columns go on from the true residual
+        if (__ballot(act) == 0) break;
+        r2 = t2;   // the resumed columns go on from the true residual
+        num = tn;
     }
 
     // ---- outputs. Each lane holds 4 consecutive antennas of one RHS: two
@@ -701,9 +748,9 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         const int b = b0 + tid;
         if (b < c.nrhs) {
             const int64_t gidx = d.rhs_base + b;
-            if (a.iters) gmem(a.iters)[gidx] = L.iters[tid];
-            if (a.relres) gmem(a.relres)[gidx] = L.rel[tid];
-            if (a.flags) gmem(a.flags)[gidx] = L.flags[tid];
+            if (a.iters) gmem(a.iters)[gidx] = its;
+            if (a.relres) gmem(a.relres)[gidx] = rel;
+            if (a.flags) gmem(a.flags)[gidx] = fl;
         }
     }
 }
@@ -796,10 +843,9 @@ hipError_t launch_variant(const VrkSolveArgs &a, const VrkWork *work, const VrkQ
 // x of one tile lives in registers when it fits: at most 16 antenna blocks
 // per wave with 8 waves (two waves per SIMD) and 8 with 16 waves (four per
 // SIMD), i.e. Nt <= 2048. Larger Nt keeps x in a workspace buffer (NA = 0).
-int vrk_mfma_supported(int32_t nt, int32_t waves)
+int vrk_mfma_supported(int32_t kpad, int32_t waves)
 {
-    (void)nt;
-    return waves == 8 || waves == 16;
+    return (waves == 8 || waves == 16) && kpad <= kMaxPass * 4 * waves;
 }
 
 int vrk_mfma_register_na(int32_t nt, int32_t waves)

@@ -67,16 +67,16 @@ struct ProbPlan {
     int32_t ncol = 0;
     // MFMA tables
     int32_t nub = 0, nab = 0, ntile = 0;
-    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, fown, gm_off, gm_c;
+    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, gm_off, gm_c;
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
     // workspace offsets
     size_t o_vs, o_ve, o_xoff, o_xidx, o_flist, o_vlist, o_inf, o_coloff, o_colusr, o_gboff,
         o_gbusr, o_perm, o_pos, o_nrm, o_fro2, o_rablo, o_rabhi, o_haoff, o_agoff, o_aguc,
-        o_fown, o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
+        o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
     size_t o_xw = 0;   // MFMA iterate buffer when x does not fit registers
-    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_fh = 0;
+    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0;
 };
 
 }  // namespace
@@ -282,9 +282,6 @@ void build_tables(ProbPlan &q)
     }
     q.ag_off[q.nab] = (int32_t)q.ag_uc.size();
     q.n_hg = (int64_t)q.ag_uc.size();
-    q.fown.assign((size_t)q.nab * VRK_AB, -1);
-    for (int u : q.flist)
-        for (int32_t n = q.vs[u]; n < q.ve[u]; ++n) q.fown[n] = q.pos[u];
     // Gram blocks (16-user block, 4-user chunk) with any pair of overlapping
     // VRs or a shared user (the diagonal), in VR-start order
     q.gm_off.assign(q.nub + 1, 0);
@@ -302,6 +299,9 @@ void build_tables(ProbPlan &q)
                 }
             if (any) q.gm_c.push_back(uc);
         }
+        // groups of 4 chunks: the solve loads and multiplies a group at once;
+        // padding chunks (-1) hold zero tiles
+        while ((q.gm_c.size() - q.gm_off[mb]) % 4) q.gm_c.push_back(-1);
     }
     q.gm_off[q.nub] = (int32_t)q.gm_c.size();
     q.n_gm = (int64_t)q.gm_c.size();
@@ -380,13 +380,13 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     pl->adjoint_ready = all_adj;
     // engine choice
     int32_t waves = o.tile_waves ? o.tile_waves : 16;   // four waves per SIMD by default
-    bool mfma_ok = o.dtype == VRK_C64 && vrk_mfma_supported(max_nt, waves);
+    bool mfma_ok = o.dtype == VRK_C64 && vrk_mfma_supported(max_kpad, waves);
     int32_t eng = o.engine;
     if (eng == VRK_ENGINE_AUTO) eng = (mfma_ok && min_rhs >= VRK_TILE_RHS) ? VRK_ENGINE_MFMA : VRK_ENGINE_VECTOR;
     if (eng == VRK_ENGINE_MFMA && !mfma_ok) {
         delete pl;
-        return fail(VRK_EUNSUPPORTED, "MFMA engine needs complex64 and nt <= %d with %d waves",
-                    16 * VRK_AB * waves, waves);
+        return fail(VRK_EUNSUPPORTED, "MFMA engine needs complex64, 8 or 16 waves and k <= %d with %d waves",
+                    32 * waves, waves);
     }
     pl->engine = eng;
     pl->waves = waves;
@@ -488,7 +488,6 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_haoff = cv.take(8 * q.ha_off.size());
         q.o_agoff = cv.take(4 * q.ag_off.size());
         q.o_aguc = cv.take(4 * q.ag_uc.size());
-        q.o_fown = cv.take(4 * q.fown.size());
         q.o_gmoff = cv.take(4 * q.gm_off.size());
         q.o_gmc = cv.take(4 * q.gm_c.size());
     }
@@ -501,9 +500,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             q.o_hg = cv.take(q.n_hg * 64 * 8);
             if (pl->na == 0) q.o_xw = cv.take((size_t)q.ntile * q.nab * 256 * 8);
             q.o_gm = cv.take(q.n_gm * 64 * 8);
-            q.o_fh = cv.take((size_t)q.nab * VRK_AB * 8);
             pl->max_tiles = std::max(pl->max_tiles, q.n_gm);
-            pl->max_tiles = std::max(pl->max_tiles, (int64_t)(q.nab + 3) / 4);   // 64 antennas per pack wave
             pl->max_tiles = std::max(pl->max_tiles, std::max(q.n_ha, q.n_hg));
         }
         if (q.p.GX) {
@@ -556,7 +553,6 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         put(img, q.o_haoff, q.ha_off);
         put(img, q.o_agoff, q.ag_off);
         put(img, q.o_aguc, q.ag_uc);
-        put(img, q.o_fown, q.fown);
         put(img, q.o_gmoff, q.gm_off);
         put(img, q.o_gmc, q.gm_c);
         VrkDesc &d = descs[i];
@@ -599,14 +595,12 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.ha_off = (const int64_t *)(base + q.o_haoff);
         d.ag_off = (const int32_t *)(base + q.o_agoff);
         d.ag_uc = (const int32_t *)(base + q.o_aguc);
-        d.fown = (const int32_t *)(base + q.o_fown);
         d.HA = pl->engine == VRK_ENGINE_MFMA ? base + q.o_ha : nullptr;
         d.HG = pl->engine == VRK_ENGINE_MFMA ? base + q.o_hg : nullptr;
         d.Xw = (pl->engine == VRK_ENGINE_MFMA && pl->na == 0) ? base + q.o_xw : nullptr;
         d.gm_off = (const int32_t *)(base + q.o_gmoff);
         d.gm_c = (const int32_t *)(base + q.o_gmc);
         d.GM = pl->engine == VRK_ENGINE_MFMA ? base + q.o_gm : nullptr;
-        d.FH = pl->engine == VRK_ENGINE_MFMA ? base + q.o_fh : nullptr;
         (void)eb;
     }
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());

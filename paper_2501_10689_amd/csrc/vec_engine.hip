@@ -110,15 +110,6 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
         }
         reinterpret_cast<cx<float> *>(d.HG)[t * 64 + lane] = v;
     }
-    // F-step table: the entry of H that antenna n meets in the orthogonal
-    // half-step (its F owner's row), 64 antennas per wave
-    if (d.FH && t * 64 + lane < (int64_t)d.nab * VRK_AB) {
-        const int n = (int)(t * 64) + lane;
-        cx<float> v = {0.f, 0.f};
-        const int o = d.fown[n];
-        if (o >= 0) v = H[(int64_t)d.perm[o] * d.ldh + n];
-        reinterpret_cast<cx<float> *>(d.FH)[n] = v;
-    }
     const int64_t n_gm = d.gm_off[d.nub];
     if (t < n_gm) {
         // Gram tile e of user block mb: lane l = i + 16 kk holds
@@ -126,10 +117,10 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
         // H[u, n] conj(H[v, n]) (+ xi on the diagonal)
         int mb = 0;
         while (d.gm_off[mb + 1] <= t) ++mb;
-        const int uc = d.gm_c[t];
+        const int uc = d.gm_c[t];   // -1: padding chunk, zero tile
         const int ku = mb * VRK_UB + i, kv = uc * 4 + kk;
         float ar = 0.f, ai = 0.f;
-        if (ku < d.k && kv < d.k) {
+        if (uc >= 0 && ku < d.k && kv < d.k) {
             const int u = d.perm[ku], v2 = d.perm[kv];
             const int lo = max(d.vs[u], d.vs[v2]), hi = min(d.ve[u], d.ve[v2]);
             for (int n = lo; n < hi; ++n) {

@@ -48,14 +48,13 @@ struct VrkDesc {
     const int32_t *rab_lo, *rab_hi;  // per 16-user block: 16-antenna block range of its bands
     const int64_t *ha_off;        // per 16-user block: first residual tile
     const int32_t *ag_off, *ag_uc;   // per 16-antenna block: 4-user chunks meeting it (CSR)
-    const int32_t *fown;          // per antenna: sorted index of the F user covering it, or -1
     void *HA;                     // residual tiles, 64 complex64 each
     void *HG;                     // aggregation tiles (conjugated), 64 complex64 each
     void *Xw;                     // iterate of each 16-RHS tile when it does not fit registers:
                                   // [tile][ab][r][lane] complex64 (MFMA result order)
-    const int32_t *gm_off, *gm_c; // per 16-user block: 4-user chunks with a nonzero Gram block (CSR)
+    const int32_t *gm_off, *gm_c; // per 16-user block: 4-user chunks with a nonzero Gram block (CSR),
+                                  // padded with -1 (zero tile) to a multiple of 4 per block
     void *GM;                     // Gram tiles of H H^H + xi I (VR-start order), 64 complex64 each
-    void *FH;                     // per antenna (nab * 16): H[perm[fown[n]], n], 0 where fown[n] < 0
     // MFMA engine with adjoint buffers: v of the forward solve and mu of the
     // adjoint solve again, [rhs][nub * 16] complex64 in VR-start user order
     // (zero on the padding users), for the gradient products
