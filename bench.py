@@ -58,13 +58,24 @@ WORKLOADS = {
 }
 
 
-def algorithmic_flops(variant, band, band_f, band_v, iters, k):
-    """Real flops of one solve per the band structure (8 per complex MAC,
-    Table I's counting with |Gamma| taken per user): GRK / VR-OGRK: a full
-    banded residual per row update (the selection needs every residual)
-    plus the row update; AHK: residual + aggregation; VR-OAHK: residual
-    check, F half-step, V residual and V aggregation. `iters` = sum over
-    vectors of the updates each vector made."""
+def algorithmic_flops(engine, variant, band, band_f, band_v, overlap, iters, vectors, k):
+    """Real flops of one solve launch, 8 per complex multiply-add.
+
+    Vector engine (the paper's steps, Table I's counting with |Gamma| taken
+    per user): GRK / VR-OGRK a full banded residual per row update plus the
+    row update; AHK residual + aggregation; VR-OAHK residual check, F
+    half-step, V residual and V aggregation.
+
+    MFMA engine (dual-space iteration): per vector-iteration the Gram
+    products over the users' overlap sets, sum_i |X_i| = `overlap` complex
+    multiply-adds for the aggregated variants (the F and V columns of M),
+    |X_pick| (on average overlap / K) for the greedy ones; once per vector
+    x = H^H q and the true residual, 2 * band.
+
+    `iters` = sum over vectors of the iterations each vector made."""
+    if engine == "mfma":
+        per_it = overlap / k if variant in ("grk", "vr_ogrk") else overlap
+        return 8.0 * (iters * per_it + vectors * 2.0 * band)
     if variant in ("grk", "vr_ogrk"):
         return iters * 8.0 * band * (1.0 + 1.0 / k)
     if variant == "ahk":
@@ -174,7 +185,9 @@ def main():
         vl = np.asarray(d.vr_len, dtype=np.int64)
         band, band_f = float(vl.sum()), float(vl[fset].sum())
         it = it_all[base:base + d.nrhs]
-        flops += algorithmic_flops(args.variant, band, band_f, band - band_f, float(it.sum()), d.k)
+        overlap = float(plan.query(j, vrk.Q_XOFF)[-1])   # sum_i |X_i|
+        flops += algorithmic_flops(engine, args.variant, band, band_f, band - band_f, overlap, float(it.sum()),
+                                   float(d.nrhs), d.k)
         base += d.nrhs
     achieved = flops / (solve_ms * 1e-3)
     if engine == "mfma":
@@ -196,7 +209,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if c128 else "f32", "data": "synthetic",
         "config": {"workload": WORKLOADS[wl], "variant": args.variant, "engine": engine,
-                   "tile_waves": int(eng[2]), "persistent": int(eng[4]), "x_in_registers": int(eng[6]) > 0,
+                   "tile_waves": int(eng[2]), "persistent": int(eng[4]), "entries_per_thread": int(eng[6]),
                    "drops": len(drops), "vectors": B, "tol": tol},
         "roofline": roof,
         "accuracy": {"max_rel_err": worst, "mean_rel_err": errsum / B,

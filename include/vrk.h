@@ -117,8 +117,6 @@ typedef struct {
     int32_t persistent;  /* MFMA engine: 1 = one workgroup per resident slot, draining
                             per-XCD work queues (drops assigned by cost); 0 = one
                             workgroup per 16-RHS tile */
-    int32_t x_in_workspace; /* MFMA engine: 1 = keep each tile's iterate in the workspace
-                            (always so for Nt > 2048); 0 = in registers when it fits */
 } vrk_options;
 
 typedef struct vrk_plan vrk_plan;
@@ -161,14 +159,13 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
 /* Autotuner. Picks the execution configuration of a batch by timing it
  * on the device: for complex64 the MFMA engine with 8 or 16 waves per
  * workgroup, each with one workgroup per 16-RHS tile or the persistent
- * per-XCD work queues, the iterate in the workspace with 16 waves, and
- * the vector engine with the gather and
+ * per-XCD work queues, and the vector engine with the gather and
  * colour-class schedules; for complex128 the vector engine's two
  * schedules. Each candidate is planned, bound to d_ws, run once and timed
  * over `reps` solves with HIP events on `stream` (the call synchronises
  * the stream; it is not graph-capturable). The caller's X and V are
- * overwritten. On return opt's engine, tile_waves, persistent, schedule
- * and x_in_workspace hold the fastest candidate and *best_ms its time per
+ * overwritten. On return opt's engine, tile_waves, persistent and schedule
+ * hold the fastest candidate and *best_ms its time per
  * solve.
  * With d_ws null nothing runs: *ws_needed gets the workspace size the
  * largest candidate needs. cache_path (nullable) names a text file of
@@ -189,7 +186,7 @@ typedef enum {
     VRK_Q_XOFF = 3,      /* CSR offsets of X_k, length k + 1 */
     VRK_Q_XIDX = 4,      /* CSR indices of X_k (ascending, includes k) */
     VRK_Q_ENGINE = 5,    /* [engine, schedule, tile_waves, lds_bytes, persistent, grid,
-                            register blocks per wave (0: iterate in the workspace),
+                            (row, column) entries per thread of the MFMA solve,
                             RHS splits of the MFMA adjoint gradient tiles] */
     VRK_Q_TILES = 6      /* [residual tiles, aggregation tiles, band entries, Gram tiles] per problem */
 } vrk_query;

@@ -15,15 +15,17 @@
 // a column whose true residual misses the tolerance resumes from it.
 //
 // Layout. Lane l of a wave is (j, g) = (l % 16, l / 16): RHS column j and
-// row group g. Wave w owns the 16-antenna blocks ab = w + W a of x, lane
-// (j, g) holding x[16 ab + 4 g + r][j] in register r of float4 pair xr[a],
-// xq[a] - the layout of an MFMA result tile, which the residual product
+// row group g. Thread (er, j) of the workgroup keeps the entries (er + 4 W k,
+// j), k < EP, of r, q and phi in registers; LDS holds phi as the operand of
+// the Gram products, their per-wave partials and, for the greedy selection,
+// r. x = H^H q is formed once, straight into the output rows: the MFMA
+// result tile of antenna block ab gives lane (j, g) the 4 consecutive
+// antennas 16 ab + 4 g + r of RHS j, and the true-residual product
 //   R[u][j] = sum_n H[u][n] x[n][j]
-// takes as its B operand when the reduction index of chunk (ab, m) is
-// ordered as antenna 16 ab + 4 kk + m for slot kk. The aggregation product
-// x[n][j] = sum_u conj(H[u][n]) q[u][j] produces tiles in that layout. Users
-// are processed in VR-start order (perm), which keeps the nonzero tiles of
-// the banded H and M few.
+// reads them back as its B operand when the reduction index of chunk (ab,
+// m) is ordered as antenna 16 ab + 4 kk + m for slot kk. Users are processed
+// in VR-start order (perm), which keeps the nonzero tiles of the banded H
+// and M few.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -71,15 +73,15 @@ struct MfmaLds {
     int *posl;
     int *agoff, *rlo, *rhi, *hoff, *gmoff;   // copies of the tile tables of this problem
     int *gmc;    // copy of the Gram chunk columns (at most nub * kpad / 4)
+    int *gmnf;   // per row block: Gram chunks holding a user of F (a multiple of 4)
     int *rsel;   // per sorted row: 1 user of F, 2 user of V, 0 padding
 };
 
 // Column state beyond the public flags: stopped on the maintained residual,
 // waiting for the true residual to confirm.
 constexpr int kPending = 8;
-// (row, column) entries per thread in the element-wise passes: at most this
-// many passes of 4 W rows, so kpad <= kMaxPass * 4 W
-constexpr int kMaxPass = 8;
+// Own entries per thread (EP) are at most this many: kpad <= kMaxEntries * 4 W.
+constexpr int kMaxEntries = 4;
 
 // Waves per 16-row block of the Gram product: the chunk groups of a block
 // are split over nparts waves when there are more waves than blocks.
@@ -105,7 +107,8 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
     char *red = take((size_t)4 * W * 16 * 4);
     char *posl = take((size_t)kpad * 4);
     char *tabs = take((size_t)(nab + 1 + 4 * (kpad / 16) + 1) * 4);
-    char *gmc = take((size_t)(kpad / 16) * (kpad / 4) * 4);
+    char *gmc = take((size_t)(kpad / 16) * (kpad / 4 + 8) * 4);
+    char *gmnf = take((size_t)(kpad / 16) * 4);
     char *rsel = take((size_t)kpad * 4);
     // test the LDS base, not L: L points into a caller's register-resident
     // struct, and comparing its address would pin that struct to memory
@@ -117,6 +120,7 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         L->hoff = L->rhi + kpad / 16;
         L->gmoff = L->hoff + kpad / 16;
         L->gmc = (int *)gmc;
+        L->gmnf = (int *)gmnf;
         L->rsel = (int *)rsel;
         L->R = (float2 *)R;
         L->Q = (float2 *)Q;
@@ -193,18 +197,40 @@ using gp = VRK_GLOBAL T *;
 struct TileCtx {
     MfmaLds L;
     gp<const float2> S, HA, HG, GM;
-    gp<float2> Xw;   // global-iterate mode: this tile's x, [ab][r][lane] (MFMA result order)
+    gp<float2> X;   // output rows of this tile's RHS (x = H^H q)
     gp<const int32_t> perm, ag_uc, gm_c;
-    int64_t lds;
+    int64_t lds, ldx;
     int K, N, nub, kpad, nab, b0, nrhs, prob;
     float xi;
 };
 
-// R <- s - H x - xi q (rows in VR-start order), two 16-user blocks at a time
-// with a deterministic cross-wave reduction through LDS (buffer Rp).
-template <int W, int NA>
-__device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[NA ? NA : 1],
-                                              const f4 (&xq)[NA ? NA : 1])
+// Four consecutive antennas n0 .. n0 + 3 of x for RHS b0 + j from the output
+// rows (zero past N and for RHS beyond the batch).
+__device__ __forceinline__ void x_quad(const TileCtx &c, int n0, float2 (&x)[4])
+{
+    const int b = c.b0 + (threadIdx.x & 15);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[m] = float2{0.f, 0.f};
+    if (b >= c.nrhs) return;
+    const gp<const float2> row = c.X + (int64_t)b * c.ldx;
+    if (n0 + 3 < c.N && ((reinterpret_cast<uintptr_t>(row + n0) & 31) == 0)) {
+        const float4 a = *(gp<const float4>)(row + n0), e = *(gp<const float4>)(row + n0 + 2);
+        x[0] = float2{a.x, a.y};
+        x[1] = float2{a.z, a.w};
+        x[2] = float2{e.x, e.y};
+        x[3] = float2{e.z, e.w};
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (n0 + m < c.N) x[m] = row[n0 + m];
+    }
+}
+
+// R <- s - H x - xi q (rows in VR-start order), x from the output rows, two
+// 16-user blocks at a time with a deterministic cross-wave reduction through
+// LDS (buffer Rp). Every wave's x rows must be written (a barrier after form_x).
+template <int W>
+__device__ __forceinline__ void tile_residual(const TileCtx &c)
 {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
     const int nug = (c.nub + 1) / 2;
@@ -218,33 +244,17 @@ __device__ __forceinline__ void tile_residual(const TileCtx &c, const f4 (&xr)[N
             if (ub < c.nub) {
                 const int lo = c.L.rlo[ub], hi = c.L.rhi[ub];
                 const int64_t hb = c.L.hoff[ub];
-                if constexpr (NA == 0) {
-                    // iterate in the workspace: the wave's blocks w, w + W, ... inside [lo, hi)
-                    int ab = lo + ((w - lo) % W + W) % W;
+                // the wave's blocks w, w + W, ... inside [lo, hi)
+                int ab = lo + ((w - lo) % W + W) % W;
 #pragma unroll 1
-                    for (; ab < hi; ab += W) {
-                        const gp<const float2> hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
-                        const gp<const float2> xp = c.Xw + (int64_t)ab * 256 + lane;
-                        float2 h0 = hp[0], h1 = hp[64], h2 = hp[128], h3 = hp[192];
-                        float2 x0 = xp[0], x1 = xp[64], x2 = xp[128], x3 = xp[192];
-                        c3mfma(acc, h0, x0);
-                        c3mfma(acc, h1, x1);
-                        c3mfma(acc, h2, x2);
-                        c3mfma(acc, h3, x3);
-                    }
-                } else {
+                for (; ab < hi; ab += W) {
+                    const gp<const float2> hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
+                    float2 h[4], x[4];
 #pragma unroll
-                    for (int t = 0; t < NA; ++t) {
-                        const int ab = w + W * t;
-                        if (ab >= lo && ab < hi) {
-                            const gp<const float2> hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
-                            float2 h0 = hp[0], h1 = hp[64], h2 = hp[128], h3 = hp[192];
-                            c3mfma(acc, h0, float2{xr[t][0], xq[t][0]});
-                            c3mfma(acc, h1, float2{xr[t][1], xq[t][1]});
-                            c3mfma(acc, h2, float2{xr[t][2], xq[t][2]});
-                            c3mfma(acc, h3, float2{xr[t][3], xq[t][3]});
-                        }
-                    }
+                    for (int m = 0; m < 4; ++m) h[m] = hp[64 * m];
+                    x_quad(c, 16 * ab + 4 * g, x);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) c3mfma(acc, h[m], x[m]);
                 }
             }
             f4 are, aim;
@@ -298,32 +308,33 @@ __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, const float2
     c3_get(acc, pr, pi);
 }
 
-// x <- H^H q (every column), into the registers of the wave's antenna
-// blocks or, without register blocks, into the tile's workspace rows.
-template <int W, int NA>
-__device__ __forceinline__ void form_x(const TileCtx &c, f4 (&xr)[NA ? NA : 1], f4 (&xq)[NA ? NA : 1])
+// x <- H^H q (every column) into the output rows: lane (j, g) of antenna
+// block ab writes antennas 16 ab + 4 g .. + 3 of RHS b0 + j (two 16-byte
+// stores when the row is 32-byte aligned). Ends with a barrier: the residual
+// reads every wave's rows.
+template <int W>
+__device__ __forceinline__ void form_x(const TileCtx &c)
 {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if constexpr (NA == 0) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    const int b = c.b0 + j;
+    const gp<float2> row = c.X + (int64_t)(b < c.nrhs ? b : 0) * c.ldx;
 #pragma unroll 1
-        for (int ab = w; ab < c.nab; ab += W) {
-            f4 qr, qi;
-            agg_block(c, ab, c.L.Q, qr, qi);
-            const gp<float2> xp = c.Xw + (int64_t)ab * 256 + lane;
+    for (int ab = w; ab < c.nab; ab += W) {
+        f4 qr, qi;
+        agg_block(c, ab, c.L.Q, qr, qi);
+        const int n0 = 16 * ab + 4 * g;
+        if (b < c.nrhs) {
+            if (n0 + 3 < c.N && ((reinterpret_cast<uintptr_t>(row + n0) & 31) == 0)) {
+                *(gp<float4>)(row + n0) = float4{qr[0], qi[0], qr[1], qi[1]};
+                *(gp<float4>)(row + n0 + 2) = float4{qr[2], qi[2], qr[3], qi[3]};
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) xp[64 * r] = float2{qr[r], qi[r]};
-        }
-        __syncthreads();   // the residual reads every wave's blocks
-    } else {
-#pragma unroll
-        for (int t = 0; t < NA; ++t) {
-            const int ab = w + W * t;
-            const f4 z = {0.f, 0.f, 0.f, 0.f};
-            xr[t] = z;
-            xq[t] = z;
-            if (ab < c.nab) agg_block(c, ab, c.L.Q, xr[t], xq[t]);
+                for (int r = 0; r < 4; ++r)
+                    if (n0 + r < c.N) row[n0 + r] = float2{qr[r], qi[r]};
+            }
         }
     }
+    __syncthreads();
 }
 
 // Gram work of a wave: with nub <= W, wave w < nparts * nub takes chunk
@@ -388,11 +399,14 @@ __device__ __forceinline__ void gram_group(const TileCtx &c, const float2 *F, in
 // Partial Gram products of the wave's work: the MFMA result (rows
 // 16 mb + 4 g + r, column j) of its chunks of M F goes to the part's slice
 // MP[part] of LDS. Parts are summed by the element-wise pass after a barrier.
+// With fonly, only the groups covering the chunks that hold users of F
+// (listed first) are taken: F is zero on every other row.
 template <int W, int GR>
-__device__ __forceinline__ void gram_part(const TileCtx &c, const float2 *F, const GramRegs<GR> &gr)
+__device__ __forceinline__ void gram_part(const TileCtx &c, const float2 *F, const GramRegs<GR> &gr, bool fonly)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
     auto block = [&](int mb, int g0, int g1, bool regs) {
+        if (fonly) g1 = min(g1, (c.L.gmnf[mb] + 3) / 4);
         C3 acc = c3_zero();
         const int e0 = c.L.gmoff[mb];
         int gg = g0;
@@ -429,6 +443,7 @@ __device__ __forceinline__ void gram_part(const TileCtx &c, const float2 *F, con
 __device__ __forceinline__ float2 gram_sum(const TileCtx &c, int np, int ku, int j)
 {
     float2 s = {0.f, 0.f};
+#pragma unroll 4
     for (int p = 0; p < np; ++p) {
         const float2 v = c.L.MP[((size_t)p * c.kpad + ku) * 16 + j];
         s.x += v.x;
@@ -437,7 +452,7 @@ __device__ __forceinline__ float2 gram_sum(const TileCtx &c, int np, int ku, int
     return s;
 }
 
-template <int W, int NA, int VARIANT>
+template <int W, int EP, int VARIANT>
 __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob, const int tile, char *smem)
 {
     // prob and tile are wave-uniform, so the descriptor is read with scalar loads
@@ -469,7 +484,8 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     c.HA = gmem(static_cast<const float2 *>(d.HA));
     c.HG = gmem(static_cast<const float2 *>(d.HG));
     c.GM = gmem(static_cast<const float2 *>(d.GM));
-    c.Xw = NA == 0 ? gmem(static_cast<float2 *>(d.Xw)) + (int64_t)tile * c.nab * 256 : nullptr;
+    c.X = X;
+    c.ldx = ldx_;
     c.perm = gmem(d.perm);
     c.ag_uc = gmem(d.ag_uc);
     c.gm_c = gmem(d.gm_c);
@@ -479,8 +495,6 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     const int er = tid >> 4;
 
     // ---- init: tables in LDS, then q = 0, r = s (z0 = 0), norms in VR-start order
-    constexpr int NR = NA ? NA : 1;
-    f4 xr[NR], xq[NR];
     for (int ku = tid; ku < kpad; ku += W * 64) {
         L.nrm[ku] = ku < K ? nrm_g[c.perm[ku]] : 1.f;
         L.rsel[ku] = ku < K ? (gmem(d.inf)[c.perm[ku]] ? 1 : 2) : 0;
@@ -489,6 +503,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     for (int i = tid; i <= c.nab; i += W * 64) L.agoff[i] = gmem(d.ag_off)[i];
     for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
     for (int i = tid; i < gmem(d.gm_off)[c.nub]; i += W * 64) L.gmc[i] = max(c.gm_c[i], 0);   // padding: zero tile
+    for (int i = tid; i < c.nub; i += W * 64) L.gmnf[i] = gmem(d.gm_nf)[i];
     for (int i = tid; i < c.nub; i += W * 64) {
         L.rlo[i] = gmem(d.rab_lo)[i];
         L.rhi[i] = gmem(d.rab_hi)[i];
@@ -496,26 +511,38 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     }
     __syncthreads();
     constexpr int variant = VARIANT;
-    // phi for the first step of an iteration from the residual of one entry:
-    // rows of F (VR-OAHK), every row (AHK), none (greedy variants: one-hot)
-    auto phi_first = [&](int ku, float2 rr) -> float2 {
-        const int rs = L.rsel[ku];
-        const bool in = variant == 1 ? rs != 0 : (variant == 3 ? rs == 1 : false);
-        const float inv = in ? 1.f / L.nrm[ku] : 0.f;
-        return float2{rr.x * inv, rr.y * inv};
+    // this thread's entries (ku, j), ku = er + rows_per_pass k: residual,
+    // dual iterate, phi, 1 / ||a_ku||^2 and the F/V selector
+    float2 rr[EP], qq[EP], pp[EP];
+    float ninv[EP];
+    int rs[EP];
+    auto own = [&](int k) { return er + rows_per_pass * k; };
+    // phi for the first step of an iteration: rows of F (VR-OAHK), every
+    // row (AHK), none (greedy variants: one-hot, written by the selection)
+    auto phi_first = [&](int k) -> float2 {
+        const bool in = variant == 1 ? rs[k] != 0 : (variant == 3 ? rs[k] == 1 : false);
+        const float f = in ? ninv[k] : 0.f;
+        return float2{rr[k].x * f, rr[k].y * f};
     };
     ColSums<W> cs{L.red, 0};
     float r2 = 0.f, num = 0.f;
-    for (int ku = er; ku < kpad; ku += rows_per_pass) {
-        float2 sv = {0.f, 0.f};
-        const int b = b0 + j;
-        if (ku < K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + c.perm[ku]];
-        L.R[ku * 16 + j] = sv;
-        L.Q[ku * 16 + j] = float2{0.f, 0.f};
-        const float2 f = phi_first(ku, sv);
-        L.P[ku * 16 + j] = f;
-        r2 += sv.x * sv.x + sv.y * sv.y;
-        num += f.x * sv.x + f.y * sv.y;
+#pragma unroll
+    for (int k = 0; k < EP; ++k) {
+        const int ku = own(k);
+        rr[k] = qq[k] = pp[k] = float2{0.f, 0.f};
+        ninv[k] = 0.f;
+        rs[k] = 0;
+        if (ku < kpad) {
+            const int b = b0 + j;
+            if (ku < K && b < c.nrhs) rr[k] = c.S[(int64_t)b * c.lds + c.perm[ku]];
+            rs[k] = L.rsel[ku];
+            ninv[k] = 1.f / L.nrm[ku];
+            pp[k] = phi_first(k);
+            L.P[ku * 16 + j] = pp[k];
+            L.R[ku * 16 + j] = rr[k];
+            r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
+            num += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
+        }
     }
     {
         const float2 t = cs.sum2(r2, num);
@@ -535,7 +562,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     }
 
     // Gram tiles kept in registers per wave (two VGPRs and a chunk column each)
-    constexpr int GR = W == 8 ? 16 : 8;
+    constexpr int GR = W == 8 ? 16 : 4;
     const int np = c.nub <= W ? gram_parts(c.nub, W) : 1;
     int64_t t_it = 0;
     for (;;) {
@@ -554,9 +581,10 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             if (__ballot(act) == 0) break;   // lanes 0..15 of a wave hold all 16 columns
 
             if constexpr (variant == 0 || variant == 2) {
-                // greedy selection, one wave per column; phi is one-hot with
-                // gamma (P is zero elsewhere). M's sparsity confines the
-                // residual change to the rows of X_pick (Theorem 2).
+                // greedy selection, one wave per column, from the residuals in
+                // LDS; phi is one-hot with gamma (P is zero elsewhere). M's
+                // sparsity confines the residual change to the rows of X_pick
+                // (Theorem 2).
                 for (int cc = w; cc < 16; cc += W) {
                     if (!__shfl(act, cc, 64)) continue;
                     const float u = (float)uniform24(a.seed, t_it, b0 + cc, c.prob);
@@ -576,45 +604,53 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                     }
                 }
                 __syncthreads();
-                gram_part<W, GR>(c, L.P, gr);
+                gram_part<W, GR>(c, L.P, gr, false);
                 __syncthreads();
                 r2 = 0.f;
-                for (int ku = er; ku < kpad; ku += rows_per_pass) {
-                    const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
-                    float2 rr = L.R[ku * 16 + j];
-                    if (act) {
-                        const float2 q = L.Q[ku * 16 + j];
-                        L.Q[ku * 16 + j] = float2{q.x + f.x, q.y + f.y};
-                        rr = float2{rr.x - m.x, rr.y - m.y};
-                        L.R[ku * 16 + j] = rr;
+#pragma unroll
+                for (int k = 0; k < EP; ++k) {
+                    const int ku = own(k);
+                    if (ku < kpad) {
+                        const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
+                        if (act) {
+                            qq[k] = float2{qq[k].x + f.x, qq[k].y + f.y};
+                            rr[k] = float2{rr[k].x - m.x, rr[k].y - m.y};
+                            L.R[ku * 16 + j] = rr[k];
+                        }
+                        L.P[ku * 16 + j] = float2{0.f, 0.f};
+                        r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                     }
-                    L.P[ku * 16 + j] = float2{0.f, 0.f};
-                    r2 += rr.x * rr.x + rr.y * rr.y;
                 }
                 r2 = cs.sum(r2);
             } else if constexpr (variant == 1) {
                 // aggregated step over all rows: phi = P, num known
-                gram_part<W, GR>(c, L.P, gr);
+                gram_part<W, GR>(c, L.P, gr, false);
                 __syncthreads();
                 float den = 0.f;
-                for (int ku = er; ku < kpad; ku += rows_per_pass) {
-                    const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
-                    den += f.x * m.x + f.y * m.y;
+                float2 mk[EP];
+#pragma unroll
+                for (int k = 0; k < EP; ++k) {
+                    mk[k] = float2{0.f, 0.f};
+                    if (own(k) < kpad) {
+                        mk[k] = gram_sum(c, np, own(k), j);
+                        den += pp[k].x * mk[k].x + pp[k].y * mk[k].y;
+                    }
                 }
                 den = cs.sum(den);
                 const float gm = (act && num > 0.f && den > 0.f) ? num / den : 0.f;
                 r2 = 0.f;
                 float nn = 0.f;
-                for (int ku = er; ku < kpad; ku += rows_per_pass) {
-                    const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
-                    const float2 q = L.Q[ku * 16 + j];
-                    const float2 rr = float2{L.R[ku * 16 + j].x - gm * m.x, L.R[ku * 16 + j].y - gm * m.y};
-                    L.Q[ku * 16 + j] = float2{q.x + gm * f.x, q.y + gm * f.y};
-                    L.R[ku * 16 + j] = rr;
-                    const float2 p = phi_first(ku, rr);
-                    L.P[ku * 16 + j] = p;
-                    r2 += rr.x * rr.x + rr.y * rr.y;
-                    nn += p.x * rr.x + p.y * rr.y;
+#pragma unroll
+                for (int k = 0; k < EP; ++k) {
+                    const int ku = own(k);
+                    if (ku < kpad) {
+                        qq[k] = float2{qq[k].x + gm * pp[k].x, qq[k].y + gm * pp[k].y};
+                        rr[k] = float2{rr[k].x - gm * mk[k].x, rr[k].y - gm * mk[k].y};
+                        pp[k] = phi_first(k);
+                        L.P[ku * 16 + j] = pp[k];
+                        r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
+                        nn += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
+                    }
                 }
                 const float2 t = cs.sum2(r2, nn);
                 r2 = t.x;
@@ -623,51 +659,58 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                 // orthogonal half-step on F with gamma = 1 (Prop. 1): q_F += phi_F,
                 // r -= M phi_F; then phi_V of the new residual
                 const bool hasv = d.nv > 0;
-                gram_part<W, GR>(c, L.P, gr);
+                gram_part<W, GR>(c, L.P, gr, true);
                 __syncthreads();
                 float nv_num = 0.f;
                 r2 = 0.f;
-                for (int ku = er; ku < kpad; ku += rows_per_pass) {
-                    const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
-                    float2 rr = L.R[ku * 16 + j];
-                    if (act) {
-                        const float2 q = L.Q[ku * 16 + j];
-                        L.Q[ku * 16 + j] = float2{q.x + f.x, q.y + f.y};
-                        rr = float2{rr.x - m.x, rr.y - m.y};
-                        L.R[ku * 16 + j] = rr;
+#pragma unroll
+                for (int k = 0; k < EP; ++k) {
+                    const int ku = own(k);
+                    if (ku < kpad) {
+                        const float2 m = gram_sum(c, np, ku, j);
+                        if (act) {
+                            qq[k] = float2{qq[k].x + pp[k].x, qq[k].y + pp[k].y};
+                            rr[k] = float2{rr[k].x - m.x, rr[k].y - m.y};
+                        }
+                        // next phi: rows of V for the aggregated step, or, without
+                        // V, rows of F for the next iteration
+                        const float f = rs[k] == (hasv ? 2 : 1) ? ninv[k] : 0.f;
+                        pp[k] = float2{rr[k].x * f, rr[k].y * f};
+                        L.P[ku * 16 + j] = pp[k];
+                        nv_num += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
+                        r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                     }
-                    // next phi: rows of V for the aggregated step, or, without
-                    // V, rows of F for the next iteration
-                    const int rs = L.rsel[ku];
-                    const float inv = rs == (hasv ? 2 : 1) ? 1.f / L.nrm[ku] : 0.f;
-                    const float2 p = float2{rr.x * inv, rr.y * inv};
-                    L.P[ku * 16 + j] = p;
-                    nv_num += p.x * rr.x + p.y * rr.y;
-                    r2 += rr.x * rr.x + rr.y * rr.y;
                 }
                 if (!hasv) {
                     r2 = cs.sum(r2);
                 } else {
                     // aggregated step on V: gamma = phi^H r / phi^H M phi
                     __syncthreads();
-                    gram_part<W, GR>(c, L.P, gr);
+                    gram_part<W, GR>(c, L.P, gr, false);
                     __syncthreads();
                     float den = 0.f;
-                    for (int ku = er; ku < kpad; ku += rows_per_pass) {
-                        const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
-                        den += f.x * m.x + f.y * m.y;
+                    float2 mk[EP];
+#pragma unroll
+                    for (int k = 0; k < EP; ++k) {
+                        mk[k] = float2{0.f, 0.f};
+                        if (own(k) < kpad) {
+                            mk[k] = gram_sum(c, np, own(k), j);
+                            den += pp[k].x * mk[k].x + pp[k].y * mk[k].y;
+                        }
                     }
                     const float2 nd = cs.sum2(nv_num, den);
                     const float gm = (act && nd.x > 0.f && nd.y > 0.f) ? nd.x / nd.y : 0.f;
                     r2 = 0.f;
-                    for (int ku = er; ku < kpad; ku += rows_per_pass) {
-                        const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
-                        const float2 q = L.Q[ku * 16 + j];
-                        const float2 rr = float2{L.R[ku * 16 + j].x - gm * m.x, L.R[ku * 16 + j].y - gm * m.y};
-                        L.Q[ku * 16 + j] = float2{q.x + gm * f.x, q.y + gm * f.y};
-                        L.R[ku * 16 + j] = rr;
-                        L.P[ku * 16 + j] = phi_first(ku, rr);
-                        r2 += rr.x * rr.x + rr.y * rr.y;
+#pragma unroll
+                    for (int k = 0; k < EP; ++k) {
+                        const int ku = own(k);
+                        if (ku < kpad) {
+                            qq[k] = float2{qq[k].x + gm * pp[k].x, qq[k].y + gm * pp[k].y};
+                            rr[k] = float2{rr[k].x - gm * mk[k].x, rr[k].y - gm * mk[k].y};
+                            pp[k] = phi_first(k);
+                            L.P[ku * 16 + j] = pp[k];
+                            r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
+                        }
                     }
                     r2 = cs.sum(r2);
                 }
@@ -675,15 +718,24 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             ++t_it;
         }
         // every column stopped: x = H^H q and the true residual decide
-        form_x<W, NA>(c, xr, xq);
-        tile_residual<W, NA>(c, xr, xq);
+#pragma unroll
+        for (int k = 0; k < EP; ++k)
+            if (own(k) < kpad) L.Q[own(k) * 16 + j] = qq[k];
+        __syncthreads();
+        form_x<W>(c);
+        tile_residual<W>(c);
         float t2 = 0.f, tn = 0.f;
-        for (int ku = er; ku < kpad; ku += rows_per_pass) {
-            const float2 rr = L.R[ku * 16 + j];
-            const float2 p = phi_first(ku, rr);
-            L.P[ku * 16 + j] = p;
-            t2 += rr.x * rr.x + rr.y * rr.y;
-            tn += p.x * rr.x + p.y * rr.y;
+#pragma unroll
+        for (int k = 0; k < EP; ++k) {
+            const int ku = own(k);
+            if (ku < kpad) {
+                rr[k] = L.R[ku * 16 + j];
+                qq[k] = L.Q[ku * 16 + j];   // (q is not held in registers across the pass)
+                pp[k] = phi_first(k);
+                L.P[ku * 16 + j] = pp[k];
+                t2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
+                tn += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
+            }
         }
         {
             const float2 t = cs.sum2(t2, tn);
@@ -704,44 +756,18 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         num = tn;
     }
 
-    // ---- outputs. Each lane holds 4 consecutive antennas of one RHS: two
-    // 16-byte stores when the row is 32-byte aligned, else four 8-byte ones.
+    // ---- outputs: x is in place (form_x); v (or mu) in caller order and in
+    // VR-start order for the gradient products
     {
         const int b = b0 + j;
         if (b < c.nrhs) {
-            const gp<float2> xrow = X + (int64_t)b * ldx_;
-            const bool vec = ((reinterpret_cast<uintptr_t>(xrow) & 31) == 0);
-            auto put4 = [&](int nb, float2 v0, float2 v1, float2 v2, float2 v3) {
-                if (vec && nb + 3 < N) {
-                    const gp<float4> p4 = (gp<float4>)(xrow + nb);
-                    p4[0] = float4{v0.x, v0.y, v1.x, v1.y};
-                    p4[1] = float4{v2.x, v2.y, v3.x, v3.y};
-                } else {
-                    if (nb < N) xrow[nb] = v0;
-                    if (nb + 1 < N) xrow[nb + 1] = v1;
-                    if (nb + 2 < N) xrow[nb + 2] = v2;
-                    if (nb + 3 < N) xrow[nb + 3] = v3;
-                }
-            };
-            if constexpr (NA == 0)
-                for (int ab = w; ab < c.nab; ab += W) {
-                    const gp<const float2> xp = c.Xw + (int64_t)ab * 256 + lane;
-                    put4(16 * ab + 4 * g, xp[0], xp[64], xp[128], xp[192]);
-                }
-#pragma unroll
-            for (int t = 0; t < NA; ++t) {
-                const int nb = 16 * (w + W * t) + 4 * g;
-                put4(nb, float2{xr[t][0], xq[t][0]}, float2{xr[t][1], xq[t][1]}, float2{xr[t][2], xq[t][2]},
-                     float2{xr[t][3], xq[t][3]});
-            }
-            if (V)
-                for (int ku = er; ku < K; ku += rows_per_pass)
-                    V[(int64_t)b * ldv_ + c.perm[ku]] = L.Q[ku * 16 + j];
-            // the same in VR-start order for the gradient products
             const gp<float2> VS = gmem(static_cast<float2 *>(a.adjoint ? d.Msrt : d.Vsrt));
-            if (VS)
-                for (int ku = er; ku < kpad; ku += rows_per_pass)
-                    VS[(int64_t)b * kpad + ku] = L.Q[ku * 16 + j];
+#pragma unroll
+            for (int k = 0; k < EP; ++k) {
+                const int ku = own(k);
+                if (V && ku < K) V[(int64_t)b * ldv_ + c.perm[ku]] = qq[k];
+                if (VS && ku < kpad) VS[(int64_t)b * kpad + ku] = qq[k];
+            }
         }
     }
     if (tid < 16) {
@@ -777,19 +803,19 @@ __device__ __forceinline__ int next_item(const VrkQueue &q, int *sh)
     return item;
 }
 
-template <int W, int NA, int VARIANT, bool PERSIST>
+template <int W, int EP, int VARIANT, bool PERSIST>
 __global__ void __launch_bounds__(W * 64) k_mfma_solve(VrkSolveArgs a, const VrkWork *work, VrkQueue q)
 {
     extern __shared__ __align__(16) char smem[];
     if constexpr (!PERSIST) {
         const VrkWork wk = gmem(work)[blockIdx.x];   // one workgroup per work item
-        solve_item<W, NA, VARIANT>(a, __builtin_amdgcn_readfirstlane(wk.prob),
+        solve_item<W, EP, VARIANT>(a, __builtin_amdgcn_readfirstlane(wk.prob),
                                    __builtin_amdgcn_readfirstlane(wk.tile), smem);
     } else {
         __shared__ int sh_item;
         for (int item = next_item(q, &sh_item); item >= 0; item = next_item(q, &sh_item)) {
             const VrkWork wk = gmem(work)[item];
-            solve_item<W, NA, VARIANT>(a, __builtin_amdgcn_readfirstlane(wk.prob),
+            solve_item<W, EP, VARIANT>(a, __builtin_amdgcn_readfirstlane(wk.prob),
                                        __builtin_amdgcn_readfirstlane(wk.tile), smem);
         }
     }
@@ -801,11 +827,11 @@ __global__ void k_queue_reset(int *count)
 }
 
 // Launch (mode 0), set the LDS attribute and report occupancy (mode 1).
-template <int W, int NA, int VARIANT, bool PERSIST>
+template <int W, int EP, int VARIANT, bool PERSIST>
 hipError_t launch_kernel(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid,
                          size_t lds, hipStream_t s, int mode, int *blocks_per_cu)
 {
-    auto kern = k_mfma_solve<W, NA, VARIANT, PERSIST>;
+    auto kern = k_mfma_solve<W, EP, VARIANT, PERSIST>;
     if (mode == 1) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -817,44 +843,43 @@ hipError_t launch_kernel(const VrkSolveArgs &a, const VrkWork *work, const VrkQu
     return hipGetLastError();
 }
 
-template <int W, int NA, int VARIANT>
+template <int W, int EP, int VARIANT>
 hipError_t launch_one(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid, size_t lds,
                       hipStream_t s, int mode, int *blocks_per_cu)
 {
-    if (q.count) return launch_kernel<W, NA, VARIANT, true>(a, work, q, grid, lds, s, mode, blocks_per_cu);
-    return launch_kernel<W, NA, VARIANT, false>(a, work, q, grid, lds, s, mode, blocks_per_cu);
+    if (q.count) return launch_kernel<W, EP, VARIANT, true>(a, work, q, grid, lds, s, mode, blocks_per_cu);
+    return launch_kernel<W, EP, VARIANT, false>(a, work, q, grid, lds, s, mode, blocks_per_cu);
 }
 
-template <int W, int NA>
+// GRK and VR-OGRK share one kernel: in the dual space the Gram column's
+// sparsity already confines each update to X_pick.
+template <int W, int EP>
 hipError_t launch_variant(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid, size_t lds,
                           hipStream_t s, int mode, int *bpc)
 {
     switch (a.variant) {
-    case 0: return launch_one<W, NA, 0>(a, work, q, grid, lds, s, mode, bpc);
-    case 1: return launch_one<W, NA, 1>(a, work, q, grid, lds, s, mode, bpc);
-    case 2: return launch_one<W, NA, 2>(a, work, q, grid, lds, s, mode, bpc);
-    case 3: return launch_one<W, NA, 3>(a, work, q, grid, lds, s, mode, bpc);
+    case 0:
+    case 2: return launch_one<W, EP, 0>(a, work, q, grid, lds, s, mode, bpc);
+    case 1: return launch_one<W, EP, 1>(a, work, q, grid, lds, s, mode, bpc);
+    case 3: return launch_one<W, EP, 3>(a, work, q, grid, lds, s, mode, bpc);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-// x of one tile lives in registers when it fits: at most 16 antenna blocks
-// per wave with 8 waves (two waves per SIMD) and 8 with 16 waves (four per
-// SIMD), i.e. Nt <= 2048. Larger Nt keeps x in a workspace buffer (NA = 0).
-int vrk_mfma_supported(int32_t kpad, int32_t waves)
+int vrk_mfma_entries(int32_t kpad, int32_t waves)
 {
-    return (waves == 8 || waves == 16) && kpad <= kMaxPass * 4 * waves;
+    if (waves != 8 && waves != 16) return 0;
+    const int need = (kpad + 4 * waves - 1) / (4 * waves);
+    int ep = 1;
+    while (ep < need) ep *= 2;
+    return ep <= kMaxEntries ? ep : 0;
 }
 
-int vrk_mfma_register_na(int32_t nt, int32_t waves)
+int vrk_mfma_supported(int32_t kpad, int32_t waves)
 {
-    const int nab = (nt + VRK_AB - 1) / VRK_AB;
-    const int cap = waves == 8 ? 16 : 8;
-    int na = (nab + waves - 1) / waves, nap = 1;
-    while (nap < na) nap *= 2;
-    return nap <= cap ? nap : 0;
+    return vrk_mfma_entries(kpad, waves) > 0;
 }
 
 size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves)
@@ -863,24 +888,20 @@ size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves)
 }
 
 hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid,
-                                 int32_t waves, int32_t na, size_t lds, hipStream_t s, int mode, int *bpc)
+                                 int32_t waves, int32_t ep, size_t lds, hipStream_t s, int mode, int *bpc)
 {
     if (grid <= 0) return hipSuccess;
-#define VRK_NA_CASES(W)                                                          \
-    switch (na) {                                                                \
+#define VRK_EP_CASES(W)                                                          \
+    switch (ep) {                                                                \
     case 1: return launch_variant<W, 1>(a, work, q, grid, lds, s, mode, bpc);    \
     case 2: return launch_variant<W, 2>(a, work, q, grid, lds, s, mode, bpc);    \
     case 4: return launch_variant<W, 4>(a, work, q, grid, lds, s, mode, bpc);    \
-    case 8: return launch_variant<W, 8>(a, work, q, grid, lds, s, mode, bpc);    \
     }
     if (waves == 8) {
-        if (na == 16) return launch_variant<8, 16>(a, work, q, grid, lds, s, mode, bpc);
-        if (na == 0) return launch_variant<8, 0>(a, work, q, grid, lds, s, mode, bpc);
-        VRK_NA_CASES(8)
+        VRK_EP_CASES(8)
     } else if (waves == 16) {
-        if (na == 0) return launch_variant<16, 0>(a, work, q, grid, lds, s, mode, bpc);
-        VRK_NA_CASES(16)
+        VRK_EP_CASES(16)
     }
-#undef VRK_NA_CASES
+#undef VRK_EP_CASES
     return hipErrorInvalidValue;
 }

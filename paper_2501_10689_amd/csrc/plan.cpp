@@ -67,7 +67,7 @@ struct ProbPlan {
     int32_t ncol = 0;
     // MFMA tables
     int32_t nub = 0, nab = 0, ntile = 0;
-    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, gm_off, gm_c;
+    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, gm_off, gm_c, gm_nf;
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
     // workspace offsets
@@ -75,8 +75,7 @@ struct ProbPlan {
         o_gbusr, o_perm, o_pos, o_nrm, o_fro2, o_rablo, o_rabhi, o_haoff, o_agoff, o_aguc,
         o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
-    size_t o_xw = 0;   // MFMA iterate buffer when x does not fit registers
-    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0;
+    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_gmnf = 0;
 };
 
 }  // namespace
@@ -84,7 +83,7 @@ struct ProbPlan {
 struct vrk_plan {
     vrk_options opt{};
     std::vector<ProbPlan> pp;
-    int32_t engine = VRK_ENGINE_VECTOR, schedule = VRK_SCHED_GATHER, waves = 8, na = 0;
+    int32_t engine = VRK_ENGINE_VECTOR, schedule = VRK_SCHED_GATHER, waves = 8, ep = 0;
     size_t lds = 0;
     size_t table_end = 0, ws_bytes = 0, o_desc = 0, o_work = 0;
     int64_t total_rhs = 0, max_tiles = 0;
@@ -283,13 +282,21 @@ void build_tables(ProbPlan &q)
     q.ag_off[q.nab] = (int32_t)q.ag_uc.size();
     q.n_hg = (int64_t)q.ag_uc.size();
     // Gram blocks (16-user block, 4-user chunk) with any pair of overlapping
-    // VRs or a shared user (the diagonal), in VR-start order
+    // VRs or a shared user (the diagonal), in VR-start order. Per block the
+    // chunks holding a user of F come first, so the orthogonal half-step
+    // (phi nonzero on F only) needs only the groups covering the first
+    // gm_nf entries; the list is padded to groups of 4 chunks, loaded and
+    // multiplied at once (padding chunks, -1, hold zero tiles).
     q.gm_off.assign(q.nub + 1, 0);
+    q.gm_nf.assign(q.nub, 0);
     q.gm_c.clear();
     for (int mb = 0; mb < q.nub; ++mb) {
         q.gm_off[mb] = (int32_t)q.gm_c.size();
+        std::vector<int32_t> with_f, rest;
         for (int uc = 0; uc < nuc; ++uc) {
-            bool any = false;
+            bool any = false, hasf = false;
+            for (int t = 0; t < 4; ++t)
+                if (uc * 4 + t < K && q.inf[q.perm[uc * 4 + t]]) hasf = true;
             for (int i = mb * VRK_UB; i < std::min(K, (mb + 1) * VRK_UB) && !any; ++i)
                 for (int t = 0; t < 4 && !any; ++t) {
                     const int kv = uc * 4 + t;
@@ -297,10 +304,11 @@ void build_tables(ProbPlan &q)
                     const int a = q.perm[i], b = q.perm[kv];
                     any = (a == b) || std::max(q.vs[a], q.vs[b]) < std::min(q.ve[a], q.ve[b]);
                 }
-            if (any) q.gm_c.push_back(uc);
+            if (any) (hasf ? with_f : rest).push_back(uc);
         }
-        // groups of 4 chunks: the solve loads and multiplies a group at once;
-        // padding chunks (-1) hold zero tiles
+        q.gm_nf[mb] = (int32_t)with_f.size();
+        q.gm_c.insert(q.gm_c.end(), with_f.begin(), with_f.end());
+        q.gm_c.insert(q.gm_c.end(), rest.begin(), rest.end());
         while ((q.gm_c.size() - q.gm_off[mb]) % 4) q.gm_c.push_back(-1);
     }
     q.gm_off[q.nub] = (int32_t)q.gm_c.size();
@@ -349,7 +357,6 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     if (o.schedule < 0 || o.schedule > 2) return fail(VRK_EINVAL, "schedule %d", o.schedule);
     if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(VRK_EINVAL, "tol %g", o.tol);
     if (o.max_iters < 1) return fail(VRK_EINVAL, "max_iters must be >= 1");
-    if (o.x_in_workspace != 0 && o.x_in_workspace != 1) return fail(VRK_EINVAL, "x_in_workspace %d", o.x_in_workspace);
     if (o.tile_waves != 0 && o.tile_waves != 8 && o.tile_waves != 16)
         return fail(VRK_EINVAL, "tile_waves %d", o.tile_waves);
     for (int i = 0; i < nprob; ++i) {
@@ -400,7 +407,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         }
     } else {
         int32_t max_nab = (max_nt + VRK_AB - 1) / VRK_AB;
-        pl->na = o.x_in_workspace ? 0 : vrk_mfma_register_na(max_nt, waves);   // 0: iterate in the workspace
+        pl->ep = vrk_mfma_entries(max_kpad, waves);
         pl->lds = vrk_mfma_lds_bytes(max_kpad, max_nab, waves);
         if (pl->lds > 160 * 1024) {
             delete pl;
@@ -490,6 +497,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_aguc = cv.take(4 * q.ag_uc.size());
         q.o_gmoff = cv.take(4 * q.gm_off.size());
         q.o_gmc = cv.take(4 * q.gm_c.size());
+        q.o_gmnf = cv.take(4 * q.gm_nf.size());
     }
     pl->table_end = cv.off;
     for (auto &q : pl->pp) {
@@ -498,7 +506,6 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         if (eng == VRK_ENGINE_MFMA) {
             q.o_ha = cv.take(q.n_ha * 64 * 8);
             q.o_hg = cv.take(q.n_hg * 64 * 8);
-            if (pl->na == 0) q.o_xw = cv.take((size_t)q.ntile * q.nab * 256 * 8);
             q.o_gm = cv.take(q.n_gm * 64 * 8);
             pl->max_tiles = std::max(pl->max_tiles, q.n_gm);
             pl->max_tiles = std::max(pl->max_tiles, std::max(q.n_ha, q.n_hg));
@@ -555,6 +562,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         put(img, q.o_aguc, q.ag_uc);
         put(img, q.o_gmoff, q.gm_off);
         put(img, q.o_gmc, q.gm_c);
+        put(img, q.o_gmnf, q.gm_nf);
         VrkDesc &d = descs[i];
         std::memset(&d, 0, sizeof d);
         const vrk_problem &p = q.p;
@@ -597,9 +605,9 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.ag_uc = (const int32_t *)(base + q.o_aguc);
         d.HA = pl->engine == VRK_ENGINE_MFMA ? base + q.o_ha : nullptr;
         d.HG = pl->engine == VRK_ENGINE_MFMA ? base + q.o_hg : nullptr;
-        d.Xw = (pl->engine == VRK_ENGINE_MFMA && pl->na == 0) ? base + q.o_xw : nullptr;
         d.gm_off = (const int32_t *)(base + q.o_gmoff);
         d.gm_c = (const int32_t *)(base + q.o_gmc);
+        d.gm_nf = (const int32_t *)(base + q.o_gmnf);
         d.GM = pl->engine == VRK_ENGINE_MFMA ? base + q.o_gm : nullptr;
         (void)eb;
     }
@@ -630,7 +638,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         int32_t *qv = reinterpret_cast<int32_t *>(base + pl->o_queue);
         VrkQueue qa{};
         if (pl->persistent) qa = VrkQueue{qv, qv + VRK_NQUEUE, qv + 2 * VRK_NQUEUE};
-        e = vrk_launch_mfma_solve(a, nullptr, qa, 1, pl->waves, pl->na, pl->lds, s, 1, &bpc);
+        e = vrk_launch_mfma_solve(a, nullptr, qa, 1, pl->waves, pl->ep, pl->lds, s, 1, &bpc);
         if (e != hipSuccess) return hip_fail(e, "MFMA kernel attributes");
         int dev = 0, cus = 0;
         e = hipGetDevice(&dev);
@@ -674,7 +682,7 @@ static vrk_status run_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float 
         VrkQueue q{};
         if (pl->persistent) q = VrkQueue{qv, qv + VRK_NQUEUE, qv + 2 * VRK_NQUEUE};
         e = vrk_launch_mfma_solve(a, reinterpret_cast<const VrkWork *>(pl->d_ws + pl->o_work), q, pl->grid,
-                                  pl->waves, pl->na, pl->lds, s, 0, nullptr);
+                                  pl->waves, pl->ep, pl->lds, s, 0, nullptr);
     } else
         e = vrk_launch_vec_solve(a, pl->lds, s);
     if (e != hipSuccess) return hip_fail(e, "solve kernel");
@@ -727,7 +735,7 @@ int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *
     case VRK_Q_XOFF: v = q.xoff; break;
     case VRK_Q_XIDX: v = q.xidx; break;
     case VRK_Q_ENGINE:
-        v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->na, pl->gsplit};
+        v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->ep, pl->gsplit};
         break;
     case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band, (int32_t)q.n_gm}; break;
     default: return -1;
@@ -783,7 +791,7 @@ uint64_t shape_key(const vrk_problem *probs, int32_t nprob, const vrk_options &o
 }
 
 struct Cand {
-    int32_t engine, waves, persistent, schedule, xws;
+    int32_t engine, waves, persistent, schedule;
 };
 
 bool cache_lookup(const char *path, uint64_t key, Cand *c, float *ms)
@@ -797,8 +805,7 @@ bool cache_lookup(const char *path, uint64_t key, Cand *c, float *ms)
         unsigned long long k;
         Cand t;
         float m;
-        if (sscanf(line, "%llx %d %d %d %d %d %f", &k, &t.engine, &t.waves, &t.persistent, &t.schedule, &t.xws,
-                   &m) == 7 &&
+        if (sscanf(line, "%llx %d %d %d %d %f", &k, &t.engine, &t.waves, &t.persistent, &t.schedule, &m) == 6 &&
             (uint64_t)k == key) {
             *c = t;
             *ms = m;
@@ -814,8 +821,8 @@ void cache_store(const char *path, uint64_t key, const Cand &c, float ms)
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%016llx %d %d %d %d %d %.6f\n", (unsigned long long)key, c.engine, c.waves, c.persistent,
-            c.schedule, c.xws, ms);
+    fprintf(f, "%016llx %d %d %d %d %.6f\n", (unsigned long long)key, c.engine, c.waves, c.persistent,
+            c.schedule, ms);
     fclose(f);
 }
 
@@ -825,7 +832,6 @@ void apply(vrk_options &o, const Cand &c)
     o.tile_waves = c.waves;
     o.persistent = c.persistent;
     o.schedule = c.schedule;
-    o.x_in_workspace = c.xws;
 }
 
 }  // namespace
@@ -839,11 +845,10 @@ extern "C" vrk_status vrk_autotune(const vrk_problem *probs, int32_t nprob, vrk_
     std::vector<Cand> cands;
     if (opt->dtype == VRK_C64) {
         for (int w : {8, 16})
-            for (int per : {0, 1}) cands.push_back({VRK_ENGINE_MFMA, w, per, VRK_SCHED_GATHER, 0});
-        cands.push_back({VRK_ENGINE_MFMA, 16, 0, VRK_SCHED_GATHER, 1});
+            for (int per : {0, 1}) cands.push_back({VRK_ENGINE_MFMA, w, per, VRK_SCHED_GATHER});
     }
-    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_GATHER, 0});
-    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_COLOUR, 0});
+    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_GATHER});
+    cands.push_back({VRK_ENGINE_VECTOR, 0, 0, VRK_SCHED_COLOUR});
     // workspace each candidate needs (host-only planning)
     std::vector<size_t> need(cands.size(), 0);
     std::vector<bool> ok(cands.size(), false);

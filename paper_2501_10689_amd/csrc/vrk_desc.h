@@ -50,10 +50,10 @@ struct VrkDesc {
     const int32_t *ag_off, *ag_uc;   // per 16-antenna block: 4-user chunks meeting it (CSR)
     void *HA;                     // residual tiles, 64 complex64 each
     void *HG;                     // aggregation tiles (conjugated), 64 complex64 each
-    void *Xw;                     // iterate of each 16-RHS tile when it does not fit registers:
-                                  // [tile][ab][r][lane] complex64 (MFMA result order)
-    const int32_t *gm_off, *gm_c; // per 16-user block: 4-user chunks with a nonzero Gram block (CSR),
-                                  // padded with -1 (zero tile) to a multiple of 4 per block
+    const int32_t *gm_off, *gm_c; // per 16-user block: 4-user chunks with a nonzero Gram block (CSR):
+                                  // chunks holding a user of F first, then the others, padded
+                                  // with -1 (zero tile) to a multiple of 4
+    const int32_t *gm_nf;         // per 16-user block: its chunks holding a user of F
     void *GM;                     // Gram tiles of H H^H + xi I (VR-start order), 64 complex64 each
     // MFMA engine with adjoint buffers: v of the forward solve and mu of the
     // adjoint solve again, [rhs][nub * 16] complex64 in VR-start user order

@@ -12,9 +12,10 @@ def to_dev(a, dtype):
 
 def run_plan(drops, variant="vr_oahk", select="baiwu", dtype="c64", engine="auto", tol=1e-5,
              max_iters=100000, seed=0, schedule="auto", adjoint_g=None, tile_waves=0,
-             persistent=0, x_in_workspace=0):
+             persistent=0, x_pad=0):
     """drops: list of (H, vs, vl, S, xi) numpy tuples. Returns per-drop dicts
-    with X, V (numpy complex128) and stats, plus the plan."""
+    with X, V (numpy complex128) and stats, plus the plan. x_pad > 0 gives
+    the X rows a stride of Nt + x_pad (a view into a wider buffer)."""
     import torch
     from paper_2501_10689_amd import vrk
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
@@ -23,7 +24,7 @@ def run_plan(drops, variant="vr_oahk", select="baiwu", dtype="c64", engine="auto
         Hd = to_dev(H, tdt)
         Sd = to_dev(np.atleast_2d(S), tdt)
         B = Sd.shape[0]
-        X = torch.full((B, H.shape[1]), float("nan"), dtype=tdt, device="cuda")
+        X = torch.full((B, H.shape[1] + x_pad), float("nan"), dtype=tdt, device="cuda")[:, :H.shape[1]]
         V = torch.full((B, H.shape[0]), float("nan"), dtype=tdt, device="cuda")
         sp = vrk.ProblemSpec(Hd, vs, vl, xi, Sd, X, V)
         if adjoint_g is not None:
@@ -34,7 +35,7 @@ def run_plan(drops, variant="vr_oahk", select="baiwu", dtype="c64", engine="auto
         specs.append(sp)
     o = vrk.options(variant=variant, select=select, dtype=dtype, engine=engine, tol=tol,
                     max_iters=max_iters, seed=seed, schedule=schedule, tile_waves=tile_waves,
-                    persistent=persistent, x_in_workspace=x_in_workspace)
+                    persistent=persistent)
     plan = vrk.Plan(specs, o)
     st = plan.stats_buffers()
     plan.solve(stats=st)

@@ -35,17 +35,23 @@ def test_many_rhs_ragged_tiles(variant, waves):
 
 
 @pytest.mark.parametrize("nt,k,nrhs", [(1000, 20, 21), (200, 16, 16), (512, 37, 33), (2048, 128, 17),
-                                       (64, 100, 16), (1536, 5, 48)])
+                                       (64, 100, 16), (1536, 5, 48), (1001, 24, 19)])
 @pytest.mark.parametrize("variant", ["grk", "vr_oahk", "ahk"])
-@pytest.mark.parametrize("waves,xws", [(8, 0), (16, 0), (16, 1)])
-def test_shapes_padding(nt, k, nrhs, variant, waves, xws):
-    """Nt not a multiple of 16, K not a multiple of 16, K > Nt, tiny K; the
-    iterate in registers (8 or 16 waves) or in the workspace."""
+@pytest.mark.parametrize("waves,x_pad", [(8, 0), (16, 0), (16, 3)])
+def test_shapes_padding(nt, k, nrhs, variant, waves, x_pad):
+    """Nt not a multiple of 16, K not a multiple of 16, K > Nt, tiny K, X
+    rows not 32-byte aligned (Nt 1001, or a row stride of Nt + 3); 1, 2 or 4
+    (row, column) entries per thread."""
     rng = np.random.default_rng(nt + k)
     H, vs, vl, xi = random_problem(rng, nt, k, lo=max(1, nt // 8), hi=max(1, nt // 2))
     S = qpsk(rng, (nrhs, k))
-    res, _ = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="mfma", tol=1e-5,
-                      tile_waves=waves, x_in_workspace=xws)
+    res, plan = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="mfma", tol=1e-5,
+                         tile_waves=waves, x_pad=x_pad)
+    kpad = -(-k // 16) * 16
+    ep = 1
+    while ep * 4 * waves < kpad:
+        ep *= 2
+    assert plan.query(0, 5)[6] == ep
     X, _ = oracle.rzf(H, vs, vl, S, xi)
     g = res[0]
     assert np.all(g["flags"] == oracle.F_CONVERGED), g["flags"]
@@ -182,13 +188,13 @@ def test_adjoint_mfma_uneven_batch():
 
 
 @pytest.mark.parametrize("variant", ["vr_oahk", "ahk", "grk", "vr_ogrk"])
-def test_large_shape_workspace_iterate(variant):
-    """Nt 4096, K 256 (VR U[256, 1024], 16-QAM): the iterate of a tile does
-    not fit registers and lives in the workspace; 2 drops x 40 vectors."""
+def test_large_shape(variant):
+    """Nt 4096, K 256 (VR U[256, 1024], 16-QAM): four (row, column) entries
+    per thread with 16 waves; 2 drops x 40 vectors."""
     ds = synth.make_workload("large", drops=2, nrhs=40)
     drops = [(d.H, d.vr_start, d.vr_len, d.S, d.xi) for d in ds]
     res, plan = run_plan(drops, variant=variant, engine="mfma", tol=1e-5)
-    assert plan.query(0, 5)[6] == 0
+    assert plan.query(0, 5)[6] == 4
     for jd, (H, vs, vl, S, xi) in enumerate(drops):
         X, _ = oracle.rzf(H, vs, vl, S, xi)
         assert np.all(res[jd]["flags"] == oracle.F_CONVERGED), (variant, jd)
