@@ -67,11 +67,10 @@ __device__ __forceinline__ void c3_get(const C3 &acc, f4 &re, f4 &im)
 }
 
 struct MfmaLds {
-    float2 *R, *Q, *Rp, *P, *MP;   // P and MP share the space of Rp (never live together);
-                                   // MP holds one partial Gram product per chunk part
+    float2 *R, *Q, *P, *MP;   // MP: one partial product (Gram or H x) per part
     float *nrm, *pre, *red;
     int *posl;
-    int *agoff, *rlo, *rhi, *hoff, *gmoff;   // copies of the tile tables of this problem
+    int *agoff, *gmoff;   // copies of the tile tables of this problem
     int *gmc;    // copy of the Gram chunk columns (at most nub * kpad / 4)
     int *gmnf;   // per row block: Gram chunks holding a user of F (a multiple of 4)
     int *rsel;   // per sorted row: 1 user of F, 2 user of V, 0 padding
@@ -98,15 +97,15 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         off += (bytes + 15) & ~size_t(15);
         return base ? base + o : nullptr;
     };
-    const size_t rp = (size_t)W * VRK_RGROUP * 16, pm = (size_t)(1 + gram_parts(kpad / 16, W)) * kpad * 16;
+    const size_t pm = (size_t)(1 + gram_parts(kpad / 16, W)) * kpad * 16;
     char *R = take((size_t)kpad * 16 * 8);
     char *Q = take((size_t)kpad * 16 * 8);
-    char *Rp = take((rp > pm ? rp : pm) * 8);
+    char *PM = take(pm * 8);
     char *nrm = take((size_t)kpad * 4);
     char *pre = take((size_t)W * kpad * 4);
     char *red = take((size_t)4 * W * 16 * 4);
     char *posl = take((size_t)kpad * 4);
-    char *tabs = take((size_t)(nab + 1 + 4 * (kpad / 16) + 1) * 4);
+    char *tabs = take((size_t)(nab + 1 + kpad / 16 + 1) * 4);
     char *gmc = take((size_t)(kpad / 16) * (kpad / 4 + 8) * 4);
     char *gmnf = take((size_t)(kpad / 16) * 4);
     char *rsel = take((size_t)kpad * 4);
@@ -115,18 +114,14 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
     if (base) {
         int *tb = (int *)tabs;
         L->agoff = tb;
-        L->rlo = tb + nab + 1;
-        L->rhi = L->rlo + kpad / 16;
-        L->hoff = L->rhi + kpad / 16;
-        L->gmoff = L->hoff + kpad / 16;
+        L->gmoff = tb + nab + 1;
         L->gmc = (int *)gmc;
         L->gmnf = (int *)gmnf;
         L->rsel = (int *)rsel;
         L->R = (float2 *)R;
         L->Q = (float2 *)Q;
-        L->Rp = (float2 *)Rp;
-        L->P = (float2 *)Rp;
-        L->MP = (float2 *)Rp + (size_t)kpad * 16;
+        L->P = (float2 *)PM;
+        L->MP = (float2 *)PM + (size_t)kpad * 16;
         L->nrm = (float *)nrm;
         L->pre = (float *)pre;
         L->red = (float *)red;
@@ -196,7 +191,7 @@ using gp = VRK_GLOBAL T *;
 
 struct TileCtx {
     MfmaLds L;
-    gp<const float2> S, HA, HG, GM;
+    gp<const float2> S, HG, GM;
     gp<float2> X;   // output rows of this tile's RHS (x = H^H q)
     gp<const int32_t> perm, ag_uc, gm_c;
     int64_t lds, ldx;
@@ -204,89 +199,8 @@ struct TileCtx {
     float xi;
 };
 
-// Four consecutive antennas n0 .. n0 + 3 of x for RHS b0 + j from the output
-// rows (zero past N and for RHS beyond the batch).
-__device__ __forceinline__ void x_quad(const TileCtx &c, int n0, float2 (&x)[4])
-{
-    const int b = c.b0 + (threadIdx.x & 15);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) x[m] = float2{0.f, 0.f};
-    if (b >= c.nrhs) return;
-    const gp<const float2> row = c.X + (int64_t)b * c.ldx;
-    if (n0 + 3 < c.N && ((reinterpret_cast<uintptr_t>(row + n0) & 31) == 0)) {
-        const float4 a = *(gp<const float4>)(row + n0), e = *(gp<const float4>)(row + n0 + 2);
-        x[0] = float2{a.x, a.y};
-        x[1] = float2{a.z, a.w};
-        x[2] = float2{e.x, e.y};
-        x[3] = float2{e.z, e.w};
-    } else {
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            if (n0 + m < c.N) x[m] = row[n0 + m];
-    }
-}
-
-// R <- s - H x - xi q (rows in VR-start order), x from the output rows, two
-// 16-user blocks at a time with a deterministic cross-wave reduction through
-// LDS (buffer Rp). Every wave's x rows must be written (a barrier after form_x).
-template <int W>
-__device__ __forceinline__ void tile_residual(const TileCtx &c)
-{
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
-    const int nug = (c.nub + 1) / 2;
-    const int er = tid >> 4, rows_per_pass = W * 4;
-#pragma unroll 1
-    for (int gi = 0; gi < nug; ++gi) {
-#pragma unroll 1
-        for (int u2 = 0; u2 < 2; ++u2) {
-            const int ub = gi * 2 + u2;
-            C3 acc = c3_zero();
-            if (ub < c.nub) {
-                const int lo = c.L.rlo[ub], hi = c.L.rhi[ub];
-                const int64_t hb = c.L.hoff[ub];
-                // the wave's blocks w, w + W, ... inside [lo, hi)
-                int ab = lo + ((w - lo) % W + W) % W;
-#pragma unroll 1
-                for (; ab < hi; ab += W) {
-                    const gp<const float2> hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
-                    float2 h[4], x[4];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) h[m] = hp[64 * m];
-                    x_quad(c, 16 * ab + 4 * g, x);
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) c3mfma(acc, h[m], x[m]);
-                }
-            }
-            f4 are, aim;
-            c3_get(acc, are, aim);
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                c.L.Rp[(w * VRK_RGROUP + u2 * 16 + 4 * g + r) * 16 + j] = float2{are[r], aim[r]};
-        }
-        __syncthreads();
-        for (int uu = er; uu < VRK_RGROUP; uu += rows_per_pass) {
-            const int ku = gi * VRK_RGROUP + uu;
-            if (ku < c.kpad) {
-                float sr = 0.f, si = 0.f;
-#pragma unroll
-                for (int ww = 0; ww < W; ++ww) {
-                    float2 p = c.L.Rp[(ww * VRK_RGROUP + uu) * 16 + j];
-                    sr += p.x;
-                    si += p.y;
-                }
-                float2 sv = {0.f, 0.f};
-                const int b = c.b0 + j;
-                if (ku < c.K && b < c.nrhs) sv = c.S[(int64_t)b * c.lds + c.perm[ku]];
-                float2 q = c.L.Q[ku * 16 + j];
-                c.L.R[ku * 16 + j] = float2{sv.x - sr - c.xi * q.x, sv.y - si - c.xi * q.y};
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // H^H F on antenna block ab (F in LDS, [row][16]): chunks e of that block's
-// list, two at a time so the loads of one pair overlap the MFMAs of the other.
+// list, four at a time so that their loads are in flight together.
 __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, const float2 *F, f4 &pr, f4 &pi)
 {
     const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
@@ -294,24 +208,24 @@ __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, const float2
     const int e0 = c.L.agoff[ab], e1 = c.L.agoff[ab + 1];
     int e = e0;
 #pragma unroll 1
-    for (; e + 1 < e1; e += 2) {
-        const int uc0 = c.ag_uc[e], uc1 = c.ag_uc[e + 1];
-        float2 h0 = c.HG[(int64_t)e * 64 + lane], h1 = c.HG[(int64_t)(e + 1) * 64 + lane];
-        float2 f0 = F[(4 * uc0 + g) * 16 + j], f1 = F[(4 * uc1 + g) * 16 + j];
-        c3mfma(acc, h0, f0);
-        c3mfma(acc, h1, f1);
+    for (; e + 3 < e1; e += 4) {
+        float2 h[4], f[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            h[i] = c.HG[(int64_t)(e + i) * 64 + lane];
+            f[i] = F[(4 * c.ag_uc[e + i] + g) * 16 + j];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c3mfma(acc, h[i], f[i]);
     }
-    if (e < e1) {
-        const int uc = c.ag_uc[e];
-        c3mfma(acc, c.HG[(int64_t)e * 64 + lane], F[(4 * uc + g) * 16 + j]);
-    }
+#pragma unroll 1
+    for (; e < e1; ++e) c3mfma(acc, c.HG[(int64_t)e * 64 + lane], F[(4 * c.ag_uc[e] + g) * 16 + j]);
     c3_get(acc, pr, pi);
 }
 
 // x <- H^H q (every column) into the output rows: lane (j, g) of antenna
 // block ab writes antennas 16 ab + 4 g .. + 3 of RHS b0 + j (two 16-byte
-// stores when the row is 32-byte aligned). Ends with a barrier: the residual
-// reads every wave's rows.
+// stores when the row is 32-byte aligned).
 template <int W>
 __device__ __forceinline__ void form_x(const TileCtx &c)
 {
@@ -334,7 +248,6 @@ __device__ __forceinline__ void form_x(const TileCtx &c)
             }
         }
     }
-    __syncthreads();
 }
 
 // Gram work of a wave: with nub <= W, wave w < nparts * nub takes chunk
@@ -481,7 +394,6 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         X = gmem(static_cast<float2 *>(d.X)); ldx_ = d.ldx;
         V = gmem(static_cast<float2 *>(d.V)); ldv_ = d.ldv;
     }
-    c.HA = gmem(static_cast<const float2 *>(d.HA));
     c.HG = gmem(static_cast<const float2 *>(d.HG));
     c.GM = gmem(static_cast<const float2 *>(d.GM));
     c.X = X;
@@ -504,11 +416,6 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
     for (int i = tid; i < gmem(d.gm_off)[c.nub]; i += W * 64) L.gmc[i] = max(c.gm_c[i], 0);   // padding: zero tile
     for (int i = tid; i < c.nub; i += W * 64) L.gmnf[i] = gmem(d.gm_nf)[i];
-    for (int i = tid; i < c.nub; i += W * 64) {
-        L.rlo[i] = gmem(d.rab_lo)[i];
-        L.rhi[i] = gmem(d.rab_hi)[i];
-        L.hoff[i] = (int)gmem(d.ha_off)[i];
-    }
     __syncthreads();
     constexpr int variant = VARIANT;
     // this thread's entries (ku, j), ku = er + rows_per_pass k: residual,
@@ -717,20 +624,26 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             }
             ++t_it;
         }
-        // every column stopped: x = H^H q and the true residual decide
+        // every column stopped: x = H^H q goes out, and the residual
+        // s - A A^H q = s - M q, evaluated afresh from q (free of the drift
+        // of the maintained residual), decides
 #pragma unroll
         for (int k = 0; k < EP; ++k)
             if (own(k) < kpad) L.Q[own(k) * 16 + j] = qq[k];
         __syncthreads();
         form_x<W>(c);
-        tile_residual<W>(c);
+        gram_part<W, GR>(c, L.Q, gr, false);
+        __syncthreads();
         float t2 = 0.f, tn = 0.f;
 #pragma unroll
         for (int k = 0; k < EP; ++k) {
             const int ku = own(k);
             if (ku < kpad) {
-                rr[k] = L.R[ku * 16 + j];
-                qq[k] = L.Q[ku * 16 + j];   // (q is not held in registers across the pass)
+                const float2 mq = gram_sum(c, np, ku, j);
+                float2 sv = {0.f, 0.f};
+                if (ku < K && b0 + j < c.nrhs) sv = c.S[(int64_t)(b0 + j) * c.lds + c.perm[ku]];
+                rr[k] = float2{sv.x - mq.x, sv.y - mq.y};
+                if (variant == 0 || variant == 2) L.R[ku * 16 + j] = rr[k];
                 pp[k] = phi_first(k);
                 L.P[ku * 16 + j] = pp[k];
                 t2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;

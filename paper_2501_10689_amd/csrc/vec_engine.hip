@@ -114,23 +114,24 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
     if (t < n_gm) {
         // Gram tile e of user block mb: lane l = i + 16 kk holds
         // M[perm[16 mb + i], perm[4 c + kk]] = sum over the overlap of
-        // H[u, n] conj(H[v, n]) (+ xi on the diagonal)
+        // H[u, n] conj(H[v, n]) (+ xi on the diagonal), accumulated in
+        // double and rounded once
         int mb = 0;
         while (d.gm_off[mb + 1] <= t) ++mb;
         const int uc = d.gm_c[t];   // -1: padding chunk, zero tile
         const int ku = mb * VRK_UB + i, kv = uc * 4 + kk;
-        float ar = 0.f, ai = 0.f;
+        double ar = 0.0, ai = 0.0;
         if (uc >= 0 && ku < d.k && kv < d.k) {
             const int u = d.perm[ku], v2 = d.perm[kv];
             const int lo = max(d.vs[u], d.vs[v2]), hi = min(d.ve[u], d.ve[v2]);
             for (int n = lo; n < hi; ++n) {
                 cx<float> a = H[(int64_t)u * d.ldh + n], b = H[(int64_t)v2 * d.ldh + n];
-                ar += a.re * b.re + a.im * b.im;
-                ai += a.im * b.re - a.re * b.im;
+                ar += (double)a.re * b.re + (double)a.im * b.im;
+                ai += (double)a.im * b.re - (double)a.re * b.im;
             }
-            if (u == v2) ar += (float)d.xi;
+            if (u == v2) ar += d.xi;
         }
-        reinterpret_cast<cx<float> *>(d.GM)[t * 64 + lane] = cx<float>{ar, ai};
+        reinterpret_cast<cx<float> *>(d.GM)[t * 64 + lane] = cx<float>{(float)ar, (float)ai};
     }
 }
 
