@@ -70,17 +70,46 @@ def algorithmic_flops(engine, variant, band, band_f, band_v, overlap, iters, vec
     products over the users' overlap sets, sum_i |X_i| = `overlap` complex
     multiply-adds for the aggregated variants (the F and V columns of M),
     |X_pick| (on average overlap / K) for the greedy ones; once per vector
-    x = H^H q and the true residual, 2 * band.
+    x = H^H q (band) and the fresh residual s - M q (overlap).
 
     `iters` = sum over vectors of the iterations each vector made."""
     if engine == "mfma":
         per_it = overlap / k if variant in ("grk", "vr_ogrk") else overlap
-        return 8.0 * (iters * per_it + vectors * 2.0 * band)
+        return 8.0 * (iters * per_it + vectors * (band + overlap))
     if variant in ("grk", "vr_ogrk"):
         return iters * 8.0 * band * (1.0 + 1.0 / k)
     if variant == "ahk":
         return iters * 16.0 * band
     return iters * 8.0 * (band + band_f + 2.0 * band_v)
+
+
+# Kernel sources whose rocprofv3 counters the committed traffic files hold.
+TRAFFIC_SOURCES = ["paper_2501_10689_amd/csrc/mfma_engine.hip", "paper_2501_10689_amd/csrc/device_common.h",
+                   "paper_2501_10689_amd/csrc/vrk_desc.h", "paper_2501_10689_amd/csrc/kernels.h"]
+
+
+def measured_traffic(workload, kernel_prefix):
+    """HBM bytes per launch of the solve kernel from profiles/traffic_solve_<workload>.txt
+    (FETCH_SIZE and WRITE_SIZE per dispatch scaled by a plain copy's reading), or None
+    when there is no such file, it covers another kernel instantiation, or the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "traffic_solve_%s.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("source_sha256") != h.hexdigest() or not kv.get("kernel", "").startswith(kernel_prefix):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def main():
@@ -197,6 +226,10 @@ def main():
         peak = PEAK_VALU_F64 if c128 else PEAK_VALU_F32
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+    if engine == "mfma":
+        vid = {"grk": 0, "vr_ogrk": 0, "ahk": 1, "vr_oahk": 3}[args.variant]
+        roof["traffic"] = measured_traffic(wl, "void (anonymous namespace)::k_mfma_solve<%d, %d, %d, %s>" % (
+            int(eng[2]), int(eng[6]), vid, "true" if int(eng[4]) else "false"))
     roof["kernel"] = "solve (%s engine, %s)" % (engine, args.variant)
     roof["kernel_ms"] = solve_ms
     roof["flops_per_launch"] = flops
