@@ -33,11 +33,11 @@ hipError_t vrk_prepare_vec_solve(int32_t dtype, size_t lds_bytes);   // LDS attr
 hipError_t vrk_launch_vec_solve(const VrkSolveArgs &a, size_t lds_bytes, hipStream_t s);
 
 // MFMA engine: 16 right-hand sides per workgroup (complex64).
-// 8 or 16 waves per tile, at most 32 users per wave (kpad: K rounded up to 16).
+// 8 or 16 waves per tile, at most 16 users per wave (kpad: K rounded up to 16).
 int vrk_mfma_supported(int32_t kpad, int32_t waves);
 // (row, column) entries per thread of the solve (1, 2 or 4), 0 if unsupported.
 int vrk_mfma_entries(int32_t kpad, int32_t waves);
-size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves);
+size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves, int32_t greedy, int32_t nmf);
 // mode 0 launches (grid = work items, or the persistent grid when q.count is
 // set); mode 1 only sets the kernel's LDS attribute and writes its resident
 // workgroups per CU to *blocks_per_cu (called once at bind, never during

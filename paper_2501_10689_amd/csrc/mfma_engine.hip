@@ -67,7 +67,12 @@ __device__ __forceinline__ void c3_get(const C3 &acc, f4 &re, f4 &im)
 }
 
 struct MfmaLds {
-    float2 *R, *Q, *P, *MP;   // MP: one partial product (Gram or H x) per part
+    float2 *R;    // residual (greedy variants: the selection reads every row)
+    float2 *PF;   // phi of the first step of an iteration (F rows, all rows, or one-hot)
+    float2 *PV;   // phi of the aggregated V step; q at the confirm pass
+    float2 *MP;   // one partial Gram product per part
+    int *fpos;    // VALU half-step: sorted positions of the users of F
+    float2 *MF;   // VALU half-step: the F columns of M, [row][f]
     float *nrm, *pre, *red;
     int *posl;
     int *agoff, *gmoff;   // copies of the tile tables of this problem
@@ -89,7 +94,8 @@ __host__ __device__ inline int gram_parts(int nub, int W)
     return nub <= W ? W / nub : 1;
 }
 
-__host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char *base, MfmaLds *L)
+__host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, bool greedy, int nmf, char *base,
+                                                  MfmaLds *L)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -97,18 +103,21 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         off += (bytes + 15) & ~size_t(15);
         return base ? base + o : nullptr;
     };
-    const size_t pm = (size_t)(1 + gram_parts(kpad / 16, W)) * kpad * 16;
-    char *R = take((size_t)kpad * 16 * 8);
-    char *Q = take((size_t)kpad * 16 * 8);
-    char *PM = take(pm * 8);
+    const size_t tile = (size_t)kpad * 16 * 8;
+    char *R = take(greedy ? tile : 0);
+    char *PF = take(tile);
+    char *PV = take(tile);
+    char *MP = take(tile * gram_parts(kpad / 16, W));
     char *nrm = take((size_t)kpad * 4);
-    char *pre = take((size_t)W * kpad * 4);
+    char *pre = take(greedy ? (size_t)W * kpad * 4 : 0);
     char *red = take((size_t)4 * W * 16 * 4);
     char *posl = take((size_t)kpad * 4);
     char *tabs = take((size_t)(nab + 1 + kpad / 16 + 1) * 4);
     char *gmc = take((size_t)(kpad / 16) * (kpad / 4 + 8) * 4);
     char *gmnf = take((size_t)(kpad / 16) * 4);
     char *rsel = take((size_t)kpad * 4);
+    char *fpos = take(16 * 4);
+    char *mf = take((size_t)kpad * nmf * 8);
     // test the LDS base, not L: L points into a caller's register-resident
     // struct, and comparing its address would pin that struct to memory
     if (base) {
@@ -117,15 +126,17 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, char
         L->gmoff = tb + nab + 1;
         L->gmc = (int *)gmc;
         L->gmnf = (int *)gmnf;
-        L->rsel = (int *)rsel;
         L->R = (float2 *)R;
-        L->Q = (float2 *)Q;
-        L->P = (float2 *)PM;
-        L->MP = (float2 *)PM + (size_t)kpad * 16;
+        L->PF = (float2 *)PF;
+        L->PV = (float2 *)PV;
+        L->MP = (float2 *)MP;
         L->nrm = (float *)nrm;
         L->pre = (float *)pre;
         L->red = (float *)red;
         L->posl = (int *)posl;
+        L->rsel = (int *)rsel;
+        L->fpos = (int *)fpos;
+        L->MF = (float2 *)mf;
     }
     return off;
 }
@@ -235,7 +246,7 @@ __device__ __forceinline__ void form_x(const TileCtx &c)
 #pragma unroll 1
     for (int ab = w; ab < c.nab; ab += W) {
         f4 qr, qi;
-        agg_block(c, ab, c.L.Q, qr, qi);
+        agg_block(c, ab, c.L.PV, qr, qi);   // q, staged in PV
         const int n0 = 16 * ab + 4 * g;
         if (b < c.nrhs) {
             if (n0 + 3 < c.N && ((reinterpret_cast<uintptr_t>(row + n0) & 31) == 0)) {
@@ -313,11 +324,15 @@ __device__ __forceinline__ void gram_group(const TileCtx &c, const float2 *F, in
 // 16 mb + 4 g + r, column j) of its chunks of M F goes to the part's slice
 // MP[part] of LDS. Parts are summed by the element-wise pass after a barrier.
 // With fonly, only the groups covering the chunks that hold users of F
-// (listed first) are taken: F is zero on every other row.
+// (listed first) are taken: F is zero on every other row. Returns the
+// lane's share of F^H (M F) for its column (0 unless with_den), so the
+// column sum of the returns over the workgroup is phi^H M phi.
 template <int W, int GR>
-__device__ __forceinline__ void gram_part(const TileCtx &c, const float2 *F, const GramRegs<GR> &gr, bool fonly)
+__device__ __forceinline__ float gram_part(const TileCtx &c, const float2 *F, const GramRegs<GR> &gr, bool fonly,
+                                           bool with_den)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    float den = 0.f;
     auto block = [&](int mb, int g0, int g1, bool regs) {
         if (fonly) g1 = min(g1, (c.L.gmnf[mb] + 3) / 4);
         C3 acc = c3_zero();
@@ -341,7 +356,14 @@ __device__ __forceinline__ void gram_part(const TileCtx &c, const float2 *F, con
         c3_get(acc, mr, mi);
         float2 *out = c.L.MP + (size_t)(regs ? gr.part : 0) * c.kpad * 16;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) out[(16 * mb + 4 * g + r) * 16 + j] = float2{mr[r], mi[r]};
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * mb + 4 * g + r;
+            out[row * 16 + j] = float2{mr[r], mi[r]};
+            if (with_den) {
+                const float2 f = F[row * 16 + j];
+                den += f.x * mr[r] + f.y * mi[r];
+            }
+        }
     };
     if (c.nub <= W) {
         if (gr.mb >= 0) block(gr.mb, gr.g0, gr.g1, true);
@@ -350,6 +372,7 @@ __device__ __forceinline__ void gram_part(const TileCtx &c, const float2 *F, con
         for (int mb = w; mb < c.nub; mb += W)
             block(mb, 0, (c.L.gmoff[mb + 1] - c.L.gmoff[mb]) / 4, mb == w);
     }
+    return den;
 }
 
 // Sum of the partial Gram products at entry (ku, j).
@@ -381,7 +404,9 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     c.xi = (float)d.xi;
     c.b0 = tile * VRK_TILE_RHS;
     c.nrhs = d.nrhs;
-    mfma_lds_layout(c.kpad, c.nab, W, smem, &c.L);
+    constexpr int variant = VARIANT;
+    constexpr bool greedy = variant == 0 || variant == 2;
+    mfma_lds_layout(c.kpad, c.nab, W, greedy, d.nmf, smem, &c.L);
     const MfmaLds &L = c.L;
     gp<float2> X, V;
     int64_t ldx_, ldv_;
@@ -416,8 +441,10 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
     for (int i = tid; i < gmem(d.gm_off)[c.nub]; i += W * 64) L.gmc[i] = max(c.gm_c[i], 0);   // padding: zero tile
     for (int i = tid; i < c.nub; i += W * 64) L.gmnf[i] = gmem(d.gm_nf)[i];
+    const int nmf = d.nmf;   // > 0: VALU orthogonal half-step from MF
+    if (tid < nmf) L.fpos[tid] = gmem(d.fpos)[tid];
+    for (int i = tid; i < kpad * nmf; i += W * 64) L.MF[i] = gmem(static_cast<const float2 *>(d.MF))[i];
     __syncthreads();
-    constexpr int variant = VARIANT;
     // this thread's entries (ku, j), ku = er + rows_per_pass k: residual,
     // dual iterate, phi, 1 / ||a_ku||^2 and the F/V selector
     float2 rr[EP], qq[EP], pp[EP];
@@ -445,8 +472,8 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             rs[k] = L.rsel[ku];
             ninv[k] = 1.f / L.nrm[ku];
             pp[k] = phi_first(k);
-            L.P[ku * 16 + j] = pp[k];
-            L.R[ku * 16 + j] = rr[k];
+            L.PF[ku * 16 + j] = pp[k];
+            if (greedy) L.R[ku * 16 + j] = rr[k];
             r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
             num += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
         }
@@ -487,9 +514,9 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             }
             if (__ballot(act) == 0) break;   // lanes 0..15 of a wave hold all 16 columns
 
-            if constexpr (variant == 0 || variant == 2) {
+            if constexpr (greedy) {
                 // greedy selection, one wave per column, from the residuals in
-                // LDS; phi is one-hot with gamma (P is zero elsewhere). M's
+                // LDS; phi is one-hot with gamma (PF is zero elsewhere). M's
                 // sparsity confines the residual change to the rows of X_pick
                 // (Theorem 2).
                 for (int cc = w; cc < 16; cc += W) {
@@ -507,43 +534,32 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                         const int ku = L.posl[i];
                         const float inv = 1.f / L.nrm[ku];
                         const float2 r = L.R[ku * 16 + cc];
-                        L.P[ku * 16 + cc] = float2{r.x * inv, r.y * inv};
+                        L.PF[ku * 16 + cc] = float2{r.x * inv, r.y * inv};
                     }
                 }
                 __syncthreads();
-                gram_part<W, GR>(c, L.P, gr, false);
+                gram_part<W, GR>(c, L.PF, gr, false, false);
                 __syncthreads();
                 r2 = 0.f;
 #pragma unroll
                 for (int k = 0; k < EP; ++k) {
                     const int ku = own(k);
                     if (ku < kpad) {
-                        const float2 m = gram_sum(c, np, ku, j), f = L.P[ku * 16 + j];
+                        const float2 m = gram_sum(c, np, ku, j), f = L.PF[ku * 16 + j];
                         if (act) {
                             qq[k] = float2{qq[k].x + f.x, qq[k].y + f.y};
                             rr[k] = float2{rr[k].x - m.x, rr[k].y - m.y};
                             L.R[ku * 16 + j] = rr[k];
                         }
-                        L.P[ku * 16 + j] = float2{0.f, 0.f};
+                        L.PF[ku * 16 + j] = float2{0.f, 0.f};
                         r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                     }
                 }
                 r2 = cs.sum(r2);
             } else if constexpr (variant == 1) {
-                // aggregated step over all rows: phi = P, num known
-                gram_part<W, GR>(c, L.P, gr, false);
-                __syncthreads();
-                float den = 0.f;
-                float2 mk[EP];
-#pragma unroll
-                for (int k = 0; k < EP; ++k) {
-                    mk[k] = float2{0.f, 0.f};
-                    if (own(k) < kpad) {
-                        mk[k] = gram_sum(c, np, own(k), j);
-                        den += pp[k].x * mk[k].x + pp[k].y * mk[k].y;
-                    }
-                }
-                den = cs.sum(den);
+                // aggregated step over all rows: phi = PF, num known; the
+                // Gram waves add phi^H M phi as they go
+                const float den = cs.sum(gram_part<W, GR>(c, L.PF, gr, false, true));
                 const float gm = (act && num > 0.f && den > 0.f) ? num / den : 0.f;
                 r2 = 0.f;
                 float nn = 0.f;
@@ -551,10 +567,11 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                 for (int k = 0; k < EP; ++k) {
                     const int ku = own(k);
                     if (ku < kpad) {
+                        const float2 m = gram_sum(c, np, ku, j);
                         qq[k] = float2{qq[k].x + gm * pp[k].x, qq[k].y + gm * pp[k].y};
-                        rr[k] = float2{rr[k].x - gm * mk[k].x, rr[k].y - gm * mk[k].y};
+                        rr[k] = float2{rr[k].x - gm * m.x, rr[k].y - gm * m.y};
                         pp[k] = phi_first(k);
-                        L.P[ku * 16 + j] = pp[k];
+                        L.PF[ku * 16 + j] = pp[k];
                         r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                         nn += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
                     }
@@ -564,26 +581,40 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                 num = t.y;
             } else {
                 // orthogonal half-step on F with gamma = 1 (Prop. 1): q_F += phi_F,
-                // r -= M phi_F; then phi_V of the new residual
+                // r -= M phi_F (the F columns of M); then phi_V of the new residual
                 const bool hasv = d.nv > 0;
-                gram_part<W, GR>(c, L.P, gr, true);
-                __syncthreads();
+                if (nmf == 0) {
+                    gram_part<W, GR>(c, L.PF, gr, true, false);
+                    __syncthreads();
+                }
                 float nv_num = 0.f;
                 r2 = 0.f;
 #pragma unroll
                 for (int k = 0; k < EP; ++k) {
                     const int ku = own(k);
                     if (ku < kpad) {
-                        const float2 m = gram_sum(c, np, ku, j);
+                        float2 m = {0.f, 0.f};
+                        if (nmf == 0) {
+                            m = gram_sum(c, np, ku, j);
+                        } else {
+                            // VALU: sum over the users of F of M[ku][f] phi_F[f]
+                            const float2 *mrow = L.MF + ku * nmf;
+#pragma unroll 4
+                            for (int t = 0; t < nmf; ++t) {
+                                const float2 mv = mrow[t], f = L.PF[L.fpos[t] * 16 + j];
+                                m.x += mv.x * f.x - mv.y * f.y;
+                                m.y += mv.x * f.y + mv.y * f.x;
+                            }
+                        }
                         if (act) {
                             qq[k] = float2{qq[k].x + pp[k].x, qq[k].y + pp[k].y};
                             rr[k] = float2{rr[k].x - m.x, rr[k].y - m.y};
                         }
-                        // next phi: rows of V for the aggregated step, or, without
-                        // V, rows of F for the next iteration
+                        // phi of the next step: rows of V for the aggregated
+                        // step, or, without V, rows of F for the next iteration
                         const float f = rs[k] == (hasv ? 2 : 1) ? ninv[k] : 0.f;
                         pp[k] = float2{rr[k].x * f, rr[k].y * f};
-                        L.P[ku * 16 + j] = pp[k];
+                        (hasv ? L.PV : L.PF)[ku * 16 + j] = pp[k];
                         nv_num += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
                         r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                     }
@@ -593,18 +624,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                 } else {
                     // aggregated step on V: gamma = phi^H r / phi^H M phi
                     __syncthreads();
-                    gram_part<W, GR>(c, L.P, gr, false);
-                    __syncthreads();
-                    float den = 0.f;
-                    float2 mk[EP];
-#pragma unroll
-                    for (int k = 0; k < EP; ++k) {
-                        mk[k] = float2{0.f, 0.f};
-                        if (own(k) < kpad) {
-                            mk[k] = gram_sum(c, np, own(k), j);
-                            den += pp[k].x * mk[k].x + pp[k].y * mk[k].y;
-                        }
-                    }
+                    const float den = gram_part<W, GR>(c, L.PV, gr, false, true);
                     const float2 nd = cs.sum2(nv_num, den);
                     const float gm = (act && nd.x > 0.f && nd.y > 0.f) ? nd.x / nd.y : 0.f;
                     r2 = 0.f;
@@ -612,10 +632,11 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                     for (int k = 0; k < EP; ++k) {
                         const int ku = own(k);
                         if (ku < kpad) {
+                            const float2 m = gram_sum(c, np, ku, j);
                             qq[k] = float2{qq[k].x + gm * pp[k].x, qq[k].y + gm * pp[k].y};
-                            rr[k] = float2{rr[k].x - gm * mk[k].x, rr[k].y - gm * mk[k].y};
+                            rr[k] = float2{rr[k].x - gm * m.x, rr[k].y - gm * m.y};
                             pp[k] = phi_first(k);
-                            L.P[ku * 16 + j] = pp[k];
+                            L.PF[ku * 16 + j] = pp[k];
                             r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                         }
                     }
@@ -629,10 +650,10 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         // of the maintained residual), decides
 #pragma unroll
         for (int k = 0; k < EP; ++k)
-            if (own(k) < kpad) L.Q[own(k) * 16 + j] = qq[k];
+            if (own(k) < kpad) L.PV[own(k) * 16 + j] = qq[k];
         __syncthreads();
         form_x<W>(c);
-        gram_part<W, GR>(c, L.Q, gr, false);
+        gram_part<W, GR>(c, L.PV, gr, false, false);
         __syncthreads();
         float t2 = 0.f, tn = 0.f;
 #pragma unroll
@@ -643,9 +664,9 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                 float2 sv = {0.f, 0.f};
                 if (ku < K && b0 + j < c.nrhs) sv = c.S[(int64_t)(b0 + j) * c.lds + c.perm[ku]];
                 rr[k] = float2{sv.x - mq.x, sv.y - mq.y};
-                if (variant == 0 || variant == 2) L.R[ku * 16 + j] = rr[k];
+                if (greedy) L.R[ku * 16 + j] = rr[k];
                 pp[k] = phi_first(k);
-                L.P[ku * 16 + j] = pp[k];
+                L.PF[ku * 16 + j] = pp[k];
                 t2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                 tn += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
             }
@@ -795,9 +816,9 @@ int vrk_mfma_supported(int32_t kpad, int32_t waves)
     return vrk_mfma_entries(kpad, waves) > 0;
 }
 
-size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves)
+size_t vrk_mfma_lds_bytes(int32_t kpad, int32_t nab, int32_t waves, int32_t greedy, int32_t nmf)
 {
-    return mfma_lds_layout(kpad, nab, waves, nullptr, nullptr);
+    return mfma_lds_layout(kpad, nab, waves, greedy != 0, nmf, nullptr, nullptr);
 }
 
 hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, const VrkQueue &q, int32_t grid,

@@ -67,7 +67,8 @@ struct ProbPlan {
     int32_t ncol = 0;
     // MFMA tables
     int32_t nub = 0, nab = 0, ntile = 0;
-    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, gm_off, gm_c, gm_nf;
+    std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, gm_off, gm_c, gm_nf, fpos;
+    int32_t nmf = 0;   // columns of MF (F users) when the solve takes the F half-step on the VALU
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
     // workspace offsets
@@ -75,7 +76,7 @@ struct ProbPlan {
         o_gbusr, o_perm, o_pos, o_nrm, o_fro2, o_rablo, o_rabhi, o_haoff, o_agoff, o_aguc,
         o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
-    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_gmnf = 0;
+    size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_gmnf = 0, o_fpos = 0, o_mf = 0;
 };
 
 }  // namespace
@@ -393,7 +394,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     if (eng == VRK_ENGINE_MFMA && !mfma_ok) {
         delete pl;
         return fail(VRK_EUNSUPPORTED, "MFMA engine needs complex64, 8 or 16 waves and k <= %d with %d waves",
-                    32 * waves, waves);
+                    16 * waves, waves);
     }
     pl->engine = eng;
     pl->waves = waves;
@@ -408,7 +409,21 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     } else {
         int32_t max_nab = (max_nt + VRK_AB - 1) / VRK_AB;
         pl->ep = vrk_mfma_entries(max_kpad, waves);
-        pl->lds = vrk_mfma_lds_bytes(max_kpad, max_nab, waves);
+        const bool greedy = o.variant == VRK_GRK || o.variant == VRK_VR_OGRK;
+        // VR-OAHK with few users in F and a nonempty V takes the orthogonal
+        // half-step on the VALU from the F columns of M (held in LDS)
+        int32_t max_nmf = 0;
+        for (auto &q : pl->pp) {
+            q.nmf = 0;
+            q.fpos.clear();
+            const int nf = (int)q.flist.size();
+            if (o.variant == VRK_VR_OAHK && nf >= 1 && nf <= 16 && !q.vlist.empty()) {
+                q.nmf = nf;
+                for (int f : q.flist) q.fpos.push_back(q.pos[f]);
+            }
+            max_nmf = std::max(max_nmf, q.nmf);
+        }
+        pl->lds = vrk_mfma_lds_bytes(max_kpad, max_nab, waves, greedy ? 1 : 0, max_nmf);
         if (pl->lds > 160 * 1024) {
             delete pl;
             return fail(VRK_EUNSUPPORTED, "MFMA engine needs %zu bytes of LDS for k=%d", pl->lds, max_k);
@@ -498,6 +513,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_gmoff = cv.take(4 * q.gm_off.size());
         q.o_gmc = cv.take(4 * q.gm_c.size());
         q.o_gmnf = cv.take(4 * q.gm_nf.size());
+        q.o_fpos = cv.take(4 * q.fpos.size());
     }
     pl->table_end = cv.off;
     for (auto &q : pl->pp) {
@@ -507,7 +523,9 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             q.o_ha = cv.take(q.n_ha * 64 * 8);
             q.o_hg = cv.take(q.n_hg * 64 * 8);
             q.o_gm = cv.take(q.n_gm * 64 * 8);
+            q.o_mf = cv.take((size_t)q.nub * VRK_UB * q.nmf * 8);
             pl->max_tiles = std::max(pl->max_tiles, q.n_gm);
+            pl->max_tiles = std::max(pl->max_tiles, (int64_t)(q.nub * VRK_UB * q.nmf + 63) / 64);
             pl->max_tiles = std::max(pl->max_tiles, std::max(q.n_ha, q.n_hg));
         }
         if (q.p.GX) {
@@ -563,6 +581,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         put(img, q.o_gmoff, q.gm_off);
         put(img, q.o_gmc, q.gm_c);
         put(img, q.o_gmnf, q.gm_nf);
+        put(img, q.o_fpos, q.fpos);
         VrkDesc &d = descs[i];
         std::memset(&d, 0, sizeof d);
         const vrk_problem &p = q.p;
@@ -609,6 +628,9 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.gm_c = (const int32_t *)(base + q.o_gmc);
         d.gm_nf = (const int32_t *)(base + q.o_gmnf);
         d.GM = pl->engine == VRK_ENGINE_MFMA ? base + q.o_gm : nullptr;
+        d.nmf = pl->engine == VRK_ENGINE_MFMA ? q.nmf : 0;
+        d.MF = d.nmf ? base + q.o_mf : nullptr;
+        d.fpos = (const int32_t *)(base + q.o_fpos);
         (void)eb;
     }
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());

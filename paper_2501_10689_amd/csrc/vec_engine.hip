@@ -110,6 +110,23 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
         }
         reinterpret_cast<cx<float> *>(d.HG)[t * 64 + lane] = v;
     }
+    // F columns of M for the VALU orthogonal half-step: entry (ku, tt) =
+    // M[perm[ku]][flist[tt]], accumulated in double and rounded once
+    if (d.MF && t * 64 + lane < (int64_t)d.nub * VRK_UB * d.nmf) {
+        const int idx = (int)(t * 64) + lane, ku = idx / d.nmf, tt = idx % d.nmf;
+        double ar = 0.0, ai = 0.0;
+        if (ku < d.k) {
+            const int u = d.perm[ku], f = d.flist[tt];
+            const int lo = max(d.vs[u], d.vs[f]), hi = min(d.ve[u], d.ve[f]);
+            for (int n = lo; n < hi; ++n) {
+                cx<float> a = H[(int64_t)u * d.ldh + n], b = H[(int64_t)f * d.ldh + n];
+                ar += (double)a.re * b.re + (double)a.im * b.im;
+                ai += (double)a.im * b.re - (double)a.re * b.im;
+            }
+            if (u == f) ar += d.xi;
+        }
+        reinterpret_cast<cx<float> *>(d.MF)[idx] = cx<float>{(float)ar, (float)ai};
+    }
     const int64_t n_gm = d.gm_off[d.nub];
     if (t < n_gm) {
         // Gram tile e of user block mb: lane l = i + 16 kk holds

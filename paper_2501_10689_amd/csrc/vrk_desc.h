@@ -19,7 +19,7 @@ enum { VRK_FLAG_CONVERGED = 1, VRK_FLAG_NONFINITE = 2, VRK_FLAG_MAXITER = 4 };
 struct VrkDesc {
     int32_t nt, k, nrhs, nf;      // antennas, users, right-hand sides, |F|
     int32_t nv, ncol, ngb, nub;   // |V|, colour classes, gather blocks, 16-user blocks
-    int32_t nab, ntile, pad0, pad1;  // 16-antenna blocks, RHS tiles of 16
+    int32_t nab, ntile, nmf, pad1;   // 16-antenna blocks, RHS tiles of 16, columns of MF (0: none)
     double xi;
     int64_t ldh, lds, ldx, ldv, ldgx, ldgh, ldgs;
     int64_t rhs_base;             // offset of this problem's RHS in the stats arrays
@@ -59,6 +59,11 @@ struct VrkDesc {
     // adjoint solve again, [rhs][nub * 16] complex64 in VR-start user order
     // (zero on the padding users), for the gradient products
     void *Vsrt, *Msrt;
+    // MFMA engine, VR-OAHK with 1..16 users in F and a nonempty V: the F
+    // columns of M, MF[ku][t] = M[perm[ku]][flist[t]] complex64 (nub * 16
+    // rows, rounded once from double), and fpos[t] = pos[flist[t]]
+    void *MF;
+    const int32_t *fpos;
 };
 
 // User blocks per tile of the MFMA adjoint gradient: the blocks 4 ubg ..
