@@ -1,11 +1,12 @@
-// Adjoint (implicit differentiation) products of the MFMA engine, complex64.
+// Adjoint (implicit differentiation) gradient products of the MFMA engine,
+// complex64.
 //
 // For x = H^H (H H^H + xi I)^-1 s and an incoming gradient g = 2 dL/d conj(x):
-//   b = H g                                   (right-hand side of the adjoint solve)
 //   GH = sum_b v_b (g_b - xh_b)^H - mu_b x_b^H  on the VR band entries
 //   gxi = -Re sum_b mu_b^H v_b
-// with mu = (H H^H + xi I)^-1 H g and xh = H^H mu from the adjoint solve.
-// Both products run on v_mfma_f32_16x16x4f32 over the band tiles of the plan.
+// with mu = (H H^H + xi I)^-1 H g and xh = H^H mu from the adjoint solve
+// (whose right-hand side b = H g the solve kernel forms itself). The
+// products run on v_mfma_f32_16x16x4f32 over the band tiles of the plan.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -36,75 +37,6 @@ __device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
 using CDesc = const VRK_CONST VrkDesc;
 template <typename T>
 using gp = VRK_GLOBAL T *;
-
-// b = H g for one tile of 16 RHS and one 16-user block:
-// D[user][rhs] = sum over the block's band chunks of HA-tile x GX. The four
-// waves take every fourth antenna block, two per step so that the loads of
-// one overlap the other's MFMAs, and add their tiles in LDS in fixed order.
-constexpr int kRW = 4;
-
-__global__ void __launch_bounds__(kRW * 64) k_adj_rhs_mfma(const VrkDesc *descs, const VrkWork *work)
-{
-    __shared__ float2 part[kRW][256];
-    const VrkWork wk = gmem(work)[blockIdx.x];
-    const int prob = __builtin_amdgcn_readfirstlane(wk.prob), tile = __builtin_amdgcn_readfirstlane(wk.tile);
-    CDesc &d = ((CDesc *)descs)[prob];
-    const int ub = blockIdx.y;
-    if (ub >= d.nub) return;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
-    const int b = tile * VRK_TILE_RHS + j;
-    const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
-    const gp<const float2> GX = gmem(static_cast<const float2 *>(d.GX));
-    const int lo = gmem(d.rab_lo)[ub], hi = gmem(d.rab_hi)[ub];
-    const int64_t hb = gmem(d.ha_off)[ub];
-    const bool bok = b < d.nrhs;
-    const int nt = d.nt;
-    const gp<const float2> grow = GX + (int64_t)(bok ? b : 0) * d.ldgx;
-    const f4 z = {0.f, 0.f, 0.f, 0.f};
-    C3 acc = {z, z, z};
-    auto load = [&](int ab, float2 (&h)[4], float2 (&x)[4]) {
-        const gp<const float2> hp = HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int n = 16 * ab + 4 * g + m;   // reduction slot g of chunk (ab, m)
-            h[m] = hp[64 * m];
-            x[m] = float2{0.f, 0.f};
-            if (bok && n < nt) x[m] = grow[n];
-        }
-    };
-    int ab = lo + w;
-    for (; ab + kRW < hi; ab += 2 * kRW) {
-        float2 h0[4], x0[4], h1[4], x1[4];
-        load(ab, h0, x0);
-        load(ab + kRW, h1, x1);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) c3mfma(acc, h0[m], x0[m]);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) c3mfma(acc, h1[m], x1[m]);
-    }
-    if (ab < hi) {
-        float2 h0[4], x0[4];
-        load(ab, h0, x0);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) c3mfma(acc, h0[m], x0[m]);
-    }
-    const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
-    // D layout: lane (j, g) register r holds user 4 g + r, RHS j
-#pragma unroll
-    for (int r = 0; r < 4; ++r) part[w][(4 * g + r) * 16 + j] = float2{re[r], im[r]};
-    __syncthreads();
-    const int ii = tid >> 4, jj = tid & 15;   // user ii of the block, RHS jj
-    const int bb = tile * VRK_TILE_RHS + jj, ku = ub * VRK_UB + ii;
-    if (bb < d.nrhs && ku < d.k) {
-        float sr = 0.f, si = 0.f;
-#pragma unroll
-        for (int q = 0; q < kRW; ++q) {
-            sr += part[q][tid].x;
-            si += part[q][tid].y;
-        }
-        gmem(static_cast<float2 *>(d.Sadj))[(int64_t)bb * d.k + gmem(d.perm)[ku]] = float2{sr, si};
-    }
-}
 
 // GH on the band tiles (ub, ab) of the user blocks ub = 4 ubg .. 4 ubg + 3
 // that meet antenna block ab: D[user i][antenna j] = sum_b A[i][b] B[b][j]
@@ -293,14 +225,6 @@ __global__ void __launch_bounds__(kGW * 64) k_adj_grads_mfma(const VrkDesc *desc
 
 
 }  // namespace
-
-hipError_t vrk_launch_adjoint_rhs_mfma(const VrkDesc *desc, const VrkWork *work, int32_t nwork,
-                                       int32_t max_nub, hipStream_t s)
-{
-    if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_rhs_mfma, dim3(nwork, max_nub), dim3(kRW * 64), 0, s, desc, work);
-    return hipGetLastError();
-}
 
 hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
                                          float2 *gpart, float *gxpart, hipStream_t s)

@@ -52,11 +52,8 @@ hipError_t vrk_launch_adjoint_rhs(const VrkDesc *desc, int32_t nprob, int32_t ma
                                   int32_t dtype, hipStream_t s);
 hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t max_k,
                                     int32_t dtype, hipStream_t s);
-// MFMA versions (complex64, plans of the MFMA engine): b = H g per RHS tile
-// and user block; GH per band tile (problem, user block, antenna block,
-// first-of-problem flag for the xi gradient; user block -1 = xi only).
-hipError_t vrk_launch_adjoint_rhs_mfma(const VrkDesc *desc, const VrkWork *work, int32_t nwork,
-                                       int32_t max_nub, hipStream_t s);
+// MFMA version of the gradient assembly (complex64, plans of the MFMA
+// engine, whose solve forms b = H g itself).
 // Tiles are (problem, user-block group, antenna block, flags: bit 0 first
 // tile of its problem, bit 1 first tile of its group, bits 2.. on a problem's
 // first tile: its problem's tile count). nsplit > 1 splits each

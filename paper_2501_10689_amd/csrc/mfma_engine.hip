@@ -202,7 +202,7 @@ using gp = VRK_GLOBAL T *;
 
 struct TileCtx {
     MfmaLds L;
-    gp<const float2> S, HG, GM;
+    gp<const float2> S, HA, HG, GM;
     gp<float2> X;   // output rows of this tile's RHS (x = H^H q)
     gp<const int32_t> perm, ag_uc, gm_c;
     int64_t lds, ldx;
@@ -375,6 +375,61 @@ __device__ __forceinline__ float gram_part(const TileCtx &c, const float2 *F, co
     return den;
 }
 
+// Right-hand side of the adjoint solve, b = H g, for this tile's RHS:
+// partial products like the Gram parts (wave w takes row block w % nub and
+// part w / nub of its antenna-block range, or whole blocks w, w + W, ...),
+// H from the residual tiles (16 users x antennas 16 ab + 4 kk + m at lane
+// i + 16 kk), g from the rows of GX as the B operand (4 consecutive
+// antennas per lane), results to MP[part]. A barrier must precede reading MP.
+template <int W>
+__device__ __forceinline__ void hg_part(const TileCtx &c, CDesc &d)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    const int b = c.b0 + j;
+    const gp<const float2> grow = gmem(static_cast<const float2 *>(d.GX)) + (int64_t)(b < c.nrhs ? b : 0) * d.ldgx;
+    auto block = [&](int mb, int part, int np) {
+        const int lo = gmem(d.rab_lo)[mb], hi = gmem(d.rab_hi)[mb];
+        const int64_t hb = gmem(d.ha_off)[mb];
+        const int a0 = lo + part * (hi - lo) / np, a1 = lo + (part + 1) * (hi - lo) / np;
+        C3 acc = c3_zero();
+        // four antenna blocks per step: their loads are in flight together
+#pragma unroll 1
+        for (int ab0 = a0; ab0 < a1; ab0 += 4) {
+            float2 h[4][4], x[4][4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int ab = ab0 + t;
+                const gp<const float2> hp = c.HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int n = 16 * ab + 4 * g + m;
+                    h[t][m] = x[t][m] = float2{0.f, 0.f};
+                    if (ab < a1) {
+                        h[t][m] = hp[64 * m];
+                        if (b < c.nrhs && n < c.N) x[t][m] = grow[n];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) c3mfma(acc, h[t][m], x[t][m]);
+        }
+        f4 mr, mi;
+        c3_get(acc, mr, mi);
+        float2 *out = c.L.MP + (size_t)part * c.kpad * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(16 * mb + 4 * g + r) * 16 + j] = float2{mr[r], mi[r]};
+    };
+    if (c.nub <= W) {
+        const int np = gram_parts(c.nub, W);
+        if (w < np * c.nub) block(w % c.nub, w / c.nub, np);
+    } else {
+#pragma unroll 1
+        for (int mb = w; mb < c.nub; mb += W) block(mb, 0, 1);
+    }
+}
+
 // Sum of the partial Gram products at entry (ku, j).
 __device__ __forceinline__ float2 gram_sum(const TileCtx &c, int np, int ku, int j)
 {
@@ -411,7 +466,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     gp<float2> X, V;
     int64_t ldx_, ldv_;
     if (a.adjoint) {
-        c.S = gmem(static_cast<const float2 *>(d.Sadj)); c.lds = c.K;
+        c.S = nullptr; c.lds = 0;   // b = H g is formed by the tile itself
         X = gmem(static_cast<float2 *>(d.Xadj)); ldx_ = c.N;
         V = gmem(static_cast<float2 *>(d.GS)); ldv_ = d.ldgs;
     } else {
@@ -419,6 +474,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         X = gmem(static_cast<float2 *>(d.X)); ldx_ = d.ldx;
         V = gmem(static_cast<float2 *>(d.V)); ldv_ = d.ldv;
     }
+    c.HA = gmem(static_cast<const float2 *>(d.HA));
     c.HG = gmem(static_cast<const float2 *>(d.HG));
     c.GM = gmem(static_cast<const float2 *>(d.GM));
     c.X = X;
@@ -445,9 +501,15 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     if (tid < nmf) L.fpos[tid] = gmem(d.fpos)[tid];
     for (int i = tid; i < kpad * nmf; i += W * 64) L.MF[i] = gmem(static_cast<const float2 *>(d.MF))[i];
     __syncthreads();
-    // this thread's entries (ku, j), ku = er + rows_per_pass k: residual,
-    // dual iterate, phi, 1 / ||a_ku||^2 and the F/V selector
-    float2 rr[EP], qq[EP], pp[EP];
+    // adjoint: b = H g for this tile's columns
+    const int np = c.nub <= W ? gram_parts(c.nub, W) : 1;
+    if (a.adjoint) {
+        hg_part<W>(c, d);
+        __syncthreads();
+    }
+    // this thread's entries (ku, j), ku = er + rows_per_pass k: right-hand
+    // side, residual, dual iterate, phi, 1 / ||a_ku||^2 and the F/V selector
+    float2 sb[EP], rr[EP], qq[EP], pp[EP];
     float ninv[EP];
     int rs[EP];
     auto own = [&](int k) { return er + rows_per_pass * k; };
@@ -463,12 +525,14 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
 #pragma unroll
     for (int k = 0; k < EP; ++k) {
         const int ku = own(k);
-        rr[k] = qq[k] = pp[k] = float2{0.f, 0.f};
+        sb[k] = rr[k] = qq[k] = pp[k] = float2{0.f, 0.f};
         ninv[k] = 0.f;
         rs[k] = 0;
         if (ku < kpad) {
             const int b = b0 + j;
-            if (ku < K && b < c.nrhs) rr[k] = c.S[(int64_t)b * c.lds + c.perm[ku]];
+            if (a.adjoint) sb[k] = gram_sum(c, np, ku, j);
+            else if (ku < K && b < c.nrhs) sb[k] = c.S[(int64_t)b * c.lds + c.perm[ku]];
+            rr[k] = sb[k];
             rs[k] = L.rsel[ku];
             ninv[k] = 1.f / L.nrm[ku];
             pp[k] = phi_first(k);
@@ -497,7 +561,6 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
 
     // Gram tiles kept in registers per wave (two VGPRs and a chunk column each)
     constexpr int GR = W == 8 ? 16 : 4;
-    const int np = c.nub <= W ? gram_parts(c.nub, W) : 1;
     int64_t t_it = 0;
     for (;;) {
         // iteration phase: runs until every column has stopped
@@ -661,9 +724,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             const int ku = own(k);
             if (ku < kpad) {
                 const float2 mq = gram_sum(c, np, ku, j);
-                float2 sv = {0.f, 0.f};
-                if (ku < K && b0 + j < c.nrhs) sv = c.S[(int64_t)(b0 + j) * c.lds + c.perm[ku]];
-                rr[k] = float2{sv.x - mq.x, sv.y - mq.y};
+                rr[k] = float2{sb[k].x - mq.x, sb[k].y - mq.y};
                 if (greedy) L.R[ku * 16 + j] = rr[k];
                 pp[k] = phi_first(k);
                 L.PF[ku * 16 + j] = pp[k];

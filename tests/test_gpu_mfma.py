@@ -149,6 +149,25 @@ def test_adjoint_mfma_matches_closed_form(nt, k, nrhs):
     assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
 
 
+@pytest.mark.parametrize("waves", [8, 16])
+def test_vr_oahk_large_orthogonal_set(waves):
+    """Short VRs (8..24 antennas of 512) give |F| around 20 with V nonempty:
+    the orthogonal half-step runs as a Gram product over the chunks holding
+    F users instead of the per-entry F columns of M (used up to 16 users)."""
+    rng = np.random.default_rng(100)
+    H, vs, vl, xi = random_problem(rng, 512, 48, lo=8, hi=24)
+    S = qpsk(rng, (40, 48))
+    res, plan = run_plan([(H, vs, vl, S, xi)], variant="vr_oahk", engine="mfma", tol=1e-6, tile_waves=waves)
+    nf = int(oracle.mis(H, vs, vl).sum())
+    assert 16 < nf < 48
+    assert len(plan.query(0, 1)) == nf
+    X, V = oracle.rzf(H, vs, vl, S, xi)
+    g = res[0]
+    assert np.all(g["flags"] == oracle.F_CONVERGED)
+    assert rel_err_rows(g["X"], X).max() <= 1e-4
+    assert rel_err_rows(g["V"], V).max() <= 1e-4
+
+
 def test_adjoint_mfma_rhs_split():
     """Enough right-hand sides that each gradient tile's RHS range is split
     over workgroups (partials reduced in a second kernel); K 72 leaves a
