@@ -47,10 +47,12 @@ using gp = VRK_GLOBAL T *;
 constexpr int kGW = 4;
 constexpr int kUG = VRK_GRAD_UG;
 
-__device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, int be0,
-                                            float2 (*part)[kUG][256], gp<float2> out)
+// Returns the lane's share of sum conj(mu) v over the users of the blocks
+// whose first antenna block is ab (each (user, RHS) pair is counted in
+// exactly one tile; users with an empty VR have mu = 0).
+__device__ __forceinline__ float grads_group(CDesc &d, int ubg, int ab, int bs0, int be0,
+                                             float2 (*part)[kUG][256], gp<float2> out)
 {
-    // (the gxi partial of a group-first tile is taken by the caller)
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 15, kk = lane >> 4;
     const gp<const float2> VS = gmem(static_cast<const float2 *>(d.Vsrt));
     const gp<const float2> MS = gmem(static_cast<const float2 *>(d.Msrt));
@@ -61,12 +63,14 @@ __device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, 
     const int nub = d.nub, kpad = nub * VRK_UB;
     const int ub0 = ubg * kUG;
     // blocks of the group that meet ab (wave-uniform)
-    bool live[kUG];
+    bool live[kUG], first[kUG];
 #pragma unroll
     for (int u = 0; u < kUG; ++u) {
         const int ub = ub0 + u;
         live[u] = ub < nub && gmem(d.rab_lo)[ub] <= ab && ab < gmem(d.rab_hi)[ub];
+        first[u] = live[u] && gmem(d.rab_lo)[ub] == ab;
     }
+    float gx = 0.f;
     const int n = ab * VRK_AB + i;           // B operand column (antenna) of this lane
     const bool nok = n < d.nt;
     const int per = (be0 - bs0 + kGW - 1) / kGW;
@@ -102,11 +106,13 @@ __device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, 
         for (int q = 0; q < kQ; ++q) {
             const float2 cy = float2{y[q].x, -y[q].y}, cx_ = float2{xv[q].x, -xv[q].y};
 #pragma unroll
-            for (int u = 0; u < kUG; ++u)
+            for (int u = 0; u < kUG; ++u) {
+                if (first[u]) gx += mu[q][u].x * v[q][u].x + mu[q][u].y * v[q][u].y;
                 if (live[u]) {
                     c3mfma(acc[u], v[q][u], cy);                                  // v conj(y)
                     c3mfma(acc[u], float2{-mu[q][u].x, -mu[q][u].y}, cx_);        // - mu conj(x)
                 }
+            }
         }
     }
     // D layout: lane (j, g) register r holds user 4 g + r, antenna j
@@ -139,6 +145,7 @@ __device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, 
             }
         }
     }
+    return gx;
 }
 
 // Workgroup (tile, u): sum the RHS-split partials of user block 4 ubg + u of
@@ -181,9 +188,10 @@ __global__ void __launch_bounds__(256) k_adj_grads_reduce(const VrkDesc *descs, 
 }
 
 // Workgroup (tile, split): one RHS range of a tile; with nsplit 1 it writes
-// GH directly, else its partials to gpart. A group-first tile (tile.w bit 1)
-// also writes the partial of dL/dxi = -Re sum_{b,k} conj(mu) v over the
-// users of its group and its RHS range to gxpart (0 for other tiles).
+// GH directly, else its partials to gpart. Every workgroup writes its share
+// of sum_{b,k} conj(mu) v (dL/dxi is minus its real part) to gxpart: the
+// users of the blocks whose first antenna block is the tile's, over its RHS
+// range, from the v and mu it loads anyway.
 __global__ void __launch_bounds__(kGW * 64) k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, int nsplit,
                                                              float2 *gpart, float *gxpart)
 {
@@ -193,26 +201,15 @@ __global__ void __launch_bounds__(kGW * 64) k_adj_grads_mfma(const VrkDesc *desc
     const int4 tl = gmem(tiles)[tix];   // (problem, user-block group, antenna block, flags)
     CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
     const int ubg = __builtin_amdgcn_readfirstlane(tl.y), ab = __builtin_amdgcn_readfirstlane(tl.z);
-    const int flags = __builtin_amdgcn_readfirstlane(tl.w);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int B = d.nrhs;
     const int per = (B + nsplit - 1) / nsplit;
     const int bs0 = min(B, split * per), be0 = min(B, bs0 + per);
-    if (ubg >= 0)
-        grads_group(d, ubg, ab, bs0, be0, part,
-                    nsplit > 1 ? gmem(gpart) + ((int64_t)tix * nsplit + split) * kUG * 256 : nullptr);
+    // the workgroup's share of sum conj(mu) v (dL/dxi = -Re of the total)
     float acc = 0.f;
-    if (ubg >= 0 && (flags & 2)) {
-        const int kpad = d.nub * VRK_UB, c0 = ubg * kUG * VRK_UB, c1 = min(kpad, c0 + kUG * VRK_UB);
-        const int cw = c1 - c0;
-        const gp<const float2> VS = gmem(static_cast<const float2 *>(d.Vsrt));
-        const gp<const float2> MS = gmem(static_cast<const float2 *>(d.Msrt));
-        for (int e = tid; e < (be0 - bs0) * cw; e += kGW * 64) {
-            const int b = bs0 + e / cw, c = c0 + e % cw;
-            const float2 mu = MS[(int64_t)b * kpad + c], v = VS[(int64_t)b * kpad + c];
-            acc += mu.x * v.x + mu.y * v.y;
-        }
-    }
+    if (ubg >= 0)
+        acc = grads_group(d, ubg, ab, bs0, be0, part,
+                          nsplit > 1 ? gmem(gpart) + ((int64_t)tix * nsplit + split) * kUG * 256 : nullptr);
     acc = wave_sum(acc);
     if (lane == 0) red[w] = acc;
     __syncthreads();

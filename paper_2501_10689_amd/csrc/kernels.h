@@ -55,7 +55,7 @@ hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t 
 // MFMA version of the gradient assembly (complex64, plans of the MFMA
 // engine, whose solve forms b = H g itself).
 // Tiles are (problem, user-block group, antenna block, flags: bit 0 first
-// tile of its problem, bit 1 first tile of its group, bits 2.. on a problem's
+// tile of its problem, bit 1 unused, bits 2.. on a problem's
 // first tile: its problem's tile count). nsplit > 1 splits each
 // tile's RHS range over nsplit workgroups writing partials to gpart
 // (ntiles * nsplit * VRK_GRAD_UG * 256 complex64); gxpart (ntiles * nsplit

@@ -454,20 +454,19 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         if (all_adj)
             for (int i = 0; i < nprob; ++i) {
                 const ProbPlan &q = pl->pp[i];
-                // (problem, user-block group, antenna block, first of problem)
-                // for every antenna block that some block of the group meets
+                // (problem, user-block group, antenna block, flags) for every
+                // antenna block that some block of the group meets; flags: 1 on
+                // the problem's first tile, which also carries its tile count
                 int first = 1;
                 const size_t t0 = pl->gtiles.size();
                 for (int ubg = 0; ubg * VRK_GRAD_UG < q.nub; ++ubg) {
                     const int u0 = ubg * VRK_GRAD_UG, u1 = std::min(q.nub, u0 + VRK_GRAD_UG);
-                    int gfirst = 2;
                     for (int ab = 0; ab < q.nab; ++ab) {
                         bool meets = false;
                         for (int ub = u0; ub < u1; ++ub) meets = meets || (q.rab_lo[ub] <= ab && ab < q.rab_hi[ub]);
                         if (!meets) continue;
-                        pl->gtiles.push_back(make_int4(i, ubg, ab, first | gfirst));
+                        pl->gtiles.push_back(make_int4(i, ubg, ab, first));
                         first = 0;
-                        gfirst = 0;
                     }
                 }
                 if (first) pl->gtiles.push_back(make_int4(i, -1, 0, 1));
@@ -478,7 +477,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             // split keeping at least 64 right-hand sides (16 per wave)
             int64_t want = 4096 / (int64_t)pl->gtiles.size();
             int64_t cap = std::max<int64_t>(1, min_rhs / 64);
-            pl->gsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 32}));
+            pl->gsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 16}));
         }
     }
     // workspace carving
