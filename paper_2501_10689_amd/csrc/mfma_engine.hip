@@ -268,8 +268,8 @@ __device__ __forceinline__ void form_x(const TileCtx &c)
 // chunk columns), loaded by gram_load.
 template <int GR>
 struct GramRegs {
-    float2 m[GR];
-    int uc[GR];
+    float2 m[GR > 0 ? GR : 1];
+    int uc[GR > 0 ? GR : 1];
     int mb, part, g0, g1;
 };
 
@@ -497,7 +497,9 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
     for (int i = tid; i < gmem(d.gm_off)[c.nub]; i += W * 64) L.gmc[i] = max(c.gm_c[i], 0);   // padding: zero tile
     for (int i = tid; i < c.nub; i += W * 64) L.gmnf[i] = gmem(d.gm_nf)[i];
-    const int nmf = d.nmf;   // > 0: VALU orthogonal half-step from MF
+    // > 0: VALU orthogonal half-step from MF (never with four entries per
+    // thread: its registers are needed elsewhere)
+    const int nmf = EP >= 4 ? 0 : d.nmf;
     if (tid < nmf) L.fpos[tid] = gmem(d.fpos)[tid];
     for (int i = tid; i < kpad * nmf; i += W * 64) L.MF[i] = gmem(static_cast<const float2 *>(d.MF))[i];
     __syncthreads();
@@ -507,17 +509,36 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         hg_part<W>(c, d);
         __syncthreads();
     }
-    // this thread's entries (ku, j), ku = er + rows_per_pass k: right-hand
-    // side, residual, dual iterate, phi, 1 / ||a_ku||^2 and the F/V selector
-    float2 sb[EP], rr[EP], qq[EP], pp[EP];
-    float ninv[EP];
-    int rs[EP];
+    // this thread's entries (ku, j), ku = er + rows_per_pass k: residual,
+    // dual iterate, phi; with up to two entries per thread also the
+    // right-hand side, 1 / ||a_ku||^2 and the F/V selector (with four, those
+    // are read again when needed: the right-hand side from S, or, in the
+    // adjoint solve, from the VR-start-order output rows that hold b until
+    // mu goes there)
+    constexpr bool lean = EP >= 4;
+    float2 rr[EP], qq[EP], pp[EP];
+    float2 sb[lean ? 1 : EP];
+    float ninv[lean ? 1 : EP];
+    int rs[lean ? 1 : EP];
     auto own = [&](int k) { return er + rows_per_pass * k; };
+    auto sel = [&](int k) { return lean ? (own(k) < kpad ? L.rsel[own(k)] : 0) : rs[k]; };
+    auto inv_norm = [&](int k) { return lean ? 1.f / L.nrm[own(k)] : ninv[k]; };
+    const gp<float2> bkeep = gmem(static_cast<float2 *>(d.Msrt));
+    auto rhs = [&](int k) -> float2 {
+        if (!lean) return sb[k];
+        const int ku = own(k), b = b0 + j;
+        if (b >= c.nrhs) return float2{0.f, 0.f};
+        if (a.adjoint) return bkeep[(int64_t)b * kpad + ku];
+        float2 v = {0.f, 0.f};
+        if (ku < K) v = c.S[(int64_t)b * c.lds + c.perm[ku]];
+        return v;
+    };
     // phi for the first step of an iteration: rows of F (VR-OAHK), every
     // row (AHK), none (greedy variants: one-hot, written by the selection)
     auto phi_first = [&](int k) -> float2 {
-        const bool in = variant == 1 ? rs[k] != 0 : (variant == 3 ? rs[k] == 1 : false);
-        const float f = in ? ninv[k] : 0.f;
+        const int rsk = sel(k);
+        const bool in = variant == 1 ? rsk != 0 : (variant == 3 ? rsk == 1 : false);
+        const float f = in ? inv_norm(k) : 0.f;
         return float2{rr[k].x * f, rr[k].y * f};
     };
     ColSums<W> cs{L.red, 0};
@@ -525,16 +546,27 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
 #pragma unroll
     for (int k = 0; k < EP; ++k) {
         const int ku = own(k);
-        sb[k] = rr[k] = qq[k] = pp[k] = float2{0.f, 0.f};
-        ninv[k] = 0.f;
-        rs[k] = 0;
+        rr[k] = qq[k] = pp[k] = float2{0.f, 0.f};
+        if (!lean) {
+            sb[k] = float2{0.f, 0.f};
+            ninv[k] = 0.f;
+            rs[k] = 0;
+        }
         if (ku < kpad) {
             const int b = b0 + j;
-            if (a.adjoint) sb[k] = gram_sum(c, np, ku, j);
-            else if (ku < K && b < c.nrhs) sb[k] = c.S[(int64_t)b * c.lds + c.perm[ku]];
-            rr[k] = sb[k];
-            rs[k] = L.rsel[ku];
-            ninv[k] = 1.f / L.nrm[ku];
+            float2 s0 = {0.f, 0.f};
+            if (a.adjoint) {
+                s0 = gram_sum(c, np, ku, j);
+                if (lean && b < c.nrhs) bkeep[(int64_t)b * kpad + ku] = s0;
+            } else if (ku < K && b < c.nrhs) {
+                s0 = c.S[(int64_t)b * c.lds + c.perm[ku]];
+            }
+            rr[k] = s0;
+            if (!lean) {
+                sb[k] = s0;
+                rs[k] = L.rsel[ku];
+                ninv[k] = 1.f / L.nrm[ku];
+            }
             pp[k] = phi_first(k);
             L.PF[ku * 16 + j] = pp[k];
             if (greedy) L.R[ku * 16 + j] = rr[k];
@@ -560,7 +592,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     }
 
     // Gram tiles kept in registers per wave (two VGPRs and a chunk column each)
-    constexpr int GR = W == 8 ? 16 : 4;
+    constexpr int GR = W == 8 ? 16 : (EP >= 2 ? 0 : 4);
     int64_t t_it = 0;
     for (;;) {
         // iteration phase: runs until every column has stopped
@@ -675,7 +707,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                         }
                         // phi of the next step: rows of V for the aggregated
                         // step, or, without V, rows of F for the next iteration
-                        const float f = rs[k] == (hasv ? 2 : 1) ? ninv[k] : 0.f;
+                        const float f = sel(k) == (hasv ? 2 : 1) ? inv_norm(k) : 0.f;
                         pp[k] = float2{rr[k].x * f, rr[k].y * f};
                         (hasv ? L.PV : L.PF)[ku * 16 + j] = pp[k];
                         nv_num += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
@@ -724,7 +756,8 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             const int ku = own(k);
             if (ku < kpad) {
                 const float2 mq = gram_sum(c, np, ku, j);
-                rr[k] = float2{sb[k].x - mq.x, sb[k].y - mq.y};
+                const float2 s0 = rhs(k);
+                rr[k] = float2{s0.x - mq.x, s0.y - mq.y};
                 if (greedy) L.R[ku * 16 + j] = rr[k];
                 pp[k] = phi_first(k);
                 L.PF[ku * 16 + j] = pp[k];

@@ -411,13 +411,14 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         pl->ep = vrk_mfma_entries(max_kpad, waves);
         const bool greedy = o.variant == VRK_GRK || o.variant == VRK_VR_OGRK;
         // VR-OAHK with few users in F and a nonempty V takes the orthogonal
-        // half-step on the VALU from the F columns of M (held in LDS)
+        // half-step on the VALU from the F columns of M (held in LDS), unless
+        // each thread holds four entries (then it stays on the MFMA)
         int32_t max_nmf = 0;
         for (auto &q : pl->pp) {
             q.nmf = 0;
             q.fpos.clear();
             const int nf = (int)q.flist.size();
-            if (o.variant == VRK_VR_OAHK && nf >= 1 && nf <= 16 && !q.vlist.empty()) {
+            if (o.variant == VRK_VR_OAHK && nf >= 1 && nf <= 16 && !q.vlist.empty() && pl->ep < 4) {
                 q.nmf = nf;
                 for (int f : q.flist) q.fpos.push_back(q.pos[f]);
             }

@@ -4,6 +4,7 @@ plan (overlap sets, orthogonal set F, colour classes) against the oracle
 and brute force."""
 from __future__ import annotations
 
+import inspect
 import itertools
 import os
 import re
@@ -25,6 +26,12 @@ def test_library_exports_every_declared_symbol():
     L = vrk.lib()
     for n in sorted(names):
         assert hasattr(L, n), n
+
+
+def test_build_entry_resolves_its_compile_steps():
+    import __graft_entry__
+    steps = __graft_entry__._builders()
+    assert len(steps) == 2 and all(inspect.isfunction(f) for f in steps)
 
 
 def test_plan_matches_oracle_structure():
