@@ -226,6 +226,9 @@ __device__ __forceinline__ void agg_block(const TileCtx &c, int ab, const float2
             h[i] = c.HG[(int64_t)(e + i) * 64 + lane];
             f[i] = F[(4 * c.ag_uc[e + i] + g) * 16 + j];
         }
+        // all four loads go out before the first wait (left alone, the
+        // scheduler turns this into load, wait, MFMA per chunk)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) c3mfma(acc, h[i], f[i]);
     }
@@ -316,6 +319,7 @@ __device__ __forceinline__ void gram_group(const TileCtx &c, const float2 *F, in
         m[i] = c.GM[(int64_t)(e + i) * 64 + lane];
         f[i] = F[c.L.gmc[e + i] * 64 + lane];   // row 4 uc + g, column j
     }
+    __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
 #pragma unroll
     for (int i = 0; i < 4; ++i) c3mfma(acc, m[i], f[i]);
 }
@@ -410,6 +414,7 @@ __device__ __forceinline__ void hg_part(const TileCtx &c, CDesc &d)
                     }
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
