@@ -1,12 +1,19 @@
 // Adjoint (implicit differentiation) gradient products of the MFMA engine,
 // complex64.
 //
-// For x = H^H (H H^H + xi I)^-1 s and an incoming gradient g = 2 dL/d conj(x):
-//   GH = sum_b v_b (g_b - xh_b)^H - mu_b x_b^H  on the VR band entries
+// For x = H^H v with v = (H H^H + xi I)^-1 s, an incoming gradient
+// g = 2 dL/d conj(x) and mu = (H H^H + xi I)^-1 H g from the adjoint solve:
+//   GH = sum_b v_b (g_b - H^H mu_b)^H - mu_b x_b^H     on the VR band entries
 //   gxi = -Re sum_b mu_b^H v_b
-// with mu = (H H^H + xi I)^-1 H g and xh = H^H mu from the adjoint solve
-// (whose right-hand side b = H g the solve kernel forms itself). The
-// products run on v_mfma_f32_16x16x4f32 over the band tiles of the plan.
+// Since x_b = H^H v_b, both products with an x reduce to the K x K matrix
+// C = sum_b v_b mu_b^H:
+//   GH = sum_b v_b g_b^H - (C + C^H) H,   gxi = -Re tr C,
+// and C is needed only on the Gram block pattern (a band entry (k, n) meets
+// H[k', n] != 0 only for users k' whose VR overlaps that of k). Two
+// kernels: the RHS-split partials of the blocks of C together with those of
+// the band tiles of sum_b v_b g_b^H, then per band tile the fixed-order sum
+// of its splits minus (C + C^H) H, and dL/dxi. All products run on
+// v_mfma_f32_16x16x4f32.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -38,39 +45,84 @@ using CDesc = const VRK_CONST VrkDesc;
 template <typename T>
 using gp = VRK_GLOBAL T *;
 
-// GH on the band tiles (ub, ab) of the user blocks ub = 4 ubg .. 4 ubg + 3
-// that meet antenna block ab: D[user i][antenna j] = sum_b A[i][b] B[b][j]
-// with A = V^T, B = conj(GX - Xadj) plus A = -M^T, B = conj(X). A wave loads
-// the antenna operands of 4 RHS once for all blocks of the group; v and mu
-// come from the VR-start-order copies (16 users = 128 contiguous bytes).
-// The RHS range is split over the waves and reduced through LDS.
+// Blocks of C: workgroup (problem, block p = (ub, ub'), split) sums
+// v_b[16 ub + i] conj(mu_b[16 ub' + j]) over its share of the RHS; the range
+// is split over the waves and reduced through LDS in fixed order, and the
+// partial goes to Cblk[p][split].
 constexpr int kGW = 4;
 constexpr int kUG = VRK_GRAD_UG;
+constexpr int kCQ = 8;          // reduction steps (4 RHS each) per batch of loads
+constexpr int kMaxCsplit = 4;   // RHS splits of a C block at most
 
-// Returns the lane's share of sum conj(mu) v over the users of the blocks
-// whose first antenna block is ab (each (user, RHS) pair is counted in
-// exactly one tile; users with an empty VR have mu = 0).
-__device__ __forceinline__ float grads_group(CDesc &d, int ubg, int ab, int bs0, int be0,
-                                             float2 (*part)[kUG][256], gp<float2> out)
+__device__ __forceinline__ void cmat_part(CDesc &d, int p, int ub, int split, int csplit, float2 (*part)[256])
+{
+    const int ubc = __builtin_amdgcn_readfirstlane(gmem(d.cp_col)[p]);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 15, kk = lane >> 4;
+    const int B = d.nrhs, kpad = d.nub * VRK_UB;
+    const int per = (B + csplit - 1) / csplit;
+    const int bs0 = min(B, split * per), be0 = min(B, bs0 + per);
+    const int pw = (be0 - bs0 + kGW - 1) / kGW;
+    const int bs = bs0 + w * pw, be = min(be0, bs + pw);
+    // A operand: v of user 16 ub + i; B operand: conj(mu) of user 16 ub' + i
+    const gp<const float2> VS = gmem(static_cast<const float2 *>(d.Vsrt)) + VRK_UB * ub + i;
+    const gp<const float2> MS = gmem(static_cast<const float2 *>(d.Msrt)) + VRK_UB * ubc + i;
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    C3 acc = {z, z, z};
+    for (int b0 = bs; b0 < be; b0 += 4 * kCQ) {
+        float2 a[kCQ], m[kCQ];
+#pragma unroll
+        for (int q = 0; q < kCQ; ++q) {
+            const int b = b0 + 4 * q + kk;
+            a[q] = m[q] = float2{0.f, 0.f};
+            if (b < be) {
+                a[q] = VS[(int64_t)b * kpad];
+                m[q] = MS[(int64_t)b * kpad];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
+#pragma unroll
+        for (int q = 0; q < kCQ; ++q) c3mfma(acc, a[q], float2{m[q].x, -m[q].y});
+    }
+    // D layout: lane (j, g) register r holds row 4 g + r, column j
+    const int jj = lane & 15, gg = lane >> 4;
+    const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[w][(4 * gg + r) * 16 + jj] = float2{re[r], im[r]};
+    __syncthreads();
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < kGW; ++ww) {
+        sr += part[ww][tid].x;
+        si += part[ww][tid].y;
+    }
+    gmem(static_cast<float2 *>(d.Cblk))[((int64_t)p * csplit + split) * 256 + tid] = float2{sr, si};
+}
+
+// GH on the band tiles (ub, ab) of the user blocks ub = 4 ubg .. 4 ubg + 3
+// that meet antenna block ab: D[user i][antenna j] = sum_b v_b[i] conj(g_b[j])
+// (A = V^T, B = conj(GX)) over an RHS range. A wave loads the antenna
+// operands of 4 RHS once for all blocks of the group; v comes from the
+// VR-start-order copy (16 users = 128 contiguous bytes). The range is split
+// over the waves and reduced through LDS; the sum goes to GH (out null) or
+// to a partial.
+constexpr int kQ = 4;   // reduction steps (4 RHS each) per batch of loads
+
+__device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, int be0, float2 (*part)[kUG][256],
+                                            gp<float2> out)
 {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 15, kk = lane >> 4;
     const gp<const float2> VS = gmem(static_cast<const float2 *>(d.Vsrt));
-    const gp<const float2> MS = gmem(static_cast<const float2 *>(d.Msrt));
     const gp<const float2> GX = gmem(static_cast<const float2 *>(d.GX));
-    const gp<const float2> XA = gmem(static_cast<const float2 *>(d.Xadj));
-    const gp<const float2> X = gmem(static_cast<const float2 *>(d.X));
-    const int64_t ldgx = d.ldgx, ldx = d.ldx, ldxa = d.nt;
+    const int64_t ldgx = d.ldgx;
     const int nub = d.nub, kpad = nub * VRK_UB;
     const int ub0 = ubg * kUG;
     // blocks of the group that meet ab (wave-uniform)
-    bool live[kUG], first[kUG];
+    bool live[kUG];
 #pragma unroll
     for (int u = 0; u < kUG; ++u) {
         const int ub = ub0 + u;
         live[u] = ub < nub && gmem(d.rab_lo)[ub] <= ab && ab < gmem(d.rab_hi)[ub];
-        first[u] = live[u] && gmem(d.rab_lo)[ub] == ab;
     }
-    float gx = 0.f;
     const int n = ab * VRK_AB + i;           // B operand column (antenna) of this lane
     const bool nok = n < d.nt;
     const int per = (be0 - bs0 + kGW - 1) / kGW;
@@ -79,40 +131,27 @@ __device__ __forceinline__ float grads_group(CDesc &d, int ubg, int ab, int bs0,
     C3 acc[kUG];
 #pragma unroll
     for (int u = 0; u < kUG; ++u) acc[u] = C3{z, z, z};
-    constexpr int kQ = 2;   // MFMA reduction steps (4 RHS each) per iteration
     for (int b0 = bs; b0 < be; b0 += 4 * kQ) {
-        float2 y[kQ], xv[kQ], v[kQ][kUG], mu[kQ][kUG];
+        float2 y[kQ], v[kQ][kUG];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             const int b = b0 + 4 * q + kk;
             const bool bok = b < be;
-            y[q] = xv[q] = float2{0.f, 0.f};
-            if (bok && nok) {
-                const float2 gx = GX[(int64_t)b * ldgx + n], xa = XA[(int64_t)b * ldxa + n];
-                y[q] = float2{gx.x - xa.x, gx.y - xa.y};
-                xv[q] = X[(int64_t)b * ldx + n];
-            }
+            y[q] = float2{0.f, 0.f};
+            if (bok && nok) y[q] = GX[(int64_t)b * ldgx + n];
 #pragma unroll
             for (int u = 0; u < kUG; ++u) {
-                v[q][u] = mu[q][u] = float2{0.f, 0.f};
-                if (live[u] && bok) {
-                    const int64_t o = (int64_t)b * kpad + (ub0 + u) * VRK_UB + i;
-                    v[q][u] = VS[o];
-                    mu[q][u] = MS[o];
-                }
+                v[q][u] = float2{0.f, 0.f};
+                if (live[u] && bok) v[q][u] = VS[(int64_t)b * kpad + (ub0 + u) * VRK_UB + i];
             }
         }
+        __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
-            const float2 cy = float2{y[q].x, -y[q].y}, cx_ = float2{xv[q].x, -xv[q].y};
+            const float2 cy = float2{y[q].x, -y[q].y};
 #pragma unroll
-            for (int u = 0; u < kUG; ++u) {
-                if (first[u]) gx += mu[q][u].x * v[q][u].x + mu[q][u].y * v[q][u].y;
-                if (live[u]) {
-                    c3mfma(acc[u], v[q][u], cy);                                  // v conj(y)
-                    c3mfma(acc[u], float2{-mu[q][u].x, -mu[q][u].y}, cx_);        // - mu conj(x)
-                }
-            }
+            for (int u = 0; u < kUG; ++u)
+                if (live[u]) c3mfma(acc[u], v[q][u], cy);
         }
     }
     // D layout: lane (j, g) register r holds user 4 g + r, antenna j
@@ -145,92 +184,163 @@ __device__ __forceinline__ float grads_group(CDesc &d, int ubg, int ab, int bs0,
             }
         }
     }
-    return gx;
 }
 
-// Workgroup (tile, u): sum the RHS-split partials of user block 4 ubg + u of
-// the tile in fixed order and write its VR band entries of GH (nsplit > 1).
-// Workgroup (first tile of a problem, 0) also adds the gxi partials of its
-// problem's tiles.
-__global__ void __launch_bounds__(256) k_adj_grads_reduce(const VrkDesc *descs, const int4 *tiles, int nsplit,
-                                                          const float2 *gpart, const float *gxpart)
-{
-    const int4 tl = gmem(tiles)[blockIdx.x];
-    CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
-    const int tid = threadIdx.x, u = blockIdx.y;
-    const int flags = __builtin_amdgcn_readfirstlane(tl.w);
-    if ((flags & 1) && u == 0 && tid < 64) {
-        // this problem's tiles: blockIdx.x and the next (flags >> 2) - 1
-        const int64_t n = (int64_t)(flags >> 2) * nsplit, e0 = (int64_t)blockIdx.x * nsplit;
-        float t = 0.f;
-        for (int64_t e = tid; e < n; e += 64) t += gmem(gxpart)[e0 + e];
-        t = wave_sum(t);
-        if (tid == 0) *gmem(d.gxi) = -(double)t;
-    }
-    if (nsplit <= 1 || tl.y < 0) return;
-    const int ub = __builtin_amdgcn_readfirstlane(tl.y) * kUG + u, ab = __builtin_amdgcn_readfirstlane(tl.z);
-    if (ub >= d.nub || ab < gmem(d.rab_lo)[ub] || ab >= gmem(d.rab_hi)[ub]) return;
-    const int ii = tid >> 4, nj = tid & 15, nn = ab * VRK_AB + nj;
-    const gp<const float2> src = gmem(gpart) + (int64_t)blockIdx.x * nsplit * kUG * 256 + u * 256 + tid;
-    float sr = 0.f, si = 0.f;
-#pragma unroll 8
-    for (int sp = 0; sp < nsplit; ++sp) {
-        const float2 p = src[(int64_t)sp * kUG * 256];
-        sr += p.x;
-        si += p.y;
-    }
-    const int kq = ub * VRK_UB + ii;
-    if (kq < d.k) {
-        const int us = gmem(d.perm)[kq];
-        if (nn >= gmem(d.vs)[us] && nn < gmem(d.ve)[us])
-            gmem(static_cast<float2 *>(d.GH))[(int64_t)us * d.ldgh + nn] = float2{sr, si};
-    }
-}
-
-// Workgroup (tile, split): one RHS range of a tile; with nsplit 1 it writes
-// GH directly, else its partials to gpart. Every workgroup writes its share
-// of sum_{b,k} conj(mu) v (dL/dxi is minus its real part) to gxpart: the
-// users of the blocks whose first antenna block is the tile's, over its RHS
-// range, from the v and mu it loads anyway.
-__global__ void __launch_bounds__(kGW * 64) k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, int nsplit,
-                                                             float2 *gpart, float *gxpart)
+// Workgroups [0, nctile): the C blocks (problem, block, split, row block);
+// then (band tile, split): one RHS range of a band tile, written to GH with
+// nsplit 1, else to its partial in gpart. Four waves per SIMD (left alone,
+// the compiler takes a third more registers and three).
+__global__ void __launch_bounds__(kGW * 64) __attribute__((amdgpu_waves_per_eu(4)))
+k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, int nsplit, const int4 *ctiles, int nctile, int csplit,
+                 float2 *gpart)
 {
     __shared__ float2 part[kGW][kUG][256];
-    __shared__ float red[kGW];
-    const int tix = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+    if ((int)blockIdx.x < nctile) {
+        const int4 tl = gmem(ctiles)[blockIdx.x];
+        CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
+        cmat_part(d, __builtin_amdgcn_readfirstlane(tl.y), __builtin_amdgcn_readfirstlane(tl.w),
+                  __builtin_amdgcn_readfirstlane(tl.z), csplit, part[0]);
+        return;
+    }
+    const int bid = blockIdx.x - nctile;
+    const int tix = bid / nsplit, split = bid % nsplit;
     const int4 tl = gmem(tiles)[tix];   // (problem, user-block group, antenna block, flags)
     CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
     const int ubg = __builtin_amdgcn_readfirstlane(tl.y), ab = __builtin_amdgcn_readfirstlane(tl.z);
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    if (ubg < 0) return;
     const int B = d.nrhs;
     const int per = (B + nsplit - 1) / nsplit;
     const int bs0 = min(B, split * per), be0 = min(B, bs0 + per);
-    // the workgroup's share of sum conj(mu) v (dL/dxi = -Re of the total)
-    float acc = 0.f;
-    if (ubg >= 0)
-        acc = grads_group(d, ubg, ab, bs0, be0, part,
-                          nsplit > 1 ? gmem(gpart) + ((int64_t)tix * nsplit + split) * kUG * 256 : nullptr);
-    acc = wave_sum(acc);
-    if (lane == 0) red[w] = acc;
-    __syncthreads();
-    if (tid == 0) {
+    grads_group(d, ubg, ab, bs0, be0, part,
+                nsplit > 1 ? gmem(gpart) + ((int64_t)tix * nsplit + split) * kUG * 256 : nullptr);
+}
+
+// Workgroup (band tile), wave u: user block ub = 4 ubg + u on antenna block
+// ab. Its entries start from the sum of the RHS-split partials in fixed
+// order (nsplit > 1) or from GH; then acc -= (C + C^H)[block ub, :]
+// H[:, block ab] over the column blocks ub' of ub whose bands meet ab, as an
+// MFMA product with A[i][k] = -(C + C^H) entry (16 ub + i, 16 ub' + k) (C
+// summed over its splits) and B[k][j] = H of user 16 ub' + k at antenna
+// 16 ab + j from the residual tiles of ub' (zero off the VRs); the result
+// goes to the VR band entries of GH. Wave 0 of a problem's first tile also
+// writes dL/dxi = -Re tr C.
+__global__ void __launch_bounds__(kGW * 64) k_adj_grads_reduce(const VrkDesc *descs, const int4 *tiles, int nsplit,
+                                                             int csplit, const float2 *gpart)
+{
+    const int4 tl = gmem(tiles)[blockIdx.x];
+    CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+    const int flags = __builtin_amdgcn_readfirstlane(tl.w);
+    const gp<const float2> CB = gmem(static_cast<const float2 *>(d.Cblk));
+    if ((flags & 1) && w == 0) {
         float t = 0.f;
-        for (int q = 0; q < kGW; ++q) t += red[q];
-        gmem(gxpart)[blockIdx.x] = t;
+        for (int e = lane; e < d.nub * VRK_UB; e += 64) {
+            const int64_t p = gmem(d.cp_diag)[e >> 4];
+            for (int cs = 0; cs < csplit; ++cs) t += CB[(p * csplit + cs) * 256 + (e & 15) * 17].x;
+        }
+        t = wave_sum(t);
+        if (lane == 0) *gmem(d.gxi) = -(double)t;
     }
+    if (tl.y < 0) return;
+    const int ub = __builtin_amdgcn_readfirstlane(tl.y) * kUG + w, ab = __builtin_amdgcn_readfirstlane(tl.z);
+    if (ub >= d.nub || ab < gmem(d.rab_lo)[ub] || ab >= gmem(d.rab_hi)[ub]) return;
+    // this lane's entries: user 16 ub + 4 g + r, antenna 16 ab + j (D layout)
+    const int j = i, g = kk, nn = ab * VRK_AB + j;
+    bool in[4];
+    int64_t gh[4];
+    f4 r0, i0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int kq = ub * VRK_UB + 4 * g + r;
+        in[r] = false;
+        gh[r] = 0;
+        if (kq < d.k) {
+            const int us = gmem(d.perm)[kq];
+            in[r] = nn >= gmem(d.vs)[us] && nn < gmem(d.ve)[us];
+            gh[r] = (int64_t)us * d.ldgh + nn;
+        }
+        r0[r] = i0[r] = 0.f;
+    }
+    const gp<float2> GH = gmem(static_cast<float2 *>(d.GH));
+    if (nsplit > 1) {
+        const gp<const float2> src = gmem(gpart) + (int64_t)blockIdx.x * nsplit * kUG * 256 + w * 256;
+#pragma unroll 4
+        for (int sp = 0; sp < nsplit; ++sp)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float2 p = src[(int64_t)sp * kUG * 256 + (4 * g + r) * 16 + j];
+                r0[r] += p.x;
+                i0[r] += p.y;
+            }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (in[r]) {
+                const float2 p = GH[gh[r]];
+                r0[r] = p.x;
+                i0[r] = p.y;
+            }
+    }
+    // C3 state with Re = u - v = r0 and Im = w - u - v = i0
+    C3 acc = {r0, f4{0.f, 0.f, 0.f, 0.f}, r0 + i0};
+    const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
+    const int p0 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub]);
+    const int p1 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub + 1]);
+#pragma unroll 1
+    for (int p = p0; p < p1; ++p) {
+        const int ubc = __builtin_amdgcn_readfirstlane(gmem(d.cp_col)[p]);
+        const int lo = __builtin_amdgcn_readfirstlane(gmem(d.rab_lo)[ubc]);
+        if (ab < lo || ab >= gmem(d.rab_hi)[ubc]) continue;
+        const int pt = __builtin_amdgcn_readfirstlane(gmem(d.cp_tr)[p]);
+        // residual tile c of ub' holds H[16 ub' + i'][16 ab + 4 kk' + m] at
+        // 64 m + i' + 16 kk' (ab = lo + c / 4, m = c % 4)
+        const gp<const float2> ht = HA + (gmem(d.ha_off)[ubc] + 4 * (int64_t)(ab - lo)) * 64;
+        float2 c1[kMaxCsplit][4], c2[kMaxCsplit][4], h[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + kk;
+            h[s] = ht[64 * (i & 3) + k + 16 * (i >> 2)];
+#pragma unroll
+            for (int cs = 0; cs < kMaxCsplit; ++cs) {
+                c1[cs][s] = c2[cs][s] = float2{0.f, 0.f};
+                if (cs < csplit) {
+                    c1[cs][s] = CB[((int64_t)p * csplit + cs) * 256 + i * 16 + k];
+                    c2[cs][s] = CB[((int64_t)pt * csplit + cs) * 256 + k * 16 + i];
+                }
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int cs = 0; cs < kMaxCsplit; ++cs) {
+                ar += c1[cs][s].x + c2[cs][s].x;
+                ai += c1[cs][s].y - c2[cs][s].y;
+            }
+            c3mfma(acc, float2{-ar, -ai}, h[s]);
+        }
+    }
+    const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (in[r]) GH[gh[r]] = float2{re[r], im[r]};
 }
 
 
 }  // namespace
 
 hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
-                                         float2 *gpart, float *gxpart, hipStream_t s)
+                                         const int4 *ctiles, int32_t nctiles, int32_t csplit, float2 *gpart,
+                                         hipStream_t s)
 {
-    if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_grads_mfma, dim3((unsigned)ntiles * nsplit), dim3(kGW * 64), 0, s, desc, tiles, nsplit,
-                       gpart, gxpart);
+    if (csplit < 1 || csplit > kMaxCsplit) return hipErrorInvalidValue;
+    const int64_t nwg = (int64_t)nctiles + (int64_t)ntiles * nsplit;
+    if (nwg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_grads_mfma, dim3((unsigned)nwg), dim3(kGW * 64), 0, s, desc, tiles, nsplit, ctiles,
+                       nctiles, csplit, gpart);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_grads_reduce, dim3(ntiles, kUG), dim3(256), 0, s, desc, tiles, nsplit, gpart, gxpart);
+    if (e != hipSuccess || ntiles <= 0) return e;
+    hipLaunchKernelGGL(k_adj_grads_reduce, dim3(ntiles), dim3(kGW * 64), 0, s, desc, tiles, nsplit, csplit, gpart);
     return hipGetLastError();
 }

@@ -53,12 +53,17 @@ hipError_t vrk_launch_adjoint_rhs(const VrkDesc *desc, int32_t nprob, int32_t ma
 hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t max_k,
                                     int32_t dtype, hipStream_t s);
 // MFMA version of the gradient assembly (complex64, plans of the MFMA
-// engine, whose solve forms b = H g itself).
-// Tiles are (problem, user-block group, antenna block, flags: bit 0 first
-// tile of its problem, bit 1 unused, bits 2.. on a problem's
-// first tile: its problem's tile count). nsplit > 1 splits each
-// tile's RHS range over nsplit workgroups writing partials to gpart
-// (ntiles * nsplit * VRK_GRAD_UG * 256 complex64); gxpart (ntiles * nsplit
-// floats) takes the partials of dL/dxi. A second kernel sums both in fixed order.
+// engine, whose solve forms b = H g itself and leaves H^H mu unformed).
+// GH = sum_b v_b g_b^H - (C + C^H) H with C = sum_b v_b mu_b^H and
+// gxi = -Re tr C. C tiles are (problem, C block, RHS split, row block): the
+// first nctiles workgroups of the first kernel write their partials to each
+// problem's Cblk (csplit, 1..4, per block). Band tiles are (problem,
+// user-block group, antenna block, flags: bit 0 first tile of its problem,
+// bit 1 unused, bits 2.. on a problem's first tile: its problem's tile
+// count). nsplit > 1 splits each band tile's RHS range over nsplit
+// workgroups writing partials to gpart (ntiles * nsplit * VRK_GRAD_UG * 256
+// complex64), else they write GH; a second kernel sums the partials in fixed
+// order, subtracts (C + C^H) H on the band and writes gxi.
 hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
-                                         float2 *gpart, float *gxpart, hipStream_t s);
+                                         const int4 *ctiles, int32_t nctiles, int32_t csplit, float2 *gpart,
+                                         hipStream_t s);

@@ -472,7 +472,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     int64_t ldx_, ldv_;
     if (a.adjoint) {
         c.S = nullptr; c.lds = 0;   // b = H g is formed by the tile itself
-        X = gmem(static_cast<float2 *>(d.Xadj)); ldx_ = c.N;
+        X = nullptr; ldx_ = 0;      // H^H mu is not formed
         V = gmem(static_cast<float2 *>(d.GS)); ldv_ = d.ldgs;
     } else {
         c.S = gmem(static_cast<const float2 *>(d.S)); c.lds = d.lds;
@@ -752,7 +752,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         for (int k = 0; k < EP; ++k)
             if (own(k) < kpad) L.PV[own(k) * 16 + j] = qq[k];
         __syncthreads();
-        form_x<W>(c);
+        if (!a.adjoint) form_x<W>(c);   // the gradient products need no H^H mu
         gram_part<W, GR>(c, L.PV, gr, false, false);
         __syncthreads();
         float t2 = 0.f, tn = 0.f;
@@ -789,7 +789,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         num = tn;
     }
 
-    // ---- outputs: x is in place (form_x); v (or mu) in caller order and in
+    // ---- outputs: x is in place (form_x, forward only); v (or mu) in caller order and in
     // VR-start order for the gradient products
     {
         const int b = b0 + j;

@@ -69,6 +69,7 @@ struct ProbPlan {
     int32_t nub = 0, nab = 0, ntile = 0;
     std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, gm_off, gm_c, gm_nf, fpos;
     int32_t nmf = 0;   // columns of MF (F users) when the solve takes the F half-step on the VALU
+    std::vector<int32_t> cp_off, cp_col, cp_tr, cp_diag;   // blocks of C on the Gram block pattern
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
     // workspace offsets
@@ -77,6 +78,7 @@ struct ProbPlan {
         o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
     size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_gmnf = 0, o_fpos = 0, o_mf = 0;
+    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0;
 };
 
 }  // namespace
@@ -96,7 +98,10 @@ struct vrk_plan {
     int32_t qbase[VRK_NQUEUE] = {0}, qsize[VRK_NQUEUE] = {0};
     size_t o_queue = 0;         // int32 counters[8], base[8], size[8]
     int32_t gsplit = 1;         // RHS splits of the adjoint gradient tiles
-    size_t o_gpart = 0, o_gxpart = 0;
+    size_t o_gpart = 0;
+    std::vector<int4> ctiles;   // (problem, C block, split, row block) of the adjoint C blocks
+    size_t o_ctiles = 0;
+    int32_t csplit = 1;         // RHS splits of the C blocks (1..4)
     int32_t persistent = 0, grid = 0;
     int32_t max_nub = 0;
     std::vector<uint8_t> image;
@@ -314,6 +319,32 @@ void build_tables(ProbPlan &q)
     }
     q.gm_off[q.nub] = (int32_t)q.gm_c.size();
     q.n_gm = (int64_t)q.gm_c.size();
+    // 16 x 16 blocks (ub, ub') of the same pattern, for C = sum_b v_b mu_b^H
+    // of the adjoint gradient; the pattern is symmetric and holds every
+    // diagonal block
+    q.cp_off.assign(q.nub + 1, 0);
+    q.cp_col.clear();
+    for (int mb = 0; mb < q.nub; ++mb) {
+        q.cp_off[mb] = (int32_t)q.cp_col.size();
+        std::vector<int32_t> cols;
+        for (int e = q.gm_off[mb]; e < q.gm_off[mb + 1]; ++e)
+            if (q.gm_c[e] >= 0) cols.push_back(q.gm_c[e] / (VRK_UB / 4));
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        q.cp_col.insert(q.cp_col.end(), cols.begin(), cols.end());
+    }
+    q.cp_off[q.nub] = (int32_t)q.cp_col.size();
+    auto find_block = [&](int r, int c) {
+        auto b0 = q.cp_col.begin() + q.cp_off[r], b1 = q.cp_col.begin() + q.cp_off[r + 1];
+        auto it = std::lower_bound(b0, b1, c);
+        return (it != b1 && *it == c) ? (int32_t)(it - q.cp_col.begin()) : -1;
+    };
+    q.cp_tr.assign(q.cp_col.size(), -1);
+    q.cp_diag.assign(q.nub, -1);
+    for (int mb = 0; mb < q.nub; ++mb) {
+        for (int e = q.cp_off[mb]; e < q.cp_off[mb + 1]; ++e) q.cp_tr[e] = find_block(q.cp_col[e], mb);
+        q.cp_diag[mb] = find_block(mb, mb);
+    }
 }
 
 template <class T>
@@ -479,6 +510,18 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             int64_t want = 4096 / (int64_t)pl->gtiles.size();
             int64_t cap = std::max<int64_t>(1, min_rhs / 64);
             pl->gsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 16}));
+            // C blocks: up to 4 RHS splits while there are fewer than 1024
+            // blocks, each split keeping at least 256 right-hand sides
+            int64_t nblk = 0;
+            for (const auto &q : pl->pp) nblk += (int64_t)q.cp_col.size();
+            pl->csplit = (int32_t)std::max<int64_t>(
+                1, std::min<int64_t>({1024 / std::max<int64_t>(1, nblk), min_rhs / 256, 4}));
+            for (int i = 0; i < nprob; ++i) {
+                const ProbPlan &q = pl->pp[i];
+                for (int mb = 0; mb < q.nub; ++mb)
+                    for (int e = q.cp_off[mb]; e < q.cp_off[mb + 1]; ++e)
+                        for (int cs = 0; cs < pl->csplit; ++cs) pl->ctiles.push_back(make_int4(i, e, cs, mb));
+            }
         }
     }
     // workspace carving
@@ -488,8 +531,8 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     pl->o_work = cv.take(sizeof(VrkWork) * std::max<size_t>(1, pl->work.size()));
     pl->o_gtiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->gtiles.size()));
     pl->o_queue = cv.take(sizeof(int32_t) * 3 * VRK_NQUEUE);
+    pl->o_ctiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->ctiles.size()));
     pl->o_gpart = cv.take(pl->gsplit > 1 ? pl->gtiles.size() * (size_t)pl->gsplit * VRK_GRAD_UG * 256 * 8 : 0);
-    pl->o_gxpart = cv.take(pl->gtiles.size() * (size_t)pl->gsplit * 4);
     for (auto &q : pl->pp) {
         const int K = q.p.k;
         q.o_vs = cv.take(4 * K);
@@ -514,6 +557,10 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_gmc = cv.take(4 * q.gm_c.size());
         q.o_gmnf = cv.take(4 * q.gm_nf.size());
         q.o_fpos = cv.take(4 * q.fpos.size());
+        q.o_cpoff = cv.take(4 * q.cp_off.size());
+        q.o_cpcol = cv.take(4 * q.cp_col.size());
+        q.o_cptr = cv.take(4 * q.cp_tr.size());
+        q.o_cpdiag = cv.take(4 * q.cp_diag.size());
     }
     pl->table_end = cv.off;
     for (auto &q : pl->pp) {
@@ -530,11 +577,12 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         }
         if (q.p.GX) {
             q.o_sadj = cv.take((size_t)eb * q.p.nrhs * q.p.k);
-            q.o_xadj = cv.take((size_t)eb * q.p.nrhs * q.p.nt);
+            q.o_xadj = eng == VRK_ENGINE_MFMA ? 0 : cv.take((size_t)eb * q.p.nrhs * q.p.nt);
             q.o_vfwd = q.p.V ? 0 : cv.take((size_t)eb * q.p.nrhs * q.p.k);
             if (eng == VRK_ENGINE_MFMA) {
                 q.o_vsrt = cv.take((size_t)8 * q.p.nrhs * q.nub * VRK_UB);
                 q.o_msrt = cv.take((size_t)8 * q.p.nrhs * q.nub * VRK_UB);
+                q.o_cblk = cv.take((size_t)8 * 256 * q.cp_col.size() * pl->csplit);
             }
         }
     }
@@ -581,6 +629,10 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         put(img, q.o_gmoff, q.gm_off);
         put(img, q.o_gmc, q.gm_c);
         put(img, q.o_gmnf, q.gm_nf);
+        put(img, q.o_cpoff, q.cp_off);
+        put(img, q.o_cpcol, q.cp_col);
+        put(img, q.o_cptr, q.cp_tr);
+        put(img, q.o_cpdiag, q.cp_diag);
         put(img, q.o_fpos, q.fpos);
         VrkDesc &d = descs[i];
         std::memset(&d, 0, sizeof d);
@@ -597,11 +649,16 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.V = p.V ? p.V : (p.GX ? base + q.o_vfwd : nullptr);
         d.GX = p.GX; d.GH = p.GH; d.GS = p.GS; d.gxi = p.gxi;
         d.Sadj = p.GX ? base + q.o_sadj : nullptr;
-        d.Xadj = p.GX ? base + q.o_xadj : nullptr;
+        d.Xadj = p.GX && pl->engine != VRK_ENGINE_MFMA ? base + q.o_xadj : nullptr;
         d.Vfwd = nullptr;
         const bool srt = p.GX && pl->engine == VRK_ENGINE_MFMA;
         d.Vsrt = srt ? base + q.o_vsrt : nullptr;
         d.Msrt = srt ? base + q.o_msrt : nullptr;
+        d.cp_off = (const int32_t *)(base + q.o_cpoff);
+        d.cp_col = (const int32_t *)(base + q.o_cpcol);
+        d.cp_tr = (const int32_t *)(base + q.o_cptr);
+        d.cp_diag = (const int32_t *)(base + q.o_cpdiag);
+        d.Cblk = srt ? base + q.o_cblk : nullptr;
         d.vs = (const int32_t *)(base + q.o_vs);
         d.ve = (const int32_t *)(base + q.o_ve);
         d.xoff = (const int32_t *)(base + q.o_xoff);
@@ -638,6 +695,8 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         std::memcpy(pl->image.data() + pl->o_work, pl->work.data(), sizeof(VrkWork) * pl->work.size());
     if (!pl->gtiles.empty())
         std::memcpy(pl->image.data() + pl->o_gtiles, pl->gtiles.data(), sizeof(int4) * pl->gtiles.size());
+    if (!pl->ctiles.empty())
+        std::memcpy(pl->image.data() + pl->o_ctiles, pl->ctiles.data(), sizeof(int4) * pl->ctiles.size());
     {
         int32_t *qv = reinterpret_cast<int32_t *>(pl->image.data() + pl->o_queue);
         for (int qi = 0; qi < VRK_NQUEUE; ++qi) {
@@ -738,8 +797,9 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
     if (st != VRK_OK) return st;
     e = mf ? vrk_launch_adjoint_grads_mfma(dd, reinterpret_cast<const int4 *>(pl->d_ws + pl->o_gtiles),
                                            (int32_t)pl->gtiles.size(), pl->gsplit,
-                                           reinterpret_cast<float2 *>(pl->d_ws + pl->o_gpart),
-                                           reinterpret_cast<float *>(pl->d_ws + pl->o_gxpart), s)
+                                           reinterpret_cast<const int4 *>(pl->d_ws + pl->o_ctiles),
+                                           (int32_t)pl->ctiles.size(), pl->csplit,
+                                           reinterpret_cast<float2 *>(pl->d_ws + pl->o_gpart), s)
            : vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient kernel");
     return VRK_OK;
@@ -757,7 +817,8 @@ int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *
     case VRK_Q_XOFF: v = q.xoff; break;
     case VRK_Q_XIDX: v = q.xidx; break;
     case VRK_Q_ENGINE:
-        v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->ep, pl->gsplit};
+        v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->ep, pl->gsplit,
+             pl->csplit};
         break;
     case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band, (int32_t)q.n_gm}; break;
     default: return -1;

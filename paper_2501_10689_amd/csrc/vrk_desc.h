@@ -32,7 +32,7 @@ struct VrkDesc {
     void *GS;
     double *gxi;
     void *Sadj;                   // workspace, B x K: right-hand side H g of the adjoint
-    void *Xadj;                   // workspace, B x Nt: x of the adjoint solve (H^H mu)
+    void *Xadj;                   // workspace, B x Nt: x of the adjoint solve (H^H mu); vector engine
     void *Vfwd;                   // V of the forward solve when the caller passed none
     // VR tables, original user index unless noted
     const int32_t *vs, *ve;       // VR [start, end)
@@ -59,6 +59,13 @@ struct VrkDesc {
     // adjoint solve again, [rhs][nub * 16] complex64 in VR-start user order
     // (zero on the padding users), for the gradient products
     void *Vsrt, *Msrt;
+    // MFMA engine with adjoint buffers: the 16 x 16 blocks (ub, ub') of
+    // C = sum_b v_b mu_b^H on the Gram block pattern. Blocks of row block ub
+    // are [cp_off[ub], cp_off[ub + 1]), column block cp_col[p], transposed
+    // block cp_tr[p]; cp_diag[ub] is block (ub, ub). Cblk holds their
+    // RHS-split partials, [block][split][16 x 16] complex64 (row-major).
+    const int32_t *cp_off, *cp_col, *cp_tr, *cp_diag;
+    void *Cblk;
     // MFMA engine, VR-OAHK with 1..16 users in F and a nonempty V: the F
     // columns of M, MF[ku][t] = M[perm[ku]][flist[t]] complex64 (nub * 16
     // rows, rounded once from double), and fpos[t] = pos[flist[t]]
