@@ -215,24 +215,30 @@ k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, int nsplit, const int4
                 nsplit > 1 ? gmem(gpart) + ((int64_t)tix * nsplit + split) * kUG * 256 : nullptr);
 }
 
-// Workgroup (band tile), wave u: user block ub = 4 ubg + u on antenna block
-// ab. Its entries start from the sum of the RHS-split partials in fixed
+// Workgroup (run of consecutive band tiles of one user-block group), wave u:
+// user block ub = 4 ubg + u on the antenna blocks ab of the run's tiles. Per
+// tile its entries start from the sum of the RHS-split partials in fixed
 // order (nsplit > 1) or from GH; then acc -= (C + C^H)[block ub, :]
-// H[:, block ab] over the column blocks ub' of ub whose bands meet ab, as an
-// MFMA product with A[i][k] = -(C + C^H) entry (16 ub + i, 16 ub' + k) (C
-// summed over its splits) and B[k][j] = H of user 16 ub' + k at antenna
-// 16 ab + j from the residual tiles of ub' (zero off the VRs); the result
-// goes to the VR band entries of GH. Wave 0 of a problem's first tile also
-// writes dL/dxi = -Re tr C.
-__global__ void __launch_bounds__(kGW * 64) k_adj_grads_reduce(const VrkDesc *descs, const int4 *tiles, int nsplit,
-                                                             int csplit, const float2 *gpart)
+// H[:, block ab] as an MFMA product over the column blocks ub' of ub whose
+// bands meet ab, with A[i][k] = -(C + C^H) entry (16 ub + i, 16 ub' + k) (C
+// summed over its splits; kRP blocks held in registers per pass over the
+// run) and B[k][j] = H of user 16 ub' + k at antenna 16 ab + j from the
+// residual tiles of ub' (zero off the VRs); the result goes to the VR band
+// entries of GH. Wave 0 of a problem's first run also writes
+// dL/dxi = -Re tr C.
+constexpr int kRP = 4;
+
+__global__ void __launch_bounds__(kGW * 64) __attribute__((amdgpu_waves_per_eu(4))) k_adj_grads_reduce(const VrkDesc *descs, const int4 *tiles,
+                                                             const int4 *runs, int nsplit, int csplit,
+                                                             const float2 *gpart)
 {
-    const int4 tl = gmem(tiles)[blockIdx.x];
-    CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
+    const int4 rn = gmem(runs)[blockIdx.x];   // (first tile, tile count, flags, 0)
+    const int t0 = __builtin_amdgcn_readfirstlane(rn.x), nt = __builtin_amdgcn_readfirstlane(rn.y);
+    const int4 tl0 = gmem(tiles)[t0];
+    CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl0.x)];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
-    const int flags = __builtin_amdgcn_readfirstlane(tl.w);
     const gp<const float2> CB = gmem(static_cast<const float2 *>(d.Cblk));
-    if ((flags & 1) && w == 0) {
+    if ((__builtin_amdgcn_readfirstlane(rn.z) & 1) && w == 0) {
         float t = 0.f;
         for (int e = lane; e < d.nub * VRK_UB; e += 64) {
             const int64_t p = gmem(d.cp_diag)[e >> 4];
@@ -241,98 +247,233 @@ __global__ void __launch_bounds__(kGW * 64) k_adj_grads_reduce(const VrkDesc *de
         t = wave_sum(t);
         if (lane == 0) *gmem(d.gxi) = -(double)t;
     }
-    if (tl.y < 0) return;
-    const int ub = __builtin_amdgcn_readfirstlane(tl.y) * kUG + w, ab = __builtin_amdgcn_readfirstlane(tl.z);
-    if (ub >= d.nub || ab < gmem(d.rab_lo)[ub] || ab >= gmem(d.rab_hi)[ub]) return;
+    const int ubg = __builtin_amdgcn_readfirstlane(tl0.y);
+    if (ubg < 0) return;
+    const int ub = ubg * kUG + w;
+    if (ub >= d.nub) return;
+    const int lo_ub = gmem(d.rab_lo)[ub], hi_ub = gmem(d.rab_hi)[ub];
     // this lane's entries: user 16 ub + 4 g + r, antenna 16 ab + j (D layout)
-    const int j = i, g = kk, nn = ab * VRK_AB + j;
-    bool in[4];
-    int64_t gh[4];
-    f4 r0, i0;
+    const int j = i, g = kk;
+    int us[4], vs[4], ve[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int kq = ub * VRK_UB + 4 * g + r;
-        in[r] = false;
-        gh[r] = 0;
+        us[r] = -1;
+        vs[r] = ve[r] = 0;
         if (kq < d.k) {
-            const int us = gmem(d.perm)[kq];
-            in[r] = nn >= gmem(d.vs)[us] && nn < gmem(d.ve)[us];
-            gh[r] = (int64_t)us * d.ldgh + nn;
+            us[r] = gmem(d.perm)[kq];
+            vs[r] = gmem(d.vs)[us[r]];
+            ve[r] = gmem(d.ve)[us[r]];
         }
-        r0[r] = i0[r] = 0.f;
     }
     const gp<float2> GH = gmem(static_cast<float2 *>(d.GH));
-    if (nsplit > 1) {
-        const gp<const float2> src = gmem(gpart) + (int64_t)blockIdx.x * nsplit * kUG * 256 + w * 256;
+    const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
+    const int p0 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub]);
+    const int p1 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub + 1]);
+#pragma unroll 1
+    for (int pb = p0; pb < p1; pb += kRP) {
+        // A operands of this pass's blocks, one RHS split of all of them at a time
+        float2 A[kRP][4];
+        int lo[kRP], hi[kRP], pc[kRP], pt[kRP];
+        int64_t hoff[kRP];
+#pragma unroll
+        for (int q = 0; q < kRP; ++q) {
+            const int p = min(pb + q, p1 - 1);
+            const int ubc = __builtin_amdgcn_readfirstlane(gmem(d.cp_col)[p]);
+            pc[q] = p;
+            pt[q] = __builtin_amdgcn_readfirstlane(gmem(d.cp_tr)[p]);
+            lo[q] = __builtin_amdgcn_readfirstlane(gmem(d.rab_lo)[ubc]);
+            hi[q] = __builtin_amdgcn_readfirstlane(gmem(d.rab_hi)[ubc]);
+            hoff[q] = gmem(d.ha_off)[ubc];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) A[q][s] = float2{0.f, 0.f};
+        }
+#pragma unroll 1
+        for (int cs = 0; cs < csplit; ++cs)
+#pragma unroll
+            for (int q0 = 0; q0 < kRP; q0 += 2) {   // two blocks' loads at a time
+                float2 c1[2][4], c2[2][4];
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = 4 * s + kk;
+                        c1[q][s] = CB[((int64_t)pc[q0 + q] * csplit + cs) * 256 + i * 16 + k];
+                        c2[q][s] = CB[((int64_t)pt[q0 + q] * csplit + cs) * 256 + k * 16 + i];
+                    }
+                __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        float2 &x = A[q0 + q][s];
+                        x = float2{x.x - c1[q][s].x - c2[q][s].x, x.y - c1[q][s].y + c2[q][s].y};
+                    }
+            }
+#pragma unroll 1
+        for (int t = t0; t < t0 + nt; ++t) {
+            const int ab = __builtin_amdgcn_readfirstlane(gmem(tiles)[t].z);
+            if (ab < lo_ub || ab >= hi_ub) continue;
+            const int nn = ab * VRK_AB + j;
+            bool in[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) in[r] = us[r] >= 0 && nn >= vs[r] && nn < ve[r];
+            // residual tile c of ub' holds H[16 ub' + i'][16 ab + 4 kk' + m] at
+            // 64 m + i' + 16 kk' (ab = lo + c / 4, m = c % 4)
+            float2 h[kRP][4];
+#pragma unroll
+            for (int q = 0; q < kRP; ++q) {
+                const bool meets = pb + q < p1 && ab >= lo[q] && ab < hi[q];
+                const gp<const float2> ht = HA + (hoff[q] + 4 * (int64_t)(ab - lo[q])) * 64;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    h[q][s] = float2{0.f, 0.f};
+                    if (meets) h[q][s] = ht[64 * (i & 3) + 4 * s + kk + 16 * (i >> 2)];
+                }
+            }
+            f4 r0, i0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) r0[r] = i0[r] = 0.f;
+            if (pb == p0 && nsplit > 1) {
+                const gp<const float2> src = gmem(gpart) + (int64_t)t * nsplit * kUG * 256 + w * 256;
 #pragma unroll 4
-        for (int sp = 0; sp < nsplit; ++sp)
+                for (int sp = 0; sp < nsplit; ++sp)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float2 p = src[(int64_t)sp * kUG * 256 + (4 * g + r) * 16 + j];
+                        r0[r] += p.x;
+                        i0[r] += p.y;
+                    }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (in[r]) {
+                        const float2 p = GH[(int64_t)us[r] * d.ldgh + nn];
+                        r0[r] = p.x;
+                        i0[r] = p.y;
+                    }
+            }
+            // C3 state with Re = u - v = r0 and Im = w - u - v = i0
+            C3 acc = {r0, f4{0.f, 0.f, 0.f, 0.f}, r0 + i0};
+#pragma unroll
+            for (int q = 0; q < kRP; ++q)
+                if (pb + q < p1 && ab >= lo[q] && ab < hi[q])
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) c3mfma(acc, A[q][s], h[q][s]);
+            const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (in[r]) GH[(int64_t)us[r] * d.ldgh + nn] = float2{re[r], im[r]};
+        }
+    }
+}
+
+
+// Tiles with RHS splits (nsplit > 1; few tiles): workgroup (band tile) of
+// 16 waves, wave (u, x) taking user block ub = 4 ubg + u, the splits
+// x, x + 4, ... and the column blocks p0 + x, p0 + x + 4, ... of the
+// correction (as in k_adj_grads_reduce, C summed over its splits); the four
+// waves of a block are added through LDS in fixed order.
+__global__ void __launch_bounds__(16 * 64) k_adj_grads_reduce_split(const VrkDesc *descs, const int4 *tiles,
+                                                                  int nsplit, int csplit, const float2 *gpart)
+{
+    __shared__ float2 part[16][256];
+    const int4 tl = gmem(tiles)[blockIdx.x];
+    CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+    const int u = w >> 2, x = w & 3;
+    const gp<const float2> CB = gmem(static_cast<const float2 *>(d.Cblk));
+    if ((__builtin_amdgcn_readfirstlane(tl.w) & 1) && w == 0) {
+        float t = 0.f;
+        for (int e = lane; e < d.nub * VRK_UB; e += 64) {
+            const int64_t p = gmem(d.cp_diag)[e >> 4];
+            for (int cs = 0; cs < csplit; ++cs) t += CB[(p * csplit + cs) * 256 + (e & 15) * 17].x;
+        }
+        t = wave_sum(t);
+        if (lane == 0) *gmem(d.gxi) = -(double)t;
+    }
+    const int ubg = __builtin_amdgcn_readfirstlane(tl.y);
+    if (ubg < 0) return;   // the whole workgroup
+    const int ub = ubg * kUG + u, ab = __builtin_amdgcn_readfirstlane(tl.z);
+    const bool live = ub < d.nub && ab >= gmem(d.rab_lo)[ub] && ab < gmem(d.rab_hi)[ub];
+    // this lane's entries: user 16 ub + 4 g + r, antenna 16 ab + j (D layout)
+    const int j = i, g = kk;
+    f4 r0 = {0.f, 0.f, 0.f, 0.f}, i0 = {0.f, 0.f, 0.f, 0.f};
+    C3 acc;
+    if (live) {
+        const gp<const float2> src = gmem(gpart) + (int64_t)blockIdx.x * nsplit * kUG * 256 + u * 256;
+#pragma unroll 2
+        for (int sp = x; sp < nsplit; sp += 4)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float2 p = src[(int64_t)sp * kUG * 256 + (4 * g + r) * 16 + j];
                 r0[r] += p.x;
                 i0[r] += p.y;
             }
-    } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (in[r]) {
-                const float2 p = GH[gh[r]];
-                r0[r] = p.x;
-                i0[r] = p.y;
-            }
     }
-    // C3 state with Re = u - v = r0 and Im = w - u - v = i0
-    C3 acc = {r0, f4{0.f, 0.f, 0.f, 0.f}, r0 + i0};
-    const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
-    const int p0 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub]);
-    const int p1 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub + 1]);
+    acc = C3{r0, f4{0.f, 0.f, 0.f, 0.f}, r0 + i0};
+    if (live) {
+        const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
+        const int p0 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub]);
+        const int p1 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub + 1]);
 #pragma unroll 1
-    for (int p = p0; p < p1; ++p) {
-        const int ubc = __builtin_amdgcn_readfirstlane(gmem(d.cp_col)[p]);
-        const int lo = __builtin_amdgcn_readfirstlane(gmem(d.rab_lo)[ubc]);
-        if (ab < lo || ab >= gmem(d.rab_hi)[ubc]) continue;
-        const int pt = __builtin_amdgcn_readfirstlane(gmem(d.cp_tr)[p]);
-        // residual tile c of ub' holds H[16 ub' + i'][16 ab + 4 kk' + m] at
-        // 64 m + i' + 16 kk' (ab = lo + c / 4, m = c % 4)
-        const gp<const float2> ht = HA + (gmem(d.ha_off)[ubc] + 4 * (int64_t)(ab - lo)) * 64;
-        float2 c1[kMaxCsplit][4], c2[kMaxCsplit][4], h[4];
+        for (int p = p0 + x; p < p1; p += 4) {
+            const int ubc = __builtin_amdgcn_readfirstlane(gmem(d.cp_col)[p]);
+            const int lo = __builtin_amdgcn_readfirstlane(gmem(d.rab_lo)[ubc]);
+            if (ab < lo || ab >= gmem(d.rab_hi)[ubc]) continue;
+            const int pt = __builtin_amdgcn_readfirstlane(gmem(d.cp_tr)[p]);
+            const gp<const float2> ht = HA + (gmem(d.ha_off)[ubc] + 4 * (int64_t)(ab - lo)) * 64;
+            float2 a[4], h[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int k = 4 * s + kk;
-            h[s] = ht[64 * (i & 3) + k + 16 * (i >> 2)];
+            for (int s = 0; s < 4; ++s) {
+                a[s] = float2{0.f, 0.f};
+                h[s] = ht[64 * (i & 3) + 4 * s + kk + 16 * (i >> 2)];
+            }
+#pragma unroll 1
+            for (int cs = 0; cs < csplit; ++cs) {
+                float2 c1[4], c2[4];
 #pragma unroll
-            for (int cs = 0; cs < kMaxCsplit; ++cs) {
-                c1[cs][s] = c2[cs][s] = float2{0.f, 0.f};
-                if (cs < csplit) {
-                    c1[cs][s] = CB[((int64_t)p * csplit + cs) * 256 + i * 16 + k];
-                    c2[cs][s] = CB[((int64_t)pt * csplit + cs) * 256 + k * 16 + i];
+                for (int s = 0; s < 4; ++s) {
+                    const int k = 4 * s + kk;
+                    c1[s] = CB[((int64_t)p * csplit + cs) * 256 + i * 16 + k];
+                    c2[s] = CB[((int64_t)pt * csplit + cs) * 256 + k * 16 + i];
                 }
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            float ar = 0.f, ai = 0.f;
-#pragma unroll
-            for (int cs = 0; cs < kMaxCsplit; ++cs) {
-                ar += c1[cs][s].x + c2[cs][s].x;
-                ai += c1[cs][s].y - c2[cs][s].y;
+                for (int s = 0; s < 4; ++s) a[s] = float2{a[s].x - c1[s].x - c2[s].x, a[s].y - c1[s].y + c2[s].y};
             }
-            c3mfma(acc, float2{-ar, -ai}, h[s]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) c3mfma(acc, a[s], h[s]);
         }
     }
     const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (in[r]) GH[gh[r]] = float2{re[r], im[r]};
+    for (int r = 0; r < 4; ++r) part[w][(4 * g + r) * 16 + j] = float2{re[r], im[r]};
+    __syncthreads();
+    if (!live || x != 0) return;
+    const int nn = ab * VRK_AB + j;
+    const gp<float2> GH = gmem(static_cast<float2 *>(d.GH));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int kq = ub * VRK_UB + 4 * g + r, e = (4 * g + r) * 16 + j;
+        if (kq >= d.k) continue;
+        const int us = gmem(d.perm)[kq];
+        if (nn < gmem(d.vs)[us] || nn >= gmem(d.ve)[us]) continue;
+        float sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int xx = 0; xx < 4; ++xx) {
+            sr += part[4 * u + xx][e].x;
+            si += part[4 * u + xx][e].y;
+        }
+        GH[(int64_t)us * d.ldgh + nn] = float2{sr, si};
+    }
 }
 
 
 }  // namespace
 
 hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
-                                         const int4 *ctiles, int32_t nctiles, int32_t csplit, float2 *gpart,
-                                         hipStream_t s)
+                                         const int4 *ctiles, int32_t nctiles, int32_t csplit, const int4 *runs,
+                                         int32_t nruns, float2 *gpart, hipStream_t s)
 {
     if (csplit < 1 || csplit > kMaxCsplit) return hipErrorInvalidValue;
     const int64_t nwg = (int64_t)nctiles + (int64_t)ntiles * nsplit;
@@ -341,6 +482,11 @@ hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles,
                        nctiles, csplit, gpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || ntiles <= 0) return e;
-    hipLaunchKernelGGL(k_adj_grads_reduce, dim3(ntiles), dim3(kGW * 64), 0, s, desc, tiles, nsplit, csplit, gpart);
+    if (nsplit > 1)
+        hipLaunchKernelGGL(k_adj_grads_reduce_split, dim3(ntiles), dim3(16 * 64), 0, s, desc, tiles, nsplit, csplit,
+                           gpart);
+    else if (nruns > 0)
+        hipLaunchKernelGGL(k_adj_grads_reduce, dim3(nruns), dim3(kGW * 64), 0, s, desc, tiles, runs, nsplit,
+                           csplit, gpart);
     return hipGetLastError();
 }

@@ -62,8 +62,10 @@ hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t 
 // bit 1 unused, bits 2.. on a problem's first tile: its problem's tile
 // count). nsplit > 1 splits each band tile's RHS range over nsplit
 // workgroups writing partials to gpart (ntiles * nsplit * VRK_GRAD_UG * 256
-// complex64), else they write GH; a second kernel sums the partials in fixed
-// order, subtracts (C + C^H) H on the band and writes gxi.
+// complex64), else they write GH. A second kernel, one workgroup per run
+// (first tile, tile count, flags: bit 0 first run of its problem, 0) of
+// consecutive band tiles of one user-block group, sums the partials in
+// fixed order, subtracts (C + C^H) H on the band and writes gxi.
 hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
-                                         const int4 *ctiles, int32_t nctiles, int32_t csplit, float2 *gpart,
-                                         hipStream_t s);
+                                         const int4 *ctiles, int32_t nctiles, int32_t csplit, const int4 *runs,
+                                         int32_t nruns, float2 *gpart, hipStream_t s);

@@ -102,6 +102,8 @@ struct vrk_plan {
     std::vector<int4> ctiles;   // (problem, C block, split, row block) of the adjoint C blocks
     size_t o_ctiles = 0;
     int32_t csplit = 1;         // RHS splits of the C blocks (1..4)
+    std::vector<int4> gruns;    // runs of band tiles of the gradient's second kernel
+    size_t o_gruns = 0;
     int32_t persistent = 0, grid = 0;
     int32_t max_nub = 0;
     std::vector<uint8_t> image;
@@ -522,6 +524,18 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
                     for (int e = q.cp_off[mb]; e < q.cp_off[mb + 1]; ++e)
                         for (int cs = 0; cs < pl->csplit; ++cs) pl->ctiles.push_back(make_int4(i, e, cs, mb));
             }
+            // runs of at most R consecutive band tiles of one (problem, user
+            // block group), R chosen for about 1024 runs
+            const int R = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)pl->gtiles.size() / 1024));
+            for (size_t t = 0; t < pl->gtiles.size();) {
+                const int4 a = pl->gtiles[t];
+                size_t e = t + 1;
+                while (e < pl->gtiles.size() && e - t < (size_t)R && pl->gtiles[e].x == a.x && pl->gtiles[e].y == a.y)
+                    ++e;
+                const bool first = t == 0 || pl->gtiles[t - 1].x != a.x;
+                pl->gruns.push_back(make_int4((int32_t)t, (int32_t)(e - t), first ? 1 : 0, 0));
+                t = e;
+            }
         }
     }
     // workspace carving
@@ -532,7 +546,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     pl->o_gtiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->gtiles.size()));
     pl->o_queue = cv.take(sizeof(int32_t) * 3 * VRK_NQUEUE);
     pl->o_ctiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->ctiles.size()));
-    pl->o_gpart = cv.take(pl->gsplit > 1 ? pl->gtiles.size() * (size_t)pl->gsplit * VRK_GRAD_UG * 256 * 8 : 0);
+    pl->o_gruns = cv.take(sizeof(int4) * std::max<size_t>(1, pl->gruns.size()));
     for (auto &q : pl->pp) {
         const int K = q.p.k;
         q.o_vs = cv.take(4 * K);
@@ -563,6 +577,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_cpdiag = cv.take(4 * q.cp_diag.size());
     }
     pl->table_end = cv.off;
+    pl->o_gpart = cv.take(pl->gsplit > 1 ? pl->gtiles.size() * (size_t)pl->gsplit * VRK_GRAD_UG * 256 * 8 : 0);
     for (auto &q : pl->pp) {
         q.o_nrm = cv.take((size_t)rb * std::max(q.p.k, q.nub * VRK_UB));
         q.o_fro2 = cv.take(rb);
@@ -697,6 +712,8 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         std::memcpy(pl->image.data() + pl->o_gtiles, pl->gtiles.data(), sizeof(int4) * pl->gtiles.size());
     if (!pl->ctiles.empty())
         std::memcpy(pl->image.data() + pl->o_ctiles, pl->ctiles.data(), sizeof(int4) * pl->ctiles.size());
+    if (!pl->gruns.empty())
+        std::memcpy(pl->image.data() + pl->o_gruns, pl->gruns.data(), sizeof(int4) * pl->gruns.size());
     {
         int32_t *qv = reinterpret_cast<int32_t *>(pl->image.data() + pl->o_queue);
         for (int qi = 0; qi < VRK_NQUEUE; ++qi) {
@@ -799,6 +816,8 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
                                            (int32_t)pl->gtiles.size(), pl->gsplit,
                                            reinterpret_cast<const int4 *>(pl->d_ws + pl->o_ctiles),
                                            (int32_t)pl->ctiles.size(), pl->csplit,
+                                           reinterpret_cast<const int4 *>(pl->d_ws + pl->o_gruns),
+                                           (int32_t)pl->gruns.size(),
                                            reinterpret_cast<float2 *>(pl->d_ws + pl->o_gpart), s)
            : vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient kernel");
