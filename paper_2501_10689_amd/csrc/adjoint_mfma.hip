@@ -369,21 +369,21 @@ __global__ void __launch_bounds__(kGW * 64) __attribute__((amdgpu_waves_per_eu(4
 }
 
 
-// Tiles with RHS splits (nsplit > 1; few tiles): workgroup (band tile) of
-// 16 waves, wave (u, x) taking user block ub = 4 ubg + u, the splits
-// x, x + 4, ... and the column blocks p0 + x, p0 + x + 4, ... of the
-// correction (as in k_adj_grads_reduce, C summed over its splits); the four
-// waves of a block are added through LDS in fixed order.
-__global__ void __launch_bounds__(16 * 64) k_adj_grads_reduce_split(const VrkDesc *descs, const int4 *tiles,
-                                                                  int nsplit, int csplit, const float2 *gpart)
+// Tiles with RHS splits (nsplit > 1; few tiles): workgroup (band tile, u) of
+// 4 waves for user block ub = 4 ubg + u, wave x taking the splits x, x + 4,
+// ... and the column blocks p0 + x, p0 + x + 4, ... of the correction (as in
+// k_adj_grads_reduce, C summed over its splits); the four waves are added
+// through LDS in fixed order.
+__global__ void __launch_bounds__(kGW * 64) k_adj_grads_reduce_split(const VrkDesc *descs, const int4 *tiles,
+                                                                   int nsplit, int csplit, const float2 *gpart)
 {
-    __shared__ float2 part[16][256];
+    __shared__ float2 part[kGW][256];
     const int4 tl = gmem(tiles)[blockIdx.x];
     CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
-    const int u = w >> 2, x = w & 3;
+    const int x = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+    const int u = blockIdx.y;
     const gp<const float2> CB = gmem(static_cast<const float2 *>(d.Cblk));
-    if ((__builtin_amdgcn_readfirstlane(tl.w) & 1) && w == 0) {
+    if ((__builtin_amdgcn_readfirstlane(tl.w) & 1) && u == 0 && x == 0) {
         float t = 0.f;
         for (int e = lane; e < d.nub * VRK_UB; e += 64) {
             const int64_t p = gmem(d.cp_diag)[e >> 4];
@@ -395,15 +395,14 @@ __global__ void __launch_bounds__(16 * 64) k_adj_grads_reduce_split(const VrkDes
     const int ubg = __builtin_amdgcn_readfirstlane(tl.y);
     if (ubg < 0) return;   // the whole workgroup
     const int ub = ubg * kUG + u, ab = __builtin_amdgcn_readfirstlane(tl.z);
-    const bool live = ub < d.nub && ab >= gmem(d.rab_lo)[ub] && ab < gmem(d.rab_hi)[ub];
+    if (ub >= d.nub || ab < gmem(d.rab_lo)[ub] || ab >= gmem(d.rab_hi)[ub]) return;   // the whole workgroup
     // this lane's entries: user 16 ub + 4 g + r, antenna 16 ab + j (D layout)
     const int j = i, g = kk;
     f4 r0 = {0.f, 0.f, 0.f, 0.f}, i0 = {0.f, 0.f, 0.f, 0.f};
-    C3 acc;
-    if (live) {
+    {
         const gp<const float2> src = gmem(gpart) + (int64_t)blockIdx.x * nsplit * kUG * 256 + u * 256;
 #pragma unroll 2
-        for (int sp = x; sp < nsplit; sp += 4)
+        for (int sp = x; sp < nsplit; sp += kGW)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float2 p = src[(int64_t)sp * kUG * 256 + (4 * g + r) * 16 + j];
@@ -411,45 +410,48 @@ __global__ void __launch_bounds__(16 * 64) k_adj_grads_reduce_split(const VrkDes
                 i0[r] += p.y;
             }
     }
-    acc = C3{r0, f4{0.f, 0.f, 0.f, 0.f}, r0 + i0};
-    if (live) {
-        const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
-        const int p0 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub]);
-        const int p1 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub + 1]);
+    C3 acc = {r0, f4{0.f, 0.f, 0.f, 0.f}, r0 + i0};
+    const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
+    const int p0 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub]);
+    const int p1 = __builtin_amdgcn_readfirstlane(gmem(d.cp_off)[ub + 1]);
 #pragma unroll 1
-        for (int p = p0 + x; p < p1; p += 4) {
-            const int ubc = __builtin_amdgcn_readfirstlane(gmem(d.cp_col)[p]);
-            const int lo = __builtin_amdgcn_readfirstlane(gmem(d.rab_lo)[ubc]);
-            if (ab < lo || ab >= gmem(d.rab_hi)[ubc]) continue;
-            const int pt = __builtin_amdgcn_readfirstlane(gmem(d.cp_tr)[p]);
-            const gp<const float2> ht = HA + (gmem(d.ha_off)[ubc] + 4 * (int64_t)(ab - lo)) * 64;
-            float2 a[4], h[4];
+    for (int p = p0 + x; p < p1; p += kGW) {
+        const int ubc = __builtin_amdgcn_readfirstlane(gmem(d.cp_col)[p]);
+        const int lo = __builtin_amdgcn_readfirstlane(gmem(d.rab_lo)[ubc]);
+        if (ab < lo || ab >= gmem(d.rab_hi)[ubc]) continue;
+        const int pt = __builtin_amdgcn_readfirstlane(gmem(d.cp_tr)[p]);
+        const gp<const float2> ht = HA + (gmem(d.ha_off)[ubc] + 4 * (int64_t)(ab - lo)) * 64;
+        float2 h[4], c1[kMaxCsplit][4], c2[kMaxCsplit][4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                a[s] = float2{0.f, 0.f};
-                h[s] = ht[64 * (i & 3) + 4 * s + kk + 16 * (i >> 2)];
-            }
-#pragma unroll 1
-            for (int cs = 0; cs < csplit; ++cs) {
-                float2 c1[4], c2[4];
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + kk;
+            h[s] = ht[64 * (i & 3) + k + 16 * (i >> 2)];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int k = 4 * s + kk;
-                    c1[s] = CB[((int64_t)p * csplit + cs) * 256 + i * 16 + k];
-                    c2[s] = CB[((int64_t)pt * csplit + cs) * 256 + k * 16 + i];
+            for (int cs = 0; cs < kMaxCsplit; ++cs) {
+                c1[cs][s] = c2[cs][s] = float2{0.f, 0.f};
+                if (cs < csplit) {
+                    c1[cs][s] = CB[((int64_t)p * csplit + cs) * 256 + i * 16 + k];
+                    c2[cs][s] = CB[((int64_t)pt * csplit + cs) * 256 + k * 16 + i];
                 }
-#pragma unroll
-                for (int s = 0; s < 4; ++s) a[s] = float2{a[s].x - c1[s].x - c2[s].x, a[s].y - c1[s].y + c2[s].y};
             }
+        }
+        __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
 #pragma unroll
-            for (int s = 0; s < 4; ++s) c3mfma(acc, a[s], h[s]);
+        for (int s = 0; s < 4; ++s) {
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int cs = 0; cs < kMaxCsplit; ++cs) {
+                ar += c1[cs][s].x + c2[cs][s].x;
+                ai += c1[cs][s].y - c2[cs][s].y;
+            }
+            c3mfma(acc, float2{-ar, -ai}, h[s]);
         }
     }
     const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) part[w][(4 * g + r) * 16 + j] = float2{re[r], im[r]};
+    for (int r = 0; r < 4; ++r) part[x][(4 * g + r) * 16 + j] = float2{re[r], im[r]};
     __syncthreads();
-    if (!live || x != 0) return;
+    if (x != 0) return;
     const int nn = ab * VRK_AB + j;
     const gp<float2> GH = gmem(static_cast<float2 *>(d.GH));
 #pragma unroll
@@ -460,9 +462,9 @@ __global__ void __launch_bounds__(16 * 64) k_adj_grads_reduce_split(const VrkDes
         if (nn < gmem(d.vs)[us] || nn >= gmem(d.ve)[us]) continue;
         float sr = 0.f, si = 0.f;
 #pragma unroll
-        for (int xx = 0; xx < 4; ++xx) {
-            sr += part[4 * u + xx][e].x;
-            si += part[4 * u + xx][e].y;
+        for (int xx = 0; xx < kGW; ++xx) {
+            sr += part[xx][e].x;
+            si += part[xx][e].y;
         }
         GH[(int64_t)us * d.ldgh + nn] = float2{sr, si};
     }
@@ -483,8 +485,8 @@ hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || ntiles <= 0) return e;
     if (nsplit > 1)
-        hipLaunchKernelGGL(k_adj_grads_reduce_split, dim3(ntiles), dim3(16 * 64), 0, s, desc, tiles, nsplit, csplit,
-                           gpart);
+        hipLaunchKernelGGL(k_adj_grads_reduce_split, dim3(ntiles, kUG), dim3(kGW * 64), 0, s, desc, tiles, nsplit,
+                           csplit, gpart);
     else if (nruns > 0)
         hipLaunchKernelGGL(k_adj_grads_reduce, dim3(nruns), dim3(kGW * 64), 0, s, desc, tiles, runs, nsplit,
                            csplit, gpart);
