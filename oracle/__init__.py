@@ -252,3 +252,52 @@ def select(r, nrm, rule, u) -> int:
     nrm = np.ascontiguousarray(nrm, dtype=np.float64)
     return int(_load().orc_select(len(r), SELECT[rule], _ptr(r), _ptr(nrm), float(nrm.sum()),
                                   float(u)))
+
+
+# ---------------------------------------------------------------------------
+# Precoding matrix and link metrics (signal model and spectral efficiency of
+# Sec. II, the RZF precoder and its power budget, Remark 1 for F = H^H V, and
+# the NMSE of the simulation section). Plain numpy in FP64.
+# ---------------------------------------------------------------------------
+
+def band_channel(H, vr_start, vr_len):
+    """H with every entry outside the users' VRs set to zero (the channel the
+    solver works on: only VR entries are nonzero)."""
+    H = np.asarray(H, dtype=np.complex128)
+    K, Nt = H.shape
+    n = np.arange(Nt)[None, :]
+    vs = np.asarray(vr_start)[:, None]
+    ve = vs + np.asarray(vr_len)[:, None]
+    return np.where((n >= vs) & (n < ve), H, 0)
+
+
+def precoder(H, vr_start, vr_len, xi):
+    """Unnormalised RZF precoding matrix, transposed: row b is f_b, the
+    precoder of user b, i.e. the solution x for s = e_b (Remark 1); K x Nt."""
+    K = np.asarray(H).shape[0]
+    X, _ = rzf(H, vr_start, vr_len, np.eye(K, dtype=np.complex128), xi)
+    return X
+
+
+def link_metrics(H, vr_start, vr_len, xi, X):
+    """Link metrics of the precoder whose transposed columns are the rows of
+    X (K x Nt). Returns (E, beta, rate):
+      E[u, b] = h_u^H f_b = sum over n in VR_u of H[u, n] X[b, n],
+      beta    = 1 / ||F||_F  (the power budget ||beta F||_F^2 <= 1 met with
+                equality),
+      rate[u] = log2(1 + rho beta^2 |E_uu|^2 / (rho beta^2 sum_{b != u}
+                |E_ub|^2 + sigma^2)), written with xi = sigma^2 / rho."""
+    X = np.asarray(X, dtype=np.complex128)
+    E = band_channel(H, vr_start, vr_len) @ X.T
+    beta = 1.0 / np.linalg.norm(X)
+    a2 = np.abs(E) ** 2
+    sig = np.diag(a2).copy()
+    intf = a2.sum(axis=1) - sig
+    rate = np.log2(1.0 + beta ** 2 * sig / (beta ** 2 * intf + xi))
+    return E, beta, rate
+
+
+def nmse(F_ref, F):
+    """||F_ref - F||_F / ||F_ref||_F, the NMSE of the simulation section."""
+    F_ref = np.asarray(F_ref)
+    return float(np.linalg.norm(F_ref - np.asarray(F)) / np.linalg.norm(F_ref))

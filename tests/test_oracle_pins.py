@@ -563,3 +563,107 @@ def test_rzf_gradient_matches_torch_autograd():
     np.testing.assert_allclose(gH + gHe * (np.abs(H) > 0), Ht.grad.numpy(), atol=1e-12)
     np.testing.assert_allclose(gS + gSe, St.grad.numpy(), atol=1e-12)
     assert abs(gxi - float(xit.grad)) <= 1e-12 * max(1.0, abs(gxi))
+
+
+# ---------------------------------------------------------------------------
+# Precoding matrix and link metrics (signal model / spectral efficiency of
+# Sec. II, RZF precoder and power budget, Remark 1, NMSE of Sec. VI)
+# ---------------------------------------------------------------------------
+
+def test_single_user_rate_is_mrt_capacity():
+    # K = 1: F = h / (|h|^2 + xi), so beta^2 |h^H f|^2 = |h|^2 and the rate
+    # is log2(1 + |h|^2 / xi) (SNR |h|^2 rho / sigma^2)
+    rng = np.random.default_rng(51)
+    H, vs, vl, _ = random_problem(rng, 48, 1)
+    xi = 0.37
+    X = oracle.precoder(H, vs, vl, xi)
+    E, beta, rate = oracle.link_metrics(H, vs, vl, xi, X)
+    h2 = float(np.sum(np.abs(H[0, vs[0]:vs[0] + vl[0]]) ** 2))
+    assert abs(beta - (h2 + xi) / np.sqrt(h2)) <= 1e-12 * beta
+    assert abs(E[0, 0] - h2 / (h2 + xi)) <= 1e-13
+    assert abs(rate[0] - np.log2(1 + h2 / xi)) <= 1e-12
+
+
+def test_disjoint_vrs_no_interference():
+    # users with disjoint VRs are orthogonal: M is diagonal, E is diagonal
+    # with E_kk = |h_k|^2 / (|h_k|^2 + xi), and each rate has no interference
+    rng = np.random.default_rng(52)
+    H, vs, vl, _ = random_problem(rng, 96, 6, disjoint=True)
+    xi = 0.8
+    X = oracle.precoder(H, vs, vl, xi)
+    E, beta, rate = oracle.link_metrics(H, vs, vl, xi, X)
+    h2 = np.array([np.sum(np.abs(H[k, vs[k]:vs[k] + vl[k]]) ** 2) for k in range(6)])
+    ekk = h2 / (h2 + xi)
+    assert np.max(np.abs(E - np.diag(ekk))) <= 1e-13
+    b2 = 1.0 / np.sum(h2 / (h2 + xi) ** 2)          # ||f_k||^2 = |h_k|^2 / (|h_k|^2 + xi)^2
+    assert abs(beta ** 2 - b2) <= 1e-12 * b2
+    assert np.max(np.abs(rate - np.log2(1 + b2 * ekk ** 2 / xi))) <= 1e-12
+
+
+def test_effective_channel_identity_and_power_budget():
+    # H F = H H^H (H H^H + xi I)^-1 = I - xi M^-1, with M formed densely and
+    # inverted by LAPACK (an independent route); ||beta F||_F = 1
+    rng = np.random.default_rng(53)
+    H, vs, vl, _ = random_problem(rng, 80, 12)
+    xi = 0.45
+    Hb = oracle.band_channel(H, vs, vl)
+    X = oracle.precoder(H, vs, vl, xi)
+    E, beta, _ = oracle.link_metrics(H, vs, vl, xi, X)
+    M = Hb @ Hb.conj().T + xi * np.eye(12)
+    ref = np.eye(12) - xi * np.linalg.inv(M)
+    assert np.max(np.abs(E - ref)) <= 1e-12
+    assert abs(np.linalg.norm(beta * X) - 1.0) <= 1e-13
+    # entries outside the VRs never enter E
+    Hn = H.copy()
+    for k in range(12):
+        Hn[k, :vs[k]] = 5.0
+        Hn[k, vs[k] + vl[k]:] = -3.0j
+    E2, _, _ = oracle.link_metrics(Hn, vs, vl, xi, X)
+    assert np.array_equal(E, E2)
+
+
+def test_rates_invariant_under_channel_and_noise_scaling():
+    # (H, xi) -> (c H, c^2 xi): M scales by c^2, F by 1/c, beta by c, E is
+    # unchanged, and every SINR (signal and interference both scaled by
+    # beta^2 against xi) is unchanged; with interference present this fails if
+    # beta^2 or xi enters the denominator wrongly
+    rng = np.random.default_rng(54)
+    H, vs, vl, _ = random_problem(rng, 64, 10)
+    xi, c = 0.6, 3.7
+    r1 = oracle.link_metrics(H, vs, vl, xi, oracle.precoder(H, vs, vl, xi))
+    r2 = oracle.link_metrics(c * H, vs, vl, c * c * xi, oracle.precoder(c * H, vs, vl, c * c * xi))
+    a2 = np.abs(r1[0]) ** 2
+    assert np.min(a2.sum(axis=1) - np.diag(a2)) > 1e-6          # interference is present
+    assert np.max(np.abs(r1[0] - r2[0])) <= 1e-12
+    assert abs(r2[1] - c * r1[1]) <= 1e-12 * r2[1]
+    assert np.max(np.abs(r1[2] - r2[2])) <= 1e-12
+
+
+def test_nmse_definition():
+    rng = np.random.default_rng(55)
+    F = rng.standard_normal((5, 9)) + 1j * rng.standard_normal((5, 9))
+    assert oracle.nmse(F, F) == 0.0
+    assert abs(oracle.nmse(F, 2 * F) - 1.0) <= 1e-15
+    assert abs(oracle.nmse(F, F * (1 + 1e-3j)) - 1e-3) <= 1e-15
+
+
+def test_interference_is_what_user_u_receives():
+    # any precoder: user 1 hears stream 0 (f_0 reaches into user 1's VR), user 0
+    # hears nothing of stream 1; y_u = h_u^H F s, so the interference at user u
+    # is sum_{b != u} |h_u^H f_b|^2 (row u of E), not column u
+    Nt, xi = 16, 0.25
+    vs, vl = np.array([0, 8]), np.array([8, 8])
+    H = np.zeros((2, Nt), dtype=np.complex128)
+    H[0, 0:8] = 0.5
+    H[1, 8:16] = 0.5j
+    X = np.zeros((2, Nt), dtype=np.complex128)
+    X[0, 0:8] = 1.0
+    X[0, 8:10] = 0.3
+    X[1, 8:16] = -1.0j
+    E, beta, rate = oracle.link_metrics(H, vs, vl, xi, X)
+    b2 = 1.0 / (8 + 2 * 0.09 + 8)
+    e00, e10, e11 = 4.0, 0.5j * 0.3 * 2, 0.5j * -1.0j * 8
+    assert np.allclose(E, [[e00, 0.0], [e10, e11]], atol=1e-15)
+    assert abs(beta ** 2 - b2) <= 1e-15
+    assert abs(rate[0] - np.log2(1 + b2 * 16 / xi)) <= 1e-12
+    assert abs(rate[1] - np.log2(1 + b2 * abs(e11) ** 2 / (b2 * abs(e10) ** 2 + xi))) <= 1e-12
