@@ -12,6 +12,9 @@ complex64, relative-residual tolerance 1e-5. The other workloads:
   large    64 drops of Nt 4096, K 256, VR U[256, 1024], 1024 16-QAM vectors, SNR 10 dB
   plain    one drop Nt 256, K 16, LoS, VR U[64, 128], one QPSK vector, complex128,
            tolerance 1e-10
+  precoder the adjoint workload's 256 drops with S = I_K: each drop's RZF precoding
+           matrix, its effective channel, beta and per-user spectral efficiency
+           (metric: precoding matrices/s; see run_precoder)
 Inputs are synthetic and resident in HBM before timing.
 
 One step = the hot path over the whole batch: the forward solve of every
@@ -55,7 +58,121 @@ WORKLOADS = {
              "SNR 10 dB, tol 1e-5; fwd+adjoint",
     "plain": "plain single instance: Nt=256, K=16, LoS, VR U[64,128], one QPSK vector, SNR 10 dB, "
              "complex128, tol 1e-10; fwd+adjoint",
+    "precoder": "RZF precoding matrices: 256 drops of Nt=1024, K=64, VR U[256,512], S = I_K, SNR 10 dB, "
+                "tol 1e-5; solve + effective channel + beta + per-user spectral efficiency",
 }
+
+
+def run_precoder(args):
+    """One step = every drop's precoding matrix (the solve on S = I_K, rows of X
+    = columns of F) and its link metrics (vrk_link_metrics). Accuracy: NMSE of
+    beta F against the FP64 Cholesky RZF's, and the largest per-user rate
+    difference. cpu_baseline: the oracle's FP64 iterations on S = I_K plus its
+    link metrics on a bounded sample of drops."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_2501_10689_amd import vrk
+
+    dev = torch.device("cuda:0")
+    drops = synth.make_workload("adjoint", snr_db=args.snr)
+    tol = args.tol if args.tol is not None else 1e-5
+    specs, E, R, Bt = [], [], [], []
+    for d in drops:
+        H = torch.from_numpy(d.H).to(torch.complex64).to(dev)
+        S = torch.eye(d.k, dtype=torch.complex64, device=dev)
+        X = torch.zeros((d.k, d.nt), dtype=torch.complex64, device=dev)
+        specs.append(vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X))
+        E.append(torch.zeros((d.k, d.k), dtype=torch.complex64, device=dev))
+        R.append(torch.zeros(d.k, dtype=torch.float64, device=dev))
+        Bt.append(torch.zeros(1, dtype=torch.float64, device=dev))
+    opts = vrk.options(variant=args.variant, dtype="c64", engine=args.engine, tol=tol,
+                       tile_waves=args.tile_waves, persistent=args.persistent)
+    plan = vrk.Plan(specs, opts)
+    eng = plan.query(0, vrk.Q_ENGINE)
+    engine = {1: "vector", 2: "mfma"}[int(eng[0])]
+    stats = plan.stats_buffers()
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        plan.solve(stream=stream, stats=stats)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.link_metrics(E, R, Bt, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for i in range(args.steps):
+        step(evs[i])
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+    solve_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    value = len(drops) / (ms_step * 1e-3)
+
+    it_all = stats[0].cpu().numpy()
+    worst_nmse, worst_rate, flops, base = 0.0, 0.0, 0.0, 0
+    for j, (d, sp) in enumerate(zip(drops, specs)):
+        Xo = oracle.precoder(d.H, d.vr_start, d.vr_len, d.xi)
+        _, bo, ro = oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi, Xo)
+        Xg = sp.X.cpu().numpy().astype(np.complex128)
+        bg = float(Bt[j].cpu().numpy()[0])
+        worst_nmse = max(worst_nmse, oracle.nmse(bo * Xo, bg * Xg))
+        worst_rate = max(worst_rate, float(np.max(np.abs(R[j].cpu().numpy() - ro))))
+        fset = plan.query(j, vrk.Q_FSET)
+        vl = np.asarray(d.vr_len, dtype=np.int64)
+        band, band_f = float(vl.sum()), float(vl[fset].sum())
+        it = it_all[base:base + d.k]
+        overlap = float(plan.query(j, vrk.Q_XOFF)[-1])
+        flops += algorithmic_flops(engine, args.variant, band, band_f, band - band_f, overlap, float(it.sum()),
+                                   float(d.k), d.k)
+        base += d.k
+    achieved = flops / (solve_ms * 1e-3)
+    roof = {"bound": "mfma" if engine == "mfma" else "alu", "achieved": achieved / 1e12,
+            "peak": (PEAK_MFMA_F32 if engine == "mfma" else PEAK_VALU_F32) / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / (PEAK_MFMA_F32 if engine == "mfma" else PEAK_VALU_F32), "traffic": None,
+            "kernel": "solve on S = I_K (%s engine, %s)" % (engine, args.variant), "kernel_ms": solve_ms,
+            "flops_per_launch": flops, "unit_of_work": "vector-iteration", "units_per_launch": float(it_all.sum())}
+    out = {
+        "metric": "RZF precoding matrices/s with link metrics, NMSE <= 1e-4 vs FP64 RZF",
+        "value": value, "unit": "matrices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["precoder"], "variant": args.variant, "engine": engine,
+                   "tile_waves": int(eng[2]), "entries_per_thread": int(eng[6]), "drops": len(drops),
+                   "vectors": int(sum(d.k for d in drops)), "tol": tol},
+        "roofline": roof,
+        "accuracy": {"max_nmse": worst_nmse, "max_rate_diff_bits": worst_rate,
+                     "mean_iters": float(it_all.mean()), "max_iters": int(it_all.max())},
+    }
+    if not args.no_cpu_baseline:
+        budget, n_cpu, t_cpu = 10.0, 0, 0.0
+        for d in drops:
+            if t_cpu > budget:
+                break
+            t = time.perf_counter()
+            Xc = oracle.solve_batch(d.H, d.vr_start, d.vr_len, np.eye(d.k, dtype=np.complex128), d.xi,
+                                    variant=args.variant, tol=tol)["X"]
+            oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi, Xc)
+            t_cpu += time.perf_counter() - t
+            n_cpu += 1
+        out["cpu_baseline"] = {"value": n_cpu / t_cpu, "unit": "matrices/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": "%d of %d drops (%.1f s): FP64 %s iterations on S = I_K to tol %g "
+                                         "(OpenMP over vectors) + link metrics" % (n_cpu, len(drops), t_cpu,
+                                                                                   args.variant, tol)}
+    print(json.dumps(out), flush=True)
 
 
 def algorithmic_flops(engine, variant, band, band_f, band_v, overlap, iters, vectors, k):
@@ -135,6 +252,10 @@ def main():
         print("bench.py measures one GPU only: the path has no cross-GPU exchange "
               "(drops shard with no communication); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "precoder":
+        run_precoder(args)
+        return
 
     import numpy as np
     import torch

@@ -150,11 +150,36 @@ vrk_status vrk_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relr
 /* Implicit-differentiation backward pass of x = H^H (H H^H + xi I)^-1 s,
  * given GX = 2 dL/d conj(x) of a real loss and the X, V of a previous
  * vrk_solve on the same plan: forms b = H g, runs the same Kaczmarz solve
- * on the same system with right-hand side b (mu = its q, xh = H^H mu = its
- * x), then writes GS = mu, *gxi = -Re sum_b mu_b^H v_b and, on VR entries,
- * GH = sum_b v_b (g_b - xh_b)^H - mu_b x_b^H. Statistics as vrk_solve. */
+ * on the same system with right-hand side b (mu = its q), then writes
+ * GS = mu, *gxi = -Re sum_b mu_b^H v_b and, on VR entries,
+ * GH = sum_b v_b (g_b - H^H mu_b)^H - mu_b x_b^H. Statistics as vrk_solve. */
 vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres,
                              int32_t *d_flags);
+
+/* Link metrics of RZF precoding (signal model, spectral efficiency and the
+ * RZF precoder of the paper, with Remark 1: running the solve on S = I_K
+ * gives the precoding matrix column by column). Every problem must have
+ * nrhs == k and S = I_K (column b of S the canonical vector e_b), and a
+ * vrk_solve on the plan must precede the call: row b of X is then f_b, the
+ * unnormalised precoder of user b, F = H^H (H H^H + xi I)^-1. For problem p
+ * the call writes (device pointers of out[p], caller-owned):
+ *   E[u * lde + b] = h_u^H f_b = sum over n in VR_u of H[u][n] X[b][n]
+ *                    (k x k, the plan's complex type, lde >= k),
+ *   beta[0]        = 1 / ||F||_F (so that ||beta F||_F = 1, the power budget),
+ *   rate[u]        = log2(1 + beta^2 |E_uu|^2 / (beta^2 sum_{b != u} |E_ub|^2 + xi))
+ *                    (double, bit/s/Hz; xi = sigma^2 / rho as in the RZF design).
+ * Asynchronous on stream. The nprob-entry output table is copied to the
+ * workspace when it differs from the previous call's on this binding (the
+ * workspace belongs to the plan while bound), so repeated calls with the
+ * same outputs copy nothing. VRK_EINVAL for a problem with nrhs != k or a
+ * null output, VRK_ESTATE before bind. */
+typedef struct {
+    void *E;       /* device out, k x k row-major */
+    int64_t lde;
+    double *rate;  /* device out, k */
+    double *beta;  /* device out, 1 */
+} vrk_link_out;
+vrk_status vrk_link_metrics(vrk_plan *pl, const vrk_link_out *out, void *stream);
 
 /* Autotuner. Picks the execution configuration of a batch by timing it
  * on the device: for complex64 the MFMA engine with 8 or 16 waves per

@@ -104,6 +104,8 @@ struct vrk_plan {
     int32_t csplit = 1;         // RHS splits of the C blocks (1..4)
     std::vector<int4> gruns;    // runs of band tiles of the gradient's second kernel
     size_t o_gruns = 0;
+    std::vector<VrkLinkOut> link_host;   // output table of the link metrics, uploaded per call
+    size_t o_link = 0;
     int32_t persistent = 0, grid = 0;
     int32_t max_nub = 0;
     std::vector<uint8_t> image;
@@ -577,6 +579,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_cpdiag = cv.take(4 * q.cp_diag.size());
     }
     pl->table_end = cv.off;
+    pl->o_link = cv.take(sizeof(VrkLinkOut) * nprob);
     pl->o_gpart = cv.take(pl->gsplit > 1 ? pl->gtiles.size() * (size_t)pl->gsplit * VRK_GRAD_UG * 256 * 8 : 0);
     for (auto &q : pl->pp) {
         q.o_nrm = cv.take((size_t)rb * std::max(q.p.k, q.nub * VRK_UB));
@@ -617,6 +620,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     uint8_t *base = reinterpret_cast<uint8_t *>(d_ws);
     pl->image.assign(pl->table_end, 0);
+    pl->link_host.clear();   // the link-metric output table is not in this workspace yet
     std::vector<VrkDesc> descs(pl->pp.size());
     const vrk_options &o = pl->opt;
     const int32_t eb = elem_bytes(o.dtype);
@@ -821,6 +825,43 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
                                            reinterpret_cast<float2 *>(pl->d_ws + pl->o_gpart), s)
            : vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient kernel");
+    return VRK_OK;
+}
+
+vrk_status vrk_link_metrics(vrk_plan *pl, const vrk_link_out *out, void *stream)
+{
+    g_err.clear();
+    if (!pl || !out) return fail(VRK_EINVAL, "plan or output table null");
+    if (!pl->bound) return fail(VRK_ESTATE, "vrk_plan_bind must precede vrk_link_metrics");
+    const int32_t nprob = (int32_t)pl->pp.size();
+    std::vector<VrkLinkOut> tab(nprob);
+    for (int32_t i = 0; i < nprob; ++i) {
+        const vrk_problem &p = pl->pp[i].p;
+        if (p.nrhs != p.k)
+            return fail(VRK_EINVAL, "problem %d: link metrics need nrhs == k (S = I_K), got nrhs %d, k %d", i,
+                        p.nrhs, p.k);
+        if (!out[i].E || !out[i].rate || !out[i].beta)
+            return fail(VRK_EINVAL, "problem %d: E, rate and beta must be set", i);
+        if (out[i].lde < p.k) return fail(VRK_EINVAL, "problem %d: lde %lld < k %d", i, (long long)out[i].lde, p.k);
+        tab[i] = VrkLinkOut{out[i].E, out[i].lde, out[i].rate, out[i].beta};
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    VrkLinkOut *d_out = reinterpret_cast<VrkLinkOut *>(pl->d_ws + pl->o_link);
+    // the table goes to the workspace only when it differs from the one there
+    // (bind clears the record, since it may bind another workspace)
+    hipError_t e = hipSuccess;
+    if (pl->link_host.size() != tab.size() ||
+        std::memcmp(pl->link_host.data(), tab.data(), sizeof(VrkLinkOut) * nprob) != 0) {
+        pl->link_host = tab;
+        e = hipMemcpyAsync(d_out, pl->link_host.data(), sizeof(VrkLinkOut) * nprob, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            pl->link_host.clear();
+            return hip_fail(e, "hipMemcpyAsync(link output table)");
+        }
+    }
+    e = vrk_launch_link(reinterpret_cast<const VrkDesc *>(pl->d_ws + pl->o_desc), d_out, nprob, pl->max_k,
+                        pl->opt.dtype == VRK_C128 ? 1 : 0, pl->engine == VRK_ENGINE_MFMA ? 1 : 0, s);
+    if (e != hipSuccess) return hip_fail(e, "link metric kernels");
     return VRK_OK;
 }
 

@@ -73,6 +73,15 @@ struct VrkDesc {
     const int32_t *fpos;
 };
 
+// Outputs of the link metrics of one problem (device pointers): the K x K
+// effective channel E (row-major, lde), the K rates and beta.
+struct VrkLinkOut {
+    void *E;
+    int64_t lde;
+    double *rate;
+    double *beta;
+};
+
 // User blocks per tile of the MFMA adjoint gradient: the blocks 4 ubg ..
 // 4 ubg + 3 that meet one antenna block share its antenna operands.
 #define VRK_GRAD_UG 4

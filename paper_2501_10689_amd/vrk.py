@@ -46,6 +46,10 @@ class Options(C.Structure):
                 ("persistent", C.c_int32)]
 
 
+class LinkOut(C.Structure):
+    _fields_ = [("E", C.c_void_p), ("lde", C.c_int64), ("rate", C.c_void_p), ("beta", C.c_void_p)]
+
+
 class VrkError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("vrk status %d (%s): %s" % (status, STATUS.get(status, "?"), msg))
@@ -78,6 +82,8 @@ def lib():
         L.vrk_autotune.restype = C.c_int
         L.vrk_autotune.argtypes = [P, C.c_int32, C.POINTER(Options), vp, C.c_size_t, vp, C.c_char_p,
                                    C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_float)]
+        L.vrk_link_metrics.restype = C.c_int
+        L.vrk_link_metrics.argtypes = [vp, C.POINTER(LinkOut), vp]
         L.vrk_plan_query.restype = C.c_int64
         L.vrk_plan_query.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int64]
         L.vrk_plan_destroy.restype = None
@@ -205,6 +211,19 @@ class Plan:
         it, rel, fl = stats if stats is not None else (None, None, None)
         _check(lib().vrk_solve_adjoint(self._h, self._stream(stream), _ptr(it), _ptr(rel), _ptr(fl)))
 
+    def link_metrics(self, E, rate, beta, stream=None):
+        """After a solve with S = I_K on every problem: the effective channels
+        E[p] (K x K, the plan's complex type), per-user rates rate[p] (K,
+        float64, bit/s/Hz) and beta[p] (1, float64), all device tensors."""
+        n = len(self.probs)
+        if not (len(E) == len(rate) == len(beta) == n):
+            raise ValueError("one E, rate and beta per problem")
+        arr = (LinkOut * n)()
+        for i in range(n):
+            arr[i].E, arr[i].lde = _ptr(E[i]), _stride(E[i])
+            arr[i].rate, arr[i].beta = _ptr(rate[i]), _ptr(beta[i])
+        _check(lib().vrk_link_metrics(self._h, arr, self._stream(stream)))
+
     def query(self, prob: int, what: int) -> np.ndarray:
         n = lib().vrk_plan_query(self._h, prob, what, None, 0)
         if n < 0:
@@ -301,6 +320,27 @@ def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, **kw):
             lib().vrk_plan_destroy(self._h)
 
     return _HP()
+
+
+def precoder(H, vr_start, vr_len, xi, variant="vr_oahk", select="baiwu", tol=1e-5, max_iters=100000,
+             seed=0, engine="auto"):
+    """RZF precoding matrix of one drop and its link metrics on the GPU: the
+    solve on S = I_K gives X = F^T (row b the unnormalised precoder of user b);
+    returns X, the effective channel E = H F on the VRs (K x K), the per-user
+    spectral efficiencies (bit/s/Hz, float64) and beta = 1 / ||F||_F."""
+    import torch
+    K = H.shape[0]
+    dtype = "c128" if H.dtype == torch.complex128 else "c64"
+    S = torch.eye(K, dtype=H.dtype, device=H.device)
+    X = torch.empty((K, H.shape[1]), dtype=H.dtype, device=H.device)
+    E = torch.empty((K, K), dtype=H.dtype, device=H.device)
+    rate = torch.empty(K, dtype=torch.float64, device=H.device)
+    beta = torch.empty(1, dtype=torch.float64, device=H.device)
+    o = options(variant=variant, select=select, dtype=dtype, engine=engine, tol=tol, max_iters=max_iters, seed=seed)
+    plan = Plan([ProblemSpec(H, vr_start, vr_len, xi, S, X, None)], o)
+    plan.solve()
+    plan.link_metrics([E], [rate], [beta])
+    return X, E, rate, float(beta.cpu()[0])
 
 
 def precode(H, vr_start, vr_len, S, xi, variant="vr_oahk", select="baiwu", tol=1e-5,
