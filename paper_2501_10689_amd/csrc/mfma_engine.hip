@@ -73,7 +73,7 @@ struct MfmaLds {
     float2 *MP;   // one partial Gram product per part
     int *fpos;    // VALU half-step: sorted positions of the users of F
     float2 *MF;   // VALU half-step: the F columns of M, [row][f]
-    float *nrm, *pre, *red;
+    float *nrm, *ninv, *pre, *red;   // ||a||^2 and 1 / ||a||^2 per sorted row
     int *posl;
     int *agoff, *gmoff;   // copies of the tile tables of this problem
     int *gmc;    // copy of the Gram chunk columns (at most nub * kpad / 4)
@@ -109,6 +109,7 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, bool
     char *PV = take(tile);
     char *MP = take(tile * gram_parts(kpad / 16, W));
     char *nrm = take((size_t)kpad * 4);
+    char *ninv = take((size_t)kpad * 4);
     char *pre = take(greedy ? (size_t)W * kpad * 4 : 0);
     char *red = take((size_t)4 * W * 16 * 4);
     char *posl = take((size_t)kpad * 4);
@@ -131,6 +132,7 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, bool
         L->PV = (float2 *)PV;
         L->MP = (float2 *)MP;
         L->nrm = (float *)nrm;
+        L->ninv = (float *)ninv;
         L->pre = (float *)pre;
         L->red = (float *)red;
         L->posl = (int *)posl;
@@ -495,6 +497,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     // ---- init: tables in LDS, then q = 0, r = s (z0 = 0), norms in VR-start order
     for (int ku = tid; ku < kpad; ku += W * 64) {
         L.nrm[ku] = ku < K ? nrm_g[c.perm[ku]] : 1.f;
+        L.ninv[ku] = 1.f / L.nrm[ku];
         L.rsel[ku] = ku < K ? (gmem(d.inf)[c.perm[ku]] ? 1 : 2) : 0;
         if (ku < K) L.posl[c.perm[ku]] = ku;
     }
@@ -527,7 +530,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     int rs[lean ? 1 : EP];
     auto own = [&](int k) { return er + rows_per_pass * k; };
     auto sel = [&](int k) { return lean ? (own(k) < kpad ? L.rsel[own(k)] : 0) : rs[k]; };
-    auto inv_norm = [&](int k) { return lean ? 1.f / L.nrm[own(k)] : ninv[k]; };
+    auto inv_norm = [&](int k) { return lean ? L.ninv[own(k)] : ninv[k]; };
     const gp<float2> bkeep = gmem(static_cast<float2 *>(d.Msrt));
     auto rhs = [&](int k) -> float2 {
         if (!lean) return sb[k];
@@ -570,7 +573,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
             if (!lean) {
                 sb[k] = s0;
                 rs[k] = L.rsel[ku];
-                ninv[k] = 1.f / L.nrm[ku];
+                ninv[k] = L.ninv[ku];
             }
             pp[k] = phi_first(k);
             L.PF[ku * 16 + j] = pp[k];
