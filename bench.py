@@ -21,9 +21,12 @@ One step = the hot path over the whole batch: the forward solve of every
 vector with the chosen variant (VR-OAHK by default) and the
 implicit-differentiation adjoint (b = H g, adjoint solve, gradient
 assembly). The plan (VR graph, colours, tiles) and the row norms / tile
-packing of the channels are built once before timing. The forward solve
-kernel is timed live with HIP events on the stream it runs on; its
-algorithmic flops over that time are the roofline's "achieved".
+packing of the channels are built once before timing. The step is
+captured once into a HIP graph and the timed value comes from replays of
+it (--eager: from eager launches). The forward solve kernel is timed live
+with HIP events on the stream it runs on, in an eager loop before the
+replays; its algorithmic flops over that time are the roofline's
+"achieved".
 
 Prints one JSON line. Extra fields: per-variant forward rates, the plain
 single-instance rate (one vector per launch), accuracy of every vector
@@ -245,6 +248,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager launches instead of replays of the step captured in a HIP graph")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after timing, copy a device buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -318,6 +323,23 @@ def main():
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / args.steps
     solve_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms_eager = ms_step
+    if not args.eager:
+        # the step captured once into a HIP graph and replayed: the timed
+        # value (the eager loop above gives the live per-launch solve time)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.solve(stats=stats)
+            plan.solve_adjoint(stats=stats_adj)
+        for _ in range(max(1, args.warmup)):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for i in range(args.steps):
+            graph.replay()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = t0.elapsed_time(t1) / args.steps
     value = B / (ms_step * 1e-3)
 
     # accuracy of every vector vs the FP64 Cholesky RZF, and the flop count
@@ -362,6 +384,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if c128 else "f32", "data": "synthetic",
+        "timing": "eager launches" if args.eager else
+                  "HIP graph of the step, replayed (eager: %.4f ms per step)" % ms_eager,
         "config": {"workload": WORKLOADS[wl], "variant": args.variant, "engine": engine,
                    "tile_waves": int(eng[2]), "persistent": int(eng[4]), "entries_per_thread": int(eng[6]),
                    "drops": len(drops), "vectors": B, "tol": tol},
