@@ -26,7 +26,8 @@ F_CONVERGED, F_NONFINITE, F_MAXITER = 1, 2, 4
 class _Problem(C.Structure):
     _fields_ = [("nt", C.c_int32), ("k", C.c_int32), ("xi", C.c_double),
                 ("H", C.c_void_p), ("ldh", C.c_int64),
-                ("vs", C.c_void_p), ("vl", C.c_void_p)]
+                ("vs", C.c_void_p), ("vl", C.c_void_p),
+                ("mask", C.c_void_p), ("n_sub", C.c_int32)]
 
 
 _lib = None
@@ -74,14 +75,16 @@ def _ptr(a: np.ndarray) -> int:
 class Problem:
     """Keeps the arrays of one drop alive and exposes the C struct."""
 
-    def __init__(self, H, vr_start, vr_len, xi):
+    def __init__(self, H, vr_start, vr_len, xi, masks=None, n_sub=0):
         self.H = np.ascontiguousarray(H, dtype=np.complex128)
         self.vs = np.ascontiguousarray(vr_start, dtype=np.int32)
         self.vl = np.ascontiguousarray(vr_len, dtype=np.int32)
         self.k, self.nt = self.H.shape
         self.xi = float(xi)
+        self.mask = None if masks is None else np.ascontiguousarray(masks, dtype=np.uint64)
         self.c = _Problem(self.nt, self.k, self.xi, _ptr(self.H), self.nt,
-                          _ptr(self.vs), _ptr(self.vl))
+                          _ptr(self.vs), _ptr(self.vl),
+                          None if self.mask is None else _ptr(self.mask), int(n_sub))
 
     @property
     def ref(self):
@@ -110,26 +113,26 @@ def uniform24(seed: int, step: int, rhs: int, drop: int) -> float:
     return _load().orc_uniform24(seed, step, rhs, drop)
 
 
-def overlap_sets(H, vr_start, vr_len, xi=1.0):
+def overlap_sets(H, vr_start, vr_len, xi=1.0, masks=None, n_sub=0):
     """Non-orthogonal sets X_k (including k) as a list of index arrays."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     xoff = np.zeros(p.k + 1, dtype=np.int32)
     xidx = np.zeros(p.k * p.k, dtype=np.int32)
     _check(_load().orc_overlap_sets(p.ref, _ptr(xoff), _ptr(xidx)))
     return [xidx[xoff[i]:xoff[i + 1]].copy() for i in range(p.k)]
 
 
-def mis(H, vr_start, vr_len, xi=1.0) -> np.ndarray:
+def mis(H, vr_start, vr_len, xi=1.0, masks=None, n_sub=0) -> np.ndarray:
     """Boolean mask of the orthogonal set F (maximum independent set)."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     m = np.zeros(p.k, dtype=np.uint8)
     _check(_load().orc_mis(p.ref, _ptr(m)))
     return m.astype(bool)
 
 
-def rzf(H, vr_start, vr_len, S, xi):
+def rzf(H, vr_start, vr_len, S, xi, masks=None, n_sub=0):
     """Closed-form RZF via Cholesky: returns (X, V), X = B x Nt, V = B x K."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     S = np.ascontiguousarray(np.atleast_2d(S), dtype=np.complex128)
     B = S.shape[0]
     X = np.zeros((B, p.nt), dtype=np.complex128)
@@ -138,10 +141,10 @@ def rzf(H, vr_start, vr_len, S, xi):
     return X, V
 
 
-def rzf_grad(H, vr_start, vr_len, S, xi, G):
+def rzf_grad(H, vr_start, vr_len, S, xi, G, masks=None, n_sub=0):
     """Closed-form gradient (torch convention) of a real loss whose gradient
     on X is G: returns (gH, gS, gxi)."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     S = np.ascontiguousarray(np.atleast_2d(S), dtype=np.complex128)
     G = np.ascontiguousarray(np.atleast_2d(G), dtype=np.complex128)
     B = S.shape[0]
@@ -154,11 +157,11 @@ def rzf_grad(H, vr_start, vr_len, S, xi, G):
 
 
 def solve(H, vr_start, vr_len, s, xi, variant="vr_oahk", select="baiwu", tol=1e-10,
-          max_iters=100000, seed=0, drop=0, rhs=0, trace=False):
+          max_iters=100000, seed=0, drop=0, rhs=0, trace=False, masks=None, n_sub=0):
     """One right-hand side. Returns a dict with x, q, iters, relres, flags
     and, with ``trace=True``, z (every iterate [x; q]) and idx (rows chosen,
     -1 / -2 for the F / V half-steps, -3 for z0)."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     s = np.ascontiguousarray(s, dtype=np.complex128).reshape(p.k)
     x = np.zeros(p.nt, dtype=np.complex128)
     q = np.zeros(p.k, dtype=np.complex128)
@@ -182,9 +185,9 @@ def solve(H, vr_start, vr_len, s, xi, variant="vr_oahk", select="baiwu", tol=1e-
 
 
 def solve_batch(H, vr_start, vr_len, S, xi, variant="vr_oahk", select="baiwu", tol=1e-5,
-                max_iters=100000, seed=0, drop=0):
+                max_iters=100000, seed=0, drop=0, masks=None, n_sub=0):
     """All right-hand sides of one drop (OpenMP over rows of S)."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     S = np.ascontiguousarray(np.atleast_2d(S), dtype=np.complex128)
     B = S.shape[0]
     X = np.zeros((B, p.nt), dtype=np.complex128)
@@ -198,8 +201,8 @@ def solve_batch(H, vr_start, vr_len, S, xi, variant="vr_oahk", select="baiwu", t
     return dict(X=X, V=V, iters=it, relres=rel, flags=fl)
 
 
-def residual(H, vr_start, vr_len, xi, s, x, q) -> np.ndarray:
-    p = Problem(H, vr_start, vr_len, xi)
+def residual(H, vr_start, vr_len, xi, s, x, q, masks=None, n_sub=0) -> np.ndarray:
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     s = np.ascontiguousarray(s, dtype=np.complex128)
     x = np.ascontiguousarray(x, dtype=np.complex128)
     q = np.ascontiguousarray(q, dtype=np.complex128)
@@ -208,16 +211,16 @@ def residual(H, vr_start, vr_len, xi, s, x, q) -> np.ndarray:
     return r
 
 
-def row_norms(H, vr_start, vr_len, xi) -> np.ndarray:
-    p = Problem(H, vr_start, vr_len, xi)
+def row_norms(H, vr_start, vr_len, xi, masks=None, n_sub=0) -> np.ndarray:
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     nrm = np.zeros(p.k, dtype=np.float64)
     _load().orc_row_norms(p.ref, _ptr(nrm))
     return nrm
 
 
-def step_row(H, vr_start, vr_len, xi, i, s, x, q):
+def step_row(H, vr_start, vr_len, xi, i, s, x, q, masks=None, n_sub=0):
     """One projection (update) onto row i; returns new (x, q)."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     s = np.ascontiguousarray(s, dtype=np.complex128)
     x = np.array(x, dtype=np.complex128)
     q = np.array(q, dtype=np.complex128)
@@ -225,9 +228,9 @@ def step_row(H, vr_start, vr_len, xi, i, s, x, q):
     return x, q
 
 
-def step_orthogonal(H, vr_start, vr_len, xi, in_f, s, x, q):
+def step_orthogonal(H, vr_start, vr_len, xi, in_f, s, x, q, masks=None, n_sub=0):
     """Proposition 1 step (gamma = 1) over the mask in_f; returns (x, q)."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     m = np.ascontiguousarray(in_f, dtype=np.uint8)
     s = np.ascontiguousarray(s, dtype=np.complex128)
     x = np.array(x, dtype=np.complex128)
@@ -236,9 +239,9 @@ def step_orthogonal(H, vr_start, vr_len, xi, in_f, s, x, q):
     return x, q
 
 
-def step_aggregate(H, vr_start, vr_len, xi, in_set, s, x, q):
+def step_aggregate(H, vr_start, vr_len, xi, in_set, s, x, q, masks=None, n_sub=0):
     """Aggregated projection (update4) over the mask in_set; returns (x, q)."""
-    p = Problem(H, vr_start, vr_len, xi)
+    p = Problem(H, vr_start, vr_len, xi, masks, n_sub)
     m = np.ascontiguousarray(in_set, dtype=np.uint8)
     s = np.ascontiguousarray(s, dtype=np.complex128)
     x = np.array(x, dtype=np.complex128)
@@ -301,3 +304,35 @@ def nmse(F_ref, F):
     """||F_ref - F||_F / ||F_ref||_F, the NMSE of the simulation section."""
     F_ref = np.asarray(F_ref)
     return float(np.linalg.norm(F_ref - np.asarray(F)) / np.linalg.norm(F_ref))
+
+
+# ---------------------------------------------------------------------------
+# Subarray VR model of Sec. II: the array is split into S subarrays of
+# Nt / S antennas and user k sees the subarrays of M_k, so its VR is their
+# union. Masks are per-user integers, bit s set when subarray s is visible;
+# every function above takes them as ``masks`` (with ``n_sub`` = S), the
+# VR interval then being the hull of the visible subarrays. The two
+# definitions below are plain numpy, for the tests.
+# ---------------------------------------------------------------------------
+
+def mask_indicator(masks, nt, n_sub):
+    """K x Nt 0/1 matrix of the VR indicator vectors u_k (eq. VR)."""
+    L = nt // n_sub
+    U = np.zeros((len(masks), nt), dtype=np.int8)
+    for k, m in enumerate(masks):
+        for s in range(n_sub):
+            if (int(m) >> s) & 1:
+                U[k, s * L:(s + 1) * L] = 1
+    return U
+
+
+def mask_graph(masks):
+    """Adjacency of the VR graph: an edge between users that share a visible
+    subarray (|M_i cap M_j| > 0), no self loops."""
+    K = len(masks)
+    A = np.zeros((K, K), dtype=bool)
+    for i in range(K):
+        for j in range(K):
+            A[i, j] = i != j and (int(masks[i]) & int(masks[j])) != 0
+    return A
+

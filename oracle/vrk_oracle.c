@@ -43,9 +43,19 @@ typedef struct {
     const cplx *H;          /* K x Nt, row stride ldh */
     int64_t ldh;
     const int32_t *vs, *vl; /* VR start / length per user */
+    const uint64_t *mask;   /* null, or per user the visible subarrays (bit s) */
+    int32_t n_sub;          /* subarrays S of Nt / S antennas each (with mask) */
 } orc_problem;
 
 static inline int32_t vr_end(const orc_problem *p, int i) { return p->vs[i] + p->vl[i]; }
+
+/* Antenna n is in user k's VR: inside [vs, ve) and, with subarray masks,
+ * on a subarray of M_k (the indicator u_k of the subarray VR model, Sec. II).
+ * Loops below run over [vs, ve) and skip the antennas this rejects. */
+static inline int seen(const orc_problem *p, int k, int32_t n)
+{
+    return !p->mask || ((p->mask[k] >> (n / (p->nt / p->n_sub))) & 1u);
+}
 
 static int validate(const orc_problem *p)
 {
@@ -55,6 +65,24 @@ static int validate(const orc_problem *p)
     for (int i = 0; i < p->k; ++i)
         if (p->vs[i] < 0 || p->vl[i] < 0 || (int64_t)p->vs[i] + p->vl[i] > p->nt)
             return ORC_EINVAL;
+    if (p->mask) {
+        /* [vs, ve) must be the hull of the visible subarrays */
+        if (p->n_sub < 1 || p->n_sub > 64 || p->nt % p->n_sub) return ORC_EINVAL;
+        const int32_t L = p->nt / p->n_sub;
+        for (int i = 0; i < p->k; ++i) {
+            uint64_t m = p->mask[i];
+            if (p->n_sub < 64 && (m >> p->n_sub)) return ORC_EINVAL;
+            int32_t lo = 0, hi = 0;
+            if (m) {
+                int s0 = 0, s1 = p->n_sub - 1;
+                while (!((m >> s0) & 1u)) ++s0;
+                while (!((m >> s1) & 1u)) --s1;
+                lo = s0 * L;
+                hi = (s1 + 1) * L;
+            }
+            if (p->vs[i] != lo || vr_end(p, i) != hi) return ORC_EINVAL;
+        }
+    }
     return ORC_OK;
 }
 
@@ -102,6 +130,7 @@ double orc_uniform24(uint64_t seed, int64_t step, int64_t rhs, int64_t drop)
  * ---------------------------------------------------------------------- */
 static int vr_overlap(const orc_problem *p, int i, int j)
 {
+    if (p->mask) return (p->mask[i] & p->mask[j]) != 0;   /* |M_i cap M_j| > 0 */
     int32_t lo = p->vs[i] > p->vs[j] ? p->vs[i] : p->vs[j];
     int32_t hi = vr_end(p, i) < vr_end(p, j) ? vr_end(p, i) : vr_end(p, j);
     return lo < hi;
@@ -123,7 +152,8 @@ int orc_overlap_sets(const orc_problem *p, int32_t *xoff, int32_t *xidx)
 }
 
 /* Orthogonal set F: a maximum independent set of the VR overlap graph
- * (problem max_set of Sec. V-B). For contiguous VRs the graph is an
+ * (problem max_set of Sec. V-B). With subarray masks see
+ * mis_reducing_peeling below. For contiguous VRs the graph is an
  * interval graph, on which the earliest-end greedy is exact: visit users by
  * (end, start, index) and keep one whose start is at or after the end of
  * the last kept one. Users with an empty VR overlap nobody and are always
@@ -136,9 +166,58 @@ static int before_by_end(const orc_problem *p, int i, int j)
     return i < j;
 }
 
+/* F on the general VR graph of the subarray model (edge iff the masks
+ * share a subarray), where maximum independent set is hard: the
+ * reducing-peeling heuristic of the linear-time method the paper cites for
+ * problem max_set. While vertices remain: a vertex of degree 0 joins F; else
+ * a vertex of degree 1 joins F and its neighbour is deleted (both exact
+ * reductions); else a vertex of largest degree is peeled (deleted). Degrees
+ * count remaining vertices; ties go to the smallest index. Afterwards the
+ * peeled vertices, latest first, join F when no neighbour is in it, so F is
+ * maximal. */
+static void mis_reducing_peeling(const orc_problem *p, uint8_t *in_f)
+{
+    const int K = p->k;
+    uint8_t *alive = malloc(K);
+    int *peeled = malloc(sizeof(int) * K), np = 0;
+    for (int v = 0; v < K; ++v) { alive[v] = 1; in_f[v] = 0; }
+    for (;;) {
+        int pick0 = -1, pick1 = -1, pickp = -1, dmax = -1;
+        for (int v = 0; v < K; ++v) {
+            if (!alive[v]) continue;
+            int d = 0;
+            for (int u = 0; u < K; ++u)
+                if (u != v && alive[u] && vr_overlap(p, u, v)) ++d;
+            if (d == 0 && pick0 < 0) pick0 = v;
+            if (d == 1 && pick1 < 0) pick1 = v;
+            if (d > dmax) { dmax = d; pickp = v; }
+        }
+        if (pickp < 0) break;                  /* nothing left */
+        if (pick0 >= 0) { in_f[pick0] = 1; alive[pick0] = 0; continue; }
+        if (pick1 >= 0) {
+            in_f[pick1] = 1;
+            alive[pick1] = 0;
+            for (int u = 0; u < K; ++u)
+                if (u != pick1 && alive[u] && vr_overlap(p, u, pick1)) alive[u] = 0;
+            continue;
+        }
+        alive[pickp] = 0;
+        peeled[np++] = pickp;
+    }
+    for (int t = np - 1; t >= 0; --t) {
+        int v = peeled[t], free_v = 1;
+        for (int u = 0; u < K && free_v; ++u)
+            if (in_f[u] && vr_overlap(p, u, v)) free_v = 0;
+        if (free_v) in_f[v] = 1;
+    }
+    free(alive);
+    free(peeled);
+}
+
 int orc_mis(const orc_problem *p, uint8_t *in_f)
 {
     if (validate(p)) return ORC_EINVAL;
+    if (p->mask) { mis_reducing_peeling(p, in_f); return ORC_OK; }
     int *ord = malloc(sizeof(int) * p->k);
     int n = 0;
     for (int k = 0; k < p->k; ++k) {
@@ -174,7 +253,8 @@ static void gram(const orc_problem *p, cplx *M)
             int32_t lo = p->vs[i] > p->vs[j] ? p->vs[i] : p->vs[j];
             int32_t hi = vr_end(p, i) < vr_end(p, j) ? vr_end(p, i) : vr_end(p, j);
             for (int32_t n = lo; n < hi; ++n)
-                acc += p->H[i * p->ldh + n] * conj(p->H[j * p->ldh + n]);
+                if (seen(p, i, n) && seen(p, j, n))
+                    acc += p->H[i * p->ldh + n] * conj(p->H[j * p->ldh + n]);
             M[i * K + j] = acc + (i == j ? p->xi : 0.0);
         }
 }
@@ -219,7 +299,8 @@ static void apply_hh(const orc_problem *p, const cplx *v, cplx *x)
     for (int n = 0; n < p->nt; ++n) x[n] = 0;
     for (int k = 0; k < p->k; ++k)
         for (int32_t n = p->vs[k]; n < vr_end(p, k); ++n)
-            x[n] += conj(p->H[k * p->ldh + n]) * v[k];
+            if (seen(p, k, n))
+                x[n] += conj(p->H[k * p->ldh + n]) * v[k];
 }
 
 /* b = H g over the VR bands. */
@@ -227,7 +308,8 @@ static void apply_h(const orc_problem *p, const cplx *g, cplx *b)
 {
     for (int k = 0; k < p->k; ++k) {
         cplx acc = 0;
-        for (int32_t n = p->vs[k]; n < vr_end(p, k); ++n) acc += p->H[k * p->ldh + n] * g[n];
+        for (int32_t n = p->vs[k]; n < vr_end(p, k); ++n)
+            if (seen(p, k, n)) acc += p->H[k * p->ldh + n] * g[n];
         b[k] = acc;
     }
 }
@@ -289,7 +371,8 @@ int orc_rzf_grad(const orc_problem *p, int32_t nrhs, const cplx *S, int64_t lds,
             gS[(int64_t)b * ldgs + k] = mu[k];
             acc_xi -= creal(conj(mu[k]) * v[k]);
             for (int32_t n = p->vs[k]; n < vr_end(p, k); ++n)
-                gH[k * ldgh + n] += v[k] * conj(g[n] - xh[n]) - mu[k] * conj(x[n]);
+                if (seen(p, k, n))
+                    gH[k * ldgh + n] += v[k] * conj(g[n] - xh[n]) - mu[k] * conj(x[n]);
         }
     }
     *gxi = acc_xi;
@@ -307,6 +390,7 @@ static double row_norm2(const orc_problem *p, int i)
 {
     double acc = 0.0;
     for (int32_t n = p->vs[i]; n < vr_end(p, i); ++n) {
+        if (!seen(p, i, n)) continue;
         cplx h = p->H[i * p->ldh + n];
         acc += creal(h) * creal(h) + cimag(h) * cimag(h);
     }
@@ -318,7 +402,8 @@ static double row_norm2(const orc_problem *p, int i)
 static cplx residual_row(const orc_problem *p, int i, const cplx *s, const cplx *x, const cplx *q)
 {
     cplx acc = 0;
-    for (int32_t n = p->vs[i]; n < vr_end(p, i); ++n) acc += p->H[i * p->ldh + n] * x[n];
+    for (int32_t n = p->vs[i]; n < vr_end(p, i); ++n)
+        if (seen(p, i, n)) acc += p->H[i * p->ldh + n] * x[n];
     return s[i] - acc - p->xi * q[i];
 }
 
@@ -327,7 +412,8 @@ static cplx residual_row(const orc_problem *p, int i, const cplx *s, const cplx 
 static void project_row(const orc_problem *p, int i, cplx r_i, double nrm_i, cplx *x, cplx *q)
 {
     cplx gamma = r_i / nrm_i;
-    for (int32_t n = p->vs[i]; n < vr_end(p, i); ++n) x[n] += gamma * conj(p->H[i * p->ldh + n]);
+    for (int32_t n = p->vs[i]; n < vr_end(p, i); ++n)
+        if (seen(p, i, n)) x[n] += gamma * conj(p->H[i * p->ldh + n]);
     q[i] += gamma;
 }
 
@@ -368,7 +454,8 @@ static void project_orthogonal(const orc_problem *p, const uint8_t *in_f, const 
     for (int i = 0; i < p->k; ++i)
         if (in_f[i]) {
             cplx phi = r[i] / nrm[i];
-            for (int32_t n = p->vs[i]; n < vr_end(p, i); ++n) x[n] += phi * conj(p->H[i * p->ldh + n]);
+            for (int32_t n = p->vs[i]; n < vr_end(p, i); ++n)
+                if (seen(p, i, n)) x[n] += phi * conj(p->H[i * p->ldh + n]);
             q[i] += phi;
         }
 }

@@ -9,6 +9,8 @@ from .channels import (  # noqa: F401
     Drop,
     WORKLOADS,
     make_drop,
+    make_subarray_drop,
+    mask_hulls,
     make_workload,
     qpsk,
     qam16,

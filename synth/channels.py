@@ -41,6 +41,8 @@ class Drop:
     S: np.ndarray          # (B, K) complex128, one symbol vector per row
     xi: float              # regulariser K / SNR_linear
     snr_db: float
+    vr_mask: np.ndarray | None = None   # (K,) uint64 visible subarrays, subarray model only
+    n_sub: int = 0                      # subarrays S of the subarray model
 
     @property
     def nt(self) -> int:
@@ -109,6 +111,66 @@ def make_drop(rng: np.random.Generator, *, nt: int, k: int, nrhs: int,
     return Drop(H=H, vr_start=vstart, vr_len=vlen, S=S, xi=float(xi), snr_db=float(snr_db))
 
 
+def mask_hulls(masks, nt: int, n_sub: int):
+    """Per-user (vr_start, vr_len) of the smallest antenna interval holding
+    every visible subarray (0, 0 for a user that sees none)."""
+    L = nt // n_sub
+    vs = np.zeros(len(masks), dtype=np.int32)
+    vl = np.zeros(len(masks), dtype=np.int32)
+    for k, m in enumerate(masks):
+        bits = [s for s in range(n_sub) if (int(m) >> s) & 1]
+        if bits:
+            vs[k] = bits[0] * L
+            vl[k] = (bits[-1] + 1) * L - vs[k]
+    return vs, vl
+
+
+def make_subarray_drop(rng: np.random.Generator, *, nt: int, k: int, nrhs: int, n_sub: int,
+                       p_vis: float, snr_db: float, fc: float = 100e9, r_lo: float = 1.0,
+                       r_hi: float = 50.0, ang_deg: float = 60.0, nlos_var: float = 0.1,
+                       symbols: str = "qpsk") -> Drop:
+    """Draw one drop of the subarray VR model: the array is split into
+    ``n_sub`` subarrays of ``nt / n_sub`` antennas and each subarray is
+    visible to each user independently with probability ``p_vis``. The
+    channel is the spherical-wave LoS path (+ CN(0, nlos_var)) on the
+    visible antennas and exactly zero on the hidden ones, so each user's
+    interval (the hull of its visible subarrays) may hold zero gaps.
+    Draw order: ranges, angles, visibility (user by user, subarray by
+    subarray), NLoS entries (user by user over the hull), symbols."""
+    if nt % n_sub or not 1 <= n_sub <= 64:
+        raise ValueError("nt must be a multiple of n_sub, 1 <= n_sub <= 64")
+    lam = C_LIGHT / fc
+    d = lam / 2.0
+    L = nt // n_sub
+    r = rng.uniform(r_lo, r_hi, size=k)
+    th = np.deg2rad(rng.uniform(-ang_deg, ang_deg, size=k))
+    vis = rng.random((k, n_sub)) < p_vis
+    masks = np.array([sum(1 << s for s in range(n_sub) if vis[u, s]) for u in range(k)],
+                     dtype=np.uint64)
+    vstart, vlen = mask_hulls(masks, nt, n_sub)
+    delta = (np.arange(nt) - (nt - 1) / 2.0) * d
+    H = np.zeros((k, nt), dtype=np.complex128)
+    for u in range(k):
+        rk = np.sqrt(r[u] ** 2 + delta ** 2 - 2.0 * r[u] * delta * np.sin(th[u]))
+        H[u] = np.exp(-2j * np.pi * rk / lam) / rk
+    if nlos_var > 0.0:
+        sd = math.sqrt(nlos_var / 2.0)
+        for u in range(k):
+            a, n = int(vstart[u]), int(vlen[u])
+            g = rng.standard_normal((n, 2)) * sd
+            H[u, a:a + n] += g[:, 0] + 1j * g[:, 1]
+    H *= np.repeat(vis, L, axis=1)
+    if symbols == "qpsk":
+        S = qpsk(rng, (nrhs, k))
+    elif symbols == "qam16":
+        S = qam16(rng, (nrhs, k))
+    else:
+        raise ValueError(symbols)
+    xi = k / (10.0 ** (snr_db / 10.0))
+    return Drop(H=H, vr_start=vstart, vr_len=vlen, S=S, xi=float(xi), snr_db=float(snr_db),
+                vr_mask=masks, n_sub=n_sub)
+
+
 def _rng(cfg: int, seed: int, drop: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([cfg, seed, drop])))
 
@@ -119,12 +181,16 @@ def _rng(cfg: int, seed: int, drop: int) -> np.random.Generator:
 #   uneven     - 512 drops, Nt in {512,1024,2048}, K in [16,128], 256 vectors each
 #   adjoint    - 256 drops of Nt=1024, K=64 with 64 QPSK vectors, SNR 10 dB
 #   large      - 64 drops of Nt=4096, K=256, 1024 16-QAM vectors, SNR 10 dB
+#   subarray   - 64 drops of the simulation setting of the paper: Nt=2000 at
+#                100 GHz in S=20 subarrays, each visible w.p. 0.35, K=30 users
+#                at 1..50 m, SNR 0 dB; 256 QPSK vectors each
 WORKLOADS = {
     "plain": dict(cfg=0, seed=0),
     "many_rhs": dict(cfg=1, seed=1),
     "uneven": dict(cfg=2, seed=2),
     "adjoint": dict(cfg=3, seed=3),
     "large": dict(cfg=4, seed=4),
+    "subarray": dict(cfg=5, seed=5),
 }
 
 
@@ -173,6 +239,13 @@ def make_workload(name: str, *, drops: int | None = None, nrhs: int | None = Non
             out.append(make_drop(rng, nt=n, k=kk, nrhs=nrhs or 1024, vr_lo=n // 16, vr_hi=n // 4,
                                  snr_db=10.0 if snr_db is None else snr_db, nlos_var=0.1,
                                  symbols="qam16"))
+    elif name == "subarray":
+        n = nt or 2000
+        kk = k or 30
+        for dd in range(drops or 64):
+            rng = _rng(cfg, sd, dd)
+            out.append(make_subarray_drop(rng, nt=n, k=kk, nrhs=nrhs or 256, n_sub=20, p_vis=0.35,
+                                          snr_db=0.0 if snr_db is None else snr_db))
     else:
         raise KeyError(name)
     return out

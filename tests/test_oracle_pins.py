@@ -15,6 +15,7 @@ import pytest
 import scipy.linalg
 
 import oracle
+import synth
 from tests.helpers import augmented, qpsk, random_problem, rzf_numpy
 
 
@@ -667,3 +668,205 @@ def test_interference_is_what_user_u_receives():
     assert abs(beta ** 2 - b2) <= 1e-15
     assert abs(rate[0] - np.log2(1 + b2 * 16 / xi)) <= 1e-12
     assert abs(rate[1] - np.log2(1 + b2 * abs(e11) ** 2 / (b2 * abs(e10) ** 2 + xi))) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Subarray VR model (Sec. II) and the orthogonal set on a general VR graph
+# (Sec. V-B)
+# ---------------------------------------------------------------------------
+
+def _brute_mis(adj):
+    K = adj.shape[0]
+    best = 0
+    for m in range(1 << K):
+        ids = [i for i in range(K) if (m >> i) & 1]
+        if all(not adj[a, b] for a in ids for b in ids):
+            best = max(best, len(ids))
+    return best
+
+
+def _graph_as_masks(adj):
+    """Subarray masks whose VR graph is adj: one subarray per edge (and
+    one private subarray per vertex with no edge, so every VR is nonempty
+    except where noted). Returns (masks, n_sub, nt, vs, vl, H=0)."""
+    K = adj.shape[0]
+    edges = [(i, j) for i in range(K) for j in range(i + 1, K) if adj[i, j]]
+    masks = [0] * K
+    for s, (i, j) in enumerate(edges):
+        masks[i] |= 1 << s
+        masks[j] |= 1 << s
+    n_sub = len(edges)
+    for v in range(K):
+        if masks[v] == 0:
+            masks[v] = 1 << n_sub
+            n_sub += 1
+    n_sub = max(n_sub, 1)
+    assert n_sub <= 64
+    nt = 2 * n_sub
+    vs, vl = synth.mask_hulls(masks, nt, n_sub)
+    return np.array(masks, dtype=np.uint64), n_sub, nt, vs, vl, np.zeros((K, nt), complex)
+
+
+def _f_of_graph(adj):
+    masks, n_sub, nt, vs, vl, H = _graph_as_masks(adj)
+    assert np.array_equal(oracle.mask_graph(masks), adj)
+    return oracle.mis(H, vs, vl, 1.0, masks=masks, n_sub=n_sub)
+
+
+def _random_forest(rng, K):
+    adj = np.zeros((K, K), dtype=bool)
+    for v in range(1, K):
+        if rng.random() < 0.8:
+            u = int(rng.integers(0, v))
+            adj[u, v] = adj[v, u] = True
+    return adj
+
+
+def test_reducing_peeling_exact_on_forests_and_maximal_on_graphs():
+    rng = np.random.default_rng(61)
+    for _ in range(40):
+        K = int(rng.integers(1, 14))
+        adj = _random_forest(rng, K)
+        F = _f_of_graph(adj)
+        assert not np.any(adj[np.ix_(F, F)])
+        assert F.sum() == _brute_mis(adj)          # degree-0/1 reductions are exact on forests
+    for _ in range(40):
+        K = int(rng.integers(2, 11))
+        while True:
+            a = np.triu(rng.random((K, K)) < rng.uniform(0.1, 0.8), 1)
+            if a.sum() <= 60:
+                break
+        adj = a | a.T
+        F = _f_of_graph(adj)
+        assert not np.any(adj[np.ix_(F, F)])          # independent
+        for v in np.flatnonzero(~F):                  # maximal
+            assert np.any(adj[v, F])
+        assert F.sum() <= _brute_mis(adj)
+
+
+def test_reducing_peeling_small_cases():
+    # a 5-cycle has no vertex of degree <= 1: one peel, then a path of 4
+    # (independence number 2); a triangle with a pendant vertex keeps the
+    # pendant vertex and one far corner; a star keeps all leaves
+    c5 = np.zeros((5, 5), bool)
+    for i in range(5):
+        c5[i, (i + 1) % 5] = c5[(i + 1) % 5, i] = True
+    F = _f_of_graph(c5)
+    assert F.sum() == 2 and not np.any(c5[np.ix_(F, F)])
+    tri = np.zeros((4, 4), bool)
+    for i, j in [(0, 1), (1, 2), (0, 2), (2, 3)]:
+        tri[i, j] = tri[j, i] = True
+    assert np.array_equal(_f_of_graph(tri), [True, False, False, True])
+    star = np.zeros((6, 6), bool)
+    star[0, 1:] = star[1:, 0] = True
+    assert np.array_equal(_f_of_graph(star), [False] + [True] * 5)
+
+
+def test_subarray_graph_matches_antenna_indicators():
+    # the subarray-level edge rule |M_i cap M_j| > 0 equals overlap of the
+    # antenna-level indicator vectors u_i, u_j; users with no visible
+    # subarray overlap nobody and are always in F
+    rng = np.random.default_rng(62)
+    nt, S, K = 120, 12, 9
+    masks = np.array([sum(1 << s for s in range(S) if rng.random() < 0.35) for _ in range(K)],
+                     dtype=np.uint64)
+    masks[0] = 0
+    U = oracle.mask_indicator(masks, nt, S)
+    vs, vl = synth.mask_hulls(masks, nt, S)
+    H = np.zeros((K, nt), complex)
+    sets = oracle.overlap_sets(H, vs, vl, 1.0, masks=masks, n_sub=S)
+    ov = (U.astype(int) @ U.T.astype(int)) > 0
+    for k in range(K):
+        want = sorted(set(np.flatnonzero(ov[k]).tolist()) | {k})
+        assert sets[k].tolist() == want
+    F = oracle.mis(H, vs, vl, 1.0, masks=masks, n_sub=S)
+    assert F[0]
+    assert not np.any((ov & ~np.eye(K, dtype=bool))[np.ix_(F, F)])
+    for k in range(K):
+        idx = np.flatnonzero(U[k])
+        if idx.size == 0:
+            assert vl[k] == 0
+        else:
+            assert vs[k] == idx[0] and vs[k] + vl[k] == idx[-1] + 1
+
+
+def _masked_drop(seed, nt=96, S=8, K=7, p=0.4):
+    rng = np.random.default_rng(seed)
+    masks = np.array([sum(1 << s for s in range(S) if rng.random() < p) or (1 << k % S)
+                      for k in range(K)], dtype=np.uint64)
+    U = oracle.mask_indicator(masks, nt, S)
+    Hbar = rng.standard_normal((K, nt)) + 1j * rng.standard_normal((K, nt))
+    vs, vl = synth.mask_hulls(masks, nt, S)
+    return masks, S, U, Hbar, vs, vl, rng
+
+
+def test_masked_oracle_reads_only_visible_antennas():
+    # with masks the oracle works on h_k = hbar_k * u_k (channel equation
+    # with the subarray indicator): the hidden entries of Hbar are never
+    # read, and the result is the dense RZF of Hbar * U, the same as the
+    # hull-band model given zero gaps
+    masks, S, U, Hbar, vs, vl, rng = _masked_drop(63)
+    K, nt = Hbar.shape
+    xi = 0.7
+    Hm = Hbar * U
+    Sm = rng.standard_normal((3, K)) + 1j * rng.standard_normal((3, K))
+    X, V = oracle.rzf(Hbar, vs, vl, Sm, xi, masks=masks, n_sub=S)
+    M = Hm @ Hm.conj().T + xi * np.eye(K)
+    Vd = np.linalg.solve(M, Sm.T).T
+    Xd = Vd @ Hm.conj()
+    assert np.max(np.abs(X - Xd)) <= 1e-12 * np.max(np.abs(Xd))
+    assert np.max(np.abs(V - Vd)) <= 1e-12 * np.max(np.abs(Vd))
+    X2, _ = oracle.rzf(Hm, vs, vl, Sm, xi)
+    assert np.max(np.abs(X2 - Xd)) <= 1e-12 * np.max(np.abs(Xd))
+    for variant in ("vr_oahk", "vr_ogrk", "ahk", "grk"):
+        out = oracle.solve(Hbar, vs, vl, Sm[0], xi, variant=variant, tol=1e-11,
+                           masks=masks, n_sub=S)
+        assert out["flags"] & oracle.F_CONVERGED
+        assert np.max(np.abs(out["x"] - Xd[0])) <= 1e-9 * np.max(np.abs(Xd[0]))
+        assert np.all(out["x"][U.sum(axis=0) == 0] == 0)   # antennas no user sees stay 0
+
+
+def test_masked_gradient_is_dense_gradient_on_visible_entries():
+    # dL/dH of the subarray model = the dense model's gradient at H = Hbar * U
+    # on the visible entries, zero on the hidden ones (chain rule of the
+    # fixed indicator)
+    masks, S, U, Hbar, vs, vl, rng = _masked_drop(64)
+    K, nt = Hbar.shape
+    Sm = rng.standard_normal((2, K)) + 1j * rng.standard_normal((2, K))
+    G = rng.standard_normal((2, nt)) + 1j * rng.standard_normal((2, nt))
+    gH, gS, gxi = oracle.rzf_grad(Hbar, vs, vl, Sm, 0.9, G, masks=masks, n_sub=S)
+    full = np.zeros(K, np.int32), np.full(K, nt, np.int32)
+    dH, dS, dxi = oracle.rzf_grad(Hbar * U, *full, Sm, 0.9, G)
+    assert np.max(np.abs(gH - dH * U)) <= 1e-12 * np.max(np.abs(dH))
+    assert np.max(np.abs(gS - dS)) <= 1e-12 * np.max(np.abs(dS))
+    assert abs(gxi - dxi) <= 1e-12 * abs(dxi)
+
+
+def test_masked_orthogonal_step_is_sequential_projection():
+    # Proposition 1 under the subarray model: users of F with disjoint masks
+    # have orthogonal rows even where their hulls overlap, so the one-shot
+    # step over F equals projecting onto its rows one after another
+    masks, S, U, Hbar, vs, vl, rng = _masked_drop(65, K=9, p=0.25)
+    K, nt = Hbar.shape
+    kw = dict(masks=masks, n_sub=S)
+    F = oracle.mis(Hbar, vs, vl, 0.5, **kw)
+    assert F.sum() >= 2
+    s = rng.standard_normal(K) + 1j * rng.standard_normal(K)
+    x0 = rng.standard_normal(nt) + 1j * rng.standard_normal(nt)
+    q0 = rng.standard_normal(K) + 1j * rng.standard_normal(K)
+    x1, q1 = oracle.step_orthogonal(Hbar, vs, vl, 0.5, F, s, x0, q0, **kw)
+    x2, q2 = x0.copy(), q0.copy()
+    for i in np.flatnonzero(F):
+        x2, q2 = oracle.step_row(Hbar, vs, vl, 0.5, i, s, x2, q2, **kw)
+    assert np.max(np.abs(x1 - x2)) <= 1e-12 * np.max(np.abs(x2))
+    assert np.max(np.abs(q1 - q2)) <= 1e-12 * np.max(np.abs(q2))
+
+
+def test_masked_oracle_rejects_wrong_hulls():
+    masks, S, U, Hbar, vs, vl, rng = _masked_drop(66)
+    bad = vs.copy()
+    bad[np.argmax(vl)] += 1
+    with pytest.raises(ValueError):
+        oracle.rzf(Hbar, bad, vl, np.ones((1, Hbar.shape[0])), 1.0, masks=masks, n_sub=S)
+    with pytest.raises(ValueError):
+        oracle.mis(Hbar, vs, vl, 1.0, masks=masks, n_sub=7)   # 96 % 7 != 0
