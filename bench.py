@@ -12,6 +12,9 @@ complex64, relative-residual tolerance 1e-5. The other workloads:
   large    64 drops of Nt 4096, K 256, VR U[256, 1024], 1024 16-QAM vectors, SNR 10 dB
   plain    one drop Nt 256, K 16, LoS, VR U[64, 128], one QPSK vector, complex128,
            tolerance 1e-10
+  subarray 64 drops of the paper's simulation setting: Nt 2000 at 100 GHz in 20
+           subarrays, each visible to each user w.p. 0.35, K 30, SNR 0 dB,
+           256 QPSK vectors each (VRs are unions of subarrays)
   precoder the adjoint workload's 256 drops with S = I_K: each drop's RZF precoding
            matrix, its effective channel, beta and per-user spectral efficiency
            (metric: precoding matrices/s; see run_precoder)
@@ -61,6 +64,9 @@ WORKLOADS = {
              "SNR 10 dB, tol 1e-5; fwd+adjoint",
     "plain": "plain single instance: Nt=256, K=16, LoS, VR U[64,128], one QPSK vector, SNR 10 dB, "
              "complex128, tol 1e-10; fwd+adjoint",
+    "subarray": "subarray VRs (simulation setting of the paper): 64 drops of Nt=2000 at 100 GHz in S=20 "
+                "subarrays, each visible w.p. 0.35, K=30 at 1..50 m, LoS+CN(0,0.1) on visible antennas, "
+                "256 QPSK vectors each, SNR 0 dB, tol 1e-5; fwd+adjoint",
     "precoder": "RZF precoding matrices: 256 drops of Nt=1024, K=64, VR U[256,512], S = I_K, SNR 10 dB, "
                 "tol 1e-5; solve + effective channel + beta + per-user spectral efficiency",
 }
@@ -306,7 +312,8 @@ def main():
         V = torch.zeros((d.nrhs, d.k), dtype=cdt, device=dev)
         GX = (torch.randn((d.nrhs, d.nt), dtype=cdt, device=dev, generator=gen) / d.nrhs)
         specs.append(vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X, V, GX, torch.zeros_like(H),
-                                     torch.zeros_like(S), torch.zeros(1, dtype=torch.float64, device=dev)))
+                                     torch.zeros_like(S), torch.zeros(1, dtype=torch.float64, device=dev),
+                                     vr_mask=d.vr_mask, n_sub=d.n_sub))
     B = sum(d.nrhs for d in drops)
     opts = vrk.options(variant=args.variant, dtype=dname, engine=engine_opt, tol=tol,
                        tile_waves=args.tile_waves, persistent=args.persistent)
@@ -368,13 +375,15 @@ def main():
     fl_all = stats[2].cpu().numpy()
     worst, errsum, flops, base = 0.0, 0.0, 0.0, 0
     for j, (d, sp) in enumerate(zip(drops, specs)):
-        Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+        Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi, masks=d.vr_mask, n_sub=d.n_sub)
         Xg = sp.X.cpu().numpy().astype(np.complex128)
         e = np.linalg.norm(Xg - Xr, axis=1) / np.linalg.norm(Xr, axis=1)
         worst = max(worst, float(e.max()))
         errsum += float(e.sum())
         fset = plan.query(j, vrk.Q_FSET)
         vl = np.asarray(d.vr_len, dtype=np.int64)
+        if d.vr_mask is not None:   # the visible antennas of each user, not its hull
+            vl = np.array([bin(int(m)).count("1") * (d.nt // d.n_sub) for m in d.vr_mask], dtype=np.int64)
         band, band_f = float(vl.sum()), float(vl[fset].sum())
         it = it_all[base:base + d.nrhs]
         overlap = float(plan.query(j, vrk.Q_XOFF)[-1])   # sum_i |X_i|
@@ -455,7 +464,8 @@ def main():
         G1 = torch.zeros((1, d0.nt), dtype=cdt, device=dev)
         p1 = vrk.Plan([vrk.ProblemSpec(sp0.H, d0.vr_start, d0.vr_len, d0.xi, S1, X1, V1, G1,
                                        torch.zeros_like(sp0.H), torch.zeros((1, d0.k), dtype=cdt, device=dev),
-                                       torch.zeros(1, dtype=torch.float64, device=dev))],
+                                       torch.zeros(1, dtype=torch.float64, device=dev),
+                                       vr_mask=d0.vr_mask, n_sub=d0.n_sub)],
                       vrk.options(variant=args.variant, dtype=dname, engine="vector", tol=tol))
         for i in range(min(3, n_plain)):
             S1.copy_(sp0.S[i:i + 1])
@@ -475,7 +485,8 @@ def main():
         torch.cuda.synchronize()
         ms = a.elapsed_time(b)
         i = n_plain - 1
-        Xr1, _ = oracle.rzf(d0.H, d0.vr_start, d0.vr_len, d0.S[i:i + 1], d0.xi)
+        Xr1, _ = oracle.rzf(d0.H, d0.vr_start, d0.vr_len, d0.S[i:i + 1], d0.xi, masks=d0.vr_mask,
+                            n_sub=d0.n_sub)
         e1 = float(np.linalg.norm(X1.cpu().numpy()[0] - Xr1[0]) / np.linalg.norm(Xr1[0]))
         plain_rate = n_plain / (ms * 1e-3)
         out["plain"] = {"vectors_per_s": plain_rate, "engine": "vector, one vector per launch, fwd+adjoint",
@@ -494,8 +505,9 @@ def main():
             Ss = d.S[:n]
             G = (gcpu.standard_normal((n, d.nt)) + 1j * gcpu.standard_normal((n, d.nt))) / d.nrhs
             t = time.perf_counter()
-            oracle.solve_batch(d.H, d.vr_start, d.vr_len, Ss, d.xi, variant=args.variant, tol=tol)
-            oracle.rzf_grad(d.H, d.vr_start, d.vr_len, Ss, d.xi, G)
+            mk = dict(masks=d.vr_mask, n_sub=d.n_sub)
+            oracle.solve_batch(d.H, d.vr_start, d.vr_len, Ss, d.xi, variant=args.variant, tol=tol, **mk)
+            oracle.rzf_grad(d.H, d.vr_start, d.vr_len, Ss, d.xi, G, **mk)
             t_cpu += time.perf_counter() - t
             n_cpu += n
             done += 1

@@ -102,6 +102,22 @@ typedef struct {
     void *GH;        int64_t ldgh;     /* device out, K x Nt: dL/dH on VR entries (others untouched) */
     void *GS;        int64_t ldgs;     /* device out, B x K: dL/ds */
     double *gxi;                       /* device out, one double: dL/dxi */
+    /* Subarray VR model (Sec. II: the array split into S subarrays of Nt / S
+     * antennas, user k seeing the subarrays of M_k). Null vr_mask: the VRs
+     * are the intervals above. Otherwise vr_mask[k] has bit s set when
+     * subarray s is visible to user k, [vr_start[k], vr_start[k] + vr_len[k])
+     * must be the hull of those subarrays ((0, 0) for none), and H must be
+     * zero on the hidden antennas inside the hull (h_k = hbar_k * u_k); the
+     * kernels read H on the hull as given. Two users then overlap when their
+     * masks share a subarray: that decides X_k, the Gram block pattern and
+     * F, which is built by the reducing-peeling heuristic the paper cites for
+     * problem max_set (degree-0 and degree-1 vertices join F, the latter
+     * deleting its neighbour; otherwise the vertex of largest degree is
+     * peeled; ties to the smallest index; peeled vertices then rejoin, latest
+     * first, when no neighbour is in F). Colour classes stay on the hulls.
+     * vrk_solve_adjoint writes GH = 0 on the hidden antennas of each hull. */
+    const uint64_t *vr_mask;           /* HOST [k] or null */
+    int32_t n_sub;                     /* S, 1..64, nt % S == 0 (with vr_mask) */
 } vrk_problem;
 
 typedef struct {
@@ -127,10 +143,11 @@ void vrk_default_options(vrk_options *o);
 
 /* Host only (no device access): validates nprob problems, builds the VR
  * plan of each (overlap sets X_k, the orthogonal set F as a maximum
- * independent set of the interval overlap graph, colour classes, tile
+ * independent set of the interval overlap graph, exact by earliest-end
+ * greedy, or of the subarray graph by reducing-peeling; colour classes, tile
  * maps) and reports the workspace size in bytes. *out receives a plan the
- * caller frees with vrk_plan_destroy. The vr_start / vr_len arrays are
- * copied; device pointers are recorded, not read. */
+ * caller frees with vrk_plan_destroy. The vr_start / vr_len / vr_mask
+ * arrays are copied; device pointers are recorded, not read. */
 vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_options *opt,
                            size_t *ws_bytes, vrk_plan **out);
 

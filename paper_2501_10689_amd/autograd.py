@@ -5,7 +5,8 @@ H g; no iterates are stored).
 
 Gradients follow torch's complex convention (grad = 2 dL/d conj(z)); the
 gradient with respect to H is nonzero only on the VR band entries, the
-only entries of H the precoder depends on.
+only entries of H the precoder depends on (under the subarray VR model, only
+on the visible subarrays).
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ class KaczmarzRZF(torch.autograd.Function):
     """x_b = H^H (H H^H + xi I)^-1 s_b for every row s_b of S."""
 
     @staticmethod
-    def forward(ctx, H, S, xi, vr_start, vr_len, opts):
+    def forward(ctx, H, S, xi, vr_start, vr_len, opts, vr_mask=None, n_sub=0):
         if not H.is_cuda:
             raise ValueError("KaczmarzRZF needs device tensors")
         dtype = "c128" if H.dtype == torch.complex128 else "c64"
@@ -34,7 +35,8 @@ class KaczmarzRZF(torch.autograd.Function):
         GS = torch.zeros_like(Sc)
         gxi = torch.zeros(1, dtype=torch.float64, device=H.device)
         o = vrk.options(dtype=dtype, **(opts or {}))
-        plan = vrk.Plan([vrk.ProblemSpec(Hc, vr_start, vr_len, xi_val, Sc, X, V, GX, GH, GS, gxi)], o)
+        plan = vrk.Plan([vrk.ProblemSpec(Hc, vr_start, vr_len, xi_val, Sc, X, V, GX, GH, GS, gxi,
+                                         vr_mask, n_sub)], o)
         stats = plan.stats_buffers()
         plan.solve(stats=stats)
         ctx.plan = plan
@@ -55,13 +57,15 @@ class KaczmarzRZF(torch.autograd.Function):
         gH = GH.clone()
         gS = GS.clone().reshape(ctx.s_shape)
         gx = gxi[0].clone() if ctx.xi_is_tensor else None
-        return gH, gS, gx, None, None, None
+        return gH, gS, gx, None, None, None, None, None
 
 
-def rzf_precode(H, S, xi, vr_start, vr_len, **opts):
+def rzf_precode(H, S, xi, vr_start, vr_len, vr_mask=None, n_sub=0, **opts):
     """Differentiable precoding of the rows of S (B x K) for channel H
-    (K x Nt) with per-user VR [vr_start, vr_start + vr_len). Options as
-    vrk.options (variant, tol, engine, ...)."""
+    (K x Nt) with per-user VR [vr_start, vr_start + vr_len) (the hulls of
+    the visible subarrays when vr_mask / n_sub give the subarray model).
+    Options as vrk.options (variant, tol, engine, ...)."""
     vs = np.ascontiguousarray(vr_start, dtype=np.int32)
     vl = np.ascontiguousarray(vr_len, dtype=np.int32)
-    return KaczmarzRZF.apply(H, S, xi, vs, vl, opts)
+    vm = None if vr_mask is None else np.ascontiguousarray(vr_mask, dtype=np.uint64)
+    return KaczmarzRZF.apply(H, S, xi, vs, vl, opts, vm, int(n_sub))

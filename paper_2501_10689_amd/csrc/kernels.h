@@ -52,6 +52,9 @@ hipError_t vrk_launch_adjoint_rhs(const VrkDesc *desc, int32_t nprob, int32_t ma
                                   int32_t dtype, hipStream_t s);
 hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t max_k,
                                     int32_t dtype, hipStream_t s);
+// Subarray VR model: GH = 0 on the hidden antennas inside each hull (the
+// desc's gap triples), after either engine's gradient kernels.
+hipError_t vrk_launch_zero_gaps(const VrkDesc *desc, int32_t nprob, int32_t dtype, hipStream_t s);
 // Link metrics after a solve with S = I_K: effective channel E = H X^T on
 // each user's VR, beta = 1 / ||X||_F and the per-user rates (one table entry
 // of outs per problem; dtype 0 complex64, 1 complex128; mfma: the plan is

@@ -70,6 +70,8 @@ struct ProbPlan {
     std::vector<int32_t> rab_lo, rab_hi, ag_off, ag_uc, gm_off, gm_c, gm_nf, fpos;
     int32_t nmf = 0;   // columns of MF (F users) when the solve takes the F half-step on the VALU
     std::vector<int32_t> cp_off, cp_col, cp_tr, cp_diag;   // blocks of C on the Gram block pattern
+    std::vector<uint64_t> mask;   // subarray masks (empty: interval VRs)
+    std::vector<int32_t> gaps;    // (user, first antenna, length) of hidden runs inside the hulls
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
     // workspace offsets
@@ -78,7 +80,7 @@ struct ProbPlan {
         o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
     size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_gmnf = 0, o_fpos = 0, o_mf = 0;
-    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0;
+    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0, o_gaps = 0;
 };
 
 }  // namespace
@@ -92,6 +94,7 @@ struct vrk_plan {
     int64_t total_rhs = 0, max_tiles = 0;
     int32_t max_rhs = 0, max_k = 0;
     bool adjoint_ready = false;
+    bool any_gaps = false;      // some problem has hidden antennas inside a hull
     std::vector<VrkWork> work;
     std::vector<int4> gtiles;   // band tiles of the adjoint gradient (MFMA engine)
     size_t o_gtiles = 0;
@@ -136,6 +139,26 @@ vrk_status validate_problem(const vrk_problem &p, int idx, const vrk_options &o)
             return fail(VRK_EINVAL, "problem %d: VR of user %d = [%lld, %lld) outside [0, %d)", idx, i,
                         (long long)s, (long long)(s + l), p.nt);
     }
+    if (p.vr_mask) {
+        if (p.n_sub < 1 || p.n_sub > 64 || p.nt % p.n_sub)
+            return fail(VRK_EINVAL, "problem %d: n_sub=%d must be in [1, 64] and divide nt=%d", idx, p.n_sub, p.nt);
+        const int32_t L = p.nt / p.n_sub;
+        for (int i = 0; i < p.k; ++i) {
+            const uint64_t m = p.vr_mask[i];
+            if (p.n_sub < 64 && (m >> p.n_sub))
+                return fail(VRK_EINVAL, "problem %d: vr_mask of user %d has bits at or above n_sub=%d", idx, i,
+                            p.n_sub);
+            int32_t lo = 0, hi = 0;
+            if (m) {
+                lo = __builtin_ctzll(m) * L;
+                hi = (64 - __builtin_clzll(m)) * L;
+            }
+            if (p.vr_start[i] != lo || p.vr_start[i] + p.vr_len[i] != hi)
+                return fail(VRK_EINVAL,
+                            "problem %d: VR of user %d = [%d, %d) is not the hull [%d, %d) of its visible subarrays",
+                            idx, i, p.vr_start[i], p.vr_start[i] + p.vr_len[i], lo, hi);
+        }
+    }
     bool any_adj = p.GX || p.GH || p.GS || p.gxi;
     if (any_adj) {
         if (!(p.GX && p.GH && p.GS && p.gxi))
@@ -147,11 +170,84 @@ vrk_status validate_problem(const vrk_problem &p, int idx, const vrk_options &o)
     return VRK_OK;
 }
 
-// Earliest-end greedy maximum independent set on the interval graph.
+// Users a and b have overlapping VRs: a shared subarray under the subarray
+// model, else intersecting intervals (Lemma 1: otherwise their rows are
+// orthogonal).
+bool vr_overlap(const ProbPlan &q, int a, int b)
+{
+    if (!q.mask.empty()) return (q.mask[a] & q.mask[b]) != 0;
+    return std::max(q.vs[a], q.vs[b]) < std::min(q.ve[a], q.ve[b]);
+}
+
+// F on the general graph of the subarray model by reducing-peeling: while
+// vertices remain, the first vertex of degree 0 joins F; else the first of
+// degree 1 joins F and its neighbour is deleted; else the first vertex of
+// largest degree is peeled. Peeled vertices rejoin, latest first, when no
+// neighbour is in F. Degrees are kept incrementally over adjacency lists.
+void build_mis_peeling(ProbPlan &q)
+{
+    const int K = q.p.k;
+    std::vector<std::vector<int32_t>> adj(K);
+    for (int a = 0; a < K; ++a)
+        for (int b = a + 1; b < K; ++b)
+            if (vr_overlap(q, a, b)) {
+                adj[a].push_back(b);
+                adj[b].push_back(a);
+            }
+    std::vector<int32_t> deg(K), peeled;
+    std::vector<uint8_t> alive(K, 1);
+    for (int v = 0; v < K; ++v) deg[v] = (int32_t)adj[v].size();
+    auto remove = [&](int v) {
+        alive[v] = 0;
+        for (int u : adj[v])
+            if (alive[u]) --deg[u];
+    };
+    for (int left = K; left > 0;) {
+        int p0 = -1, p1 = -1, pp = -1;
+        for (int v = 0; v < K; ++v) {
+            if (!alive[v]) continue;
+            if (deg[v] == 0 && p0 < 0) p0 = v;
+            if (deg[v] == 1 && p1 < 0) p1 = v;
+            if (pp < 0 || deg[v] > deg[pp]) pp = v;
+        }
+        if (p0 >= 0) {
+            q.inf[p0] = 1;
+            remove(p0);
+            --left;
+        } else if (p1 >= 0) {
+            int w = -1;
+            for (int u : adj[p1])
+                if (alive[u]) w = u;
+            q.inf[p1] = 1;
+            remove(p1);
+            remove(w);
+            left -= 2;
+        } else {
+            peeled.push_back(pp);
+            remove(pp);
+            --left;
+        }
+    }
+    for (auto it = peeled.rbegin(); it != peeled.rend(); ++it) {
+        bool free_v = true;
+        for (int u : adj[*it]) free_v = free_v && !q.inf[u];
+        if (free_v) q.inf[*it] = 1;
+    }
+}
+
+// Orthogonal set F: earliest-end greedy maximum independent set on the
+// interval graph (exact there), reducing-peeling under the subarray model.
 void build_mis(ProbPlan &q)
 {
     const int K = q.p.k;
     q.inf.assign(K, 0);
+    if (!q.mask.empty()) {
+        build_mis_peeling(q);
+        q.flist.clear();
+        q.vlist.clear();
+        for (int i = 0; i < K; ++i) (q.inf[i] ? q.flist : q.vlist).push_back(i);
+        return;
+    }
     std::vector<int32_t> ord;
     for (int i = 0; i < K; ++i) {
         if (q.ve[i] == q.vs[i]) q.inf[i] = 1;   // empty VR: orthogonal to every row
@@ -215,6 +311,24 @@ void build_tables(ProbPlan &q)
     const int K = p.k, N = p.nt;
     q.vs.assign(p.vr_start, p.vr_start + K);
     q.ve.resize(K);
+    q.mask.clear();
+    q.gaps.clear();
+    if (p.vr_mask) {
+        q.mask.assign(p.vr_mask, p.vr_mask + K);
+        const int32_t L = p.nt / p.n_sub;
+        for (int u = 0; u < K; ++u) {
+            const uint64_t m = q.mask[u];
+            if (!m) continue;
+            const int s1 = 63 - __builtin_clzll(m);
+            for (int s = __builtin_ctzll(m); s <= s1;) {
+                if ((m >> s) & 1u) { ++s; continue; }
+                int e = s;
+                while (!((m >> e) & 1u)) ++e;
+                q.gaps.insert(q.gaps.end(), {u, s * L, (e - s) * L});
+                s = e;
+            }
+        }
+    }
     q.band = 0;
     for (int i = 0; i < K; ++i) { q.ve[i] = q.vs[i] + p.vr_len[i]; q.band += p.vr_len[i]; }
     // users sorted by (start, end, index)
@@ -232,10 +346,8 @@ void build_tables(ProbPlan &q)
     q.xidx.clear();
     for (int kk = 0; kk < K; ++kk) {
         q.xoff[kk] = (int32_t)q.xidx.size();
-        for (int j = 0; j < K; ++j) {
-            bool ov = std::max(q.vs[kk], q.vs[j]) < std::min(q.ve[kk], q.ve[j]);
-            if (j == kk || ov) q.xidx.push_back(j);
-        }
+        for (int j = 0; j < K; ++j)
+            if (j == kk || vr_overlap(q, kk, j)) q.xidx.push_back(j);
     }
     q.xoff[K] = (int32_t)q.xidx.size();
     build_mis(q);
@@ -292,7 +404,7 @@ void build_tables(ProbPlan &q)
     q.ag_off[q.nab] = (int32_t)q.ag_uc.size();
     q.n_hg = (int64_t)q.ag_uc.size();
     // Gram blocks (16-user block, 4-user chunk) with any pair of overlapping
-    // VRs or a shared user (the diagonal), in VR-start order. Per block the
+    // VRs (a shared subarray under the subarray model) or a shared user (the diagonal), in VR-start order. Per block the
     // chunks holding a user of F come first, so the orthogonal half-step
     // (phi nonzero on F only) needs only the groups covering the first
     // gm_nf entries; the list is padded to groups of 4 chunks, loaded and
@@ -312,7 +424,7 @@ void build_tables(ProbPlan &q)
                     const int kv = uc * 4 + t;
                     if (kv >= K) break;
                     const int a = q.perm[i], b = q.perm[kv];
-                    any = (a == b) || std::max(q.vs[a], q.vs[b]) < std::min(q.ve[a], q.ve[b]);
+                    any = (a == b) || vr_overlap(q, a, b);
                 }
             if (any) (hasf ? with_f : rest).push_back(uc);
         }
@@ -413,12 +525,14 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         pl->max_rhs = std::max(pl->max_rhs, q.p.nrhs);
         pl->max_k = std::max(pl->max_k, q.p.k);
         all_adj = all_adj && q.p.GX;
+        pl->any_gaps = pl->any_gaps || !q.gaps.empty();
         max_nt = std::max(max_nt, q.p.nt);
         max_k = std::max(max_k, q.p.k);
         max_kpad = std::max(max_kpad, q.nub * VRK_UB);
         min_rhs = std::min(min_rhs, q.p.nrhs);
         q.p.vr_start = nullptr;   // the caller's host arrays are not kept
         q.p.vr_len = nullptr;
+        q.p.vr_mask = nullptr;
     }
     pl->adjoint_ready = all_adj;
     // engine choice
@@ -577,6 +691,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_cpcol = cv.take(4 * q.cp_col.size());
         q.o_cptr = cv.take(4 * q.cp_tr.size());
         q.o_cpdiag = cv.take(4 * q.cp_diag.size());
+        q.o_gaps = cv.take(4 * q.gaps.size());
     }
     pl->table_end = cv.off;
     pl->o_link = cv.take(sizeof(VrkLinkOut) * nprob);
@@ -653,6 +768,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         put(img, q.o_cptr, q.cp_tr);
         put(img, q.o_cpdiag, q.cp_diag);
         put(img, q.o_fpos, q.fpos);
+        put(img, q.o_gaps, q.gaps);
         VrkDesc &d = descs[i];
         std::memset(&d, 0, sizeof d);
         const vrk_problem &p = q.p;
@@ -707,6 +823,9 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.nmf = pl->engine == VRK_ENGINE_MFMA ? q.nmf : 0;
         d.MF = d.nmf ? base + q.o_mf : nullptr;
         d.fpos = (const int32_t *)(base + q.o_fpos);
+        d.masked = q.mask.empty() ? 0 : 1;
+        d.ngap = (int32_t)(q.gaps.size() / 3);
+        d.gaps = (const int32_t *)(base + q.o_gaps);
         (void)eb;
     }
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());
@@ -825,6 +944,10 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
                                            reinterpret_cast<float2 *>(pl->d_ws + pl->o_gpart), s)
            : vrk_launch_adjoint_grads(dd, (int32_t)pl->pp.size(), pl->max_k, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient kernel");
+    if (pl->any_gaps) {
+        e = vrk_launch_zero_gaps(dd, (int32_t)pl->pp.size(), pl->opt.dtype, s);
+        if (e != hipSuccess) return hip_fail(e, "gap kernel");
+    }
     return VRK_OK;
 }
 
@@ -929,6 +1052,7 @@ uint64_t shape_key(const vrk_problem *probs, int32_t nprob, const vrk_options &o
         for (int k = 0; k < probs[i].k; ++k) band += probs[i].vr_len[k];
         int64_t v[4] = {probs[i].nt, probs[i].k, probs[i].nrhs, band};
         hsh = fnv1a(hsh, v, sizeof v);
+        if (probs[i].vr_mask) hsh = fnv1a(hsh, probs[i].vr_mask, sizeof(uint64_t) * probs[i].k);
     }
     return hsh;
 }

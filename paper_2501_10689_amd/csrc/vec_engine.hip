@@ -373,8 +373,11 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                 aggregate(c, [](int) { return true; }, a.schedule);
             } else {
                 // orthogonal half-step on F with gamma = 1 (Prop. 1): the
-                // bands are disjoint, so all of F updates concurrently
+                // bands are disjoint, so all of F updates concurrently. Under
+                // the subarray model only the visible antennas are disjoint
+                // (the hulls may overlap): one user at a time.
                 for (int e = 0; e < d.nf; ++e) {
+                    if (d.masked) __syncthreads();
                     int i = d.flist[e];
                     R inv = (R)1 / c.nrm[i];
                     cx<R> f = {c.r[i].re * inv, c.r[i].im * inv};
@@ -542,5 +545,30 @@ hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t 
     dim3 grid((unsigned)max_k, (unsigned)nprob);
     if (dtype == 1) hipLaunchKernelGGL(k_adjoint_grads<double>, grid, dim3(kThreads), 0, s, desc);
     else hipLaunchKernelGGL(k_adjoint_grads<float>, grid, dim3(kThreads), 0, s, desc);
+    return hipGetLastError();
+}
+
+namespace {
+
+// One workgroup per problem: zero GH on each gap (user, first antenna,
+// length), the hidden antennas of the subarray model, where h = hbar * u
+// has no free entry.
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_zero_gaps(const VrkDesc *descs)
+{
+    const VrkDesc &d = descs[blockIdx.x];
+    cx<R> *GH = reinterpret_cast<cx<R> *>(d.GH);
+    for (int e = 0; e < d.ngap; ++e) {
+        const int u = d.gaps[3 * e], a = d.gaps[3 * e + 1], len = d.gaps[3 * e + 2];
+        for (int n = a + (int)threadIdx.x; n < a + len; n += kThreads) GH[(int64_t)u * d.ldgh + n] = cx<R>{0, 0};
+    }
+}
+
+}  // namespace
+
+hipError_t vrk_launch_zero_gaps(const VrkDesc *desc, int32_t nprob, int32_t dtype, hipStream_t s)
+{
+    if (dtype == 1) hipLaunchKernelGGL(k_zero_gaps<double>, dim3((unsigned)nprob), dim3(kThreads), 0, s, desc);
+    else hipLaunchKernelGGL(k_zero_gaps<float>, dim3((unsigned)nprob), dim3(kThreads), 0, s, desc);
     return hipGetLastError();
 }

@@ -19,7 +19,8 @@ enum { VRK_FLAG_CONVERGED = 1, VRK_FLAG_NONFINITE = 2, VRK_FLAG_MAXITER = 4 };
 struct VrkDesc {
     int32_t nt, k, nrhs, nf;      // antennas, users, right-hand sides, |F|
     int32_t nv, ncol, ngb, nub;   // |V|, colour classes, gather blocks, 16-user blocks
-    int32_t nab, ntile, nmf, pad1;   // 16-antenna blocks, RHS tiles of 16, columns of MF (0: none)
+    int32_t nab, ntile, nmf, ngap;   // 16-antenna blocks, RHS tiles of 16, columns of MF (0: none),
+                                     // hidden runs inside the hulls (subarray VR model)
     double xi;
     int64_t ldh, lds, ldx, ldv, ldgx, ldgh, ldgs;
     int64_t rhs_base;             // offset of this problem's RHS in the stats arrays
@@ -71,6 +72,11 @@ struct VrkDesc {
     // rows, rounded once from double), and fpos[t] = pos[flist[t]]
     void *MF;
     const int32_t *fpos;
+    // Subarray VR model: masked = 1 when the VRs come from subarray masks
+    // (then users of F may have overlapping hulls); gaps holds ngap triples
+    // (user, first antenna, length) of hidden antennas inside the hulls
+    int32_t masked, pad2;
+    const int32_t *gaps;
 };
 
 // Outputs of the link metrics of one problem (device pointers): the K x K

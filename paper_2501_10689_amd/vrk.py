@@ -36,7 +36,8 @@ class Problem(C.Structure):
                 ("GX", C.c_void_p), ("ldgx", C.c_int64),
                 ("GH", C.c_void_p), ("ldgh", C.c_int64),
                 ("GS", C.c_void_p), ("ldgs", C.c_int64),
-                ("gxi", C.c_void_p)]
+                ("gxi", C.c_void_p),
+                ("vr_mask", C.c_void_p), ("n_sub", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -132,7 +133,8 @@ def _stride(t) -> int:
 
 @dataclass
 class ProblemSpec:
-    """One drop: device tensors (torch) and host VR arrays (numpy int32)."""
+    """One drop: device tensors (torch) and host VR arrays (numpy int32;
+    vr_mask uint64 with n_sub for the subarray VR model)."""
 
     H: object
     vr_start: np.ndarray
@@ -145,6 +147,8 @@ class ProblemSpec:
     GH: object = None
     GS: object = None
     gxi: object = None
+    vr_mask: object = None
+    n_sub: int = 0
 
 
 class Plan:
@@ -175,6 +179,10 @@ class Plan:
             p.GH, p.ldgh = _ptr(sp.GH), _stride(sp.GH)
             p.GS, p.ldgs = _ptr(sp.GS), _stride(sp.GS)
             p.gxi = _ptr(sp.gxi)
+            if sp.vr_mask is not None:
+                vm = np.ascontiguousarray(sp.vr_mask, dtype=np.uint64)
+                self._keep.append(vm)
+                p.vr_mask, p.n_sub = vm.ctypes.data, int(sp.n_sub)
         self._arr = arr
         ws = C.c_size_t(0)
         h = C.c_void_p()
@@ -264,6 +272,10 @@ def _problem_array(probs):
         p.GH, p.ldgh = _ptr(sp.GH), _stride(sp.GH)
         p.GS, p.ldgs = _ptr(sp.GS), _stride(sp.GS)
         p.gxi = _ptr(sp.gxi)
+        if sp.vr_mask is not None:
+            vm = np.ascontiguousarray(sp.vr_mask, dtype=np.uint64)
+            keep.append(vm)
+            p.vr_mask, p.n_sub = vm.ctypes.data, int(sp.n_sub)
     return arr, keep
 
 
@@ -289,12 +301,15 @@ def autotune(probs, opts: Options, cache_path=None, reps=3, stream=None):
     return o, float(ms.value)
 
 
-def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, **kw):
+def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, vr_mask=None, n_sub=0, **kw):
     """Plan one problem on the host only (no device memory is touched; the
     device pointers are dummies). For inspecting the VR plan."""
     vs = np.ascontiguousarray(vr_start, dtype=np.int32)
     vl = np.ascontiguousarray(vr_len, dtype=np.int32)
+    vm = None if vr_mask is None else np.ascontiguousarray(vr_mask, dtype=np.uint64)
     p = Problem()
+    if vm is not None:
+        p.vr_mask, p.n_sub = vm.ctypes.data, int(n_sub)
     p.nt, p.k, p.xi = nt, k, xi
     p.H, p.ldh = 256, nt
     p.vr_start, p.vr_len = vs.ctypes.data, vl.ctypes.data

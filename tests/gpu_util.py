@@ -13,20 +13,24 @@ def to_dev(a, dtype):
 def run_plan(drops, variant="vr_oahk", select="baiwu", dtype="c64", engine="auto", tol=1e-5,
              max_iters=100000, seed=0, schedule="auto", adjoint_g=None, tile_waves=0,
              persistent=0, x_pad=0):
-    """drops: list of (H, vs, vl, S, xi) numpy tuples. Returns per-drop dicts
-    with X, V (numpy complex128) and stats, plus the plan. x_pad > 0 gives
-    the X rows a stride of Nt + x_pad (a view into a wider buffer)."""
+    """drops: list of (H, vs, vl, S, xi) numpy tuples, or (H, vs, vl, S, xi,
+    vr_mask, n_sub) for the subarray VR model. Returns per-drop dicts with
+    X, V (numpy complex128) and stats, plus the plan. x_pad > 0 gives the X
+    rows a stride of Nt + x_pad (a view into a wider buffer)."""
     import torch
     from paper_2501_10689_amd import vrk
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
     specs = []
-    for j, (H, vs, vl, S, xi) in enumerate(drops):
+    for j, dr in enumerate(drops):
+        H, vs, vl, S, xi = dr[:5]
         Hd = to_dev(H, tdt)
         Sd = to_dev(np.atleast_2d(S), tdt)
         B = Sd.shape[0]
         X = torch.full((B, H.shape[1] + x_pad), float("nan"), dtype=tdt, device="cuda")[:, :H.shape[1]]
         V = torch.full((B, H.shape[0]), float("nan"), dtype=tdt, device="cuda")
         sp = vrk.ProblemSpec(Hd, vs, vl, xi, Sd, X, V)
+        if len(dr) > 5:
+            sp.vr_mask, sp.n_sub = dr[5], dr[6]
         if adjoint_g is not None:
             sp.GX = to_dev(adjoint_g[j], tdt)
             sp.GH = torch.zeros_like(Hd)

@@ -127,3 +127,80 @@ def test_solve_before_bind_is_a_state_error():
     assert vrk.lib().vrk_solve_adjoint(h, None, None, None, None) == 5
     assert vrk.lib().vrk_plan_bind(h, None, 0, None) == 3
     vrk.lib().vrk_plan_destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# Subarray VR model: overlap and F from the masks, bit-exact against the
+# oracle; colour classes on the hulls; argument checks
+# ---------------------------------------------------------------------------
+
+def _bernoulli_masks(rng, k, n_sub, p):
+    return np.array([sum(1 << s for s in range(n_sub) if rng.random() < p) for _ in range(k)],
+                    dtype=np.uint64)
+
+
+@pytest.mark.parametrize("engine", ["vector", "mfma"])
+def test_masked_plan_matches_oracle_structure(engine):
+    import synth
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        n_sub = int(rng.choice([4, 8, 20, 64]))
+        nt = n_sub * int(rng.integers(1, 6))
+        k = int(rng.integers(1, 60))
+        p = float(rng.uniform(0.05, 0.6))
+        masks = _bernoulli_masks(rng, k, n_sub, p)
+        if trial % 5 == 0:
+            masks[0] = 0                      # a user that sees nothing
+        vs, vl = synth.mask_hulls(masks, nt, n_sub)
+        H = np.zeros((k, nt), complex)
+        hp = vrk.host_plan(nt, k, vs, vl, 1.0, nrhs=16 if engine == "mfma" else 0, vr_mask=masks,
+                           n_sub=n_sub, engine=engine)
+        f = np.zeros(k, dtype=bool)
+        f[hp.query(vrk.Q_FSET)] = True
+        assert np.array_equal(f, oracle.mis(H, vs, vl, 1.0, masks=masks, n_sub=n_sub)), trial
+        xoff, xidx = hp.query(vrk.Q_XOFF), hp.query(vrk.Q_XIDX)
+        want = oracle.overlap_sets(H, vs, vl, 1.0, masks=masks, n_sub=n_sub)
+        for i in range(k):
+            assert np.array_equal(xidx[xoff[i]:xoff[i + 1]], want[i])
+        col = hp.query(vrk.Q_COLOUR)
+        for a, b in itertools.combinations(range(k), 2):
+            if col[a] == col[b]:   # the colour schedule writes whole hulls concurrently
+                assert max(vs[a], vs[b]) >= min(vs[a] + vl[a], vs[b] + vl[b])
+
+
+def test_masked_gram_pattern_is_smaller_than_the_hulls():
+    # users u < 32 see subarrays u and u + 32: every hull overlaps every
+    # other, no two masks do; the other 32 users see nothing. Under the
+    # masks F is everyone and the Gram pattern keeps only the chunks on the
+    # diagonal
+    import synth
+    nt, n_sub, k = 128, 64, 64
+    masks = np.array([(1 << u) | (1 << (u + 32)) for u in range(32)] + [0] * 32, dtype=np.uint64)
+    vs, vl = synth.mask_hulls(masks, nt, n_sub)
+    hp_m = vrk.host_plan(nt, k, vs, vl, 1.0, nrhs=16, vr_mask=masks, n_sub=n_sub, engine="mfma")
+    hp_h = vrk.host_plan(nt, k, vs, vl, 1.0, nrhs=16, engine="mfma")
+    assert len(hp_m.query(vrk.Q_FSET)) == k
+    assert len(hp_h.query(vrk.Q_FSET)) == 33
+    assert hp_m.query(vrk.Q_TILES)[3] == 16
+    assert hp_h.query(vrk.Q_TILES)[3] == 24
+
+
+@pytest.mark.parametrize("bad", ["hull", "bits", "nsub0", "nsubdiv", "nsub65"])
+def test_masked_validation_errors(bad):
+    import synth
+    nt, n_sub, k = 40, 8, 3
+    masks = np.array([0b00100101, 0b00011000, 0], dtype=np.uint64)
+    vs, vl = synth.mask_hulls(masks, nt, n_sub)
+    if bad == "hull":
+        vl[0] -= 5
+    elif bad == "bits":
+        masks[1] |= np.uint64(1 << 9)
+    elif bad == "nsub0":
+        n_sub = 0
+    elif bad == "nsubdiv":
+        n_sub = 7
+    elif bad == "nsub65":
+        n_sub = 65
+    with pytest.raises(vrk.VrkError) as e:
+        vrk.host_plan(nt, k, vs, vl, 1.0, vr_mask=masks, n_sub=n_sub, engine="vector")
+    assert e.value.status == 1
