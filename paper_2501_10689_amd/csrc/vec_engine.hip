@@ -550,15 +550,17 @@ hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t 
 
 namespace {
 
-// One workgroup per problem: zero GH on each gap (user, first antenna,
-// length), the hidden antennas of the subarray model, where h = hbar * u
-// has no free entry.
+// GH = 0 on each gap (user, first antenna, length), the hidden antennas of
+// the subarray model, where h = hbar * u has no free entry: blockIdx.x is
+// the problem, workgroup y takes gaps y, y + gridDim.y, ...
+constexpr int kGapGroups = 16;
+
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_zero_gaps(const VrkDesc *descs)
 {
     const VrkDesc &d = descs[blockIdx.x];
     cx<R> *GH = reinterpret_cast<cx<R> *>(d.GH);
-    for (int e = 0; e < d.ngap; ++e) {
+    for (int e = blockIdx.y; e < d.ngap; e += kGapGroups) {
         const int u = d.gaps[3 * e], a = d.gaps[3 * e + 1], len = d.gaps[3 * e + 2];
         for (int n = a + (int)threadIdx.x; n < a + len; n += kThreads) GH[(int64_t)u * d.ldgh + n] = cx<R>{0, 0};
     }
@@ -568,7 +570,8 @@ __global__ void __launch_bounds__(kThreads) k_zero_gaps(const VrkDesc *descs)
 
 hipError_t vrk_launch_zero_gaps(const VrkDesc *desc, int32_t nprob, int32_t dtype, hipStream_t s)
 {
-    if (dtype == 1) hipLaunchKernelGGL(k_zero_gaps<double>, dim3((unsigned)nprob), dim3(kThreads), 0, s, desc);
-    else hipLaunchKernelGGL(k_zero_gaps<float>, dim3((unsigned)nprob), dim3(kThreads), 0, s, desc);
+    const dim3 grid((unsigned)nprob, kGapGroups);
+    if (dtype == 1) hipLaunchKernelGGL(k_zero_gaps<double>, grid, dim3(kThreads), 0, s, desc);
+    else hipLaunchKernelGGL(k_zero_gaps<float>, grid, dim3(kThreads), 0, s, desc);
     return hipGetLastError();
 }
