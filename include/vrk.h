@@ -114,8 +114,11 @@ typedef struct {
      * problem max_set (degree-0 and degree-1 vertices join F, the latter
      * deleting its neighbour; otherwise the vertex of largest degree is
      * peeled; ties to the smallest index; peeled vertices then rejoin, latest
-     * first, when no neighbour is in F). Colour classes stay on the hulls.
-     * vrk_solve_adjoint writes GH = 0 on the hidden antennas of each hull. */
+     * first, when no neighbour is in F). Colour classes come from a greedy
+     * colouring of the same graph (users in VR-start order, smallest free
+     * colour); concurrent updates of F or of a class write only visible
+     * antennas. vrk_solve_adjoint writes GH = 0 on the hidden antennas of
+     * each hull. */
     const uint64_t *vr_mask;           /* HOST [k] or null */
     int32_t n_sub;                     /* S, 1..64, nt % S == 0 (with vr_mask) */
 } vrk_problem;

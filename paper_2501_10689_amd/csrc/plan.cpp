@@ -80,7 +80,7 @@ struct ProbPlan {
         o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
     size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_gmnf = 0, o_fpos = 0, o_mf = 0;
-    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0, o_gaps = 0;
+    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0, o_gaps = 0, o_mask = 0;
 };
 
 }  // namespace
@@ -266,37 +266,58 @@ void build_mis(ProbPlan &q)
     for (int i = 0; i < K; ++i) (q.inf[i] ? q.flist : q.vlist).push_back(i);
 }
 
-// Optimal interval colouring: sweep by start, reuse the smallest colour
-// whose interval has ended.
+// Colour classes: sets of users with pairwise disjoint VRs. Interval VRs:
+// optimal interval colouring (sweep by start, reuse the smallest colour whose
+// interval has ended). Subarray model: greedy colouring of the mask graph,
+// users in VR-start order, each taking the smallest colour none of its
+// already coloured neighbours holds.
 void build_colours(ProbPlan &q)
 {
     const int K = q.p.k;
     q.colour.assign(K, 0);
-    std::vector<int32_t> ord;
-    for (int i = 0; i < K; ++i)
-        if (q.ve[i] > q.vs[i]) ord.push_back(i);
-    std::sort(ord.begin(), ord.end(), [&](int a, int b) {
-        if (q.vs[a] != q.vs[b]) return q.vs[a] < q.vs[b];
-        if (q.ve[a] != q.ve[b]) return q.ve[a] < q.ve[b];
-        return a < b;
-    });
-    using End = std::pair<int32_t, int32_t>;   // (end, colour)
-    std::priority_queue<End, std::vector<End>, std::greater<End>> active;
-    std::set<int32_t> freec;
-    int32_t ncol = 0;
-    for (int i : ord) {
-        while (!active.empty() && active.top().first <= q.vs[i]) {
-            freec.insert(active.top().second);
-            active.pop();
+    if (!q.mask.empty()) {
+        int32_t ncol = 1;
+        std::vector<uint8_t> done(K, 0), used;
+        for (int i = 0; i < K; ++i) {
+            const int u = q.perm[i];
+            used.assign(ncol + 1, 0);
+            for (int v = 0; v < K; ++v)
+                if (done[v] && v != u && vr_overlap(q, u, v)) used[q.colour[v]] = 1;
+            int32_t c = 0;
+            while (used[c]) ++c;
+            q.colour[u] = c;
+            ncol = std::max(ncol, c + 1);
+            done[u] = 1;
         }
-        int32_t c;
-        if (!freec.empty()) { c = *freec.begin(); freec.erase(freec.begin()); }
-        else c = ncol++;
-        q.colour[i] = c;
-        active.push({q.ve[i], c});
+        q.ncol = ncol;
+    } else {
+        std::vector<int32_t> ord;
+        for (int i = 0; i < K; ++i)
+            if (q.ve[i] > q.vs[i]) ord.push_back(i);
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+            if (q.vs[a] != q.vs[b]) return q.vs[a] < q.vs[b];
+            if (q.ve[a] != q.ve[b]) return q.ve[a] < q.ve[b];
+            return a < b;
+        });
+        using End = std::pair<int32_t, int32_t>;   // (end, colour)
+        std::priority_queue<End, std::vector<End>, std::greater<End>> active;
+        std::set<int32_t> freec;
+        int32_t ncol = 0;
+        for (int i : ord) {
+            while (!active.empty() && active.top().first <= q.vs[i]) {
+                freec.insert(active.top().second);
+                active.pop();
+            }
+            int32_t c;
+            if (!freec.empty()) { c = *freec.begin(); freec.erase(freec.begin()); }
+            else c = ncol++;
+            q.colour[i] = c;
+            active.push({q.ve[i], c});
+        }
+        if (ncol == 0) ncol = 1;   // only empty VRs: one class
+        q.ncol = ncol;
     }
-    if (ncol == 0) ncol = 1;   // only empty VRs: one class
-    q.ncol = ncol;
+    const int32_t ncol = q.ncol;
     q.col_off.assign(ncol + 1, 0);
     for (int i = 0; i < K; ++i) q.col_off[q.colour[i] + 1]++;
     for (int c = 0; c < ncol; ++c) q.col_off[c + 1] += q.col_off[c];
@@ -692,6 +713,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_cptr = cv.take(4 * q.cp_tr.size());
         q.o_cpdiag = cv.take(4 * q.cp_diag.size());
         q.o_gaps = cv.take(4 * q.gaps.size());
+        q.o_mask = cv.take(8 * q.mask.size());
     }
     pl->table_end = cv.off;
     pl->o_link = cv.take(sizeof(VrkLinkOut) * nprob);
@@ -769,6 +791,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         put(img, q.o_cpdiag, q.cp_diag);
         put(img, q.o_fpos, q.fpos);
         put(img, q.o_gaps, q.gaps);
+        put(img, q.o_mask, q.mask);
         VrkDesc &d = descs[i];
         std::memset(&d, 0, sizeof d);
         const vrk_problem &p = q.p;
@@ -824,6 +847,8 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.MF = d.nmf ? base + q.o_mf : nullptr;
         d.fpos = (const int32_t *)(base + q.o_fpos);
         d.masked = q.mask.empty() ? 0 : 1;
+        d.sub_len = q.mask.empty() ? 0 : p.nt / p.n_sub;
+        d.vmask = (const uint64_t *)(base + q.o_mask);
         d.ngap = (int32_t)(q.gaps.size() / 3);
         d.gaps = (const int32_t *)(base + q.o_gaps);
         (void)eb;

@@ -187,6 +187,15 @@ __device__ void residual_rows(const VecCtx<R> &c, const int32_t *list, int n)
     }
 }
 
+// Antenna n of user u's interval is visible to it: always for interval VRs;
+// under the subarray model when its subarray is in the user's mask. Users of
+// F and of one colour class have disjoint visible sets, so concurrent
+// updates that touch only visible antennas never meet.
+__device__ __forceinline__ bool visible(const VrkDesc &d, bool masked, int u, int n)
+{
+    return !masked || ((d.vmask[u] >> (n / d.sub_len)) & 1ull);
+}
+
 // Aggregated projection (update4) over the rows with in_set(i):
 // phi_i = r_i / ||a_i||^2, p = H^H phi, gamma = sum |r_i|^2/||a_i||^2 /
 // (||p||^2 + xi ||phi||^2), x += gamma p, q += gamma phi.
@@ -213,6 +222,7 @@ __device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
     if (schedule == VRK_SCHED_COLOUR) {
         for (int n = tid; n < d.nt; n += kThreads) c.p[n] = {0, 0};
         __syncthreads();
+        const bool masked = d.masked != 0;
         for (int col = 0; col < d.ncol; ++col) {
             // users of one class have pairwise disjoint VRs: no write conflicts
             for (int e = d.col_off[col]; e < d.col_off[col + 1]; ++e) {
@@ -221,6 +231,7 @@ __device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
                 if (f.re == 0 && f.im == 0) continue;
                 const cx<R> *h = c.H + (int64_t)u * d.ldh;
                 for (int n = d.vs[u] + tid; n < d.ve[u]; n += kThreads) {
+                    if (!visible(d, masked, u, n)) continue;
                     cx<R> t = cmulc(f, h[n]);
                     c.p[n].re += t.re;
                     c.p[n].im += t.im;
@@ -373,16 +384,17 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                 aggregate(c, [](int) { return true; }, a.schedule);
             } else {
                 // orthogonal half-step on F with gamma = 1 (Prop. 1): the
-                // bands are disjoint, so all of F updates concurrently. Under
-                // the subarray model only the visible antennas are disjoint
-                // (the hulls may overlap): one user at a time.
+                // VRs are disjoint, so all of F updates concurrently (under
+                // the subarray model the hulls may overlap, so only the
+                // visible antennas are written)
+                const bool masked = d.masked != 0;
                 for (int e = 0; e < d.nf; ++e) {
-                    if (d.masked) __syncthreads();
                     int i = d.flist[e];
                     R inv = (R)1 / c.nrm[i];
                     cx<R> f = {c.r[i].re * inv, c.r[i].im * inv};
                     const cx<R> *h = c.H + (int64_t)i * d.ldh;
                     for (int n = d.vs[i] + tid; n < d.ve[i]; n += kThreads) {
+                        if (!visible(d, masked, i, n)) continue;
                         cx<R> tv = cmulc(f, h[n]);
                         c.x[n].re += tv.re;
                         c.x[n].im += tv.im;

@@ -73,9 +73,12 @@ struct VrkDesc {
     void *MF;
     const int32_t *fpos;
     // Subarray VR model: masked = 1 when the VRs come from subarray masks
-    // (then users of F may have overlapping hulls); gaps holds ngap triples
-    // (user, first antenna, length) of hidden antennas inside the hulls
-    int32_t masked, pad2;
+    // (then users of F or of a colour class may have overlapping hulls, and
+    // only their visible antennas are disjoint); vmask[k] = the subarrays
+    // user k sees, sub_len antennas each; gaps holds ngap triples (user,
+    // first antenna, length) of hidden antennas inside the hulls
+    int32_t masked, sub_len;
+    const uint64_t *vmask;
     const int32_t *gaps;
 };
 

@@ -76,6 +76,26 @@ def test_subarray_c128_vector_follows_oracle(variant, schedule):
     assert rel_err_rows(r["X"], X).max() <= 1e-8
 
 
+def test_subarray_colour_and_gather_schedules_agree():
+    # complex64 vector engine: the colour schedule (greedy classes of the
+    # mask graph, several users with overlapping hulls per class) and the
+    # antenna-gather schedule reach the same RZF
+    d = _sparse_drop(7, nrhs=24)
+    kw = dict(masks=d.vr_mask, n_sub=d.n_sub)
+    X, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi, **kw)
+    out = {}
+    for sch in ("colour", "gather"):
+        res, plan = run_plan([_tuple(d)], variant="vr_oahk", engine="vector", tol=1e-6, schedule=sch)
+        assert np.all(res[0]["flags"] == oracle.F_CONVERGED)
+        assert rel_err_rows(res[0]["X"], X).max() <= 1e-5
+        out[sch] = res[0]["X"]
+    col = plan.query(0, 2)
+    vs, ve = d.vr_start, d.vr_start + d.vr_len
+    assert any(col[a] == col[b] and max(vs[a], vs[b]) < min(ve[a], ve[b])
+               for a in range(d.k) for b in range(a + 1, d.k))
+    assert rel_err_rows(out["colour"], out["gather"]).max() <= 1e-5
+
+
 @pytest.mark.parametrize("engine,dtype,tol,bound", [("mfma", "c64", 1e-6, 2e-4),
                                                     ("vector", "c128", 1e-12, 1e-9)])
 def test_subarray_adjoint_matches_closed_form(engine, dtype, tol, bound):

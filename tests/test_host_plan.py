@@ -162,10 +162,19 @@ def test_masked_plan_matches_oracle_structure(engine):
         want = oracle.overlap_sets(H, vs, vl, 1.0, masks=masks, n_sub=n_sub)
         for i in range(k):
             assert np.array_equal(xidx[xoff[i]:xoff[i + 1]], want[i])
+        # colour classes: a greedy colouring of the mask graph in VR-start
+        # order (the colour schedule writes only visible antennas)
         col = hp.query(vrk.Q_COLOUR)
-        for a, b in itertools.combinations(range(k), 2):
-            if col[a] == col[b]:   # the colour schedule writes whole hulls concurrently
-                assert max(vs[a], vs[b]) >= min(vs[a] + vl[a], vs[b] + vl[b])
+        adj = oracle.mask_graph(masks)
+        assert not np.any(adj & (col[:, None] == col[None, :]))
+        want = np.zeros(k, np.int64)
+        seen = []
+        for u in hp.query(vrk.Q_PERM):
+            used = {want[v] for v in seen if adj[u, v]}
+            want[u] = min(c for c in range(k + 1) if c not in used)
+            seen.append(u)
+        assert np.array_equal(col, want)
+        assert col.max() <= adj.sum(axis=1).max()
 
 
 def test_masked_gram_pattern_is_smaller_than_the_hulls():
