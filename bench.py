@@ -267,6 +267,8 @@ def main():
     ap.add_argument("--variant", default="vr_oahk", choices=["grk", "ahk", "vr_ogrk", "vr_oahk"])
     ap.add_argument("--engine", default="auto", choices=["auto", "vector", "mfma"])
     ap.add_argument("--snr", type=float, default=None)
+    ap.add_argument("--p-vis", type=float, default=None,
+                    help="subarray workload: visibility probability of each subarray (default 0.35)")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--tile-waves", type=int, default=0, choices=[0, 8, 16])
     ap.add_argument("--persistent", type=int, default=0, choices=[0, 1])
@@ -301,7 +303,9 @@ def main():
     dname = "c128" if c128 else "c64"
     tol = args.tol if args.tol is not None else (1e-10 if c128 else 1e-5)
     engine_opt = "vector" if c128 else args.engine
-    drops = synth.make_workload(wl, snr_db=args.snr)
+    if args.p_vis is not None and wl != "subarray":
+        sys.exit("--p-vis applies to the subarray workload only")
+    drops = synth.make_workload(wl, snr_db=args.snr, **({"p_vis": args.p_vis} if args.p_vis is not None else {}))
     gen = torch.Generator(device=dev)
     gen.manual_seed(12345)
     specs = []
@@ -418,6 +422,7 @@ def main():
         "config": {"workload": WORKLOADS[wl], "variant": args.variant, "engine": engine,
                    "tile_waves": int(eng[2]), "persistent": int(eng[4]), "entries_per_thread": int(eng[6]),
                    "drops": len(drops), "vectors": B, "tol": tol},
+        "orthogonal_set_mean": float(np.mean([len(plan.query(j, vrk.Q_FSET)) for j in range(len(drops))])),
         "roofline": roof,
         "accuracy": {"max_rel_err": worst, "mean_rel_err": errsum / B,
                      "all_converged": bool(np.all(fl_all == 1)), "mean_iters": float(it_all.mean()),
@@ -425,6 +430,8 @@ def main():
     }
     if tuned_ms is not None:
         out["config"]["autotuned_ms"] = tuned_ms
+    if args.p_vis is not None:
+        out["config"]["p_vis"] = args.p_vis   # overrides the 0.35 in the workload text
 
     # per-variant forward rates on the same batch and engine choice
     if not args.no_variants and wl == "many_rhs":

@@ -196,10 +196,12 @@ WORKLOADS = {
 
 def make_workload(name: str, *, drops: int | None = None, nrhs: int | None = None,
                   snr_db: float | None = None, nt: int | None = None,
-                  k: int | None = None, seed: int | None = None) -> list[Drop]:
+                  k: int | None = None, seed: int | None = None,
+                  p_vis: float | None = None) -> list[Drop]:
     """Build the drops of a named workload. ``drops``/``nrhs``/``nt``/``k``
     shrink it for tests (same recipe, smaller shape); ``seed`` overrides the
-    recipe's seed."""
+    recipe's seed; ``p_vis`` the subarray visibility probability (subarray
+    workload only)."""
     w = WORKLOADS[name]
     cfg, sd = w["cfg"], (w["seed"] if seed is None else seed)
     out = []
@@ -244,7 +246,8 @@ def make_workload(name: str, *, drops: int | None = None, nrhs: int | None = Non
         kk = k or 30
         for dd in range(drops or 64):
             rng = _rng(cfg, sd, dd)
-            out.append(make_subarray_drop(rng, nt=n, k=kk, nrhs=nrhs or 256, n_sub=20, p_vis=0.35,
+            out.append(make_subarray_drop(rng, nt=n, k=kk, nrhs=nrhs or 256, n_sub=20,
+                                          p_vis=0.35 if p_vis is None else p_vis,
                                           snr_db=0.0 if snr_db is None else snr_db))
     else:
         raise KeyError(name)

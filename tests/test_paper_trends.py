@@ -1,0 +1,52 @@
+"""Qualitative claims of the simulation section, reproduced with the FP64
+oracle on the subarray VR model (CPU; the paper's figure data are absent, so
+only the direction of each trend is checked)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def _cost(d, variant, nb=3, tol=1e-6):
+    """Multiplications of the VR-restricted steps (Table I's counting, VR
+    sizes = visible antennas): VR-OGRK pays |Gamma_i| for the update of the
+    chosen row i plus the residuals of its overlap set X_i; VR-OAHK pays per
+    iteration the residual check, the F half-step, the V residual and the V
+    aggregation."""
+    kw = dict(masks=d.vr_mask, n_sub=d.n_sub)
+    L = d.nt // d.n_sub
+    g = np.array([bin(int(m)).count("1") * L for m in d.vr_mask])
+    X = oracle.overlap_sets(d.H, d.vr_start, d.vr_len, d.xi, **kw)
+    F = oracle.mis(d.H, d.vr_start, d.vr_len, d.xi, **kw)
+    tot = 0.0
+    for b in range(nb):
+        o = oracle.solve(d.H, d.vr_start, d.vr_len, d.S[b], d.xi, variant=variant, tol=tol,
+                         trace=variant == "vr_ogrk", max_iters=20000, **kw)
+        assert o["flags"] & oracle.F_CONVERGED
+        if variant == "vr_ogrk":
+            tot += sum(g[i] + g[X[i]].sum() for i in o["idx"][1:])
+        else:
+            tot += o["iters"] * (g.sum() + g[F].sum() + 2 * g[~F].sum())
+    return tot / nb, F.sum()
+
+
+def test_complexity_grows_with_visibility_probability():
+    # Fig. 7's claim: a larger p (weaker spatial non-stationarity) raises the
+    # complexity of both VR-OGRK and VR-OAHK, and VR-OAHK stays far cheaper;
+    # the orthogonal set shrinks as the VR graph densifies
+    rows = []
+    for p in (0.1, 0.35, 0.9):
+        c = []
+        for dd in range(2):
+            rng = np.random.default_rng([77, dd, int(p * 100)])
+            d = synth.make_subarray_drop(rng, nt=400, k=30, nrhs=3, n_sub=20, p_vis=p, snr_db=0.0)
+            og, nf = _cost(d, "vr_ogrk")
+            oa, _ = _cost(d, "vr_oahk")
+            c.append((og, oa, nf))
+        rows.append(np.mean(c, axis=0))
+    rows = np.array(rows)
+    assert np.all(np.diff(rows[:, 0]) > 0) and np.all(np.diff(rows[:, 1]) > 0)
+    assert np.all(rows[:, 1] < rows[:, 0] / 2)
+    assert np.all(np.diff(rows[:, 2]) < 0)
