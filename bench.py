@@ -18,6 +18,8 @@ complex64, relative-residual tolerance 1e-5. The other workloads:
   precoder the adjoint workload's 256 drops with S = I_K: each drop's RZF precoding
            matrix, its effective channel, beta and per-user spectral efficiency
            (metric: precoding matrices/s; see run_precoder)
+  paper_precoder  the same for 256 drops of the paper's simulation setting (Nt 2000,
+           100 GHz, 20 subarrays visible w.p. 0.35, K 30, five near-field paths, SNR 0 dB)
 Inputs are synthetic and resident in HBM before timing.
 
 One step = the hot path over the whole batch: the forward solve of every
@@ -67,6 +69,10 @@ WORKLOADS = {
     "subarray": "subarray VRs (simulation setting of the paper): 64 drops of Nt=2000 at 100 GHz in S=20 "
                 "subarrays, each visible w.p. 0.35, K=30 at 1..50 m, LoS+CN(0,0.1) on visible antennas, "
                 "256 QPSK vectors each, SNR 0 dB, tol 1e-5; fwd+adjoint",
+    "paper_precoder": "RZF precoding matrices in the paper's simulation setting: 256 drops of Nt=2000 at 100 GHz, "
+                      "S=20 subarrays visible w.p. 0.35, K=30 at 1..50 m, L_k=5 near-field paths, unit-norm "
+                      "rows, SNR 0 dB (xi = 1), S = I_K, tol 1e-5; solve + effective channel + beta + per-user "
+                      "spectral efficiency",
     "precoder": "RZF precoding matrices: 256 drops of Nt=1024, K=64, VR U[256,512], S = I_K, SNR 10 dB, "
                 "tol 1e-5; solve + effective channel + beta + per-user spectral efficiency",
 }
@@ -86,14 +92,15 @@ def run_precoder(args):
     from paper_2501_10689_amd import vrk
 
     dev = torch.device("cuda:0")
-    drops = synth.make_workload("adjoint", snr_db=args.snr)
+    wl = args.workload
+    drops = synth.make_workload("paper" if wl == "paper_precoder" else "adjoint", snr_db=args.snr)
     tol = args.tol if args.tol is not None else 1e-5
     specs, E, R, Bt = [], [], [], []
     for d in drops:
         H = torch.from_numpy(d.H).to(torch.complex64).to(dev)
         S = torch.eye(d.k, dtype=torch.complex64, device=dev)
         X = torch.zeros((d.k, d.nt), dtype=torch.complex64, device=dev)
-        specs.append(vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X))
+        specs.append(vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X, vr_mask=d.vr_mask, n_sub=d.n_sub))
         E.append(torch.zeros((d.k, d.k), dtype=torch.complex64, device=dev))
         R.append(torch.zeros(d.k, dtype=torch.float64, device=dev))
         Bt.append(torch.zeros(1, dtype=torch.float64, device=dev))
@@ -159,6 +166,8 @@ def run_precoder(args):
         worst_rate = max(worst_rate, float(np.max(np.abs(R[j].cpu().numpy() - ro))))
         fset = plan.query(j, vrk.Q_FSET)
         vl = np.asarray(d.vr_len, dtype=np.int64)
+        if d.vr_mask is not None:   # the visible antennas of each user, not its hull
+            vl = np.array([bin(int(m)).count("1") * (d.nt // d.n_sub) for m in d.vr_mask], dtype=np.int64)
         band, band_f = float(vl.sum()), float(vl[fset].sum())
         it = it_all[base:base + d.k]
         overlap = float(plan.query(j, vrk.Q_XOFF)[-1])
@@ -178,7 +187,7 @@ def run_precoder(args):
         "dtype": "f32", "data": "synthetic",
         "timing": "eager launches" if args.eager else
                   "HIP graph of the step, replayed (eager: %.4f ms per step)" % ms_eager,
-        "config": {"workload": WORKLOADS["precoder"], "variant": args.variant, "engine": engine,
+        "config": {"workload": WORKLOADS[wl], "variant": args.variant, "engine": engine,
                    "tile_waves": int(eng[2]), "entries_per_thread": int(eng[6]), "drops": len(drops),
                    "vectors": int(sum(d.k for d in drops)), "tol": tol},
         "roofline": roof,
@@ -192,7 +201,7 @@ def run_precoder(args):
                 break
             t = time.perf_counter()
             Xc = oracle.solve_batch(d.H, d.vr_start, d.vr_len, np.eye(d.k, dtype=np.complex128), d.xi,
-                                    variant=args.variant, tol=tol)["X"]
+                                    variant=args.variant, tol=tol, masks=d.vr_mask, n_sub=d.n_sub)["X"]
             oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi, Xc)
             t_cpu += time.perf_counter() - t
             n_cpu += 1
@@ -286,7 +295,7 @@ def main():
               "(drops shard with no communication); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "precoder":
+    if args.workload in ("precoder", "paper_precoder"):
         run_precoder(args)
         return
 

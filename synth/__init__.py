@@ -9,6 +9,7 @@ from .channels import (  # noqa: F401
     Drop,
     WORKLOADS,
     make_drop,
+    make_multipath_drop,
     make_subarray_drop,
     mask_hulls,
     make_workload,

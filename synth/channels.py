@@ -171,6 +171,54 @@ def make_subarray_drop(rng: np.random.Generator, *, nt: int, k: int, nrhs: int, 
                 vr_mask=masks, n_sub=n_sub)
 
 
+def make_multipath_drop(rng: np.random.Generator, *, nt: int = 2000, k: int = 30, nrhs: int = 0,
+                        n_sub: int = 20, p_vis: float = 0.35, n_paths: int = 5, fc: float = 100e9,
+                        r_lo: float = 1.0, r_hi: float = 50.0, snr_db: float = 0.0,
+                        nlos_gain: float = 0.1) -> Drop:
+    """Draw one drop of the simulation setting of the paper: the near-field
+    multipath channel of Sec. II (LoS path plus n_paths - 1 scatterers, each
+    a spherical-wave array response with phases relative to the array
+    centre, scaled by sqrt(Nt / L_k)) on a ULA along the x axis with antenna
+    n at (n d, 0), n = -(Nt-1)/2 .. (Nt-1)/2, times the Bernoulli subarray
+    indicator. Each row is normalised to unit norm, so the per-user SNR
+    rho ||h_k||^2 / sigma^2 is the same for every user (the power control
+    of the simulation section), and xi = sigma^2 / rho = 1 / SNR.
+
+    Choices the paper leaves open: users and scatterers at distances
+    U[r_lo, r_hi] m and angles U[30, 150] degrees from the array axis (in
+    front of it); gains beta_{k,1} ~ CN(0, 1) for the LoS path and
+    CN(0, nlos_gain) for the others. Draw order: per user its path
+    distances, angles and gains (LoS first), then the visibility matrix,
+    then the symbols (nrhs QPSK vectors; nrhs = 0 for S = I_K work)."""
+    if nt % n_sub or not 1 <= n_sub <= 64:
+        raise ValueError("nt must be a multiple of n_sub, 1 <= n_sub <= 64")
+    lam = C_LIGHT / fc
+    d = lam / 2.0
+    pos = (np.arange(nt) - (nt - 1) / 2.0) * d
+    Hbar = np.zeros((k, nt), dtype=np.complex128)
+    for u in range(k):
+        r = rng.uniform(r_lo, r_hi, size=n_paths)
+        th = np.deg2rad(rng.uniform(30.0, 150.0, size=n_paths))
+        var = np.full(n_paths, nlos_gain)
+        var[0] = 1.0
+        g = (rng.standard_normal(n_paths) + 1j * rng.standard_normal(n_paths)) * np.sqrt(var / 2.0)
+        for l in range(n_paths):
+            dn = np.sqrt(r[l] ** 2 + pos ** 2 - 2.0 * pos * r[l] * np.cos(th[l]))
+            Hbar[u] += g[l] * np.exp(-2j * np.pi * (dn - r[l]) / lam) / np.sqrt(nt)
+        Hbar[u] *= np.sqrt(nt / n_paths)
+    L = nt // n_sub
+    vis = rng.random((k, n_sub)) < p_vis
+    masks = np.array([sum(1 << s for s in range(n_sub) if vis[u, s]) for u in range(k)], dtype=np.uint64)
+    vstart, vlen = mask_hulls(masks, nt, n_sub)
+    H = Hbar * np.repeat(vis, L, axis=1)
+    nrm = np.linalg.norm(H, axis=1)
+    H[nrm > 0] /= nrm[nrm > 0, None]
+    S = qpsk(rng, (nrhs, k))
+    xi = 1.0 / (10.0 ** (snr_db / 10.0))
+    return Drop(H=H, vr_start=vstart, vr_len=vlen, S=S, xi=float(xi), snr_db=float(snr_db),
+                vr_mask=masks, n_sub=n_sub)
+
+
 def _rng(cfg: int, seed: int, drop: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([cfg, seed, drop])))
 
@@ -184,6 +232,9 @@ def _rng(cfg: int, seed: int, drop: int) -> np.random.Generator:
 #   subarray   - 64 drops of the simulation setting of the paper: Nt=2000 at
 #                100 GHz in S=20 subarrays, each visible w.p. 0.35, K=30 users
 #                at 1..50 m, SNR 0 dB; 256 QPSK vectors each
+#   paper      - 256 drops of the same setting with the paper's near-field
+#                multipath channel (L_k = 5 paths, unit-norm rows, xi = 1/SNR),
+#                for precoding matrices (S = I_K, no symbol vectors)
 WORKLOADS = {
     "plain": dict(cfg=0, seed=0),
     "many_rhs": dict(cfg=1, seed=1),
@@ -191,6 +242,7 @@ WORKLOADS = {
     "adjoint": dict(cfg=3, seed=3),
     "large": dict(cfg=4, seed=4),
     "subarray": dict(cfg=5, seed=5),
+    "paper": dict(cfg=6, seed=6),
 }
 
 
@@ -249,6 +301,12 @@ def make_workload(name: str, *, drops: int | None = None, nrhs: int | None = Non
             out.append(make_subarray_drop(rng, nt=n, k=kk, nrhs=nrhs or 256, n_sub=20,
                                           p_vis=0.35 if p_vis is None else p_vis,
                                           snr_db=0.0 if snr_db is None else snr_db))
+    elif name == "paper":
+        for dd in range(drops or 256):
+            rng = _rng(cfg, sd, dd)
+            out.append(make_multipath_drop(rng, nt=nt or 2000, k=k or 30, nrhs=nrhs or 0,
+                                           p_vis=0.35 if p_vis is None else p_vis,
+                                           snr_db=0.0 if snr_db is None else snr_db))
     else:
         raise KeyError(name)
     return out
