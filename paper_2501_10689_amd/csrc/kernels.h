@@ -56,11 +56,12 @@ hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t 
 // desc's gap triples), after either engine's gradient kernels.
 hipError_t vrk_launch_zero_gaps(const VrkDesc *desc, int32_t nprob, int32_t dtype, hipStream_t s);
 // Link metrics after a solve with S = I_K: effective channel E = H X^T on
-// each user's VR, beta = 1 / ||X||_F and the per-user rates (one table entry
-// of outs per problem; dtype 0 complex64, 1 complex128; mfma: the plan is
-// the MFMA engine's, whose residual tiles feed the matrix cores).
+// each user's VR (MFMA plans: (M - xi I) V^T from the Gram tiles), beta =
+// 1 / ||X||_F and the per-user rates (one table entry of outs per problem;
+// dtype 0 complex64, 1 complex128; mfma: the plan is the MFMA engine's;
+// part: VRK_LINK_GROUPS doubles per problem of workspace).
 hipError_t vrk_launch_link(const VrkDesc *desc, const VrkLinkOut *outs, int32_t nprob, int32_t max_k, int32_t dtype,
-                           int32_t mfma, hipStream_t s);
+                           int32_t mfma, double *part, hipStream_t s);
 // MFMA version of the gradient assembly (complex64, plans of the MFMA
 // engine, whose solve forms b = H g itself and leaves H^H mu unformed).
 // GH = sum_b v_b g_b^H - (C + C^H) H with C = sum_b v_b mu_b^H and

@@ -5,9 +5,12 @@
 //   beta    = 1 / ||F||_F                      (power budget ||beta F||_F = 1)
 //   R_u     = log2(1 + beta^2 |E_uu|^2 / (beta^2 sum_{b != u} |E_ub|^2 + xi))
 // with xi = sigma^2 / rho, so the rate is the spectral efficiency of user u.
-// E is a K x K product over the band: on the matrix cores from the residual
-// tiles of the MFMA engine's plans, else tiled through LDS on the VALU;
-// accumulated in the data type, the sums of the rates in double.
+// On MFMA-engine plans X = H^H V exactly (the solve forms x from its dual
+// iterate q = v), so E = H H^H V^T = (M - xi I) V^T: a K x K x K product
+// with the Gram tiles instead of a band product over the antennas. Vector
+// engine plans take the band product, tiled through LDS. ||X||_F^2 is summed
+// from X itself in double, in a fixed order, over VRK_LINK_GROUPS
+// workgroups per problem.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -88,41 +91,51 @@ __global__ void __launch_bounds__(256) k_link_effective(const VrkDesc *descs, co
     }
 }
 
-// beta and the rates, one workgroup per problem: ||X||_F^2 summed in a fixed
-// order (thread t takes column t, t + 1024, ... of each row into one of
-// eight partial sums by row, eight rows in flight, then a tree over the
-// threads), then one user per thread.
+// Partial sums of ||X||_F^2: workgroup (p, y) adds |X[b][n]|^2 in double
+// over the rows b = y, y + VRK_LINK_GROUPS, ... of problem p (thread t the
+// columns t + 256 q + 1024 i into accumulator q), then a tree
+// over the threads; the partial goes to part[p * VRK_LINK_GROUPS + y].
 template <typename R>
-__global__ void __launch_bounds__(1024) k_link_rates(const VrkDesc *descs, const VrkLinkOut *outs)
+__global__ void __launch_bounds__(256) k_link_fro(const VrkDesc *descs, double *part)
 {
-    __shared__ double red[1024];
+    __shared__ double red[256];
     const VrkDesc &d = descs[blockIdx.x];
-    const VrkLinkOut o = outs[blockIdx.x];
     const int tid = threadIdx.x, K = d.k, N = d.nt;
     const C<R> *X = reinterpret_cast<const C<R> *>(d.X);
-    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int n = tid; n < N; n += 1024)
-        for (int b0 = 0; b0 < K; b0 += 8) {
-            C<R> v[8];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = blockIdx.y; b < K; b += VRK_LINK_GROUPS) {
+        const C<R> *row = X + (int64_t)b * d.ldx;
+        for (int n0 = tid; n0 < N; n0 += 1024) {
+            C<R> v[4];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                v[q] = C<R>{0, 0};
-                if (b0 + q < K) v[q] = X[(int64_t)(b0 + q) * d.ldx + n];
-            }
+            for (int q = 0; q < 4; ++q) v[q] = n0 + 256 * q < N ? row[n0 + 256 * q] : C<R>{0, 0};
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc[q] += (double)v[q].x * v[q].x + (double)v[q].y * v[q].y;
+            for (int q = 0; q < 4; ++q) acc[q] += (double)v[q].x * v[q].x + (double)v[q].y * v[q].y;
         }
-    red[tid] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    }
+    red[tid] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __syncthreads();
-    for (int m = 512; m > 0; m >>= 1) {
+    for (int m = 128; m > 0; m >>= 1) {
         if (tid < m) red[tid] += red[tid + m];
         __syncthreads();
     }
-    const double fro2 = red[0];
+    if (tid == 0) part[(int64_t)blockIdx.x * VRK_LINK_GROUPS + blockIdx.y] = red[0];
+}
+
+// beta and the rates, one workgroup per problem: ||X||_F^2 = the partials
+// added in group order, then one user per thread.
+template <typename R>
+__global__ void __launch_bounds__(256) k_link_rates(const VrkDesc *descs, const VrkLinkOut *outs, const double *part)
+{
+    const VrkDesc &d = descs[blockIdx.x];
+    const VrkLinkOut o = outs[blockIdx.x];
+    const int K = d.k;
+    double fro2 = 0.0;
+    for (int y = 0; y < VRK_LINK_GROUPS; ++y) fro2 += part[(int64_t)blockIdx.x * VRK_LINK_GROUPS + y];
     const double beta2 = fro2 > 0.0 ? 1.0 / fro2 : 0.0;
-    if (tid == 0) o.beta[0] = fro2 > 0.0 ? 1.0 / sqrt(fro2) : 0.0;
+    if (threadIdx.x == 0) o.beta[0] = fro2 > 0.0 ? 1.0 / sqrt(fro2) : 0.0;
     const C<R> *E = reinterpret_cast<const C<R> *>(o.E);
-    for (int u = tid; u < K; u += 1024) {
+    for (int u = threadIdx.x; u < K; u += 256) {
         double sig = 0.0, intf = 0.0;
         for (int b = 0; b < K; ++b) {
             const C<R> v = E[(int64_t)u * o.lde + b];
@@ -150,79 +163,84 @@ __device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
 }
 
 // E on the matrix cores (complex64, MFMA-engine plans): wave w of block x
-// takes item 4 x + w = (user block ub, precoder block tb) of problem
-// blockIdx.y. A = the residual tiles of ub (lane i + 16 kk of tile
-// (ab, m) holds H[16 ub + i][16 ab + 4 kk + m], zero off the VRs), B = rows
-// 16 tb + j of X at antennas 16 ab + 4 kk + m; four antenna blocks' loads
-// in flight at a time.
-__global__ void __launch_bounds__(256) k_link_effective_mfma(const VrkDesc *descs, const VrkLinkOut *outs)
+// takes item 4 x + w = (user block mb, precoder block tb) of problem
+// blockIdx.y and multiplies the Gram tiles of row block mb (A: lane
+// i + 16 kk of tile e holds M[16 mb + i][4 c + kk], users in VR-start order,
+// only the chunks c of the block pattern, so M is zero elsewhere) by
+// B[kk][j] = V[16 tb + j][perm[4 c + kk]], then subtracts xi V. Rows of
+// users without any visible antenna are written as zero (their row of M is
+// xi e_u).
+__global__ void __launch_bounds__(256) k_link_effective_gram(const VrkDesc *descs, const VrkLinkOut *outs)
 {
     const VrkDesc &d = descs[blockIdx.y];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
     const int K = d.k, nub = d.nub, ntb = (K + 15) / 16;
     const int item = blockIdx.x * 4 + w;
     if (item >= nub * ntb) return;
-    const int ub = __builtin_amdgcn_readfirstlane(item / ntb), tb = __builtin_amdgcn_readfirstlane(item % ntb);
-    const int lo = __builtin_amdgcn_readfirstlane(d.rab_lo[ub]), hi = __builtin_amdgcn_readfirstlane(d.rab_hi[ub]);
-    const float2 *ha = reinterpret_cast<const float2 *>(d.HA) + d.ha_off[ub] * 64 + lane;
-    const int b = tb * 16 + j, N = d.nt;
-    const float2 *xrow = reinterpret_cast<const float2 *>(d.X) + (int64_t)(b < K ? b : 0) * d.ldx;
+    const int mb = __builtin_amdgcn_readfirstlane(item / ntb), tb = __builtin_amdgcn_readfirstlane(item % ntb);
+    const int e0 = d.gm_off[mb], e1 = d.gm_off[mb + 1];
+    const float2 *gm = reinterpret_cast<const float2 *>(d.GM) + lane;
+    const float2 *V = reinterpret_cast<const float2 *>(d.V);
+    const int b = tb * 16 + j;
     const f4 z = {0.f, 0.f, 0.f, 0.f};
     C3 acc = {z, z, z};
-    for (int ab0 = lo; ab0 < hi; ab0 += 4) {
-        float2 h[4][4], x[4][4];
+    for (int e = e0; e < e1; e += 4) {   // the lists are padded to groups of four
+        float2 a[4], v[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int ab = ab0 + t;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int n = 16 * ab + 4 * g + m;
-                h[t][m] = x[t][m] = float2{0.f, 0.f};
-                if (ab < hi) {
-                    h[t][m] = ha[(int64_t)(4 * (ab - lo) + m) * 64];
-                    if (b < K && n < N) x[t][m] = xrow[n];
-                }
-            }
+            const int c = d.gm_c[e + t];   // -1: padding chunk, zero tile
+            const int kv = 4 * c + g;
+            a[t] = gm[(int64_t)(e + t) * 64];
+            v[t] = (c >= 0 && kv < K && b < K) ? V[(int64_t)b * d.ldv + d.perm[kv]] : float2{0.f, 0.f};
         }
         __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            if (ab0 + t < hi)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) c3mfma(acc, h[t][m], x[t][m]);
+        for (int t = 0; t < 4; ++t) c3mfma(acc, a[t], v[t]);
     }
-    // D layout: lane (j, g) register r holds user 16 ub + 4 g + r, precoder 16 tb + j
+    // D layout: lane (j, g) register r holds user 16 mb + 4 g + r, precoder 16 tb + j
     const VrkLinkOut o = outs[blockIdx.y];
     const f4 re = acc.u - acc.v, im = acc.w - acc.u - acc.v;
+    const float xi = (float)d.xi;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int su = ub * 16 + 4 * g + r;
-        if (su < K && b < K)
-            reinterpret_cast<float2 *>(o.E)[(int64_t)d.perm[su] * o.lde + b] = float2{re[r], im[r]};
+        const int su = mb * 16 + 4 * g + r;
+        if (su < K && b < K) {
+            const int u = d.perm[su];
+            float2 ev = {0.f, 0.f};
+            if (d.ve[u] > d.vs[u]) {
+                const float2 q = V[(int64_t)b * d.ldv + u];
+                ev = float2{re[r] - xi * q.x, im[r] - xi * q.y};
+            }
+            reinterpret_cast<float2 *>(o.E)[(int64_t)u * o.lde + b] = ev;
+        }
     }
 }
 
 }  // namespace
 
 hipError_t vrk_launch_link(const VrkDesc *desc, const VrkLinkOut *outs, int32_t nprob, int32_t max_k, int32_t dtype,
-                           int32_t mfma, hipStream_t s)
+                           int32_t mfma, double *part, hipStream_t s)
 {
     if (nprob <= 0 || max_k <= 0) return hipSuccess;
+    const dim3 gf((unsigned)nprob, VRK_LINK_GROUPS);
     if (mfma && dtype == 0) {
         const int nt1 = (max_k + 15) / 16;
-        hipLaunchKernelGGL(k_link_effective_mfma, dim3((unsigned)((nt1 * nt1 + 3) / 4), (unsigned)nprob), dim3(256), 0,
+        hipLaunchKernelGGL(k_link_effective_gram, dim3((unsigned)((nt1 * nt1 + 3) / 4), (unsigned)nprob), dim3(256), 0,
                            s, desc, outs);
-        hipLaunchKernelGGL(k_link_rates<float>, dim3(nprob), dim3(1024), 0, s, desc, outs);
+        hipLaunchKernelGGL(k_link_fro<float>, gf, dim3(256), 0, s, desc, part);
+        hipLaunchKernelGGL(k_link_rates<float>, dim3(nprob), dim3(256), 0, s, desc, outs, part);
         return hipGetLastError();
     }
     const int t1 = (max_k + 15) / 16;
     const dim3 ge((unsigned)(t1 * t1), (unsigned)nprob);
     if (dtype == 1) {
         hipLaunchKernelGGL(k_link_effective<double>, ge, dim3(256), 0, s, desc, outs, t1);
-        hipLaunchKernelGGL(k_link_rates<double>, dim3(nprob), dim3(1024), 0, s, desc, outs);
+        hipLaunchKernelGGL(k_link_fro<double>, gf, dim3(256), 0, s, desc, part);
+        hipLaunchKernelGGL(k_link_rates<double>, dim3(nprob), dim3(256), 0, s, desc, outs, part);
     } else {
         hipLaunchKernelGGL(k_link_effective<float>, ge, dim3(256), 0, s, desc, outs, t1);
-        hipLaunchKernelGGL(k_link_rates<float>, dim3(nprob), dim3(1024), 0, s, desc, outs);
+        hipLaunchKernelGGL(k_link_fro<float>, gf, dim3(256), 0, s, desc, part);
+        hipLaunchKernelGGL(k_link_rates<float>, dim3(nprob), dim3(256), 0, s, desc, outs, part);
     }
     return hipGetLastError();
 }

@@ -71,6 +71,7 @@ struct ProbPlan {
     int32_t nmf = 0;   // columns of MF (F users) when the solve takes the F half-step on the VALU
     std::vector<int32_t> cp_off, cp_col, cp_tr, cp_diag;   // blocks of C on the Gram block pattern
     std::vector<uint64_t> mask;   // subarray masks (empty: interval VRs)
+    bool keep_v = false;          // V goes to the workspace (caller gave none; adjoint or S = I_K shape)
     std::vector<int32_t> gaps;    // (user, first antenna, length) of hidden runs inside the hulls
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
@@ -108,7 +109,7 @@ struct vrk_plan {
     std::vector<int4> gruns;    // runs of band tiles of the gradient's second kernel
     size_t o_gruns = 0;
     std::vector<VrkLinkOut> link_host;   // output table of the link metrics, uploaded per call
-    size_t o_link = 0;
+    size_t o_link = 0, o_linkpart = 0;   // link-metric output table; partial sums of ||X||_F^2
     int32_t persistent = 0, grid = 0;
     int32_t max_nub = 0;
     std::vector<uint8_t> image;
@@ -717,6 +718,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     }
     pl->table_end = cv.off;
     pl->o_link = cv.take(sizeof(VrkLinkOut) * nprob);
+    pl->o_linkpart = cv.take(sizeof(double) * VRK_LINK_GROUPS * nprob);
     pl->o_gpart = cv.take(pl->gsplit > 1 ? pl->gtiles.size() * (size_t)pl->gsplit * VRK_GRAD_UG * 256 * 8 : 0);
     for (auto &q : pl->pp) {
         q.o_nrm = cv.take((size_t)rb * std::max(q.p.k, q.nub * VRK_UB));
@@ -730,10 +732,14 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             pl->max_tiles = std::max(pl->max_tiles, (int64_t)(q.nub * VRK_UB * q.nmf + 63) / 64);
             pl->max_tiles = std::max(pl->max_tiles, std::max(q.n_ha, q.n_hg));
         }
+        // v of the forward solve is kept when the caller passes no V: the
+        // adjoint needs it, and so do the link metrics of an S = I_K solve
+        // (E = (M - xi I) V^T on the matrix cores)
+        q.keep_v = !q.p.V && (q.p.GX || q.p.nrhs == q.p.k);
+        q.o_vfwd = q.keep_v ? cv.take((size_t)eb * q.p.nrhs * q.p.k) : 0;
         if (q.p.GX) {
             q.o_sadj = cv.take((size_t)eb * q.p.nrhs * q.p.k);
             q.o_xadj = eng == VRK_ENGINE_MFMA ? 0 : cv.take((size_t)eb * q.p.nrhs * q.p.nt);
-            q.o_vfwd = q.p.V ? 0 : cv.take((size_t)eb * q.p.nrhs * q.p.k);
             if (eng == VRK_ENGINE_MFMA) {
                 q.o_vsrt = cv.take((size_t)8 * q.p.nrhs * q.nub * VRK_UB);
                 q.o_msrt = cv.take((size_t)8 * q.p.nrhs * q.nub * VRK_UB);
@@ -804,7 +810,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.ldgx = p.ldgx; d.ldgh = p.ldgh; d.ldgs = p.ldgs;
         d.rhs_base = q.rhs_base;
         d.H = p.H; d.S = p.S; d.X = p.X;
-        d.V = p.V ? p.V : (p.GX ? base + q.o_vfwd : nullptr);
+        d.V = p.V ? p.V : (q.keep_v ? base + q.o_vfwd : nullptr);
         d.GX = p.GX; d.GH = p.GH; d.GS = p.GS; d.gxi = p.gxi;
         d.Sadj = p.GX ? base + q.o_sadj : nullptr;
         d.Xadj = p.GX && pl->engine != VRK_ENGINE_MFMA ? base + q.o_xadj : nullptr;
@@ -1008,7 +1014,8 @@ vrk_status vrk_link_metrics(vrk_plan *pl, const vrk_link_out *out, void *stream)
         }
     }
     e = vrk_launch_link(reinterpret_cast<const VrkDesc *>(pl->d_ws + pl->o_desc), d_out, nprob, pl->max_k,
-                        pl->opt.dtype == VRK_C128 ? 1 : 0, pl->engine == VRK_ENGINE_MFMA ? 1 : 0, s);
+                        pl->opt.dtype == VRK_C128 ? 1 : 0, pl->engine == VRK_ENGINE_MFMA ? 1 : 0,
+                        reinterpret_cast<double *>(pl->d_ws + pl->o_linkpart), s);
     if (e != hipSuccess) return hip_fail(e, "link metric kernels");
     return VRK_OK;
 }

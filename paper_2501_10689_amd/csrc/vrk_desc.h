@@ -13,6 +13,8 @@
 #define VRK_AB 16
 // users per group of the cross-wave residual reduction in the MFMA engine
 #define VRK_RGROUP 32
+// workgroups per problem of the ||X||_F^2 partial sums of the link metrics
+#define VRK_LINK_GROUPS 16
 
 enum { VRK_FLAG_CONVERGED = 1, VRK_FLAG_NONFINITE = 2, VRK_FLAG_MAXITER = 4 };
 
