@@ -188,6 +188,10 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
  *   beta[0]        = 1 / ||F||_F (so that ||beta F||_F = 1, the power budget),
  *   rate[u]        = log2(1 + beta^2 |E_uu|^2 / (beta^2 sum_{b != u} |E_ub|^2 + xi))
  *                    (double, bit/s/Hz; xi = sigma^2 / rho as in the RZF design).
+ * On MFMA-engine plans E is evaluated as (H H^H) V^T = (M - xi I) V^T from
+ * the plan's Gram tiles and the solve's V (the MFMA solve forms x = H^H v, so
+ * this is the same quantity; V is kept in the workspace when the caller
+ * passed none); beta is summed from X itself.
  * Asynchronous on stream. The nprob-entry output table is copied to the
  * workspace when it differs from the previous call's on this binding (the
  * workspace belongs to the plan while bound), so repeated calls with the
