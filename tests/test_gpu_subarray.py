@@ -166,3 +166,33 @@ def test_subarray_user_without_visible_subarray():
     assert 5 in plan.query(0, 1)
     assert rel_err_rows(res[0]["X"], X).max() <= 1e-4
     assert np.max(np.abs(res[0]["V"][:, 5] - d.S[:, 5] / d.xi)) <= 1e-5 * np.max(np.abs(d.S[:, 5] / d.xi))
+
+
+@pytest.mark.parametrize("nt,n_sub,k,p,engine,dtype", [
+    (128, 64, 1, 1.0, "vector", "c128"),     # one user seeing every subarray (hull = array)
+    (64, 64, 20, 0.3, "mfma", "c64"),        # one antenna per subarray, bit 63 in use
+    (64, 64, 20, 0.3, "vector", "c128"),
+    (300, 3, 40, 0.5, "mfma", "c64"),        # three wide subarrays, K > Nt / 8
+])
+def test_subarray_edge_shapes(nt, n_sub, k, p, engine, dtype):
+    rng = np.random.default_rng(nt + n_sub + k)
+    d = synth.make_subarray_drop(rng, nt=nt, k=k, nrhs=20, n_sub=n_sub, p_vis=p, snr_db=10.0, fc=28e9,
+                                 r_lo=5.0)
+    if k > 1:
+        d.vr_mask[1] = 0
+        d.H[1] = 0
+        d.vr_start[1] = d.vr_len[1] = 0
+        d.vr_mask[2] = np.uint64(1) << np.uint64(n_sub - 1)
+        d.H[2, : nt - nt // n_sub] = 0
+        d.H[2, nt - nt // n_sub:] = 1.0 + 0.5j
+        d.vr_start[2], d.vr_len[2] = nt - nt // n_sub, nt // n_sub
+    kw = dict(masks=d.vr_mask, n_sub=d.n_sub)
+    X, V = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi, **kw)
+    tol = 1e-12 if dtype == "c128" else 1e-6
+    res, plan = run_plan([_tuple(d)], variant="vr_oahk", dtype=dtype, engine=engine, tol=tol)
+    r = res[0]
+    assert np.all(r["flags"] == oracle.F_CONVERGED)
+    assert rel_err_rows(r["X"], X).max() <= (1e-9 if dtype == "c128" else 1e-4)
+    f = np.zeros(k, bool)
+    f[plan.query(0, 1)] = True
+    assert np.array_equal(f, oracle.mis(d.H, d.vr_start, d.vr_len, d.xi, **kw))
