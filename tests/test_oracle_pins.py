@@ -760,6 +760,13 @@ def test_reducing_peeling_small_cases():
     star = np.zeros((6, 6), bool)
     star[0, 1:] = star[1:, 0] = True
     assert np.array_equal(_f_of_graph(star), [False] + [True] * 5)
+    # bowtie (two triangles sharing vertex 0): no vertex of degree <= 1, so
+    # the centre (largest degree) is peeled first, then the two edges reduce
+    # by degree 1 to {1, 3}; peeling a smallest-degree vertex would give {2, 3}
+    bow = np.zeros((5, 5), bool)
+    for i, j in [(0, 1), (1, 2), (0, 2), (0, 3), (3, 4), (0, 4)]:
+        bow[i, j] = bow[j, i] = True
+    assert np.array_equal(_f_of_graph(bow), [False, True, False, True, False])
 
 
 def test_subarray_graph_matches_antenna_indicators():
