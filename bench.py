@@ -78,6 +78,23 @@ WORKLOADS = {
 }
 
 
+def time_bind(plan, stream, reps=5):
+    """Mean time of vrk_plan_bind on the stream (plan tables to the
+    workspace, row norms, tile packing and Gram tiles: the per-channel setup
+    that precedes the solves), in ms."""
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    plan.bind(stream)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        plan.bind(stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
 def run_precoder(args):
     """One step = every drop's precoding matrix (the solve on S = I_K, rows of X
     = columns of F) and its link metrics (vrk_link_metrics). Accuracy: NMSE of
@@ -111,6 +128,7 @@ def run_precoder(args):
     engine = {1: "vector", 2: "mfma"}[int(eng[0])]
     stats = plan.stats_buffers()
     stream = torch.cuda.current_stream(dev)
+    bind_ms = time_bind(plan, stream)
 
     def step(ev=None):
         if ev is not None:
@@ -191,6 +209,8 @@ def run_precoder(args):
                    "tile_waves": int(eng[2]), "entries_per_thread": int(eng[6]), "drops": len(drops),
                    "vectors": int(sum(d.k for d in drops)), "tol": tol},
         "roofline": roof,
+        "bind_ms": bind_ms,
+        "matrices_per_s_with_bind": len(drops) / ((ms_step + bind_ms) * 1e-3),
         "accuracy": {"max_nmse": worst_nmse, "max_rate_diff_bits": worst_rate,
                      "mean_iters": float(it_all.mean()), "max_iters": int(it_all.max())},
     }
@@ -339,6 +359,7 @@ def main():
     stats = plan.stats_buffers()
     stats_adj = plan.stats_buffers()
     stream = torch.cuda.current_stream(dev)
+    bind_ms = time_bind(plan, stream)
 
     def step(ev=None):
         if ev is not None:
@@ -433,6 +454,7 @@ def main():
                    "drops": len(drops), "vectors": B, "tol": tol},
         "orthogonal_set_mean": float(np.mean([len(plan.query(j, vrk.Q_FSET)) for j in range(len(drops))])),
         "roofline": roof,
+        "bind_ms": bind_ms,
         "accuracy": {"max_rel_err": worst, "mean_rel_err": errsum / B,
                      "all_converged": bool(np.all(fl_all == 1)), "mean_iters": float(it_all.mean()),
                      "max_iters": int(it_all.max())},

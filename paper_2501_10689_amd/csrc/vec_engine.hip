@@ -30,34 +30,39 @@ __device__ R block_sum(R v, R *red)
 }
 
 // ---------------------------------------------------------------------------
-// Row norms: nrm_i = ||H[i, VR_i]||^2 + xi (the stored norms of Alg. 1) and
-// ||A||_F^2 = sum_i nrm_i. One workgroup per problem.
+// Row norms: nrm_i = ||H[i, VR_i]||^2 + xi (the stored norms of Alg. 1), one
+// wave per row, rows spread over kNormGroups workgroups per problem; then
+// ||A||_F^2 = sum_i nrm_i in index order by one thread per problem.
 // ---------------------------------------------------------------------------
+constexpr int kNormGroups = 64;
+
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_norms(const VrkDesc *descs)
 {
-    __shared__ R red[kWaves];
     const VrkDesc &d = descs[blockIdx.x];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const cx<R> *H = reinterpret_cast<const cx<R> *>(d.H);
     R *nrm = reinterpret_cast<R *>(d.nrm);
-    R part = 0;
-    for (int i = w; i < d.k; i += kWaves) {
+    for (int i = blockIdx.y * kWaves + w; i < d.k; i += kNormGroups * kWaves) {
         R acc = 0;
         for (int n = d.vs[i] + lane; n < d.ve[i]; n += 64) acc += cnorm2(H[(int64_t)i * d.ldh + n]);
         acc = wave_sum(acc) + (R)d.xi;
         if (lane == 0) nrm[i] = acc;
-        part += acc;
     }
     // padded users of the MFMA engine get a unit norm (their residual is 0)
-    for (int i = d.k + threadIdx.x; i < d.nub * VRK_UB; i += kThreads) nrm[i] = 1;
-    if (lane == 0) red[w] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        R t = 0;
-        for (int i = 0; i < kWaves; ++i) t += red[i];
-        *reinterpret_cast<R *>(d.fro2) = t;
-    }
+    if (blockIdx.y == 0)
+        for (int i = d.k + threadIdx.x; i < d.nub * VRK_UB; i += kThreads) nrm[i] = 1;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64) k_fro(const VrkDesc *descs)
+{
+    const VrkDesc &d = descs[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const R *nrm = reinterpret_cast<const R *>(d.nrm);
+    R t = 0;
+    for (int i = 0; i < d.k; ++i) t += nrm[i];
+    *reinterpret_cast<R *>(d.fro2) = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -65,7 +70,7 @@ __global__ void __launch_bounds__(kThreads) k_norms(const VrkDesc *descs)
 // holds H[perm[16 ub + i], 16 ab + 4 kk + m] with ab = rab_lo[ub] + c / 4,
 // m = c % 4, zero outside that user's VR. Aggregation tile e of antenna
 // block ab: lane l = i + 16 kk holds conj(H[perm[4 uc + kk], 16 ab + i]).
-// Gram tiles hold H H^H + xi I in VR-start order. One wave per tile.
+// One wave per tile; the Gram tiles and F columns follow in k_gram, k_mf.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
 {
@@ -110,46 +115,99 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
         }
         reinterpret_cast<cx<float> *>(d.HG)[t * 64 + lane] = v;
     }
-    // F columns of M for the VALU orthogonal half-step: entry (ku, tt) =
-    // M[perm[ku]][flist[tt]], accumulated in double and rounded once
-    if (d.MF && t * 64 + lane < (int64_t)d.nub * VRK_UB * d.nmf) {
-        const int idx = (int)(t * 64) + lane, ku = idx / d.nmf, tt = idx % d.nmf;
-        double ar = 0.0, ai = 0.0;
-        if (ku < d.k) {
-            const int u = d.perm[ku], f = d.flist[tt];
-            const int lo = max(d.vs[u], d.vs[f]), hi = min(d.ve[u], d.ve[f]);
-            for (int n = lo; n < hi; ++n) {
-                cx<float> a = H[(int64_t)u * d.ldh + n], b = H[(int64_t)f * d.ldh + n];
-                ar += (double)a.re * b.re + (double)a.im * b.im;
-                ai += (double)a.im * b.re - (double)a.re * b.im;
-            }
-            if (u == f) ar += d.xi;
+}
+
+// Gram tiles of M = H H^H + xi I, one wave per tile e of user block mb: lane
+// l = i + 16 kk holds M[perm[16 mb + i], perm[4 c + kk]] = the sum over the
+// antennas of H[u, n] conj(H[v, n]) (+ xi on the diagonal), accumulated in
+// double in antenna order and rounded once. The wave stages 64 antennas of
+// its 16 + 4 rows at a time in LDS (coalesced loads, zero off each VR) over
+// the antennas where a row of the block and a row of the chunk can meet.
+constexpr int kGramRows = VRK_UB + 4;
+
+__global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
+{
+    __shared__ cx<float> st[kWaves][kGramRows][65];   // padded rows: the 16 block rows hit different banks
+    const VrkDesc &d = descs[blockIdx.y];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+    const int64_t t = (int64_t)blockIdx.x * kWaves + w;
+    if (t >= d.gm_off[d.nub]) return;   // the wave only: no barrier below
+    int mb = 0;
+    while (d.gm_off[mb + 1] <= t) ++mb;
+    const int uc = d.gm_c[t];   // -1: padding chunk, zero tile
+    const cx<float> *H = reinterpret_cast<const cx<float> *>(d.H);
+    // rows 0..15: users of the block, 16..19: users of the chunk (-1: none);
+    // lane r < 20 keeps row r's user and VR, read back as scalars
+    int ru = -1, rvs = 0, rve = 0;
+    if (lane < kGramRows && uc >= 0) {
+        const int ks = lane < VRK_UB ? mb * VRK_UB + lane : uc * 4 + (lane - VRK_UB);
+        if (ks < d.k) {
+            ru = d.perm[ks];
+            rvs = d.vs[ru];
+            rve = d.ve[ru];
         }
-        reinterpret_cast<cx<float> *>(d.MF)[idx] = cx<float>{(float)ar, (float)ai};
     }
-    const int64_t n_gm = d.gm_off[d.nub];
-    if (t < n_gm) {
-        // Gram tile e of user block mb: lane l = i + 16 kk holds
-        // M[perm[16 mb + i], perm[4 c + kk]] = sum over the overlap of
-        // H[u, n] conj(H[v, n]) (+ xi on the diagonal), accumulated in
-        // double and rounded once
-        int mb = 0;
-        while (d.gm_off[mb + 1] <= t) ++mb;
-        const int uc = d.gm_c[t];   // -1: padding chunk, zero tile
-        const int ku = mb * VRK_UB + i, kv = uc * 4 + kk;
-        double ar = 0.0, ai = 0.0;
-        if (uc >= 0 && ku < d.k && kv < d.k) {
-            const int u = d.perm[ku], v2 = d.perm[kv];
-            const int lo = max(d.vs[u], d.vs[v2]), hi = min(d.ve[u], d.ve[v2]);
-            for (int n = lo; n < hi; ++n) {
-                cx<float> a = H[(int64_t)u * d.ldh + n], b = H[(int64_t)v2 * d.ldh + n];
-                ar += (double)a.re * b.re + (double)a.im * b.im;
-                ai += (double)a.im * b.re - (double)a.re * b.im;
-            }
-            if (u == v2) ar += d.xi;
+    int lo_b = d.nt, hi_b = 0, lo_c = d.nt, hi_c = 0;
+#pragma unroll
+    for (int r = 0; r < kGramRows; ++r) {
+        const int u = __builtin_amdgcn_readlane(ru, r), a = __builtin_amdgcn_readlane(rvs, r),
+                  b = __builtin_amdgcn_readlane(rve, r);
+        if (u < 0 || b <= a) continue;
+        if (r < VRK_UB) { lo_b = min(lo_b, a); hi_b = max(hi_b, b); }
+        else { lo_c = min(lo_c, a); hi_c = max(hi_c, b); }
+    }
+    const int lo = max(lo_b, lo_c), hi = min(hi_b, hi_c);
+    double ar = 0.0, ai = 0.0;
+    for (int n0 = lo; n0 < hi; n0 += 64) {
+        const int n = n0 + lane;
+        cx<float> v[kGramRows];
+#pragma unroll
+        for (int r = 0; r < kGramRows; ++r) {
+            const int u = __builtin_amdgcn_readlane(ru, r), a = __builtin_amdgcn_readlane(rvs, r),
+                      b = __builtin_amdgcn_readlane(rve, r);
+            v[r] = cx<float>{0.f, 0.f};
+            if (u >= 0 && n < hi && n >= a && n < b) v[r] = H[(int64_t)u * d.ldh + n];
         }
-        reinterpret_cast<cx<float> *>(d.GM)[t * 64 + lane] = cx<float>{(float)ar, (float)ai};
+        __builtin_amdgcn_sched_barrier(0);   // all rows' loads in flight before the first wait
+#pragma unroll
+        for (int r = 0; r < kGramRows; ++r) st[w][r][lane] = v[r];
+        __builtin_amdgcn_wave_barrier();
+        const int m = min(64, hi - n0);
+        for (int q = 0; q < m; ++q) {
+            const cx<float> a = st[w][i][q], b = st[w][VRK_UB + kk][q];
+            ar += (double)a.re * b.re + (double)a.im * b.im;
+            ai += (double)a.im * b.re - (double)a.re * b.im;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
+    const int ku = mb * VRK_UB + i, kv = uc * 4 + kk;
+    if (uc >= 0 && ku < d.k && kv < d.k && d.perm[ku] == d.perm[kv]) ar += d.xi;
+    if (uc < 0) ar = ai = 0.0;
+    reinterpret_cast<cx<float> *>(d.GM)[t * 64 + lane] = cx<float>{(float)ar, (float)ai};
+}
+
+// F columns of M for the VALU orthogonal half-step: entry (ku, tt) =
+// M[perm[ku]][flist[tt]], copied from the Gram tiles (the same double sums,
+// rounded once): tile (ku / 16, chunk pos[f] / 4) of the block pattern,
+// lane ku % 16 + 16 (pos[f] % 4); zero when the chunk is not in the pattern
+// (no overlap).
+__global__ void __launch_bounds__(kThreads) k_mf(const VrkDesc *descs)
+{
+    const VrkDesc &d = descs[blockIdx.y];
+    if (!d.MF) return;
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= (int64_t)d.nub * VRK_UB * d.nmf) return;
+    const int ku = (int)(idx / d.nmf), tt = (int)(idx % d.nmf);
+    cx<float> v = {0.f, 0.f};
+    if (ku < d.k) {
+        const int mb = ku / VRK_UB, pf = d.pos[d.flist[tt]], c = pf / 4;
+        for (int e = d.gm_off[mb]; e < d.gm_off[mb + 1]; ++e)
+            if (d.gm_c[e] == c) {
+                v = reinterpret_cast<const cx<float> *>(d.GM)[(int64_t)e * 64 + (ku % VRK_UB) + 16 * (pf % 4)];
+                break;
+            }
+    }
+    reinterpret_cast<cx<float> *>(d.MF)[idx] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -508,16 +566,26 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_grads(const VrkDesc *descs
 
 hipError_t vrk_launch_norms(const VrkDesc *desc, int32_t nprob, int32_t dtype, hipStream_t s)
 {
-    if (dtype == 1) hipLaunchKernelGGL(k_norms<double>, dim3(nprob), dim3(kThreads), 0, s, desc);
-    else hipLaunchKernelGGL(k_norms<float>, dim3(nprob), dim3(kThreads), 0, s, desc);
+    const dim3 grid((unsigned)nprob, kNormGroups);
+    if (dtype == 1) {
+        hipLaunchKernelGGL(k_norms<double>, grid, dim3(kThreads), 0, s, desc);
+        hipLaunchKernelGGL(k_fro<double>, dim3(nprob), dim3(64), 0, s, desc);
+    } else {
+        hipLaunchKernelGGL(k_norms<float>, grid, dim3(kThreads), 0, s, desc);
+        hipLaunchKernelGGL(k_fro<float>, dim3(nprob), dim3(64), 0, s, desc);
+    }
     return hipGetLastError();
 }
 
 hipError_t vrk_launch_pack(const VrkDesc *desc, int32_t nprob, int64_t max_tiles, hipStream_t s)
 {
     if (max_tiles <= 0) return hipSuccess;
-    unsigned gx = (unsigned)((max_tiles + kWaves - 1) / kWaves);
+    const unsigned gx = (unsigned)((max_tiles + kWaves - 1) / kWaves);
     hipLaunchKernelGGL(k_pack, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
+    hipLaunchKernelGGL(k_gram, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
+    // MF entries: at most 64 * max_tiles per problem (the plan counts them in max_tiles)
+    const unsigned gm = (unsigned)((max_tiles * 64 + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_mf, dim3(gm, nprob), dim3(kThreads), 0, s, desc);
     return hipGetLastError();
 }
 
