@@ -70,7 +70,8 @@ __global__ void __launch_bounds__(64) k_fro(const VrkDesc *descs)
 // holds H[perm[16 ub + i], 16 ab + 4 kk + m] with ab = rab_lo[ub] + c / 4,
 // m = c % 4, zero outside that user's VR. Aggregation tile e of antenna
 // block ab: lane l = i + 16 kk holds conj(H[perm[4 uc + kk], 16 ab + i]).
-// One wave per tile; the Gram tiles and F columns follow in k_gram, k_mf.
+// Wave t packs residual tiles 4t .. 4t + 3 and aggregation tile t; the Gram
+// tiles and F columns follow in k_gram, k_mf.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
 {
@@ -81,19 +82,26 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
     const int64_t n_hg = d.ag_off[d.nab];
     const cx<float> *H = reinterpret_cast<const cx<float> *>(d.H);
     const int i = lane & 15, kk = lane >> 4;
-    if (t < n_ha) {
+    if (t * 4 < n_ha) {
+        // the four residual tiles m = 0..3 of one (user block, antenna
+        // block): lane (i, kk) loads antennas 16 ab + 4 kk .. + 3 of its row
+        // (contiguous) and writes one of them to each tile
         int ub = 0;
-        while (d.ha_off[ub + 1] <= t) ++ub;
-        int64_t c = t - d.ha_off[ub];
-        int ab = d.rab_lo[ub] + (int)(c >> 2), m = (int)(c & 3);
-        int n = ab * VRK_AB + 4 * kk + m;
-        int ku = ub * VRK_UB + i;
-        cx<float> v = {0.f, 0.f};
+        while (d.ha_off[ub + 1] <= t * 4) ++ub;
+        const int64_t c0 = t * 4 - d.ha_off[ub];
+        const int ab = d.rab_lo[ub] + (int)(c0 >> 2);
+        const int ku = ub * VRK_UB + i;
+        cx<float> v[4] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
         if (ku < d.k) {
-            int u = d.perm[ku];
-            if (n >= d.vs[u] && n < d.ve[u]) v = H[(int64_t)u * d.ldh + n];
+            const int u = d.perm[ku];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int n = ab * VRK_AB + 4 * kk + m;
+                if (n >= d.vs[u] && n < d.ve[u]) v[m] = H[(int64_t)u * d.ldh + n];
+            }
         }
-        reinterpret_cast<cx<float> *>(d.HA)[t * 64 + lane] = v;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) reinterpret_cast<cx<float> *>(d.HA)[(t * 4 + m) * 64 + lane] = v[m];
     }
     if (t < n_hg) {
         int lo = 0, hi = d.nab;   // ab with ag_off[ab] <= t < ag_off[ab+1]
