@@ -235,3 +235,29 @@ def test_large_shape_adjoint():
     assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m])
     assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS)
     assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
+
+
+@pytest.mark.parametrize("engine", ["mfma", "vector"])
+def test_rebind_and_resolve_are_bitwise_deterministic(engine):
+    """Binding again (row norms, tiles and Gram tiles recomputed from H) and
+    solving again reproduce X, V and the iteration counts bit for bit; so
+    does a second plan on the same inputs."""
+    import torch
+    from paper_2501_10689_amd import vrk
+    d = synth.make_workload("uneven", drops=3, nrhs=40, seed=11)
+    drops = [(x.H, x.vr_start, x.vr_len, x.S, x.xi) for x in d]
+    a, plan = run_plan(drops, variant="vr_oahk", engine=engine, tol=1e-6)
+    st = plan.stats_buffers()
+    plan.bind()
+    plan.solve(stats=st)
+    torch.cuda.synchronize()
+    it = st[0].cpu().numpy()
+    base = 0
+    for j, sp in enumerate(plan.probs):
+        B = sp.S.shape[0]
+        assert np.array_equal(sp.X.cpu().numpy().astype(np.complex128), a[j]["X"])
+        assert np.array_equal(it[base:base + B], a[j]["iters"])
+        base += B
+    b, _ = run_plan(drops, variant="vr_oahk", engine=engine, tol=1e-6)
+    for x, y in zip(a, b):
+        assert np.array_equal(x["X"], y["X"]) and np.array_equal(x["V"], y["V"])
