@@ -338,7 +338,7 @@ def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, vr_mask=None, n_sub=0, **
 
 
 def precoder(H, vr_start, vr_len, xi, variant="vr_oahk", select="baiwu", tol=1e-5, max_iters=100000,
-             seed=0, engine="auto"):
+             seed=0, engine="auto", vr_mask=None, n_sub=0):
     """RZF precoding matrix of one drop and its link metrics on the GPU: the
     solve on S = I_K gives X = F^T (row b the unnormalised precoder of user b);
     returns X, the effective channel E = H F on the VRs (K x K), the per-user
@@ -352,7 +352,7 @@ def precoder(H, vr_start, vr_len, xi, variant="vr_oahk", select="baiwu", tol=1e-
     rate = torch.empty(K, dtype=torch.float64, device=H.device)
     beta = torch.empty(1, dtype=torch.float64, device=H.device)
     o = options(variant=variant, select=select, dtype=dtype, engine=engine, tol=tol, max_iters=max_iters, seed=seed)
-    plan = Plan([ProblemSpec(H, vr_start, vr_len, xi, S, X, None)], o)
+    plan = Plan([ProblemSpec(H, vr_start, vr_len, xi, S, X, None, vr_mask=vr_mask, n_sub=n_sub)], o)
     plan.solve()
     plan.link_metrics([E], [rate], [beta])
     return X, E, rate, float(beta.cpu()[0])
@@ -360,8 +360,10 @@ def precoder(H, vr_start, vr_len, xi, variant="vr_oahk", select="baiwu", tol=1e-
 
 def precode(H, vr_start, vr_len, S, xi, variant="vr_oahk", select="baiwu", tol=1e-5,
             max_iters=100000, seed=0, engine="auto", schedule="auto", tile_waves=0,
-            return_stats=False, V=True):
-    """Precode the rows of S (B x K) for channel H (K x Nt) on the GPU.
+            return_stats=False, V=True, vr_mask=None, n_sub=0):
+    """Precode the rows of S (B x K) for channel H (K x Nt) on the GPU
+    (vr_mask / n_sub: the subarray VR model, with vr_start / vr_len the
+    hulls of the visible subarrays).
 
     Returns X (B x Nt) and V (B x K) as torch tensors (and the per-RHS
     iteration counts, relative residuals and flags with return_stats)."""
@@ -375,7 +377,7 @@ def precode(H, vr_start, vr_len, S, xi, variant="vr_oahk", select="baiwu", tol=1
     Vt = torch.empty((B, H.shape[0]), dtype=H.dtype, device=H.device) if V else None
     o = options(variant=variant, select=select, dtype=dtype, engine=engine, tol=tol,
                 max_iters=max_iters, seed=seed, schedule=schedule, tile_waves=tile_waves)
-    plan = Plan([ProblemSpec(H, vr_start, vr_len, xi, S, X, Vt)], o)
+    plan = Plan([ProblemSpec(H, vr_start, vr_len, xi, S, X, Vt, vr_mask=vr_mask, n_sub=n_sub)], o)
     st = plan.stats_buffers()
     plan.solve(stats=st)
     if return_stats:

@@ -89,3 +89,21 @@ def test_rates_after_fifteen_iterations():
             _, _, rr = oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi,
                                            oracle.precoder(d.H, d.vr_start, d.vr_len, d.xi))
             assert abs(R.cpu().numpy().sum() - rr.sum()) <= 1e-3 * rr.sum()
+
+
+def test_precoder_helper_on_the_paper_setting():
+    # vrk.precoder with the subarray masks: converged precoding matrix, E,
+    # beta and rates against the FP64 RZF and its link metrics
+    import torch
+    from paper_2501_10689_amd import vrk
+    d = _drop(3, snr_db=10.0)
+    Hd = torch.tensor(d.H, dtype=torch.complex64, device="cuda")
+    X, E, rate, beta = vrk.precoder(Hd, d.vr_start, d.vr_len, d.xi, tol=1e-6, vr_mask=d.vr_mask, n_sub=d.n_sub)
+    torch.cuda.synchronize()
+    Xr = oracle.precoder(d.H, d.vr_start, d.vr_len, d.xi)
+    Er, br, rr = oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi, Xr)
+    Xg = X.cpu().numpy().astype(np.complex128)
+    assert oracle.nmse(br * Xr, beta * Xg) <= 1e-4
+    assert np.max(np.abs(E.cpu().numpy() - Er)) <= 1e-4
+    assert np.max(np.abs(rate.cpu().numpy() - rr)) <= 2e-4 * max(1.0, rr.max())
+    assert abs(beta - br) <= 1e-4 * br
