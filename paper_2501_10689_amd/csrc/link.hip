@@ -162,25 +162,34 @@ __device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
     acc.w = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, acc.w, 0, 0, 0);
 }
 
-// E on the matrix cores (complex64, MFMA-engine plans): wave w of block x
-// takes item 4 x + w = (user block mb, precoder block tb) of problem
-// blockIdx.y and multiplies the Gram tiles of row block mb (A: lane
-// i + 16 kk of tile e holds M[16 mb + i][4 c + kk], users in VR-start order,
-// only the chunks c of the block pattern, so M is zero elsewhere) by
-// B[kk][j] = V[16 tb + j][perm[4 c + kk]], then subtracts xi V. Rows of
-// users without any visible antenna are written as zero (their row of M is
-// xi e_u).
+// E on the matrix cores (complex64, MFMA-engine plans): workgroup x of
+// problem blockIdx.y takes precoder block tb = x % ntb and user blocks
+// mb = 4 (x / ntb) + w (one per wave). The workgroup stages rows 16 tb .. +15
+// of V in LDS with the users in VR-start order, then each wave multiplies
+// the Gram tiles of its row block (A: lane i + 16 kk of tile e holds
+// M[16 mb + i][4 c + kk], only the chunks c of the block pattern, so M is
+// zero elsewhere) by B[kk][j] = V[16 tb + j][perm[4 c + kk]] and subtracts
+// xi V. Rows of users without any visible antenna are written as zero (their
+// row of M is xi e_u).
+constexpr int kLinkUsers = 16 * 16;   // users per problem on the MFMA engine (16 waves x 16)
+
 __global__ void __launch_bounds__(256) k_link_effective_gram(const VrkDesc *descs, const VrkLinkOut *outs)
 {
+    __shared__ float2 vsrt[16][kLinkUsers + 1];
     const VrkDesc &d = descs[blockIdx.y];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
-    const int K = d.k, nub = d.nub, ntb = (K + 15) / 16;
-    const int item = blockIdx.x * 4 + w;
-    if (item >= nub * ntb) return;
-    const int mb = __builtin_amdgcn_readfirstlane(item / ntb), tb = __builtin_amdgcn_readfirstlane(item % ntb);
+    const int K = d.k, nub = d.nub, ntb = (K + 15) / 16, kpad = nub * 16;
+    if ((int)blockIdx.x >= ntb * ((nub + 3) / 4)) return;   // the whole workgroup
+    const int tb = blockIdx.x % ntb, mb = (blockIdx.x / ntb) * 4 + w;
+    const float2 *V = reinterpret_cast<const float2 *>(d.V);
+    for (int t = threadIdx.x; t < 16 * kpad; t += 256) {
+        const int jj = t / kpad, ks = t % kpad, bb = tb * 16 + jj;
+        vsrt[jj][ks] = (bb < K && ks < K) ? V[(int64_t)bb * d.ldv + d.perm[ks]] : float2{0.f, 0.f};
+    }
+    __syncthreads();
+    if (mb >= nub) return;
     const int e0 = d.gm_off[mb], e1 = d.gm_off[mb + 1];
     const float2 *gm = reinterpret_cast<const float2 *>(d.GM) + lane;
-    const float2 *V = reinterpret_cast<const float2 *>(d.V);
     const int b = tb * 16 + j;
     const f4 z = {0.f, 0.f, 0.f, 0.f};
     C3 acc = {z, z, z};
@@ -189,9 +198,8 @@ __global__ void __launch_bounds__(256) k_link_effective_gram(const VrkDesc *desc
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int c = d.gm_c[e + t];   // -1: padding chunk, zero tile
-            const int kv = 4 * c + g;
             a[t] = gm[(int64_t)(e + t) * 64];
-            v[t] = (c >= 0 && kv < K && b < K) ? V[(int64_t)b * d.ldv + d.perm[kv]] : float2{0.f, 0.f};
+            v[t] = c >= 0 ? vsrt[j][4 * c + g] : float2{0.f, 0.f};
         }
         __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
 #pragma unroll
@@ -208,7 +216,7 @@ __global__ void __launch_bounds__(256) k_link_effective_gram(const VrkDesc *desc
             const int u = d.perm[su];
             float2 ev = {0.f, 0.f};
             if (d.ve[u] > d.vs[u]) {
-                const float2 q = V[(int64_t)b * d.ldv + u];
+                const float2 q = vsrt[j][su];
                 ev = float2{re[r] - xi * q.x, im[r] - xi * q.y};
             }
             reinterpret_cast<float2 *>(o.E)[(int64_t)u * o.lde + b] = ev;
@@ -225,8 +233,8 @@ hipError_t vrk_launch_link(const VrkDesc *desc, const VrkLinkOut *outs, int32_t 
     const dim3 gf((unsigned)nprob, VRK_LINK_GROUPS);
     if (mfma && dtype == 0) {
         const int nt1 = (max_k + 15) / 16;
-        hipLaunchKernelGGL(k_link_effective_gram, dim3((unsigned)((nt1 * nt1 + 3) / 4), (unsigned)nprob), dim3(256), 0,
-                           s, desc, outs);
+        hipLaunchKernelGGL(k_link_effective_gram, dim3((unsigned)(nt1 * ((nt1 + 3) / 4)), (unsigned)nprob), dim3(256),
+                           0, s, desc, outs);
         hipLaunchKernelGGL(k_link_fro<float>, gf, dim3(256), 0, s, desc, part);
         hipLaunchKernelGGL(k_link_rates<float>, dim3(nprob), dim3(256), 0, s, desc, outs, part);
         return hipGetLastError();
