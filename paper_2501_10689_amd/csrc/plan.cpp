@@ -72,6 +72,7 @@ struct ProbPlan {
     std::vector<int32_t> cp_off, cp_col, cp_tr, cp_diag;   // blocks of C on the Gram block pattern
     std::vector<uint64_t> mask;   // subarray masks (empty: interval VRs)
     bool keep_v = false;          // V goes to the workspace (caller gave none; adjoint or S = I_K shape)
+    bool stage_h = false;         // vector engine: H's VR entries staged in LDS
     std::vector<int32_t> gaps;    // (user, first antenna, length) of hidden runs inside the hulls
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
@@ -577,6 +578,16 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             return fail(VRK_EUNSUPPORTED, "vector engine needs %zu bytes of LDS (> 160 KiB) for nt=%d k=%d",
                         pl->lds, max_nt, max_k);
         }
+        // small channels: the workgroup keeps H (K x Nt) in LDS after its
+        // state, so the iterations read no H from memory; the whole
+        // allocation stays within 96 KiB
+        size_t extra = 0;
+        for (auto &q : pl->pp) {
+            const size_t hb = (size_t)q.p.k * q.p.nt * elem_bytes(o.dtype);
+            q.stage_h = pl->lds + hb <= 96 * 1024;
+            if (q.stage_h) extra = std::max(extra, hb);
+        }
+        pl->lds += extra;
     } else {
         int32_t max_nab = (max_nt + VRK_AB - 1) / VRK_AB;
         pl->ep = vrk_mfma_entries(max_kpad, waves);
@@ -853,6 +864,7 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
         d.MF = d.nmf ? base + q.o_mf : nullptr;
         d.fpos = (const int32_t *)(base + q.o_fpos);
         d.masked = q.mask.empty() ? 0 : 1;
+        d.stage_h = (pl->engine == VRK_ENGINE_VECTOR && q.stage_h) ? 1 : 0;
         d.sub_len = q.mask.empty() ? 0 : p.nt / p.n_sub;
         d.vmask = (const uint64_t *)(base + q.o_mask);
         d.ngap = (int32_t)(q.gaps.size() / 3);

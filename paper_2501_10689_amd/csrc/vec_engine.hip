@@ -224,7 +224,8 @@ __global__ void __launch_bounds__(kThreads) k_mf(const VrkDesc *descs)
 template <typename R>
 struct VecCtx {
     const VrkDesc *d;
-    const cx<R> *H;
+    const cx<R> *H;   // the channel in memory, or its VR entries staged in LDS
+    int64_t ldh;      // row stride of H
     cx<R> *x, *p, *r, *q, *phi, *s;
     R *nrm, *pre, *red;
     R xi;
@@ -239,7 +240,7 @@ __device__ void residual_rows(const VecCtx<R> &c, const int32_t *list, int n)
     const VrkDesc &d = *c.d;
     for (int t = w; t < n; t += kWaves) {
         int i = list ? list[t] : t;
-        const cx<R> *h = c.H + (int64_t)i * d.ldh;
+        const cx<R> *h = c.H + (int64_t)i * c.ldh;
         R ar = 0, ai = 0;
         for (int nn = d.vs[i] + lane; nn < d.ve[i]; nn += 64) {
             cx<R> hv = h[nn], xv = c.x[nn];
@@ -295,7 +296,7 @@ __device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
                 int u = d.col_users[e];
                 cx<R> f = c.phi[u];
                 if (f.re == 0 && f.im == 0) continue;
-                const cx<R> *h = c.H + (int64_t)u * d.ldh;
+                const cx<R> *h = c.H + (int64_t)u * c.ldh;
                 for (int n = d.vs[u] + tid; n < d.ve[u]; n += kThreads) {
                     if (!visible(d, masked, u, n)) continue;
                     cx<R> t = cmulc(f, h[n]);
@@ -316,7 +317,7 @@ __device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
                 cx<R> f = c.phi[u];
                 if (f.re == 0 && f.im == 0) continue;
                 if (n >= d.vs[u] && n < d.ve[u]) {
-                    cx<R> t = cmulc(f, c.H[(int64_t)u * d.ldh + n]);
+                    cx<R> t = cmulc(f, c.H[(int64_t)u * c.ldh + n]);
                     ar += t.re;
                     ai += t.im;
                 }
@@ -364,6 +365,18 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
     c.nrm = reinterpret_cast<R *>(c.s + K);
     c.pre = c.nrm + K;
     c.red = c.pre + K;
+    c.ldh = d.ldh;
+    if (d.stage_h) {
+        // H's VR entries into LDS after the state (16-byte aligned), rows of
+        // Nt; only entries inside each VR are ever read
+        uintptr_t o = reinterpret_cast<uintptr_t>(c.red + 4 * kWaves);
+        cx<R> *hs = reinterpret_cast<cx<R> *>((o + 15) & ~uintptr_t(15));
+        for (int u = 0; u < K; ++u)
+            for (int n = d.vs[u] + tid; n < d.ve[u]; n += kThreads) hs[(int64_t)u * N + n] = c.H[(int64_t)u * d.ldh + n];
+        c.H = hs;
+        c.ldh = N;
+        __syncthreads();
+    }
     __shared__ int sh_i;
     __shared__ R sh_g[2];
 
@@ -431,7 +444,7 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                 const int i = sh_i;
                 const cx<R> g = {sh_g[0], sh_g[1]};
                 // single-row projection (update): x += gamma conj(H[i, VR_i]), q_i += gamma
-                const cx<R> *h = c.H + (int64_t)i * d.ldh;
+                const cx<R> *h = c.H + (int64_t)i * c.ldh;
                 for (int n = d.vs[i] + tid; n < d.ve[i]; n += kThreads) {
                     cx<R> tv = cmulc(g, h[n]);
                     c.x[n].re += tv.re;
@@ -458,7 +471,7 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                     int i = d.flist[e];
                     R inv = (R)1 / c.nrm[i];
                     cx<R> f = {c.r[i].re * inv, c.r[i].im * inv};
-                    const cx<R> *h = c.H + (int64_t)i * d.ldh;
+                    const cx<R> *h = c.H + (int64_t)i * c.ldh;
                     for (int n = d.vs[i] + tid; n < d.ve[i]; n += kThreads) {
                         if (!visible(d, masked, i, n)) continue;
                         cx<R> tv = cmulc(f, h[n]);

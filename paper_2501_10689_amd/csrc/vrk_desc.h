@@ -80,6 +80,9 @@ struct VrkDesc {
     // user k sees, sub_len antennas each; gaps holds ngap triples (user,
     // first antenna, length) of hidden antennas inside the hulls
     int32_t masked, sub_len;
+    // vector engine: stage_h = 1 when the workgroup copies H's VR entries
+    // into LDS (K x Nt, row stride Nt, after its state) before iterating
+    int32_t stage_h, pad3;
     const uint64_t *vmask;
     const int32_t *gaps;
 };
