@@ -578,12 +578,15 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
             return fail(VRK_EUNSUPPORTED, "vector engine needs %zu bytes of LDS (> 160 KiB) for nt=%d k=%d",
                         pl->lds, max_nt, max_k);
         }
-        // small channels: the workgroup keeps H (K x Nt) in LDS after its
-        // state, so the iterations read no H from memory; the whole
-        // allocation stays within 96 KiB
+        // small channels: the workgroup keeps H (K x Nt) and the plan tables
+        // its steps read in LDS after its state, so the iterations wait on no
+        // memory; the whole allocation stays within 96 KiB
         size_t extra = 0;
         for (auto &q : pl->pp) {
-            const size_t hb = (size_t)q.p.k * q.p.nt * elem_bytes(o.dtype);
+            const size_t tb = 4 * (2 * (size_t)q.p.k + q.flist.size() + q.vlist.size() + q.gb_off.size() +
+                                   q.gb_users.size() + q.xoff.size() + q.xidx.size()) +
+                              (size_t)q.p.k;
+            const size_t hb = 16 + (size_t)q.p.k * q.p.nt * elem_bytes(o.dtype) + tb;
             q.stage_h = pl->lds + hb <= 96 * 1024;
             if (q.stage_h) extra = std::max(extra, hb);
         }

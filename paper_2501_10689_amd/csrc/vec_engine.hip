@@ -1,7 +1,8 @@
 // Vector engine: one workgroup (4 waves) per right-hand side, for
 // complex64 and complex128. The whole Kaczmarz solve of one symbol vector
 // runs inside one launch with x, q, r, phi in LDS; H is read from its VR
-// bands in global memory (L2-resident across the workgroups of a drop).
+// bands in global memory (L2-resident across the workgroups of a drop), or,
+// for small channels, staged in LDS with the plan tables the steps read.
 //
 // Also here: row norms, MFMA tile packing, and the adjoint right-hand side
 // and gradient kernels.
@@ -226,30 +227,41 @@ struct VecCtx {
     const VrkDesc *d;
     const cx<R> *H;   // the channel in memory, or its VR entries staged in LDS
     int64_t ldh;      // row stride of H
+    // the plan tables the iterations read, in memory or staged in LDS
+    const int32_t *vs, *ve, *flist, *vlist, *gb_off, *gb_users, *xoff, *xidx;
+    const uint8_t *inf;
     cx<R> *x, *p, *r, *q, *phi, *s;
     R *nrm, *pre, *red;
     R xi;
 };
 
 // r_i = s_i - H[i, VR_i] x[VR_i] - xi q_i for the rows of `list` (all rows
-// when list is null): one wave per row, lanes along the band.
+// when list is null): each wave takes four rows at a time, sixteen lanes per
+// row along its band, and sums over those sixteen lanes (four exchange steps
+// per row instead of six, four rows in flight).
 template <typename R>
 __device__ void residual_rows(const VecCtx<R> &c, const int32_t *list, int n)
 {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const VrkDesc &d = *c.d;
-    for (int t = w; t < n; t += kWaves) {
-        int i = list ? list[t] : t;
-        const cx<R> *h = c.H + (int64_t)i * c.ldh;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rg = lane >> 4, sl = lane & 15;
+    for (int t0 = w * 4; t0 < n; t0 += kWaves * 4) {
+        const int t = t0 + rg;
+        int i = -1;
         R ar = 0, ai = 0;
-        for (int nn = d.vs[i] + lane; nn < d.ve[i]; nn += 64) {
-            cx<R> hv = h[nn], xv = c.x[nn];
-            ar += hv.re * xv.re - hv.im * xv.im;
-            ai += hv.re * xv.im + hv.im * xv.re;
+        if (t < n) {
+            i = list ? list[t] : t;
+            const cx<R> *h = c.H + (int64_t)i * c.ldh;
+            for (int nn = c.vs[i] + sl; nn < c.ve[i]; nn += 16) {
+                cx<R> hv = h[nn], xv = c.x[nn];
+                ar += hv.re * xv.re - hv.im * xv.im;
+                ai += hv.re * xv.im + hv.im * xv.re;
+            }
         }
-        ar = wave_sum(ar);
-        ai = wave_sum(ai);
-        if (lane == 0)
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) {
+            ar += __shfl_xor(ar, m, 64);
+            ai += __shfl_xor(ai, m, 64);
+        }
+        if (sl == 0 && i >= 0)
             c.r[i] = {c.s[i].re - ar - c.xi * c.q[i].re, c.s[i].im - ai - c.xi * c.q[i].im};
     }
 }
@@ -297,7 +309,7 @@ __device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
                 cx<R> f = c.phi[u];
                 if (f.re == 0 && f.im == 0) continue;
                 const cx<R> *h = c.H + (int64_t)u * c.ldh;
-                for (int n = d.vs[u] + tid; n < d.ve[u]; n += kThreads) {
+                for (int n = c.vs[u] + tid; n < c.ve[u]; n += kThreads) {
                     if (!visible(d, masked, u, n)) continue;
                     cx<R> t = cmulc(f, h[n]);
                     c.p[n].re += t.re;
@@ -312,11 +324,11 @@ __device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
         for (int n = tid; n < d.nt; n += kThreads) {
             int g = n / VRK_GATHER_BLOCK;
             R ar = 0, ai = 0;
-            for (int e = d.gb_off[g]; e < d.gb_off[g + 1]; ++e) {
-                int u = d.gb_users[e];
+            for (int e = c.gb_off[g]; e < c.gb_off[g + 1]; ++e) {
+                int u = c.gb_users[e];
                 cx<R> f = c.phi[u];
                 if (f.re == 0 && f.im == 0) continue;
-                if (n >= d.vs[u] && n < d.ve[u]) {
+                if (n >= c.vs[u] && n < c.ve[u]) {
                     cx<R> t = cmulc(f, c.H[(int64_t)u * c.ldh + n]);
                     ar += t.re;
                     ai += t.im;
@@ -366,15 +378,43 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
     c.pre = c.nrm + K;
     c.red = c.pre + K;
     c.ldh = d.ldh;
+    c.vs = d.vs;
+    c.ve = d.ve;
+    c.flist = d.flist;
+    c.vlist = d.vlist;
+    c.gb_off = d.gb_off;
+    c.gb_users = d.gb_users;
+    c.xoff = d.xoff;
+    c.xidx = d.xidx;
+    c.inf = d.inf;
     if (d.stage_h) {
         // H's VR entries into LDS after the state (16-byte aligned), rows of
-        // Nt; only entries inside each VR are ever read
+        // Nt (only entries inside each VR are ever read), then the plan
+        // tables the iterations read, so that no step waits on memory
         uintptr_t o = reinterpret_cast<uintptr_t>(c.red + 4 * kWaves);
         cx<R> *hs = reinterpret_cast<cx<R> *>((o + 15) & ~uintptr_t(15));
         for (int u = 0; u < K; ++u)
             for (int n = d.vs[u] + tid; n < d.ve[u]; n += kThreads) hs[(int64_t)u * N + n] = c.H[(int64_t)u * d.ldh + n];
         c.H = hs;
         c.ldh = N;
+        int32_t *ts = reinterpret_cast<int32_t *>(hs + (int64_t)K * N);
+        auto stage = [&](const int32_t *src, int cnt) {
+            for (int e = tid; e < cnt; e += kThreads) ts[e] = src[e];
+            const int32_t *dst = ts;
+            ts += cnt;
+            return dst;
+        };
+        c.vs = stage(d.vs, K);
+        c.ve = stage(d.ve, K);
+        c.flist = stage(d.flist, d.nf);
+        c.vlist = stage(d.vlist, d.nv);
+        c.gb_off = stage(d.gb_off, d.ngb + 1);
+        c.gb_users = stage(d.gb_users, d.gb_off[d.ngb]);
+        c.xoff = stage(d.xoff, K + 1);
+        c.xidx = stage(d.xidx, d.xoff[K]);
+        uint8_t *ib = reinterpret_cast<uint8_t *>(ts);
+        for (int e = tid; e < K; e += kThreads) ib[e] = d.inf[e];
+        c.inf = ib;
         __syncthreads();
     }
     __shared__ int sh_i;
@@ -445,7 +485,7 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                 const cx<R> g = {sh_g[0], sh_g[1]};
                 // single-row projection (update): x += gamma conj(H[i, VR_i]), q_i += gamma
                 const cx<R> *h = c.H + (int64_t)i * c.ldh;
-                for (int n = d.vs[i] + tid; n < d.ve[i]; n += kThreads) {
+                for (int n = c.vs[i] + tid; n < c.ve[i]; n += kThreads) {
                     cx<R> tv = cmulc(g, h[n]);
                     c.x[n].re += tv.re;
                     c.x[n].im += tv.im;
@@ -456,7 +496,7 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                 }
                 __syncthreads();
                 if (variant == 2) {   // refresh only the rows of X_i (Theorem 2)
-                    residual_rows(c, d.xidx + d.xoff[i], d.xoff[i + 1] - d.xoff[i]);
+                    residual_rows(c, c.xidx + c.xoff[i], c.xoff[i + 1] - c.xoff[i]);
                     __syncthreads();
                 }
             } else if (variant == 1) {
@@ -468,11 +508,11 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                 // visible antennas are written)
                 const bool masked = d.masked != 0;
                 for (int e = 0; e < d.nf; ++e) {
-                    int i = d.flist[e];
+                    int i = c.flist[e];
                     R inv = (R)1 / c.nrm[i];
                     cx<R> f = {c.r[i].re * inv, c.r[i].im * inv};
                     const cx<R> *h = c.H + (int64_t)i * c.ldh;
-                    for (int n = d.vs[i] + tid; n < d.ve[i]; n += kThreads) {
+                    for (int n = c.vs[i] + tid; n < c.ve[i]; n += kThreads) {
                         if (!visible(d, masked, i, n)) continue;
                         cx<R> tv = cmulc(f, h[n]);
                         c.x[n].re += tv.re;
@@ -485,9 +525,9 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                 }
                 __syncthreads();
                 if (d.nv > 0) {
-                    residual_rows(c, d.vlist, d.nv);
+                    residual_rows(c, c.vlist, d.nv);
                     __syncthreads();
-                    const uint8_t *inf = d.inf;
+                    const uint8_t *inf = c.inf;
                     aggregate(c, [inf](int i) { return inf[i] == 0; }, a.schedule);
                 }
             }
