@@ -30,6 +30,30 @@ __device__ R block_sum(R v, R *red)
     return t;
 }
 
+// Two block sums with one pair of barriers (slots red[0..kWaves) and
+// red[kWaves..2 kWaves)).
+template <typename R>
+__device__ void block_sum2(R &a, R &b, R *red)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (lane == 0) {
+        red[w] = a;
+        red[kWaves + w] = b;
+    }
+    __syncthreads();
+    R ta = 0, tb = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        ta += red[i];
+        tb += red[kWaves + i];
+    }
+    a = ta;
+    b = tb;
+}
+
 // ---------------------------------------------------------------------------
 // Row norms: nrm_i = ||H[i, VR_i]||^2 + xi (the stored norms of Alg. 1), one
 // wave per row, rows spread over kNormGroups workgroups per problem; then
@@ -294,8 +318,7 @@ __device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
         }
         c.phi[i] = f;
     }
-    num = block_sum(num, c.red);
-    phin = block_sum(phin, c.red + kWaves);
+    block_sum2(num, phin, c.red);
     if (!(num > 0)) return;   // zero residual on the set: no move (uniform)
     R pn = 0;
     if (schedule == VRK_SCHED_COLOUR) {
@@ -323,16 +346,25 @@ __device__ void aggregate(const VecCtx<R> &c, InSet in_set, int schedule)
         // each thread owns antennas and gathers the users covering them
         for (int n = tid; n < d.nt; n += kThreads) {
             int g = n / VRK_GATHER_BLOCK;
+            // users covering this antenna, two at a time (independent loads),
+            // added in list order
             R ar = 0, ai = 0;
-            for (int e = c.gb_off[g]; e < c.gb_off[g + 1]; ++e) {
-                int u = c.gb_users[e];
-                cx<R> f = c.phi[u];
-                if (f.re == 0 && f.im == 0) continue;
-                if (n >= c.vs[u] && n < c.ve[u]) {
-                    cx<R> t = cmulc(f, c.H[(int64_t)u * c.ldh + n]);
-                    ar += t.re;
-                    ai += t.im;
+            const int e1 = c.gb_off[g + 1];
+            for (int e = c.gb_off[g]; e < e1; e += 2) {
+                cx<R> t0 = {0, 0}, t1 = {0, 0};
+                const int u0 = c.gb_users[e], u1 = e + 1 < e1 ? c.gb_users[e + 1] : -1;
+                const cx<R> f0 = c.phi[u0];
+                if ((f0.re != 0 || f0.im != 0) && n >= c.vs[u0] && n < c.ve[u0])
+                    t0 = cmulc(f0, c.H[(int64_t)u0 * c.ldh + n]);
+                if (u1 >= 0) {
+                    const cx<R> f1 = c.phi[u1];
+                    if ((f1.re != 0 || f1.im != 0) && n >= c.vs[u1] && n < c.ve[u1])
+                        t1 = cmulc(f1, c.H[(int64_t)u1 * c.ldh + n]);
                 }
+                ar += t0.re;
+                ai += t0.im;
+                ar += t1.re;
+                ai += t1.im;
             }
             c.p[n] = {ar, ai};
             pn += ar * ar + ai * ai;
