@@ -148,6 +148,18 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, bool
 // alternate between the two halves of the buffer (ColSums), so a sum never
 // overwrites partials that a thread may still be reading from the previous
 // one, and the sum before that was read before the previous barrier.
+// Sum over the four lanes j, j + 16, j + 32, j + 48 of a column, in every
+// one of them: gfx950's row-swap moves (16-lane rows, then 32-lane halves)
+// instead of two LDS permutes; (v_j + v_j+16) + (v_j+32 + v_j+48) in the
+// same order in all four lanes.
+__device__ __forceinline__ float col4_sum(float v)
+{
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
 template <int W>
 struct ColSums {
     float *red;   // 2 halves x 2 values x W waves x 16 columns
@@ -163,8 +175,7 @@ struct ColSums {
     {
         const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
         float *b = next();
-        v += __shfl_xor(v, 16, 64);
-        v += __shfl_xor(v, 32, 64);
+        v = col4_sum(v);
         if (lane < 16) b[w * 16 + lane] = v;
         __syncthreads();
         float s = 0.f;
@@ -177,10 +188,8 @@ struct ColSums {
     {
         const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
         float *b = next();
-        a += __shfl_xor(a, 16, 64);
-        a += __shfl_xor(a, 32, 64);
-        c += __shfl_xor(c, 16, 64);
-        c += __shfl_xor(c, 32, 64);
+        a = col4_sum(a);
+        c = col4_sum(c);
         if (lane < 16) {
             b[w * 16 + lane] = a;
             b[(W + w) * 16 + lane] = c;
