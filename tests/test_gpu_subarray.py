@@ -196,3 +196,44 @@ def test_subarray_edge_shapes(nt, n_sub, k, p, engine, dtype):
     f = np.zeros(k, bool)
     f[plan.query(0, 1)] = True
     assert np.array_equal(f, oracle.mis(d.H, d.vr_start, d.vr_len, d.xi, **kw))
+
+
+def test_subarray_autotune_keys_on_masks(tmp_path):
+    # the autotuner times candidates on masked drops, caches the winner under
+    # a key that includes the masks (other masks on the same shapes: a new
+    # entry), and the tuned plan still meets the RZF
+    import torch
+    from paper_2501_10689_amd import vrk
+    ds = _drops(3, 32)
+    def specs_of(drops):
+        return [vrk.ProblemSpec(torch.tensor(d.H, dtype=torch.complex64, device="cuda"), d.vr_start, d.vr_len,
+                                d.xi, torch.tensor(d.S, dtype=torch.complex64, device="cuda"),
+                                torch.zeros((d.nrhs, d.nt), dtype=torch.complex64, device="cuda"),
+                                torch.zeros((d.nrhs, d.k), dtype=torch.complex64, device="cuda"),
+                                vr_mask=d.vr_mask, n_sub=d.n_sub) for d in drops]
+    specs = specs_of(ds)
+    cache = str(tmp_path / "tune.txt")
+    o, ms = vrk.autotune(specs, vrk.options(variant="vr_oahk"), cache_path=cache, reps=2)
+    assert ms > 0 and len(open(cache).read().splitlines()) == 1
+    # the same hulls with one hidden subarray made visible (its channel stays
+    # zero, which is a valid input): only the masks differ
+    import copy
+    other = [copy.deepcopy(d) for d in ds]
+    for d in other:
+        for u in range(d.k):
+            m = int(d.vr_mask[u])
+            gaps = [s_ for s_ in range(d.n_sub) if m and (m >> s_) & 1 == 0
+                    and s_ * (d.nt // d.n_sub) >= d.vr_start[u]
+                    and (s_ + 1) * (d.nt // d.n_sub) <= d.vr_start[u] + d.vr_len[u]]
+            if gaps:
+                d.vr_mask[u] = np.uint64(m | (1 << gaps[0]))
+                break
+    assert any(not np.array_equal(a.vr_mask, b.vr_mask) for a, b in zip(ds, other))
+    vrk.autotune(specs_of(other), vrk.options(variant="vr_oahk"), cache_path=cache, reps=2)
+    assert len(open(cache).read().splitlines()) == 2
+    plan = vrk.Plan(specs, o)
+    plan.solve()
+    torch.cuda.synchronize()
+    for sp, d in zip(specs, ds):
+        Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi, masks=d.vr_mask, n_sub=d.n_sub)
+        assert rel_err_rows(sp.X.cpu().numpy().astype(np.complex128), Xr).max() <= 1e-4
