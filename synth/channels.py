@@ -223,7 +223,7 @@ def _rng(cfg: int, seed: int, drop: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([cfg, seed, drop])))
 
 
-# Workload recipes. Sizes follow the five evaluation shapes of this build:
+# Workload recipes (seven named shapes):
 #   plain      - one instance, Nt=256, K=16, LoS only, one QPSK vector, SNR 10 dB
 #   many_rhs   - one channel, Nt=1024, K=64, LoS + CN(0,0.1), 4096 QPSK vectors
 #   uneven     - 512 drops, Nt in {512,1024,2048}, K in [16,128], 256 vectors each
