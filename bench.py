@@ -454,8 +454,8 @@ def main():
         "timing": "eager launches" if args.eager else
                   "HIP graph of the step, replayed (eager: %.4f ms per step)" % ms_eager,
         "config": {"workload": WORKLOADS[wl], "variant": args.variant, "engine": engine,
-                   "tile_waves": int(eng[2]), "persistent": int(eng[4]), "entries_per_thread": int(eng[6]),
-                   "drops": len(drops), "vectors": B, "tol": tol},
+                   "tile_waves": int(eng[2]), "tile_waves_adjoint": int(eng[9]), "persistent": int(eng[4]),
+                   "entries_per_thread": int(eng[6]), "drops": len(drops), "vectors": B, "tol": tol},
         "orthogonal_set_mean": float(np.mean([len(plan.query(j, vrk.Q_FSET)) for j in range(len(drops))])),
         "roofline": roof,
         "bind_ms": bind_ms,

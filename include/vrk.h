@@ -237,7 +237,9 @@ typedef enum {
     VRK_Q_ENGINE = 5,    /* [engine, schedule, tile_waves, lds_bytes, persistent, grid,
                             (row, column) entries per thread of the MFMA solve,
                             RHS splits of the MFMA adjoint gradient tiles, RHS splits of
-                            the blocks of C = sum_b v_b mu_b^H of the MFMA adjoint] */
+                            the blocks of C = sum_b v_b mu_b^H of the MFMA adjoint,
+                            tile_waves of the MFMA adjoint solve (8 when every drop has
+                            at most 64 users and tile_waves is auto, else tile_waves)] */
     VRK_Q_TILES = 6      /* [residual tiles, aggregation tiles, band entries, Gram tiles] per problem */
 } vrk_query;
 int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *out, int64_t cap);

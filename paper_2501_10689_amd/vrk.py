@@ -301,9 +301,10 @@ def autotune(probs, opts: Options, cache_path=None, reps=3, stream=None):
     return o, float(ms.value)
 
 
-def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, vr_mask=None, n_sub=0, **kw):
+def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, vr_mask=None, n_sub=0, adjoint=False, **kw):
     """Plan one problem on the host only (no device memory is touched; the
-    device pointers are dummies). For inspecting the VR plan."""
+    device pointers are dummies, adjoint buffers included with adjoint=True).
+    For inspecting the VR plan."""
     vs = np.ascontiguousarray(vr_start, dtype=np.int32)
     vl = np.ascontiguousarray(vr_len, dtype=np.int32)
     vm = None if vr_mask is None else np.ascontiguousarray(vr_mask, dtype=np.uint64)
@@ -315,6 +316,8 @@ def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, vr_mask=None, n_sub=0, **
     p.vr_start, p.vr_len = vs.ctypes.data, vl.ctypes.data
     p.nrhs = nrhs
     p.S, p.lds, p.X, p.ldx = 256, k, 256, nt
+    if adjoint:
+        p.GX, p.ldgx, p.GH, p.ldgh, p.GS, p.ldgs, p.gxi = 256, nt, 256, nt, 256, k, 256
     o = options(**kw)
     ws = C.c_size_t(0)
     h = C.c_void_p()

@@ -213,3 +213,20 @@ def test_masked_validation_errors(bad):
     with pytest.raises(vrk.VrkError) as e:
         vrk.host_plan(nt, k, vs, vl, 1.0, vr_mask=masks, n_sub=n_sub, engine="vector")
     assert e.value.status == 1
+
+
+def test_adjoint_tile_shape_choice():
+    # MFMA plans with adjoint buffers and at most 64 users run the adjoint
+    # solve on 8-wave tiles when the tile size is left to the plan
+    vs = np.zeros(48, np.int32)
+    vl = np.full(48, 100, np.int32)
+    q = vrk.host_plan(256, 48, vs, vl, nrhs=32, adjoint=True, engine="mfma").query(vrk.Q_ENGINE)
+    assert q[2] == 16 and q[9] == 8
+    q = vrk.host_plan(256, 48, vs, vl, nrhs=32, adjoint=True, engine="mfma", tile_waves=16).query(vrk.Q_ENGINE)
+    assert q[2] == 16 and q[9] == 16
+    q = vrk.host_plan(256, 48, vs, vl, nrhs=32, engine="mfma").query(vrk.Q_ENGINE)
+    assert q[9] == 16                      # no adjoint buffers: one shape
+    vs2 = np.zeros(100, np.int32)
+    vl2 = np.full(100, 100, np.int32)
+    q = vrk.host_plan(256, 100, vs2, vl2, nrhs=32, adjoint=True, engine="mfma").query(vrk.Q_ENGINE)
+    assert q[9] == q[2] == 16
