@@ -16,59 +16,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-// Sum over each row of 16 lanes with DPP moves (quad swaps, half-row and
-// row mirrors): every lane of the row ends with the same value, added in the
-// same order. Doubles move as two 32-bit halves.
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-template <typename R>
-__device__ __forceinline__ R row16_sum(R v)
-{
-    v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]: lane ^ 1
-    v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]: lane ^ 2
-    v += dpp_move<0x141>(v);   // row_half_mirror: the other quad of the 8
-    v += dpp_move<0x140>(v);   // row_mirror: the other half of the 16
-    return v;
-}
-
-template <typename R>
-__device__ __forceinline__ R lane_read(R v, int lane);
-
-template <>
-__device__ __forceinline__ float lane_read(float v, int lane)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-template <>
-__device__ __forceinline__ double lane_read(double v, int lane)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over the 64 lanes: the four row sums added in row order (uniform).
-template <typename R>
-__device__ __forceinline__ R wave_sum_dpp(R v)
-{
-    v = row16_sum(v);
-    return ((lane_read(v, 0) + lane_read(v, 16)) + lane_read(v, 32)) + lane_read(v, 48);
-}
-
 template <typename R>
 __device__ R block_sum(R v, R *red)
 {
