@@ -601,37 +601,84 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_rhs(const VrkDesc *descs)
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint gradients, one workgroup per (problem, user k):
+// Adjoint gradients:
 //   GH[k, n] = sum_b V[b,k] conj(GX[b,n] - Xadj[b,n]) - GS[b,k] conj(X[b,n])
-// on the VR band of k, and (by user 0) gxi = -Re sum_{b,k} conj(GS[b,k]) V[b,k].
+// on the VR band of k, and gxi = -Re sum_{b,k} conj(GS[b,k]) V[b,k].
+// A workgroup takes kGradUsers consecutive users and kGradAnt antennas
+// (chunks slot, slot + kGradSlots, ... of its problem), so each entry of GX,
+// Xadj and X is read once per user group rather than once per user. Its
+// threads form kGradStreams rows of kGradAnt lanes; row t takes the
+// right-hand sides b = t, t + kGradStreams, ... and the rows' partial sums
+// are added in row order. Workgroup 0 of each problem also forms gxi.
 // ---------------------------------------------------------------------------
+constexpr int kGradUsers = 8;
+constexpr int kGradSlots = 64;
+constexpr int kGradAnt = 16;
+constexpr int kGradStreams = kThreads / kGradAnt;
+
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_adjoint_grads(const VrkDesc *descs)
 {
+    __shared__ cx<R> part[kGradStreams - 1][kGradUsers][kGradAnt];
     __shared__ R red[kWaves];
     const VrkDesc &d = descs[blockIdx.y];
-    const int k = blockIdx.x;
-    if (k >= d.k) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int st = threadIdx.x / kGradAnt, al = threadIdx.x % kGradAnt;
+    const int u0 = (int)(blockIdx.x / kGradSlots) * kGradUsers, slot = (int)(blockIdx.x % kGradSlots);
     const cx<R> *V = reinterpret_cast<const cx<R> *>(d.V);
     const cx<R> *GS = reinterpret_cast<const cx<R> *>(d.GS);
     const cx<R> *GX = reinterpret_cast<const cx<R> *>(d.GX);
     const cx<R> *XA = reinterpret_cast<const cx<R> *>(d.Xadj);
     const cx<R> *X = reinterpret_cast<const cx<R> *>(d.X);
-    cx<R> *GH = reinterpret_cast<cx<R> *>(d.GH) + (int64_t)k * d.ldgh;
-    for (int n = d.vs[k] + threadIdx.x; n < d.ve[k]; n += kThreads) {
-        R ar = 0, ai = 0;
-        for (int b = 0; b < d.nrhs; ++b) {
-            cx<R> v = V[(int64_t)b * d.ldv + k], mu = GS[(int64_t)b * d.ldgs + k];
-            cx<R> gx = GX[(int64_t)b * d.ldgx + n], xa = XA[(int64_t)b * d.nt + n];
-            cx<R> xv = X[(int64_t)b * d.ldx + n];
-            cx<R> t1 = cmulc(v, cx<R>{gx.re - xa.re, gx.im - xa.im});
-            cx<R> t2 = cmulc(mu, xv);
-            ar += t1.re - t2.re;
-            ai += t1.im - t2.im;
+    cx<R> *GH = reinterpret_cast<cx<R> *>(d.GH);
+    if (u0 < d.k) {
+        const int nu = min(kGradUsers, d.k - u0);
+        const int nch = (d.nt + kGradAnt - 1) / kGradAnt;
+        for (int ch = slot; ch < nch; ch += kGradSlots) {
+            const int c0 = ch * kGradAnt, n = c0 + al;
+            bool any = false;   // some user of the group has band entries in this chunk (uniform)
+            for (int e = 0; e < nu; ++e) any = any || (d.vs[u0 + e] < c0 + kGradAnt && d.ve[u0 + e] > c0);
+            if (!any) continue;
+            cx<R> acc[kGradUsers];
+#pragma unroll
+            for (int e = 0; e < kGradUsers; ++e) acc[e] = {0, 0};
+            if (n < d.nt) {
+                for (int b = st; b < d.nrhs; b += kGradStreams) {
+                    const cx<R> gx = GX[(int64_t)b * d.ldgx + n], xa = XA[(int64_t)b * d.nt + n];
+                    const cx<R> xv = X[(int64_t)b * d.ldx + n];
+                    const cx<R> df = {gx.re - xa.re, gx.im - xa.im};
+#pragma unroll
+                    for (int e = 0; e < kGradUsers; ++e)
+                        if (e < nu) {
+                            const cx<R> v = V[(int64_t)b * d.ldv + u0 + e], mu = GS[(int64_t)b * d.ldgs + u0 + e];
+                            const cx<R> t1 = cmulc(v, df), t2 = cmulc(mu, xv);
+                            acc[e].re += t1.re - t2.re;
+                            acc[e].im += t1.im - t2.im;
+                        }
+                }
+            }
+            if (st > 0)
+#pragma unroll
+                for (int e = 0; e < kGradUsers; ++e) part[st - 1][e][al] = acc[e];
+            __syncthreads();
+            if (st == 0 && n < d.nt) {
+#pragma unroll
+                for (int e = 0; e < kGradUsers; ++e) {
+                    const int u = u0 + e;
+                    if (e < nu && n >= d.vs[u] && n < d.ve[u]) {
+                        cx<R> t = acc[e];
+                        for (int q = 0; q < kGradStreams - 1; ++q) {
+                            t.re += part[q][e][al].re;
+                            t.im += part[q][e][al].im;
+                        }
+                        GH[(int64_t)u * d.ldgh + n] = t;
+                    }
+                }
+            }
+            __syncthreads();
         }
-        GH[n] = {ar, ai};
     }
-    if (k == 0) {
+    if (blockIdx.x == 0) {
         R acc = 0;
         int64_t tot = (int64_t)d.nrhs * d.k;
         for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
@@ -640,7 +687,6 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_grads(const VrkDesc *descs
             acc += mu.re * v.re + mu.im * v.im;
         }
         acc = wave_sum(acc);
-        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
         if (lane == 0) red[w] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -711,7 +757,7 @@ hipError_t vrk_launch_adjoint_rhs(const VrkDesc *desc, int32_t nprob, int32_t ma
 hipError_t vrk_launch_adjoint_grads(const VrkDesc *desc, int32_t nprob, int32_t max_k, int32_t dtype,
                                     hipStream_t s)
 {
-    dim3 grid((unsigned)max_k, (unsigned)nprob);
+    dim3 grid((unsigned)(((max_k + kGradUsers - 1) / kGradUsers) * kGradSlots), (unsigned)nprob);
     if (dtype == 1) hipLaunchKernelGGL(k_adjoint_grads<double>, grid, dim3(kThreads), 0, s, desc);
     else hipLaunchKernelGGL(k_adjoint_grads<float>, grid, dim3(kThreads), 0, s, desc);
     return hipGetLastError();

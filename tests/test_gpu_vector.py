@@ -133,16 +133,20 @@ def test_uneven_batch_vector_engine():
         assert rel_err_rows(res[j]["X"], X).max() <= 1e-4
 
 
-@pytest.mark.parametrize("dtype,tol,bound", [("c128", 1e-11, 1e-8), ("c64", 1e-6, 2e-4)])
-def test_adjoint_matches_closed_form_gradient(dtype, tol, bound):
+@pytest.mark.parametrize("dtype,tol,bound,nt,k,nrhs", [("c128", 1e-11, 1e-8, 128, 12, 5),
+                                                        ("c64", 1e-6, 2e-4, 128, 12, 5),
+                                                        ("c128", 1e-11, 1e-8, 200, 20, 70)])
+def test_adjoint_matches_closed_form_gradient(dtype, tol, bound, nt, k, nrhs):
     """Implicit-differentiation backward pass vs the oracle's closed-form
-    gradient for L = mean ||H x - s||^2 + 0.1 ||x||^2 (Nt 128, K 12)."""
+    gradient for L = mean ||H x - s||^2 + 0.1 ||x||^2 (Nt 128, K 12, 5
+    vectors; and Nt 200, K 20, 70 vectors: a ragged antenna chunk, a partial
+    user group and many right-hand sides per wave in the gradient kernel)."""
     rng = np.random.default_rng(7)
-    H, vs, vl, xi = random_problem(rng, 128, 12)
-    S = qpsk(rng, (5, 12))
+    H, vs, vl, xi = random_problem(rng, nt, k)
+    S = qpsk(rng, (nrhs, k))
     X, _ = oracle.rzf(H, vs, vl, S, xi)
     R = X @ H.T - S
-    G = 2.0 * (R @ H.conj() + 0.1 * X) / 5
+    G = 2.0 * (R @ H.conj() + 0.1 * X) / nrhs
     gH, gS, gxi = oracle.rzf_grad(H, vs, vl, S, xi, G)
     res, _ = run_plan([(H, vs, vl, S, xi)], variant="vr_oahk", engine="vector", dtype=dtype,
                       tol=tol, adjoint_g=[G])
