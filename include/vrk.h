@@ -160,6 +160,26 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
  * Must be called again if H changes. */
 vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc): vrk_plan_bind with the
+ * library's own workspace instead of the caller's. That workspace is one
+ * VRK_SCRATCH_BYTES array per device, held from the library's first use of
+ * the device until the process ends. The call binds the plan to the array
+ * of the current device (make the device the plan's buffers live on current
+ * first) and does what vrk_plan_bind does: tables copied in, row-norm and
+ * tile kernels enqueued on `stream`; it allocates nothing. Plans whose
+ * ws_bytes (from vrk_plan_create) exceed VRK_SCRATCH_BYTES get
+ * VRK_EWORKSPACE before anything is enqueued. Every plan bound this way on
+ * one device shares the array, and only the latest binding owns it: vrk_solve,
+ * vrk_solve_adjoint and vrk_link_metrics of a plan bound earlier return
+ * VRK_ESTATE until it is bound again. Work of different plans on that array
+ * must not overlap in time: a binding enqueued while another plan's solve on
+ * the array may still run (on another stream, or from another thread) races
+ * with it. Nothing in the array needs to start zeroed (every kernel writes
+ * what it later reads). */
+#define VRK_SCRATCH_BYTES ((size_t)64 << 20)
+vrk_status vrk_plan_bind_static(vrk_plan *pl, void *stream);
+
 /* Enqueues the solve of every right-hand side of every problem. Writes X,
  * V and, when non-null, per-RHS statistics laid out problem after problem
  * (sum of nrhs entries): d_iters (updates done), d_relres (final relative

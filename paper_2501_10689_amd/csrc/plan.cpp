@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <queue>
 #include <set>
@@ -120,6 +121,10 @@ struct vrk_plan {
     std::vector<uint8_t> image;
     uint8_t *d_ws = nullptr;
     bool bound = false;
+    // bound to the library's scratch array of device static_dev (-1: to a
+    // caller workspace) by the scratch binding numbered static_gen
+    int32_t static_dev = -1;
+    uint64_t static_gen = 0;
 };
 
 namespace {
@@ -784,13 +789,13 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     return VRK_OK;
 }
 
-vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+// Tables into the workspace at d_ws (checked by the caller), then the
+// row-norm and tile kernels; shared by both binding entry points.
+static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
 {
-    g_err.clear();
-    if (!pl) return fail(VRK_EINVAL, "plan null");
-    if (!d_ws || ws_bytes < pl->ws_bytes || (reinterpret_cast<uintptr_t>(d_ws) & 255))
-        return fail(VRK_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned (got %zu at %p)",
-                    pl->ws_bytes, ws_bytes, d_ws);
+    pl->bound = false;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     uint8_t *base = reinterpret_cast<uint8_t *>(d_ws);
     pl->image.assign(pl->table_end, 0);
@@ -948,6 +953,92 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
     return VRK_OK;
 }
 
+// Workspace owned by the library for callers that cannot allocate device
+// memory (vrk_plan_bind_static): one copy on every device the library runs
+// on, kept until the process ends. Host code never passes `scratch` itself
+// to the device (its name is a host-side stand-in there): it takes the
+// device address from hipGetSymbolAddress, once per device, and keeps it.
+static __device__ __align__(256) uint8_t scratch[VRK_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchSlot {
+    void *ptr = nullptr;   // device address of `scratch` on this device
+    uint64_t gen = 0;      // number of the latest binding to it
+};
+
+std::mutex g_scratch_mu;
+ScratchSlot g_scratch[kMaxDevices];
+
+// The plan's workspace is still its own: for a scratch binding, no other
+// plan has been bound to that device's scratch since.
+vrk_status check_bound(const vrk_plan *pl, const char *what)
+{
+    if (!pl->bound) return fail(VRK_ESTATE, "vrk_plan_bind or vrk_plan_bind_static must precede %s", what);
+    if (pl->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch[pl->static_dev].gen != pl->static_gen)
+            return fail(VRK_ESTATE,
+                        "%s: another plan was bound to the scratch workspace of device %d since this one; "
+                        "bind this plan again", what, pl->static_dev);
+    }
+    return VRK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    if (!pl) return fail(VRK_EINVAL, "plan null");
+    if (!d_ws || ws_bytes < pl->ws_bytes || (reinterpret_cast<uintptr_t>(d_ws) & 255))
+        return fail(VRK_EWORKSPACE, "workspace must be >= %zu bytes and 256-byte aligned (got %zu at %p)",
+                    pl->ws_bytes, ws_bytes, d_ws);
+    pl->static_dev = -1;
+    return bind_at(pl, d_ws, stream);
+}
+
+vrk_status vrk_plan_bind_static(vrk_plan *pl, void *stream)
+{
+    g_err.clear();
+    if (!pl) return fail(VRK_EINVAL, "plan null");
+    if (pl->ws_bytes > VRK_SCRATCH_BYTES)
+        return fail(VRK_EWORKSPACE,
+                    "the plan needs %zu bytes of workspace, more than the %zu-byte scratch array of "
+                    "vrk_plan_bind_static; bind a caller workspace with vrk_plan_bind instead",
+                    pl->ws_bytes, (size_t)VRK_SCRATCH_BYTES);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(VRK_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    void *ptr = nullptr;
+    uint64_t gen = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ScratchSlot &sl = g_scratch[dev];
+        if (!sl.ptr) {
+            // first binding on this device (the current one): its copy's address
+            e = hipGetSymbolAddress(&sl.ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !sl.ptr) {
+                sl.ptr = nullptr;
+                return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+            }
+        }
+        ptr = sl.ptr;
+        gen = ++sl.gen;   // plans bound to this scratch before are now stale
+    }
+    pl->static_dev = -1;
+    vrk_status st = bind_at(pl, ptr, stream);
+    if (st != VRK_OK) return st;
+    pl->static_dev = dev;
+    pl->static_gen = gen;
+    return VRK_OK;
+}
+
 static vrk_status run_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres,
                             int32_t *d_flags, int adjoint)
 {
@@ -987,7 +1078,7 @@ vrk_status vrk_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relr
 {
     g_err.clear();
     if (!pl) return fail(VRK_EINVAL, "plan null");
-    if (!pl->bound) return fail(VRK_ESTATE, "vrk_plan_bind must precede vrk_solve");
+    if (vrk_status st = check_bound(pl, "vrk_solve")) return st;
     return run_solve(pl, stream, d_iters, d_relres, d_flags, 0);
 }
 
@@ -996,7 +1087,7 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
 {
     g_err.clear();
     if (!pl) return fail(VRK_EINVAL, "plan null");
-    if (!pl->bound) return fail(VRK_ESTATE, "vrk_plan_bind must precede vrk_solve_adjoint");
+    if (vrk_status st = check_bound(pl, "vrk_solve_adjoint")) return st;
     if (!pl->adjoint_ready) return fail(VRK_ESTATE, "problems were planned without adjoint buffers");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(pl->d_ws + pl->o_desc);
@@ -1028,7 +1119,7 @@ vrk_status vrk_link_metrics(vrk_plan *pl, const vrk_link_out *out, void *stream)
 {
     g_err.clear();
     if (!pl || !out) return fail(VRK_EINVAL, "plan or output table null");
-    if (!pl->bound) return fail(VRK_ESTATE, "vrk_plan_bind must precede vrk_link_metrics");
+    if (vrk_status st = check_bound(pl, "vrk_link_metrics")) return st;
     const int32_t nprob = (int32_t)pl->pp.size();
     std::vector<VrkLinkOut> tab(nprob);
     for (int32_t i = 0; i < nprob; ++i) {

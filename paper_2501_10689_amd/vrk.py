@@ -76,6 +76,8 @@ def lib():
                                       C.POINTER(vp)]
         L.vrk_plan_bind.restype = C.c_int
         L.vrk_plan_bind.argtypes = [vp, vp, C.c_size_t, vp]
+        L.vrk_plan_bind_static.restype = C.c_int
+        L.vrk_plan_bind_static.argtypes = [vp, vp]
         L.vrk_solve.restype = C.c_int
         L.vrk_solve.argtypes = [vp, vp, vp, vp, vp]
         L.vrk_solve_adjoint.restype = C.c_int
@@ -151,11 +153,16 @@ class ProblemSpec:
     n_sub: int = 0
 
 
+SCRATCH_BYTES = 64 << 20   # VRK_SCRATCH_BYTES of include/vrk.h
+
+
 class Plan:
     """Owns a vrk_plan, its workspace and references to every buffer it
-    records. ``probs`` is a list of ProblemSpec."""
+    records. ``probs`` is a list of ProblemSpec. With ``static=True`` no
+    workspace is allocated: the plan is bound to the library's scratch array
+    on the current device (vrk_plan_bind_static)."""
 
-    def __init__(self, probs, opts: Options, device=None, stream=None):
+    def __init__(self, probs, opts: Options, device=None, stream=None, static=False):
         import torch
         self._torch = torch
         self.probs = list(probs)
@@ -191,9 +198,13 @@ class Plan:
         self.ws_bytes = int(ws.value)
         self.nrhs_total = sum(int(arr[i].nrhs) for i in range(len(self.probs)))
         self.device = device if device is not None else (self.probs[0].H.device)
-        self.workspace = torch.empty(max(self.ws_bytes, 256) + 256, dtype=torch.uint8, device=self.device)
-        off = (-self.workspace.data_ptr()) % 256
-        self._ws_ptr = self.workspace.data_ptr() + off
+        self.static = bool(static)
+        if self.static:
+            self.workspace, self._ws_ptr = None, None
+        else:
+            self.workspace = torch.empty(max(self.ws_bytes, 256) + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.workspace.data_ptr()) % 256
+            self._ws_ptr = self.workspace.data_ptr() + off
         self.bind(stream)
 
     def _stream(self, stream):
@@ -202,7 +213,10 @@ class Plan:
         return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
     def bind(self, stream=None):
-        _check(lib().vrk_plan_bind(self._h, self._ws_ptr, self.ws_bytes, self._stream(stream)))
+        if self.static:
+            _check(lib().vrk_plan_bind_static(self._h, self._stream(stream)))
+        else:
+            _check(lib().vrk_plan_bind(self._h, self._ws_ptr, self.ws_bytes, self._stream(stream)))
 
     def stats_buffers(self):
         t = self._torch
