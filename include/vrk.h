@@ -260,7 +260,11 @@ typedef enum {
                             the blocks of C = sum_b v_b mu_b^H of the MFMA adjoint,
                             tile_waves of the MFMA adjoint solve (8 when every drop has
                             at most 64 users and tile_waves is auto, else tile_waves)] */
-    VRK_Q_TILES = 6      /* [residual tiles, aggregation tiles, band entries, Gram tiles] per problem */
+    VRK_Q_TILES = 6,     /* [residual tiles, aggregation tiles, band entries, Gram tiles] per problem */
+    VRK_Q_GRAD = 7       /* MFMA adjoint gradient of the whole plan: [band tiles, RHS splits of a band
+                            tile, blocks of C, RHS splits of a C block, runs of the reduction kernel,
+                            longest run (band tiles one reduction workgroup takes)]; zeros
+                            without adjoint buffers or on the vector engine */
 } vrk_query;
 int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *out, int64_t cap);
 

@@ -8,7 +8,8 @@
  * Plain, slow and written to be checked against the paper by eye:
  * std C11 `double complex`, no blocking, no fusion, no reordering beyond
  * what the cited definitions state. OpenMP appears only as an outer loop
- * over independent right-hand sides.
+ * over independent right-hand sides, or over users where the gradient sums
+ * over right-hand sides (each sum still taken in right-hand-side order).
  *
  * Orientation. H is K x Nt, row-major, row k = what user k sees (the
  * paper's channel matrix is its conjugate transpose). The augmented system
@@ -355,28 +356,44 @@ int orc_rzf_grad(const orc_problem *p, int32_t nrhs, const cplx *S, int64_t lds,
     gram(p, M);
     int st = cholesky(K, M, L);
     if (st != ORC_OK) { free(M); free(L); return st; }
-    for (int k = 0; k < K; ++k)
-        for (int n = 0; n < N; ++n) gH[k * ldgh + n] = 0;
-    double acc_xi = 0.0;
-    cplx *v = malloc(sizeof(cplx) * K), *x = malloc(sizeof(cplx) * N);
-    cplx *hg = malloc(sizeof(cplx) * K), *mu = malloc(sizeof(cplx) * K), *xh = malloc(sizeof(cplx) * N);
+    /* per right-hand side (independent): v_b, x_b, mu_b, xh_b */
+    cplx *Vb = malloc(sizeof(cplx) * (size_t)nrhs * K), *Xb = malloc(sizeof(cplx) * (size_t)nrhs * N);
+    cplx *MUb = malloc(sizeof(cplx) * (size_t)nrhs * K), *XHb = malloc(sizeof(cplx) * (size_t)nrhs * N);
+#pragma omp parallel for schedule(static)
     for (int b = 0; b < nrhs; ++b) {
         const cplx *s = S + (int64_t)b * lds, *g = G + (int64_t)b * ldg;
+        cplx *v = Vb + (size_t)b * K, *x = Xb + (size_t)b * N;
+        cplx *mu = MUb + (size_t)b * K, *xh = XHb + (size_t)b * N;
+        cplx *hg = malloc(sizeof(cplx) * K);
         chol_solve(K, L, s, v);
         apply_hh(p, v, x);
         apply_h(p, g, hg);
         chol_solve(K, L, hg, mu);
         apply_hh(p, mu, xh);
-        for (int k = 0; k < K; ++k) {
-            gS[(int64_t)b * ldgs + k] = mu[k];
-            acc_xi -= creal(conj(mu[k]) * v[k]);
+        free(hg);
+    }
+    /* sums over the right-hand sides, b = 0, 1, ... in order for every entry
+     * (users are independent, so they may run in parallel) */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < K; ++k) {
+        for (int n = 0; n < N; ++n) gH[k * ldgh + n] = 0;
+        for (int b = 0; b < nrhs; ++b) {
+            const cplx *g = G + (int64_t)b * ldg, *x = Xb + (size_t)b * N, *xh = XHb + (size_t)b * N;
+            const cplx vk = Vb[(size_t)b * K + k], muk = MUb[(size_t)b * K + k];
             for (int32_t n = p->vs[k]; n < vr_end(p, k); ++n)
                 if (seen(p, k, n))
-                    gH[k * ldgh + n] += v[k] * conj(g[n] - xh[n]) - mu[k] * conj(x[n]);
+                    gH[k * ldgh + n] += vk * conj(g[n] - xh[n]) - muk * conj(x[n]);
         }
     }
+    double acc_xi = 0.0;
+    for (int b = 0; b < nrhs; ++b)
+        for (int k = 0; k < K; ++k) {
+            const cplx mu = MUb[(size_t)b * K + k];
+            gS[(int64_t)b * ldgs + k] = mu;
+            acc_xi -= creal(conj(mu) * Vb[(size_t)b * K + k]);
+        }
     *gxi = acc_xi;
-    free(v); free(x); free(hg); free(mu); free(xh); free(M); free(L);
+    free(Vb); free(Xb); free(MUb); free(XHb); free(M); free(L);
     return ORC_OK;
 }
 

@@ -21,8 +21,10 @@ class KaczmarzRZF(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, H, S, xi, vr_start, vr_len, opts, vr_mask=None, n_sub=0):
-        if not H.is_cuda:
+        if not H.is_cuda or not S.is_cuda:
             raise ValueError("KaczmarzRZF needs device tensors")
+        if H.dtype not in (torch.complex64, torch.complex128) or S.dtype != H.dtype:
+            raise ValueError("H and S must share one complex dtype (got %s and %s)" % (H.dtype, S.dtype))
         dtype = "c128" if H.dtype == torch.complex128 else "c64"
         xi_val = float(xi) if not torch.is_tensor(xi) else float(xi.detach().cpu())
         Hc = H.detach().contiguous()

@@ -1169,6 +1169,13 @@ int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *
              pl->csplit, pl->engine == VRK_ENGINE_MFMA ? pl->waves_adj : pl->waves};
         break;
     case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band, (int32_t)q.n_gm}; break;
+    case VRK_Q_GRAD: {
+        int32_t rmax = 0;
+        for (const int4 &r : pl->gruns) rmax = std::max(rmax, r.y);
+        v = {(int32_t)pl->gtiles.size(), pl->gsplit, (int32_t)pl->ctiles.size() / std::max(1, pl->csplit),
+             pl->csplit, (int32_t)pl->gruns.size(), rmax};
+        break;
+    }
     default: return -1;
     }
     int64_t n = (int64_t)v.size();

@@ -22,7 +22,7 @@ ENGINES = {"auto": 0, "vector": 1, "mfma": 2}
 SCHEDULES = {"auto": 0, "gather": 1, "colour": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace", 4: "HIP error", 5: "call order"}
 F_CONVERGED, F_NONFINITE, F_MAXITER = 1, 2, 4
-Q_PERM, Q_FSET, Q_COLOUR, Q_XOFF, Q_XIDX, Q_ENGINE, Q_TILES = range(7)
+Q_PERM, Q_FSET, Q_COLOUR, Q_XOFF, Q_XIDX, Q_ENGINE, Q_TILES, Q_GRAD = range(8)
 
 
 class Problem(C.Structure):
@@ -156,6 +156,47 @@ class ProblemSpec:
 SCRATCH_BYTES = 64 << 20   # VRK_SCRATCH_BYTES of include/vrk.h
 
 
+def _validate_spec(sp: ProblemSpec, i: int, opts: Options):
+    """What the C side cannot see from raw pointers: every buffer a device
+    tensor on H's device, of the plan's element type, rows contiguous
+    (unit inner stride), shapes consistent with H (K x Nt) and S (B x K),
+    and one VR entry per user. Raises ValueError; nothing reaches the
+    library otherwise."""
+    import torch
+    cdt = torch.complex128 if opts.dtype == DTYPES["c128"] else torch.complex64
+    H = sp.H
+    if not torch.is_tensor(H) or H.dim() != 2:
+        raise ValueError("problem %d: H must be a 2-D torch tensor" % i)
+    K, N = int(H.shape[0]), int(H.shape[1])
+    B = int(sp.S.shape[0]) if sp.S is not None else 0
+    shapes = {"H": (K, N), "S": (B, K), "X": (B, N), "V": (B, K), "GX": (B, N), "GH": (K, N), "GS": (B, K)}
+    for name, want in shapes.items():
+        t = getattr(sp, name)
+        if t is None:
+            if name in ("H", "S", "X") and (name == "H" or B > 0):
+                raise ValueError("problem %d: %s is required" % (i, name))
+            continue
+        if not torch.is_tensor(t) or not t.is_cuda:
+            raise ValueError("problem %d: %s must be a device (CUDA) tensor" % (i, name))
+        if t.device != H.device:
+            raise ValueError("problem %d: %s is on %s, H on %s" % (i, name, t.device, H.device))
+        if t.dtype != cdt:
+            raise ValueError("problem %d: %s is %s, the plan computes in %s" % (i, name, t.dtype, cdt))
+        if t.dim() != 2 or tuple(t.shape) != want:
+            raise ValueError("problem %d: %s has shape %s, expected %s" % (i, name, tuple(t.shape), want))
+        if t.numel() and (t.stride(1) != 1 or t.stride(0) < want[1]):
+            raise ValueError("problem %d: %s rows must be contiguous (strides %s)" % (i, name, t.stride()))
+    if sp.gxi is not None:
+        g = sp.gxi
+        if not torch.is_tensor(g) or not g.is_cuda or g.device != H.device or g.dtype != torch.float64 \
+                or g.numel() < 1:
+            raise ValueError("problem %d: gxi must be a float64 device tensor on H's device" % i)
+    if len(np.atleast_1d(sp.vr_start)) != K or len(np.atleast_1d(sp.vr_len)) != K:
+        raise ValueError("problem %d: vr_start and vr_len need one entry per user (K = %d)" % (i, K))
+    if sp.vr_mask is not None and len(np.atleast_1d(sp.vr_mask)) != K:
+        raise ValueError("problem %d: vr_mask needs one entry per user (K = %d)" % (i, K))
+
+
 class Plan:
     """Owns a vrk_plan, its workspace and references to every buffer it
     records. ``probs`` is a list of ProblemSpec. With ``static=True`` no
@@ -168,6 +209,8 @@ class Plan:
         self.probs = list(probs)
         self.opts = opts
         self._keep = []
+        for i, sp in enumerate(self.probs):
+            _validate_spec(sp, i, opts)
         arr = (Problem * len(self.probs))()
         for i, sp in enumerate(self.probs):
             vs = np.ascontiguousarray(sp.vr_start, dtype=np.int32)
@@ -297,6 +340,8 @@ def autotune(probs, opts: Options, cache_path=None, reps=3, stream=None):
     """Run vrk_autotune on the batch (device timing; overwrites X and V).
     Returns (tuned Options, ms per solve)."""
     import torch
+    for i, sp in enumerate(probs):
+        _validate_spec(sp, i, opts)
     arr, keep = _problem_array(probs)
     o = Options()
     C.pointer(o)[0] = opts

@@ -68,3 +68,34 @@ def rel_err_rows(X, Xref):
     num = np.linalg.norm(X - Xref, axis=1)
     den = np.maximum(np.linalg.norm(Xref, axis=1), 1e-300)
     return num / den
+
+
+def check_grads(g, ref, mask, norm_bound, entry_bound=None, label=""):
+    """Gradient parity against the oracle's closed form (gH, gS, gxi) =
+    ref, on the band entries `mask` of H:
+      - in norm: ||dGH|| <= b ||gH||, ||dGS|| <= b ||gS||, |dgxi| <= b |gxi|
+        with b = norm_bound;
+      - entry by entry: |dGH[k, n]| <= e max|gH| on every band entry and
+        ||dGH[k, :]|| <= e max_k ||gH[k, :]|| for every user row, with
+        e = entry_bound (default norm_bound), so an error confined to one
+        band tile, antenna block or user block fails;
+      - per vector: ||dGS[b, :]|| <= e ||gS[b, :]|| for every right-hand
+        side b (GS = mu_b, a solve output like x);
+      - zero off the band (GH is written only on VR entries).
+    Returns the measured ratios."""
+    gH, gS, gxi = ref
+    e = norm_bound if entry_bound is None else entry_bound
+    dH = np.where(mask, g["GH"] - gH, 0)
+    r = {
+        "gh_norm": np.linalg.norm(dH) / np.linalg.norm(gH[mask]),
+        "gs_norm": np.linalg.norm(g["GS"] - gS) / np.linalg.norm(gS),
+        "gxi": abs(g["gxi"] - gxi) / abs(gxi),
+        "gh_entry": np.abs(dH).max() / np.abs(gH[mask]).max(),
+        "gh_row": (np.linalg.norm(dH, axis=1) / np.linalg.norm(gH, axis=1).max()).max(),
+        "gs_vec": (np.linalg.norm(g["GS"] - gS, axis=1) / np.maximum(np.linalg.norm(gS, axis=1), 1e-300)).max(),
+    }
+    print("grad parity %s: %s" % (label, " ".join("%s %.2e" % kv for kv in r.items())), flush=True)
+    assert r["gh_norm"] <= norm_bound and r["gs_norm"] <= norm_bound and r["gxi"] <= norm_bound, (label, r)
+    assert r["gh_entry"] <= e and r["gh_row"] <= e and r["gs_vec"] <= e, (label, r)
+    assert not np.asarray(g["GH"])[~mask].any(), label
+    return r

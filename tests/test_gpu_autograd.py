@@ -61,3 +61,10 @@ def test_autograd_matches_closed_form_adjoint_workload(variant):
     print(variant, "rel err dH %.2e dS %.2e dxi %.2e" % (eH, eS, exi))
     assert eH <= 1e-4 and eS <= 1e-4 and exi <= 1e-4
     assert not Ht.grad.cpu().numpy()[~m].any()
+    # entry by entry (relative to the largest band entry), per user row and
+    # per right-hand side
+    dH = np.where(m, Ht.grad.cpu().numpy() - gH, 0)
+    dS = St.grad.cpu().numpy() - gS
+    assert np.abs(dH).max() <= 5e-4 * np.abs(gH[m]).max()
+    assert np.linalg.norm(dH, axis=1).max() <= 5e-4 * np.linalg.norm(gH, axis=1).max()
+    assert (np.linalg.norm(dS, axis=1) / np.linalg.norm(gS, axis=1)).max() <= 5e-4

@@ -142,3 +142,33 @@ def test_autotune_picks_a_valid_config_and_caches(tmp_path):
     for sp, d in zip(specs, ds):
         Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
         assert rel_err_rows(sp.X.cpu().numpy().astype(np.complex128), Xr).max() <= 1e-4
+
+
+def test_binding_rejects_mismatched_buffers():
+    """Host-side checks of the Python binding (nothing is launched): element
+    type against the plan's, shapes against H and S, unit inner stride, the
+    VR arrays' length; KaczmarzRZF rejects S of another dtype than H."""
+    import torch
+    from paper_2501_10689_amd import vrk
+    from paper_2501_10689_amd.autograd import rzf_precode
+    K, N, B = 4, 64, 3
+    H = torch.zeros((K, N), dtype=torch.complex64, device="cuda")
+    S = torch.zeros((B, K), dtype=torch.complex64, device="cuda")
+    X = torch.zeros((B, N), dtype=torch.complex64, device="cuda")
+    vs, vl = np.zeros(K, np.int32), np.full(K, 8, np.int32)
+    bad = [
+        dict(S=S.to(torch.complex128)),                                   # dtype
+        dict(X=torch.zeros((B, N + 1), dtype=torch.complex64, device="cuda")),   # shape
+        dict(X=torch.zeros((N, B), dtype=torch.complex64, device="cuda").t()),   # inner stride
+        dict(GX=X, GH=torch.zeros((K, N), dtype=torch.complex64, device="cuda"),
+             GS=torch.zeros((B, K + 1), dtype=torch.complex64, device="cuda"),
+             gxi=torch.zeros(1, dtype=torch.float64, device="cuda")),     # GS shape
+        dict(vr_len=np.full(K + 1, 8, np.int32)),                         # VR arrays
+    ]
+    for kw in bad:
+        args = dict(H=H, vr_start=vs, vr_len=vl, xi=1.0, S=S, X=X)
+        args.update(kw)
+        with pytest.raises(ValueError):
+            vrk.Plan([vrk.ProblemSpec(**args)], vrk.options(dtype="c64"))
+    with pytest.raises(ValueError):
+        rzf_precode(H, S.to(torch.complex128), 1.0, vs, vl)

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import rel_err_rows, run_plan
+from tests.gpu_util import check_grads, rel_err_rows, run_plan
 from tests.helpers import qpsk, random_problem
 
 pytestmark = pytest.mark.gpu
@@ -15,12 +15,14 @@ pytestmark = pytest.mark.gpu
 VARIANTS = ["grk", "ahk", "vr_ogrk", "vr_oahk"]
 
 
+@pytest.mark.parametrize("snr", [0.0, 10.0, 20.0])
 @pytest.mark.parametrize("waves", [8, 16])
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_many_rhs_ragged_tiles(variant, waves):
-    """Nt 1024, K 64 with 37 vectors: two full tiles of 16 and a ragged tail,
-    with 8 and 16 waves per workgroup."""
-    d = synth.make_workload("many_rhs", nrhs=37)[0]
+def test_many_rhs_ragged_tiles(variant, waves, snr):
+    """Nt 1024, K 64 with 37 vectors at SNR 0, 10 and 20 dB (the 20 dB point
+    has the smallest xi, so the worst-conditioned Gram matrix): two full tiles
+    of 16 and a ragged tail, with 8 and 16 waves per workgroup."""
+    d = synth.make_workload("many_rhs", nrhs=37, snr_db=snr)[0]
     res, plan = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, engine="mfma",
                          tile_waves=waves)
     assert plan.query(0, 5)[0] == 2   # MFMA engine chosen
@@ -144,9 +146,7 @@ def test_adjoint_mfma_matches_closed_form(nt, k, nrhs):
     g = res[0]
     m = np.abs(H) > 0
     assert np.all(g["adj_flags"] == oracle.F_CONVERGED)
-    assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m])
-    assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS)
-    assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
+    check_grads(g, (gH, gS, gxi), m, 2e-4)
 
 
 @pytest.mark.parametrize("waves", [8, 16])
@@ -183,10 +183,7 @@ def test_adjoint_mfma_rhs_split():
     g = res[0]
     m = np.abs(H) > 0
     assert np.all(g["adj_flags"] == oracle.F_CONVERGED)
-    assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m])
-    assert not g["GH"][~m].any()
-    assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS)
-    assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
+    check_grads(g, (gH, gS, gxi), m, 2e-4)
 
 
 def test_adjoint_mfma_uneven_batch():
@@ -203,9 +200,7 @@ def test_adjoint_mfma_uneven_batch():
     for jd, (gH, gS, gxi) in enumerate(refs):
         g = res[jd]
         m = np.abs(drops[jd][0]) > 0
-        assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m]), jd
-        assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS), jd
-        assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi), jd
+        check_grads(g, (gH, gS, gxi), m, 2e-4, label="drop %d" % jd)
 
 
 @pytest.mark.parametrize("variant", ["vr_oahk", "ahk", "grk", "vr_ogrk"])
@@ -232,9 +227,7 @@ def test_large_shape_adjoint():
                       adjoint_g=[G])
     g = res[0]
     m = np.abs(d.H) > 0
-    assert np.linalg.norm((g["GH"] - gH)[m]) <= 2e-4 * np.linalg.norm(gH[m])
-    assert np.linalg.norm(g["GS"] - gS) <= 2e-4 * np.linalg.norm(gS)
-    assert abs(g["gxi"] - gxi) <= 2e-4 * abs(gxi)
+    check_grads(g, (gH, gS, gxi), m, 2e-4)
 
 
 @pytest.mark.parametrize("engine", ["mfma", "vector"])
@@ -261,3 +254,84 @@ def test_rebind_and_resolve_are_bitwise_deterministic(engine):
     b, _ = run_plan(drops, variant="vr_oahk", engine=engine, tol=1e-6)
     for x, y in zip(a, b):
         assert np.array_equal(x["X"], y["X"]) and np.array_equal(x["V"], y["V"])
+
+
+@pytest.mark.parametrize("variant", ["grk", "vr_ogrk"])
+@pytest.mark.parametrize("rule", ["max", "residual"])
+def test_greedy_rules_mfma(variant, rule):
+    """The greedy-Kaczmarz (max) and printed residual-proportional rules on
+    the MFMA engine: Nt 1024, K 64, 37 vectors, every x within 1e-4 of the
+    FP64 RZF. The max rule is deterministic: both greedy variants take the
+    same rows, so they agree bit for bit."""
+    d = synth.make_workload("many_rhs", nrhs=37)[0]
+    res, _ = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, select=rule, engine="mfma")
+    X, V = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+    g = res[0]
+    assert np.all(g["flags"] == oracle.F_CONVERGED)
+    assert rel_err_rows(g["X"], X).max() <= 1e-4
+    assert rel_err_rows(g["V"], V).max() <= 1e-4
+    if rule == "max":
+        other = "vr_ogrk" if variant == "grk" else "grk"
+        r2, _ = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=other, select=rule, engine="mfma")
+        assert np.array_equal(r2[0]["X"], g["X"]) and np.array_equal(r2[0]["iters"], g["iters"])
+
+
+def _loss_grad(d, X, n_vec):
+    """Incoming gradient of L = (1/n_vec) sum ||H x - s||^2 + 0.1 ||x||^2 on
+    X (2 dL/d conj x), from the oracle's X."""
+    return 2.0 * ((X @ d.H.T - d.S) @ d.H.conj() + 0.1 * X) / n_vec
+
+
+def test_adjoint_full_workload_reduction_runs():
+    """The adjoint workload as benchmarked: 256 drops of Nt 1024, K 64 with
+    64 QPSK vectors each, forward + adjoint in one launch each. The gradient
+    reduction takes runs of many band tiles per workgroup here (asserted), a
+    path one-drop tests never reach. Every x within 1e-4 of the FP64 RZF and
+    every drop's dL/dH, dL/ds, dL/dxi against the closed form, entry by entry."""
+    ds = synth.make_workload("adjoint")
+    n_vec = sum(d.nrhs for d in ds)
+    drops, Gs, Xs = [], [], []
+    for d in ds:
+        X, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+        drops.append((d.H, d.vr_start, d.vr_len, d.S, d.xi))
+        Gs.append(_loss_grad(d, X, n_vec))
+        Xs.append(X)
+    res, plan = run_plan(drops, variant="vr_oahk", engine="mfma", tol=1e-6, adjoint_g=Gs)
+    gq = plan.query(0, 7)
+    print("gradient plan: band tiles %d, splits %d, C blocks %d, runs %d, longest run %d"
+          % (gq[0], gq[1], gq[2], gq[4], gq[5]))
+    assert gq[5] > 1
+    worst = {}
+    for jd, d in enumerate(ds):
+        g = res[jd]
+        assert np.all(g["flags"] == oracle.F_CONVERGED) and np.all(g["adj_flags"] == oracle.F_CONVERGED), jd
+        assert rel_err_rows(g["X"], Xs[jd]).max() <= 1e-4, jd
+        ref = oracle.rzf_grad(d.H, d.vr_start, d.vr_len, d.S, d.xi, Gs[jd])
+        r = check_grads(g, ref, np.abs(d.H) > 0, 2e-4, label="drop %d" % jd)
+        worst = {k: max(v, worst.get(k, 0.0)) for k, v in r.items()}
+    print("worst over drops:", worst)
+
+
+def test_large_adjoint_reduction_runs():
+    """Six drops of the large workload at full size (Nt 4096, K 256, VR
+    U[256, 1024], 1024 16-QAM vectors each): enough band tiles that each
+    reduction workgroup takes runs of two or more. Forward every x within
+    1e-4, adjoint against the closed form entry by entry."""
+    ds = synth.make_workload("large", drops=6)
+    n_vec = sum(d.nrhs for d in ds)
+    drops, Gs, Xs = [], [], []
+    for d in ds:
+        X, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+        drops.append((d.H, d.vr_start, d.vr_len, d.S, d.xi))
+        Gs.append(_loss_grad(d, X, n_vec))
+        Xs.append(X)
+    res, plan = run_plan(drops, variant="vr_oahk", engine="mfma", tol=1e-6, adjoint_g=Gs)
+    gq = plan.query(0, 7)
+    print("gradient plan: band tiles %d, splits %d, runs %d, longest run %d" % (gq[0], gq[1], gq[4], gq[5]))
+    assert gq[5] > 1
+    for jd, d in enumerate(ds):
+        g = res[jd]
+        assert np.all(g["flags"] == oracle.F_CONVERGED) and np.all(g["adj_flags"] == oracle.F_CONVERGED), jd
+        assert rel_err_rows(g["X"], Xs[jd]).max() <= 1e-4, jd
+        ref = oracle.rzf_grad(d.H, d.vr_start, d.vr_len, d.S, d.xi, Gs[jd])
+        check_grads(g, ref, np.abs(d.H) > 0, 2e-4, label="large drop %d" % jd)

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import rel_err_rows, run_plan
+from tests.gpu_util import check_grads, rel_err_rows, run_plan
 
 pytestmark = pytest.mark.gpu
 
@@ -111,9 +111,7 @@ def test_subarray_adjoint_matches_closed_form(engine, dtype, tol, bound):
     U = oracle.mask_indicator(d.vr_mask, d.nt, d.n_sub).astype(bool)
     assert np.all(g["adj_flags"] == oracle.F_CONVERGED)
     assert np.all(g["GH"][~U] == 0)
-    assert np.linalg.norm(g["GH"] - gH) <= bound * np.linalg.norm(gH)
-    assert np.linalg.norm(g["GS"] - gS) <= bound * np.linalg.norm(gS)
-    assert abs(g["gxi"] - gxi) <= bound * abs(gxi)
+    check_grads(g, (gH, gS, gxi), U, bound)
 
 
 def test_subarray_autograd_masks_the_channel_gradient():
@@ -138,6 +136,9 @@ def test_subarray_autograd_masks_the_channel_gradient():
     got = Hb.grad.cpu().numpy()
     assert np.all(got[oracle.mask_indicator(d.vr_mask, d.nt, d.n_sub) == 0] == 0)
     assert np.linalg.norm(got - gH) <= 2e-4 * np.linalg.norm(gH)
+    # entry by entry and per user row, relative to the largest entry / row
+    assert np.abs(got - gH).max() <= 1e-3 * np.abs(gH).max()
+    assert (np.linalg.norm(got - gH, axis=1)).max() <= 1e-3 * np.linalg.norm(gH, axis=1).max()
 
 
 def test_subarray_full_workload_every_vector():

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import rel_err_rows, run_plan
+from tests.gpu_util import check_grads, rel_err_rows, run_plan
 from tests.helpers import qpsk, random_problem
 
 pytestmark = pytest.mark.gpu
@@ -16,12 +16,12 @@ VARIANTS = ["grk", "ahk", "vr_ogrk", "vr_oahk"]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("rule", ["baiwu", "max"])
+@pytest.mark.parametrize("rule", ["baiwu", "max", "residual"])
 def test_plain_c128_matches_oracle_trajectory(variant, rule):
     """Plain instance (Nt 256, K 16, LoS, one QPSK vector, SNR 10 dB) in
     complex128 to relative residual 1e-10: same iterate as the FP64 oracle
     run with the same rule and Philox stream, and the RZF x to 1e-9."""
-    if rule == "max" and variant in ("ahk", "vr_oahk"):
+    if rule != "baiwu" and variant in ("ahk", "vr_oahk"):
         pytest.skip("selection rule unused by aggregated variants")
     d = synth.make_workload("plain")[0]
     res, _ = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, select=rule,
@@ -152,6 +152,4 @@ def test_adjoint_matches_closed_form_gradient(dtype, tol, bound, nt, k, nrhs):
                       tol=tol, adjoint_g=[G])
     g = res[0]
     mask = np.abs(H) > 0
-    assert np.linalg.norm((g["GH"] - gH)[mask]) <= bound * np.linalg.norm(gH[mask])
-    assert np.linalg.norm(g["GS"] - gS) <= bound * np.linalg.norm(gS)
-    assert abs(g["gxi"] - gxi) <= bound * abs(gxi)
+    check_grads(g, (gH, gS, gxi), mask, bound)

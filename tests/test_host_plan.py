@@ -230,3 +230,16 @@ def test_adjoint_tile_shape_choice():
     vl2 = np.full(100, 100, np.int32)
     q = vrk.host_plan(256, 100, vs2, vl2, nrhs=32, adjoint=True, engine="mfma").query(vrk.Q_ENGINE)
     assert q[9] == q[2] == 16
+
+
+def test_binding_rejects_host_tensors_before_the_library():
+    """The Python binding checks what raw pointers cannot show: a host
+    (CPU) tensor for a device buffer is a ValueError, raised before any
+    call into libvrk.so."""
+    import torch
+    H = torch.zeros((4, 32), dtype=torch.complex64)
+    S = torch.zeros((3, 4), dtype=torch.complex64)
+    X = torch.zeros((3, 32), dtype=torch.complex64)
+    sp = vrk.ProblemSpec(H, np.zeros(4, np.int32), np.full(4, 8, np.int32), 1.0, S, X)
+    with pytest.raises(ValueError, match="device"):
+        vrk.Plan([sp], vrk.options())
