@@ -1,15 +1,16 @@
 #!/usr/bin/env python3
 """Throughput benchmark: precoded vectors/s on one MI355X.
 
-Default workload (--workload many_rhs): one channel drop (Nt = 1024
-antennas, K = 64 users, VR lengths uniform in [256, 512] at uniform starts,
-LoS spherical wave at 28 GHz plus CN(0, 0.1) scattering on the VR entries)
-with 4096 QPSK symbol vectors sharing it, SNR 10 dB (xi = K / SNR),
-complex64, relative-residual tolerance 1e-5. The other workloads:
+Default workload (--workload large): 64 channel drops of Nt = 4096 antennas
+and K = 256 users (VR lengths uniform in [256, 1024] at uniform starts, LoS
+spherical wave at 28 GHz plus CN(0, 0.1) scattering on the VR entries), each
+with 1024 16-QAM symbol vectors, SNR 10 dB (xi = K / SNR), complex64,
+relative-residual tolerance 1e-5, VR-OAHK forward plus adjoint in one
+batched launch each. The other workloads:
+  many_rhs one drop Nt 1024, K 64, VR U[256, 512], 4096 QPSK vectors, SNR 10 dB
   uneven   512 drops, Nt in {512, 1024, 2048}, K in [16, 128], VR U[Nt/8, Nt/2],
            256 QPSK vectors each, SNR U[0, 20] dB (one launch for all drops)
   adjoint  256 drops of Nt 1024, K 64, VR U[256, 512], 64 QPSK vectors, SNR 10 dB
-  large    64 drops of Nt 4096, K 256, VR U[256, 1024], 1024 16-QAM vectors, SNR 10 dB
   plain    one drop Nt 256, K 16, LoS, VR U[64, 128], one QPSK vector, complex128,
            tolerance 1e-10
   subarray 64 drops of the paper's simulation setting: Nt 2000 at 100 GHz in 20
@@ -22,21 +23,25 @@ complex64, relative-residual tolerance 1e-5. The other workloads:
            100 GHz, 20 subarrays visible w.p. 0.35, K 30, five near-field paths, SNR 0 dB)
 Inputs are synthetic and resident in HBM before timing.
 
-One step = the hot path over the whole batch: the forward solve of every
+One step = the hot path over the whole batch: what the binding derives from
+the channels (row norms, channel and Gram tiles: vrk_plan_refresh, since the
+channel is an input of the differentiated step), the forward solve of every
 vector with the chosen variant (VR-OAHK by default) and the
 implicit-differentiation adjoint (b = H g, adjoint solve, gradient
-assembly). The plan (VR graph, colours, tiles) and the row norms / tile
-packing of the channels are built once before timing. The step is
-captured once into a HIP graph and the timed value comes from replays of
-it (--eager: from eager launches). The forward solve kernel is timed live
-with HIP events on the stream it runs on, in an eager loop before the
-replays; its algorithmic flops over that time are the roofline's
-"achieved".
+assembly). The plan (VR graph, colours, tiles) is built once before timing.
+The step is captured once into a HIP graph and the timed value comes from
+replays of it (--eager: from eager launches); the rate without the refresh
+(one channel serving many symbol batches) is reported beside it. The forward
+solve kernel is timed live with HIP events on the stream it runs on, in an
+eager loop before the replays; its algorithmic flops over that time are the
+roofline's "achieved".
 
-Prints one JSON line. Extra fields: per-variant forward rates, the plain
-single-instance rate (one vector per launch), accuracy of every vector
-against the FP64 Cholesky RZF, and the FP64 oracle timed on the host
-(cpu_baseline).
+Prints one JSON line. Extra fields: per-variant forward rates (many_rhs), the
+plain single-instance rate (one vector per launch, launches replayed from a
+HIP graph) and the plain configuration's microseconds per solve next to the
+oracle's, accuracy of every vector against the FP64 Cholesky RZF, and the
+FP64 oracle timed on the host (cpu_baseline, with its Cholesky-RZF,
+VR-OAHK and GRK legs at all threads and one thread).
 """
 from __future__ import annotations
 
@@ -291,12 +296,192 @@ def measured_traffic(workload, kernel_prefix):
     return float(kv["hbm_bytes_per_launch"])
 
 
+def cpu_model():
+    """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def timed_leg(drops, budget_s, work):
+    """Runs work(drop) -> vectors over the drops in order (cycling) until
+    budget_s of wall time is spent; returns (vectors/s, vectors, drop calls,
+    seconds)."""
+    n_vec, calls, t_all = 0, 0, 0.0
+    while t_all <= budget_s:
+        d = drops[calls % len(drops)]
+        t = time.perf_counter()
+        n_vec += work(d)
+        t_all += time.perf_counter() - t
+        calls += 1
+    return n_vec / t_all, n_vec, calls, t_all
+
+
+def cpu_baseline(drops, variant, tol, wl, threads):
+    """The FP64 oracle timed on the host, on bounded samples of the same
+    workload: the same work as one GPU step (the variant's iterations plus the
+    closed-form gradient), and the legs of the CPU baseline plan (Cholesky
+    RZF, reference VR-OAHK, reference GRK), each with all threads and with
+    one thread."""
+    import numpy as np
+
+    import oracle
+    gcpu = np.random.default_rng(7)
+    cap = 256 if wl == "large" else None
+
+    def sub(d, n=None):
+        n = d.nrhs if n is None else min(n, d.nrhs)
+        return d.S[:n], dict(masks=d.vr_mask, n_sub=d.n_sub)
+
+    def step_work(d):
+        Ss, mk = sub(d, cap)
+        G = (gcpu.standard_normal((len(Ss), d.nt)) + 1j * gcpu.standard_normal((len(Ss), d.nt))) / d.nrhs
+        oracle.solve_batch(d.H, d.vr_start, d.vr_len, Ss, d.xi, variant=variant, tol=tol, **mk)
+        oracle.rzf_grad(d.H, d.vr_start, d.vr_len, Ss, d.xi, G, **mk)
+        return len(Ss)
+
+    def chol_work(d):
+        Ss, mk = sub(d)
+        oracle.rzf(d.H, d.vr_start, d.vr_len, Ss, d.xi, **mk)
+        return len(Ss)
+
+    def iter_work(var, n):
+        def f(d):
+            Ss, mk = sub(d, n)
+            oracle.solve_batch(d.H, d.vr_start, d.vr_len, Ss, d.xi, variant=var, tol=tol, **mk)
+            return len(Ss)
+        return f
+
+    out = {}
+    nthreads = threads
+    oracle.set_num_threads(nthreads)
+    v, n, c, t = timed_leg(drops, 8.0, step_work)
+    out["step"] = (v, "%d vectors in %d drop solves (drops in order, %d distinct of %d; %.1f s): FP64 %s "
+                   "iterations to tol %g + closed-form gradient, %d threads"
+                   % (n, c, min(c, len(drops)), len(drops), t, variant, tol, nthreads))
+    legs = {}
+    # per leg: (work with all threads, work with one thread, seconds); the
+    # greedy leg costs about a hundred times the aggregated one per vector
+    grk_n = 16 if wl == "large" else 64
+    plan_legs = (("cholesky_rzf", chol_work, chol_work, 3.0),
+                 ("vr_oahk", iter_work("vr_oahk", cap), iter_work("vr_oahk", 32), 3.0),
+                 ("grk", iter_work("grk", grk_n * nthreads), iter_work("grk", 2), 4.0))
+    for label, w_all, w_one, budget in plan_legs:
+        row = {}
+        for th, w, bud in ((nthreads, w_all, budget), (1, w_one, budget / 2)):
+            oracle.set_num_threads(th)
+            v, n, c, t = timed_leg(drops, bud, w)
+            row["vectors_per_s_%dthreads" % th] = v
+            row["sample_%dthreads" % th] = "%d vectors, %d drop calls, %.1f s" % (n, c, t)
+        legs[label] = row
+    oracle.set_num_threads(nthreads)
+    return out, legs
+
+
+def plain_leg(d0, sp0, cdt, variant, tol, n_plain, stream):
+    """The plain single-instance GPU solver: one vector per launch (vector
+    engine), forward + adjoint, on n_plain rows of the first drop. One plan per
+    vector (its S, X, V, GX rows are views into the batch buffers) so that the
+    n_plain solves are captured once into a HIP graph and replayed: no host
+    work between the launches. Returns (vectors/s, us per vector, the last
+    vector's X row)."""
+    import torch
+
+    from paper_2501_10689_amd import vrk
+    dev = sp0.H.device
+    plans = []
+    for i in range(n_plain):
+        sp = vrk.ProblemSpec(sp0.H, d0.vr_start, d0.vr_len, d0.xi, sp0.S[i:i + 1], sp0.X[i:i + 1].clone(),
+                             sp0.V[i:i + 1].clone(), sp0.GX[i:i + 1], torch.zeros_like(sp0.H),
+                             torch.zeros((1, d0.k), dtype=cdt, device=dev),
+                             torch.zeros(1, dtype=torch.float64, device=dev),
+                             vr_mask=d0.vr_mask, n_sub=d0.n_sub)
+        plans.append(vrk.Plan([sp], vrk.options(variant=variant, dtype="c128" if cdt == torch.complex128 else "c64",
+                                                engine="vector", tol=tol)))
+    for p in plans:
+        p.solve(stream=stream)
+        p.solve_adjoint(stream=stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for p in plans:
+            p.solve()
+            p.solve_adjoint()
+    graph.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    a.record(stream)
+    for _ in range(reps):
+        graph.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return n_plain / (ms * 1e-3), ms * 1e3 / n_plain, plans[-1].probs[0].X
+
+
+def plain_c1(stream):
+    """The plain single-instance configuration itself (Nt 256, K 16, LoS, one
+    QPSK vector, complex128, tolerance 1e-10): microseconds per forward solve
+    on the GPU (graph replays of one-vector launches) per variant, next to the
+    FP64 oracle's time per vector on the host (one thread: a single vector)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_2501_10689_amd import vrk
+    d = synth.make_workload("plain")[0]
+    dev = torch.device("cuda:0")
+    H = torch.from_numpy(d.H).to(dev)
+    S = torch.from_numpy(d.S).to(dev)
+    Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+    out = {}
+    for var in ("grk", "ahk", "vr_oahk"):
+        X = torch.zeros((1, d.nt), dtype=torch.complex128, device=dev)
+        V = torch.zeros((1, d.k), dtype=torch.complex128, device=dev)
+        plan = vrk.Plan([vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X, V)],
+                        vrk.options(variant=var, dtype="c128", engine="vector", tol=1e-10))
+        st = plan.stats_buffers()
+        plan.solve(stream=stream, stats=st)
+        torch.cuda.synchronize()
+        n = 64
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(n):
+                plan.solve(stats=st)
+        graph.replay()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        graph.replay()
+        b.record(stream)
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / n
+        err = float(np.linalg.norm(X.cpu().numpy()[0] - Xr[0]) / np.linalg.norm(Xr[0]))
+        reps, t = 0, 0.0
+        while t < 0.3:
+            t0 = time.perf_counter()
+            oracle.solve(d.H, d.vr_start, d.vr_len, d.S[0], d.xi, variant=var, tol=1e-10)
+            t += time.perf_counter() - t0
+            reps += 1
+        out[var] = {"gpu_us_per_solve": us, "oracle_us_per_solve": t * 1e6 / reps,
+                    "iters": int(st[0].cpu()[0]), "rel_err": err}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="many_rhs", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", default="vr_oahk", choices=["grk", "ahk", "vr_ogrk", "vr_oahk"])
     ap.add_argument("--engine", default="auto", choices=["auto", "vector", "mfma"])
     ap.add_argument("--snr", type=float, default=None)
@@ -365,7 +550,13 @@ def main():
     stream = torch.cuda.current_stream(dev)
     bind_ms = time_bind(plan, stream)
 
-    def step(ev=None):
+    # One step: what the binding derives from the channel (row norms, tiles,
+    # Gram tiles: vrk_plan_refresh), the forward solve of every vector and the
+    # adjoint (b = H g, adjoint solve, gradient assembly). The channel is an
+    # input of the differentiated step, so its per-channel work is timed too.
+    def step(ev=None, refresh=True):
+        if refresh:
+            plan.refresh(stream=stream)
         if ev is not None:
             ev[0].record(stream)
         plan.solve(stream=stream, stats=stats)
@@ -389,29 +580,37 @@ def main():
     ms_step = t0.elapsed_time(t1) / args.steps
     solve_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     ms_eager = ms_step
+    ms_reuse = None
     if not args.eager:
         # the step captured once into a HIP graph and replayed: the timed
-        # value (the eager loop above gives the live per-launch solve time)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            plan.solve(stats=stats)
-            plan.solve_adjoint(stats=stats_adj)
-        for _ in range(max(1, args.warmup)):
-            graph.replay()
-        torch.cuda.synchronize()
-        t0.record(stream)
-        for i in range(args.steps):
-            graph.replay()
-        t1.record(stream)
-        torch.cuda.synchronize()
-        ms_step = t0.elapsed_time(t1) / args.steps
+        # value (the eager loop above gives the live per-launch solve time);
+        # a second graph without the refresh gives the rate when one channel
+        # serves many batches of symbols
+        def replay_ms(refresh):
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                if refresh:
+                    plan.refresh()
+                plan.solve(stats=stats)
+                plan.solve_adjoint(stats=stats_adj)
+            for _ in range(max(1, args.warmup)):
+                graph.replay()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(args.steps):
+                graph.replay()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            return t0.elapsed_time(t1) / args.steps
+        ms_step = replay_ms(True)
+        ms_reuse = replay_ms(False)
     value = B / (ms_step * 1e-3)
 
-    # accuracy of every vector vs the FP64 Cholesky RZF, and the flop count
+    # accuracy of every vector vs the FP64 Cholesky RZF, and the flop counts
     import oracle
     it_all = stats[0].cpu().numpy()
     fl_all = stats[2].cpu().numpy()
-    worst, errsum, flops, base = 0.0, 0.0, 0.0, 0
+    worst, errsum, flops, flops_primal, base = 0.0, 0.0, 0.0, 0.0, 0
     for j, (d, sp) in enumerate(zip(drops, specs)):
         Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi, masks=d.vr_mask, n_sub=d.n_sub)
         Xg = sp.X.cpu().numpy().astype(np.complex128)
@@ -425,8 +624,9 @@ def main():
         band, band_f = float(vl.sum()), float(vl[fset].sum())
         it = it_all[base:base + d.nrhs]
         overlap = float(plan.query(j, vrk.Q_XOFF)[-1])   # sum_i |X_i|
-        flops += algorithmic_flops(engine, args.variant, band, band_f, band - band_f, overlap, float(it.sum()),
-                                   float(d.nrhs), d.k)
+        args_f = (args.variant, band, band_f, band - band_f, overlap, float(it.sum()), float(d.nrhs), d.k)
+        flops += algorithmic_flops(engine, *args_f)
+        flops_primal += algorithmic_flops("vector", *args_f)
         base += d.nrhs
     achieved = flops / (solve_ms * 1e-3)
     if engine == "mfma":
@@ -440,11 +640,20 @@ def main():
         vid = {"grk": 0, "vr_ogrk": 0, "ahk": 1, "vr_oahk": 3}[args.variant]
         roof["traffic"] = measured_traffic(wl, "void (anonymous namespace)::k_mfma_solve<%d, %d, %d, %s>" % (
             int(eng[2]), int(eng[6]), vid, "true" if int(eng[4]) else "false"))
-    roof["kernel"] = "solve (%s engine, %s)" % (engine, args.variant)
+    roof["kernel"] = "forward solve (%s engine, %s)" % (engine, args.variant)
     roof["kernel_ms"] = solve_ms
     roof["flops_per_launch"] = flops
     roof["unit_of_work"] = "vector-iteration"
     roof["units_per_launch"] = float(it_all.sum())
+    if engine == "mfma":
+        # Table I's count of the paper's primal steps (residual check, F
+        # half-step, V residual, V aggregation over the users' VRs), which this
+        # engine does not execute: it iterates in the dual space on the Gram
+        # matrix (formed by the refresh), so achieved/peak on this count is
+        # no utilisation figure and can exceed 1
+        roof["count"] = "executed dual-space flops: Gram products over the overlap sets + x = H^H q + fresh residual"
+        roof["primal_table_i_flops_per_launch"] = flops_primal
+        roof["primal_table_i_over_peak"] = flops_primal / (solve_ms * 1e-3) / PEAK_MFMA_F32
 
     out = {
         "metric": METRIC, "value": value, "unit": "vectors/s", "n_gpus": 1,
@@ -452,10 +661,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if c128 else "f32", "data": "synthetic",
         "timing": "eager launches" if args.eager else
-                  "HIP graph of the step, replayed (eager: %.4f ms per step)" % ms_eager,
+                  "HIP graph of the step (refresh + forward solve + adjoint), replayed (eager: %.4f ms per step)"
+                  % ms_eager,
         "config": {"workload": WORKLOADS[wl], "variant": args.variant, "engine": engine,
                    "tile_waves": int(eng[2]), "tile_waves_adjoint": int(eng[9]), "persistent": int(eng[4]),
-                   "entries_per_thread": int(eng[6]), "drops": len(drops), "vectors": B, "tol": tol},
+                   "entries_per_thread": int(eng[6]), "drops": len(drops), "vectors": B, "tol": tol,
+                   "step": "vrk_plan_refresh (row norms, channel and Gram tiles) + vrk_solve + vrk_solve_adjoint"},
         "orthogonal_set_mean": float(np.mean([len(plan.query(j, vrk.Q_FSET)) for j in range(len(drops))])),
         "roofline": roof,
         "bind_ms": bind_ms,
@@ -463,6 +674,10 @@ def main():
                      "all_converged": bool(np.all(fl_all == 1)), "mean_iters": float(it_all.mean()),
                      "max_iters": int(it_all.max())},
     }
+    if ms_reuse is not None:
+        out["channel_reused"] = {"ms_per_step": ms_reuse, "vectors_per_s": B / (ms_reuse * 1e-3),
+                                 "note": "forward solve + adjoint only, the channel's tiles kept from the "
+                                         "previous step (many symbol batches per channel)"}
     if tuned_ms is not None:
         out["config"]["autotuned_ms"] = tuned_ms
     if args.p_vis is not None:
@@ -499,66 +714,27 @@ def main():
     # plain single-instance solver: one vector per launch (vector engine), fwd + adjoint
     if not args.no_plain:
         d0, sp0 = drops[0], specs[0]
-        n_plain = min(128, d0.nrhs)
-        S1 = torch.zeros((1, d0.k), dtype=cdt, device=dev)
-        X1 = torch.zeros((1, d0.nt), dtype=cdt, device=dev)
-        V1 = torch.zeros((1, d0.k), dtype=cdt, device=dev)
-        G1 = torch.zeros((1, d0.nt), dtype=cdt, device=dev)
-        p1 = vrk.Plan([vrk.ProblemSpec(sp0.H, d0.vr_start, d0.vr_len, d0.xi, S1, X1, V1, G1,
-                                       torch.zeros_like(sp0.H), torch.zeros((1, d0.k), dtype=cdt, device=dev),
-                                       torch.zeros(1, dtype=torch.float64, device=dev),
-                                       vr_mask=d0.vr_mask, n_sub=d0.n_sub)],
-                      vrk.options(variant=args.variant, dtype=dname, engine="vector", tol=tol))
-        for i in range(min(3, n_plain)):
-            S1.copy_(sp0.S[i:i + 1])
-            G1.copy_(sp0.GX[i:i + 1])
-            p1.solve(stream=stream)
-            p1.solve_adjoint(stream=stream)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for i in range(n_plain):
-            S1.copy_(sp0.S[i:i + 1])
-            G1.copy_(sp0.GX[i:i + 1])
-            p1.solve(stream=stream)
-            p1.solve_adjoint(stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b)
+        n_plain = min(32, d0.nrhs)
+        rate, us, Xl = plain_leg(d0, sp0, cdt, args.variant, tol, n_plain, stream)
         i = n_plain - 1
         Xr1, _ = oracle.rzf(d0.H, d0.vr_start, d0.vr_len, d0.S[i:i + 1], d0.xi, masks=d0.vr_mask,
                             n_sub=d0.n_sub)
-        e1 = float(np.linalg.norm(X1.cpu().numpy()[0] - Xr1[0]) / np.linalg.norm(Xr1[0]))
-        plain_rate = n_plain / (ms * 1e-3)
-        out["plain"] = {"vectors_per_s": plain_rate, "engine": "vector, one vector per launch, fwd+adjoint",
+        e1 = float(np.linalg.norm(Xl.cpu().numpy()[0] - Xr1[0]) / np.linalg.norm(Xr1[0]))
+        out["plain"] = {"vectors_per_s": rate, "us_per_vector": us,
+                        "engine": "vector, one vector per launch, fwd+adjoint, %d launches in a HIP graph" % n_plain,
                         "sample": n_plain, "rel_err_last": e1}
-        out["speedup_vs_plain"] = value / plain_rate
+        out["speedup_vs_plain"] = value / rate
+        out["plain_c1"] = plain_c1(stream)
 
     # FP64 oracle on the host: the same work (forward iterations with the same
-    # variant and tolerance, plus the closed-form gradient) on a bounded sample
+    # variant and tolerance, plus the closed-form gradient) on a bounded
+    # sample, and the legs of the CPU baseline plan
     if not args.no_cpu_baseline:
-        # drops in order, cycling when one pass takes less than the budget
-        budget, done, n_cpu, t_cpu = 10.0, 0, 0, 0.0
-        gcpu = np.random.default_rng(7)
-        while t_cpu <= budget:
-            d = drops[done % len(drops)]
-            n = d.nrhs if wl != "large" else min(d.nrhs, 256)
-            Ss = d.S[:n]
-            G = (gcpu.standard_normal((n, d.nt)) + 1j * gcpu.standard_normal((n, d.nt))) / d.nrhs
-            t = time.perf_counter()
-            mk = dict(masks=d.vr_mask, n_sub=d.n_sub)
-            oracle.solve_batch(d.H, d.vr_start, d.vr_len, Ss, d.xi, variant=args.variant, tol=tol, **mk)
-            oracle.rzf_grad(d.H, d.vr_start, d.vr_len, Ss, d.xi, G, **mk)
-            t_cpu += time.perf_counter() - t
-            n_cpu += n
-            done += 1
-        out["cpu_baseline"] = {"value": n_cpu / t_cpu, "unit": "vectors/s", "cores": oracle.num_threads(),
-                               "kind": "oracle",
-                               "sample": "%d vectors in %d drop solves (drops taken in order, %d distinct of %d; "
-                                         "%.1f s): FP64 %s iterations to tol %g (OpenMP over vectors) + "
-                                         "closed-form gradient" % (n_cpu, done, min(done, len(drops)), len(drops),
-                                                                  t_cpu, args.variant, tol)}
+        thr = oracle.num_threads()
+        step_cpu, legs = cpu_baseline(drops, args.variant, tol, wl, thr)
+        out["cpu_baseline"] = {"value": step_cpu[0], "unit": "vectors/s", "cores": thr, "kind": "oracle",
+                               "sample": step_cpu[1], "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                               "legs": legs}
     if args.copy_mb:
         src = torch.ones(args.copy_mb * 262144, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

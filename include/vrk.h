@@ -180,6 +180,15 @@ vrk_status vrk_plan_bind(vrk_plan *pl, void *d_ws, size_t ws_bytes, void *stream
 #define VRK_SCRATCH_BYTES ((size_t)64 << 20)
 vrk_status vrk_plan_bind_static(vrk_plan *pl, void *stream);
 
+/* After the caller changed the values of H in place (same buffers, same VRs,
+ * e.g. a training step on the channel), recomputes on `stream` what a binding
+ * derives from H: the row norms ||a_i||^2 = ||H[i, VR_i]||^2 + xi and
+ * ||A||_F^2 (Alg. 1 initialisation) and, on the MFMA engine, the packed
+ * channel tiles and the Gram tiles of H H^H + xi I. Only enqueues kernels
+ * (no copy, no allocation, no synchronisation), so it can be captured into a
+ * HIP graph with the solves. VRK_ESTATE before a binding. */
+vrk_status vrk_plan_refresh(vrk_plan *pl, void *stream);
+
 /* Enqueues the solve of every right-hand side of every problem. Writes X,
  * V and, when non-null, per-RHS statistics laid out problem after problem
  * (sum of nrhs entries): d_iters (updates done), d_relres (final relative

@@ -60,6 +60,7 @@ def _load():
             "orc_step_aggregate": (C.c_int, [P, vp, vp, vp, vp]),
             "orc_select": (C.c_int, [C.c_int, C.c_int, vp, vp, f64, f64]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_num_threads": (None, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -99,6 +100,11 @@ def _check(st):
 def num_threads() -> int:
     """OpenMP threads the batched oracle calls use."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the batched oracle calls from now on (for timing)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def philox4x64_10(ctr, key) -> np.ndarray:

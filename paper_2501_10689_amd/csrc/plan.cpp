@@ -791,6 +791,20 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
 
 }  // extern "C"
 
+// The kernels that read H: row norms and ||A||_F^2, and on the MFMA engine
+// the residual, aggregation and Gram tiles (with the F columns of M).
+static vrk_status channel_kernels(vrk_plan *pl, uint8_t *base, hipStream_t s)
+{
+    const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(base + pl->o_desc);
+    hipError_t e = vrk_launch_norms(dd, (int32_t)pl->pp.size(), pl->opt.dtype, s);
+    if (e != hipSuccess) return hip_fail(e, "row-norm kernel");
+    if (pl->engine == VRK_ENGINE_MFMA) {
+        e = vrk_launch_pack(dd, (int32_t)pl->pp.size(), pl->max_tiles, s);
+        if (e != hipSuccess) return hip_fail(e, "tile-pack kernel");
+    }
+    return VRK_OK;
+}
+
 // Tables into the workspace at d_ws (checked by the caller), then the
 // row-norm and tile kernels; shared by both binding entry points.
 static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
@@ -915,12 +929,8 @@ static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
     }
     hipError_t e = hipMemcpyAsync(base, pl->image.data(), pl->table_end, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan tables)");
-    const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(base + pl->o_desc);
-    e = vrk_launch_norms(dd, (int32_t)pl->pp.size(), o.dtype, s);
-    if (e != hipSuccess) return hip_fail(e, "row-norm kernel");
+    if (vrk_status st = channel_kernels(pl, base, s)) return st;
     if (pl->engine == VRK_ENGINE_MFMA) {
-        e = vrk_launch_pack(dd, (int32_t)pl->pp.size(), pl->max_tiles, s);
-        if (e != hipSuccess) return hip_fail(e, "tile-pack kernel");
         VrkSolveArgs a{};
         a.variant = o.variant;
         int bpc = 0;
@@ -1072,6 +1082,14 @@ static vrk_status run_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float 
         e = vrk_launch_vec_solve(a, pl->lds, s);
     if (e != hipSuccess) return hip_fail(e, "solve kernel");
     return VRK_OK;
+}
+
+vrk_status vrk_plan_refresh(vrk_plan *pl, void *stream)
+{
+    g_err.clear();
+    if (!pl) return fail(VRK_EINVAL, "plan null");
+    if (vrk_status st = check_bound(pl, "vrk_plan_refresh")) return st;
+    return channel_kernels(pl, pl->d_ws, reinterpret_cast<hipStream_t>(stream));
 }
 
 vrk_status vrk_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float *d_relres, int32_t *d_flags)

@@ -78,6 +78,8 @@ def lib():
         L.vrk_plan_bind.argtypes = [vp, vp, C.c_size_t, vp]
         L.vrk_plan_bind_static.restype = C.c_int
         L.vrk_plan_bind_static.argtypes = [vp, vp]
+        L.vrk_plan_refresh.restype = C.c_int
+        L.vrk_plan_refresh.argtypes = [vp, vp]
         L.vrk_solve.restype = C.c_int
         L.vrk_solve.argtypes = [vp, vp, vp, vp, vp]
         L.vrk_solve_adjoint.restype = C.c_int
@@ -260,6 +262,11 @@ class Plan:
             _check(lib().vrk_plan_bind_static(self._h, self._stream(stream)))
         else:
             _check(lib().vrk_plan_bind(self._h, self._ws_ptr, self.ws_bytes, self._stream(stream)))
+
+    def refresh(self, stream=None):
+        """Recompute what the binding derives from H (row norms, tiles, Gram
+        tiles) after H changed in place; graph-capturable."""
+        _check(lib().vrk_plan_refresh(self._h, self._stream(stream)))
 
     def stats_buffers(self):
         t = self._torch
