@@ -19,7 +19,7 @@ import numpy as np
 from .build import LIB, build
 
 VARIANTS = {"grk": 0, "ahk": 1, "vr_ogrk": 2, "vr_oahk": 3}
-SELECT = {"baiwu": 0, "residual": 1, "max": 2}
+SELECT = {"baiwu": 0, "residual": 1, "max": 2, "energy": 3, "uniform": 4}
 F_CONVERGED, F_NONFINITE, F_MAXITER = 1, 2, 4
 
 

@@ -34,7 +34,7 @@ typedef double complex cplx;
 /* Status / flag values (mirrored in oracle/__init__.py). */
 enum { ORC_OK = 0, ORC_EINVAL = 1 };
 enum { ORC_GRK = 0, ORC_AHK = 1, ORC_VR_OGRK = 2, ORC_VR_OAHK = 3 };
-enum { ORC_SEL_BAIWU = 0, ORC_SEL_RESIDUAL = 1, ORC_SEL_MAX = 2 };
+enum { ORC_SEL_BAIWU = 0, ORC_SEL_RESIDUAL = 1, ORC_SEL_MAX = 2, ORC_SEL_ENERGY = 3, ORC_SEL_UNIFORM = 4 };
 enum { ORC_F_CONVERGED = 1, ORC_F_NONFINITE = 2, ORC_F_MAXITER = 4 };
 
 /* One channel drop. */
@@ -477,7 +477,8 @@ static void project_orthogonal(const orc_problem *p, const uint8_t *in_f, const 
         }
 }
 
-/* Greedy selection for GRK / VR-OGRK (Sec. IV-A). Returns the chosen row.
+/* Row selection of the single-row sweeps (GRK / VR-OGRK, Sec. IV-A; the
+ * randomized Kaczmarz criteria of Sec. III-A). Returns the chosen row.
  *  RESIDUAL: p_i = |r_i|^2 / ||r||^2 (the printed GRK rule).
  *  BAIWU: the greedy randomized rule the paper cites (Bai & Wu 2018):
  *    eps = (max_i |r_i|^2/||a_i||^2 / ||r||^2 + 1/||A||_F^2) / 2,
@@ -486,11 +487,24 @@ static void project_orthogonal(const orc_problem *p, const uint8_t *in_f, const 
  *    theta = min(rho_max, (rho_max + ||r||^2/||A||_F^2)/2).
  *  MAX: argmax_i |r_i|^2/||a_i||^2, lowest index on ties (the greedy
  *    Kaczmarz benchmark).
+ *  ENERGY: p_i = ||a_i||^2 / ||A||_F^2, the energy criterion of the
+ *    randomized Kaczmarz method (Sec. III-A); the residual plays no part.
+ *  UNIFORM: p_i = 1/K, the uniform criterion (Sec. III-A; URK of Table I).
  * Sampling: smallest i whose inclusive prefix of weights (index order)
  * exceeds u * W, W = the prefix total; if rounding leaves none, the last
  * index of positive weight. */
 static int select_row(int K, int rule, const cplx *r, const double *nrm, double fro2, double u)
 {
+    if (rule == ORC_SEL_ENERGY || rule == ORC_SEL_UNIFORM) {
+        double W = 0.0;
+        for (int i = 0; i < K; ++i) W += rule == ORC_SEL_ENERGY ? nrm[i] : 1.0;
+        double target = u * W, acc = 0.0;
+        for (int i = 0; i < K; ++i) {
+            acc += rule == ORC_SEL_ENERGY ? nrm[i] : 1.0;
+            if (acc > target) return i;
+        }
+        return K - 1;
+    }
     double rr = 0.0, rho_max = -1.0;
     int imax = 0;
     for (int i = 0; i < K; ++i) {
@@ -552,7 +566,7 @@ int orc_kaczmarz(const orc_problem *p, int variant, int rule, double tol, int64_
                  cplx *x, cplx *q, int64_t *iters, double *relres, int32_t *flags,
                  cplx *trace_z, int32_t *trace_idx, int64_t trace_cap, int64_t *trace_n)
 {
-    if (validate(p) || variant < 0 || variant > 3 || rule < 0 || rule > 2 || !(tol >= 0.0) ||
+    if (validate(p) || variant < 0 || variant > 3 || rule < 0 || rule > 4 || !(tol >= 0.0) ||
         max_iters < 0)
         return ORC_EINVAL;
     const int K = p->k, N = p->nt;

@@ -232,7 +232,7 @@ def test_mis_is_maximum_independent_set_bruteforce():
 # Iterations converge to the pinned RZF for every variant, rule and seed
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("variant", ["grk", "ahk", "vr_ogrk", "vr_oahk"])
-@pytest.mark.parametrize("rule", ["baiwu", "residual", "max"])
+@pytest.mark.parametrize("rule", ["baiwu", "residual", "max", "energy", "uniform"])
 def test_iterations_converge_to_rzf(variant, rule):
     rng = np.random.default_rng(15)
     H, vs, vl, xi = random_problem(rng, 96, 12)
@@ -421,6 +421,59 @@ def test_selection_rules_against_definitions():
         freq = np.bincount(picks, minlength=K) / len(us)
         np.testing.assert_allclose(freq, w / w.sum(), atol=2.0 / 4096)
         assert oracle.select(r, nrm, "max", 0.3) == int(np.argmax(w / nrm))
+
+
+def test_randomized_criteria_against_definitions():
+    """Sec. III-A's criteria: with u swept over [0, 1), ENERGY picks row i
+    with frequency ||a_i||^2 / ||A||_F^2 and UNIFORM with 1/K, whatever the
+    residual (a zero residual included)."""
+    rng = np.random.default_rng(26)
+    us = (np.arange(4096) + 0.5) / 4096
+    for _ in range(10):
+        K = int(rng.integers(2, 20))
+        r = (rng.standard_normal(K) + 1j * rng.standard_normal(K)) * rng.random(K) ** 3
+        nrm = rng.random(K) * 3 + 0.1
+        for rr in (r, np.zeros(K, dtype=complex)):
+            pe = np.array([oracle.select(rr, nrm, "energy", u) for u in us])
+            np.testing.assert_allclose(np.bincount(pe, minlength=K) / len(us), nrm / nrm.sum(), atol=2.0 / 4096)
+            pu = np.array([oracle.select(rr, nrm, "uniform", u) for u in us])
+            np.testing.assert_allclose(np.bincount(pu, minlength=K) / len(us), np.full(K, 1.0 / K), atol=2.0 / 4096)
+        # the first row whose inclusive prefix exceeds u times the total
+        u = 0.37
+        assert oracle.select(r, nrm, "energy", u) == int(np.argmax(np.cumsum(nrm) > u * nrm.sum()))
+
+
+def test_randomized_criteria_expected_decrease():
+    """One single-row step from a common state, averaged over the sampling
+    (u swept over [0, 1)): the energy criterion removes on average exactly
+    ||r||^2 / ||A||_F^2 of the squared error (Strohmer and Vershynin's
+    identity, each row's decrease being |r_i|^2 / ||a_i||^2 by the
+    Pythagorean identity), the uniform one (1/K) sum_i |r_i|^2 / ||a_i||^2;
+    both at least sigma_min(A)^2 ||e||^2 / (K max_i ||a_i||^2)."""
+    rng = np.random.default_rng(27)
+    H, vs, vl, xi = random_problem(rng, 60, 9)
+    H[:, :] *= np.linspace(0.3, 2.0, 9)[:, None]   # unequal row energies
+    s = qpsk(rng, (9,))
+    zs = _zstar(H, vs, vl, s, xi)
+    o = oracle.solve(H, vs, vl, s, xi, variant="vr_oahk", tol=0.0, max_iters=1)
+    x0, q0 = o["x"], o["q"]
+    e0 = np.sum(np.abs(_zz(np.concatenate([x0, q0]), 60, xi) - zs) ** 2)
+    r = oracle.residual(H, vs, vl, xi, s, x0, q0)
+    nrm = oracle.row_norms(H, vs, vl, xi)
+    A = augmented(H, xi)
+    sig_min = np.linalg.svd(A, compute_uv=False)[-1]
+    us = (np.arange(2048) + 0.5) / 2048
+    for rule, want in (("energy", np.sum(np.abs(r) ** 2) / nrm.sum()),
+                       ("uniform", np.mean(np.abs(r) ** 2 / nrm))):
+        dec = []
+        for u in us:
+            i = oracle.select(r, nrm, rule, u)
+            x1, q1 = oracle.step_row(H, vs, vl, xi, i, s, x0, q0)
+            dec.append(e0 - np.sum(np.abs(_zz(np.concatenate([x1, q1]), 60, xi) - zs) ** 2))
+        # the sweep's frequencies differ from p_i by at most 1/2048 per row
+        slack = 2.0 / 2048 * np.sum(np.abs(r) ** 2 / nrm)
+        assert abs(np.mean(dec) - want) <= slack, (rule, np.mean(dec), want)
+        assert want >= sig_min ** 2 * e0 / (9 * nrm.max()) * (1 - 1e-12)
 
 
 def test_theorem3_rate_bound():
