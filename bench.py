@@ -379,7 +379,7 @@ def cpu_baseline(drops, variant, tol, wl, threads):
             row["sample_%dthreads" % th] = "%d vectors, %d drop calls, %.1f s" % (n, c, t)
         legs[label] = row
     oracle.set_num_threads(nthreads)
-    return out, legs
+    return out["step"], legs
 
 
 def plain_leg(d0, sp0, cdt, variant, tol, n_plain, stream):
@@ -686,16 +686,21 @@ def main():
     # per-variant forward rates on the same batch and engine choice
     if not args.no_variants and wl == "many_rhs":
         rates = {}
-        for var in ("grk", "ahk", "vr_ogrk", "vr_oahk"):
+        # the four variants with the default rule, then the benchmark rules of
+        # the single-row sweep: greedy Kaczmarz (max), energy and uniform RK
+        for name, var, rule in (("grk", "grk", "baiwu"), ("ahk", "ahk", "baiwu"), ("vr_ogrk", "vr_ogrk", "baiwu"),
+                                ("vr_oahk", "vr_oahk", "baiwu"), ("gk_max", "grk", "max"),
+                                ("rk_energy", "grk", "energy"), ("urk_uniform", "grk", "uniform")):
             sv_specs = [vrk.ProblemSpec(sp.H, d.vr_start, d.vr_len, d.xi, sp.S, torch.zeros_like(sp.X),
                                         torch.zeros_like(sp.V)) for sp, d in zip(specs, drops)]
-            o = vrk.options(variant=var, dtype=dname, engine=engine_opt, tol=tol, tile_waves=args.tile_waves,
-                            persistent=args.persistent)
+            o = vrk.options(variant=var, select=rule, dtype=dname, engine=engine_opt, tol=tol,
+                            tile_waves=args.tile_waves, persistent=args.persistent)
             pv = vrk.Plan(sv_specs, o)
             sv = pv.stats_buffers()
             pv.solve(stream=stream, stats=sv)
             torch.cuda.synchronize()
             reps = 3 if var in ("grk", "vr_ogrk") else 10
+            reps = 1 if rule in ("energy", "uniform") else reps
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
@@ -706,8 +711,8 @@ def main():
             ms = a.elapsed_time(b) / reps
             Xr, _ = oracle.rzf(drops[0].H, drops[0].vr_start, drops[0].vr_len, drops[0].S, drops[0].xi)
             e2 = np.linalg.norm(sv_specs[0].X.cpu().numpy() - Xr, axis=1) / np.linalg.norm(Xr, axis=1)
-            rates[var] = {"vectors_per_s": B / (ms * 1e-3), "ms": ms, "max_rel_err": float(e2.max()),
-                          "mean_iters": float(sv[0].float().mean().item())}
+            rates[name] = {"variant": var, "select": rule, "vectors_per_s": B / (ms * 1e-3), "ms": ms,
+                           "max_rel_err": float(e2.max()), "mean_iters": float(sv[0].float().mean().item())}
             del pv
         out["variants_fwd"] = rates
 

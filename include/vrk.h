@@ -59,17 +59,30 @@ typedef enum {
 
 typedef enum { VRK_GRK = 0, VRK_AHK = 1, VRK_VR_OGRK = 2, VRK_VR_OAHK = 3 } vrk_variant;
 
-/* Row selection of the greedy sweeps (Sec. IV-A).
+/* Row selection of the single-row sweeps VRK_GRK and VRK_VR_OGRK: the greedy
+ * rules of Sec. IV-A and, as the benchmarks of the simulation section, the
+ * residual-free criteria of the randomized Kaczmarz method (Sec. III-A).
  *  BAIWU    threshold-and-sample rule of the greedy randomized Kaczmarz the
  *           paper cites: rows with |r_i|^2 >= eps ||r||^2 ||a_i||^2,
  *           eps = (max_i |r_i|^2/||a_i||^2 / ||r||^2 + 1/||A||_F^2) / 2, are
  *           sampled with probability proportional to |r_i|^2.
  *  RESIDUAL the printed rule p_i = |r_i|^2 / ||r||^2.
- *  MAX      argmax_i |r_i|^2 / ||a_i||^2 (lowest index on ties).
+ *  MAX      argmax_i |r_i|^2 / ||a_i||^2 (lowest index on ties): greedy
+ *           Kaczmarz (GK of Table I).
+ *  ENERGY   p_i = ||a_i||^2 / ||A||_F^2, the energy criterion (randomized
+ *           Kaczmarz; with VRK_GRK the sweep is that method).
+ *  UNIFORM  p_i = 1 / K, the uniform criterion (with VRK_GRK: URK of Table I).
  * Sampling draws u = (Philox4x64-10(key (seed, 0), counter (step, rhs, prob, 0))[0]
  * >> 40) * 2^-24 and picks the smallest row index whose inclusive prefix of
- * weights exceeds u times their total. */
-typedef enum { VRK_SEL_BAIWU = 0, VRK_SEL_RESIDUAL = 1, VRK_SEL_MAX = 2 } vrk_select;
+ * weights exceeds u times their total. The stop rule still evaluates the
+ * residual of every row. */
+typedef enum {
+    VRK_SEL_BAIWU = 0,
+    VRK_SEL_RESIDUAL = 1,
+    VRK_SEL_MAX = 2,
+    VRK_SEL_ENERGY = 3,
+    VRK_SEL_UNIFORM = 4
+} vrk_select;
 
 typedef enum { VRK_C64 = 0, VRK_C128 = 1 } vrk_dtype;
 

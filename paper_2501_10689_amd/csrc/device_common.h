@@ -166,18 +166,40 @@ __device__ __forceinline__ double uniform24(uint64_t seed, int64_t step, int64_t
     return (double)(w >> 40) * (1.0 / 16777216.0);
 }
 
-// Greedy row selection by one wave (Sec. IV-A). get(i) returns
-// {|r_i|^2, ||a_i||^2} for user i (original index order). The threshold
-// rule keeps rows with rho_i = |r_i|^2/||a_i||^2 >= theta,
-// theta = min(rho_max, (rho_max + ||r||^2/||A||_F^2)/2) (the cited greedy
-// randomized Kaczmarz criterion); RESIDUAL keeps every row; MAX returns the
-// first argmax of rho. Sampling: smallest index whose inclusive prefix of
-// kept weights exceeds u * total, else the last kept index. `pre` is LDS
+// Row selection by one wave (Sec. IV-A; Sec. III-A for the randomized
+// criteria). get(i) returns {|r_i|^2, ||a_i||^2} for user i (original index
+// order). The threshold rule keeps rows with rho_i = |r_i|^2/||a_i||^2 >=
+// theta, theta = min(rho_max, (rho_max + ||r||^2/||A||_F^2)/2) (the cited
+// greedy randomized Kaczmarz criterion), weighted by |r_i|^2; RESIDUAL keeps
+// every row, weighted by |r_i|^2; MAX returns the first argmax of rho;
+// ENERGY weights row i by ||a_i||^2 and UNIFORM every row by 1, whatever the
+// residual. Sampling: smallest index whose inclusive prefix of weights
+// exceeds u * total, else the last index of positive weight. `pre` is LDS
 // scratch of K entries owned by the calling wave.
 template <typename R, typename Get>
 __device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
 {
     const int lane = threadIdx.x & 63;
+    if (rule == 3 || rule == 4) {
+        // residual-free criteria: one prefix pass over the weights
+        R carry = 0;
+        for (int base = 0; base < K; base += 64) {
+            const int i = base + lane;
+            R wt = 0;
+            if (i < K) wt = rule == 3 ? get(i).im : (R)1;
+            const R v = wave_scan(wt, lane);
+            if (i < K) pre[i] = carry + v;
+            carry += __shfl(v, 63, 64);
+        }
+        const R target = u * carry;
+        __builtin_amdgcn_wave_barrier();
+        for (int base = 0; base < K; base += 64) {
+            const int i = base + lane;
+            const uint64_t hit = __ballot(i < K && pre[i] > target);
+            if (hit) return base + __ffsll((unsigned long long)hit) - 1;
+        }
+        return K - 1;
+    }
     R rr = 0, best = -1;
     int bi = 0x7fffffff;
     for (int base = 0; base < K; base += 64) {

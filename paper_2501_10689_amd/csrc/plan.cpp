@@ -531,7 +531,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     if (!opt) return fail(VRK_EINVAL, "options null");
     const vrk_options &o = *opt;
     if (o.variant < 0 || o.variant > 3) return fail(VRK_EINVAL, "variant %d", o.variant);
-    if (o.select < 0 || o.select > 2) return fail(VRK_EINVAL, "select %d", o.select);
+    if (o.select < 0 || o.select > 4) return fail(VRK_EINVAL, "select %d", o.select);
     if (o.dtype != VRK_C64 && o.dtype != VRK_C128) return fail(VRK_EINVAL, "dtype %d", o.dtype);
     if (o.engine < 0 || o.engine > 2) return fail(VRK_EINVAL, "engine %d", o.engine);
     if (o.schedule < 0 || o.schedule > 2) return fail(VRK_EINVAL, "schedule %d", o.schedule);

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvrk.so")
 
 VARIANTS = {"grk": 0, "ahk": 1, "vr_ogrk": 2, "vr_oahk": 3}
-SELECT = {"baiwu": 0, "residual": 1, "max": 2}
+SELECT = {"baiwu": 0, "residual": 1, "max": 2, "energy": 3, "uniform": 4}
 DTYPES = {"c64": 0, "c128": 1}
 ENGINES = {"auto": 0, "vector": 1, "mfma": 2}
 SCHEDULES = {"auto": 0, "gather": 1, "colour": 2}

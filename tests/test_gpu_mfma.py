@@ -257,12 +257,12 @@ def test_rebind_and_resolve_are_bitwise_deterministic(engine):
 
 
 @pytest.mark.parametrize("variant", ["grk", "vr_ogrk"])
-@pytest.mark.parametrize("rule", ["max", "residual"])
+@pytest.mark.parametrize("rule", ["max", "residual", "energy", "uniform"])
 def test_greedy_rules_mfma(variant, rule):
-    """The greedy-Kaczmarz (max) and printed residual-proportional rules on
-    the MFMA engine: Nt 1024, K 64, 37 vectors, every x within 1e-4 of the
-    FP64 RZF. The max rule is deterministic: both greedy variants take the
-    same rows, so they agree bit for bit."""
+    """The greedy-Kaczmarz (max), printed residual-proportional, energy and
+    uniform rules on the MFMA engine: Nt 1024, K 64, 37 vectors, every x
+    within 1e-4 of the FP64 RZF. The max rule is deterministic: both greedy
+    variants take the same rows, so they agree bit for bit."""
     d = synth.make_workload("many_rhs", nrhs=37)[0]
     res, _ = run_plan([(d.H, d.vr_start, d.vr_len, d.S, d.xi)], variant=variant, select=rule, engine="mfma")
     X, V = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)

@@ -16,7 +16,7 @@ VARIANTS = ["grk", "ahk", "vr_ogrk", "vr_oahk"]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("rule", ["baiwu", "max", "residual"])
+@pytest.mark.parametrize("rule", ["baiwu", "max", "residual", "energy", "uniform"])
 def test_plain_c128_matches_oracle_trajectory(variant, rule):
     """Plain instance (Nt 256, K 16, LoS, one QPSK vector, SNR 10 dB) in
     complex128 to relative residual 1e-10: same iterate as the FP64 oracle
@@ -153,3 +153,20 @@ def test_adjoint_matches_closed_form_gradient(dtype, tol, bound, nt, k, nrhs):
     g = res[0]
     mask = np.abs(H) > 0
     check_grads(g, (gH, gS, gxi), mask, bound)
+
+
+@pytest.mark.parametrize("rule", ["energy", "uniform"])
+def test_randomized_criteria_c128_follow_the_oracle_on_uneven_rows(rule):
+    """Energy and uniform criteria where they differ (rows of unequal
+    energy): complex128 GPU trajectories equal the oracle's (same rows drawn,
+    same iteration counts) on several vectors of a random drop."""
+    rng = np.random.default_rng(31)
+    H, vs, vl, xi = random_problem(rng, 96, 12)
+    H *= np.linspace(0.2, 2.5, 12)[:, None]
+    S = qpsk(rng, (5, 12))
+    res, _ = run_plan([(H, vs, vl, S, xi)], variant="grk", select=rule, dtype="c128", engine="vector",
+                      tol=1e-10, seed=3)
+    for b in range(5):
+        o = oracle.solve(H, vs, vl, S[b], xi, variant="grk", select=rule, tol=1e-10, seed=3, drop=0, rhs=b)
+        assert res[0]["iters"][b] == o["iters"], b
+        assert np.linalg.norm(res[0]["X"][b] - o["x"]) <= 1e-12 * np.linalg.norm(o["x"])
