@@ -133,6 +133,9 @@ def run_precoder(args):
     opts = vrk.options(variant=args.variant, dtype="c64", engine=args.engine, tol=tol,
                        tile_waves=args.tile_waves, persistent=args.persistent)
     plan = vrk.Plan(specs, opts)
+    # sigma^2 / rho of the rates: 1 / SNR (the regulariser is K / SNR on the
+    # adjoint drops, 1 / SNR on the paper's setting)
+    noise = [10.0 ** (-d.snr_db / 10.0) for d in drops]
     eng = plan.query(0, vrk.Q_ENGINE)
     engine = {1: "vector", 2: "mfma"}[int(eng[0])]
     stats = plan.stats_buffers()
@@ -145,7 +148,7 @@ def run_precoder(args):
         plan.solve(stream=stream, stats=stats)
         if ev is not None:
             ev[1].record(stream)
-        plan.link_metrics(E, R, Bt, stream=stream)
+        plan.link_metrics(E, R, Bt, noise, stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -170,7 +173,7 @@ def run_precoder(args):
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             plan.solve(stats=stats)
-            plan.link_metrics(E, R, Bt)
+            plan.link_metrics(E, R, Bt, noise)
         for _ in range(max(1, args.warmup)):
             graph.replay()
         torch.cuda.synchronize()
@@ -186,7 +189,7 @@ def run_precoder(args):
     worst_nmse, worst_rate, flops, base = 0.0, 0.0, 0.0, 0
     for j, (d, sp) in enumerate(zip(drops, specs)):
         Xo = oracle.precoder(d.H, d.vr_start, d.vr_len, d.xi)
-        _, bo, ro = oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi, Xo)
+        _, bo, ro = oracle.link_metrics(d.H, d.vr_start, d.vr_len, noise[j], Xo)
         Xg = sp.X.cpu().numpy().astype(np.complex128)
         bg = float(Bt[j].cpu().numpy()[0])
         worst_nmse = max(worst_nmse, oracle.nmse(bo * Xo, bg * Xg))
@@ -231,7 +234,7 @@ def run_precoder(args):
             t = time.perf_counter()
             Xc = oracle.solve_batch(d.H, d.vr_start, d.vr_len, np.eye(d.k, dtype=np.complex128), d.xi,
                                     variant=args.variant, tol=tol, masks=d.vr_mask, n_sub=d.n_sub)["X"]
-            oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi, Xc)
+            oracle.link_metrics(d.H, d.vr_start, d.vr_len, 10.0 ** (-d.snr_db / 10.0), Xc)
             t_cpu += time.perf_counter() - t
             n_cpu += 1
         out["cpu_baseline"] = {"value": n_cpu / t_cpu, "unit": "matrices/s", "cores": oracle.num_threads(),

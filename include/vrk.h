@@ -228,8 +228,11 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
  *   E[u * lde + b] = h_u^H f_b = sum over n in VR_u of H[u][n] X[b][n]
  *                    (k x k, the plan's complex type, lde >= k),
  *   beta[0]        = 1 / ||F||_F (so that ||beta F||_F = 1, the power budget),
- *   rate[u]        = log2(1 + beta^2 |E_uu|^2 / (beta^2 sum_{b != u} |E_ub|^2 + xi))
- *                    (double, bit/s/Hz; xi = sigma^2 / rho as in the RZF design).
+ *   rate[u]        = log2(1 + beta^2 |E_uu|^2 / (beta^2 sum_{b != u} |E_ub|^2 + noise))
+ *                    (double, bit/s/Hz), the spectral efficiency of user u under the
+ *                    signal model with noise = sigma^2 / rho given per problem (the
+ *                    regulariser xi of the plan is not used here: it equals sigma^2 / rho
+ *                    only when chosen so; with xi = K sigma^2 / rho, noise = xi / K).
  * On MFMA-engine plans E is evaluated as (H H^H) V^T = (M - xi I) V^T from
  * the plan's Gram tiles and the solve's V (the MFMA solve forms x = H^H v, so
  * this is the same quantity; V is kept in the workspace when the caller
@@ -237,13 +240,14 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
  * Asynchronous on stream. The nprob-entry output table is copied to the
  * workspace when it differs from the previous call's on this binding (the
  * workspace belongs to the plan while bound), so repeated calls with the
- * same outputs copy nothing. VRK_EINVAL for a problem with nrhs != k or a
- * null output, VRK_ESTATE before bind. */
+ * same outputs copy nothing. VRK_EINVAL for a problem with nrhs != k, a
+ * null output or a noise that is not finite and > 0; VRK_ESTATE before bind. */
 typedef struct {
     void *E;       /* device out, k x k row-major */
     int64_t lde;
     double *rate;  /* device out, k */
     double *beta;  /* device out, 1 */
+    double noise;  /* host value: sigma^2 / rho of the rate formula, finite and > 0 */
 } vrk_link_out;
 vrk_status vrk_link_metrics(vrk_plan *pl, const vrk_link_out *out, void *stream);
 

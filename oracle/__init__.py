@@ -288,21 +288,21 @@ def precoder(H, vr_start, vr_len, xi):
     return X
 
 
-def link_metrics(H, vr_start, vr_len, xi, X):
+def link_metrics(H, vr_start, vr_len, noise, X):
     """Link metrics of the precoder whose transposed columns are the rows of
     X (K x Nt). Returns (E, beta, rate):
       E[u, b] = h_u^H f_b = sum over n in VR_u of H[u, n] X[b, n],
       beta    = 1 / ||F||_F  (the power budget ||beta F||_F^2 <= 1 met with
                 equality),
       rate[u] = log2(1 + rho beta^2 |E_uu|^2 / (rho beta^2 sum_{b != u}
-                |E_ub|^2 + sigma^2)), written with xi = sigma^2 / rho."""
+                |E_ub|^2 + sigma^2)), written with noise = sigma^2 / rho."""
     X = np.asarray(X, dtype=np.complex128)
     E = band_channel(H, vr_start, vr_len) @ X.T
     beta = 1.0 / np.linalg.norm(X)
     a2 = np.abs(E) ** 2
     sig = np.diag(a2).copy()
     intf = a2.sum(axis=1) - sig
-    rate = np.log2(1.0 + beta ** 2 * sig / (beta ** 2 * intf + xi))
+    rate = np.log2(1.0 + beta ** 2 * sig / (beta ** 2 * intf + noise))
     return E, beta, rate
 
 

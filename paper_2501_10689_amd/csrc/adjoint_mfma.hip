@@ -21,26 +21,6 @@
 
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Sums of complex products with three real products each (Gauss):
-// u += Ar Br, v += Ai Bi, w += (Ar + Ai)(Br + Bi); Re = u - v, Im = w - u - v.
-struct C3 {
-    f4 u, v, w;
-};
-
-__device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
-{
-    acc.u = mfma(a.x, b.x, acc.u);
-    acc.v = mfma(a.y, b.y, acc.v);
-    acc.w = mfma(a.x + a.y, b.x + b.y, acc.w);
-}
-
 using CDesc = const VRK_CONST VrkDesc;
 template <typename T>
 using gp = VRK_GLOBAL T *;

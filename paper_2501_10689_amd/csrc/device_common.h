@@ -1,5 +1,6 @@
 // Device helpers shared by the HIP kernels: complex arithmetic, wave64
-// reductions, Philox4x64-10 and the greedy row selection.
+// reductions, Philox4x64-10, the row selection and the complex products on
+// the FP32 matrix cores.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -264,4 +265,55 @@ __device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
         if (hit) return base + __ffsll((unsigned long long)hit) - 1;
     }
     return last;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 matrix cores (v_mfma_f32_16x16x4f32). A is 16 x 4 (lane l holds row
+// l % 16, reduction index l / 16), B is 4 x 16 (lane l holds reduction index
+// l / 16, column l % 16), C and D are 16 x 16 (lane l holds rows
+// 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16).
+// ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Complex product A * B accumulated with three real products (Gauss):
+// u += Ar Br, v += Ai Bi, w += (Ar + Ai)(Br + Bi); then Re = u - v and
+// Im = w - u - v. Operands are held one complex value per lane.
+struct C3 {
+    f4 u, v, w;
+};
+
+__device__ __forceinline__ C3 c3_zero()
+{
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    return C3{z, z, z};
+}
+
+__device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
+{
+    acc.u = mfma(a.x, b.x, acc.u);
+    acc.v = mfma(a.y, b.y, acc.v);
+    acc.w = mfma(a.x + a.y, b.x + b.y, acc.w);
+}
+
+__device__ __forceinline__ void c3_get(const C3 &acc, f4 &re, f4 &im)
+{
+    re = acc.u - acc.v;
+    im = acc.w - acc.u - acc.v;
+}
+
+// Sum over the four lanes j, j + 16, j + 32, j + 48 of a column of the C
+// layout, in every one of them: gfx950's row-swap moves (16-lane rows, then
+// 32-lane halves), (v_j + v_j+16) + (v_j+32 + v_j+48) in the same order in
+// all four lanes.
+__device__ __forceinline__ float col4_sum(float v)
+{
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }

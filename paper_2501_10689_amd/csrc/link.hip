@@ -3,8 +3,9 @@
 // is f_b, column b of the unnormalised precoding matrix F. Per problem:
 //   E[u][b] = h_u^H f_b = sum over n in VR_u of H[u][n] X[b][n]
 //   beta    = 1 / ||F||_F                      (power budget ||beta F||_F = 1)
-//   R_u     = log2(1 + beta^2 |E_uu|^2 / (beta^2 sum_{b != u} |E_ub|^2 + xi))
-// with xi = sigma^2 / rho, so the rate is the spectral efficiency of user u.
+//   R_u     = log2(1 + beta^2 |E_uu|^2 / (beta^2 sum_{b != u} |E_ub|^2 + sigma^2 / rho))
+// with sigma^2 / rho given per problem (the output table's noise), so the
+// rate is the spectral efficiency of user u.
 // On MFMA-engine plans X = H^H V exactly (the solve forms x from its dual
 // iterate q = v), so E = H H^H V^T = (M - xi I) V^T: a K x K x K product
 // with the Gram tiles instead of a band product over the antennas. Vector
@@ -143,23 +144,8 @@ __global__ void __launch_bounds__(256) k_link_rates(const VrkDesc *descs, const 
             if (b == u) sig = a2;
             else intf += a2;
         }
-        o.rate[u] = log2(1.0 + beta2 * sig / (beta2 * intf + d.xi));
+        o.rate[u] = log2(1.0 + beta2 * sig / (beta2 * intf + o.noise));
     }
-}
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-// Sums of complex products with three real products each (Gauss):
-// u += Ar Br, v += Ai Bi, w += (Ar + Ai)(Br + Bi); Re = u - v, Im = w - u - v.
-struct C3 {
-    f4 u, v, w;
-};
-
-__device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
-{
-    acc.u = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc.u, 0, 0, 0);
-    acc.v = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc.v, 0, 0, 0);
-    acc.w = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, acc.w, 0, 0, 0);
 }
 
 // E on the matrix cores (complex64, MFMA-engine plans): workgroup x of

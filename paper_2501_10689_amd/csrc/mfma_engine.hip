@@ -11,8 +11,9 @@
 // products, r -= M (gamma phi): the same iterates as the paper's updates of
 // x and the re-evaluated residuals, at the cost of the Gram band instead of
 // the channel band per step. When every column has met the stop rule, x =
-// H^H q is formed and the true residual s - H x - xi q is evaluated from it;
-// a column whose true residual misses the tolerance resumes from it.
+// H^H q is formed and the residual s - M q is evaluated afresh from q (equal
+// to s - H x - xi q in exact arithmetic, free of the maintained residual's
+// drift); a column whose fresh residual misses the tolerance resumes from it.
 //
 // Layout. Lane l of a wave is (j, g) = (l % 16, l / 16): RHS column j and
 // row group g. Thread (er, j) of the workgroup keeps the entries (er + 4 W k,
@@ -32,39 +33,6 @@
 #include "kernels.h"
 
 namespace {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Complex product A * B accumulated with three real products (Gauss):
-// u += Ar Br, v += Ai Bi, w += (Ar + Ai)(Br + Bi); then Re = u - v and
-// Im = w - u - v. Operands are held one complex value per lane.
-struct C3 {
-    f4 u, v, w;
-};
-
-__device__ __forceinline__ C3 c3_zero()
-{
-    const f4 z = {0.f, 0.f, 0.f, 0.f};
-    return C3{z, z, z};
-}
-
-__device__ __forceinline__ void c3mfma(C3 &acc, float2 a, float2 b)
-{
-    acc.u = mfma(a.x, b.x, acc.u);
-    acc.v = mfma(a.y, b.y, acc.v);
-    acc.w = mfma(a.x + a.y, b.x + b.y, acc.w);
-}
-
-__device__ __forceinline__ void c3_get(const C3 &acc, f4 &re, f4 &im)
-{
-    re = acc.u - acc.v;
-    im = acc.w - acc.u - acc.v;
-}
 
 struct MfmaLds {
     float2 *R;    // residual (greedy variants: the selection reads every row)
@@ -147,19 +115,8 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, bool
 // its column's totals, added in a fixed order. One barrier: consecutive sums
 // alternate between the two halves of the buffer (ColSums), so a sum never
 // overwrites partials that a thread may still be reading from the previous
-// one, and the sum before that was read before the previous barrier.
-// Sum over the four lanes j, j + 16, j + 32, j + 48 of a column, in every
-// one of them: gfx950's row-swap moves (16-lane rows, then 32-lane halves)
-// instead of two LDS permutes; (v_j + v_j+16) + (v_j+32 + v_j+48) in the
-// same order in all four lanes.
-__device__ __forceinline__ float col4_sum(float v)
-{
-    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
-    const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
-}
-
+// one, and the sum before that was read before the previous barrier. Within
+// a wave the four lanes of a column are added by col4_sum.
 template <int W>
 struct ColSums {
     float *red;   // 2 halves x 2 values x W waves x 16 columns

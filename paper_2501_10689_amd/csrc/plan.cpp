@@ -1148,7 +1148,9 @@ vrk_status vrk_link_metrics(vrk_plan *pl, const vrk_link_out *out, void *stream)
         if (!out[i].E || !out[i].rate || !out[i].beta)
             return fail(VRK_EINVAL, "problem %d: E, rate and beta must be set", i);
         if (out[i].lde < p.k) return fail(VRK_EINVAL, "problem %d: lde %lld < k %d", i, (long long)out[i].lde, p.k);
-        tab[i] = VrkLinkOut{out[i].E, out[i].lde, out[i].rate, out[i].beta};
+        if (!(out[i].noise > 0.0) || !std::isfinite(out[i].noise))
+            return fail(VRK_EINVAL, "problem %d: noise (sigma^2 / rho) %g must be finite and > 0", i, out[i].noise);
+        tab[i] = VrkLinkOut{out[i].E, out[i].lde, out[i].rate, out[i].beta, out[i].noise};
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     VrkLinkOut *d_out = reinterpret_cast<VrkLinkOut *>(pl->d_ws + pl->o_link);

@@ -94,6 +94,7 @@ struct VrkLinkOut {
     int64_t lde;
     double *rate;
     double *beta;
+    double noise;   // sigma^2 / rho of the rate
 };
 
 // User blocks per tile of the MFMA adjoint gradient: the blocks 4 ubg ..

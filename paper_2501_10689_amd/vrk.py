@@ -48,7 +48,8 @@ class Options(C.Structure):
 
 
 class LinkOut(C.Structure):
-    _fields_ = [("E", C.c_void_p), ("lde", C.c_int64), ("rate", C.c_void_p), ("beta", C.c_void_p)]
+    _fields_ = [("E", C.c_void_p), ("lde", C.c_int64), ("rate", C.c_void_p), ("beta", C.c_void_p),
+                ("noise", C.c_double)]
 
 
 class VrkError(RuntimeError):
@@ -283,17 +284,20 @@ class Plan:
         it, rel, fl = stats if stats is not None else (None, None, None)
         _check(lib().vrk_solve_adjoint(self._h, self._stream(stream), _ptr(it), _ptr(rel), _ptr(fl)))
 
-    def link_metrics(self, E, rate, beta, stream=None):
+    def link_metrics(self, E, rate, beta, noise, stream=None):
         """After a solve with S = I_K on every problem: the effective channels
         E[p] (K x K, the plan's complex type), per-user rates rate[p] (K,
-        float64, bit/s/Hz) and beta[p] (1, float64), all device tensors."""
+        float64, bit/s/Hz) and beta[p] (1, float64), all device tensors;
+        noise[p] (or one float for all) is sigma^2 / rho of the rate."""
         n = len(self.probs)
-        if not (len(E) == len(rate) == len(beta) == n):
-            raise ValueError("one E, rate and beta per problem")
+        noise = [float(noise)] * n if np.isscalar(noise) else [float(v) for v in noise]
+        if not (len(E) == len(rate) == len(beta) == len(noise) == n):
+            raise ValueError("one E, rate, beta and noise per problem")
         arr = (LinkOut * n)()
         for i in range(n):
             arr[i].E, arr[i].lde = _ptr(E[i]), _stride(E[i])
             arr[i].rate, arr[i].beta = _ptr(rate[i]), _ptr(beta[i])
+            arr[i].noise = noise[i]
         _check(lib().vrk_link_metrics(self._h, arr, self._stream(stream)))
 
     def query(self, prob: int, what: int) -> np.ndarray:
@@ -406,12 +410,13 @@ def host_plan(nt, k, vr_start, vr_len, xi=1.0, nrhs=0, vr_mask=None, n_sub=0, ad
     return _HP()
 
 
-def precoder(H, vr_start, vr_len, xi, variant="vr_oahk", select="baiwu", tol=1e-5, max_iters=100000,
+def precoder(H, vr_start, vr_len, xi, noise, variant="vr_oahk", select="baiwu", tol=1e-5, max_iters=100000,
              seed=0, engine="auto", vr_mask=None, n_sub=0):
     """RZF precoding matrix of one drop and its link metrics on the GPU: the
     solve on S = I_K gives X = F^T (row b the unnormalised precoder of user b);
     returns X, the effective channel E = H F on the VRs (K x K), the per-user
-    spectral efficiencies (bit/s/Hz, float64) and beta = 1 / ||F||_F."""
+    spectral efficiencies (bit/s/Hz, float64, with noise = sigma^2 / rho) and
+    beta = 1 / ||F||_F."""
     import torch
     K = H.shape[0]
     dtype = "c128" if H.dtype == torch.complex128 else "c64"
@@ -423,7 +428,7 @@ def precoder(H, vr_start, vr_len, xi, variant="vr_oahk", select="baiwu", tol=1e-
     o = options(variant=variant, select=select, dtype=dtype, engine=engine, tol=tol, max_iters=max_iters, seed=seed)
     plan = Plan([ProblemSpec(H, vr_start, vr_len, xi, S, X, None, vr_mask=vr_mask, n_sub=n_sub)], o)
     plan.solve()
-    plan.link_metrics([E], [rate], [beta])
+    plan.link_metrics([E], [rate], [beta], noise)
     return X, E, rate, float(beta.cpu()[0])
 
 

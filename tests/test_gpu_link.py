@@ -13,14 +13,20 @@ from tests.gpu_util import to_dev
 pytestmark = pytest.mark.gpu
 
 
+def _noise(drop):
+    """sigma^2 / rho of the rate: the fifth entry of the drop tuple, else xi / K
+    (the workloads' regulariser is xi = K sigma^2 / rho)."""
+    return drop[4] if len(drop) > 4 else drop[3] / drop[0].shape[0]
+
+
 def _run(drops, dtype="c64", engine="auto", tol=1e-5):
-    """drops: list of (H, vs, vl, xi). Solve S = I_K for every drop in one
-    plan, then the link metrics; returns per-drop (X, E, rate, beta)."""
+    """drops: list of (H, vs, vl, xi[, noise]). Solve S = I_K for every drop
+    in one plan, then the link metrics; returns per-drop (X, E, rate, beta)."""
     import torch
     from paper_2501_10689_amd import vrk
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
     specs, E, R, Bt = [], [], [], []
-    for H, vs, vl, xi in drops:
+    for H, vs, vl, xi in (dr[:4] for dr in drops):
         K, Nt = H.shape
         Hd = to_dev(H, tdt)
         S = torch.eye(K, dtype=tdt, device="cuda")
@@ -31,24 +37,25 @@ def _run(drops, dtype="c64", engine="auto", tol=1e-5):
         Bt.append(torch.full((1,), float("nan"), dtype=torch.float64, device="cuda"))
     plan = vrk.Plan(specs, vrk.options(dtype=dtype, engine=engine, tol=tol))
     plan.solve()
-    plan.link_metrics(E, R, Bt)
+    plan.link_metrics(E, R, Bt, [_noise(dr) for dr in drops])
     torch.cuda.synchronize()
     return [(sp.X.cpu().numpy().astype(np.complex128), e.cpu().numpy().astype(np.complex128),
              r.cpu().numpy(), float(b.cpu().numpy()[0])) for sp, e, r, b in zip(specs, E, R, Bt)], plan
 
 
 def _check(drop, out, e_tol, r_tol, b_tol, nmse_tol, own_tol):
-    H, vs, vl, xi = drop
+    H, vs, vl, xi = drop[:4]
+    nz = _noise(drop)
     X, E, rate, beta = out
     # against the oracle's exact RZF precoder
     Xo = oracle.precoder(H, vs, vl, xi)
-    Eo, bo, ro = oracle.link_metrics(H, vs, vl, xi, Xo)
+    Eo, bo, ro = oracle.link_metrics(H, vs, vl, nz, Xo)
     assert np.max(np.abs(E - Eo)) <= e_tol
     assert np.max(np.abs(rate - ro)) <= r_tol
     assert abs(beta - bo) <= b_tol * bo
     assert oracle.nmse(bo * Xo, beta * X) <= nmse_tol
     # the link kernels alone: the oracle's metrics of the GPU's own precoder
-    Eg, bg, rg = oracle.link_metrics(H, vs, vl, xi, X)
+    Eg, bg, rg = oracle.link_metrics(H, vs, vl, nz, X)
     assert np.max(np.abs(E - Eg)) <= own_tol
     assert np.max(np.abs(rate - rg)) <= own_tol
     assert abs(beta - bg) <= 1e-12 * bg
@@ -87,14 +94,17 @@ def test_link_metrics_c128_vector_engine():
 
 
 def test_link_metrics_single_user_c64():
-    # K = 1 (vector engine): the rate is log2(1 + |h|^2 / xi)
+    # K = 1 (vector engine): with xi = sigma^2 / rho the rate is
+    # log2(1 + |h|^2 / xi); with another noise level n it is log2(1 + beta^2
+    # |E|^2 / n), beta^2 |E|^2 = |h|^2 for a single user
     rng = np.random.default_rng(3)
     H = np.zeros((1, 64), dtype=np.complex128)
     H[0, 10:40] = rng.standard_normal(30) + 1j * rng.standard_normal(30)
-    drop = (H, np.array([10], np.int32), np.array([30], np.int32), 0.5)
-    out, _ = _run([drop])
     h2 = float(np.sum(np.abs(H) ** 2))
-    assert abs(out[0][2][0] - np.log2(1 + h2 / 0.5)) <= 1e-4
+    for noise in (0.5, 0.07):
+        drop = (H, np.array([10], np.int32), np.array([30], np.int32), 0.5, noise)
+        out, _ = _run([drop])
+        assert abs(out[0][2][0] - np.log2(1 + h2 / noise)) <= 1e-4
 
 
 def test_link_metrics_rejects_other_right_hand_sides():
@@ -110,4 +120,4 @@ def test_link_metrics_rejects_other_right_hand_sides():
     r = torch.empty(16, dtype=torch.float64, device="cuda")
     b = torch.empty(1, dtype=torch.float64, device="cuda")
     with pytest.raises(vrk.VrkError):
-        plan.link_metrics([E], [r], [b])
+        plan.link_metrics([E], [r], [b], 0.1)

@@ -79,7 +79,7 @@ def test_rates_after_fifteen_iterations():
         E = torch.zeros((d.k, d.k), dtype=torch.complex64, device="cuda")
         R = torch.zeros(d.k, dtype=torch.float64, device="cuda")
         B = torch.zeros(1, dtype=torch.float64, device="cuda")
-        plan.link_metrics([E], [R], [B])
+        plan.link_metrics([E], [R], [B], d.xi)   # xi = sigma^2 / rho on this setting
         torch.cuda.synchronize()
         Xo = _oracle_X(d, variant, 15)
         _, bo, ro = oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi, Xo)
@@ -98,7 +98,8 @@ def test_precoder_helper_on_the_paper_setting():
     from paper_2501_10689_amd import vrk
     d = _drop(3, snr_db=10.0)
     Hd = torch.tensor(d.H, dtype=torch.complex64, device="cuda")
-    X, E, rate, beta = vrk.precoder(Hd, d.vr_start, d.vr_len, d.xi, tol=1e-6, vr_mask=d.vr_mask, n_sub=d.n_sub)
+    X, E, rate, beta = vrk.precoder(Hd, d.vr_start, d.vr_len, d.xi, d.xi, tol=1e-6, vr_mask=d.vr_mask,
+                                    n_sub=d.n_sub)
     torch.cuda.synchronize()
     Xr = oracle.precoder(d.H, d.vr_start, d.vr_len, d.xi)
     Er, br, rr = oracle.link_metrics(d.H, d.vr_start, d.vr_len, d.xi, Xr)

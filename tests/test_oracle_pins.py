@@ -621,7 +621,7 @@ def test_rzf_gradient_matches_torch_autograd():
 
 # ---------------------------------------------------------------------------
 # Precoding matrix and link metrics (signal model / spectral efficiency of
-# Sec. II, RZF precoder and power budget, Remark 1, NMSE of Sec. VI)
+# Sec. II, RZF precoder and power budget, Remark 1, NMSE of Sec. VII)
 # ---------------------------------------------------------------------------
 
 def test_single_user_rate_is_mrt_capacity():
