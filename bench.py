@@ -271,8 +271,9 @@ def algorithmic_flops(engine, variant, band, band_f, band_v, overlap, iters, vec
 
 
 # Kernel sources whose rocprofv3 counters the committed traffic files hold.
-TRAFFIC_SOURCES = ["paper_2501_10689_amd/csrc/mfma_engine.hip", "paper_2501_10689_amd/csrc/device_common.h",
-                   "paper_2501_10689_amd/csrc/vrk_desc.h", "paper_2501_10689_amd/csrc/kernels.h"]
+TRAFFIC_SOURCES = ["paper_2501_10689_amd/csrc/mfma_engine.hip", "paper_2501_10689_amd/csrc/wave_engine.hip",
+                   "paper_2501_10689_amd/csrc/device_common.h", "paper_2501_10689_amd/csrc/vrk_desc.h",
+                   "paper_2501_10689_amd/csrc/kernels.h"]
 
 
 def measured_traffic(workload, kernel_prefix):
@@ -493,6 +494,8 @@ def main():
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--tile-waves", type=int, default=0, choices=[0, 8, 16])
     ap.add_argument("--persistent", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--wave-tiles", type=int, default=0, choices=[-1, 0, 1, 2, 4, 8],
+                    help="MFMA engine, AHK / VR-OAHK: waves per wave-owned tile (-1 block tiles, 0 auto)")
     ap.add_argument("--autotune", action="store_true", help="pick engine/tiles with vrk_autotune first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -541,7 +544,7 @@ def main():
                                      vr_mask=d.vr_mask, n_sub=d.n_sub))
     B = sum(d.nrhs for d in drops)
     opts = vrk.options(variant=args.variant, dtype=dname, engine=engine_opt, tol=tol,
-                       tile_waves=args.tile_waves, persistent=args.persistent)
+                       tile_waves=args.tile_waves, persistent=args.persistent, wave_tiles=args.wave_tiles)
     tuned_ms = None
     if args.autotune:
         opts, tuned_ms = vrk.autotune(specs, opts, reps=3)
@@ -641,8 +644,12 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
     if engine == "mfma":
         vid = {"grk": 0, "vr_ogrk": 0, "ahk": 1, "vr_oahk": 3}[args.variant]
-        roof["traffic"] = measured_traffic(wl, "void (anonymous namespace)::k_mfma_solve<%d, %d, %d, %s>" % (
-            int(eng[2]), int(eng[6]), vid, "true" if int(eng[4]) else "false"))
+        if int(eng[10]):
+            kname = "void (anonymous namespace)::k_wave_solve<%d, %d, %d>" % (int(eng[10]), int(eng[11]), vid)
+        else:
+            kname = "void (anonymous namespace)::k_mfma_solve<%d, %d, %d, %s>" % (
+                int(eng[2]), int(eng[6]), vid, "true" if int(eng[4]) else "false")
+        roof["traffic"] = measured_traffic(wl, kname)
     roof["kernel"] = "forward solve (%s engine, %s)" % (engine, args.variant)
     roof["kernel_ms"] = solve_ms
     roof["flops_per_launch"] = flops
@@ -668,6 +675,7 @@ def main():
                   % ms_eager,
         "config": {"workload": WORKLOADS[wl], "variant": args.variant, "engine": engine,
                    "tile_waves": int(eng[2]), "tile_waves_adjoint": int(eng[9]), "persistent": int(eng[4]),
+                   "wave_owned_tile_waves": int(eng[10]), "wave_owned_blocks_per_wave": int(eng[11]),
                    "entries_per_thread": int(eng[6]), "drops": len(drops), "vectors": B, "tol": tol,
                    "step": "vrk_plan_refresh (row norms, channel and Gram tiles) + vrk_solve + vrk_solve_adjoint"},
         "orthogonal_set_mean": float(np.mean([len(plan.query(j, vrk.Q_FSET)) for j in range(len(drops))])),

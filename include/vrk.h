@@ -149,6 +149,15 @@ typedef struct {
     int32_t persistent;  /* MFMA engine: 1 = one workgroup per resident slot, draining
                             per-XCD work queues (drops assigned by cost); 0 = one
                             workgroup per 16-RHS tile */
+    int32_t wave_tiles;  /* MFMA engine, AHK and VR-OAHK: how the waves of a tile share it.
+                            -1: block tiles (tile_waves waves split every Gram product of
+                            one tile); 1, 2, 4 or 8: wave-owned tiles, that many waves per
+                            tile, each owning whole 16-user row blocks (at most 4 each, 2
+                            with 8 waves) with its state in registers, several tiles per
+                            compute unit, XCD-contiguous work order; 0: auto (wave-owned
+                            tiles with two row blocks per wave when tiles x waves per
+                            tile >= 4096, every drop has at most 16 chunks of F users
+                            and tile_waves, persistent are unset) */
 } vrk_options;
 
 typedef struct vrk_plan vrk_plan;
@@ -285,7 +294,9 @@ typedef enum {
                             RHS splits of the MFMA adjoint gradient tiles, RHS splits of
                             the blocks of C = sum_b v_b mu_b^H of the MFMA adjoint,
                             tile_waves of the MFMA adjoint solve (8 when every drop has
-                            at most 64 users and tile_waves is auto, else tile_waves)] */
+                            at most 64 users and tile_waves is auto, else tile_waves),
+                            waves per wave-owned tile (0: block tiles), row blocks per
+                            wave of the wave-owned tiles] */
     VRK_Q_TILES = 6,     /* [residual tiles, aggregation tiles, band entries, Gram tiles] per problem */
     VRK_Q_GRAD = 7       /* MFMA adjoint gradient of the whole plan: [band tiles, RHS splits of a band
                             tile, blocks of C, RHS splits of a C block, runs of the reduction kernel,

@@ -46,6 +46,15 @@ hipError_t vrk_launch_mfma_solve(const VrkSolveArgs &a, const VrkWork *work, con
                                  int32_t waves, int32_t ep, size_t lds_bytes, hipStream_t s, int mode,
                                  int *blocks_per_cu);
 
+// Wave-owned MFMA engine (AHK and VR-OAHK, complex64): one workgroup of
+// `waves` waves per 16-RHS tile, each wave owning up to `bpw` (4 or 2)
+// 16-user row blocks; supported for waves 1, 2, 4 with bpw 4 and 1, 2, 4, 8
+// with bpw 2, kpad <= 16 waves bpw. mode as vrk_launch_mfma_solve.
+int vrk_wave_supported(int32_t variant, int32_t kpad, int32_t waves, int32_t bpw);
+size_t vrk_wave_lds_bytes(int32_t variant, int32_t kpad, int32_t waves);
+hipError_t vrk_launch_wave_solve(const VrkSolveArgs &a, const VrkWork *work, int32_t nitems, int32_t waves, int32_t bpw,
+                                 size_t lds, hipStream_t s, int mode, int *blocks_per_cu);
+
 // Adjoint pieces: b = H g (right-hand side of the adjoint solve) and the
 // gradient assembly.
 hipError_t vrk_launch_adjoint_rhs(const VrkDesc *desc, int32_t nprob, int32_t max_rhs,

@@ -75,6 +75,7 @@ struct ProbPlan {
     bool keep_v = false;          // V goes to the workspace (caller gave none; adjoint or S = I_K shape)
     bool stage_h = false;         // vector engine: H's VR entries staged in LDS
     std::vector<int32_t> gaps;    // (user, first antenna, length) of hidden runs inside the hulls
+    std::vector<int32_t> fch;     // 4-user chunks (VR-start order) holding a user of F, ascending
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
     // workspace offsets
@@ -83,7 +84,7 @@ struct ProbPlan {
         o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
     size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_gmnf = 0, o_fpos = 0, o_mf = 0;
-    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0, o_gaps = 0, o_mask = 0;
+    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0, o_gaps = 0, o_mask = 0, o_fch = 0;
 };
 
 }  // namespace
@@ -97,6 +98,10 @@ struct vrk_plan {
     // at most 64 users and the tile size is left to the plan, else the same)
     int32_t waves_adj = 8, ep_adj = 0, grid_adj = 0;
     size_t lds_adj = 0;
+    // MFMA engine, wave-owned tiles (AHK, VR-OAHK): waves per tile and row
+    // blocks per wave (0: block tiles), LDS per tile
+    int32_t wave_T = 0, wave_bpw = 0;
+    size_t lds_wave = 0;
     size_t table_end = 0, ws_bytes = 0, o_desc = 0, o_work = 0;
     int64_t total_rhs = 0, max_tiles = 0;
     int32_t max_rhs = 0, max_k = 0;
@@ -384,6 +389,10 @@ void build_tables(ProbPlan &q)
     q.xoff[K] = (int32_t)q.xidx.size();
     build_mis(q);
     build_colours(q);
+    q.fch.clear();
+    for (int f : q.flist) q.fch.push_back(q.pos[f] / 4);
+    std::sort(q.fch.begin(), q.fch.end());
+    q.fch.erase(std::unique(q.fch.begin(), q.fch.end()), q.fch.end());
     // gather lists: users meeting each 64-antenna block
     const int ngb = (N + VRK_GATHER_BLOCK - 1) / VRK_GATHER_BLOCK;
     q.gb_off.assign(ngb + 1, 0);
@@ -539,6 +548,9 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     if (o.max_iters < 1) return fail(VRK_EINVAL, "max_iters must be >= 1");
     if (o.tile_waves != 0 && o.tile_waves != 8 && o.tile_waves != 16)
         return fail(VRK_EINVAL, "tile_waves %d", o.tile_waves);
+    if (o.wave_tiles != -1 && o.wave_tiles != 0 && o.wave_tiles != 1 && o.wave_tiles != 2 && o.wave_tiles != 4 &&
+        o.wave_tiles != 8)
+        return fail(VRK_EINVAL, "wave_tiles %d", o.wave_tiles);
     for (int i = 0; i < nprob; ++i) {
         vrk_status s = validate_problem(probs[i], i, o);
         if (s != VRK_OK) return s;
@@ -634,6 +646,52 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
                 pl->waves_adj = 8;
                 pl->ep_adj = vrk_mfma_entries(max_kpad, 8);
                 pl->lds_adj = l8;
+            }
+        }
+        // Wave-owned tiles for the aggregated sweeps: forced by wave_tiles > 0,
+        // or chosen when the batch is many tiles deep (several tiles per
+        // compute unit) and the block tiles are not asked for
+        {
+            int64_t ntiles = 0;
+            size_t max_fch = 0;
+            for (auto &q : pl->pp) {
+                ntiles += q.ntile;
+                max_fch = std::max(max_fch, q.fch.size());
+            }
+            const bool agg = o.variant == VRK_AHK || o.variant == VRK_VR_OAHK;
+            const bool fits = o.variant != VRK_VR_OAHK || max_fch <= VRK_WAVE_FCHUNKS;
+            int32_t T = 0;
+            if (o.wave_tiles > 0) {
+                if (!agg || !fits || o.persistent) {
+                    delete pl;
+                    return fail(VRK_EUNSUPPORTED,
+                                "wave-owned tiles need AHK or VR-OAHK, at most %d chunks of F users per drop "
+                                "(here %zu) and no persistent launch", VRK_WAVE_FCHUNKS, max_fch);
+                }
+                T = o.wave_tiles;
+            } else if (o.wave_tiles == 0 && agg && fits && o.tile_waves == 0 && !o.persistent) {
+                // two row blocks per wave (the 128-register build: four waves
+                // per SIMD), so the waves per tile follow K; taken when the
+                // batch has enough tiles for about four waves per SIMD
+                const int32_t nubm = max_kpad / VRK_UB;
+                int32_t t = 1;
+                while (2 * t < nubm) t *= 2;
+                if (ntiles * t >= 4096) T = t;
+            }
+            if (T > 0) {
+                const int32_t nubm = max_kpad / VRK_UB;
+                const int32_t bpw = (nubm + T - 1) / T <= 2 ? 2 : 4;
+                if (!vrk_wave_supported(o.variant, max_kpad, T, bpw)) {
+                    delete pl;
+                    return fail(VRK_EUNSUPPORTED, "wave-owned tiles: %d waves cannot own %d row blocks", T, nubm);
+                }
+                pl->wave_T = T;
+                pl->wave_bpw = bpw;
+                pl->lds_wave = vrk_wave_lds_bytes(o.variant, max_kpad, T);
+                if (pl->lds_wave > 160 * 1024) {
+                    delete pl;
+                    return fail(VRK_EUNSUPPORTED, "wave-owned tiles need %zu bytes of LDS", pl->lds_wave);
+                }
             }
         }
         // Work items (problem, tile). Problems go to the XCD queues by cost,
@@ -751,6 +809,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_cpdiag = cv.take(4 * q.cp_diag.size());
         q.o_gaps = cv.take(4 * q.gaps.size());
         q.o_mask = cv.take(8 * q.mask.size());
+        q.o_fch = cv.take(4 * q.fch.size());
     }
     pl->table_end = cv.off;
     pl->o_link = cv.take(sizeof(VrkLinkOut) * nprob);
@@ -848,6 +907,7 @@ static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
         put(img, q.o_fpos, q.fpos);
         put(img, q.o_gaps, q.gaps);
         put(img, q.o_mask, q.mask);
+        put(img, q.o_fch, q.fch);
         VrkDesc &d = descs[i];
         std::memset(&d, 0, sizeof d);
         const vrk_problem &p = q.p;
@@ -908,6 +968,8 @@ static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
         d.vmask = (const uint64_t *)(base + q.o_mask);
         d.ngap = (int32_t)(q.gaps.size() / 3);
         d.gaps = (const int32_t *)(base + q.o_gaps);
+        d.nfch = (int32_t)q.fch.size();
+        d.fch = (const int32_t *)(base + q.o_fch);
         (void)eb;
     }
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());
@@ -944,6 +1006,12 @@ static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
             a.adjoint = 1;
             e = vrk_launch_mfma_solve(a, nullptr, qa, 1, pl->waves_adj, pl->ep_adj, pl->lds_adj, s, 1, &bpc_adj);
             if (e != hipSuccess) return hip_fail(e, "MFMA kernel attributes (adjoint)");
+        }
+        if (pl->wave_T) {
+            int bw = 0;
+            e = vrk_launch_wave_solve(a, nullptr, 1, pl->wave_T, pl->wave_bpw, pl->lds_wave, s, 1, &bw);
+            if (e != hipSuccess) return hip_fail(e, "wave-owned kernel attributes");
+            bpc = bpc_adj = bw;
         }
         int dev = 0, cus = 0;
         e = hipGetDevice(&dev);
@@ -1074,10 +1142,14 @@ static vrk_status run_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float 
         int32_t *qv = reinterpret_cast<int32_t *>(pl->d_ws + pl->o_queue);
         VrkQueue q{};
         if (pl->persistent) q = VrkQueue{qv, qv + VRK_NQUEUE, qv + 2 * VRK_NQUEUE};
-        e = adjoint ? vrk_launch_mfma_solve(a, reinterpret_cast<const VrkWork *>(pl->d_ws + pl->o_work), q,
-                                            pl->grid_adj, pl->waves_adj, pl->ep_adj, pl->lds_adj, s, 0, nullptr)
-                    : vrk_launch_mfma_solve(a, reinterpret_cast<const VrkWork *>(pl->d_ws + pl->o_work), q, pl->grid,
-                                            pl->waves, pl->ep, pl->lds, s, 0, nullptr);
+        const VrkWork *wl = reinterpret_cast<const VrkWork *>(pl->d_ws + pl->o_work);
+        if (pl->wave_T)
+            e = vrk_launch_wave_solve(a, wl, (int32_t)pl->work.size(), pl->wave_T, pl->wave_bpw, pl->lds_wave, s, 0,
+                                      nullptr);
+        else
+            e = adjoint ? vrk_launch_mfma_solve(a, wl, q, pl->grid_adj, pl->waves_adj, pl->ep_adj, pl->lds_adj, s, 0,
+                                                nullptr)
+                        : vrk_launch_mfma_solve(a, wl, q, pl->grid, pl->waves, pl->ep, pl->lds, s, 0, nullptr);
     } else
         e = vrk_launch_vec_solve(a, pl->lds, s);
     if (e != hipSuccess) return hip_fail(e, "solve kernel");
@@ -1186,7 +1258,7 @@ int64_t vrk_plan_query(const vrk_plan *pl, int32_t prob, int32_t what, int32_t *
     case VRK_Q_XIDX: v = q.xidx; break;
     case VRK_Q_ENGINE:
         v = {pl->engine, pl->schedule, pl->waves, (int32_t)pl->lds, pl->persistent, pl->grid, pl->ep, pl->gsplit,
-             pl->csplit, pl->engine == VRK_ENGINE_MFMA ? pl->waves_adj : pl->waves};
+             pl->csplit, pl->engine == VRK_ENGINE_MFMA ? pl->waves_adj : pl->waves, pl->wave_T, pl->wave_bpw};
         break;
     case VRK_Q_TILES: v = {(int32_t)q.n_ha, (int32_t)q.n_hg, (int32_t)q.band, (int32_t)q.n_gm}; break;
     case VRK_Q_GRAD: {

@@ -85,7 +85,14 @@ struct VrkDesc {
     int32_t stage_h, pad3;
     const uint64_t *vmask;
     const int32_t *gaps;
+    // wave-owned MFMA engine, VR-OAHK: the 4-user chunks (VR-start order)
+    // holding a user of F, ascending; at most VRK_WAVE_FCHUNKS
+    int32_t nfch, pad4;
+    const int32_t *fch;
 };
+
+// Chunks of F users the wave-owned engine keeps in its compact buffer.
+#define VRK_WAVE_FCHUNKS 16
 
 // Outputs of the link metrics of one problem (device pointers): the K x K
 // effective channel E (row-major, lde), the K rates and beta.

@@ -12,7 +12,7 @@ def to_dev(a, dtype):
 
 def run_plan(drops, variant="vr_oahk", select="baiwu", dtype="c64", engine="auto", tol=1e-5,
              max_iters=100000, seed=0, schedule="auto", adjoint_g=None, tile_waves=0,
-             persistent=0, x_pad=0):
+             persistent=0, x_pad=0, wave_tiles=0):
     """drops: list of (H, vs, vl, S, xi) numpy tuples, or (H, vs, vl, S, xi,
     vr_mask, n_sub) for the subarray VR model. Returns per-drop dicts with
     X, V (numpy complex128) and stats, plus the plan. x_pad > 0 gives the X
@@ -39,7 +39,7 @@ def run_plan(drops, variant="vr_oahk", select="baiwu", dtype="c64", engine="auto
         specs.append(sp)
     o = vrk.options(variant=variant, select=select, dtype=dtype, engine=engine, tol=tol,
                     max_iters=max_iters, seed=seed, schedule=schedule, tile_waves=tile_waves,
-                    persistent=persistent)
+                    persistent=persistent, wave_tiles=wave_tiles)
     plan = vrk.Plan(specs, o)
     st = plan.stats_buffers()
     plan.solve(stats=st)

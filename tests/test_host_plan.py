@@ -243,3 +243,31 @@ def test_binding_rejects_host_tensors_before_the_library():
     sp = vrk.ProblemSpec(H, np.zeros(4, np.int32), np.full(4, 8, np.int32), 1.0, S, X)
     with pytest.raises(ValueError, match="device"):
         vrk.Plan([sp], vrk.options())
+
+
+def test_wave_owned_tile_choice():
+    """Aggregated sweeps get wave-owned tiles (two 16-user blocks per wave,
+    so the waves per tile follow K) when tiles x waves per tile reach 4096;
+    fewer tiles, the greedy sweeps, an explicit block-tile request or tile
+    size keep block tiles; unsupported requests are refused."""
+    rng = np.random.default_rng(3)
+    H, vs, vl, xi = random_problem(rng, 1024, 64)
+    big = vrk.host_plan(1024, 64, vs, vl, nrhs=2048 * 16, variant="vr_oahk")
+    assert tuple(big.query(vrk.Q_ENGINE)[10:12]) == (2, 2)
+    for kw in (dict(nrhs=2047 * 16), dict(nrhs=2048 * 16, variant="grk"), dict(nrhs=2048 * 16, wave_tiles=-1),
+               dict(nrhs=2048 * 16, tile_waves=16)):
+        kw.setdefault("variant", "vr_oahk")
+        assert vrk.host_plan(1024, 64, vs, vl, **kw).query(vrk.Q_ENGINE)[10] == 0, kw
+    H2, vs2, vl2, _ = random_problem(rng, 4096, 256, lo=256, hi=1024)
+    p = vrk.host_plan(4096, 256, vs2, vl2, nrhs=512 * 16, variant="ahk")
+    assert tuple(p.query(vrk.Q_ENGINE)[10:12]) == (8, 2)
+    H3, vs3, vl3, _ = random_problem(rng, 512, 30)
+    assert tuple(vrk.host_plan(512, 30, vs3, vl3, nrhs=4096 * 16, variant="vr_oahk")
+                 .query(vrk.Q_ENGINE)[10:12]) == (1, 2)
+    assert vrk.host_plan(512, 30, vs3, vl3, nrhs=4095 * 16, variant="vr_oahk").query(vrk.Q_ENGINE)[10] == 0
+    assert tuple(vrk.host_plan(4096, 256, vs2, vl2, nrhs=64, variant="ahk", wave_tiles=8)
+                 .query(vrk.Q_ENGINE)[10:12]) == (8, 2)
+    with pytest.raises(vrk.VrkError):
+        vrk.host_plan(4096, 256, vs2, vl2, nrhs=64, variant="ahk", wave_tiles=2)   # 16 blocks on 2 waves
+    with pytest.raises(vrk.VrkError):
+        vrk.host_plan(1024, 64, vs, vl, nrhs=64, variant="grk", wave_tiles=1)
