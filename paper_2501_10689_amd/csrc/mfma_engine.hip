@@ -47,6 +47,9 @@ struct MfmaLds {
     int *gmc;    // copy of the Gram chunk columns (at most nub * kpad / 4)
     int *gmnf;   // per row block: Gram chunks holding a user of F (a multiple of 4)
     int *rsel;   // per sorted row: 1 user of F, 2 user of V, 0 padding
+    int *gidx;   // greedy: entry of the Gram chunk list of (row block, chunk), or -1: [nub][kpad / 4]
+    int *selk;   // greedy: per column, the sorted position of the chosen row (-1: none)
+    float2 *selg;   // greedy: per column, gamma of the chosen row
 };
 
 // Column state beyond the public flags: stopped on the maintained residual,
@@ -73,7 +76,7 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, bool
     };
     const size_t tile = (size_t)kpad * 16 * 8;
     char *R = take(greedy ? tile : 0);
-    char *PF = take(tile);
+    char *PF = take(greedy ? 0 : tile);   // the greedy step takes one Gram column, no operand
     char *PV = take(tile);
     char *MP = take(tile * gram_parts(kpad / 16, W));
     char *nrm = take((size_t)kpad * 4);
@@ -87,6 +90,9 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, bool
     char *rsel = take((size_t)kpad * 4);
     char *fpos = take(16 * 4);
     char *mf = take((size_t)kpad * nmf * 8);
+    char *gidx = take(greedy ? (size_t)(kpad / 16) * (kpad / 4) * 4 : 0);
+    char *selk = take(greedy ? 16 * 4 : 0);
+    char *selg = take(greedy ? 16 * 8 : 0);
     // test the LDS base, not L: L points into a caller's register-resident
     // struct, and comparing its address would pin that struct to memory
     if (base) {
@@ -107,6 +113,9 @@ __host__ __device__ inline size_t mfma_lds_layout(int kpad, int nab, int W, bool
         L->rsel = (int *)rsel;
         L->fpos = (int *)fpos;
         L->MF = (float2 *)mf;
+        L->gidx = (int *)gidx;
+        L->selk = (int *)selk;
+        L->selg = (float2 *)selg;
     }
     return off;
 }
@@ -471,6 +480,18 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     for (int i = tid; i <= c.nub; i += W * 64) L.gmoff[i] = gmem(d.gm_off)[i];
     for (int i = tid; i < gmem(d.gm_off)[c.nub]; i += W * 64) L.gmc[i] = max(c.gm_c[i], 0);   // padding: zero tile
     for (int i = tid; i < c.nub; i += W * 64) L.gmnf[i] = gmem(d.gm_nf)[i];
+    if (greedy) {
+        // (row block, chunk) -> entry of the block's Gram chunk list
+        for (int i = tid; i < c.nub * (kpad / 4); i += W * 64) L.gidx[i] = -1;
+        __syncthreads();
+        for (int mb = 0; mb < c.nub; ++mb) {
+            const int e0 = gmem(d.gm_off)[mb], e1 = gmem(d.gm_off)[mb + 1];
+            for (int e = e0 + tid; e < e1; e += W * 64) {
+                const int uc = c.gm_c[e];
+                if (uc >= 0) L.gidx[mb * (kpad / 4) + uc] = e;
+            }
+        }
+    }
     // > 0: VALU orthogonal half-step from MF (never with four entries per
     // thread: its registers are needed elsewhere)
     const int nmf = EP >= 4 ? 0 : d.nmf;
@@ -542,7 +563,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                 ninv[k] = L.ninv[ku];
             }
             pp[k] = phi_first(k);
-            L.PF[ku * 16 + j] = pp[k];
+            if (!greedy) L.PF[ku * 16 + j] = pp[k];
             if (greedy) L.R[ku * 16 + j] = rr[k];
             r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
             num += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
@@ -585,11 +606,15 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
 
             if constexpr (greedy) {
                 // greedy selection, one wave per column, from the residuals in
-                // LDS; phi is one-hot with gamma (PF is zero elsewhere). M's
-                // sparsity confines the residual change to the rows of X_pick
-                // (Theorem 2).
+                // LDS: column cc projects onto row i with gamma = r_i / ||a_i||^2.
+                // In the dual that step is q_i += gamma, r -= gamma M[:, i]: only
+                // the rows of X_i change (Theorem 2: M[:, i] is zero elsewhere),
+                // taken from the one Gram tile column holding i per row block.
                 for (int cc = w; cc < 16; cc += W) {
-                    if (!__shfl(act, cc, 64)) continue;
+                    if (!__shfl(act, cc, 64)) {
+                        if (lane == 0) L.selk[cc] = -1;
+                        continue;
+                    }
                     const float u = (float)uniform24(a.seed, t_it, b0 + cc, c.prob);
                     const float2 *Rl = L.R;
                     const float *nl = L.nrm;
@@ -603,24 +628,28 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                         const int ku = L.posl[i];
                         const float inv = 1.f / L.nrm[ku];
                         const float2 r = L.R[ku * 16 + cc];
-                        L.PF[ku * 16 + cc] = float2{r.x * inv, r.y * inv};
+                        L.selk[cc] = ku;
+                        L.selg[cc] = float2{r.x * inv, r.y * inv};
                     }
                 }
                 __syncthreads();
-                gram_part<W, GR>(c, L.PF, gr, false, false);
-                __syncthreads();
+                const int kp = L.selk[j];
+                const float2 gmv = L.selg[j];
                 r2 = 0.f;
 #pragma unroll
                 for (int k = 0; k < EP; ++k) {
                     const int ku = own(k);
                     if (ku < kpad) {
-                        const float2 m = gram_sum(c, np, ku, j), f = L.PF[ku * 16 + j];
-                        if (act) {
-                            qq[k] = float2{qq[k].x + f.x, qq[k].y + f.y};
-                            rr[k] = float2{rr[k].x - m.x, rr[k].y - m.y};
+                        if (kp >= 0) {
+                            const int e = L.gidx[(ku >> 4) * (kpad / 4) + (kp >> 2)];
+                            if (e >= 0) {
+                                const float2 m = c.GM[(int64_t)e * 64 + (ku & 15) + 16 * (kp & 3)];
+                                rr[k] = float2{rr[k].x - (m.x * gmv.x - m.y * gmv.y),
+                                               rr[k].y - (m.x * gmv.y + m.y * gmv.x)};
+                            }
+                            if (ku == kp) qq[k] = float2{qq[k].x + gmv.x, qq[k].y + gmv.y};
                             L.R[ku * 16 + j] = rr[k];
                         }
-                        L.PF[ku * 16 + j] = float2{0.f, 0.f};
                         r2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                     }
                 }
@@ -734,7 +763,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
                 rr[k] = float2{s0.x - mq.x, s0.y - mq.y};
                 if (greedy) L.R[ku * 16 + j] = rr[k];
                 pp[k] = phi_first(k);
-                L.PF[ku * 16 + j] = pp[k];
+                if (!greedy) L.PF[ku * 16 + j] = pp[k];
                 t2 += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
                 tn += pp[k].x * rr[k].x + pp[k].y * rr[k].y;
             }
