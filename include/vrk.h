@@ -158,12 +158,17 @@ typedef struct {
                             tiles with two row blocks per wave when tiles x waves per
                             tile >= 4096, every drop has at most 16 chunks of F users
                             and tile_waves, persistent are unset) */
+    int32_t check_every; /* the stop rule is tested when the iteration count is a multiple of
+                            it (and at max_iters); 0 or 1: every iteration. Later tests only
+                            add iterations: the sweeps never increase the error (Lemma 2,
+                            Lemma 3), so x stays within the tolerance; iteration counts are
+                            multiples of it unless the cap stopped the column. */
 } vrk_options;
 
 typedef struct vrk_plan vrk_plan;
 
 /* Fills o with: VR_OAHK, BAIWU, C64, AUTO engine, tol 1e-5,
- * max_iters 100000, seed 0, schedules and tiles auto. */
+ * max_iters 100000, seed 0, schedules and tiles auto, check_every 1. */
 void vrk_default_options(vrk_options *o);
 
 /* Host only (no device access): validates nprob problems, builds the VR

@@ -16,6 +16,7 @@ struct VrkSolveArgs {
     int32_t adjoint;          // 0: S -> X, V; 1: Sadj -> Xadj, GS
     double tol;
     int64_t max_iters;
+    int64_t check_every;      // stop rule tested when the iteration count is a multiple (>= 1)
     uint64_t seed;
     int32_t *iters;
     float *relres;

@@ -594,8 +594,9 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
         GramRegs<GR> gr;
         gram_load<W, GR>(c, gr);
         for (;;) {
-            // stop rule on the maintained residual
-            if (act) {
+            // stop rule on the maintained residual, every check_every
+            // iterations and at the cap
+            if (act && (a.check_every == 1 || t_it % a.check_every == 0 || t_it >= a.max_iters)) {
                 rel = sqrtf(r2) / sn;
                 its = (int)t_it;
                 if (!isfinite(rel)) { fl = VRK_FLAG_NONFINITE; act = false; }

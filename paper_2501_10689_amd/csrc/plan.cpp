@@ -528,6 +528,8 @@ void vrk_default_options(vrk_options *o)
     o->schedule = VRK_SCHED_AUTO;
     o->tile_waves = 0;
     o->persistent = 0;
+    o->wave_tiles = 0;
+    o->check_every = 1;
 }
 
 vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_options *opt,
@@ -546,6 +548,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     if (o.schedule < 0 || o.schedule > 2) return fail(VRK_EINVAL, "schedule %d", o.schedule);
     if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(VRK_EINVAL, "tol %g", o.tol);
     if (o.max_iters < 1) return fail(VRK_EINVAL, "max_iters must be >= 1");
+    if (o.check_every < 0) return fail(VRK_EINVAL, "check_every must be >= 0 (0: every iteration)");
     if (o.tile_waves != 0 && o.tile_waves != 8 && o.tile_waves != 16)
         return fail(VRK_EINVAL, "tile_waves %d", o.tile_waves);
     if (o.wave_tiles != -1 && o.wave_tiles != 0 && o.wave_tiles != 1 && o.wave_tiles != 2 && o.wave_tiles != 4 &&
@@ -1132,6 +1135,7 @@ static vrk_status run_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float 
     a.adjoint = adjoint;
     a.tol = pl->opt.tol;
     a.max_iters = pl->opt.max_iters;
+    a.check_every = pl->opt.check_every > 0 ? pl->opt.check_every : 1;
     a.seed = pl->opt.seed;
     a.iters = d_iters;
     a.relres = d_relres;

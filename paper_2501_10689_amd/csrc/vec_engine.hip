@@ -488,13 +488,16 @@ __global__ void __launch_bounds__(kThreads) k_vec_solve(VrkSolveArgs a)
                 residual_rows(c, nullptr, K);
                 __syncthreads();
             }
-            R r2 = 0;
-            for (int i = tid; i < K; i += kThreads) r2 += cnorm2(c.r[i]);
-            r2 = block_sum(r2, c.red + 3 * kWaves);
-            rel = sqrt(r2) / snorm;
-            if (!isfinite(rel)) { flags = VRK_FLAG_NONFINITE; break; }
-            if (rel <= (R)a.tol) { flags = VRK_FLAG_CONVERGED; break; }
-            if (t >= a.max_iters) { flags = VRK_FLAG_MAXITER; break; }
+            // stop rule every check_every iterations (and at the cap)
+            if (a.check_every == 1 || t % a.check_every == 0 || t >= a.max_iters) {
+                R r2 = 0;
+                for (int i = tid; i < K; i += kThreads) r2 += cnorm2(c.r[i]);
+                r2 = block_sum(r2, c.red + 3 * kWaves);
+                rel = sqrt(r2) / snorm;
+                if (!isfinite(rel)) { flags = VRK_FLAG_NONFINITE; break; }
+                if (rel <= (R)a.tol) { flags = VRK_FLAG_CONVERGED; break; }
+                if (t >= a.max_iters) { flags = VRK_FLAG_MAXITER; break; }
+            }
             if (variant == 0 || variant == 2) {
                 if (w == 0) {
                     R u = (R)uniform24(a.seed, t, b, prob);

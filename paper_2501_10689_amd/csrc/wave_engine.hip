@@ -319,8 +319,9 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
     int64_t t_it = 0;
     for (;;) {
         for (;;) {
-            // stop rule on the maintained residual
-            if (act) {
+            // stop rule on the maintained residual, every check_every
+            // iterations and at the cap
+            if (act && (a.check_every == 1 || t_it % a.check_every == 0 || t_it >= a.max_iters)) {
                 rel = sqrtf(r2) / sn;
                 its = (int)t_it;
                 if (!isfinite(rel)) { fl = VRK_FLAG_NONFINITE; act = false; }

@@ -44,7 +44,7 @@ class Options(C.Structure):
     _fields_ = [("variant", C.c_int32), ("select", C.c_int32), ("dtype", C.c_int32),
                 ("engine", C.c_int32), ("tol", C.c_double), ("max_iters", C.c_int64),
                 ("seed", C.c_uint64), ("schedule", C.c_int32), ("tile_waves", C.c_int32),
-                ("persistent", C.c_int32), ("wave_tiles", C.c_int32)]
+                ("persistent", C.c_int32), ("wave_tiles", C.c_int32), ("check_every", C.c_int32)]
 
 
 class LinkOut(C.Structure):
@@ -108,7 +108,8 @@ def _check(st: int):
 
 
 def options(variant="vr_oahk", select="baiwu", dtype="c64", engine="auto", tol=1e-5,
-            max_iters=100000, seed=0, schedule="auto", tile_waves=0, persistent=0, wave_tiles=0) -> Options:
+            max_iters=100000, seed=0, schedule="auto", tile_waves=0, persistent=0, wave_tiles=0,
+            check_every=1) -> Options:
     o = Options()
     lib().vrk_default_options(C.byref(o))
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
@@ -122,6 +123,7 @@ def options(variant="vr_oahk", select="baiwu", dtype="c64", engine="auto", tol=1
     o.tile_waves = int(tile_waves)
     o.persistent = int(persistent)
     o.wave_tiles = int(wave_tiles)
+    o.check_every = int(check_every)
     return o
 
 

@@ -237,3 +237,41 @@ def test_refresh_after_the_channel_changes(engine):
         torch.cuda.synchronize()
         for a, (x, gh) in zip(sp, want):
             assert torch.equal(a.X, x) and torch.equal(a.GH, gh)
+
+
+@pytest.mark.parametrize("engine,variant,wave_tiles", [("vector", "vr_oahk", 0), ("vector", "grk", 0),
+                                                      ("mfma", "vr_oahk", -1), ("mfma", "grk", -1),
+                                                      ("mfma", "ahk", 2)])
+def test_check_every(engine, variant, wave_tiles):
+    """The stop rule tested every third iteration: every column still meets
+    the tolerance and the RZF, its count is a multiple of three (on the
+    vector engine the first multiple at or past the every-iteration count),
+    and check_every 1 is the default behaviour bit for bit."""
+    d = synth.make_workload("many_rhs", nrhs=35, nt=512, k=40)[0]
+    drop = [(d.H, d.vr_start, d.vr_len, d.S, d.xi)]
+    X, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
+    base, _ = run_plan(drop, variant=variant, engine=engine, tol=1e-5, wave_tiles=wave_tiles)
+    from paper_2501_10689_amd import vrk
+    import torch
+    sp = vrk.ProblemSpec(torch.from_numpy(d.H).to("cuda", torch.complex64), d.vr_start, d.vr_len, d.xi,
+                         torch.from_numpy(d.S).to("cuda", torch.complex64),
+                         torch.zeros((35, 512), dtype=torch.complex64, device="cuda"),
+                         torch.zeros((35, 40), dtype=torch.complex64, device="cuda"))
+    for ce in (1, 3):
+        plan = vrk.Plan([sp], vrk.options(variant=variant, engine=engine, tol=1e-5, wave_tiles=wave_tiles,
+                                          check_every=ce))
+        st = plan.stats_buffers()
+        plan.solve(stats=st)
+        torch.cuda.synchronize()
+        it, rel, fl = [t.cpu().numpy() for t in st]
+        Xg = sp.X.cpu().numpy().astype(np.complex128)
+        assert np.all(fl == oracle.F_CONVERGED) and np.all(rel <= 1e-5)
+        assert rel_err_rows(Xg, X).max() <= 1e-4
+        if ce == 1:
+            assert np.array_equal(Xg, base[0]["X"]) and np.array_equal(it, base[0]["iters"])
+        else:
+            assert np.all(it % 3 == 0)
+            if engine == "vector":   # the first multiple of 3 at or past the every-iteration stop
+                assert np.all(it >= base[0]["iters"])
+            else:                    # the MFMA engines' confirm pass may end a column earlier or later
+                assert abs(it.mean() - base[0]["iters"].mean()) <= 3.0
