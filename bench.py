@@ -447,27 +447,29 @@ def plain_c1(stream):
     Xr, _ = oracle.rzf(d.H, d.vr_start, d.vr_len, d.S, d.xi)
     out = {}
     for var in ("grk", "ahk", "vr_oahk"):
-        X = torch.zeros((1, d.nt), dtype=torch.complex128, device=dev)
-        V = torch.zeros((1, d.k), dtype=torch.complex128, device=dev)
-        plan = vrk.Plan([vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X, V)],
-                        vrk.options(variant=var, dtype="c128", engine="vector", tol=1e-10))
-        st = plan.stats_buffers()
-        plan.solve(stream=stream, stats=st)
-        torch.cuda.synchronize()
-        n = 64
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            for _ in range(n):
-                plan.solve(stats=st)
-        graph.replay()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        graph.replay()
-        b.record(stream)
-        torch.cuda.synchronize()
-        us = a.elapsed_time(b) * 1e3 / n
+        us = {}
+        for waves in (1, 4):   # the single-wave form (chosen for this size) and the four-wave form
+            X = torch.zeros((1, d.nt), dtype=torch.complex128, device=dev)
+            V = torch.zeros((1, d.k), dtype=torch.complex128, device=dev)
+            plan = vrk.Plan([vrk.ProblemSpec(H, d.vr_start, d.vr_len, d.xi, S, X, V)],
+                            vrk.options(variant=var, dtype="c128", engine="vector", tol=1e-10, tile_waves=waves))
+            st = plan.stats_buffers()
+            plan.solve(stream=stream, stats=st)
+            torch.cuda.synchronize()
+            n = 64
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                for _ in range(n):
+                    plan.solve(stats=st)
+            graph.replay()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            graph.replay()
+            b.record(stream)
+            torch.cuda.synchronize()
+            us[waves] = a.elapsed_time(b) * 1e3 / n
         err = float(np.linalg.norm(X.cpu().numpy()[0] - Xr[0]) / np.linalg.norm(Xr[0]))
         reps, t = 0, 0.0
         while t < 0.3:
@@ -475,8 +477,8 @@ def plain_c1(stream):
             oracle.solve(d.H, d.vr_start, d.vr_len, d.S[0], d.xi, variant=var, tol=1e-10)
             t += time.perf_counter() - t0
             reps += 1
-        out[var] = {"gpu_us_per_solve": us, "oracle_us_per_solve": t * 1e6 / reps,
-                    "iters": int(st[0].cpu()[0]), "rel_err": err}
+        out[var] = {"gpu_us_per_solve": us[1], "gpu_us_per_solve_four_wave": us[4],
+                    "oracle_us_per_solve": t * 1e6 / reps, "iters": int(st[0].cpu()[0]), "rel_err": err}
     return out
 
 
@@ -492,7 +494,8 @@ def main():
     ap.add_argument("--p-vis", type=float, default=None,
                     help="subarray workload: visibility probability of each subarray (default 0.35)")
     ap.add_argument("--tol", type=float, default=None)
-    ap.add_argument("--tile-waves", type=int, default=0, choices=[0, 8, 16])
+    ap.add_argument("--tile-waves", type=int, default=0, choices=[0, 1, 4, 8, 16],
+                    help="MFMA engine: waves per tile (8, 16); vector engine: waves per vector (1, 4); 0 auto")
     ap.add_argument("--persistent", type=int, default=0, choices=[0, 1])
     ap.add_argument("--wave-tiles", type=int, default=0, choices=[-1, 0, 1, 2, 4, 8],
                     help="MFMA engine, AHK / VR-OAHK: waves per wave-owned tile (-1 block tiles, 0 auto)")

@@ -87,7 +87,8 @@ typedef enum {
 typedef enum { VRK_C64 = 0, VRK_C128 = 1 } vrk_dtype;
 
 /* Execution engine. VECTOR: one workgroup per right-hand side, vector ALU,
- * complex64 or complex128. MFMA: 16 right-hand sides per workgroup sharing
+ * complex64 or complex128 (a small-channel form for nt <= 1024, k <= 64:
+ * see vrk_options.tile_waves). MFMA: 16 right-hand sides per workgroup sharing
  * H, residual and aggregation as FP32 matrix-core products (complex64
  * only). AUTO picks MFMA for complex64 problems with >= 16 right-hand
  * sides, VECTOR otherwise. */
@@ -145,7 +146,15 @@ typedef struct {
     int64_t max_iters;   /* > 0: row updates (greedy) or iterations (aggregated) */
     uint64_t seed;       /* Philox key word 0 */
     int32_t schedule;    /* vrk_schedule */
-    int32_t tile_waves;  /* MFMA engine waves per workgroup: 0 (auto = 16), 8 or 16 */
+    int32_t tile_waves;  /* MFMA engine: waves per workgroup, 0 (auto = 16), 8 or 16.
+                            VECTOR engine: 1 selects the small-channel form (one wave per
+                            64-antenna slot, at most four, per right-hand side; the
+                            channel zero-padded in LDS, x and the per-user state in
+                            registers; needs nt <= 1024, k <= 64, interval VRs and the
+                            padded channel, k rows of 64, 128, 256, 512 or 1024 antennas,
+                            within 128 KiB), 4 the general form (four waves, any size
+                            within LDS), 0, 8 or 16 the small-channel form where it fits.
+                            1 or 4 with the AUTO engine selects the VECTOR engine. */
     int32_t persistent;  /* MFMA engine: 1 = one workgroup per resident slot, draining
                             per-XCD work queues (drops assigned by cost); 0 = one
                             workgroup per 16-RHS tile */

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvrk.so")
-SOURCES = ["plan.cpp", "vec_engine.hip", "mfma_engine.hip", "wave_engine.hip", "adjoint_mfma.hip", "link.hip"]
+SOURCES = ["plan.cpp", "vec_engine.hip", "small_engine.hip", "mfma_engine.hip", "wave_engine.hip", "adjoint_mfma.hip",
+           "link.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

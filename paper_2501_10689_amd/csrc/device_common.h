@@ -86,6 +86,12 @@ __device__ __forceinline__ float lane_read(float v, int lane)
 }
 
 template <>
+__device__ __forceinline__ int lane_read(int v, int lane)
+{
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+template <>
 __device__ __forceinline__ double lane_read(double v, int lane)
 {
     const long long b = __double_as_longlong(v);
@@ -124,15 +130,39 @@ __device__ __forceinline__ R wave_max(R v)
     return v;
 }
 
-// Inclusive prefix sum across the 64 lanes (Hillis-Steele).
-template <typename R>
-__device__ __forceinline__ R wave_scan(R v, int lane)
+// DPP move with explicit row and bank masks: lanes outside the masks, and
+// lanes whose source is outside their row, read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_zero(int v)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        R o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_zero(float v)
+{
+    return __int_as_float(dpp_zero<CTRL, ROWS>(__float_as_int(v)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_zero(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_zero<CTRL, ROWS>((int)b), hi = dpp_zero<CTRL, ROWS>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive prefix sum across the 64 lanes with DPP moves only: shifts by 1,
+// 2, 4, 8 inside each row of 16 (Hillis-Steele), then the last lane of rows
+// 0 and 2 added to rows 1 and 3 (row_bcast:15) and lane 31 to rows 2 and 3
+// (row_bcast:31). The total is in lane 63.
+template <typename R>
+__device__ __forceinline__ R wave_scan(R v, int /*lane*/)
+{
+    v += dpp_zero<0x111, 0xF>(v);
+    v += dpp_zero<0x112, 0xF>(v);
+    v += dpp_zero<0x114, 0xF>(v);
+    v += dpp_zero<0x118, 0xF>(v);
+    v += dpp_zero<0x142, 0xA>(v);
+    v += dpp_zero<0x143, 0xC>(v);
     return v;
 }
 
@@ -176,23 +206,29 @@ __device__ __forceinline__ double uniform24(uint64_t seed, int64_t step, int64_t
 // ENERGY weights row i by ||a_i||^2 and UNIFORM every row by 1, whatever the
 // residual. Sampling: smallest index whose inclusive prefix of weights
 // exceeds u * total, else the last index of positive weight. `pre` is LDS
-// scratch of K entries owned by the calling wave.
+// scratch of K entries owned by the calling wave (unused for K <= 64, where
+// the prefixes stay in registers).
 template <typename R, typename Get>
 __device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
 {
     const int lane = threadIdx.x & 63;
     if (rule == 3 || rule == 4) {
         // residual-free criteria: one prefix pass over the weights
-        R carry = 0;
+        R carry = 0, v0 = 0;
         for (int base = 0; base < K; base += 64) {
             const int i = base + lane;
             R wt = 0;
             if (i < K) wt = rule == 3 ? get(i).im : (R)1;
             const R v = wave_scan(wt, lane);
-            if (i < K) pre[i] = carry + v;
-            carry += __shfl(v, 63, 64);
+            if (K <= 64) v0 = v;   // one pass: the prefixes stay in registers
+            else if (i < K) pre[i] = carry + v;
+            carry += lane_read(v, 63);
         }
         const R target = u * carry;
+        if (K <= 64) {
+            const uint64_t hit = __ballot(lane < K && v0 > target);
+            return hit ? __ffsll((unsigned long long)hit) - 1 : K - 1;
+        }
         __builtin_amdgcn_wave_barrier();
         for (int base = 0; base < K; base += 64) {
             const int i = base + lane;
@@ -241,7 +277,7 @@ __device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
         theta = (R)0.5 * (best + rr / fro2);
         if (theta > best) theta = best;
     }
-    R carry = 0;
+    R carry = 0, v0 = 0;
     int last = bi;
     for (int base = 0; base < K; base += 64) {
         int i = base + lane;
@@ -252,12 +288,17 @@ __device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
             wt = (in && wn.re > 0) ? wn.re : (R)0;
         }
         R v = wave_scan(wt, lane);
-        if (i < K) pre[i] = carry + v;
+        if (K <= 64) v0 = v;
+        else if (i < K) pre[i] = carry + v;
         uint64_t pos = __ballot(wt > 0);
         if (pos) last = base + 63 - __clzll(pos);
-        carry += __shfl(v, 63, 64);
+        carry += lane_read(v, 63);
     }
     R target = u * carry;
+    if (K <= 64) {
+        const uint64_t hit = __ballot(lane < K && v0 > target);
+        return hit ? __ffsll((unsigned long long)hit) - 1 : last;
+    }
     __builtin_amdgcn_wave_barrier();
     for (int base = 0; base < K; base += 64) {
         int i = base + lane;

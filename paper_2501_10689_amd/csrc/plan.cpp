@@ -94,6 +94,9 @@ struct vrk_plan {
     std::vector<ProbPlan> pp;
     int32_t engine = VRK_ENGINE_VECTOR, schedule = VRK_SCHED_GATHER, waves = 8, ep = 0;
     size_t lds = 0;
+    // vector engine: one wave per right-hand side (the single-wave form)
+    bool small = false;
+    int32_t max_nt = 0;
     // MFMA engine: the adjoint solve's tile shape (8 waves when every drop has
     // at most 64 users and the tile size is left to the plan, else the same)
     int32_t waves_adj = 8, ep_adj = 0, grid_adj = 0;
@@ -549,7 +552,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(VRK_EINVAL, "tol %g", o.tol);
     if (o.max_iters < 1) return fail(VRK_EINVAL, "max_iters must be >= 1");
     if (o.check_every < 0) return fail(VRK_EINVAL, "check_every must be >= 0 (0: every iteration)");
-    if (o.tile_waves != 0 && o.tile_waves != 8 && o.tile_waves != 16)
+    if (o.tile_waves != 0 && o.tile_waves != 1 && o.tile_waves != 4 && o.tile_waves != 8 && o.tile_waves != 16)
         return fail(VRK_EINVAL, "tile_waves %d", o.tile_waves);
     if (o.wave_tiles != -1 && o.wave_tiles != 0 && o.wave_tiles != 1 && o.wave_tiles != 2 && o.wave_tiles != 4 &&
         o.wave_tiles != 8)
@@ -595,7 +598,26 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     pl->engine = eng;
     pl->waves = waves;
     pl->schedule = o.schedule == VRK_SCHED_AUTO ? VRK_SCHED_GATHER : o.schedule;
-    if (eng == VRK_ENGINE_VECTOR) {
+    pl->max_nt = max_nt;
+    bool any_masked = false;
+    for (auto &q : pl->pp) any_masked = any_masked || !q.mask.empty();
+    // small-channel form of the vector engine (the channel zero-padded in
+    // LDS, x in registers, a wave per 64-antenna slot up to four): forced by
+    // tile_waves 1, the general form by 4, else chosen whenever it fits
+    const bool small_ok = eng == VRK_ENGINE_VECTOR && vrk_small_supported(o.dtype, max_nt, max_k, any_masked ? 1 : 0);
+    if (eng == VRK_ENGINE_VECTOR && o.tile_waves == 1 && !small_ok) {
+        delete pl;
+        return fail(VRK_EUNSUPPORTED,
+                    "small-channel vector engine needs nt <= 1024, k <= 64, interval VRs and the channel, "
+                    "zero-padded to 64, 128, 256, 512 or 1024 antennas, within 128 KiB (nt %d, k %d)",
+                    max_nt, max_k);
+    }
+    if (small_ok && o.tile_waves != 4) {
+        pl->small = true;
+        pl->waves = 1;
+        pl->lds = vrk_small_lds_bytes(o.dtype, max_nt, max_k);
+    } else if (eng == VRK_ENGINE_VECTOR) {
+        pl->waves = 4;
         pl->lds = vrk_vec_lds_bytes(o.dtype, max_nt, max_k);
         if (pl->lds > 160 * 1024) {
             delete pl;
@@ -1026,7 +1048,7 @@ static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
         pl->grid = pl->persistent ? (int32_t)std::min<int64_t>(g, nw) : (int32_t)nw;
         pl->grid_adj = pl->persistent ? (int32_t)std::min<int64_t>(ga, nw) : (int32_t)nw;
     } else {
-        e = vrk_prepare_vec_solve(o.dtype, pl->lds);
+        e = pl->small ? vrk_prepare_small_solve(o.dtype, pl->max_nt, pl->lds) : vrk_prepare_vec_solve(o.dtype, pl->lds);
         if (e != hipSuccess) return hip_fail(e, "vector kernel attributes");
     }
     pl->d_ws = base;
@@ -1154,8 +1176,9 @@ static vrk_status run_solve(vrk_plan *pl, void *stream, int32_t *d_iters, float 
             e = adjoint ? vrk_launch_mfma_solve(a, wl, q, pl->grid_adj, pl->waves_adj, pl->ep_adj, pl->lds_adj, s, 0,
                                                 nullptr)
                         : vrk_launch_mfma_solve(a, wl, q, pl->grid, pl->waves, pl->ep, pl->lds, s, 0, nullptr);
-    } else
-        e = vrk_launch_vec_solve(a, pl->lds, s);
+    } else {
+        e = pl->small ? vrk_launch_small_solve(a, pl->max_nt, pl->lds, s) : vrk_launch_vec_solve(a, pl->lds, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "solve kernel");
     return VRK_OK;
 }

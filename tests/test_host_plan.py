@@ -271,3 +271,39 @@ def test_wave_owned_tile_choice():
         vrk.host_plan(4096, 256, vs2, vl2, nrhs=64, variant="ahk", wave_tiles=2)   # 16 blocks on 2 waves
     with pytest.raises(vrk.VrkError):
         vrk.host_plan(1024, 64, vs, vl, nrhs=64, variant="grk", wave_tiles=1)
+
+
+def test_small_channel_vector_form_choice():
+    """The vector engine takes its small-channel form (one wave per 64-antenna
+    slot, at most four, per right-hand side) when nt <= 1024, k <= 64, the
+    VRs are intervals and the zero-padded channel fits 128 KiB of LDS, and
+    the general four-wave form otherwise; tile_waves 1 or 4 forces the form
+    (1 refused where it does not fit) and selects the vector engine under
+    AUTO. Q_ENGINE reports 1 and 4 for the two forms."""
+    rng = np.random.default_rng(4)
+    _, vs, vl, _ = random_problem(rng, 256, 16)
+    small = vrk.host_plan(256, 16, vs, vl, nrhs=1, dtype="c128", engine="vector")
+    assert small.query(vrk.Q_ENGINE)[2] == 1
+    assert vrk.host_plan(256, 16, vs, vl, nrhs=1, dtype="c128", engine="vector",
+                         tile_waves=4).query(vrk.Q_ENGINE)[2] == 4
+    q = vrk.host_plan(256, 16, vs, vl, nrhs=64, dtype="c64", tile_waves=1).query(vrk.Q_ENGINE)
+    assert (q[0], q[2]) == (vrk.ENGINES["vector"], 1)
+    # 64 users x 1024 antennas: 1 MiB in complex128
+    _, vs1, vl1, _ = random_problem(rng, 1024, 64)
+    assert vrk.host_plan(1024, 64, vs1, vl1, nrhs=1, dtype="c128", engine="vector").query(vrk.Q_ENGINE)[2] == 4
+    with pytest.raises(vrk.VrkError):
+        vrk.host_plan(1024, 64, vs1, vl1, nrhs=1, dtype="c128", engine="vector", tile_waves=1)
+    # 8 x 1024 and 64 x 128 complex128 (128 KiB) fit; 33 x 256 does not
+    _, vs2, vl2, _ = random_problem(rng, 1000, 8)
+    assert vrk.host_plan(1000, 8, vs2, vl2, nrhs=1, dtype="c128", engine="vector").query(vrk.Q_ENGINE)[2] == 1
+    _, vs3, vl3, _ = random_problem(rng, 100, 64)
+    assert vrk.host_plan(100, 64, vs3, vl3, nrhs=1, dtype="c128", engine="vector").query(vrk.Q_ENGINE)[2] == 1
+    _, vs4, vl4, _ = random_problem(rng, 256, 33)
+    assert vrk.host_plan(256, 33, vs4, vl4, nrhs=1, dtype="c128", engine="vector").query(vrk.Q_ENGINE)[2] == 4
+    assert vrk.host_plan(256, 33, vs4, vl4, nrhs=1, dtype="c64", engine="vector").query(vrk.Q_ENGINE)[2] == 1
+    _, vs5, vl5, _ = random_problem(rng, 2048, 16)
+    assert vrk.host_plan(2048, 16, vs5, vl5, nrhs=1, engine="vector").query(vrk.Q_ENGINE)[2] == 4
+    _, vs6, vl6, _ = random_problem(rng, 256, 65)
+    assert vrk.host_plan(256, 65, vs6, vl6, nrhs=1, engine="vector").query(vrk.Q_ENGINE)[2] == 4
+    with pytest.raises(vrk.VrkError):
+        vrk.host_plan(256, 16, vs, vl, nrhs=1, tile_waves=2)
