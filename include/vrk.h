@@ -151,8 +151,8 @@ typedef struct {
                             64-antenna slot, at most four, per right-hand side; the
                             channel zero-padded in LDS, x and the per-user state in
                             registers; needs nt <= 1024, k <= 64, interval VRs and the
-                            padded channel, k rows of 64, 128, 256, 512 or 1024 antennas,
-                            within 128 KiB), 4 the general form (four waves, any size
+                            padded channel, 16 ceil(k / 16) rows of 64, 128, 256, 512 or
+                            1024 antennas, within 128 KiB), 4 the general form (four waves, any size
                             within LDS), 0, 8 or 16 the small-channel form where it fits.
                             1 or 4 with the AUTO engine selects the VECTOR engine. */
     int32_t persistent;  /* MFMA engine: 1 = one workgroup per resident slot, draining

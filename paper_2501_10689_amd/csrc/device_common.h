@@ -99,14 +99,80 @@ __device__ __forceinline__ double lane_read(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over the 64 lanes: the four row sums added in row order (uniform).
+// gfx950 row-swap moves (v_permlane16_swap, v_permlane32_swap) as pair
+// sums: swap_sum16(a, b) leaves a + the a of lane l ^ 16 in lanes whose bit 4
+// is clear and b + the b of lane l ^ 16 where it is set (swap_sum32 the same
+// for bit 5), the two terms in the same order in both lanes of a pair.
+// Doubles move as two 32-bit halves, both with the same lanes.
+__device__ __forceinline__ float swap_sum32(float a, float b)
+{
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ __forceinline__ float swap_sum16(float a, float b)
+{
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ __forceinline__ double swap_sum32(double a, double b)
+{
+    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ab, (unsigned)bb, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false);
+    const double x0 = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+    const double x1 = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+    return x0 + x1;
+}
+__device__ __forceinline__ double swap_sum16(double a, double b)
+{
+    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ab, (unsigned)bb, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false);
+    const double x0 = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+    const double x1 = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+    return x0 + x1;
+}
+
+// Sum over the 64 lanes, in every lane: the sixteen-lane row sums, then
+// rows 0 + 1 and 2 + 3, then the two halves; the same order in all lanes.
 template <typename R>
 __device__ __forceinline__ R wave_sum_dpp(R v)
 {
     v = row16_sum(v);
-    return ((lane_read(v, 0) + lane_read(v, 16)) + lane_read(v, 32)) + lane_read(v, 48);
+    return swap_sum32(swap_sum16(v, v), swap_sum16(v, v));
 }
 
+// Largest of v over lanes l and l ^ 16 (BIT 16) or l ^ 32 (BIT 32), through
+// the row-swap moves of v with itself.
+template <int BIT>
+__device__ __forceinline__ float swap_max(float v)
+{
+    const auto p = BIT == 16 ? __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false)
+                             : __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+}
+template <int BIT>
+__device__ __forceinline__ double swap_max(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const auto lo = BIT == 16 ? __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false)
+                              : __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = BIT == 16 ? __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false)
+                              : __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return fmax(__longlong_as_double(((long long)hi[0] << 32) | lo[0]),
+                __longlong_as_double(((long long)hi[1] << 32) | lo[1]));
+}
+
+// Largest value over the 64 lanes, in every lane (exact: no rounding).
+template <typename R>
+__device__ __forceinline__ R wave_max_dpp(R v)
+{
+    v = fmax(v, dpp_move<0xB1>(v));
+    v = fmax(v, dpp_move<0x4E>(v));
+    v = fmax(v, dpp_move<0x141>(v));
+    v = fmax(v, dpp_move<0x140>(v));
+    return swap_max<32>(swap_max<16>(v));
+}
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_move(int v)
@@ -198,37 +264,75 @@ __device__ __forceinline__ double uniform24(uint64_t seed, int64_t step, int64_t
 }
 
 // Row selection by one wave (Sec. IV-A; Sec. III-A for the randomized
-// criteria). get(i) returns {|r_i|^2, ||a_i||^2} for user i (original index
-// order). The threshold rule keeps rows with rho_i = |r_i|^2/||a_i||^2 >=
-// theta, theta = min(rho_max, (rho_max + ||r||^2/||A||_F^2)/2) (the cited
-// greedy randomized Kaczmarz criterion), weighted by |r_i|^2; RESIDUAL keeps
-// every row, weighted by |r_i|^2; MAX returns the first argmax of rho;
-// ENERGY weights row i by ||a_i||^2 and UNIFORM every row by 1, whatever the
-// residual. Sampling: smallest index whose inclusive prefix of weights
-// exceeds u * total, else the last index of positive weight. `pre` is LDS
-// scratch of K entries owned by the calling wave (unused for K <= 64, where
-// the prefixes stay in registers).
+// criteria). The threshold rule keeps rows with rho_i = |r_i|^2/||a_i||^2
+// >= theta, theta = min(rho_max, (rho_max + ||r||^2/||A||_F^2)/2) (the
+// cited greedy randomized Kaczmarz criterion), weighted by |r_i|^2;
+// RESIDUAL keeps every row, weighted by |r_i|^2; MAX returns the first
+// argmax of rho; ENERGY weights row i by ||a_i||^2 and UNIFORM every row by
+// 1, whatever the residual. Sampling: smallest index whose inclusive prefix
+// of weights exceeds u * total, else the last index of positive weight.
+//
+// K <= 64 users, user i in lane i: w2 = |r_i|^2 and nrm = ||a_i||^2 of the
+// lane's user (ignored on lanes >= K). Straight-line, every intermediate in
+// registers.
+template <typename R>
+__device__ int select_row_64(int K, int rule, R fro2, R u, R w2, R nrm)
+{
+    const int lane = threadIdx.x & 63;
+    const bool in = lane < K;
+    R wt;
+    int last = K - 1;
+    if (rule == 3 || rule == 4) {
+        // residual-free criteria
+        wt = in ? (rule == 3 ? nrm : (R)1) : (R)0;
+    } else {
+        const R rho = in ? w2 / nrm : (R)-1;
+        const R rr = wave_sum_dpp(in ? w2 : (R)0);
+        // first argmax: the largest rho, then the first lane holding it
+        const R best = wave_max_dpp(rho);
+        const uint64_t at = __ballot(in && rho == best);
+        const int bi = at ? __ffsll((unsigned long long)at) - 1 : 0;
+        if (rule == 2) return bi;
+        R theta = 0;
+        if (rule == 0) {
+            theta = (R)0.5 * (best + rr / fro2);
+            if (theta > best) theta = best;
+        }
+        const bool keep = in && (rule == 1 || rho >= theta);
+        wt = (keep && w2 > 0) ? w2 : (R)0;
+        const uint64_t pos = __ballot(wt > 0);
+        last = pos ? 63 - __clzll(pos) : bi;
+    }
+    const R v = wave_scan(wt, lane);
+    const R target = u * lane_read(v, 63);
+    const uint64_t hit = __ballot(in && v > target);
+    return hit ? __ffsll((unsigned long long)hit) - 1 : last;
+}
+
+// The same selection for any K: get(i) returns {|r_i|^2, ||a_i||^2} for user
+// i (original index order); `pre` is LDS scratch of K entries owned by the
+// calling wave (unused for K <= 64).
 template <typename R, typename Get>
 __device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
 {
     const int lane = threadIdx.x & 63;
+    if (K <= 64) {
+        cx<R> wn = {0, 1};
+        if (lane < K) wn = get(lane);
+        return select_row_64<R>(K, rule, fro2, u, wn.re, wn.im);
+    }
     if (rule == 3 || rule == 4) {
         // residual-free criteria: one prefix pass over the weights
-        R carry = 0, v0 = 0;
+        R carry = 0;
         for (int base = 0; base < K; base += 64) {
             const int i = base + lane;
             R wt = 0;
             if (i < K) wt = rule == 3 ? get(i).im : (R)1;
             const R v = wave_scan(wt, lane);
-            if (K <= 64) v0 = v;   // one pass: the prefixes stay in registers
-            else if (i < K) pre[i] = carry + v;
+            if (i < K) pre[i] = carry + v;
             carry += lane_read(v, 63);
         }
         const R target = u * carry;
-        if (K <= 64) {
-            const uint64_t hit = __ballot(lane < K && v0 > target);
-            return hit ? __ffsll((unsigned long long)hit) - 1 : K - 1;
-        }
         __builtin_amdgcn_wave_barrier();
         for (int base = 0; base < K; base += 64) {
             const int i = base + lane;
@@ -277,7 +381,7 @@ __device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
         theta = (R)0.5 * (best + rr / fro2);
         if (theta > best) theta = best;
     }
-    R carry = 0, v0 = 0;
+    R carry = 0;
     int last = bi;
     for (int base = 0; base < K; base += 64) {
         int i = base + lane;
@@ -288,17 +392,12 @@ __device__ int select_row_wave(int K, int rule, R fro2, R u, Get get, R *pre)
             wt = (in && wn.re > 0) ? wn.re : (R)0;
         }
         R v = wave_scan(wt, lane);
-        if (K <= 64) v0 = v;
-        else if (i < K) pre[i] = carry + v;
+        if (i < K) pre[i] = carry + v;
         uint64_t pos = __ballot(wt > 0);
         if (pos) last = base + 63 - __clzll(pos);
         carry += lane_read(v, 63);
     }
     R target = u * carry;
-    if (K <= 64) {
-        const uint64_t hit = __ballot(lane < K && v0 > target);
-        return hit ? __ffsll((unsigned long long)hit) - 1 : last;
-    }
     __builtin_amdgcn_wave_barrier();
     for (int base = 0; base < K; base += 64) {
         int i = base + lane;

@@ -93,8 +93,8 @@ hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles,
 // Vector engine, small-channel form: T <= 4 waves per right-hand side (one
 // per 64-antenna slot, up to four slots each), the channel zero-padded in
 // LDS, x and the per-user state in registers; for nt <= 1024, k <= 64,
-// interval VRs and the padded channel (k rows of 64, 128, 256, 512 or 1024
-// antennas) within 128 KiB.
+// interval VRs and the padded channel (16 ceil(k / 16) rows of 64, 128, 256,
+// 512 or 1024 antennas) within 128 KiB.
 int vrk_small_supported(int32_t dtype, int32_t max_nt, int32_t max_k, int32_t masked);
 size_t vrk_small_lds_bytes(int32_t dtype, int32_t max_nt, int32_t max_k);
 hipError_t vrk_prepare_small_solve(int32_t dtype, int32_t max_nt, size_t lds_bytes);   // LDS attribute, at bind

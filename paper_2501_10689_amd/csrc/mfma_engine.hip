@@ -430,7 +430,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
 {
     // prob and tile are wave-uniform, so the descriptor is read with scalar loads
     CDesc &d = ((CDesc *)a.desc)[prob];
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15, g = lane >> 4;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, j = lane & 15;
     TileCtx c;
     c.prob = prob;
     c.K = d.k;
@@ -465,7 +465,7 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     c.ag_uc = gmem(d.ag_uc);
     c.gm_c = gmem(d.gm_c);
     const gp<const float> nrm_g = gmem(static_cast<const float *>(d.nrm));
-    const int K = c.K, N = c.N, kpad = c.kpad, b0 = c.b0;
+    const int K = c.K, kpad = c.kpad, b0 = c.b0;
     const int rows_per_pass = W * 4;   // (row, column) entries: tid -> (tid / 16, tid % 16)
     const int er = tid >> 4;
 

@@ -609,7 +609,8 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         delete pl;
         return fail(VRK_EUNSUPPORTED,
                     "small-channel vector engine needs nt <= 1024, k <= 64, interval VRs and the channel, "
-                    "zero-padded to 64, 128, 256, 512 or 1024 antennas, within 128 KiB (nt %d, k %d)",
+                    "zero-padded to 16-row blocks of 64, 128, 256, 512 or 1024 antennas, within 128 KiB "
+                    "(nt %d, k %d)",
                     max_nt, max_k);
     }
     if (small_ok && o.tile_waves != 4) {

@@ -1,22 +1,24 @@
 // Vector engine, small-channel form (Nt <= 1024, K <= 64 and the channel,
-// zero-padded to whole waves of 64-antenna slots, within 128 KiB of LDS): one workgroup of T <= 4 waves
-// per right-hand side, complex64 or complex128, the same steps in the same
-// order as the general form (Alg. 1 initialisation; the residual, selection
-// and single-row projection of GRK and VR-OGRK; the aggregated projection of
-// AHK; the orthogonal half-step on F and the aggregated step on V of
-// VR-OAHK, Alg. 3).
+// zero-padded to 16-row blocks of whole waves of 64-antenna slots, within
+// 128 KiB of LDS): one workgroup of T <= 4 waves per right-hand side,
+// complex64 or complex128, the same steps in the same order as the general
+// form (Alg. 1 initialisation; the residual, selection and single-row
+// projection of GRK and VR-OGRK; the aggregated projection of AHK; the
+// orthogonal half-step on F and the aggregated step on V of VR-OAHK,
+// Alg. 3).
 //
 // Laid out for latency. The channel sits in LDS zero-padded to whole rows of
-// 64-antenna slots, so every product is a run of unconditional loads and
-// FMAs. Wave w owns NA slots (antennas 64 (w NA + m) + lane) and holds their
-// x in registers; every wave holds the per-user state (residual, dual
-// iterate q, row norm, VR) of user u in lane u, the same in all of them, and
-// takes the same selections and step sizes redundantly, so the only
-// exchanges are the residual rows (each wave's partial sums over its slots)
-// and ||p||^2: one barrier each. Residual rows go sixteen (or four) at a
-// time: each lane forms its partial sums of all of them and one
-// reduce-scatter across the wave (six pair levels, half of the values to
-// each side) totals them with about a sixth of the moves of a sum per row.
+// 64-antenna slots (and to a multiple of 16 rows), so every product is a run
+// of unconditional loads and FMAs. Wave w owns NA slots (antennas
+// 64 (w NA + m) + lane) and holds their x in registers; every wave holds the
+// per-user state (residual, dual iterate q, row norm, VR) of user u in lane
+// u, the same in all of them, and takes the same selections and step sizes
+// redundantly, so the only exchanges are the residual rows (each wave's
+// partial sums over its slots) and ||p||^2: one barrier each. Residual rows
+// go sixteen (or four) at a time: each lane forms its partial sums of all of
+// them and one reduce-scatter across the wave (six pair levels, half of the
+// values to each side) totals them with about a sixth of the moves of a sum
+// per row.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -31,40 +33,11 @@ template <typename R>
 using C = cx<R>;
 
 // Pair levels of the reduce-scatter. BIT 32 and 16 pair lane l with l ^ BIT
-// through the gfx950 row-swap moves; 8, 4, 2 and 1 pair lanes inside a row
-// of 16 with DPP moves (rotate by 8, mirror within 8, quad swaps), partners
-// that differ in that bit. Each level leaves, in every lane, own + partner
-// of one of two values a, b: a where the lane's bit is clear, b where set.
-__device__ __forceinline__ float swap_sum32(float a, float b)
-{
-    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
-}
-__device__ __forceinline__ float swap_sum16(float a, float b)
-{
-    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
-}
-// doubles: the same lane moves on both 32-bit halves
-__device__ __forceinline__ double swap_sum32(double a, double b)
-{
-    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
-    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ab, (unsigned)bb, false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false);
-    const double x0 = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
-    const double x1 = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
-    return x0 + x1;
-}
-__device__ __forceinline__ double swap_sum16(double a, double b)
-{
-    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
-    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ab, (unsigned)bb, false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false);
-    const double x0 = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
-    const double x1 = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
-    return x0 + x1;
-}
-
+// through the gfx950 row-swap moves (swap_sum32, swap_sum16); 8, 4, 2 and 1
+// pair lanes inside a row of 16 with DPP moves (rotate by 8, mirror within
+// 8, quad swaps), partners that differ in that bit. Each level leaves, in
+// every lane, own + partner of one of two values a, b: a where the lane's
+// bit is clear, b where set.
 template <int BIT>
 constexpr int pair_ctrl()
 {
@@ -249,6 +222,60 @@ __device__ __forceinline__ void residual_set(Ctx<R, T, NA> &c, uint64_t m)
     }
 }
 
+// r_i = s_i - H[i, :] x - xi q_i for every user: rows sixteen at a time
+// with their offsets known at compile time (the channel's rows are padded
+// with zero rows to a multiple of 16), otherwise as residual_set.
+template <typename R, int T, int NA>
+__device__ __forceinline__ void residual_all(Ctx<R, T, NA> &c)
+{
+    constexpr int kNpad = 64 * T * NA;
+    R mine_re = 0, mine_im = 0;
+    R *xb = c.xch + (size_t)(c.nx & 1) * T * kXch + (size_t)c.w * kXch;
+    const int nch = (c.K + 15) >> 4;
+    for (int ch = 0; ch < nch; ++ch) {
+        const C<R> *h = c.hd + (size_t)(16 * ch) * kNpad + c.n0;
+        R v[32];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            R ar = 0, ai = 0;
+#pragma unroll
+            for (int m = 0; m < NA; ++m) {
+                const C<R> hv = h[t * kNpad + 64 * m];
+                ar = fma(hv.re, c.x[m].re, ar);
+                ar = fma(-hv.im, c.x[m].im, ar);
+                ai = fma(hv.re, c.x[m].im, ai);
+                ai = fma(hv.im, c.x[m].re, ai);
+            }
+            v[2 * t] = ar;
+            v[2 * t + 1] = ai;
+        }
+        const R tot = reduce_scatter<32>(v, c.lane);
+        if constexpr (T == 1) {
+            const int src = 4 * (c.lane & 15);
+            const R re = __shfl(tot, src, 64), im = __shfl(tot, src + 2, 64);
+            if ((c.lane >> 4) == ch) { mine_re = re; mine_im = im; }
+        } else {
+            if ((c.lane & 1) == 0) xb[32 * ch + (c.lane >> 1)] = tot;
+        }
+    }
+    if constexpr (T > 1) {
+        __syncthreads();
+        const R *xr = c.xch + (size_t)(c.nx & 1) * T * kXch;
+        ++c.nx;
+        if (c.lane < c.K) {
+#pragma unroll
+            for (int w = 0; w < T; ++w) {
+                mine_re += xr[w * kXch + 2 * c.lane];
+                mine_im += xr[w * kXch + 2 * c.lane + 1];
+            }
+        }
+    }
+    if (c.lane < c.K) {
+#pragma clang fp contract(off)
+        c.r = C<R>{c.s.re - mine_re - c.xi * c.q.re, c.s.im - mine_im - c.xi * c.q.im};
+    }
+}
+
 // The sum over the waves of one wave-uniform value per wave, in wave order.
 template <typename R, int T, int NA>
 __device__ __forceinline__ R across_waves(Ctx<R, T, NA> &c, R v)
@@ -370,18 +397,18 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
     const bool isu = lane < K;
     const int vs = isu ? d.vs[lane] : 0, ve = isu ? d.ve[lane] : 0;
     const R nrm = isu ? reinterpret_cast<const R *>(d.nrm)[lane] : (R)1;
+    const R invn = (R)1 / nrm;   // the single-row step's 1 / ||a_i||^2
     const bool inF = isu && d.inf[lane] != 0;
     c.s = C<R>{0, 0};
     if (isu) c.s = S[(int64_t)b * lds_ + lane];
     const R fro2 = *reinterpret_cast<const R *>(d.fro2);
 
-    // LDS: the zero-padded channel, the exchange buffers, then per wave the
-    // broadcast slots and the selection scratch
+    // LDS: the channel zero-padded to kpad = 16 ceil(K / 16) rows of kNpad
+    // antennas, the exchange buffers, then per wave the broadcast slots
+    const int kpad = (K + 15) & ~15;
     C<R> *hd = reinterpret_cast<C<R> *>(smem);
-    R *xch = reinterpret_cast<R *>(hd + (size_t)K * kNpad);
+    R *xch = reinterpret_cast<R *>(hd + (size_t)kpad * kNpad);
     C<R> *ph = reinterpret_cast<C<R> *>(xch + (T > 1 ? 2 * T * kXch : 0)) + (size_t)w * K;
-    R *pre = reinterpret_cast<R *>(reinterpret_cast<C<R> *>(xch + (T > 1 ? 2 * T * kXch : 0)) + (size_t)T * K) +
-             (size_t)w * K;
     c.hd = hd;
     c.xch = xch;
     c.ph = ph;
@@ -390,12 +417,13 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
     {
         constexpr int G = 16 / NA;
         const C<R> *H = reinterpret_cast<const C<R> *>(d.H);
-        for (int u0 = 0; u0 < K; u0 += G) {
+        for (int u0 = 0; u0 < kpad; u0 += G) {
             C<R> tmp[G * NA];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int u = u0 + g < K ? u0 + g : K - 1;
-                const int us = __builtin_amdgcn_readlane(vs, u), ue = __builtin_amdgcn_readlane(ve, u);
+                int us = __builtin_amdgcn_readlane(vs, u), ue = __builtin_amdgcn_readlane(ve, u);
+                if (u0 + g >= K) us = ue = 0;   // a padding row
 #pragma unroll
                 for (int m = 0; m < NA; ++m) {
                     const int n = c.n0 + 64 * m;
@@ -405,7 +433,7 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
             }
 #pragma unroll
             for (int g = 0; g < G; ++g)
-                if (u0 + g < K) {
+                if (u0 + g < kpad) {
 #pragma unroll
                     for (int m = 0; m < NA; ++m) hd[(size_t)(u0 + g) * kNpad + c.n0 + 64 * m] = tmp[g * NA + m];
                 }
@@ -419,7 +447,11 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
     c.q = C<R>{0, 0};
     const R s2 = wave_sum_dpp(cnorm2(c.s));
     const R snorm = sqrt(s2);
-    const uint64_t users = __ballot(isu);
+    // ||r||^2 above `far` cannot round to ||r|| / ||s|| <= tol (a 1e-5
+    // relative margin over the few roundings of either side), so the stop
+    // test needs the square root and the division only below it
+    const R ts = (R)a.tol * snorm, far = ts * ts * (R)1.00001;
+    const bool can_skip = far > 0 && isfinite(far);
 
     int32_t flags = 0;
     int64_t t = 0;
@@ -433,23 +465,24 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
         flags = VRK_FLAG_CONVERGED;
     } else {
         for (;;) {
-            if (variant != 2) residual_set(c, users);   // every variant but VR-OGRK recomputes all rows
+            if (variant != 2) residual_all(c);   // every variant but VR-OGRK recomputes all rows
             // stop rule every check_every iterations (and at the cap)
             if (a.check_every == 1 || t % a.check_every == 0 || t >= a.max_iters) {
                 const R r2 = wave_sum_dpp(cnorm2(c.r));
-                rel = sqrt(r2) / snorm;
-                if (!isfinite(rel)) { flags = VRK_FLAG_NONFINITE; break; }
-                if (rel <= (R)a.tol) { flags = VRK_FLAG_CONVERGED; break; }
-                if (t >= a.max_iters) { flags = VRK_FLAG_MAXITER; break; }
+                if (!(can_skip && r2 > far && isfinite(r2) && t < a.max_iters)) {
+                    rel = sqrt(r2) / snorm;
+                    if (!isfinite(rel)) { flags = VRK_FLAG_NONFINITE; break; }
+                    if (rel <= (R)a.tol) { flags = VRK_FLAG_CONVERGED; break; }
+                    if (t >= a.max_iters) { flags = VRK_FLAG_MAXITER; break; }
+                }
             }
             if (variant == 0 || variant == 2) {
                 if ((t & 63) == 0) udraw = (R)uniform24(a.seed, t + lane, b, prob);
                 const R u = lane_read(udraw, (int)(t & 63));
-                const R w2 = cnorm2(c.r);
-                const int i = select_row_wave<R>(K, a.select, fro2, u, [&](int) -> cx<R> { return {w2, nrm}; }, pre);
+                const int i = select_row_64<R>(K, a.select, fro2, u, cnorm2(c.r), nrm);
                 // single-row projection (update): x += gamma conj(H[i, :]),
                 // q_i += gamma, gamma = r_i / ||a_i||^2
-                const R inv = (R)1 / lane_read(nrm, i);
+                const R inv = lane_read(invn, i);
                 const C<R> g = C<R>{lane_read(c.r.re, i) * inv, lane_read(c.r.im, i) * inv};
                 add_row(c, i, g);
                 if (lane == i) c.q = C<R>{c.q.re + g.re, c.q.im + g.im};
@@ -539,8 +572,8 @@ size_t vrk_small_lds_bytes(int32_t dtype, int32_t max_nt, int32_t max_k)
     int T, NA;
     small_shape(max_nt, &T, &NA);
     const size_t eb = dtype == 1 ? 16 : 8, rb = dtype == 1 ? 8 : 4;
-    return (size_t)max_k * 64 * T * NA * eb + (T > 1 ? 2 * (size_t)T * kXch * rb : 0) +
-           (size_t)T * max_k * (eb + rb);
+    const size_t kpad = (size_t)(max_k + 15) / 16 * 16;
+    return kpad * 64 * T * NA * eb + (T > 1 ? 2 * (size_t)T * kXch * rb : 0) + (size_t)T * max_k * eb;
 }
 
 int vrk_small_supported(int32_t dtype, int32_t max_nt, int32_t max_k, int32_t masked)
@@ -549,7 +582,8 @@ int vrk_small_supported(int32_t dtype, int32_t max_nt, int32_t max_k, int32_t ma
     int T, NA;
     small_shape(max_nt, &T, &NA);
     const size_t eb = dtype == 1 ? 16 : 8;
-    return (size_t)max_k * 64 * T * NA * eb <= kSmallChannelBytes;
+    const size_t kpad = (size_t)(max_k + 15) / 16 * 16;
+    return kpad * 64 * T * NA * eb <= kSmallChannelBytes;
 }
 
 hipError_t vrk_prepare_small_solve(int32_t dtype, int32_t max_nt, size_t lds_bytes)

@@ -185,33 +185,34 @@ def test_randomized_criteria_c128_follow_the_oracle_on_uneven_rows(rule, waves):
         assert np.linalg.norm(res[0]["X"][b] - o["x"]) <= 1e-12 * np.linalg.norm(o["x"])
 
 
-# (nt, k): one wave of one 64-antenna slot, two waves, four waves of one,
-# two and four slots (nt up to 256, 512, 1024), ragged antenna tails, K below,
-# at and past one chunk of 16 rows (17: a second chunk of one row), K = 64
-# and K > nt; every padded channel within 128 KiB in complex128
-SMALL_SHAPES = [(1, 1), (63, 5), (64, 16), (65, 17), (130, 30), (256, 32), (300, 16), (1000, 8), (24, 40),
-                (100, 64)]
+# (nt, k, dtype): one wave of one 64-antenna slot, two waves, four waves of
+# one, two and four slots (nt up to 256, 512, 1024), ragged antenna tails, K
+# below, at and past one block of 16 rows (17: a second block of one row), K
+# = 64 and K > nt; every padded channel within 128 KiB
+SMALL_SHAPES = [(1, 1, "c128"), (63, 5, "c128"), (64, 16, "c128"), (65, 17, "c128"), (130, 30, "c128"),
+                (256, 32, "c128"), (300, 16, "c128"), (24, 40, "c128"), (100, 64, "c128"), (1000, 8, "c64"),
+                (700, 16, "c64"), (200, 48, "c64")]
 
 
-@pytest.mark.parametrize("nt,k", SMALL_SHAPES)
+@pytest.mark.parametrize("nt,k,dtype", SMALL_SHAPES)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_small_channel_form_shapes(nt, k, variant):
-    """The small-channel form over its whole shape range, complex128 to
-    1e-11, against the FP64 RZF; and its iteration counts against the
-    general form's on the same drop (equal up to the rounding order of the
-    sums: at most one apart)."""
+def test_small_channel_form_shapes(nt, k, dtype, variant):
+    """The small-channel form over its whole shape range against the FP64
+    RZF (complex128 to 1e-11: x within 1e-9; complex64 to 1e-5: within
+    1e-4), and its iteration counts against the general form's on the same
+    drop (equal up to the rounding order of the sums: at most one apart in
+    complex128, three in complex64)."""
     rng = np.random.default_rng(nt * 131 + k)
     H, vs, vl, xi = random_problem(rng, nt, k, lo=1, hi=nt)
     S = qpsk(rng, (3, k))
-    a, pa = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="vector", dtype="c128", tol=1e-11,
-                     tile_waves=1)
+    tol, bound, slack = (1e-11, 1e-9, 1) if dtype == "c128" else (1e-5, 1e-4, 3)
+    a, pa = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="vector", dtype=dtype, tol=tol, tile_waves=1)
     assert pa.query(0, vrk.Q_ENGINE)[2] == 1
-    b, _ = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="vector", dtype="c128", tol=1e-11,
-                    tile_waves=4)
+    b, _ = run_plan([(H, vs, vl, S, xi)], variant=variant, engine="vector", dtype=dtype, tol=tol, tile_waves=4)
     X, V = oracle.rzf(H, vs, vl, S, xi)
     g = a[0]
     print(nt, k, variant, "iters", g["iters"], b[0]["iters"])
     assert np.all(g["flags"] == oracle.F_CONVERGED)
-    assert rel_err_rows(g["X"], X).max() <= 1e-9
-    assert np.allclose(g["V"], V, atol=1e-9 * max(1.0, np.abs(V).max()))
-    assert np.abs(g["iters"].astype(int) - b[0]["iters"]).max() <= 1
+    assert rel_err_rows(g["X"], X).max() <= bound
+    assert np.allclose(g["V"], V, atol=bound * max(1.0, np.abs(V).max()))
+    assert np.abs(g["iters"].astype(int) - b[0]["iters"]).max() <= slack

@@ -276,7 +276,8 @@ def test_wave_owned_tile_choice():
 def test_small_channel_vector_form_choice():
     """The vector engine takes its small-channel form (one wave per 64-antenna
     slot, at most four, per right-hand side) when nt <= 1024, k <= 64, the
-    VRs are intervals and the zero-padded channel fits 128 KiB of LDS, and
+    VRs are intervals and the channel, zero-padded to 16-row blocks, fits
+    128 KiB of LDS, and
     the general four-wave form otherwise; tile_waves 1 or 4 forces the form
     (1 refused where it does not fit) and selects the vector engine under
     AUTO. Q_ENGINE reports 1 and 4 for the two forms."""
@@ -293,9 +294,11 @@ def test_small_channel_vector_form_choice():
     assert vrk.host_plan(1024, 64, vs1, vl1, nrhs=1, dtype="c128", engine="vector").query(vrk.Q_ENGINE)[2] == 4
     with pytest.raises(vrk.VrkError):
         vrk.host_plan(1024, 64, vs1, vl1, nrhs=1, dtype="c128", engine="vector", tile_waves=1)
-    # 8 x 1024 and 64 x 128 complex128 (128 KiB) fit; 33 x 256 does not
+    # rows pad to 16: 16 x 1024 complex64 and 64 x 128 complex128 (128 KiB)
+    # fit, 16 x 1024 complex128 and 48 x 256 complex128 do not
     _, vs2, vl2, _ = random_problem(rng, 1000, 8)
-    assert vrk.host_plan(1000, 8, vs2, vl2, nrhs=1, dtype="c128", engine="vector").query(vrk.Q_ENGINE)[2] == 1
+    assert vrk.host_plan(1000, 8, vs2, vl2, nrhs=1, dtype="c64", engine="vector").query(vrk.Q_ENGINE)[2] == 1
+    assert vrk.host_plan(1000, 8, vs2, vl2, nrhs=1, dtype="c128", engine="vector").query(vrk.Q_ENGINE)[2] == 4
     _, vs3, vl3, _ = random_problem(rng, 100, 64)
     assert vrk.host_plan(100, 64, vs3, vl3, nrhs=1, dtype="c128", engine="vector").query(vrk.Q_ENGINE)[2] == 1
     _, vs4, vl4, _ = random_problem(rng, 256, 33)
