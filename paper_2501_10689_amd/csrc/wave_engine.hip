@@ -184,6 +184,15 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
     // r and the last product in registers, q and the row scales in LDS
     auto blk = [&](int k) { return w + T * k; };
     auto row = [&](int k, int r) { return 16 * blk(k) + 4 * g + r; };
+    // this lane's entries of the per-row LDS arrays, slot (0, 0); slot
+    // (k, r) lies 16 T k + r rows further, a constant, so every access is
+    // one base register plus an immediate offset
+    auto ro = [](int k, int r) { return 16 * T * k + r; };
+    const int r00 = 16 * w + 4 * g;
+    float2 *const Qr = L.Q + r00 * 16 + j;
+    float2 *const PVr = L.PV + r00 * 16 + j;
+    const float *const fvr = L.fv + r00;
+    const float *const ffr = L.ff + r00;
     float2 rr[BPW][4], pp[BPW][4];
     for (int ku = tid; ku < kpad; ku += T * 64) {
         float fv = 0.f, ff = 0.f;
@@ -262,12 +271,16 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                 if (colok && blk(k) < nub && ku < K) rr[k][r] = S[(int64_t)b * d.lds + perm[ku]];
             }
     }
-    auto rhs = [&](int k, int r) -> float2 {
-        const int ku = 16 * blk(k) + 4 * g + r;
+    // s (or b) of slot (k, r) again at the confirm pass; gq is this lane's
+    // g made opaque to the compiler there, so that the addresses are formed
+    // anew rather than kept live (spilled) from the first read
+    auto rhs = [&](int k, int r, int gq) -> float2 {
+        const int ku = 16 * blk(k) + 4 * gq + r;
+        const int bq = b0 + (lane & 15);
         if (!colok || blk(k) >= nub) return float2{0.f, 0.f};
-        if (a.adjoint) return bkeep[(int64_t)b * kpad + ku];
+        if (a.adjoint) return bkeep[(int64_t)bq * kpad + ku];
         if (ku >= K) return float2{0.f, 0.f};
-        return S[(int64_t)b * d.lds + perm[ku]];
+        return S[(int64_t)bq * d.lds + perm[ku]];
     };
 
     // Publish what the next step's products read, with the partial sums:
@@ -289,11 +302,11 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                 const float n2 = x.x * x.x + x.y * x.y;
                 part[0] += n2;
                 if (oahk) {
-                    const float f = L.ff[row(k, r)];
+                    const float f = ffr[ro(k, r)];
                     L.PF[slot * 64 + r * 16 + j] = float2{x.x * f, x.y * f};
                 } else {
-                    const float f = L.fv[row(k, r)];
-                    L.PV[row(k, r) * 16 + j] = float2{x.x * f, x.y * f};
+                    const float f = fvr[ro(k, r)];
+                    PVr[ro(k, r) * 16] = float2{x.x * f, x.y * f};
                     part[1] += n2 * f;
                 }
             }
@@ -344,16 +357,15 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                     block_product<true>(GM, gmc, e0, e0 + ((nf + 3) & ~3), L.PF, L.fslot, pr, pi);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int ku = row(k, r);
-                        const float ff = act ? L.ff[ku] : 0.f;
+                        const float ff = act ? ffr[ro(k, r)] : 0.f;
                         if (ff != 0.f) {
-                            const float2 q = L.Q[ku * 16 + j];
-                            L.Q[ku * 16 + j] = float2{q.x + rr[k][r].x * ff, q.y + rr[k][r].y * ff};
+                            const float2 q = Qr[ro(k, r) * 16];
+                            Qr[ro(k, r) * 16] = float2{q.x + rr[k][r].x * ff, q.y + rr[k][r].y * ff};
                         }
                         if (act) rr[k][r] = float2{rr[k][r].x - pr[r], rr[k][r].y - pi[r]};
-                        const float f = L.fv[ku];
+                        const float f = fvr[ro(k, r)];
                         const float2 x = rr[k][r];
-                        L.PV[ku * 16 + j] = float2{x.x * f, x.y * f};
+                        PVr[ro(k, r) * 16] = float2{x.x * f, x.y * f};
                         nv[0] += (x.x * x.x + x.y * x.y) * f;
                     }
                 }
@@ -374,7 +386,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     pp[k][r] = float2{pr[r], pi[r]};
-                    dn[0] += (rr[k][r].x * pr[r] + rr[k][r].y * pi[r]) * L.fv[row(k, r)];
+                    dn[0] += (rr[k][r].x * pr[r] + rr[k][r].y * pi[r]) * fvr[ro(k, r)];
                 }
             }
             colsum<T, 1>(dn, L.red, 2);
@@ -385,10 +397,9 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                     if (blk(k) >= nub) continue;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int ku = row(k, r);
-                        const float f = gm * L.fv[ku];
-                        const float2 q = L.Q[ku * 16 + j];
-                        L.Q[ku * 16 + j] = float2{q.x + f * rr[k][r].x, q.y + f * rr[k][r].y};
+                        const float f = gm * fvr[ro(k, r)];
+                        const float2 q = Qr[ro(k, r) * 16];
+                        Qr[ro(k, r) * 16] = float2{q.x + f * rr[k][r].x, q.y + f * rr[k][r].y};
                         rr[k][r] = float2{rr[k][r].x - gm * pp[k][r].x, rr[k][r].y - gm * pp[k][r].y};
                     }
                 }
@@ -446,6 +457,8 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
             }
         }
         float t2[1] = {0.f};
+        int gq = g;
+        asm volatile("" : "+v"(gq));
 #pragma unroll
         for (int k = 0; k < BPW; ++k) {
             const int mb = blk(k);
@@ -456,7 +469,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
             block_product<false>(GM, gmc, e0, e1, L.Q, L.fslot, pr, pi);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float2 s0 = rhs(k, r);
+                const float2 s0 = rhs(k, r, gq);
                 rr[k][r] = float2{s0.x - pr[r], s0.y - pi[r]};
                 t2[0] += rr[k][r].x * rr[k][r].x + rr[k][r].y * rr[k][r].y;
             }
@@ -490,7 +503,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ku = row(k, r);
-                const float2 q = L.Q[ku * 16 + j];
+                const float2 q = Qr[ro(k, r) * 16];
                 if (V && ku < K) V[(int64_t)b * ldv + perm[ku]] = q;
                 if (VS) VS[(int64_t)b * kpad + ku] = q;
             }
