@@ -1211,9 +1211,11 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
     const VrkDesc *dd = reinterpret_cast<const VrkDesc *>(pl->d_ws + pl->o_desc);
     if (pl->total_rhs == 0) return VRK_OK;
     const bool mf = pl->engine == VRK_ENGINE_MFMA;
-    // the MFMA solve forms b = H g itself; the vector engine takes it from a kernel
-    hipError_t e = mf ? hipSuccess
-                      : vrk_launch_adjoint_rhs(dd, (int32_t)pl->pp.size(), pl->max_rhs, pl->opt.dtype, s);
+    // the MFMA solve and the vector engine's small-channel form form b = H g
+    // themselves; the general vector form takes it from a kernel
+    hipError_t e = mf || pl->small
+                       ? hipSuccess
+                       : vrk_launch_adjoint_rhs(dd, (int32_t)pl->pp.size(), pl->max_rhs, pl->opt.dtype, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint right-hand side kernel");
     vrk_status st = run_solve(pl, stream, d_iters, d_relres, d_flags, 1);
     if (st != VRK_OK) return st;

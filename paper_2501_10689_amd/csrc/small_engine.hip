@@ -307,28 +307,31 @@ __device__ __forceinline__ void add_row(Ctx<R, T, NA> &c, int u, C<R> g)
     }
 }
 
-// p = H^H f on this wave's antennas, f_u in lane u (0 on users outside the
-// step's set), users four at a time through this wave's broadcast slots.
-// Terms of users with f_u = 0 are exact zeros, so p is the sum over the set.
+// p = H^H f on this wave's antennas over the users in m (f_u in lane u),
+// four at a time through this wave's broadcast slots, in ascending user
+// order.
 template <typename R, int T, int NA>
-__device__ __forceinline__ void adjoint_product(const Ctx<R, T, NA> &c, C<R> f, C<R> (&p)[NA])
+__device__ __forceinline__ void adjoint_product(const Ctx<R, T, NA> &c, C<R> f, uint64_t m, C<R> (&p)[NA])
 {
+    constexpr int kNpad = 64 * T * NA;
     if (c.lane < c.K) c.ph[c.lane] = f;
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int m = 0; m < NA; ++m) p[m] = C<R>{0, 0};
-    for (int u0 = 0; u0 < c.K; u0 += 4) {
+    for (int k = 0; k < NA; ++k) p[k] = C<R>{0, 0};
+    while (m) {
+        int us[4];
+        pop_rows(m, us);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int u = u0 + j < c.K ? u0 + j : c.K - 1;
+            const int u = us[j] < 0 ? us[0] : us[j];
             C<R> fu = c.ph[u];
-            if (u0 + j >= c.K) fu = C<R>{0, 0};
-            const C<R> *h = c.hd + (int64_t)u * c.npad + c.n0;
+            if (us[j] < 0) fu = C<R>{0, 0};
+            const C<R> *h = c.hd + (size_t)u * kNpad + c.n0;
 #pragma unroll
-            for (int m = 0; m < NA; ++m) {
-                const C<R> t = cmulc(fu, h[64 * m]);
-                p[m].re += t.re;
-                p[m].im += t.im;
+            for (int k = 0; k < NA; ++k) {
+                const C<R> t = cmulc(fu, h[64 * k]);
+                p[k].re += t.re;
+                p[k].im += t.im;
             }
         }
     }
@@ -347,7 +350,7 @@ __device__ __forceinline__ void aggregate(Ctx<R, T, NA> &c, bool in_set, R nrm)
     const R phin = wave_sum_dpp(cnorm2(phi));
     if (!(num > 0)) return;   // zero residual on the set: no move (the same in every wave)
     C<R> p[NA];
-    adjoint_product(c, phi, p);
+    adjoint_product(c, phi, __ballot(in_set), p);
     R pn = 0;
 #pragma unroll
     for (int m = 0; m < NA; ++m) pn += cnorm2(p[m]);
@@ -373,15 +376,13 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
     const int N = d.nt, K = d.k;
     constexpr int kNpad = 64 * T * NA;   // antennas of the zero-padded rows
 
-    const C<R> *S;
+    // the adjoint solve forms its right-hand side b = H g itself, below
     C<R> *X, *V;
-    int64_t lds_, ldx_, ldv_;
+    int64_t ldx_, ldv_;
     if (a.adjoint) {
-        S = reinterpret_cast<const C<R> *>(d.Sadj); lds_ = K;
         X = reinterpret_cast<C<R> *>(d.Xadj); ldx_ = N;
         V = reinterpret_cast<C<R> *>(d.GS); ldv_ = d.ldgs;
     } else {
-        S = reinterpret_cast<const C<R> *>(d.S); lds_ = d.lds;
         X = reinterpret_cast<C<R> *>(d.X); ldx_ = d.ldx;
         V = reinterpret_cast<C<R> *>(d.V); ldv_ = d.ldv;
     }
@@ -400,7 +401,7 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
     const R invn = (R)1 / nrm;   // the single-row step's 1 / ||a_i||^2
     const bool inF = isu && d.inf[lane] != 0;
     c.s = C<R>{0, 0};
-    if (isu) c.s = S[(int64_t)b * lds_ + lane];
+    if (isu && !a.adjoint) c.s = reinterpret_cast<const C<R> *>(d.S)[(int64_t)b * d.lds + lane];
     const R fro2 = *reinterpret_cast<const R *>(d.fro2);
 
     // LDS: the channel zero-padded to kpad = 16 ceil(K / 16) rows of kNpad
@@ -441,6 +442,19 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
     }
     __syncthreads();
 
+    if (a.adjoint) {
+        // b = H g from the staged channel: the residual sweep with s = 0,
+        // q = 0 and g in place of x leaves r = -H g (exactly)
+        const C<R> *G = reinterpret_cast<const C<R> *>(d.GX) + (int64_t)b * d.ldgx;
+#pragma unroll
+        for (int m = 0; m < NA; ++m) {
+            const int n = c.n0 + 64 * m;
+            c.x[m] = n < N ? G[n] : C<R>{0, 0};
+        }
+        c.q = C<R>{0, 0};
+        residual_all(c);
+        if (isu) c.s = C<R>{-c.r.re, -c.r.im};
+    }
 #pragma unroll
     for (int m = 0; m < NA; ++m) c.x[m] = C<R>{0, 0};
     c.r = c.s;   // z0 = 0: r0 = s
@@ -502,7 +516,7 @@ __global__ void __launch_bounds__(64 * T) k_small_solve(VrkSolveArgs a)
                 const R invf = inF ? (R)1 / nrm : (R)0;
                 const C<R> phif = C<R>{c.r.re * invf, c.r.im * invf};
                 C<R> p[NA];
-                adjoint_product(c, phif, p);
+                adjoint_product(c, phif, __ballot(inF), p);
 #pragma unroll
                 for (int m = 0; m < NA; ++m) {
                     c.x[m].re += p[m].re;
