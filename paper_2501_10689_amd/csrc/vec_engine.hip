@@ -150,31 +150,39 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
     }
 }
 
-// Gram tiles of M = H H^H + xi I, one wave per tile e of user block mb: lane
-// l = i + 16 kk holds M[perm[16 mb + i], perm[4 c + kk]] = the sum over the
-// antennas of H[u, n] conj(H[v, n]) (+ xi on the diagonal), accumulated in
-// double in antenna order and rounded once. The wave stages 64 antennas of
-// its 16 + 4 rows at a time in LDS (coalesced loads, zero off each VR) over
-// the antennas where a row of the block and a row of the chunk can meet.
-constexpr int kGramRows = VRK_UB + 4;
+// Gram tiles of M = H H^H + xi I on the FP64 matrix cores. One wave takes a
+// group of four entries t0 .. t0 + 3 of a user block's chunk list (the lists
+// are padded to multiples of four, so a group never straddles two blocks):
+// D[i][4 q + kk] = sum_n H[u_i, n] conj(H[v_{q,kk}, n]) for the block's 16
+// users u_i and the four chunks' 16 users v, as three real
+// v_mfma_f64_16x16x4f64 products per four antennas (Gauss), over the
+// antennas where the block and any of the chunks can meet; entries outside
+// a user's VR are taken as zero. Lane l holds the operands of user l % 16 at
+// antenna step offset l / 16 (the loads of sixteen antennas in flight
+// together, one batch ahead); sums in double, rounded once to complex64,
+// plus xi on the diagonal. Tile t's lane i + 16 kk holds entry (i, kk).
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
 {
-    __shared__ cx<float> st[kWaves][kGramRows][65];   // padded rows: the 16 block rows hit different banks
     const VrkDesc &d = descs[blockIdx.y];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
-    const int64_t t = (int64_t)blockIdx.x * kWaves + w;
-    if (t >= d.gm_off[d.nub]) return;   // the wave only: no barrier below
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t t0 = ((int64_t)blockIdx.x * kWaves + w) * 4;
+    if (t0 >= d.gm_off[d.nub]) return;   // the wave only: no barrier below
     int mb = 0;
-    while (d.gm_off[mb + 1] <= t) ++mb;
-    const int uc = d.gm_c[t];   // -1: padding chunk, zero tile
+    while (d.gm_off[mb + 1] <= t0) ++mb;
     const cx<float> *H = reinterpret_cast<const cx<float> *>(d.H);
-    // rows 0..15: users of the block, 16..19: users of the chunk (-1: none);
-    // lane r < 20 keeps row r's user and VR, read back as scalars
+    // lanes 0..15: the block's users; 16..31: the four chunks' users (-1: none)
     int ru = -1, rvs = 0, rve = 0;
-    if (lane < kGramRows && uc >= 0) {
-        const int ks = lane < VRK_UB ? mb * VRK_UB + lane : uc * 4 + (lane - VRK_UB);
-        if (ks < d.k) {
+    if (lane < 32) {
+        int ks = -1;
+        if (lane < VRK_UB) {
+            ks = mb * VRK_UB + lane;
+        } else {
+            const int uc = d.gm_c[t0 + ((lane - VRK_UB) >> 2)];
+            if (uc >= 0) ks = uc * 4 + ((lane - VRK_UB) & 3);
+        }
+        if (ks >= 0 && ks < d.k) {
             ru = d.perm[ks];
             rvs = d.vs[ru];
             rve = d.ve[ru];
@@ -182,7 +190,7 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
     }
     int lo_b = d.nt, hi_b = 0, lo_c = d.nt, hi_c = 0;
 #pragma unroll
-    for (int r = 0; r < kGramRows; ++r) {
+    for (int r = 0; r < 32; ++r) {
         const int u = __builtin_amdgcn_readlane(ru, r), a = __builtin_amdgcn_readlane(rvs, r),
                   b = __builtin_amdgcn_readlane(rve, r);
         if (u < 0 || b <= a) continue;
@@ -190,33 +198,61 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
         else { lo_c = min(lo_c, a); hi_c = max(hi_c, b); }
     }
     const int lo = max(lo_b, lo_c), hi = min(hi_b, hi_c);
-    double ar = 0.0, ai = 0.0;
-    for (int n0 = lo; n0 < hi; n0 += 64) {
-        const int n = n0 + lane;
-        cx<float> v[kGramRows];
+    // this lane's A row (block user) and B column (chunk user), and its step offset
+    const int i = lane & 15, kq = lane >> 4;
+    const int ua = __shfl(ru, i, 64), avs = __shfl(rvs, i, 64), ave = __shfl(rve, i, 64);
+    const int ub = __shfl(ru, VRK_UB + i, 64), bvs = __shfl(rvs, VRK_UB + i, 64), bve = __shfl(rve, VRK_UB + i, 64);
+    const cx<float> *ha = H + (int64_t)(ua < 0 ? 0 : ua) * d.ldh;
+    const cx<float> *hb = H + (int64_t)(ub < 0 ? 0 : ub) * d.ldh;
+    d4 uu = {0, 0, 0, 0}, vv = uu, ww = uu;
+    // sixteen antennas per batch; the next batch's loads are in flight while
+    // this one's products run
+    auto load = [&](int n0, cx<float> (&a)[4], cx<float> (&b)[4]) {
 #pragma unroll
-        for (int r = 0; r < kGramRows; ++r) {
-            const int u = __builtin_amdgcn_readlane(ru, r), a = __builtin_amdgcn_readlane(rvs, r),
-                      b = __builtin_amdgcn_readlane(rve, r);
-            v[r] = cx<float>{0.f, 0.f};
-            if (u >= 0 && n < hi && n >= a && n < b) v[r] = H[(int64_t)u * d.ldh + n];
+        for (int st = 0; st < 4; ++st) {
+            const int n = n0 + 4 * st + kq;
+            a[st] = b[st] = cx<float>{0.f, 0.f};
+            if (ua >= 0 && n < hi && n >= avs && n < ave) a[st] = ha[n];
+            if (ub >= 0 && n < hi && n >= bvs && n < bve) b[st] = hb[n];
         }
-        __builtin_amdgcn_sched_barrier(0);   // all rows' loads in flight before the first wait
+    };
+    cx<float> a[4], b[4], an[4], bn[4];
+    if (lo < hi) load(lo, a, b);
+    for (int n0 = lo; n0 < hi; n0 += 16) {
+        const bool more = n0 + 16 < hi;
+        if (more) load(n0 + 16, an, bn);
+        __builtin_amdgcn_sched_barrier(0);   // the next loads issue before this batch's products
 #pragma unroll
-        for (int r = 0; r < kGramRows; ++r) st[w][r][lane] = v[r];
-        __builtin_amdgcn_wave_barrier();
-        const int m = min(64, hi - n0);
-        for (int q = 0; q < m; ++q) {
-            const cx<float> a = st[w][i][q], b = st[w][VRK_UB + kk][q];
-            ar += (double)a.re * b.re + (double)a.im * b.im;
-            ai += (double)a.im * b.re - (double)a.re * b.im;
+        for (int st = 0; st < 4; ++st) {
+            // a conj(b) with three real products (Gauss): u = ar br,
+            // v = -ai bi, w = (ar + ai)(br - bi); Re = u - v, Im = w - u - v
+            const double ar = a[st].re, ai = a[st].im, br = b[st].re, bi = b[st].im;
+            uu = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, uu, 0, 0, 0);
+            vv = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, -bi, vv, 0, 0, 0);
+            ww = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, br - bi, ww, 0, 0, 0);
         }
-        __builtin_amdgcn_wave_barrier();
+        if (more) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                a[st] = an[st];
+                b[st] = bn[st];
+            }
+        }
     }
-    const int ku = mb * VRK_UB + i, kv = uc * 4 + kk;
-    if (uc >= 0 && ku < d.k && kv < d.k && d.perm[ku] == d.perm[kv]) ar += d.xi;
-    if (uc < 0) ar = ai = 0.0;
-    reinterpret_cast<cx<float> *>(d.GM)[t * 64 + lane] = cx<float>{(float)ar, (float)ai};
+    // output layout of the FP64 product: lane (j, g) holds rows g + 4 r of
+    // column j = 4 q + kk (interleaved, unlike the FP32 products' 4 g + r)
+    const int j = lane & 15, g = lane >> 4, q = j >> 2, kk = j & 3;
+    const int64_t t = t0 + q;
+    const int uc = d.gm_c[t];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ie = g + 4 * r;
+        double re = uu[r] - vv[r], im = ww[r] - uu[r] - vv[r];
+        const int ku = mb * VRK_UB + ie, kv = uc * 4 + kk;
+        if (uc >= 0 && ku < d.k && kv < d.k && d.perm[ku] == d.perm[kv]) re += d.xi;
+        if (uc < 0) re = im = 0.0;
+        reinterpret_cast<cx<float> *>(d.GM)[t * 64 + ie + 16 * kk] = cx<float>{(float)re, (float)im};
+    }
 }
 
 // F columns of M for the VALU orthogonal half-step: entry (ku, tt) =
@@ -720,7 +756,9 @@ hipError_t vrk_launch_pack(const VrkDesc *desc, int32_t nprob, int64_t max_tiles
     if (max_tiles <= 0) return hipSuccess;
     const unsigned gx = (unsigned)((max_tiles + kWaves - 1) / kWaves);
     hipLaunchKernelGGL(k_pack, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
-    hipLaunchKernelGGL(k_gram, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
+    // Gram tiles: one wave per group of four (the per-block lists are padded to multiples of four)
+    const unsigned g4 = (unsigned)((max_tiles + 4 * kWaves - 1) / (4 * kWaves));
+    hipLaunchKernelGGL(k_gram, dim3(g4, nprob), dim3(kThreads), 0, s, desc);
     // MF entries: at most 64 * max_tiles per problem (the plan counts them in max_tiles)
     const unsigned gm = (unsigned)((max_tiles * 64 + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_mf, dim3(gm, nprob), dim3(kThreads), 0, s, desc);
