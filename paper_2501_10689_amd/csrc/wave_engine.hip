@@ -444,10 +444,27 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                 f4 xr, xi;
                 c3_get(acc, xr, xi);
                 const int n0 = 16 * ab + 4 * g;
+                // Streaming stores that fill whole 32-byte sectors: lanes g
+                // and g ^ 1 of a column trade halves (row-swap move), so that
+                // one store writes bytes [0, 32) and [64, 96) of the 16
+                // antennas' 128-byte run and the other [32, 64) and [96, 128).
+                // x is not read again here; it should not push the channel's
+                // tiles out of L2.
+                const f4 h0 = {xr[0], xi[0], xr[1], xi[1]}, h1 = {xr[2], xi[2], xr[3], xi[3]};
+                f4 sa, sb;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(h0[c]), __float_as_uint(h1[c]),
+                                                                    false, false);
+                    sa[c] = __uint_as_float(p[0]);
+                    sb[c] = __uint_as_float(p[1]);
+                }
                 if (colok) {
-                    if (n0 + 3 < N && ((reinterpret_cast<uintptr_t>(row + n0) & 31) == 0)) {
-                        *(gp<float4>)(row + n0) = float4{xr[0], xi[0], xr[1], xi[1]};
-                        *(gp<float4>)(row + n0 + 2) = float4{xr[2], xi[2], xr[3], xi[3]};
+                    const int nb = 16 * ab;
+                    if (nb + 15 < N && ((reinterpret_cast<uintptr_t>(row + nb) & 31) == 0)) {
+                        const int oa = nb + 4 * (g & 2) + 2 * (g & 1), ob = oa + 4;
+                        __builtin_nontemporal_store(sa, (gp<f4>)(row + oa));
+                        __builtin_nontemporal_store(sb, (gp<f4>)(row + ob));
                     } else {
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
