@@ -220,42 +220,84 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
 
     // right-hand side: s (forward) or b = H g (adjoint, from the residual
     // tiles: 16 users x antennas 16 ab + 4 kk + m at lane i + 16 kk, times the
-    // rows of g; the product's output layout is the state layout)
+    // rows of g; the product's output layout is the state layout). The
+    // tile's 16 rows of g go through LDS (the PV buffer, free until the
+    // first publish) nub antenna blocks at a time, in the products' operand
+    // layout [ab][m][lane]: every wave's blocks read them from there, so
+    // each row of g leaves memory once per tile instead of once per block
+    // whose band covers it
     if (a.adjoint) {
         const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
-        const gp<const float2> grow = gmem(static_cast<const float2 *>(d.GX)) + (int64_t)(colok ? b : 0) * d.ldgx;
+        const gp<const float2> GX = gmem(static_cast<const float2 *>(d.GX));
+        const int nbat = nub;   // antenna blocks per batch: PV holds nub x 4 x 64 entries
+        const int span = 16 * nbat;
+        C3 acc[BPW];
+#pragma unroll
+        for (int k = 0; k < BPW; ++k) acc[k] = c3_zero();
+        // this thread's entries e = tid + q T 64 of a batch (16 rows x span
+        // antennas, at most 4 BPW per thread), loaded one batch ahead
+        constexpr int kE = 4 * BPW;
+        float2 gv[kE];
+        auto load_batch = [&](int ab0) {
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const int e = tid + q * T * 64;
+                const int jr = e / span, n = 16 * ab0 + (e - jr * span), br = b0 + jr;
+                gv[q] = float2{0.f, 0.f};
+                if (e < 16 * span && br < nrhs && n < N) gv[q] = GX[(int64_t)br * d.ldgx + n];
+            }
+        };
+        load_batch(0);
+#pragma unroll 1
+        for (int ab0 = 0; ab0 < nab; ab0 += nbat) {
+            __syncthreads();   // the previous batch is consumed
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const int e = tid + q * T * 64;
+                if (e < 16 * span) {
+                    const int jr = e / span, no = e - jr * span, wi = no & 15;   // antenna 16 ab + 4 g' + m
+                    L.PV[((no >> 4) * 4 + (wi & 3)) * 64 + jr + 16 * (wi >> 2)] = gv[q];
+                }
+            }
+            __syncthreads();
+            if (ab0 + nbat < nab) load_batch(ab0 + nbat);   // in flight during the products
+#pragma unroll
+            for (int k = 0; k < BPW; ++k) {
+                const int mb = blk(k);
+                if (mb >= nub) continue;
+                const int lo = gmem(d.rab_lo)[mb], hi = gmem(d.rab_hi)[mb];
+                const int64_t hb = gmem(d.ha_off)[mb];
+                const int a0 = lo > ab0 ? lo : ab0, a1 = hi < ab0 + nbat ? hi : ab0 + nbat;
+#pragma unroll 1
+                for (int ab = a0; ab < a1; ab += 2) {
+                    float2 h[2][4], x[2][4];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const gp<const float2> hp = HA + (hb + 4 * (int64_t)(ab + t - lo)) * 64 + lane;
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            h[t][m] = x[t][m] = float2{0.f, 0.f};
+                            if (ab + t < a1) {
+                                h[t][m] = hp[64 * m];
+                                x[t][m] = L.PV[((ab + t - ab0) * 4 + m) * 64 + lane];
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) c3mfma(acc[k], h[t][m], x[t][m]);
+                }
+            }
+        }
+        __syncthreads();   // PV is free again for the first publish
 #pragma unroll
         for (int k = 0; k < BPW; ++k) {
             const int mb = blk(k);
             if (mb >= nub) continue;
-            const int lo = gmem(d.rab_lo)[mb], hi = gmem(d.rab_hi)[mb];
-            const int64_t hb = gmem(d.ha_off)[mb];
-            C3 acc = c3_zero();
-#pragma unroll 1
-            for (int ab0 = lo; ab0 < hi; ab0 += 2) {
-                float2 h[2][4], x[2][4];
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int ab = ab0 + t;
-                    const gp<const float2> hp = HA + (hb + 4 * (int64_t)(ab - lo)) * 64 + lane;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int n = 16 * ab + 4 * g + m;
-                        h[t][m] = x[t][m] = float2{0.f, 0.f};
-                        if (ab < hi) {
-                            h[t][m] = hp[64 * m];
-                            if (colok && n < N) x[t][m] = grow[n];
-                        }
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) c3mfma(acc, h[t][m], x[t][m]);
-            }
             f4 re, im;
-            c3_get(acc, re, im);
+            c3_get(acc[k], re, im);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 rr[k][r] = float2{re[r], im[r]};
