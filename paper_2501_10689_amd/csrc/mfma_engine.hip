@@ -791,12 +791,16 @@ __device__ __forceinline__ void solve_item(const VrkSolveArgs &a, const int prob
     // ---- outputs: x is in place (form_x, forward only); v (or mu) in caller order and in
     // VR-start order for the gradient products
     {
-        const int b = b0 + j;
+        // the column and the first row made opaque here, so that the output
+        // addresses are formed now rather than kept live (spilled) from init
+        int jq = j, eq = er;
+        asm volatile("" : "+v"(jq), "+v"(eq));
+        const int b = b0 + jq;
         if (b < c.nrhs) {
             const gp<float2> VS = gmem(static_cast<float2 *>(a.adjoint ? d.Msrt : d.Vsrt));
 #pragma unroll
             for (int k = 0; k < EP; ++k) {
-                const int ku = own(k);
+                const int ku = eq + rows_per_pass * k;
                 if (V && ku < K) V[(int64_t)b * ldv_ + c.perm[ku]] = qq[k];
                 if (VS && ku < kpad) VS[(int64_t)b * kpad + ku] = qq[k];
             }
