@@ -150,25 +150,28 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
     }
 }
 
-// Gram tiles of M = H H^H + xi I on the FP64 matrix cores. One wave takes a
-// group of four entries t0 .. t0 + 3 of a user block's chunk list (the lists
-// are padded to multiples of four, so a group never straddles two blocks):
-// D[i][4 q + kk] = sum_n H[u_i, n] conj(H[v_{q,kk}, n]) for the block's 16
-// users u_i and the four chunks' 16 users v, as three real
+// Gram tiles of M = H H^H + xi I on the FP64 matrix cores. One workgroup
+// takes a group of four entries t0 .. t0 + 3 of a user block's chunk list
+// (the lists are padded to multiples of four, so a group never straddles two
+// blocks): D[i][4 q + kk] = sum_n H[u_i, n] conj(H[v_{q,kk}, n]) for the
+// block's 16 users u_i and the four chunks' 16 users v, as three real
 // v_mfma_f64_16x16x4f64 products per four antennas (Gauss), over the
-// antennas where the block and any of the chunks can meet; entries outside
-// a user's VR are taken as zero. Lane l holds the operands of user l % 16 at
-// antenna step offset l / 16 (the loads of sixteen antennas in flight
-// together, one batch ahead); sums in double, rounded once to complex64,
-// plus xi on the diagonal. Tile t's lane i + 16 kk holds entry (i, kk).
+// antennas where the block and any of the chunks can meet, split into four
+// contiguous shares, one per wave; entries outside a user's VR are taken as
+// zero. Lane l holds the operands of user l % 16 at antenna step offset
+// l / 16 (the loads of sixteen antennas in flight together, one batch
+// ahead). The waves' partial sums meet in LDS and are added in wave order,
+// in double, rounded once to complex64, plus xi on the diagonal; wave q
+// writes tile t0 + q, whose lane i + 16 kk holds entry (i, kk).
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
 {
+    __shared__ double part[kWaves][3][4][64];
     const VrkDesc &d = descs[blockIdx.y];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t t0 = ((int64_t)blockIdx.x * kWaves + w) * 4;
-    if (t0 >= d.gm_off[d.nub]) return;   // the wave only: no barrier below
+    const int64_t t0 = (int64_t)blockIdx.x * 4;
+    if (t0 >= d.gm_off[d.nub]) return;   // the whole workgroup: no barrier reached
     int mb = 0;
     while (d.gm_off[mb + 1] <= t0) ++mb;
     const cx<float> *H = reinterpret_cast<const cx<float> *>(d.H);
@@ -198,6 +201,9 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
         else { lo_c = min(lo_c, a); hi_c = max(hi_c, b); }
     }
     const int lo = max(lo_b, lo_c), hi = min(hi_b, hi_c);
+    // this wave's share: batches of 16 antennas split evenly over the waves
+    const int nbt = hi > lo ? (hi - lo + 15) / 16 : 0, per = (nbt + kWaves - 1) / kWaves;
+    const int s0 = lo + 16 * w * per, s1 = min(hi, lo + 16 * (w + 1) * per);
     // this lane's A row (block user) and B column (chunk user), and its step offset
     const int i = lane & 15, kq = lane >> 4;
     const int ua = __shfl(ru, i, 64), avs = __shfl(rvs, i, 64), ave = __shfl(rve, i, 64);
@@ -205,21 +211,19 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
     const cx<float> *ha = H + (int64_t)(ua < 0 ? 0 : ua) * d.ldh;
     const cx<float> *hb = H + (int64_t)(ub < 0 ? 0 : ub) * d.ldh;
     d4 uu = {0, 0, 0, 0}, vv = uu, ww = uu;
-    // sixteen antennas per batch; the next batch's loads are in flight while
-    // this one's products run
     auto load = [&](int n0, cx<float> (&a)[4], cx<float> (&b)[4]) {
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
             const int n = n0 + 4 * st + kq;
             a[st] = b[st] = cx<float>{0.f, 0.f};
-            if (ua >= 0 && n < hi && n >= avs && n < ave) a[st] = ha[n];
-            if (ub >= 0 && n < hi && n >= bvs && n < bve) b[st] = hb[n];
+            if (ua >= 0 && n < s1 && n >= avs && n < ave) a[st] = ha[n];
+            if (ub >= 0 && n < s1 && n >= bvs && n < bve) b[st] = hb[n];
         }
     };
     cx<float> a[4], b[4], an[4], bn[4];
-    if (lo < hi) load(lo, a, b);
-    for (int n0 = lo; n0 < hi; n0 += 16) {
-        const bool more = n0 + 16 < hi;
+    if (s0 < s1) load(s0, a, b);
+    for (int n0 = s0; n0 < s1; n0 += 16) {
+        const bool more = n0 + 16 < s1;
         if (more) load(n0 + 16, an, bn);
         __builtin_amdgcn_sched_barrier(0);   // the next loads issue before this batch's products
 #pragma unroll
@@ -239,20 +243,30 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
             }
         }
     }
-    // output layout of the FP64 product: lane (j, g) holds rows g + 4 r of
-    // column j = 4 q + kk (interleaved, unlike the FP32 products' 4 g + r)
-    const int j = lane & 15, g = lane >> 4, q = j >> 2, kk = j & 3;
-    const int64_t t = t0 + q;
-    const int uc = d.gm_c[t];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int ie = g + 4 * r;
-        double re = uu[r] - vv[r], im = ww[r] - uu[r] - vv[r];
-        const int ku = mb * VRK_UB + ie, kv = uc * 4 + kk;
-        if (uc >= 0 && ku < d.k && kv < d.k && d.perm[ku] == d.perm[kv]) re += d.xi;
-        if (uc < 0) re = im = 0.0;
-        reinterpret_cast<cx<float> *>(d.GM)[t * 64 + ie + 16 * kk] = cx<float>{(float)re, (float)im};
+        part[w][0][r][lane] = uu[r];
+        part[w][1][r][lane] = vv[r];
+        part[w][2][r][lane] = ww[r];
     }
+    __syncthreads();
+    // wave q writes tile t0 + q: lane l = ie + 16 kk, D column 4 q + kk, row
+    // ie; the FP64 product's lane (j, g) holds rows g + 4 r of column j
+    const int ie = lane & 15, kk = lane >> 4, src = 4 * w + kk + 16 * (ie & 3), r = ie >> 2;
+    double su = 0.0, sv = 0.0, sw = 0.0;
+#pragma unroll
+    for (int x = 0; x < kWaves; ++x) {
+        su += part[x][0][r][src];
+        sv += part[x][1][r][src];
+        sw += part[x][2][r][src];
+    }
+    const int64_t t = t0 + w;
+    const int uc = d.gm_c[t];
+    double re = su - sv, im = sw - su - sv;
+    const int ku = mb * VRK_UB + ie, kv = uc * 4 + kk;
+    if (uc >= 0 && ku < d.k && kv < d.k && d.perm[ku] == d.perm[kv]) re += d.xi;
+    if (uc < 0) re = im = 0.0;
+    reinterpret_cast<cx<float> *>(d.GM)[t * 64 + lane] = cx<float>{(float)re, (float)im};
 }
 
 // F columns of M for the VALU orthogonal half-step: entry (ku, tt) =
@@ -756,8 +770,8 @@ hipError_t vrk_launch_pack(const VrkDesc *desc, int32_t nprob, int64_t max_tiles
     if (max_tiles <= 0) return hipSuccess;
     const unsigned gx = (unsigned)((max_tiles + kWaves - 1) / kWaves);
     hipLaunchKernelGGL(k_pack, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
-    // Gram tiles: one wave per group of four (the per-block lists are padded to multiples of four)
-    const unsigned g4 = (unsigned)((max_tiles + 4 * kWaves - 1) / (4 * kWaves));
+    // Gram tiles: one workgroup per group of four (the per-block lists are padded to multiples of four)
+    const unsigned g4 = (unsigned)((max_tiles + 3) / 4);
     hipLaunchKernelGGL(k_gram, dim3(g4, nprob), dim3(kThreads), 0, s, desc);
     // MF entries: at most 64 * max_tiles per problem (the plan counts them in max_tiles)
     const unsigned gm = (unsigned)((max_tiles * 64 + kThreads - 1) / kThreads);
