@@ -686,7 +686,10 @@ def main():
         "bind_ms": bind_ms,
         "accuracy": {"max_rel_err": worst, "mean_rel_err": errsum / B,
                      "all_converged": bool(np.all(fl_all == 1)), "mean_iters": float(it_all.mean()),
-                     "max_iters": int(it_all.max())},
+                     "max_iters": int(it_all.max()),
+                     "adjoint_mean_iters": float(stats_adj[0].float().mean().item()),
+                     "adjoint_max_iters": int(stats_adj[0].max().item()),
+                     "adjoint_all_converged": bool((stats_adj[2] == 1).all().item())},
     }
     if ms_reuse is not None:
         out["channel_reused"] = {"ms_per_step": ms_reuse, "vectors_per_s": B / (ms_reuse * 1e-3),

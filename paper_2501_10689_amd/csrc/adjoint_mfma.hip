@@ -111,7 +111,40 @@ __device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, 
     C3 acc[kUG];
 #pragma unroll
     for (int u = 0; u < kUG; ++u) acc[u] = C3{z, z, z};
-    for (int b0 = bs; b0 < be; b0 += 4 * kQ) {
+    // whole batches: every RHS of the batch is in range, so the loads need no
+    // per-lane guard; the antenna operand comes from a clamped column (a
+    // column past nt only feeds output entries that are never written), the
+    // user operands of a block that does not meet ab are neither loaded nor
+    // used (a wave-uniform branch)
+    int b0 = bs;
+    {
+        const int64_t sy = 4 * ldgx, sv = 4 * (int64_t)kpad;
+        gp<const float2> gy = GX + (int64_t)(bs + kk) * ldgx + (nok ? n : d.nt - 1);
+        gp<const float2> gv = VS + (int64_t)(bs + kk) * kpad + ub0 * VRK_UB + i;
+        for (; b0 + 4 * kQ <= be; b0 += 4 * kQ) {
+            float2 y[kQ], v[kQ][kUG];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) y[q] = gy[q * sy];
+#pragma unroll
+            for (int u = 0; u < kUG; ++u)
+                if (live[u]) {
+#pragma unroll
+                    for (int q = 0; q < kQ; ++q) v[q][u] = gv[q * sv + u * VRK_UB];
+                }
+            gy += kQ * sy;
+            gv += kQ * sv;
+            __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const float2 cy = float2{y[q].x, -y[q].y};
+#pragma unroll
+                for (int u = 0; u < kUG; ++u)
+                    if (live[u]) c3mfma(acc[u], v[q][u], cy);
+            }
+        }
+    }
+    // the last partial batch, guarded per lane
+    for (; b0 < be; b0 += 4 * kQ) {
         float2 y[kQ], v[kQ][kUG];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
@@ -168,11 +201,15 @@ __device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, 
 
 // Workgroups [0, nctile): the C blocks (problem, block, split, row block);
 // then (band tile, split): one RHS range of a band tile, written to GH with
-// nsplit 1, else to its partial in gpart. Four waves per SIMD (left alone,
-// the compiler takes a third more registers and three).
+// nsplit 1, else to its partial in gpart. The band workgroups take the
+// tiles in the order `order` lists them (the groups of one antenna block
+// side by side), dealt out so that each XCD (workgroup x runs on XCD x % 8)
+// walks a contiguous run of that list: tiles that read the same columns of
+// the incoming gradient run together on one L2. Four waves per SIMD (left
+// alone, the compiler takes a third more registers and three).
 __global__ void __launch_bounds__(kGW * 64) __attribute__((amdgpu_waves_per_eu(4)))
-k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, int nsplit, const int4 *ctiles, int nctile, int csplit,
-                 float2 *gpart)
+k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, const int32_t *order, int ntiles, int nsplit,
+                 const int4 *ctiles, int nctile, int csplit, float2 *gpart)
 {
     __shared__ float2 part[kGW][kUG][256];
     if ((int)blockIdx.x < nctile) {
@@ -182,8 +219,10 @@ k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, int nsplit, const int4
                   __builtin_amdgcn_readfirstlane(tl.z), csplit, part[0]);
         return;
     }
-    const int bid = blockIdx.x - nctile;
-    const int tix = bid / nsplit, split = bid % nsplit;
+    const int bid = blockIdx.x - nctile, n = ntiles * nsplit;
+    const int q = n / VRK_NQUEUE, rem = n % VRK_NQUEUE, xq = bid % VRK_NQUEUE, iq = bid / VRK_NQUEUE;
+    const int item = xq < rem ? xq * (q + 1) + iq : rem * (q + 1) + (xq - rem) * q + iq;
+    const int tix = gmem(order)[item / nsplit], split = item % nsplit;
     const int4 tl = gmem(tiles)[tix];   // (problem, user-block group, antenna block, flags)
     CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
     const int ubg = __builtin_amdgcn_readfirstlane(tl.y), ab = __builtin_amdgcn_readfirstlane(tl.z);
@@ -453,15 +492,16 @@ __global__ void __launch_bounds__(kGW * 64) k_adj_grads_reduce_split(const VrkDe
 
 }  // namespace
 
-hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, int32_t ntiles, int32_t nsplit,
+hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, const int32_t *order, int32_t ntiles,
+                                         int32_t nsplit,
                                          const int4 *ctiles, int32_t nctiles, int32_t csplit, const int4 *runs,
                                          int32_t nruns, float2 *gpart, hipStream_t s)
 {
     if (csplit < 1 || csplit > kMaxCsplit) return hipErrorInvalidValue;
     const int64_t nwg = (int64_t)nctiles + (int64_t)ntiles * nsplit;
     if (nwg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_grads_mfma, dim3((unsigned)nwg), dim3(kGW * 64), 0, s, desc, tiles, nsplit, ctiles,
-                       nctiles, csplit, gpart);
+    hipLaunchKernelGGL(k_adj_grads_mfma, dim3((unsigned)nwg), dim3(kGW * 64), 0, s, desc, tiles, order, ntiles,
+                       nsplit, ctiles, nctiles, csplit, gpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || ntiles <= 0) return e;
     if (nsplit > 1)

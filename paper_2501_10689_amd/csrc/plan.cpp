@@ -122,6 +122,8 @@ struct vrk_plan {
     int32_t csplit = 1;         // RHS splits of the C blocks (1..4)
     std::vector<int4> gruns;    // runs of band tiles of the gradient's second kernel
     size_t o_gruns = 0;
+    std::vector<int32_t> gorder;   // band tiles in dispatch order: by (problem, antenna block, group)
+    size_t o_gorder = 0;
     std::vector<VrkLinkOut> link_host;   // output table of the link metrics, uploaded per call
     size_t o_link = 0, o_linkpart = 0;   // link-metric output table; partial sums of ||X||_F^2
     int32_t persistent = 0, grid = 0;
@@ -782,6 +784,16 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
                     for (int e = q.cp_off[mb]; e < q.cp_off[mb + 1]; ++e)
                         for (int cs = 0; cs < pl->csplit; ++cs) pl->ctiles.push_back(make_int4(i, e, cs, mb));
             }
+            // dispatch order of the band tiles: the groups that meet one
+            // antenna block next to each other, so that they read its columns
+            // of the incoming gradient from one XCD's L2 at about one time
+            pl->gorder.resize(pl->gtiles.size());
+            for (size_t t = 0; t < pl->gtiles.size(); ++t) pl->gorder[t] = (int32_t)t;
+            std::stable_sort(pl->gorder.begin(), pl->gorder.end(), [&](int32_t a, int32_t b) {
+                const int4 &ta = pl->gtiles[a], &tb = pl->gtiles[b];
+                if (ta.x != tb.x) return ta.x < tb.x;
+                return ta.z < tb.z;
+            });
             // runs of at most R consecutive band tiles of one (problem, user
             // block group), R chosen for about 1024 runs
             const int R = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)pl->gtiles.size() / 1024));
@@ -805,6 +817,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
     pl->o_queue = cv.take(sizeof(int32_t) * 3 * VRK_NQUEUE);
     pl->o_ctiles = cv.take(sizeof(int4) * std::max<size_t>(1, pl->ctiles.size()));
     pl->o_gruns = cv.take(sizeof(int4) * std::max<size_t>(1, pl->gruns.size()));
+    pl->o_gorder = cv.take(sizeof(int32_t) * std::max<size_t>(1, pl->gorder.size()));
     for (auto &q : pl->pp) {
         const int K = q.p.k;
         q.o_vs = cv.take(4 * K);
@@ -1007,6 +1020,8 @@ static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
         std::memcpy(pl->image.data() + pl->o_ctiles, pl->ctiles.data(), sizeof(int4) * pl->ctiles.size());
     if (!pl->gruns.empty())
         std::memcpy(pl->image.data() + pl->o_gruns, pl->gruns.data(), sizeof(int4) * pl->gruns.size());
+    if (!pl->gorder.empty())
+        std::memcpy(pl->image.data() + pl->o_gorder, pl->gorder.data(), sizeof(int32_t) * pl->gorder.size());
     {
         int32_t *qv = reinterpret_cast<int32_t *>(pl->image.data() + pl->o_queue);
         for (int qi = 0; qi < VRK_NQUEUE; ++qi) {
@@ -1220,6 +1235,7 @@ vrk_status vrk_solve_adjoint(vrk_plan *pl, void *stream, int32_t *d_iters, float
     vrk_status st = run_solve(pl, stream, d_iters, d_relres, d_flags, 1);
     if (st != VRK_OK) return st;
     e = mf ? vrk_launch_adjoint_grads_mfma(dd, reinterpret_cast<const int4 *>(pl->d_ws + pl->o_gtiles),
+                                           reinterpret_cast<const int32_t *>(pl->d_ws + pl->o_gorder),
                                            (int32_t)pl->gtiles.size(), pl->gsplit,
                                            reinterpret_cast<const int4 *>(pl->d_ws + pl->o_ctiles),
                                            (int32_t)pl->ctiles.size(), pl->csplit,
