@@ -87,6 +87,64 @@ __device__ __forceinline__ void cmat_part(CDesc &d, int p, int ub, int split, in
 // to a partial.
 constexpr int kQ = 4;   // reduction steps (4 RHS each) per batch of loads
 
+// The whole stages of one wave's RHS range [bs, be) for the band tile
+// blocks in MASK (bit u: block ub0 + u meets the antenna block; a
+// compile-time set, so every load is unconditional and the compiler knows
+// how many are in flight): a stage is KP steps of 4 RHS, the next stage's
+// loads are issued before this stage's products. After the last stage the
+// pointers stop advancing, so the loads of the stage after it repeat the
+// last one (in range) and are not used. Returns the first RHS not done.
+template <int MASK>
+__device__ __forceinline__ int band_stages(gp<const float2> gy, gp<const float2> gv, int64_t ldgx, int kpad, int bs,
+                                           int be, C3 (&acc)[kUG])
+{
+    constexpr int nl = __builtin_popcount(MASK);
+    constexpr int KP = nl <= 2 ? 4 : 2;
+    const int64_t sy = 4 * ldgx, sv = 4 * (int64_t)kpad;
+    const int nst = (be - bs) / (4 * KP);
+    if (nst <= 0) return bs;
+    struct Stage {
+        float2 y[KP], v[KP][kUG];
+    };
+    auto load = [&](Stage &t) {
+#pragma unroll
+        for (int q = 0; q < KP; ++q) t.y[q] = gy[q * sy];
+#pragma unroll
+        for (int u = 0; u < kUG; ++u)
+            if (MASK >> u & 1) {
+#pragma unroll
+                for (int q = 0; q < KP; ++q) t.v[q][u] = gv[q * sv + u * VRK_UB];
+            }
+    };
+    auto advance = [&](bool more) {
+        gy += more ? KP * sy : 0;
+        gv += more ? KP * sv : 0;
+    };
+    auto mul = [&](const Stage &t) {
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            const float2 cy = float2{t.y[q].x, -t.y[q].y};
+#pragma unroll
+            for (int u = 0; u < kUG; ++u)
+                if (MASK >> u & 1) c3mfma(acc[u], t.v[q][u], cy);
+        }
+    };
+    Stage A, B;
+    load(A);
+#pragma unroll 1
+    for (int st = 0; st < nst; st += 2) {
+        advance(st + 1 < nst);
+        load(B);   // stage st + 1, or stage st again
+        __builtin_amdgcn_sched_barrier(0);   // the loads issue before the products
+        mul(A);    // stage st
+        advance(st + 2 < nst);
+        load(A);   // stage st + 2, or the last stage again
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < nst) mul(B);
+    }
+    return bs + nst * 4 * KP;
+}
+
 __device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, int be0, float2 (*part)[kUG][256],
                                             gp<float2> out)
 {
@@ -111,36 +169,25 @@ __device__ __forceinline__ void grads_group(CDesc &d, int ubg, int ab, int bs0, 
     C3 acc[kUG];
 #pragma unroll
     for (int u = 0; u < kUG; ++u) acc[u] = C3{z, z, z};
-    // whole batches: every RHS of the batch is in range, so the loads need no
+    // whole stages: every RHS of the stage is in range, so the loads need no
     // per-lane guard; the antenna operand comes from a clamped column (a
-    // column past nt only feeds output entries that are never written), the
-    // user operands of a block that does not meet ab are neither loaded nor
-    // used (a wave-uniform branch)
+    // column past nt only feeds output entries that are never written)
     int b0 = bs;
     {
-        const int64_t sy = 4 * ldgx, sv = 4 * (int64_t)kpad;
+        int mask = 0;
+#pragma unroll
+        for (int u = 0; u < kUG; ++u) mask |= live[u] ? 1 << u : 0;
+        mask = __builtin_amdgcn_readfirstlane(mask);
         gp<const float2> gy = GX + (int64_t)(bs + kk) * ldgx + (nok ? n : d.nt - 1);
         gp<const float2> gv = VS + (int64_t)(bs + kk) * kpad + ub0 * VRK_UB + i;
-        for (; b0 + 4 * kQ <= be; b0 += 4 * kQ) {
-            float2 y[kQ], v[kQ][kUG];
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) y[q] = gy[q * sy];
-#pragma unroll
-            for (int u = 0; u < kUG; ++u)
-                if (live[u]) {
-#pragma unroll
-                    for (int q = 0; q < kQ; ++q) v[q][u] = gv[q * sv + u * VRK_UB];
-                }
-            gy += kQ * sy;
-            gv += kQ * sv;
-            __builtin_amdgcn_sched_barrier(0);   // all loads in flight before the first wait
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const float2 cy = float2{y[q].x, -y[q].y};
-#pragma unroll
-                for (int u = 0; u < kUG; ++u)
-                    if (live[u]) c3mfma(acc[u], v[q][u], cy);
-            }
+        switch (mask) {
+#define VRK_BAND_CASE(M) \
+    case M: b0 = band_stages<M>(gy, gv, ldgx, kpad, bs, be, acc); break;
+            VRK_BAND_CASE(1) VRK_BAND_CASE(2) VRK_BAND_CASE(3) VRK_BAND_CASE(4) VRK_BAND_CASE(5)
+            VRK_BAND_CASE(6) VRK_BAND_CASE(7) VRK_BAND_CASE(8) VRK_BAND_CASE(9) VRK_BAND_CASE(10)
+            VRK_BAND_CASE(11) VRK_BAND_CASE(12) VRK_BAND_CASE(13) VRK_BAND_CASE(14) VRK_BAND_CASE(15)
+#undef VRK_BAND_CASE
+            default: break;
         }
     }
     // the last partial batch, guarded per lane
