@@ -266,9 +266,7 @@ k_adj_grads_mfma(const VrkDesc *descs, const int4 *tiles, const int32_t *order, 
                   __builtin_amdgcn_readfirstlane(tl.z), csplit, part[0]);
         return;
     }
-    const int bid = blockIdx.x - nctile, n = ntiles * nsplit;
-    const int q = n / VRK_NQUEUE, rem = n % VRK_NQUEUE, xq = bid % VRK_NQUEUE, iq = bid / VRK_NQUEUE;
-    const int item = xq < rem ? xq * (q + 1) + iq : rem * (q + 1) + (xq - rem) * q + iq;
+    const int item = xcd_item(blockIdx.x - nctile, ntiles * nsplit);
     const int tix = gmem(order)[item / nsplit], split = item % nsplit;
     const int4 tl = gmem(tiles)[tix];   // (problem, user-block group, antenna block, flags)
     CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl.x)];
@@ -298,7 +296,8 @@ __global__ void __launch_bounds__(kGW * 64) __attribute__((amdgpu_waves_per_eu(4
                                                              const int4 *runs, int nsplit, int csplit,
                                                              const float2 *gpart)
 {
-    const int4 rn = gmem(runs)[blockIdx.x];   // (first tile, tile count, flags, 0)
+    // each XCD takes a contiguous run of the list (neighbouring runs read the same tiles of H)
+    const int4 rn = gmem(runs)[xcd_item(blockIdx.x, gridDim.x)];   // (first tile, tile count, flags, 0)
     const int t0 = __builtin_amdgcn_readfirstlane(rn.x), nt = __builtin_amdgcn_readfirstlane(rn.y);
     const int4 tl0 = gmem(tiles)[t0];
     CDesc &d = ((CDesc *)descs)[__builtin_amdgcn_readfirstlane(tl0.x)];

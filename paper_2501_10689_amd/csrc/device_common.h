@@ -457,3 +457,14 @@ __device__ __forceinline__ float col4_sum(float v)
     const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
     return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
+
+// Workgroup x of a launch of n runs on XCD x % VRK_NQUEUE (the order in
+// which the dispatcher deals workgroups out). This returns the work item it
+// takes so that each XCD walks its own contiguous run of the items, x / 8
+// ascending (split evenly when 8 does not divide n): items next to each
+// other in the list share one L2 and run at about one time.
+__device__ __forceinline__ int xcd_item(int x, int n)
+{
+    const int q = n / VRK_NQUEUE, rem = n % VRK_NQUEUE, xq = x % VRK_NQUEUE, iq = x / VRK_NQUEUE;
+    return xq < rem ? xq * (q + 1) + iq : rem * (q + 1) + (xq - rem) * q + iq;
+}

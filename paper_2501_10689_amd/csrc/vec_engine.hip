@@ -168,9 +168,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
 {
     __shared__ double part[kWaves][3][4][64];
-    const VrkDesc &d = descs[blockIdx.y];
+    // (problem, group) from an XCD-contiguous walk of the grid, so that the
+    // groups of one user block, which read the same rows of H, share an L2
+    const int item = xcd_item(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const VrkDesc &d = descs[item / gridDim.x];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t t0 = (int64_t)blockIdx.x * 4;
+    const int64_t t0 = (int64_t)(item % gridDim.x) * 4;
     if (t0 >= d.gm_off[d.nub]) return;   // the whole workgroup: no barrier reached
     int mb = 0;
     while (d.gm_off[mb + 1] <= t0) ++mb;

@@ -576,19 +576,14 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
     }
 }
 
-// One workgroup per work item. Workgroup x runs on XCD x % 8 (the order in
-// which the dispatcher deals workgroups out), so it takes work item
-// (x % 8) * n / 8 + x / 8 (split evenly when 8 does not divide n): each XCD
-// walks its own contiguous run of items, so its L2 holds the tiles of few
-// channels at a time.
+// One workgroup per work item, dealt out by xcd_item: each XCD walks its own
+// contiguous run of items, so its L2 holds the tiles of few channels at a
+// time.
 template <int T, int BPW, int VARIANT>
 __global__ void __launch_bounds__(T * 64) __attribute__((amdgpu_waves_per_eu(BPW == 4 ? 2 : 4))) k_wave_solve(VrkSolveArgs a, const VrkWork *work, int nitems)
 {
     extern __shared__ __align__(16) char smem[];
-    const int q = nitems / VRK_NQUEUE, rem = nitems % VRK_NQUEUE;
-    const int xcd = blockIdx.x % VRK_NQUEUE, idx = blockIdx.x / VRK_NQUEUE;
-    const int item = xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
-    const VrkWork wk = gmem(work)[item];
+    const VrkWork wk = gmem(work)[xcd_item(blockIdx.x, nitems)];
     wave_item<T, BPW, VARIANT>(a, __builtin_amdgcn_readfirstlane(wk.prob), __builtin_amdgcn_readfirstlane(wk.tile),
                                smem);
 }
