@@ -111,40 +111,41 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
         // the four residual tiles m = 0..3 of one (user block, antenna
         // block): lane (i, kk) loads antennas 16 ab + 4 kk .. + 3 of its row
         // (contiguous) and writes one of them to each tile
-        int ub = 0;
-        while (d.ha_off[ub + 1] <= t * 4) ++ub;
+        const int ub = wave_segment(d.ha_off, d.nub, t * 4);
         const int64_t c0 = t * 4 - d.ha_off[ub];
         const int ab = d.rab_lo[ub] + (int)(c0 >> 2);
         const int ku = ub * VRK_UB + i;
         cx<float> v[4] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
         if (ku < d.k) {
+            // the row's entries load beside its VR bounds, then the VR selects
             const int u = d.perm[ku];
+            const cx<float> *h = H + (int64_t)u * d.ldh;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int n = ab * VRK_AB + 4 * kk + m;
-                if (n >= d.vs[u] && n < d.ve[u]) v[m] = H[(int64_t)u * d.ldh + n];
+                if (n < d.nt) v[m] = h[n];
+            }
+            const int vs = d.vs[u], ve = d.ve[u];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int n = ab * VRK_AB + 4 * kk + m;
+                if (n < vs || n >= ve) v[m] = cx<float>{0.f, 0.f};
             }
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) reinterpret_cast<cx<float> *>(d.HA)[(t * 4 + m) * 64 + lane] = v[m];
     }
     if (t < n_hg) {
-        int lo = 0, hi = d.nab;   // ab with ag_off[ab] <= t < ag_off[ab+1]
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (d.ag_off[mid] <= t) lo = mid; else hi = mid;
-        }
-        int ab = lo;
-        int uc = d.ag_uc[t];
-        int n = ab * VRK_AB + i;
-        int ku = uc * 4 + kk;
+        const int ab = wave_segment(d.ag_off, d.nab, t);   // ag_off[ab] <= t < ag_off[ab + 1]
+        const int uc = d.ag_uc[t];
+        const int n = ab * VRK_AB + i;
+        const int ku = uc * 4 + kk;
         cx<float> v = {0.f, 0.f};
         if (ku < d.k) {
-            int u = d.perm[ku];
-            if (n >= d.vs[u] && n < d.ve[u]) {
-                cx<float> h = H[(int64_t)u * d.ldh + n];
-                v = {h.re, -h.im};
-            }
+            const int u = d.perm[ku];
+            cx<float> h = {0.f, 0.f};
+            if (n < d.nt) h = H[(int64_t)u * d.ldh + n];
+            if (n >= d.vs[u] && n < d.ve[u]) v = {h.re, -h.im};
         }
         reinterpret_cast<cx<float> *>(d.HG)[t * 64 + lane] = v;
     }
@@ -175,8 +176,7 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t t0 = (int64_t)(item % gridDim.x) * 4;
     if (t0 >= d.gm_off[d.nub]) return;   // the whole workgroup: no barrier reached
-    int mb = 0;
-    while (d.gm_off[mb + 1] <= t0) ++mb;
+    const int mb = wave_segment(d.gm_off, d.nub, t0);
     const cx<float> *H = reinterpret_cast<const cx<float> *>(d.H);
     // lanes 0..15: the block's users; 16..31: the four chunks' users (-1: none)
     int ru = -1, rvs = 0, rve = 0;
