@@ -222,15 +222,22 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
     // tiles: 16 users x antennas 16 ab + 4 kk + m at lane i + 16 kk, times the
     // rows of g; the product's output layout is the state layout). The
     // tile's 16 rows of g go through LDS (the PV buffer, free until the
-    // first publish) nub antenna blocks at a time, in the products' operand
-    // layout [ab][m][lane]: every wave's blocks read them from there, so
-    // each row of g leaves memory once per tile instead of once per block
-    // whose band covers it
+    // first publish) a batch of antenna blocks at a time: every wave's blocks
+    // read them from there, so each row of g leaves memory once per tile
+    // instead of once per block whose band covers it. The batch is stored
+    // row by row (as read from memory), antenna n of row jr at
+    // span jr + (n ^ f(jr)) with f(jr) = (jr & 3) + 8 (jr >> 2): the stores
+    // are contiguous runs, and the operand reads (row j, antennas
+    // 4 kk + m + 16 c of the 32 lanes of a half-wave) fall in distinct banks
     if (a.adjoint) {
         const gp<const float2> HA = gmem(static_cast<const float2 *>(d.HA));
         const gp<const float2> GX = gmem(static_cast<const float2 *>(d.GX));
-        const int nbat = nub;   // antenna blocks per batch: PV holds nub x 4 x 64 entries
+        // antenna blocks per batch (PV holds 16 rows x 16 nub entries), even
+        // when it can be so that a row spans whole 32-entry swizzle groups
+        const int nbat = nub >= 2 ? (nub & ~1) : 1;
         const int span = 16 * nbat;
+        const bool swz = (span & 31) == 0;
+        auto fsw = [&](int jr) { return swz ? (jr & 3) + 8 * (jr >> 2) : 0; };
         C3 acc[BPW];
 #pragma unroll
         for (int k = 0; k < BPW; ++k) acc[k] = c3_zero();
@@ -248,6 +255,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
             }
         };
         load_batch(0);
+        const int fj = fsw(j);
 #pragma unroll 1
         for (int ab0 = 0; ab0 < nab; ab0 += nbat) {
             __syncthreads();   // the previous batch is consumed
@@ -255,8 +263,8 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
             for (int q = 0; q < kE; ++q) {
                 const int e = tid + q * T * 64;
                 if (e < 16 * span) {
-                    const int jr = e / span, no = e - jr * span, wi = no & 15;   // antenna 16 ab + 4 g' + m
-                    L.PV[((no >> 4) * 4 + (wi & 3)) * 64 + jr + 16 * (wi >> 2)] = gv[q];
+                    const int jr = e / span, no = e - jr * span;
+                    L.PV[jr * span + (no ^ fsw(jr))] = gv[q];
                 }
             }
             __syncthreads();
@@ -279,7 +287,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                             h[t][m] = x[t][m] = float2{0.f, 0.f};
                             if (ab + t < a1) {
                                 h[t][m] = hp[64 * m];
-                                x[t][m] = L.PV[((ab + t - ab0) * 4 + m) * 64 + lane];
+                                x[t][m] = L.PV[j * span + ((16 * (ab + t - ab0) + 4 * g + m) ^ fj)];
                             }
                         }
                     }
