@@ -168,7 +168,11 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
 {
-    __shared__ double part[kWaves][3][4][64];
+    // partial tiles, row-major with rows padded to 17 entries: the stores
+    // (a row's 16 columns) and the transposed reads (one column's 16 rows)
+    // both fall in distinct LDS banks
+    constexpr int kRow = 17;
+    __shared__ double part[kWaves][3][16 * kRow];
     // (problem, group) from an XCD-contiguous walk of the grid, so that the
     // groups of one user block, which read the same rows of H, share an L2
     const int item = xcd_item(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -246,22 +250,23 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
             }
         }
     }
+    // the FP64 product's lane (j, g) holds rows g + 4 r of column j
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        part[w][0][r][lane] = uu[r];
-        part[w][1][r][lane] = vv[r];
-        part[w][2][r][lane] = ww[r];
+        const int o = ((lane >> 4) + 4 * r) * kRow + (lane & 15);
+        part[w][0][o] = uu[r];
+        part[w][1][o] = vv[r];
+        part[w][2][o] = ww[r];
     }
     __syncthreads();
-    // wave q writes tile t0 + q: lane l = ie + 16 kk, D column 4 q + kk, row
-    // ie; the FP64 product's lane (j, g) holds rows g + 4 r of column j
-    const int ie = lane & 15, kk = lane >> 4, src = 4 * w + kk + 16 * (ie & 3), r = ie >> 2;
+    // wave q writes tile t0 + q: lane l = ie + 16 kk, D row ie, column 4 q + kk
+    const int ie = lane & 15, kk = lane >> 4, src = ie * kRow + 4 * w + kk;
     double su = 0.0, sv = 0.0, sw = 0.0;
 #pragma unroll
     for (int x = 0; x < kWaves; ++x) {
-        su += part[x][0][r][src];
-        sv += part[x][1][r][src];
-        sw += part[x][2][r][src];
+        su += part[x][0][src];
+        sv += part[x][1][src];
+        sw += part[x][2][src];
     }
     const int64_t t = t0 + w;
     const int uc = d.gm_c[t];
