@@ -76,6 +76,7 @@ struct ProbPlan {
     bool stage_h = false;         // vector engine: H's VR entries staged in LDS
     std::vector<int32_t> gaps;    // (user, first antenna, length) of hidden runs inside the hulls
     std::vector<int32_t> fch;     // 4-user chunks (VR-start order) holding a user of F, ascending
+    std::vector<int32_t> gm_fs;   // per Gram list entry: its chunk's index in fch, else VRK_WAVE_FCHUNKS
     std::vector<int64_t> ha_off;
     int64_t n_ha = 0, n_hg = 0, n_gm = 0, band = 0;
     // workspace offsets
@@ -84,7 +85,8 @@ struct ProbPlan {
         o_ha, o_hg, o_sadj, o_xadj, o_vfwd, o_vsrt = 0, o_msrt = 0;
     int64_t rhs_base = 0;
     size_t o_gmoff = 0, o_gmc = 0, o_gm = 0, o_gmnf = 0, o_fpos = 0, o_mf = 0;
-    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0, o_gaps = 0, o_mask = 0, o_fch = 0;
+    size_t o_cpoff = 0, o_cpcol = 0, o_cptr = 0, o_cpdiag = 0, o_cblk = 0, o_gaps = 0, o_mask = 0, o_fch = 0,
+           o_gmfs = 0;
 };
 
 }  // namespace
@@ -481,6 +483,12 @@ void build_tables(ProbPlan &q)
     }
     q.gm_off[q.nub] = (int32_t)q.gm_c.size();
     q.n_gm = (int64_t)q.gm_c.size();
+    q.gm_fs.assign(q.gm_c.size(), VRK_WAVE_FCHUNKS);
+    for (size_t e = 0; e < q.gm_c.size(); ++e) {
+        const auto it = std::lower_bound(q.fch.begin(), q.fch.end(), q.gm_c[e]);
+        if (q.gm_c[e] >= 0 && it != q.fch.end() && *it == q.gm_c[e] && it - q.fch.begin() < VRK_WAVE_FCHUNKS)
+            q.gm_fs[e] = (int32_t)(it - q.fch.begin());
+    }
     // 16 x 16 blocks (ub, ub') of the same pattern, for C = sum_b v_b mu_b^H
     // of the adjoint gradient; the pattern is symmetric and holds every
     // diagonal block
@@ -849,6 +857,7 @@ vrk_status vrk_plan_create(const vrk_problem *probs, int32_t nprob, const vrk_op
         q.o_gaps = cv.take(4 * q.gaps.size());
         q.o_mask = cv.take(8 * q.mask.size());
         q.o_fch = cv.take(4 * q.fch.size());
+        q.o_gmfs = cv.take(4 * q.gm_fs.size());
     }
     pl->table_end = cv.off;
     pl->o_link = cv.take(sizeof(VrkLinkOut) * nprob);
@@ -947,6 +956,7 @@ static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
         put(img, q.o_gaps, q.gaps);
         put(img, q.o_mask, q.mask);
         put(img, q.o_fch, q.fch);
+        put(img, q.o_gmfs, q.gm_fs);
         VrkDesc &d = descs[i];
         std::memset(&d, 0, sizeof d);
         const vrk_problem &p = q.p;
@@ -1009,6 +1019,7 @@ static vrk_status bind_at(vrk_plan *pl, void *d_ws, void *stream)
         d.gaps = (const int32_t *)(base + q.o_gaps);
         d.nfch = (int32_t)q.fch.size();
         d.fch = (const int32_t *)(base + q.o_fch);
+        d.gm_fs = (const int32_t *)(base + q.o_gmfs);
         (void)eb;
     }
     std::memcpy(pl->image.data() + pl->o_desc, descs.data(), sizeof(VrkDesc) * descs.size());

@@ -89,6 +89,10 @@ struct VrkDesc {
     // holding a user of F, ascending; at most VRK_WAVE_FCHUNKS
     int32_t nfch, pad4;
     const int32_t *fch;
+    // wave-owned MFMA engine, VR-OAHK: per entry of the Gram chunk lists
+    // (gm_c), the chunk's slot in the compact buffer when it holds a user of
+    // F, else VRK_WAVE_FCHUNKS (the spare slot, kept zero)
+    const int32_t *gm_fs;
 };
 
 // Chunks of F users the wave-owned engine keeps in its compact buffer.

@@ -50,7 +50,7 @@ struct WLds {
     float2 *Q;    // the dual iterate q: [row][16]; each entry is touched by its owner lane
                   // only, except as the operand of x = H^H q and M q at the confirm pass
     float2 *PF;   // VR-OAHK: phi of the orthogonal half-step, the chunks holding users of F:
-                  // [slot][64], slot VRK_WAVE_FCHUNKS takes the writes of other chunks
+                  // [slot][64]; slot VRK_WAVE_FCHUNKS stays zero (the operand of other chunks)
     int *fslot;   // VR-OAHK: chunk -> slot in PF, or VRK_WAVE_FCHUNKS
     float *fv;    // per row: 1 / ||a||^2 on the rows of the aggregated step, else 0
     float *ff;    // per row (VR-OAHK): 1 / ||a||^2 on the rows of F, else 0
@@ -115,23 +115,19 @@ __device__ __forceinline__ void colsum(float (&v)[NV], float *red, int slot)
 
 // Product of one owned row block with the B operand in LDS: the block's
 // chunk entries [e0, e1) (a multiple of four; padding entries hold zero
-// tiles), tile e of M at GM[64 e + lane] times chunk gmc[e] of the operand.
-// FONLY: the operand is the compact PF buffer (chunks of F users), zero for
-// other chunks. Software-pipelined: the tiles of the next four chunks are
-// in flight while the current four are multiplied.
-template <bool FONLY>
-__device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> gmc, int e0, int e1, const float2 *B,
-                                              const int *fslot, f4 &pr, f4 &pi)
+// tiles), tile e of M at GM[64 e + lane] times chunk idx[e] of the operand
+// (the entry's chunk, gm_c; or for the compact PF buffer of F chunks its
+// slot there, gm_fs, whose spare slot is zero for other chunks).
+// Software-pipelined: the tiles of the next four chunks are in flight while
+// the current four are multiplied.
+__device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> idx, int e0, int e1, const float2 *B,
+                                              f4 &pr, f4 &pi)
 {
     const int lane = threadIdx.x & 63;
     C3 acc = c3_zero();
     auto operand = [&](int e) -> float2 {
-        const int uc = __builtin_amdgcn_readfirstlane(gmc[e]);
-        if (FONLY) {
-            const int s = uc >= 0 ? fslot[uc] : VRK_WAVE_FCHUNKS;
-            return s < VRK_WAVE_FCHUNKS ? B[s * 64 + lane] : float2{0.f, 0.f};
-        }
-        return B[(uc > 0 ? uc : 0) * 64 + lane];
+        const int c = __builtin_amdgcn_readfirstlane(idx[e]);
+        return B[(c > 0 ? c : 0) * 64 + lane];
     };
     float2 m[4], mn[4];
     if (e0 < e1) {
@@ -174,7 +170,8 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
     wave_lds_layout(kpad, T, oahk, smem, &L);
     const gp<const float2> GM = gmem(static_cast<const float2 *>(d.GM));
     const gp<const int32_t> perm = gmem(d.perm);
-    const cp<int32_t> gmoff = (cp<int32_t>)d.gm_off, gmc = (cp<int32_t>)d.gm_c, gmnf = (cp<int32_t>)d.gm_nf;
+    const cp<int32_t> gmoff = (cp<int32_t>)d.gm_off, gmc = (cp<int32_t>)d.gm_c, gmnf = (cp<int32_t>)d.gm_nf,
+                      gmfs = (cp<int32_t>)d.gm_fs;
     const gp<const float> nrm_g = gmem(static_cast<const float *>(d.nrm));
     const gp<const uint8_t> inf = gmem(d.inf);
     const gp<float2> bkeep = gmem(static_cast<float2 *>(d.Msrt));
@@ -209,6 +206,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
     }
     if (oahk) {
         for (int i = tid; i < kpad / 4; i += T * 64) L.fslot[i] = VRK_WAVE_FCHUNKS;
+        if (tid < 64) L.PF[VRK_WAVE_FCHUNKS * 64 + tid] = float2{0.f, 0.f};
         __syncthreads();
         for (int t = tid; t < d.nfch; t += T * 64) L.fslot[gmem(d.fch)[t]] = t;
     }
@@ -344,7 +342,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
             const int mb = blk(k);
             if (mb >= nub) continue;
             // chunk 4 mb + g holds this lane's four rows; chunks without a
-            // user of F write to the spare slot
+            // user of F write nothing (their operand is the zero spare slot)
             const int slot = oahk ? L.fslot[4 * mb + g] : 0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -353,7 +351,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                 part[0] += n2;
                 if (oahk) {
                     const float f = ffr[ro(k, r)];
-                    L.PF[slot * 64 + r * 16 + j] = float2{x.x * f, x.y * f};
+                    if (slot < VRK_WAVE_FCHUNKS) L.PF[slot * 64 + r * 16 + j] = float2{x.x * f, x.y * f};
                 } else {
                     const float f = fvr[ro(k, r)];
                     PVr[ro(k, r) * 16] = float2{x.x * f, x.y * f};
@@ -404,7 +402,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                     const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
                     const int nf = __builtin_amdgcn_readfirstlane(gmnf[mb]);
                     f4 pr, pi;
-                    block_product<true>(GM, gmc, e0, e0 + ((nf + 3) & ~3), L.PF, L.fslot, pr, pi);
+                    block_product(GM, gmfs, e0, e0 + ((nf + 3) & ~3), L.PF, pr, pi);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float ff = act ? ffr[ro(k, r)] : 0.f;
@@ -432,7 +430,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                 const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
                 const int e1 = __builtin_amdgcn_readfirstlane(gmoff[mb + 1]);
                 f4 pr, pi;
-                block_product<false>(GM, gmc, e0, e1, L.PV, L.fslot, pr, pi);
+                block_product(GM, gmc, e0, e1, L.PV, pr, pi);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     pp[k][r] = float2{pr[r], pi[r]};
@@ -533,7 +531,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
             const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
             const int e1 = __builtin_amdgcn_readfirstlane(gmoff[mb + 1]);
             f4 pr, pi;
-            block_product<false>(GM, gmc, e0, e1, L.Q, L.fslot, pr, pi);
+            block_product(GM, gmc, e0, e1, L.Q, pr, pi);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float2 s0 = rhs(k, r, gq);
