@@ -469,27 +469,38 @@ __device__ __forceinline__ int xcd_item(int x, int n)
     return xq < rem ? xq * (q + 1) + iq : rem * (q + 1) + (xq - rem) * q + iq;
 }
 
-// Segment of a wave-uniform position t in a nondecreasing offset table
-// off[0 .. n] with off[0] <= t < off[n]: the s with off[s] <= t < off[s + 1]
-// (empty segments skipped), counted as the entries off[1 .. n] that are
-// <= t. Every lane loads its share of the table at once and a ballot counts,
-// so the search costs one memory latency rather than one per step. Call it
-// with the whole wave active.
-template <typename T>
-__device__ __forceinline__ int wave_segment(const T *offp, int n, int64_t t)
+// Segments of Q wave-uniform positions t0 + q stride in a nondecreasing
+// offset table off[0 .. n] with off[0] <= t: s[q] with off[s] <= t < off[s + 1]
+// (empty segments skipped; n for a position at or past off[n]), counted as
+// the entries off[1 .. n] that are <= t. Every lane loads its share of the
+// table once and ballots count for all Q positions, so the search costs one
+// memory latency rather than one per step. Call it with the whole wave
+// active.
+template <int Q, typename T>
+__device__ __forceinline__ void wave_segments(const T *offp, int n, int64_t t0, int64_t stride, int (&s)[Q])
 {
     const auto off = gmem(offp);
     const int lane = threadIdx.x & 63;
-    int s = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] = 0;
     for (int c0 = 0; c0 < n; c0 += 256) {
         int64_t v[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int j = 1 + c0 + 64 * c + lane;
-            v[c] = j <= n ? (int64_t)off[j] : t + 1;
+            v[c] = j <= n ? (int64_t)off[j] : INT64_MAX;
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) s += __popcll(__ballot(v[c] <= t));
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) s[q] += __popcll(__ballot(v[c] <= t0 + q * stride));
     }
-    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ int wave_segment(const T *offp, int n, int64_t t)
+{
+    int s[1];
+    wave_segments<1>(offp, n, t, 0, s);
+    return s[0];
 }

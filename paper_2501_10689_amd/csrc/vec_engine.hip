@@ -98,56 +98,100 @@ __global__ void __launch_bounds__(64) k_fro(const VrkDesc *descs)
 // Wave t packs residual tiles 4t .. 4t + 3 and aggregation tile t; the Gram
 // tiles and F columns follow in k_gram, k_mf.
 // ---------------------------------------------------------------------------
+template <int kPackQ>
 __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
 {
+    // each wave takes kPackQ consecutive items of both kinds, their loads in
+    // flight together: the per-item chain (offset table, row index, row
+    // data) is paid once for kPackQ items (4 on deep batches; 1 when there
+    // are too few items to fill the device that way)
     const VrkDesc &d = descs[blockIdx.y];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)blockIdx.x * kWaves + w;
+    const int64_t t0 = ((int64_t)blockIdx.x * kWaves + w) * kPackQ;
     const int64_t n_ha = d.ha_off[d.nub];
     const int64_t n_hg = d.ag_off[d.nab];
     const cx<float> *H = reinterpret_cast<const cx<float> *>(d.H);
+    cx<float> *HA = reinterpret_cast<cx<float> *>(d.HA);
+    cx<float> *HG = reinterpret_cast<cx<float> *>(d.HG);
     const int i = lane & 15, kk = lane >> 4;
-    if (t * 4 < n_ha) {
-        // the four residual tiles m = 0..3 of one (user block, antenna
-        // block): lane (i, kk) loads antennas 16 ab + 4 kk .. + 3 of its row
-        // (contiguous) and writes one of them to each tile
-        const int ub = wave_segment(d.ha_off, d.nub, t * 4);
-        const int64_t c0 = t * 4 - d.ha_off[ub];
-        const int ab = d.rab_lo[ub] + (int)(c0 >> 2);
-        const int ku = ub * VRK_UB + i;
-        cx<float> v[4] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-        if (ku < d.k) {
-            // the row's entries load beside its VR bounds, then the VR selects
-            const int u = d.perm[ku];
-            const cx<float> *h = H + (int64_t)u * d.ldh;
+    if (t0 * 4 < n_ha) {
+        // item q: the four residual tiles m = 0..3 of one (user block,
+        // antenna block), tiles 4 (t0 + q) + m: lane (i, kk) loads antennas
+        // 16 ab + 4 kk .. + 3 of its row (contiguous) and writes one of them
+        // to each tile
+        int ub[kPackQ];
+        wave_segments<kPackQ>(d.ha_off, d.nub, t0 * 4, 4, ub);
+        int ab[kPackQ], u[kPackQ];
+        bool ok[kPackQ];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int n = ab * VRK_AB + 4 * kk + m;
-                if (n < d.nt) v[m] = h[n];
-            }
-            const int vs = d.vs[u], ve = d.ve[u];
+        for (int q = 0; q < kPackQ; ++q) {
+            ok[q] = (t0 + q) * 4 < n_ha;
+            const int b = ok[q] ? ub[q] : 0;
+            ab[q] = d.rab_lo[b] + (int)(((t0 + q) * 4 - d.ha_off[b]) >> 2);
+            const int ku = b * VRK_UB + i;
+            u[q] = ok[q] && ku < d.k ? d.perm[ku] : -1;
+        }
+        cx<float> v[kPackQ][4];
+        int vs[kPackQ], ve[kPackQ];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int n = ab * VRK_AB + 4 * kk + m;
-                if (n < vs || n >= ve) v[m] = cx<float>{0.f, 0.f};
+        for (int q = 0; q < kPackQ; ++q) {
+            vs[q] = ve[q] = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v[q][m] = cx<float>{0.f, 0.f};
+            if (u[q] >= 0) {
+                // the row's entries load beside its VR bounds, then the VR selects
+                const cx<float> *h = H + (int64_t)u[q] * d.ldh;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int n = ab[q] * VRK_AB + 4 * kk + m;
+                    if (n < d.nt) v[q][m] = h[n];
+                }
+                vs[q] = d.vs[u[q]];
+                ve[q] = d.ve[u[q]];
             }
         }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) reinterpret_cast<cx<float> *>(d.HA)[(t * 4 + m) * 64 + lane] = v[m];
+        for (int q = 0; q < kPackQ; ++q) {
+            if (!ok[q]) continue;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int n = ab[q] * VRK_AB + 4 * kk + m;
+                const cx<float> x = n < vs[q] || n >= ve[q] ? cx<float>{0.f, 0.f} : v[q][m];
+                HA[((t0 + q) * 4 + m) * 64 + lane] = x;
+            }
+        }
     }
-    if (t < n_hg) {
-        const int ab = wave_segment(d.ag_off, d.nab, t);   // ag_off[ab] <= t < ag_off[ab + 1]
-        const int uc = d.ag_uc[t];
-        const int n = ab * VRK_AB + i;
-        const int ku = uc * 4 + kk;
-        cx<float> v = {0.f, 0.f};
-        if (ku < d.k) {
-            const int u = d.perm[ku];
-            cx<float> h = {0.f, 0.f};
-            if (n < d.nt) h = H[(int64_t)u * d.ldh + n];
-            if (n >= d.vs[u] && n < d.ve[u]) v = {h.re, -h.im};
+    if (t0 < n_hg) {
+        // item q: aggregation tile t0 + q of antenna block ab, chunk uc:
+        // lane (i, kk) holds conj(H[perm[4 uc + kk], 16 ab + i])
+        int ab[kPackQ];
+        wave_segments<kPackQ>(d.ag_off, d.nab, t0, 1, ab);   // ag_off[ab] <= t < ag_off[ab + 1]
+        int u[kPackQ];
+#pragma unroll
+        for (int q = 0; q < kPackQ; ++q) {
+            const bool ok = t0 + q < n_hg;
+            const int ku = ok ? d.ag_uc[t0 + q] * 4 + kk : d.k;
+            u[q] = ku < d.k ? d.perm[ku] : -1;
         }
-        reinterpret_cast<cx<float> *>(d.HG)[t * 64 + lane] = v;
+        cx<float> h[kPackQ];
+        int vs[kPackQ], ve[kPackQ];
+#pragma unroll
+        for (int q = 0; q < kPackQ; ++q) {
+            const int n = ab[q] * VRK_AB + i;
+            h[q] = cx<float>{0.f, 0.f};
+            vs[q] = ve[q] = 0;
+            if (u[q] >= 0) {
+                if (n < d.nt) h[q] = H[(int64_t)u[q] * d.ldh + n];
+                vs[q] = d.vs[u[q]];
+                ve[q] = d.ve[u[q]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPackQ; ++q) {
+            if (t0 + q >= n_hg) continue;
+            const int n = ab[q] * VRK_AB + i;
+            HG[(t0 + q) * 64 + lane] = n >= vs[q] && n < ve[q] ? cx<float>{h[q].re, -h[q].im} : cx<float>{0.f, 0.f};
+        }
     }
 }
 
@@ -776,8 +820,13 @@ hipError_t vrk_launch_norms(const VrkDesc *desc, int32_t nprob, int32_t dtype, h
 hipError_t vrk_launch_pack(const VrkDesc *desc, int32_t nprob, int64_t max_tiles, hipStream_t s)
 {
     if (max_tiles <= 0) return hipSuccess;
-    const unsigned gx = (unsigned)((max_tiles + kWaves - 1) / kWaves);
-    hipLaunchKernelGGL(k_pack, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
+    if (max_tiles * nprob >= 4 * 16384) {
+        const unsigned gx = (unsigned)((max_tiles + kWaves * 4 - 1) / (kWaves * 4));
+        hipLaunchKernelGGL(k_pack<4>, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
+    } else {
+        const unsigned gx = (unsigned)((max_tiles + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL(k_pack<1>, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
+    }
     // Gram tiles: one workgroup per group of four (the per-block lists are padded to multiples of four)
     const unsigned g4 = (unsigned)((max_tiles + 3) / 4);
     hipLaunchKernelGGL(k_gram, dim3(g4, nprob), dim3(kThreads), 0, s, desc);
