@@ -82,12 +82,18 @@ __global__ void __launch_bounds__(kThreads) k_norms(const VrkDesc *descs)
 template <typename R>
 __global__ void __launch_bounds__(64) k_fro(const VrkDesc *descs)
 {
+    // the sum in index order, as one thread would take it; the wave loads
+    // 64 norms at a time (all in flight) and the adds read them lane by lane
     const VrkDesc &d = descs[blockIdx.x];
-    if (threadIdx.x != 0) return;
     const R *nrm = reinterpret_cast<const R *>(d.nrm);
+    const int lane = threadIdx.x;
     R t = 0;
-    for (int i = 0; i < d.k; ++i) t += nrm[i];
-    *reinterpret_cast<R *>(d.fro2) = t;
+    for (int i0 = 0; i0 < d.k; i0 += 64) {
+        const R v = i0 + lane < d.k ? nrm[i0 + lane] : (R)0;
+        const int n = d.k - i0 < 64 ? d.k - i0 : 64;
+        for (int l = 0; l < n; ++l) t += lane_read(v, l);
+    }
+    if (lane == 0) *reinterpret_cast<R *>(d.fro2) = t;
 }
 
 // ---------------------------------------------------------------------------
