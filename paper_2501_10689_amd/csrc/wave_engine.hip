@@ -117,11 +117,14 @@ __device__ __forceinline__ void colsum(float (&v)[NV], float *red, int slot)
 // chunk entries [e0, e1) (a multiple of four; padding entries hold zero
 // tiles), tile e of M at GM[64 e + lane] times chunk idx[e] of the operand
 // (the entry's chunk, gm_c; or for the compact PF buffer of F chunks its
-// slot there, gm_fs, whose spare slot is zero for other chunks).
+// slot there, gm_fs, whose spare slot is zero for other chunks). Entries at
+// or past e_real, or with a negative index (padding), contribute zero: their
+// tiles are loaded like the others (so the waits stay fixed counts) but
+// their products are skipped (a wave-uniform branch).
 // Software-pipelined: the tiles of the next four chunks are in flight while
 // the current four are multiplied.
-__device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> idx, int e0, int e1, const float2 *B,
-                                              f4 &pr, f4 &pi)
+__device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> idx, int e0, int e1, int e_real,
+                                              const float2 *B, f4 &pr, f4 &pi)
 {
     const int lane = threadIdx.x & 63;
     C3 acc = c3_zero();
@@ -129,6 +132,7 @@ __device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> i
         const int c = __builtin_amdgcn_readfirstlane(idx[e]);
         return B[(c > 0 ? c : 0) * 64 + lane];
     };
+    auto real = [&](int e) { return e < e_real && __builtin_amdgcn_readfirstlane(idx[e]) >= 0; };
     float2 m[4], mn[4];
     if (e0 < e1) {
 #pragma unroll
@@ -145,7 +149,8 @@ __device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> i
 #pragma unroll
         for (int i = 0; i < 4; ++i) f[i] = operand(e + i);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) c3mfma(acc, m[i], f[i]);
+        for (int i = 0; i < 4; ++i)
+            if (real(e + i)) c3mfma(acc, m[i], f[i]);
         if (more) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) m[i] = mn[i];
@@ -402,7 +407,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                     const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
                     const int nf = __builtin_amdgcn_readfirstlane(gmnf[mb]);
                     f4 pr, pi;
-                    block_product(GM, gmfs, e0, e0 + ((nf + 3) & ~3), L.PF, pr, pi);
+                    block_product(GM, gmfs, e0, e0 + ((nf + 3) & ~3), e0 + nf, L.PF, pr, pi);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float ff = act ? ffr[ro(k, r)] : 0.f;
@@ -430,7 +435,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                 const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
                 const int e1 = __builtin_amdgcn_readfirstlane(gmoff[mb + 1]);
                 f4 pr, pi;
-                block_product(GM, gmc, e0, e1, L.PV, pr, pi);
+                block_product(GM, gmc, e0, e1, e1, L.PV, pr, pi);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     pp[k][r] = float2{pr[r], pi[r]};
@@ -531,7 +536,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
             const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
             const int e1 = __builtin_amdgcn_readfirstlane(gmoff[mb + 1]);
             f4 pr, pi;
-            block_product(GM, gmc, e0, e1, L.Q, pr, pi);
+            block_product(GM, gmc, e0, e1, e1, L.Q, pr, pi);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float2 s0 = rhs(k, r, gq);
