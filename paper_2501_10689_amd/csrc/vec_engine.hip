@@ -101,8 +101,10 @@ __global__ void __launch_bounds__(64) k_fro(const VrkDesc *descs)
 // holds H[perm[16 ub + i], 16 ab + 4 kk + m] with ab = rab_lo[ub] + c / 4,
 // m = c % 4, zero outside that user's VR. Aggregation tile e of antenna
 // block ab: lane l = i + 16 kk holds conj(H[perm[4 uc + kk], 16 ab + i]).
-// Wave t packs residual tiles 4t .. 4t + 3 and aggregation tile t; the Gram
-// tiles and F columns follow in k_gram, k_mf.
+// An item is the four residual tiles 4t .. 4t + 3 (one user block, one
+// antenna block), or aggregation tile t; a wave packs items t of both kinds
+// for kPackQ consecutive t. The Gram tiles and F columns follow in k_gram,
+// k_mf.
 // ---------------------------------------------------------------------------
 template <int kPackQ>
 __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
