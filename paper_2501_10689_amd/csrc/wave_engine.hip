@@ -117,13 +117,13 @@ __device__ __forceinline__ void colsum(float (&v)[NV], float *red, int slot)
 // chunk entries [e0, e1) (a multiple of four; padding entries hold zero
 // tiles), tile e of M at GM[64 e + lane] times chunk idx[e] of the operand
 // (the entry's chunk, gm_c; or for the compact PF buffer of F chunks its
-// slot there, gm_fs, whose spare slot is zero for other chunks). Entries at
-// or past e_real, or with a negative index (padding), contribute zero: their
-// tiles are loaded like the others (so the waits stay fixed counts) but
-// their products are skipped (a wave-uniform branch).
-// Software-pipelined: the tiles of the next four chunks are in flight while
-// the current four are multiplied.
-__device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> idx, int e0, int e1, int e_real,
+// slot there, gm_fs, whose spare slot is zero for other chunks). Only the
+// entries before e_real contribute (the others are padding, at the end of
+// the list): whole groups of four run without branches, software-pipelined
+// (the tiles of the next group in flight while the current one is
+// multiplied); the last group, when e_real cuts it, skips the products of
+// its padding entries.
+__device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> idx, int e0, int e_real,
                                               const float2 *B, f4 &pr, f4 &pi)
 {
     const int lane = threadIdx.x & 63;
@@ -132,15 +132,16 @@ __device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> i
         const int c = __builtin_amdgcn_readfirstlane(idx[e]);
         return B[(c > 0 ? c : 0) * 64 + lane];
     };
-    auto real = [&](int e) { return e < e_real && __builtin_amdgcn_readfirstlane(idx[e]) >= 0; };
+    const int ef = e0 + ((e_real - e0) & ~3);   // end of the whole groups
+    const int eg = ef < e_real ? ef + 4 : ef;   // end of the groups loaded
     float2 m[4], mn[4];
-    if (e0 < e1) {
+    if (e0 < eg) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) m[i] = GM[(int64_t)(e0 + i) * 64 + lane];
     }
 #pragma unroll 1
-    for (int e = e0; e < e1; e += 4) {
-        const bool more = e + 4 < e1;
+    for (int e = e0; e < ef; e += 4) {
+        const bool more = e + 4 < eg;
         if (more) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) mn[i] = GM[(int64_t)(e + 4 + i) * 64 + lane];
@@ -149,14 +150,32 @@ __device__ __forceinline__ void block_product(gp<const float2> GM, cp<int32_t> i
 #pragma unroll
         for (int i = 0; i < 4; ++i) f[i] = operand(e + i);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (real(e + i)) c3mfma(acc, m[i], f[i]);
+        for (int i = 0; i < 4; ++i) c3mfma(acc, m[i], f[i]);
         if (more) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) m[i] = mn[i];
         }
     }
+    if (ef < e_real) {
+        float2 f[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] = operand(ef + i);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (ef + i < e_real) c3mfma(acc, m[i], f[i]);
+    }
     c3_get(acc, pr, pi);
+}
+
+// End of the real entries of a chunk list [e0, e1): the padding (-1) entries
+// close it, at most three (the lists are padded to a multiple of four).
+__device__ __forceinline__ int list_real_end(cp<int32_t> idx, int e0, int e1)
+{
+    int e = e1;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (e > e0 && __builtin_amdgcn_readfirstlane(idx[e - 1]) < 0) --e;
+    return e;
 }
 
 template <int T, int BPW, int VARIANT>
@@ -407,7 +426,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                     const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
                     const int nf = __builtin_amdgcn_readfirstlane(gmnf[mb]);
                     f4 pr, pi;
-                    block_product(GM, gmfs, e0, e0 + ((nf + 3) & ~3), e0 + nf, L.PF, pr, pi);
+                    block_product(GM, gmfs, e0, e0 + nf, L.PF, pr, pi);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float ff = act ? ffr[ro(k, r)] : 0.f;
@@ -435,7 +454,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
                 const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
                 const int e1 = __builtin_amdgcn_readfirstlane(gmoff[mb + 1]);
                 f4 pr, pi;
-                block_product(GM, gmc, e0, e1, e1, L.PV, pr, pi);
+                block_product(GM, gmc, e0, list_real_end(gmc, e0, e1), L.PV, pr, pi);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     pp[k][r] = float2{pr[r], pi[r]};
@@ -536,7 +555,7 @@ __device__ __forceinline__ void wave_item(const VrkSolveArgs &a, const int prob,
             const int e0 = __builtin_amdgcn_readfirstlane(gmoff[mb]);
             const int e1 = __builtin_amdgcn_readfirstlane(gmoff[mb + 1]);
             f4 pr, pi;
-            block_product(GM, gmc, e0, e1, e1, L.Q, pr, pi);
+            block_product(GM, gmc, e0, list_real_end(gmc, e0, e1), L.Q, pr, pi);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float2 s0 = rhs(k, r, gq);
