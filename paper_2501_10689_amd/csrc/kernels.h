@@ -85,7 +85,9 @@ hipError_t vrk_launch_link(const VrkDesc *desc, const VrkLinkOut *outs, int32_t 
 // complex64), else they write GH. A second kernel, one workgroup per run
 // (first tile, tile count, flags: bit 0 first run of its problem, 0) of
 // consecutive band tiles of one user-block group, sums the partials in
-// fixed order, subtracts (C + C^H) H on the band and writes gxi.
+// fixed order, subtracts (C + C^H) H on the band and writes gxi. order
+// (ntiles entries) lists the band tiles in dispatch order, by problem and
+// antenna block.
 hipError_t vrk_launch_adjoint_grads_mfma(const VrkDesc *desc, const int4 *tiles, const int32_t *order, int32_t ntiles,
                                          int32_t nsplit,
                                          const int4 *ctiles, int32_t nctiles, int32_t csplit, const int4 *runs,
