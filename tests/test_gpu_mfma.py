@@ -335,3 +335,40 @@ def test_large_adjoint_reduction_runs():
         assert rel_err_rows(g["X"], Xs[jd]).max() <= 1e-4, jd
         ref = oracle.rzf_grad(d.H, d.vr_start, d.vr_len, d.S, d.xi, Gs[jd])
         check_grads(g, ref, np.abs(d.H) > 0, 2e-4, label="large drop %d" % jd)
+
+
+@pytest.mark.parametrize("nrhs", [64, 256])
+def test_adjoint_band_tiles_with_gaps_in_the_block_set(nrhs):
+    """VRs built so that the user blocks meeting an antenna block are not
+    contiguous (Nt 1024, K 64: four blocks of 16 users in VR-start order, the
+    first and third with long VRs, the second and fourth with short ones), so
+    the gradient's band loop runs its variants for block sets such as {0, 2},
+    {0, 2, 3} and {2} as well as {0} and {0, 1}; 64 vectors (one RHS split per
+    band tile) and 256 (split tiles). dL/dH, dL/ds, dL/dxi against the closed
+    form entry by entry."""
+    rng = np.random.default_rng(77)
+    nt, k = 1024, 64
+    starts = np.concatenate([np.arange(16), 100 + np.arange(16), 200 + np.arange(16), 300 + np.arange(16)])
+    lens = np.concatenate([1008 - np.arange(16), np.full(16, 60), np.full(16, 800), np.full(16, 40)])
+    order = rng.permutation(k)
+    vs, vl = starts[order].astype(np.int32), lens[order].astype(np.int32)
+    H = np.zeros((k, nt), dtype=np.complex128)
+    for u in range(k):
+        H[u, vs[u]:vs[u] + vl[u]] = (rng.standard_normal(vl[u]) + 1j * rng.standard_normal(vl[u])) * 0.3
+    xi = k / 10.0
+    # the block sets per 16-antenna block, blocks in VR-start order
+    srt = np.argsort(vs, kind="stable")
+    hull = [(vs[srt[16 * b:16 * b + 16]].min(), (vs + vl)[srt[16 * b:16 * b + 16]].max()) for b in range(4)]
+    sets = {tuple(b for b in range(4) if hull[b][0] < 16 * (ab + 1) and 16 * ab < hull[b][1]) for ab in range(nt // 16)}
+    assert (vs + vl).max() <= nt and {(0, 2), (0, 2, 3), (2,)} <= sets, sets
+    S = qpsk(rng, (nrhs, k))
+    X, _ = oracle.rzf(H, vs, vl, S, xi)
+    d = type("D", (), {"H": H, "S": S})
+    G = _loss_grad(d, X, nrhs)
+    res, plan = run_plan([(H, vs, vl, S, xi)], variant="vr_oahk", engine="mfma", tol=1e-6, adjoint_g=[G])
+    g = res[0]
+    print("gradient plan: band tiles %d, splits %d" % tuple(plan.query(0, 7)[:2]))
+    assert np.all(g["flags"] == oracle.F_CONVERGED) and np.all(g["adj_flags"] == oracle.F_CONVERGED)
+    assert rel_err_rows(g["X"], X).max() <= 1e-4
+    ref = oracle.rzf_grad(H, vs, vl, S, xi, G)
+    check_grads(g, ref, np.abs(H) > 0, 2e-4, label="block-set gaps, %d vectors" % nrhs)
