@@ -372,3 +372,35 @@ def test_adjoint_band_tiles_with_gaps_in_the_block_set(nrhs):
     assert rel_err_rows(g["X"], X).max() <= 1e-4
     ref = oracle.rzf_grad(H, vs, vl, S, xi, G)
     check_grads(g, ref, np.abs(H) > 0, 2e-4, label="block-set gaps, %d vectors" % nrhs)
+
+
+@pytest.mark.parametrize("wave_tiles", [0, 2])
+def test_wide_array_many_drops(wave_tiles):
+    """Thirty-two drops of Nt 8192 (512 antenna blocks: the tile packing and the
+    Gram kernels search offset tables of more than 256 entries, in several
+    passes) with K 48 and VR U[512, 2048], 16 QPSK vectors each: enough
+    tiles that the packing takes four items per wave. VR-OAHK forward and
+    adjoint on the block tiles and on wave-owned tiles; every x within 1e-4
+    of the FP64 RZF and every gradient against the closed form entry by
+    entry."""
+    rng = np.random.default_rng(8192)
+    nt, k, nv = 8192, 48, 16
+    drops, Gs, Xs, ref = [], [], [], []
+    for _ in range(32):
+        H, vs, vl, xi = random_problem(rng, nt, k, lo=512, hi=2048)
+        S = qpsk(rng, (nv, k))
+        X, _ = oracle.rzf(H, vs, vl, S, xi)
+        d = type("D", (), {"H": H, "S": S})
+        drops.append((H, vs, vl, S, xi))
+        Xs.append(X)
+        Gs.append(_loss_grad(d, X, 32 * nv))
+    res, plan = run_plan(drops, variant="vr_oahk", engine="mfma", tol=1e-6, adjoint_g=Gs, wave_tiles=wave_tiles)
+    tq = [plan.query(j, 6) for j in range(len(drops))]
+    # residual, aggregation and Gram tiles: enough for the four-item packing
+    assert max(max(int(t[0]), int(t[1]), int(t[3])) for t in tq) * len(drops) >= 4 * 16384, tq[0]
+    for jd, (H, vs, vl, S, xi) in enumerate(drops):
+        g = res[jd]
+        assert np.all(g["flags"] == oracle.F_CONVERGED) and np.all(g["adj_flags"] == oracle.F_CONVERGED), jd
+        assert rel_err_rows(g["X"], Xs[jd]).max() <= 1e-4, jd
+        r = oracle.rzf_grad(H, vs, vl, S, xi, Gs[jd])
+        check_grads(g, r, np.abs(H) > 0, 2e-4, label="Nt 8192 drop %d" % jd)
