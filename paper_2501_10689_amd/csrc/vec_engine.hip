@@ -209,8 +209,9 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
 // blocks): D[i][4 q + kk] = sum_n H[u_i, n] conj(H[v_{q,kk}, n]) for the
 // block's 16 users u_i and the four chunks' 16 users v, as three real
 // v_mfma_f64_16x16x4f64 products per four antennas (Gauss), over the
-// antennas where the block and any of the chunks can meet, split into four
-// contiguous shares, one per wave; entries outside a user's VR are taken as
+// antennas where the block and any of the chunks can meet, split into
+// contiguous shares, one per wave (four, or eight when there are few groups
+// to fill the device); entries outside a user's VR are taken as
 // zero. Lane l holds the operands of user l % 16 at antenna step offset
 // l / 16 (the loads of sixteen antennas in flight together, one batch
 // ahead). The waves' partial sums meet in LDS and are added in wave order,
@@ -218,13 +219,14 @@ __global__ void __launch_bounds__(kThreads) k_pack(const VrkDesc *descs)
 // writes tile t0 + q, whose lane i + 16 kk holds entry (i, kk).
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
+template <int GW>
+__global__ void __launch_bounds__(GW * 64) k_gram(const VrkDesc *descs)
 {
     // partial tiles, row-major with rows padded to 17 entries: the stores
     // (a row's 16 columns) and the transposed reads (one column's 16 rows)
     // both fall in distinct LDS banks
     constexpr int kRow = 17;
-    __shared__ double part[kWaves][3][16 * kRow];
+    __shared__ double part[GW][3][16 * kRow];
     // (problem, group) from an XCD-contiguous walk of the grid, so that the
     // groups of one user block, which read the same rows of H, share an L2
     const int item = xcd_item(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -261,7 +263,7 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
     }
     const int lo = max(lo_b, lo_c), hi = min(hi_b, hi_c);
     // this wave's share: batches of 16 antennas split evenly over the waves
-    const int nbt = hi > lo ? (hi - lo + 15) / 16 : 0, per = (nbt + kWaves - 1) / kWaves;
+    const int nbt = hi > lo ? (hi - lo + 15) / 16 : 0, per = (nbt + GW - 1) / GW;
     const int s0 = lo + 16 * w * per, s1 = min(hi, lo + 16 * (w + 1) * per);
     // this lane's A row (block user) and B column (chunk user), and its step offset
     const int i = lane & 15, kq = lane >> 4;
@@ -311,11 +313,12 @@ __global__ void __launch_bounds__(kThreads) k_gram(const VrkDesc *descs)
         part[w][2][o] = ww[r];
     }
     __syncthreads();
+    if (w >= 4) return;   // past the barrier: waves 4.. only added range shares
     // wave q writes tile t0 + q: lane l = ie + 16 kk, D row ie, column 4 q + kk
     const int ie = lane & 15, kk = lane >> 4, src = ie * kRow + 4 * w + kk;
     double su = 0.0, sv = 0.0, sw = 0.0;
 #pragma unroll
-    for (int x = 0; x < kWaves; ++x) {
+    for (int x = 0; x < GW; ++x) {
         su += part[x][0][src];
         sv += part[x][1][src];
         sw += part[x][2][src];
@@ -835,9 +838,14 @@ hipError_t vrk_launch_pack(const VrkDesc *desc, int32_t nprob, int64_t max_tiles
         const unsigned gx = (unsigned)((max_tiles + kWaves - 1) / kWaves);
         hipLaunchKernelGGL(k_pack<1>, dim3(gx, nprob), dim3(kThreads), 0, s, desc);
     }
-    // Gram tiles: one workgroup per group of four (the per-block lists are padded to multiples of four)
+    // Gram tiles: one workgroup per group of four (the per-block lists are
+    // padded to multiples of four); eight waves share a group's antenna range
+    // when there are few groups to fill the device
     const unsigned g4 = (unsigned)((max_tiles + 3) / 4);
-    hipLaunchKernelGGL(k_gram, dim3(g4, nprob), dim3(kThreads), 0, s, desc);
+    if ((int64_t)g4 * nprob < 2048)
+        hipLaunchKernelGGL(k_gram<8>, dim3(g4, nprob), dim3(8 * 64), 0, s, desc);
+    else
+        hipLaunchKernelGGL(k_gram<4>, dim3(g4, nprob), dim3(4 * 64), 0, s, desc);
     // MF entries: at most 64 * max_tiles per problem (the plan counts them in max_tiles)
     const unsigned gm = (unsigned)((max_tiles * 64 + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_mf, dim3(gm, nprob), dim3(kThreads), 0, s, desc);
